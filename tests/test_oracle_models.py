@@ -1,0 +1,187 @@
+"""Pins for the oracle's priors, per-observation densities and gradients.
+
+Each check compares with something the oracle does not compute itself:
+scipy's densities, the paper's Table 1 (golden fixture), the data-generating
+process run forward, exact symmetries and finite differences.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+import synthdata as SD
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _table1():
+    with open(os.path.join(GOLDEN, "table1_priors.json")) as f:
+        return json.load(f)
+
+
+def _egarch_model(K, shock, T=400, seed=11, theta=None):
+    th = theta if theta is not None else (SD.egarch11_truth() if K == 1 else SD.egarch2t_truth())
+    if K == 2 and shock == SD.GAUSS:
+        th = th[:8]
+    if K == 1 and shock == SD.STUDENT_T:
+        th = np.concatenate([th, [math.log(6.0)]])
+    y, z, h = SD.egarch_series(th, T, K, shock, seed, return_path=True)
+    return O.Model(O.EGARCH, T, y, K=K, shock=shock), th, z, h
+
+
+# ---------------------------------------------------------------- priors ---
+
+@pytest.mark.parametrize("K,shock", [(1, 0), (2, 0), (2, 1)])
+def test_egarch_logprior_is_table1(K, shock):
+    t1 = _table1()
+    m, th, _, _ = _egarch_model(K, shock, T=10)
+    means = ([t1["theta1_mu"]["mean"], math.log(t1["theta2_sigma"]["mean_log_of"])]
+             + [math.atanh(t1["theta3_alpha"]["mean_atanh_of"])] * K
+             + [math.log(t1["theta4_beta"]["mean_log_of"])] * K
+             + [t1["theta5_gamma"]["mean"]] * K)
+    sds = ([t1["theta1_mu"]["sd"], t1["theta2_sigma"]["sd"]] + [t1["theta3_alpha"]["sd"]] * K
+           + [t1["theta4_beta"]["sd"]] * K + [t1["theta5_gamma"]["sd"]] * K)
+    if shock == SD.STUDENT_T:
+        means.append(math.log(t1["theta9_nu"]["mean_log_of"]))
+        sds.append(t1["theta9_nu"]["sd"])
+    rng = np.random.default_rng(1)
+    for _ in range(5):
+        x = th + rng.standard_normal(th.size)
+        want = stats.norm.logpdf(x, means, sds).sum()
+        assert O.logprior(m, x) == pytest.approx(want, rel=1e-13, abs=1e-12)
+
+
+def test_linreg_logprior_is_nig():
+    y, X = SD.linreg_series(T=20)
+    m = O.Model(O.LINREG, 20, y, nreg=3, X=X)
+    rng = np.random.default_rng(2)
+    for _ in range(5):
+        th = rng.standard_normal(4)
+        s2 = math.exp(th[3])
+        want = (stats.invgamma.logpdf(s2, 2.0, scale=1.0) + th[3]
+                + stats.norm.logpdf(th[:3], 0.0, math.sqrt(100.0 * s2)).sum())
+        assert O.logprior(m, th) == pytest.approx(want, rel=1e-13)
+
+
+def test_prior_draws_match_prior_distribution():
+    w = SD.workload("egarch2t", T=10)
+    m = O.Model.from_workload(w)
+    draws = np.array([O.prior_draw(m, 9, 0, p) for p in range(3000)])
+    t1 = _table1()
+    assert stats.kstest(draws[:, 1], "norm", args=(math.log(0.01), 1.0)).pvalue > 1e-3
+    assert stats.kstest(draws[:, 6], "norm", args=(0.0, t1["theta5_gamma"]["sd"])).pvalue > 1e-3
+    assert stats.kstest(draws[:, 8], "norm", args=(math.log(10.0), 1.0)).pvalue > 1e-3
+    # linreg: s2 ~ InvGamma(2, 1), beta | s2 ~ N(0, 100 s2)
+    y, X = SD.linreg_series(T=5)
+    ml = O.Model(O.LINREG, 5, y, nreg=3, X=X)
+    d2 = np.array([O.prior_draw(ml, 9, 0, p) for p in range(3000)])
+    s2 = np.exp(d2[:, 3])
+    assert stats.kstest(s2, "invgamma", args=(2.0, 0, 1.0)).pvalue > 1e-3
+    assert stats.kstest(d2[:, 0] / np.sqrt(100 * s2), "norm").pvalue > 1e-3
+
+
+# -------------------------------------------------------------- densities ---
+
+def test_linreg_loglik_is_gaussian_regression():
+    y, X = SD.linreg_series(T=200)
+    m = O.Model(O.LINREG, 200, y, nreg=3, X=X)
+    th = np.array([0.9, -0.4, 0.3, math.log(0.5)])
+    want = stats.norm.logpdf(y, X @ th[:3], math.sqrt(0.5)).sum()
+    assert O.loglik(m, th)[0] == pytest.approx(want, rel=1e-13)
+    want60 = stats.norm.logpdf(y[:60], X[:60] @ th[:3], math.sqrt(0.5)).sum()
+    assert O.loglik(m, th, t=60)[0] == pytest.approx(want60, rel=1e-13)
+
+
+@pytest.mark.parametrize("K,shock", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_egarch_without_volatility_dynamics_is_iid(K, shock):
+    """beta_k = gamma_k = 0 leaves v = 0: returns iid with scale sigma_Y."""
+    m, th, _, _ = _egarch_model(K, shock, T=300)
+    th = th.copy()
+    th[2 + K:2 + 2 * K] = -800.0   # beta = exp(-800) = 0
+    th[2 + 2 * K:2 + 3 * K] = 0.0  # gamma = 0
+    mu, sig = th[0] / 1000, math.exp(th[1])
+    if shock == SD.GAUSS:
+        want = stats.norm.logpdf(m.y, mu, sig).sum()
+    else:
+        nu = 2 + math.exp(th[2 + 3 * K])
+        want = stats.t.logpdf(m.y, nu, mu, sig * math.sqrt((nu - 2) / nu)).sum()
+    assert O.loglik(m, th)[0] == pytest.approx(want, rel=1e-12)
+
+
+@pytest.mark.parametrize("K,shock", [(1, 0), (2, 0), (1, 1), (2, 1)])
+def test_egarch_filter_recovers_simulated_shocks(K, shock):
+    """At the parameters that generated the data the likelihood recursion
+    inverts the data-generating process: eps_t equals the simulated shock and
+    the log-likelihood is sum_t log f(z_t) - log h_t."""
+    T = 500
+    m, th, z, h = _egarch_model(K, shock, T=T)
+    ll, st = O.loglik(m, th)
+    assert st[K] == pytest.approx(z[-1], rel=1e-9)
+    for t in (1, 2, 3, 17, 250):
+        assert O.loglik(m, th, t=t)[1][K] == pytest.approx(z[t - 1], rel=1e-9, abs=1e-12)
+    if shock == SD.GAUSS:
+        want = (stats.norm.logpdf(z) - np.log(h)).sum()
+    else:
+        nu = 2 + math.exp(th[2 + 3 * K])
+        sc = math.sqrt((nu - 2) / nu)
+        want = (stats.t.logpdf(z, nu, 0, sc) - np.log(h)).sum()
+    assert ll == pytest.approx(want, rel=1e-11)
+
+
+def test_egarch_factors_are_exchangeable():
+    m, th, _, _ = _egarch_model(2, 1, T=400)
+    sw = th.copy()
+    for base in (2, 4, 6):
+        sw[base], sw[base + 1] = th[base + 1], th[base]
+    assert O.loglik(m, sw)[0] == pytest.approx(O.loglik(m, th)[0], rel=1e-13)
+    assert O.logprior(m, sw) == pytest.approx(O.logprior(m, th), rel=1e-13)
+
+
+@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t"])
+def test_loglik_splits_over_dates(name):
+    w = SD.workload(name, T=300)
+    m = O.Model.from_workload(w)
+    th = SD.random_thetas(w, 1, 3)[0]
+    full, st_full = O.loglik(m, th)
+    a, st = O.loglik(m, th, t=123)
+    b, st2 = O.loglik(m, th, t=300, state=st if m.S else None, t0=123)
+    assert a + b == pytest.approx(full, rel=1e-13)
+    if m.S:
+        assert np.allclose(st2, st_full, rtol=1e-14, atol=0)
+
+
+# -------------------------------------------------------------- gradients ---
+
+@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t"])
+def test_gradient_matches_central_differences(name):
+    w = SD.workload(name, T=250)
+    m = O.Model.from_workload(w)
+    rng = np.random.default_rng(4)
+    for th in SD.random_thetas(w, 3, 7):
+        ll, g = O.loglik_grad(m, th)
+        assert ll == pytest.approx(O.loglik(m, th)[0], rel=1e-13)
+        lp, gp = O.logprior_grad(m, th)
+        assert lp == pytest.approx(O.logprior(m, th), rel=1e-13)
+        for i in range(th.size):
+            e = np.zeros_like(th)
+            e[i] = 1e-5
+            fd = (O.loglik(m, th + e)[0] - O.loglik(m, th - e)[0]) / 2e-5
+            assert g[i] == pytest.approx(fd, rel=2e-6, abs=1e-4 * (1 + abs(fd)) * 1e-2)
+            fdp = (O.logprior(m, th + e) - O.logprior(m, th - e)) / 2e-5
+            assert gp[i] == pytest.approx(fdp, rel=1e-6, abs=1e-7)
+    del rng
+
+
+def test_linreg_gradient_closed_form():
+    y, X = SD.linreg_series(T=200)
+    m = O.Model(O.LINREG, 200, y, nreg=3, X=X)
+    th = np.array([0.9, -0.4, 0.3, math.log(0.5)])
+    _, g = O.loglik_grad(m, th)
+    r = y - X @ th[:3]
+    s2 = math.exp(th[3])
+    assert np.allclose(g[:3], X.T @ r / s2, rtol=1e-12)
+    assert g[3] == pytest.approx(-len(y) / 2 + (r @ r) / (2 * s2), rel=1e-12)

@@ -1,0 +1,273 @@
+"""Pins for the oracle's C, S and M phases and its estimators.
+
+Pins used here: hand-computed values on tiny inputs, numpy's covariance and
+Cholesky, exact statistical properties (unbiased resampling counts, invariance
+of the Metropolis kernel, Proposition 1's t(J-1) law of the standardised
+error) and the closed-form marginal likelihood and posterior of the
+conjugate regression.
+"""
+import math
+
+import numpy as np
+import pytest
+from scipy import stats
+
+import oracle as O
+import synthdata as SD
+from oracle import closed_form as CF
+
+
+# ------------------------------------------------------------- estimators ---
+
+def test_rss_special_cases():
+    assert O.rss(np.zeros(1000)) == pytest.approx(1.0, rel=1e-15)
+    lw = np.full(1000, -np.inf)
+    lw[17] = 3.0
+    assert O.rss(lw) == pytest.approx(1e-3, rel=1e-15)
+    # w = (1, 2, 3, 4): ESS = 10^2 / 30, RSS = ESS / 4
+    assert O.rss(np.log([1.0, 2.0, 3.0, 4.0]) + 500.0) == pytest.approx(100 / 120, rel=1e-14)
+
+
+def test_log_ml_hand_values():
+    # one cycle, group mean weights 1 and 3: wbar = 2, NSE = sqrt(2/2)/2
+    out = O.log_ml(np.log([[1.0, 3.0]]))
+    assert out == pytest.approx([math.log(2.0), 0.5, math.log(2.0)], rel=1e-14)
+    # two cycles: wbar_j = (2, 6), wbar = 4, NSE = sqrt(8/2)/4; wtilde = 2 * 2
+    out = O.log_ml(np.log([[1.0, 3.0], [2.0, 2.0]]))
+    assert out == pytest.approx([math.log(4.0), 0.5, math.log(4.0)], rel=1e-14)
+    # equal groups: no numerical error
+    out = O.log_ml(np.full((5, 8), -3.25))
+    assert out[0] == pytest.approx(-16.25, rel=1e-15)
+    assert out[1] == 0.0
+    # shift invariance of the estimator in the log domain
+    g = np.random.default_rng(0).normal(size=(4, 6))
+    a, b = O.log_ml(g), O.log_ml(g + 1000.0)
+    assert b[0] - a[0] == pytest.approx(4000.0, rel=1e-12)
+    assert b[1] == pytest.approx(a[1], rel=1e-12)
+
+
+def test_rne_hand_value_and_iid():
+    y, X = SD.linreg_series(T=5)
+    m = O.Model(O.LINREG, 5, y, nreg=3, X=X)
+    pop = O.Pop(m, 2, 2)
+    pop.theta[:] = np.array([[0.0], [2.0], [1.0], [3.0]]) * np.ones((1, 4))
+    # gbar_j = (1, 2): vhat = 2 * 0.5 = 1; var-hat = 5/3
+    assert O.rne_mean(pop) == pytest.approx(5.0 / 3.0, rel=1e-14)
+    # iid draws: RNE near one (Condition 6)
+    pop = O.Pop(m, 64, 256)
+    pop.theta[:] = np.random.default_rng(3).standard_normal(pop.theta.shape)
+    assert 0.6 < O.rne_mean(pop) < 1.6
+
+
+# -------------------------------------------------------------- S phase -----
+
+def test_resample_equal_weights_is_identity():
+    for scheme in (O.RESIDUAL,):
+        anc, bad = O.resample(3, 64, np.full(192, -7.0), scheme, seed=4)
+        assert bad == 0
+        assert np.array_equal(anc, np.arange(192))
+
+
+def test_resample_integer_copies_are_exact():
+    # N W = (2, 1, 1, 0): residual resampling is deterministic
+    lw = np.log([0.5, 0.25, 0.25, 1e-300])
+    anc, bad = O.resample(1, 4, lw, O.RESIDUAL, seed=2)
+    assert bad == 0
+    assert anc.tolist() == [0, 0, 1, 2]
+    # group offsets
+    anc, _ = O.resample(2, 4, np.concatenate([lw, lw[::-1]]), O.RESIDUAL, seed=2)
+    assert anc.tolist() == [0, 0, 1, 2, 5, 6, 7, 7]
+
+
+def test_resample_dead_group_reported():
+    lw = np.zeros(8)
+    lw[4:] = -np.inf
+    anc, bad = O.resample(2, 4, lw, O.RESIDUAL, seed=1)
+    assert bad == 1
+    assert anc[4:].tolist() == [4, 5, 6, 7]
+
+
+@pytest.mark.parametrize("scheme", [O.RESIDUAL, O.MULTINOMIAL])
+def test_resample_counts_unbiased(scheme):
+    N = 16
+    w = np.random.default_rng(8).gamma(0.7, size=N)
+    W = w / w.sum()
+    lw = np.log(w)
+    counts = np.zeros(N)
+    n_rep = 4000
+    for seed in range(n_rep):
+        anc, _ = O.resample(1, N, lw, scheme, seed=seed)
+        assert np.all(np.diff(anc) >= 0)
+        c = np.bincount(anc, minlength=N)
+        assert c.sum() == N
+        if scheme == O.RESIDUAL:
+            assert np.all(c >= np.floor(N * W))
+        counts += c
+    # E[count_n] = N W_n; multinomial variance bounds the residual one
+    mean = counts / n_rep
+    sd = np.sqrt(N * W * (1 - W) / n_rep)
+    assert np.all(np.abs(mean - N * W) < 4.5 * sd + 1e-12)
+
+
+# ---------------------------------------------------------------- moments ---
+
+def test_moments_match_numpy():
+    w = SD.workload("egarch2t", T=10)
+    m = O.Model.from_workload(w)
+    pop = O.Pop(m, 4, 100)
+    rng = np.random.default_rng(1)
+    A = rng.standard_normal((9, 9))
+    pop.theta[:] = rng.standard_normal((400, 9)) @ A + 3.0
+    mean, cov, chol, rc = O.moments(pop)
+    assert rc == 0
+    assert np.allclose(mean, pop.theta.mean(0), rtol=1e-13)
+    assert np.allclose(cov, np.cov(pop.theta.T), rtol=1e-11, atol=1e-12)
+    assert np.allclose(chol, np.linalg.cholesky(np.cov(pop.theta.T)), rtol=1e-9, atol=1e-10)
+    pop.theta[:, 3] = 1.0  # singular
+    assert O.moments(pop)[3] == -1
+
+
+# ---------------------------------------------------------------- M phase ---
+
+@pytest.mark.parametrize("kernel", [O.RW, O.MALA])
+def test_metropolis_leaves_posterior_invariant(kernel):
+    """Start from exact posterior draws of the conjugate regression; after
+    several Metropolis iterations the marginals are still the posterior."""
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    rng = np.random.default_rng(21)
+    J, N = 8, 512
+    pop = O.Pop(m, J, N)
+    pop.theta[:] = CF.posterior_draws(w.y, w.X, J * N, rng)
+    for p in range(J * N):
+        pop.logprior[p] = O.logprior(m, pop.theta[p])
+    pop.loglik[:] = O.loglik_batch(m, pop.theta)[0]
+    start = pop.theta.copy()
+    n_acc_tot = 0
+    for it in range(1, 7):
+        mean, cov, chol, rc = O.moments(pop)
+        assert rc == 0
+        n_acc, acc = O.mutate(m, pop, w.T, 0.5 * chol, seed=5, cycle=1, it=it, kernel=kernel)
+        n_acc_tot += n_acc
+    assert n_acc_tot > 0.2 * 6 * J * N
+    assert np.mean(np.any(pop.theta != start, axis=1)) > 0.8
+    fresh = CF.posterior_draws(w.y, w.X, J * N, np.random.default_rng(99))
+    for i in range(4):
+        assert stats.ks_2samp(pop.theta[:, i], fresh[:, i]).pvalue > 1e-3
+    # the stored likelihood and prior follow the accepted particles
+    ll = O.loglik_batch(m, pop.theta[:50])[0]
+    assert np.allclose(ll, pop.loglik[:50], rtol=1e-13)
+
+
+def test_mutate_accept_rule_extremes():
+    w = SD.workload("egarch11", T=200)
+    m = O.Model.from_workload(w)
+    pop = O.Pop(m, 2, 8)
+    O.init(m, pop, seed=3)
+    pop.loglik[:] = O.loglik_batch(m, pop.theta, t=200)[0]
+    # zero step: proposal equals current, Delta = 0 > log u whenever the
+    # posterior kernel is finite (a non-finite one gives a NaN Delta: reject)
+    finite = np.isfinite(pop.loglik)
+    n, acc = O.mutate(m, pop, 200, np.zeros((5, 5)), seed=1)
+    assert n == finite.sum() and np.array_equal(acc.astype(bool), finite)
+    # a current state with infinite posterior mass is never left
+    pop.loglik[:] = np.inf
+    n, acc = O.mutate(m, pop, 200, 0.1 * np.eye(5), seed=1)
+    assert n == 0
+
+
+# ------------------------------------------------------------ end to end ----
+
+def _linreg_run(J, N, seed, **kw):
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    rc, rec, pop = O.run(m, J, N, seed, check_every=1, force_every=20, **kw)
+    assert rc == 0
+    return w, rec, pop
+
+
+@pytest.mark.parametrize("seed", [1, 2, 3, 4])
+def test_linreg_log_ml_matches_closed_form(seed):
+    w, rec, pop = _linreg_run(16, 256, seed)
+    s = rec.summary()
+    exact = CF.log_ml(w.y, w.X)
+    assert abs(s["log_ml"] - exact) < 3.5 * s["nse"]
+    assert abs(s["log_ml_tilde"] - exact) < 3.5 * s["nse"] + 0.05
+    assert s["t_end"][-1] == w.T
+    assert all(t % 20 == 0 or t == w.T or t < 20 * (t // 20 + 1) for t in s["t_end"])
+    # dates of interest are cycle ends
+    assert set(range(20, 201, 20)) <= set(s["t_end"].tolist())
+
+
+def test_linreg_predictive_likelihoods_match_closed_form():
+    w, rec, pop = _linreg_run(16, 256, 7)
+    s = rec.summary()
+    t_prev = 0
+    for l in range(s["L"]):
+        g = s["group_logwbar"][l]
+        mx = g.max()
+        r = np.exp(g - mx)
+        est = mx + math.log(r.mean())
+        nse = math.sqrt(((r - r.mean()) ** 2).sum() / (16 * 15)) / r.mean()
+        exact = CF.log_predictive(w.y, w.X, t_prev, s["t_end"][l])
+        assert abs(est - exact) < 4.5 * nse + 1e-3, (l, est, exact, nse)
+        t_prev = s["t_end"][l]
+
+
+def test_linreg_posterior_means_match_closed_form():
+    w, rec, pop = _linreg_run(16, 256, 11)
+    mb, es2, elog = CF.posterior_means(w.y, w.X)
+    want = np.concatenate([mb, [elog]])
+    gj = pop.theta.reshape(16, 256, 4).mean(1)
+    nse = gj.std(0, ddof=1) / math.sqrt(16)
+    assert np.all(np.abs(gj.mean(0) - want) < 4.5 * nse)
+
+
+def test_replay_reproduces_and_new_seed_agrees():
+    w, rec, pop = _linreg_run(8, 256, 5)
+    s = rec.summary()
+    m = O.Model.from_workload(w)
+    rc, rec2, pop2 = O.run(m, 8, 256, 5, check_every=1, record=rec)
+    assert rc == 0
+    s2 = rec2.summary()
+    assert np.array_equal(s2["t_end"], s["t_end"])
+    assert s2["log_ml"] == s["log_ml"]
+    assert np.array_equal(pop2.theta, pop.theta)
+    rc, rec3, _ = O.run(m, 8, 256, 6, check_every=1, record=rec)
+    s3 = rec3.summary()
+    assert abs(s3["log_ml"] - s["log_ml"]) < 3.5 * math.hypot(s["nse"], s3["nse"])
+
+
+def test_deterministic_m_phase_lengths():
+    w, rec, pop = _linreg_run(4, 256, 3)
+    s = rec.summary()
+    for l in range(s["L"]):
+        assert s["R"][l] == (21 if s["rss"][l] < 0.2 else 7)
+
+
+def test_rne_stopping_rule():
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    rc, rec, pop = O.run(m, 8, 128, 2, check_every=1, force_every=20, stop_rule=1, E1=0.35,
+                         Rmax=40)
+    assert rc == 0
+    s = rec.summary()
+    assert np.all((s["R"] >= 1) & (s["R"] <= 40))
+    assert O.rne_mean(pop) > 0.35 or s["R"][-1] == 40
+    exact = CF.log_ml(w.y, w.X)
+    assert abs(s["log_ml"] - exact) < 4.5 * s["nse"]
+
+
+@pytest.mark.slow
+def test_nse_calibration_proposition1():
+    """(log-ML - exact) / NSE across independent runs follows t(J-1)."""
+    w = SD.workload("linreg", T=100)
+    m = O.Model.from_workload(w)
+    exact = CF.log_ml(w.y, w.X)
+    J = 8
+    z = []
+    for seed in range(1, 81):
+        rc, rec, _ = O.run(m, J, 128, seed, check_every=1, force_every=20)
+        assert rc == 0
+        z.append((rec.c.log_ml - exact) / rec.c.nse)
+    assert stats.kstest(z, "t", args=(J - 1,)).pvalue > 1e-3
