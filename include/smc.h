@@ -1,0 +1,272 @@
+/*
+ * smc.h - C ABI of the MI355X (gfx950) sequential posterior simulator.
+ *
+ * The library implements the data-parallel path of the adaptive sequential
+ * posterior simulator of Durham & Geweke (Sections 3.1-3.3, 4.2 and 5.1):
+ * J groups of N particles cycled through Correction (reweight by the
+ * incremental likelihood, RSS test), Selection (within-group resampling) and
+ * Mutation (random-walk Metropolis with the particle covariance), where each
+ * Metropolis step evaluates the full-data log-likelihood recursion of every
+ * particle.
+ *
+ * Conventions for every call:
+ *  - Return value: SMC_OK (0) or a negative smc_status.  Argument errors are
+ *    detected before anything is enqueued.  A HIP launch failure returns
+ *    SMC_E_DEVICE; smc_last_error() gives a thread-local message.
+ *  - Memory: every array argument is caller-owned DEVICE memory unless the
+ *    comment says host.  The library never allocates device memory; scratch
+ *    comes from the caller's workspace (smc_workspace_bytes).
+ *  - Layout: particle p = j*N + n (group j, member n), P = J*N.  Parameter
+ *    arrays are parameter-major, theta[i*P + p] for i < d; states likewise
+ *    state[k*P + p] for k < S.  All such arrays hold FP64, except the state of
+ *    a model created with SMC_FP32, which holds float.
+ *  - Streams: `stream` is a hipStream_t (NULL = the default stream).  All
+ *    device work is enqueued on it.  Only the calls documented as
+ *    synchronising wait for it.
+ *  - Random numbers: Philox4x64-10 (Salmon et al. 2011) keyed by
+ *    (rng.seed, rng.run) with counters (index, cycle, iteration, purpose),
+ *    so results do not depend on launch geometry.
+ *  - A non-finite per-particle density is not an error: its weight becomes
+ *    zero (log weight -inf) or the proposal is rejected.
+ */
+#ifndef SMC_H
+#define SMC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef int32_t smc_status;
+#define SMC_OK 0
+#define SMC_E_INVALID_ARG (-1) /* bad pointer, size, enum or shape */
+#define SMC_E_UNSUPPORTED (-2) /* valid request this build does not provide */
+#define SMC_E_DEVICE (-3)      /* a HIP call failed */
+#define SMC_E_NUMERIC (-4)     /* a group lost all weight, or V is not PD */
+#define SMC_E_WORKSPACE (-5)   /* workspace smaller than smc_workspace_bytes */
+
+/* Model family (Section 5.1; the regression is the conjugate test model). */
+#define SMC_MODEL_LINREG 1 /* y_t = x_t' beta + e_t, e_t ~ N(0, s2) */
+#define SMC_MODEL_EGARCH 2 /* eqs EGARCH_mod1/2 with K factors */
+#define SMC_SHOCK_GAUSS 0
+#define SMC_SHOCK_STUDENT_T 1 /* unit-variance Student-t(nu) shocks */
+/* Arithmetic of the likelihood recursion.  Log weights, log-likelihood sums,
+ * logsumexp, covariance, Cholesky, the marginal likelihood and its NSE are
+ * FP64 in both cases. */
+#define SMC_FP64 0
+#define SMC_FP32 1
+
+#define SMC_RESAMPLE_RESIDUAL 0    /* Section 3.3 default */
+#define SMC_RESAMPLE_MULTINOMIAL 1
+
+#define SMC_KERNEL_RW 0   /* Gaussian random walk, Section 3.3 (default) */
+#define SMC_KERNEL_MALA 1 /* preconditioned Langevin proposal (extension) */
+
+#define SMC_FLAG_DEAD_GROUP 1 /* a group had no positive weight (S phase) */
+#define SMC_FLAG_NOT_PD 2     /* particle variance not positive definite */
+
+/* Model description.  The parameter vector theta (dimension d) is:
+ *   LINREG: (beta_1..beta_k, log s2), d = k + 1, prior beta | s2 ~
+ *           N(0, 100 s2 I), s2 ~ InvGamma(2, 1) (conjugate);
+ *   EGARCH: (theta_1, theta_2, theta_3k.., theta_4k.., theta_5k..
+ *           [, log(nu - 2)]) with Table 1's transforms and Gaussian priors,
+ *           d = 2 + 3K (+1 for Student-t); state S = K + 1 (the K factors
+ *           and the previous standardised shock). */
+typedef struct {
+  int32_t kind;      /* SMC_MODEL_* */
+  int32_t K;         /* EGARCH factors, 1 or 2 */
+  int32_t shock;     /* SMC_SHOCK_* (EGARCH) */
+  int32_t nreg;      /* regressors k, 1..8 (LINREG) */
+  int32_t precision; /* SMC_FP64 or SMC_FP32 (FP32: EGARCH only) */
+  int32_t reserved;  /* must be 0 */
+  int64_t T;         /* observations, >= 1 */
+  const double *y;   /* device [T] */
+  const float *y32;  /* device [T], y as float; required for SMC_FP32 */
+  const double *X;   /* device [T][nreg] row-major (LINREG), else NULL */
+} smc_model_desc;
+
+/* Opaque, immutable after creation; may be used from several streams.  The
+ * device arrays it points to must outlive it. */
+typedef struct smc_model smc_model;
+
+/* A particle population; every pointer is caller-owned device memory. */
+typedef struct {
+  int32_t J, N;       /* groups and particles per group, J >= 2, N >= 2 */
+  double *theta;      /* [d][P] */
+  double *logprior;   /* [P] log p(theta_p) */
+  double *loglik;     /* [P] log p(y_{1:t} | theta_p) at the current date */
+  void *state;        /* [S][P] recursion state at the current date (NULL if S = 0) */
+  double *logw;       /* [P] log C-phase weight */
+  double *grad;       /* [d][P] gradient of log prior + log likelihood, MALA only, else NULL */
+  int32_t *ancestor;  /* [P] last S-phase ancestors */
+  void *ws;           /* workspace, >= smc_workspace_bytes(...) bytes, 256-byte aligned */
+  size_t ws_bytes;
+} smc_particles;
+
+typedef struct {
+  uint64_t seed; /* Philox key word 0 */
+  uint64_t run;  /* Philox key word 1 (independent runs) */
+} smc_rng;
+
+/* --- models and sizing -------------------------------------------------- */
+
+/* Validates the description and creates a handle (host allocation only). */
+smc_status smc_model_create(const smc_model_desc *desc, smc_model **out);
+smc_status smc_model_destroy(smc_model *m);
+int32_t smc_model_dim(const smc_model *m);       /* d, or -1 for NULL */
+int32_t smc_model_state_dim(const smc_model *m); /* S, or -1 for NULL */
+
+/* Workspace bytes needed by a population of J x N particles whose C phases
+ * are evaluated in chunks of at most `max_chunk` observations (0 = default
+ * 256).  The same workspace serves every call below. */
+size_t smc_workspace_bytes(const smc_model *m, int32_t J, int32_t N, int64_t max_chunk);
+
+/* --- the seven calls of the simulator --------------------------------- */
+
+/* Algorithm 1 step 1: theta_p ~ p(theta) (counter (p, 0, 0, PRIOR)),
+ * logprior, loglik = 0, logw = 0, state = the initial state s0. */
+smc_status smc_init_from_prior(const smc_model *m, smc_particles *pop, smc_rng rng,
+                               void *stream);
+
+/* C phase of cycle `cycle` (Algorithm 1 step 2a, eq C_phase_compute): sets
+ * logw = 0 and, for s = t_from+1, ..., adds log p(y_s | y_{1:s-1}, theta_p)
+ * to logw_p and loglik_p while advancing the state.  At every check date (s a
+ * multiple of `check_every`, and s = t_max) the pooled RSS = (sum w)^2 /
+ * (P sum w^2) is formed (Section 3.3); the phase stops at the first check
+ * date with RSS < rss_min, or at t_max.  Writes group_logwbar[j] = log(N^-1
+ * sum_n w_jn) (device [J], Section 4.2), *t_to (host) = the end date and,
+ * when rss is not NULL, *rss (host) = the RSS there.
+ * With rss_min <= 0 the phase runs to t_max; if in addition rss is NULL the
+ * call does not synchronise (capturable).  Otherwise it synchronises the
+ * stream once per evaluated chunk of observations. */
+smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
+                       int64_t check_every, double rss_min, double *group_logwbar,
+                       int64_t *t_to, double *rss, void *stream);
+
+/* S phase (Algorithm 1 step 2b) in every group independently: residual
+ * (Section 3.3 default) or multinomial resampling on logw.  Residual: copy n
+ * floor(N W_n) times, then draw the remaining R = N - sum floor(N W_n) from
+ * the residuals N W_n - floor(N W_n); draw k of group j uses word k%4 of
+ * Philox(j, cycle, k/4, RESAMPLE) as u in [0,1) and selects the first n whose
+ * running residual sum exceeds u times the total.  Ancestors are written in
+ * ascending order to pop->ancestor; theta, logprior, loglik, state and grad
+ * (if not NULL) are replaced by the ancestors'.  A group without positive
+ * weight keeps its particles and raises SMC_FLAG_DEAD_GROUP (smc_flags). */
+smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, smc_rng rng,
+                        int32_t cycle, void *stream);
+
+/* One Metropolis iteration (Algorithm 1 step 2c, Section 3.3) at date t for
+ * every particle: z ~ N(0, I_d) from Philox(p, cycle, iter, PROPOSAL | b<<8)
+ * by Box-Muller, theta' = theta + hL z (hchol: device [d][d] row-major lower
+ * triangular, hL with Sigma = hL hL' = h^2 V); accept iff
+ * log u < log p(theta') + log p(y_{1:t}|theta') - (same at theta), u in (0,1)
+ * from Philox(p, cycle, iter, ACCEPT).  The likelihood is the full recursion
+ * over 1..t from s0.  Accepted particles take theta', logprior, loglik and the
+ * state at t.  With kernel = SMC_KERNEL_MALA the proposal mean adds
+ * (1/2) hL hL' grad and the acceptance includes the proposal-density ratio;
+ * pop->grad must hold the gradient at the current particles and is updated.
+ * The number accepted is ADDED to *n_accept (device int64); accepted
+ * (device [P] bytes, may be NULL) receives the 0/1 decisions. */
+smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t kernel,
+                      const double *hchol, smc_rng rng, int32_t cycle, int32_t iter,
+                      int64_t *n_accept, uint8_t *accepted, void *stream);
+
+/* log p(y_{1:t} | theta_p) for P parameter vectors (theta device [d][P]) by
+ * the model's recursion from s0 (eq p(y|theta) as a product of
+ * p(y_s | y_{1:s-1}, theta)).  loglik: device [P]; state_out: device [S][P]
+ * (precision of the model) or NULL. */
+smc_status smc_loglik(const smc_model *m, int64_t P, const double *theta, int64_t t,
+                      double *loglik, void *state_out, void *stream);
+
+/* Adjoint of smc_loglik: dtheta[i][p] = dloglik[p] * d log p(y_{1:t}|theta_p)
+ * / d theta_ip.  The forward recursion is checkpointed every 64 observations
+ * into the workspace ws (>= smc_backward_ws_bytes bytes) and replayed
+ * segment by segment in reverse.  d|x|/dx is taken as 0 at x = 0. */
+smc_status smc_loglik_backward(const smc_model *m, int64_t P, const double *theta, int64_t t,
+                               const double *dloglik, double *dtheta, void *ws,
+                               size_t ws_bytes, void *stream);
+size_t smc_backward_ws_bytes(const smc_model *m, int64_t P, int64_t t);
+
+/* Marginal likelihood from the per-cycle group mean weights (Section 4.2):
+ * group_logwbar: device [L][J] (log wbar_j(l-1)); out: device [3] =
+ * { log wbar, NSE of log wbar by the delta method of eq ML_se, log wtilde }. */
+smc_status smc_log_ml(int32_t L, int32_t J, const double *group_logwbar, double *out,
+                      void *stream);
+
+/* --- helpers of the M phase -------------------------------------------- */
+
+/* Pooled particle mean (device [d]), variance V with divisor P - 1 (device
+ * [d][d]) and hchol = h L with V = L L' and h = (*mh) / 10 (mh: device int32
+ * holding h in tenths, Section 3.3).  mean and cov may be NULL.  A variance
+ * that is not positive definite raises SMC_FLAG_NOT_PD and leaves hchol
+ * zero (a zero step: every proposal equals the current particle). */
+smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, const int32_t *mh,
+                                double *mean, double *cov, double *hchol, void *stream);
+
+/* Step-size rule of Section 3.3 on device: with a = *n_accept / P,
+ * *mh += 1 if a > target_permille / 1000 else *mh -= 1, clamped to [1, 10].
+ * The comparison is exact in integers. */
+smc_status smc_adapt_scale(const int64_t *n_accept, int64_t P, int32_t target_permille,
+                           int32_t *mh, void *stream);
+
+/* Mean over the parameters of RNE = var-hat / v-hat with g_i(theta) = theta_i
+ * (Section 2.3): device double [1]. */
+smc_status smc_rne(const smc_model *m, const smc_particles *pop, double *rne, void *stream);
+
+/* Reads and clears the SMC_FLAG_* bits raised in the workspace (host int32;
+ * synchronises the stream). */
+smc_status smc_flags(const smc_particles *pop, int32_t *flags, void *stream);
+
+/* --- the whole simulator ------------------------------------------------ */
+
+/* Algorithm 2 with the rules of Section 3.3 (adaptive), or Algorithm 1 on a
+ * recorded design {t_l, Sigma_lr, R_l} (replay = step 2 of Algorithm 3). */
+typedef struct {
+  int32_t J, N;
+  smc_rng rng;
+  int32_t check_every;  /* RSS check dates: every k-th observation (1) */
+  int32_t force_every;  /* dates of interest: cycle ends every k-th obs (0 = none) */
+  double D1, D2;        /* 0.5, 0.2 */
+  int32_t Rbar, kappa;  /* 7, 3 */
+  int32_t stop_rule;    /* 0 deterministic R_l, 1 RNE-based */
+  double E1;            /* 0.35 */
+  int32_t Rmax;         /* 100 */
+  int32_t scheme;       /* SMC_RESAMPLE_* */
+  int32_t kernel;       /* SMC_KERNEL_* */
+  int32_t replay;       /* 0 adaptive, 1 replay the record's design */
+  int32_t Lmax;         /* record capacity in cycles */
+  int32_t RmaxRec;      /* record capacity in iterations per cycle */
+  int64_t max_chunk;    /* C-phase chunk bound, as given to smc_workspace_bytes */
+} smc_run_config;
+
+typedef struct {
+  int32_t L;             /* out: cycles run */
+  int32_t reserved;
+  int64_t *t_end;        /* host [Lmax]: out (adaptive) / in (replay) */
+  int32_t *R;            /* host [Lmax]: out / in */
+  double *rss;           /* host [Lmax]: out, RSS at the end of each C phase */
+  int64_t *n_accept;     /* device [Lmax][RmaxRec]: out, accepted per iteration */
+  double *hchol;         /* device [Lmax][RmaxRec][d][d]: out / in */
+  double *group_logwbar; /* device [Lmax][J]: out */
+  double *log_ml;        /* device [3]: out, as smc_log_ml */
+  int64_t evals;         /* out: particle x observation density evaluations */
+  int64_t mh_steps;      /* out: Metropolis iterations */
+} smc_run_record;
+
+/* Runs the simulator on `pop` (which must hold a workspace for
+ * cfg->max_chunk).  Synchronises the stream once per C-phase chunk (and per
+ * M iteration under the RNE rule). */
+smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                   smc_run_record *rec, void *stream);
+
+/* --- diagnostics ------------------------------------------------------- */
+const char *smc_status_string(smc_status s);
+const char *smc_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SMC_H */

@@ -264,6 +264,20 @@ def mutate(m: Model, pop: Pop, t, hchol, seed, run=0, cycle=1, it=1, kernel=RW):
     return int(n), acc
 
 
+def mutate_particle(m: Model, p, theta, lp, ll, t, hchol, seed, run=0, cycle=1, it=1,
+                    kernel=RW):
+    """M step of the single particle with global index p; returns
+    (accepted, theta, lp, ll, state)."""
+    th = _f64(theta).copy()
+    lpv, llv = C.c_double(lp), C.c_double(ll)
+    st = np.zeros(max(m.S, 1))
+    acc = lib().orc_mutate_particle(C.byref(m.c), C.c_int64(p), _dp(th), C.byref(lpv),
+                                    C.byref(llv), _dp(st), C.c_int64(t), C.c_int(kernel),
+                                    _dp(_f64(hchol)), C.c_uint64(seed), C.c_uint64(run),
+                                    C.c_uint64(cycle), C.c_uint64(it))
+    return bool(acc), th, lpv.value, llv.value, st[:m.S]
+
+
 def rne_mean(pop: Pop):
     pop._sync()
     return lib().orc_rne_mean(C.byref(pop.c))

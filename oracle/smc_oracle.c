@@ -619,6 +619,99 @@ enum { ORC_RW = 0, ORC_MALA = 1 };
  * log posterior to the proposal mean and the proposal-density ratio to the
  * acceptance test.  `hchol` is hL, d x d row-major lower triangular.
  * Writes accept flags (optional) and returns the number accepted. */
+/* The M step of one particle with global index p (its Philox counters use
+ * p): theta (d), lp and ll are updated in place on acceptance, state (S)
+ * too.  Returns 1 when the proposal is accepted. */
+int orc_mutate_particle(const orc_model *m, int64_t p, double *th, double *lp, double *ll,
+                        double *state, int64_t t, int kernel, const double *hchol, uint64_t seed,
+                        uint64_t run, uint64_t cycle, uint64_t iter) {
+  int d = orc_dim(m), S = orc_state_dim(m);
+  double z[ORC_DMAX], prop[ORC_DMAX], st[ORC_SMAX];
+  double g0[ORC_DMAX], g1[ORC_DMAX], gp[ORC_DMAX];
+  normals(seed, run, (uint64_t)p, cycle, iter, ORC_PROPOSAL, d, z);
+  double drift[ORC_DMAX];
+  for (int i = 0; i < d; ++i) drift[i] = 0.0;
+  if (kernel == ORC_MALA) {
+    /* gradient of the log posterior kernel at the current particle */
+    orc_loglik_grad(m, th, t, g0);
+    orc_logprior_grad(m, th, gp);
+    for (int i = 0; i < d; ++i) g0[i] += gp[i];
+    /* (1/2) (hL)(hL)' g0 */
+    double w[ORC_DMAX];
+    for (int k = 0; k < d; ++k) {
+      w[k] = 0.0;
+      for (int i = k; i < d; ++i) w[k] += hchol[i * d + k] * g0[i];
+    }
+    for (int i = 0; i < d; ++i) {
+      drift[i] = 0.0;
+      for (int k = 0; k <= i; ++k) drift[i] += 0.5 * hchol[i * d + k] * w[k];
+    }
+  }
+  for (int i = 0; i < d; ++i) {
+    double step = 0.0;
+    for (int k = 0; k <= i; ++k) step += hchol[i * d + k] * z[k];
+    prop[i] = th[i] + drift[i] + step;
+  }
+  double lp_new = orc_logprior(m, prop);
+  int acc = 0;
+  double ll_new = -INFINITY;
+  if (lp_new > -INFINITY) {
+    double logq_ratio = 0.0;
+    if (kernel == ORC_MALA) {
+      ll_new = orc_loglik_grad(m, prop, t, g1);
+      orc_logprior_grad(m, prop, gp);
+      for (int i = 0; i < d; ++i) g1[i] += gp[i];
+      /* reverse move: solve (hL) w = theta - theta' - (1/2)(hL)(hL)' g1 */
+      double v[ORC_DMAX], a[ORC_DMAX], wv[ORC_DMAX];
+      for (int k = 0; k < d; ++k) {
+        v[k] = 0.0;
+        for (int i = k; i < d; ++i) v[k] += hchol[i * d + k] * g1[i];
+      }
+      for (int i = 0; i < d; ++i) {
+        double dr = 0.0;
+        for (int k = 0; k <= i; ++k) dr += 0.5 * hchol[i * d + k] * v[k];
+        a[i] = th[i] - prop[i] - dr;
+      }
+      for (int i = 0; i < d; ++i) {
+        double s = a[i];
+        for (int k = 0; k < i; ++k) s -= hchol[i * d + k] * wv[k];
+        wv[i] = s / hchol[i * d + i];
+      }
+      double zz = 0.0, ww = 0.0;
+      for (int i = 0; i < d; ++i) { zz += z[i] * z[i]; ww += wv[i] * wv[i]; }
+      logq_ratio = -0.5 * ww + 0.5 * zz;
+      /* the state at t is needed on acceptance */
+      orc_state_init(m, st);
+      orc_loglik_range(m, prop, 0, t, st);
+    } else {
+      orc_state_init(m, st);
+      ll_new = orc_loglik_range(m, prop, 0, t, st);
+    }
+    double delta = (lp_new + ll_new) - (*lp + *ll) + logq_ratio;
+    uint64_t x[4];
+    draw4(seed, run, (uint64_t)p, cycle, iter, ORC_ACCEPT, x);
+    double logu = log(u01_oo(x[0]));
+    acc = (logu < delta) ? 1 : 0; /* false for NaN */
+  }
+  if (acc) {
+    for (int i = 0; i < d; ++i) th[i] = prop[i];
+    for (int k = 0; k < S; ++k) state[k] = st[k];
+    *lp = lp_new;
+    *ll = ll_new;
+  }
+  return acc;
+}
+
+/* One M-phase Metropolis iteration (Algorithm 1, step 2c with the Gaussian
+ * random walk of Section 3.3) over every particle at date t:
+ *   z ~ N(0, I) from counter (p, l, r, PROPOSAL | block),
+ *   theta' = theta + (h L) z with Sigma_lr = h^2 V_lr = (hL)(hL)',
+ *   accept when log u < log p(theta') + log p(y_{1:t}|theta') - (same at theta),
+ *   u in (0,1) from counter (p, l, r, ACCEPT), first word.
+ * The Langevin variant (kernel = ORC_MALA) adds the drift (1/2)(hL)(hL)' grad
+ * log posterior to the proposal mean and the proposal-density ratio to the
+ * acceptance test.  `hchol` is hL, d x d row-major lower triangular.
+ * Writes accept flags (optional) and returns the number accepted. */
 int64_t orc_mutate(const orc_model *m, orc_pop *pop, int64_t t, int kernel, const double *hchol,
                    uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter, uint8_t *accepted) {
   int64_t P = (int64_t)pop->J * pop->N;
@@ -626,79 +719,12 @@ int64_t orc_mutate(const orc_model *m, orc_pop *pop, int64_t t, int kernel, cons
   int64_t n_acc = 0;
 #pragma omp parallel for schedule(dynamic, 16) reduction(+ : n_acc)
   for (int64_t p = 0; p < P; ++p) {
-    double *th = pop->theta + p * d;
-    double z[ORC_DMAX], prop[ORC_DMAX], st[ORC_SMAX];
-    double g0[ORC_DMAX], g1[ORC_DMAX], gp[ORC_DMAX];
-    normals(seed, run, (uint64_t)p, cycle, iter, ORC_PROPOSAL, d, z);
-    double drift[ORC_DMAX];
-    for (int i = 0; i < d; ++i) drift[i] = 0.0;
-    if (kernel == ORC_MALA) {
-      /* gradient of the log posterior kernel at the current particle */
-      orc_loglik_grad(m, th, t, g0);
-      orc_logprior_grad(m, th, gp);
-      for (int i = 0; i < d; ++i) g0[i] += gp[i];
-      /* (1/2) (hL)(hL)' g0 */
-      double w[ORC_DMAX];
-      for (int k = 0; k < d; ++k) {
-        w[k] = 0.0;
-        for (int i = k; i < d; ++i) w[k] += hchol[i * d + k] * g0[i];
-      }
-      for (int i = 0; i < d; ++i) {
-        drift[i] = 0.0;
-        for (int k = 0; k <= i; ++k) drift[i] += 0.5 * hchol[i * d + k] * w[k];
-      }
-    }
-    for (int i = 0; i < d; ++i) {
-      double step = 0.0;
-      for (int k = 0; k <= i; ++k) step += hchol[i * d + k] * z[k];
-      prop[i] = th[i] + drift[i] + step;
-    }
-    double lp_new = orc_logprior(m, prop);
-    int acc = 0;
-    double ll_new = -INFINITY;
-    if (lp_new > -INFINITY) {
-      double logq_ratio = 0.0;
-      if (kernel == ORC_MALA) {
-        ll_new = orc_loglik_grad(m, prop, t, g1);
-        orc_logprior_grad(m, prop, gp);
-        for (int i = 0; i < d; ++i) g1[i] += gp[i];
-        /* reverse move: solve (hL) w = theta - theta' - (1/2)(hL)(hL)' g1 */
-        double v[ORC_DMAX], a[ORC_DMAX], wv[ORC_DMAX];
-        for (int k = 0; k < d; ++k) {
-          v[k] = 0.0;
-          for (int i = k; i < d; ++i) v[k] += hchol[i * d + k] * g1[i];
-        }
-        for (int i = 0; i < d; ++i) {
-          double dr = 0.0;
-          for (int k = 0; k <= i; ++k) dr += 0.5 * hchol[i * d + k] * v[k];
-          a[i] = th[i] - prop[i] - dr;
-        }
-        for (int i = 0; i < d; ++i) {
-          double s = a[i];
-          for (int k = 0; k < i; ++k) s -= hchol[i * d + k] * wv[k];
-          wv[i] = s / hchol[i * d + i];
-        }
-        double zz = 0.0, ww = 0.0;
-        for (int i = 0; i < d; ++i) { zz += z[i] * z[i]; ww += wv[i] * wv[i]; }
-        logq_ratio = -0.5 * ww + 0.5 * zz;
-        /* the state at t is needed on acceptance */
-        orc_state_init(m, st);
-        orc_loglik_range(m, prop, 0, t, st);
-      } else {
-        orc_state_init(m, st);
-        ll_new = orc_loglik_range(m, prop, 0, t, st);
-      }
-      double delta = (lp_new + ll_new) - (pop->logprior[p] + pop->loglik[p]) + logq_ratio;
-      uint64_t x[4];
-      draw4(seed, run, (uint64_t)p, cycle, iter, ORC_ACCEPT, x);
-      double logu = log(u01_oo(x[0]));
-      acc = (logu < delta) ? 1 : 0; /* false for NaN */
-    }
+    double stp[ORC_SMAX];
+    for (int k = 0; k < S; ++k) stp[k] = pop->state[p * S + k];
+    int acc = orc_mutate_particle(m, p, pop->theta + p * d, pop->logprior + p, pop->loglik + p,
+                                  stp, t, kernel, hchol, seed, run, cycle, iter);
     if (acc) {
-      for (int i = 0; i < d; ++i) th[i] = prop[i];
-      for (int k = 0; k < S; ++k) pop->state[p * S + k] = st[k];
-      pop->logprior[p] = lp_new;
-      pop->loglik[p] = ll_new;
+      for (int k = 0; k < S; ++k) pop->state[p * S + k] = stp[k];
       n_acc += 1;
     }
     if (accepted) accepted[p] = (uint8_t)acc;

@@ -1,0 +1,347 @@
+"""ctypes binding of libsmc.so (include/smc.h): argument marshalling only.
+
+Every computation runs in the HIP library.  torch supplies device memory and
+the stream; nothing here falls back to the CPU.  If the library is missing
+the import of a call raises immediately.
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+
+import torch
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libsmc.so")
+
+# Enums (values fixed by include/smc.h).
+SMC_OK = 0
+SMC_MODEL_LINREG, SMC_MODEL_EGARCH = 1, 2
+SMC_SHOCK_GAUSS, SMC_SHOCK_STUDENT_T = 0, 1
+SMC_FP64, SMC_FP32 = 0, 1
+SMC_RESAMPLE_RESIDUAL, SMC_RESAMPLE_MULTINOMIAL = 0, 1
+SMC_KERNEL_RW, SMC_KERNEL_MALA = 0, 1
+SMC_FLAG_DEAD_GROUP, SMC_FLAG_NOT_PD = 1, 2
+
+_vp = C.c_void_p
+
+
+class ModelDesc(C.Structure):
+    _fields_ = [("kind", C.c_int32), ("K", C.c_int32), ("shock", C.c_int32),
+                ("nreg", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("T", C.c_int64), ("y", _vp), ("y32", _vp), ("X", _vp)]
+
+
+class Particles(C.Structure):
+    _fields_ = [("J", C.c_int32), ("N", C.c_int32), ("theta", _vp), ("logprior", _vp),
+                ("loglik", _vp), ("state", _vp), ("logw", _vp), ("grad", _vp),
+                ("ancestor", _vp), ("ws", _vp), ("ws_bytes", C.c_size_t)]
+
+
+class Rng(C.Structure):
+    _fields_ = [("seed", C.c_uint64), ("run", C.c_uint64)]
+
+
+class RunConfig(C.Structure):
+    _fields_ = [("J", C.c_int32), ("N", C.c_int32), ("rng", Rng),
+                ("check_every", C.c_int32), ("force_every", C.c_int32),
+                ("D1", C.c_double), ("D2", C.c_double), ("Rbar", C.c_int32),
+                ("kappa", C.c_int32), ("stop_rule", C.c_int32), ("E1", C.c_double),
+                ("Rmax", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
+                ("replay", C.c_int32), ("Lmax", C.c_int32), ("RmaxRec", C.c_int32),
+                ("max_chunk", C.c_int64)]
+
+
+class RunRecord(C.Structure):
+    _fields_ = [("L", C.c_int32), ("reserved", C.c_int32), ("t_end", _vp), ("R", _vp),
+                ("rss", _vp), ("n_accept", _vp), ("hchol", _vp), ("group_logwbar", _vp),
+                ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64)]
+
+
+_L = None
+
+
+def lib():
+    """The loaded library; raises if it has not been built."""
+    global _L
+    if _L is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError(f"{LIB_PATH} is missing: run __graft_entry__.build() first")
+        L = C.CDLL(LIB_PATH)
+        st = C.c_int32
+        P = C.POINTER
+        L.smc_status_string.restype = C.c_char_p
+        L.smc_status_string.argtypes = [st]
+        L.smc_last_error.restype = C.c_char_p
+        L.smc_last_error.argtypes = []
+        L.smc_model_create.restype = st
+        L.smc_model_create.argtypes = [P(ModelDesc), P(_vp)]
+        L.smc_model_destroy.restype = st
+        L.smc_model_destroy.argtypes = [_vp]
+        L.smc_model_dim.restype = C.c_int32
+        L.smc_model_dim.argtypes = [_vp]
+        L.smc_model_state_dim.restype = C.c_int32
+        L.smc_model_state_dim.argtypes = [_vp]
+        L.smc_workspace_bytes.restype = C.c_size_t
+        L.smc_workspace_bytes.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64]
+        L.smc_backward_ws_bytes.restype = C.c_size_t
+        L.smc_backward_ws_bytes.argtypes = [_vp, C.c_int64, C.c_int64]
+        L.smc_init_from_prior.restype = st
+        L.smc_init_from_prior.argtypes = [_vp, P(Particles), Rng, _vp]
+        L.smc_correct.restype = st
+        L.smc_correct.argtypes = [_vp, P(Particles), C.c_int64, C.c_int64, C.c_int64,
+                                  C.c_double, _vp, P(C.c_int64), P(C.c_double), _vp]
+        L.smc_resample.restype = st
+        L.smc_resample.argtypes = [_vp, P(Particles), C.c_int32, Rng, C.c_int32, _vp]
+        L.smc_particle_moments.restype = st
+        L.smc_particle_moments.argtypes = [_vp, P(Particles), _vp, _vp, _vp, _vp, _vp]
+        L.smc_mutate.restype = st
+        L.smc_mutate.argtypes = [_vp, P(Particles), C.c_int64, C.c_int32, _vp, Rng,
+                                 C.c_int32, C.c_int32, _vp, _vp, _vp]
+        L.smc_loglik.restype = st
+        L.smc_loglik.argtypes = [_vp, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp]
+        L.smc_loglik_backward.restype = st
+        L.smc_loglik_backward.argtypes = [_vp, C.c_int64, _vp, C.c_int64, _vp, _vp, _vp,
+                                          C.c_size_t, _vp]
+        L.smc_log_ml.restype = st
+        L.smc_log_ml.argtypes = [C.c_int32, C.c_int32, _vp, _vp, _vp]
+        L.smc_adapt_scale.restype = st
+        L.smc_adapt_scale.argtypes = [_vp, C.c_int64, C.c_int32, _vp, _vp]
+        L.smc_rne.restype = st
+        L.smc_rne.argtypes = [_vp, P(Particles), _vp, _vp]
+        L.smc_flags.restype = st
+        L.smc_flags.argtypes = [P(Particles), P(C.c_int32), _vp]
+        L.smc_run.restype = st
+        L.smc_run.argtypes = [_vp, P(Particles), P(RunConfig), P(RunRecord), _vp]
+        _L = L
+    return _L
+
+
+class SmcError(RuntimeError):
+    def __init__(self, status, where):
+        L = lib()
+        msg = L.smc_status_string(status).decode()
+        detail = L.smc_last_error().decode()
+        super().__init__(f"{where}: {msg} ({status}): {detail}")
+        self.status = status
+
+
+def _check(status, where):
+    if status != SMC_OK:
+        raise SmcError(status, where)
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _stream(stream):
+    if stream is None:
+        stream = torch.cuda.current_stream()
+    return C.c_void_p(stream.cuda_stream)
+
+
+class Model:
+    """A model handle plus the device copies of its data."""
+
+    def __init__(self, kind, y, X=None, K=1, shock=SMC_SHOCK_GAUSS, precision=SMC_FP64,
+                 device="cuda"):
+        self.y = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
+        self.y32 = self.y.float().contiguous() if precision == SMC_FP32 else None
+        self.X = (torch.as_tensor(X, dtype=torch.float64).to(device).contiguous()
+                  if X is not None else None)
+        nreg = int(self.X.shape[1]) if self.X is not None else 0
+        self.kind, self.K, self.shock, self.precision = kind, K, shock, precision
+        self.T = int(self.y.numel())
+        self.device = device
+        self.desc = ModelDesc(kind, K, shock, nreg, precision, 0, self.T, _ptr(self.y),
+                              _ptr(self.y32), _ptr(self.X))
+        h = C.c_void_p()
+        _check(lib().smc_model_create(C.byref(self.desc), C.byref(h)), "smc_model_create")
+        self.h = h
+
+    @classmethod
+    def from_workload(cls, w, precision=SMC_FP64, device="cuda"):
+        return cls(w.kind, w.y, X=w.X, K=w.K, shock=w.shock, precision=precision,
+                   device=device)
+
+    @property
+    def d(self):
+        return lib().smc_model_dim(self.h)
+
+    @property
+    def S(self):
+        return lib().smc_model_state_dim(self.h)
+
+    @property
+    def state_dtype(self):
+        return torch.float32 if self.precision == SMC_FP32 else torch.float64
+
+    def __del__(self):
+        try:
+            if getattr(self, "h", None):
+                lib().smc_model_destroy(self.h)
+                self.h = None
+        except Exception:
+            pass
+
+
+class Population:
+    """Device buffers of J x N particles ([d][P] layouts) and a workspace."""
+
+    def __init__(self, model: Model, J, N, max_chunk=256, with_grad=False):
+        dev = model.device
+        P = J * N
+        self.model, self.J, self.N, self.P = model, J, N, P
+        f64 = dict(dtype=torch.float64, device=dev)
+        self.theta = torch.zeros((model.d, P), **f64)
+        self.logprior = torch.zeros(P, **f64)
+        self.loglik = torch.zeros(P, **f64)
+        self.state = (torch.zeros((model.S, P), dtype=model.state_dtype, device=dev)
+                      if model.S > 0 else None)
+        self.logw = torch.zeros(P, **f64)
+        self.grad = torch.zeros((model.d, P), **f64) if with_grad else None
+        self.ancestor = torch.zeros(P, dtype=torch.int32, device=dev)
+        self.max_chunk = max_chunk
+        nb = lib().smc_workspace_bytes(model.h, J, N, max_chunk)
+        if nb == 0:
+            raise SmcError(-1, "smc_workspace_bytes")
+        self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
+        off = (-self.ws.data_ptr()) % 256
+        self.ws_view = self.ws[off:off + nb]
+        self.c = Particles(J, N, _ptr(self.theta), _ptr(self.logprior), _ptr(self.loglik),
+                           _ptr(self.state), _ptr(self.logw), _ptr(self.grad),
+                           _ptr(self.ancestor), _ptr(self.ws_view), nb)
+
+
+# --- the calls, same names as the C ABI ----------------------------------
+
+def smc_init_from_prior(model: Model, pop: Population, seed, run=0, stream=None):
+    _check(lib().smc_init_from_prior(model.h, C.byref(pop.c), Rng(seed, run), _stream(stream)),
+           "smc_init_from_prior")
+
+
+def smc_correct(model, pop, t_from, t_max, check_every=1, rss_min=0.5, group_logwbar=None,
+                want_rss=True, stream=None):
+    """Returns (t_to, rss or None, group_logwbar tensor [J])."""
+    glwb = group_logwbar if group_logwbar is not None else torch.empty(
+        pop.J, dtype=torch.float64, device=model.device)
+    t_to = C.c_int64(0)
+    rss = C.c_double(0.0)
+    _check(lib().smc_correct(model.h, C.byref(pop.c), t_from, t_max, check_every, rss_min,
+                             _ptr(glwb), C.byref(t_to), C.byref(rss) if want_rss else None,
+                             _stream(stream)), "smc_correct")
+    return t_to.value, (rss.value if want_rss else None), glwb
+
+
+def smc_resample(model, pop, scheme=SMC_RESAMPLE_RESIDUAL, seed=1, run=0, cycle=1,
+                 stream=None):
+    _check(lib().smc_resample(model.h, C.byref(pop.c), scheme, Rng(seed, run), cycle,
+                              _stream(stream)), "smc_resample")
+
+
+def smc_particle_moments(model, pop, mh, mean=None, cov=None, hchol=None, stream=None):
+    if hchol is None:
+        hchol = torch.zeros((model.d, model.d), dtype=torch.float64, device=model.device)
+    _check(lib().smc_particle_moments(model.h, C.byref(pop.c), _ptr(mh), _ptr(mean), _ptr(cov),
+                                      _ptr(hchol), _stream(stream)), "smc_particle_moments")
+    return hchol
+
+
+def smc_mutate(model, pop, t, hchol, seed, run=0, cycle=1, it=1, kernel=SMC_KERNEL_RW,
+               n_accept=None, accepted=None, stream=None):
+    if n_accept is None:
+        n_accept = torch.zeros(1, dtype=torch.int64, device=model.device)
+    _check(lib().smc_mutate(model.h, C.byref(pop.c), t, kernel, _ptr(hchol), Rng(seed, run),
+                            cycle, it, _ptr(n_accept), _ptr(accepted), _stream(stream)),
+           "smc_mutate")
+    return n_accept
+
+
+def smc_loglik(model, theta, t, state_out=None, stream=None):
+    P = int(theta.shape[1])
+    out = torch.empty(P, dtype=torch.float64, device=model.device)
+    _check(lib().smc_loglik(model.h, P, _ptr(theta), t, _ptr(out), _ptr(state_out),
+                            _stream(stream)), "smc_loglik")
+    return out
+
+
+def smc_loglik_backward(model, theta, t, dloglik, stream=None):
+    P = int(theta.shape[1])
+    dtheta = torch.empty_like(theta)
+    nb = lib().smc_backward_ws_bytes(model.h, P, t)
+    ws = torch.empty(max(nb, 1), dtype=torch.uint8, device=model.device)
+    _check(lib().smc_loglik_backward(model.h, P, _ptr(theta), t, _ptr(dloglik), _ptr(dtheta),
+                                     _ptr(ws), nb, _stream(stream)), "smc_loglik_backward")
+    return dtheta
+
+
+def smc_log_ml(group_logwbar, stream=None):
+    g = group_logwbar.contiguous()
+    L, J = g.shape
+    out = torch.empty(3, dtype=torch.float64, device=g.device)
+    _check(lib().smc_log_ml(L, J, _ptr(g), _ptr(out), _stream(stream)), "smc_log_ml")
+    return out
+
+
+def smc_adapt_scale(n_accept, P, target_permille, mh, stream=None):
+    _check(lib().smc_adapt_scale(_ptr(n_accept), P, target_permille, _ptr(mh), _stream(stream)),
+           "smc_adapt_scale")
+
+
+def smc_rne(model, pop, stream=None):
+    out = torch.empty(1, dtype=torch.float64, device=model.device)
+    _check(lib().smc_rne(model.h, C.byref(pop.c), _ptr(out), _stream(stream)), "smc_rne")
+    return out
+
+
+def smc_flags(pop, stream=None):
+    f = C.c_int32(0)
+    _check(lib().smc_flags(C.byref(pop.c), C.byref(f), _stream(stream)), "smc_flags")
+    return f.value
+
+
+class Record:
+    """Host and device arrays of a run's design and outputs."""
+
+    def __init__(self, model, J, Lmax=512, RmaxRec=128):
+        import numpy as np
+        d, dev = model.d, model.device
+        self.Lmax, self.RmaxRec, self.J, self.d = Lmax, RmaxRec, J, d
+        self.t_end = np.zeros(Lmax, dtype=np.int64)
+        self.R = np.zeros(Lmax, dtype=np.int32)
+        self.rss = np.zeros(Lmax, dtype=np.float64)
+        self.n_accept = torch.zeros((Lmax, RmaxRec), dtype=torch.int64, device=dev)
+        self.hchol = torch.zeros((Lmax, RmaxRec, d, d), dtype=torch.float64, device=dev)
+        self.group_logwbar = torch.zeros((Lmax, J), dtype=torch.float64, device=dev)
+        self.log_ml = torch.zeros(3, dtype=torch.float64, device=dev)
+        self.c = RunRecord(0, 0, self.t_end.ctypes.data, self.R.ctypes.data, self.rss.ctypes.data,
+                           _ptr(self.n_accept), _ptr(self.hchol), _ptr(self.group_logwbar),
+                           _ptr(self.log_ml), 0, 0)
+
+    @property
+    def L(self):
+        return self.c.L
+
+    def summary(self):
+        L = self.L
+        lm = self.log_ml.cpu().numpy()
+        return dict(L=L, t_end=self.t_end[:L].copy(), R=self.R[:L].copy(), rss=self.rss[:L].copy(),
+                    log_ml=float(lm[0]), nse=float(lm[1]), log_ml_tilde=float(lm[2]),
+                    evals=self.c.evals, mh_steps=self.c.mh_steps,
+                    group_logwbar=self.group_logwbar[:L].cpu().numpy(),
+                    n_accept=self.n_accept[:L].cpu().numpy())
+
+
+def smc_run(model, pop, seed, run=0, check_every=1, force_every=0, D1=0.5, D2=0.2, Rbar=7,
+            kappa=3, stop_rule=0, E1=0.35, Rmax=100, scheme=SMC_RESAMPLE_RESIDUAL,
+            kernel=SMC_KERNEL_RW, record=None, replay=False, Lmax=512, RmaxRec=128,
+            stream=None):
+    """Whole simulator (adaptive, or replay of ``record``'s design)."""
+    rec = record if record is not None else Record(model, pop.J, Lmax, RmaxRec)
+    cfg = RunConfig(pop.J, pop.N, Rng(seed, run), check_every, force_every, D1, D2, Rbar, kappa,
+                    stop_rule, E1, Rmax, scheme, kernel, 1 if replay else 0, rec.Lmax,
+                    rec.RmaxRec, pop.max_chunk)
+    _check(lib().smc_run(model.h, C.byref(pop.c), C.byref(cfg), C.byref(rec.c), _stream(stream)),
+           "smc_run")
+    return rec

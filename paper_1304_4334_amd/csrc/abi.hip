@@ -1,0 +1,476 @@
+// C ABI of the simulator (declared in include/smc.h): argument validation,
+// workspace carve-up, the adaptive C-phase chunking, and the native driver
+// of Algorithms 1 and 2.
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <vector>
+
+#include "common.h"
+#include "launch.h"
+#include "smc.h"
+
+namespace smc {
+
+namespace {
+thread_local char g_err[512] = "";
+
+inline hipStream_t as_stream(void *s) { return reinterpret_cast<hipStream_t>(s); }
+
+inline char *wsb(const smc_particles *pop) { return reinterpret_cast<char *>(pop->ws); }
+
+template <typename T>
+inline T *ws_at(const smc_particles *pop, size_t off) {
+  return reinterpret_cast<T *>(wsb(pop) + off);
+}
+
+}  // namespace
+
+smc_status set_error(smc_status status, const char *fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof g_err, fmt, ap);
+  va_end(ap);
+  return status;
+}
+
+WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
+  const size_t P = (size_t)J * (size_t)N;
+  WsLayout L{};
+  size_t off = 0;
+  L.small = off;
+  off += align256(kSmallBytes);
+  L.rsscols = off;
+  off += align256(kMaxChunk * sizeof(double));
+  L.gather = off;
+  off += align256((size_t)(2 * m.d + m.S + 2) * P * sizeof(double));
+  L.cum = off;
+  off += align256(P * sizeof(double));
+  L.mpart = off;
+  off += align256((size_t)kMomBlocks * (16 + 256) * sizeof(double));
+  L.rpart = off;
+  off += align256((size_t)J * 2 * kDMax * sizeof(double));
+  L.wcols = off;
+  L.fixed = off;
+  return L;
+}
+
+namespace {
+
+smc_status check_model(const smc_model *m) {
+  if (!m) return set_error(SMC_E_INVALID_ARG, "model handle is NULL");
+  return SMC_OK;
+}
+
+smc_status check_pop(const smc_model *m, const smc_particles *pop, bool need_ws = true) {
+  if (!pop) return set_error(SMC_E_INVALID_ARG, "particles is NULL");
+  if (pop->J < 2 || pop->N < 2) return set_error(SMC_E_INVALID_ARG, "need J >= 2 and N >= 2");
+  if (pop->N > 16384) return set_error(SMC_E_UNSUPPORTED, "N > 16384 per group");
+  if ((int64_t)pop->J * pop->N > (int64_t)1 << 30)
+    return set_error(SMC_E_UNSUPPORTED, "more than 2^30 particles");
+  if (!pop->theta || !pop->logprior || !pop->loglik || !pop->logw || !pop->ancestor)
+    return set_error(SMC_E_INVALID_ARG, "a particle array is NULL");
+  if (m->dev.S > 0 && !pop->state) return set_error(SMC_E_INVALID_ARG, "state is NULL");
+  if (need_ws) {
+    if (!pop->ws) return set_error(SMC_E_INVALID_ARG, "workspace is NULL");
+    if (reinterpret_cast<uintptr_t>(pop->ws) & 255)
+      return set_error(SMC_E_INVALID_ARG, "workspace is not 256-byte aligned");
+    const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+    if (pop->ws_bytes < L.fixed)
+      return set_error(SMC_E_WORKSPACE, "workspace of %zu bytes < %zu", pop->ws_bytes, L.fixed);
+  }
+  return SMC_OK;
+}
+
+int64_t chunk_capacity(const smc_model *m, const smc_particles *pop) {
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  const size_t P = (size_t)pop->J * pop->N;
+  if (pop->ws_bytes <= L.wcols) return 0;
+  return std::min<int64_t>(kMaxChunk, (int64_t)((pop->ws_bytes - L.wcols) / (P * sizeof(double))));
+}
+
+int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8; }
+
+}  // namespace
+}  // namespace smc
+
+using namespace smc;
+
+extern "C" {
+
+const char *smc_status_string(smc_status s) {
+  switch (s) {
+    case SMC_OK: return "ok";
+    case SMC_E_INVALID_ARG: return "invalid argument";
+    case SMC_E_UNSUPPORTED: return "unsupported";
+    case SMC_E_DEVICE: return "device error";
+    case SMC_E_NUMERIC: return "numerical failure";
+    case SMC_E_WORKSPACE: return "workspace too small";
+    default: return "unknown status";
+  }
+}
+
+const char *smc_last_error(void) { return g_err; }
+
+smc_status smc_model_create(const smc_model_desc *desc, smc_model **out) {
+  if (!desc || !out) return set_error(SMC_E_INVALID_ARG, "NULL description or output");
+  *out = nullptr;
+  if (desc->reserved != 0) return set_error(SMC_E_INVALID_ARG, "reserved field must be 0");
+  if (desc->T < 1) return set_error(SMC_E_INVALID_ARG, "T must be >= 1");
+  if (!desc->y) return set_error(SMC_E_INVALID_ARG, "y is NULL");
+  if (desc->precision != SMC_FP64 && desc->precision != SMC_FP32)
+    return set_error(SMC_E_INVALID_ARG, "precision %d", desc->precision);
+  DevModel d{};
+  d.kind = desc->kind;
+  d.K = desc->K;
+  d.shock = desc->shock;
+  d.nreg = desc->nreg;
+  d.prec = desc->precision;
+  d.T = desc->T;
+  d.y = desc->y;
+  d.y32 = desc->y32;
+  d.X = desc->X;
+  if (desc->kind == SMC_MODEL_LINREG) {
+    if (desc->nreg < 1 || desc->nreg > 4)
+      return set_error(SMC_E_UNSUPPORTED, "regression needs 1..4 regressors");
+    if (!desc->X) return set_error(SMC_E_INVALID_ARG, "X is NULL");
+    if (desc->precision != SMC_FP64)
+      return set_error(SMC_E_UNSUPPORTED, "the regression runs in FP64 only");
+    d.d = desc->nreg + 1;
+    d.S = 0;
+  } else if (desc->kind == SMC_MODEL_EGARCH) {
+    if (desc->K < 1 || desc->K > 2) return set_error(SMC_E_UNSUPPORTED, "EGARCH needs K in {1,2}");
+    if (desc->shock != SMC_SHOCK_GAUSS && desc->shock != SMC_SHOCK_STUDENT_T)
+      return set_error(SMC_E_INVALID_ARG, "shock %d", desc->shock);
+    if (desc->precision == SMC_FP32 && !desc->y32)
+      return set_error(SMC_E_INVALID_ARG, "FP32 recursion needs y32");
+    d.d = 2 + 3 * desc->K + (desc->shock == SMC_SHOCK_STUDENT_T ? 1 : 0);
+    d.S = desc->K + 1;
+  } else {
+    return set_error(SMC_E_INVALID_ARG, "model kind %d", desc->kind);
+  }
+  smc_model *m = new (std::nothrow) smc_model;
+  if (!m) return set_error(SMC_E_INVALID_ARG, "out of host memory");
+  m->dev = d;
+  *out = m;
+  return SMC_OK;
+}
+
+smc_status smc_model_destroy(smc_model *m) {
+  delete m;
+  return SMC_OK;
+}
+
+int32_t smc_model_dim(const smc_model *m) { return m ? m->dev.d : -1; }
+int32_t smc_model_state_dim(const smc_model *m) { return m ? m->dev.S : -1; }
+
+size_t smc_workspace_bytes(const smc_model *m, int32_t J, int32_t N, int64_t max_chunk) {
+  if (!m || J < 1 || N < 1) return 0;
+  if (max_chunk <= 0) max_chunk = kDefaultChunk;
+  if (max_chunk > kMaxChunk) max_chunk = kMaxChunk;
+  const WsLayout L = ws_layout(m->dev, J, N);
+  return L.wcols + (size_t)max_chunk * (size_t)J * (size_t)N * sizeof(double);
+}
+
+smc_status smc_init_from_prior(const smc_model *m, smc_particles *pop, smc_rng rng,
+                               void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop, false))) return st;
+  const int64_t P = (int64_t)pop->J * pop->N;
+  return launch_init(m->dev, P, rng.seed, rng.run, pop->theta, pop->logprior, pop->loglik,
+                     pop->state, pop->logw, as_stream(stream));
+}
+
+smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
+                       int64_t check_every, double rss_min, double *group_logwbar,
+                       int64_t *t_to, double *rss, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!group_logwbar || !t_to) return set_error(SMC_E_INVALID_ARG, "NULL output");
+  if (t_from < 0 || t_max > m->dev.T || t_from > t_max)
+    return set_error(SMC_E_INVALID_ARG, "dates 0 <= t_from <= t_max <= T violated");
+  if (check_every < 1) return set_error(SMC_E_INVALID_ARG, "check_every < 1");
+  hipStream_t s = as_stream(stream);
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  double *rsscols = ws_at<double>(pop, L.rsscols);
+  double *W = ws_at<double>(pop, L.wcols);
+  if ((st = fill_f64(pop->logw, P, 0.0, s))) return st;
+  int64_t t_stop = t_max;
+  double rss_at_stop = 1.0;
+  const bool adaptive = rss_min > 0.0 && t_from < t_max;
+  if (!adaptive) {
+    if (t_max > t_from &&
+        (st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t_from,
+                             t_max, s)))
+      return st;
+    if (rss) {
+      if ((st = launch_rss_cols(pop->logw, P, 1, rsscols, s))) return st;
+      if (hipMemcpyAsync(&rss_at_stop, rsscols, sizeof(double), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "correct: reading the RSS failed");
+    }
+  } else {
+    const int64_t cap = chunk_capacity(m, pop);
+    if (cap < 1) return set_error(SMC_E_WORKSPACE, "workspace has no room for C-phase chunks");
+    int64_t chunk = std::min<int64_t>(16, cap);
+    int64_t t = t_from;
+    std::vector<int64_t> dates;
+    std::vector<double> host_rss;
+    bool stopped = false;
+    while (!stopped) {
+      const int64_t t1 = std::min(t + chunk, t_max);
+      dates.clear();
+      for (int64_t u = t + 1; u <= t1; ++u)
+        if (u % check_every == 0 || u == t_max) dates.push_back(u);
+      if (dates.empty()) {
+        if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
+                                 t1, s)))
+          return st;
+        t = t1;
+        chunk = std::min(2 * chunk, cap);
+        continue;
+      }
+      if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, t, t1, check_every,
+                             t_max, W, s)))
+        return st;
+      const int64_t nc = (int64_t)dates.size();
+      if ((st = launch_rss_cols(W, P, nc, rsscols, s))) return st;
+      host_rss.resize(nc);
+      if (hipMemcpyAsync(host_rss.data(), rsscols, nc * sizeof(double), hipMemcpyDeviceToHost,
+                         s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "correct: reading the RSS failed");
+      int64_t stop_col = -1;
+      for (int64_t c = 0; c < nc; ++c)
+        if (host_rss[c] < rss_min) {
+          stop_col = c;
+          break;
+        }
+      const int64_t t_commit = stop_col >= 0 ? dates[stop_col] : t1;
+      if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
+                               t_commit, s)))
+        return st;
+      rss_at_stop = stop_col >= 0 ? host_rss[stop_col] : host_rss[nc - 1];
+      t = t_commit;
+      if (stop_col >= 0 || t >= t_max) stopped = true;
+      chunk = std::min(2 * chunk, cap);
+    }
+    t_stop = t;
+  }
+  if ((st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s))) return st;
+  *t_to = t_stop;
+  if (rss) *rss = rss_at_stop;
+  return SMC_OK;
+}
+
+smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, smc_rng rng,
+                        int32_t cycle, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (scheme != SMC_RESAMPLE_RESIDUAL && scheme != SMC_RESAMPLE_MULTINOMIAL)
+    return set_error(SMC_E_INVALID_ARG, "resampling scheme %d", scheme);
+  hipStream_t s = as_stream(stream);
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  if ((st = launch_resample(pop->logw, pop->J, pop->N, scheme, rng.seed, rng.run,
+                            (uint64_t)cycle, pop->ancestor, ws_at<double>(pop, L.cum),
+                            ws_at<int32_t>(pop, L.small + kSmallFlags), s)))
+    return st;
+  return launch_gather(pop->ancestor, P, m->dev.d, m->dev.S, state_bytes(m), pop->theta,
+                       pop->logprior, pop->loglik, pop->state, pop->grad,
+                       ws_at<double>(pop, L.gather), s);
+}
+
+smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, const int32_t *mh,
+                                double *mean, double *cov, double *hchol, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!mh || !hchol) return set_error(SMC_E_INVALID_ARG, "mh and hchol are required");
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  double *mean_ws = mean ? mean : ws_at<double>(pop, L.small + kSmallMean);
+  return launch_moments(pop->theta, P, m->dev.d, mh, mean_ws, cov, hchol,
+                        ws_at<double>(pop, L.mpart), ws_at<int32_t>(pop, L.small + kSmallFlags),
+                        as_stream(stream));
+}
+
+smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t kernel,
+                      const double *hchol, smc_rng rng, int32_t cycle, int32_t iter,
+                      int64_t *n_accept, uint8_t *accepted, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop, false))) return st;
+  if (!hchol || !n_accept) return set_error(SMC_E_INVALID_ARG, "hchol and n_accept are required");
+  if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date t out of range");
+  const int64_t P = (int64_t)pop->J * pop->N;
+  if (kernel == SMC_KERNEL_RW)
+    return launch_mutate_rw(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
+                            hchol, rng.seed, rng.run, (uint64_t)cycle, (uint64_t)iter, n_accept,
+                            accepted, as_stream(stream));
+  if (kernel == SMC_KERNEL_MALA)
+    return set_error(SMC_E_UNSUPPORTED, "Langevin kernel not built");
+  return set_error(SMC_E_INVALID_ARG, "kernel %d", kernel);
+}
+
+smc_status smc_loglik(const smc_model *m, int64_t P, const double *theta, int64_t t,
+                      double *loglik, void *state_out, void *stream) {
+  smc_status st;
+  if ((st = check_model(m))) return st;
+  if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date t out of range");
+  if (P == 0) return SMC_OK;
+  if (P < 0 || !theta || !loglik) return set_error(SMC_E_INVALID_ARG, "bad loglik arguments");
+  return launch_loglik(m->dev, P, theta, t, loglik, state_out, as_stream(stream));
+}
+
+size_t smc_backward_ws_bytes(const smc_model *m, int64_t P, int64_t t) {
+  (void)m;
+  (void)P;
+  (void)t;
+  return 0;
+}
+
+smc_status smc_loglik_backward(const smc_model *m, int64_t P, const double *theta, int64_t t,
+                               const double *dloglik, double *dtheta, void *ws, size_t ws_bytes,
+                               void *stream) {
+  (void)m; (void)P; (void)theta; (void)t; (void)dloglik; (void)dtheta; (void)ws;
+  (void)ws_bytes; (void)stream;
+  return set_error(SMC_E_UNSUPPORTED, "adjoint kernel not built");
+}
+
+smc_status smc_log_ml(int32_t L, int32_t J, const double *group_logwbar, double *out,
+                      void *stream) {
+  if (L < 1 || J < 2 || !group_logwbar || !out)
+    return set_error(SMC_E_INVALID_ARG, "need L >= 1, J >= 2 and device arrays");
+  return launch_log_ml(L, J, group_logwbar, out, as_stream(stream));
+}
+
+smc_status smc_adapt_scale(const int64_t *n_accept, int64_t P, int32_t target_permille,
+                           int32_t *mh, void *stream) {
+  if (!n_accept || !mh || P < 1 || target_permille < 0 || target_permille > 1000)
+    return set_error(SMC_E_INVALID_ARG, "bad adapt_scale arguments");
+  return launch_adapt(n_accept, P, target_permille, mh, as_stream(stream));
+}
+
+smc_status smc_rne(const smc_model *m, const smc_particles *pop, double *rne, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!rne) return set_error(SMC_E_INVALID_ARG, "rne is NULL");
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  return launch_rne(pop->theta, pop->J, pop->N, m->dev.d, ws_at<double>(pop, L.rpart), rne,
+                    as_stream(stream));
+}
+
+smc_status smc_flags(const smc_particles *pop, int32_t *flags, void *stream) {
+  if (!pop || !pop->ws || !flags) return set_error(SMC_E_INVALID_ARG, "bad flags arguments");
+  hipStream_t s = as_stream(stream);
+  int32_t *dflags = reinterpret_cast<int32_t *>(reinterpret_cast<char *>(pop->ws) + kSmallFlags);
+  if (hipMemcpyAsync(flags, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "reading flags failed");
+  return fill_i32(dflags, 1, 0, s);
+}
+
+smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                   smc_run_record *rec, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!cfg || !rec) return set_error(SMC_E_INVALID_ARG, "NULL config or record");
+  if (cfg->J != pop->J || cfg->N != pop->N)
+    return set_error(SMC_E_INVALID_ARG, "config and population shapes differ");
+  if (!rec->t_end || !rec->R || !rec->rss || !rec->n_accept || !rec->hchol ||
+      !rec->group_logwbar || !rec->log_ml)
+    return set_error(SMC_E_INVALID_ARG, "a record array is NULL");
+  if (cfg->Lmax < 1 || cfg->RmaxRec < 1 || cfg->check_every < 1 || cfg->force_every < 0)
+    return set_error(SMC_E_INVALID_ARG, "bad record capacity or check spacing");
+  if (cfg->kernel != SMC_KERNEL_RW)
+    return set_error(SMC_E_UNSUPPORTED, "only the random-walk kernel is built");
+  hipStream_t s = as_stream(stream);
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const int32_t d = m->dev.d;
+  const int64_t T = m->dev.T;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  int32_t *mh = ws_at<int32_t>(pop, L.small + kSmallMh);
+  int32_t *dflags = ws_at<int32_t>(pop, L.small + kSmallFlags);
+  if ((st = fill_i32(dflags, 1, 0, s))) return st;
+  if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
+  if ((st = smc_init_from_prior(m, pop, cfg->rng, stream))) return st;
+  int64_t t = 0, evals = 0, steps = 0;
+  int32_t l = 0;
+  const int32_t target = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
+  while (t < T) {
+    if (l >= cfg->Lmax) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
+    int64_t t_stop = T;
+    if (cfg->force_every > 0) t_stop = std::min(t_stop, (t / cfg->force_every + 1) * cfg->force_every);
+    if (cfg->replay) {
+      t_stop = rec->t_end[l];
+      if (t_stop <= t || t_stop > T)
+        return set_error(SMC_E_INVALID_ARG, "replayed date %lld out of order", (long long)t_stop);
+    }
+    int64_t t_new = t;
+    double rss = NAN;
+    if ((st = smc_correct(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
+                          rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
+                          cfg->replay ? nullptr : &rss, stream)))
+      return st;
+    evals += P * (t_new - t);
+    if ((st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream))) return st;
+    int32_t R = cfg->replay ? rec->R[l] : (rss < cfg->D2 ? cfg->kappa * cfg->Rbar : cfg->Rbar);
+    if (R < 1) return set_error(SMC_E_INVALID_ARG, "R_l < 1 in cycle %d", l);
+    if ((st = fill_i32(mh, 1, 5, s))) return st;
+    int32_t r = 0;
+    for (;;) {
+      ++r;
+      if (r > cfg->RmaxRec)
+        return set_error(SMC_E_INVALID_ARG, "record holds only %d iterations", cfg->RmaxRec);
+      double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
+      int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
+      if (!cfg->replay && (st = smc_particle_moments(m, pop, mh, nullptr, nullptr, hl, stream)))
+        return st;
+      if ((st = smc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->rng, l + 1, r, nacc, nullptr,
+                           stream)))
+        return st;
+      evals += P * t_new;
+      ++steps;
+      if (!cfg->replay && (st = smc_adapt_scale(nacc, P, target, mh, stream))) return st;
+      if (cfg->replay || cfg->stop_rule == 0) {
+        if (r >= R) break;
+      } else {
+        double *rne_d = ws_at<double>(pop, L.small + kSmallRne);
+        if ((st = smc_rne(m, pop, rne_d, stream))) return st;
+        double rne = 0.0;
+        if (hipMemcpyAsync(&rne, rne_d, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+          return set_error(SMC_E_DEVICE, "reading the RNE failed");
+        if (rne > cfg->E1 || r >= cfg->Rmax) break;
+      }
+    }
+    if (!cfg->replay) {
+      rec->t_end[l] = t_new;
+      rec->R[l] = r;
+    }
+    rec->rss[l] = rss;
+    t = t_new;
+    ++l;
+    int32_t fl = 0;
+    if (!cfg->replay) {
+      if (hipMemcpyAsync(&fl, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "reading flags failed");
+      if (fl) {
+        rec->L = l;
+        return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", fl, l);
+      }
+    }
+  }
+  rec->L = l;
+  rec->evals = evals;
+  rec->mh_steps = steps;
+  if ((st = smc_log_ml(l, pop->J, rec->group_logwbar, rec->log_ml, stream))) return st;
+  return SMC_OK;
+}
+
+}  // extern "C"

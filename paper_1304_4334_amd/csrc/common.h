@@ -1,0 +1,72 @@
+// Shared host/device definitions of the HIP library (gfx950 only).
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "smc.h"
+
+namespace smc {
+
+constexpr int kDMax = 16;      // largest parameter dimension (padded MFMA tile)
+constexpr int kSMax = 4;       // largest recursion state
+constexpr int kBlock = 256;    // threads per block of the bandwidth-shaped kernels
+
+// Philox purposes (counter word 3, low byte).
+enum Purpose : uint64_t { kPrior = 1, kResample = 2, kProposal = 3, kAccept = 4 };
+
+// Everything a kernel needs to know about a model, passed by value.
+struct DevModel {
+  int32_t kind;
+  int32_t K;
+  int32_t shock;
+  int32_t nreg;
+  int32_t prec;
+  int32_t d;
+  int32_t S;
+  int32_t pad;
+  int64_t T;
+  const double *y;
+  const float *y32;
+  const double *X;
+};
+
+// Workspace carve-up (offsets in bytes, each 256-aligned).  The speculative
+// C-phase columns come last, so their capacity follows from the workspace size.
+struct WsLayout {
+  size_t small;    // flags, mh, counters, small vectors (kSmallBytes)
+  size_t rsscols;  // [kMaxChunk] doubles
+  size_t gather;   // [2d + S + 2][P] doubles
+  size_t cum;      // [P] doubles (resample running sums)
+  size_t mpart;    // [kMomBlocks][16 + 256] doubles (moments)
+  size_t rpart;    // [J][2 * kDMax] doubles (RNE)
+  size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
+  size_t fixed;    // bytes before wcols
+};
+
+constexpr int64_t kMaxChunk = 4096;
+constexpr int64_t kDefaultChunk = 256;
+constexpr int kMomBlocks = 256;
+
+// Offsets inside the `small` region.
+constexpr size_t kSmallFlags = 0;    // int32
+constexpr size_t kSmallMh = 16;      // int32
+constexpr size_t kSmallNacc = 32;    // int64
+constexpr size_t kSmallRss = 64;     // double
+constexpr size_t kSmallRne = 72;     // double
+constexpr size_t kSmallMean = 256;   // double[16]
+constexpr size_t kSmallCov = 512;    // double[256]
+constexpr size_t kSmallHchol = 2560; // double[256]
+constexpr size_t kSmallStop = 4608;  // int64: first stop column
+constexpr size_t kSmallBytes = 8192;
+
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N);
+
+}  // namespace smc
+
+// Opaque model handle.
+struct smc_model {
+  smc::DevModel dev;
+};

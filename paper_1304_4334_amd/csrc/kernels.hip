@@ -1,0 +1,703 @@
+// HIP kernels of the sequential posterior simulator for gfx950 (CDNA4) and
+// their host-side launchers.
+//
+// Geometry: the likelihood kernels map one particle to one lane and launch
+// 64-thread blocks (one wave each), so a population spreads over as many
+// compute units as it has waves; observations are wave-uniform and reach the
+// lanes through scalar loads into SGPRs.  The bandwidth-shaped kernels
+// (reductions, resampling, gathers) use 256-thread blocks.  Every reduction
+// combines in a fixed order, so results do not depend on timing.
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include "common.h"
+#include "launch.h"
+#include "model.h"
+#include "reduce.h"
+#include "rng.h"
+
+namespace smc {
+
+namespace {
+
+inline dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+inline smc_status launch_status(const char *what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(SMC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return SMC_OK;
+}
+
+template <typename T>
+__device__ __forceinline__ T *typed(void *p) { return reinterpret_cast<T *>(p); }
+template <typename T>
+__device__ __forceinline__ const T *typed(const void *p) { return reinterpret_cast<const T *>(p); }
+
+}  // namespace
+
+// ------------------------------------------------------------------ fills --
+__global__ void k_fill_f64(double *a, int64_t n, double v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+__global__ void k_fill_i64(int64_t *a, int64_t n, int64_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+__global__ void k_fill_i32(int32_t *a, int64_t n, int32_t v) {
+  const int64_t i = blockIdx.x * (int64_t)blockDim.x + threadIdx.x;
+  if (i < n) a[i] = v;
+}
+
+smc_status fill_f64(double *a, int64_t n, double v, hipStream_t s) {
+  if (n <= 0) return SMC_OK;
+  hipLaunchKernelGGL(k_fill_f64, grid_for(n, kBlock), dim3(kBlock), 0, s, a, n, v);
+  return launch_status("fill_f64");
+}
+smc_status fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t s) {
+  if (n <= 0) return SMC_OK;
+  hipLaunchKernelGGL(k_fill_i64, grid_for(n, kBlock), dim3(kBlock), 0, s, a, n, v);
+  return launch_status("fill_i64");
+}
+smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
+  if (n <= 0) return SMC_OK;
+  hipLaunchKernelGGL(k_fill_i32, grid_for(n, kBlock), dim3(kBlock), 0, s, a, n, v);
+  return launch_status("fill_i32");
+}
+
+// --------------------------------------------------------- prior (a1) ------
+template <class M>
+__global__ void __launch_bounds__(64) k_init(DevModel dm, int64_t P, uint64_t seed, uint64_t run,
+                                             double *theta, double *logprior, double *loglik,
+                                             void *state, double *logw) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D];
+  M::prior_draw(seed, run, (uint64_t)p, th);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) theta[i * P + p] = th[i];
+  logprior[p] = M::logprior(th);
+  loglik[p] = 0.0;
+  logw[p] = 0.0;
+  using R = typename M::R;
+#pragma unroll
+  for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state)[k * P + p] = (R)0;
+}
+
+// ------------------------------------------------------------ C phase (a2) --
+// Speculative pass: from the committed state at t0, evaluate observations
+// t0+1..t1 and record the running log weight at every check date, without
+// committing anything.
+template <class M>
+__global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
+                                              const void *state, const double *logw, int64_t t0,
+                                              int64_t t1, int64_t check_every, int64_t t_max,
+                                              double *W) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
+  double lw = logw[p];
+  int64_t col = 0;
+  for (int64_t s = t0 + 1; s <= t1; ++s) {
+    double lp = Eval<M>::advance(dm, par, st, s - 1, s);
+    if (isnan(lp)) lp = -INFINITY;
+    lw += lp;
+    if (s % check_every == 0 || s == t_max) {
+      W[col * P + p] = lw;
+      ++col;
+    }
+  }
+}
+
+// Commit: advance from t0 to t1, adding the log densities to logw and loglik.
+template <class M>
+__global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
+                                                void *state, double *logw, double *loglik,
+                                                int64_t t0, int64_t t1) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (k < SS) ? typed<R>(state)[k * P + p] : (R)0;
+  double lp = Eval<M>::advance(dm, par, st, t0, t1);
+  if (isnan(lp)) lp = -INFINITY;
+  logw[p] += lp;
+  loglik[p] += lp;
+#pragma unroll
+  for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
+}
+
+// RSS of each recorded column: (sum e)^2 / (P sum e^2), e = exp(w - max w).
+__global__ void __launch_bounds__(256) k_rss_cols(const double *W, int64_t P, double *rss) {
+  __shared__ double sh[4];
+  const double *w = W + blockIdx.x * P;
+  double mx = -INFINITY;
+  for (int64_t p = threadIdx.x; p < P; p += kBlock) mx = fmax(mx, w[p]);
+  mx = block_reduce<OpMax<double>>(mx, sh);
+  double s1 = 0.0, s2 = 0.0;
+  if (mx > -INFINITY) {
+    for (int64_t p = threadIdx.x; p < P; p += kBlock) {
+      const double e = exp(w[p] - mx);
+      s1 += e;
+      s2 = fma(e, e, s2);
+    }
+  }
+  s1 = block_reduce<OpSum<double>>(s1, sh);
+  s2 = block_reduce<OpSum<double>>(s2, sh);
+  if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
+}
+
+// log wbar_j = log(N^-1 sum_n exp(logw_jn)) per group (Section 4.2).
+__global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32_t N,
+                                                       double *out) {
+  __shared__ double sh[4];
+  const double *w = logw + (int64_t)blockIdx.x * N;
+  double mx = -INFINITY;
+  for (int n = threadIdx.x; n < N; n += kBlock) mx = fmax(mx, w[n]);
+  mx = block_reduce<OpMax<double>>(mx, sh);
+  double s = 0.0;
+  if (mx > -INFINITY)
+    for (int n = threadIdx.x; n < N; n += kBlock) s += exp(w[n] - mx);
+  s = block_reduce<OpSum<double>>(s, sh);
+  if (threadIdx.x == 0) out[blockIdx.x] = (mx > -INFINITY) ? mx + log(s / (double)N) : -INFINITY;
+}
+
+// ------------------------------------------------------------ S phase (a3) --
+// One block per group.  Counts live in LDS (dynamic, N int32); the running
+// residual sums in the workspace.
+__global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
+                                                  uint64_t seed, uint64_t run, uint64_t cycle,
+                                                  int32_t *anc, double *cum_ws, int32_t *flags) {
+  extern __shared__ int32_t cnt[];
+  __shared__ double shd[kBlock];
+  __shared__ int64_t shi[kBlock];
+  const int j = blockIdx.x;
+  const int64_t base = (int64_t)j * N;
+  const double *lw = logw + base;
+  double *cum = cum_ws + base;
+  const int tid = threadIdx.x;
+
+  double mx = -INFINITY;
+  for (int n = tid; n < N; n += kBlock) mx = fmax(mx, lw[n]);
+  mx = block_reduce<OpMax<double>>(mx, shd);
+  if (!(mx > -INFINITY)) {
+    for (int n = tid; n < N; n += kBlock) anc[base + n] = (int32_t)(base + n);
+    if (tid == 0) atomicOr(flags, SMC_FLAG_DEAD_GROUP);
+    return;
+  }
+  double se = 0.0;
+  for (int n = tid; n < N; n += kBlock) se += exp(lw[n] - mx);
+  se = block_reduce<OpSum<double>>(se, shd);
+
+  // Thread-contiguous chunks for the scans.
+  const int m = (N + kBlock - 1) / kBlock;
+  const int lo = min(tid * m, N), hi = min(lo + m, N);
+  double rsum = 0.0;
+  int64_t csum = 0;
+  for (int n = lo; n < hi; ++n) {
+    const double nw = ((double)N * exp(lw[n] - mx)) / se;  // N W_n
+    const double c = (scheme == SMC_RESAMPLE_RESIDUAL) ? floor(nw) : 0.0;
+    rsum += nw - c;
+    cum[n] = rsum;
+    cnt[n] = (int32_t)c;
+    csum += (int64_t)c;
+  }
+  double rtot;
+  const double roff = block_inclusive_scan<double>(rsum, shd, rtot) - rsum;
+  for (int n = lo; n < hi; ++n) cum[n] += roff;
+  int64_t ctot;
+  (void)block_inclusive_scan<int64_t>(csum, shi, ctot);
+  __syncthreads();
+  const double total = cum[N - 1];
+  const int64_t R = (int64_t)N - ctot;
+  for (int64_t k = tid; k < R; k += kBlock) {
+    const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k >> 2), kResample);
+    const uint64_t x = (k & 3) == 0 ? w.x0 : (k & 3) == 1 ? w.x1 : (k & 3) == 2 ? w.x2 : w.x3;
+    const double target = u01_co(x) * total;
+    int a_lo = 0, a_hi = N;  // first n with cum[n] > target
+    while (a_lo < a_hi) {
+      const int mid = (a_lo + a_hi) >> 1;
+      if (cum[mid] > target) a_hi = mid;
+      else a_lo = mid + 1;
+    }
+    int a = a_lo;
+    if (a >= N) {
+      a = N - 1;
+      while (a > 0 && !(cum[a] > cum[a - 1])) --a;
+    }
+    atomicAdd(&cnt[a], 1);
+  }
+  __syncthreads();
+  int64_t my = 0;
+  for (int n = lo; n < hi; ++n) my += cnt[n];
+  int64_t tot2;
+  int64_t pos = block_inclusive_scan<int64_t>(my, shi, tot2) - my;
+  for (int n = lo; n < hi; ++n)
+    for (int c = 0; c < cnt[n] && pos < N; ++c) anc[base + pos++] = (int32_t)(base + n);
+}
+
+struct GatherArgs {
+  const int32_t *anc;
+  int64_t P;
+  int32_t d, S, st_bytes, has_grad;
+  double *theta, *logprior, *loglik, *grad;
+  void *state;
+  double *tmp;  // [2d + S + 2][P]
+};
+
+__global__ void __launch_bounds__(256) k_gather(GatherArgs g) {
+  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= g.P) return;
+  const int64_t a = g.anc[p];
+  const int64_t P = g.P;
+  int r = 0;
+  for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.theta[i * P + a];
+  g.tmp[r++ * P + p] = g.logprior[a];
+  g.tmp[r++ * P + p] = g.loglik[a];
+  for (int k = 0; k < g.S; ++k, ++r)
+    g.tmp[r * P + p] = g.st_bytes == 8 ? typed<double>(g.state)[k * P + a]
+                                       : (double)typed<float>(g.state)[k * P + a];
+  if (g.has_grad)
+    for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.grad[i * P + a];
+}
+
+__global__ void __launch_bounds__(256) k_scatter_back(GatherArgs g) {
+  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
+  if (p >= g.P) return;
+  const int64_t P = g.P;
+  int r = 0;
+  for (int i = 0; i < g.d; ++i, ++r) g.theta[i * P + p] = g.tmp[r * P + p];
+  g.logprior[p] = g.tmp[r++ * P + p];
+  g.loglik[p] = g.tmp[r++ * P + p];
+  for (int k = 0; k < g.S; ++k, ++r) {
+    if (g.st_bytes == 8) typed<double>(g.state)[k * P + p] = g.tmp[r * P + p];
+    else typed<float>(g.state)[k * P + p] = (float)g.tmp[r * P + p];
+  }
+  if (g.has_grad)
+    for (int i = 0; i < g.d; ++i, ++r) g.grad[i * P + p] = g.tmp[r * P + p];
+}
+
+// ----------------------------------------------- particle moments (a4) ----
+__global__ void __launch_bounds__(256) k_mean_partial(const double *theta, int64_t P, int32_t d,
+                                                      int64_t chunk, double *part) {
+  __shared__ double sh[4];
+  const int64_t p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  for (int i = 0; i < d; ++i) {
+    double s = 0.0;
+    for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) s += theta[i * P + p];
+    s = block_reduce<OpSum<double>>(s, sh);
+    if (threadIdx.x == 0) part[blockIdx.x * kDMax + i] = s;
+  }
+}
+
+__global__ void k_mean_final(const double *part, int32_t nb, int32_t d, int64_t P, double *mean) {
+  const int i = threadIdx.x;
+  if (i >= d) return;
+  double s = 0.0;
+  for (int b = 0; b < nb; ++b) s += part[b * kDMax + i];
+  mean[i] = s / (double)P;
+}
+
+// Centred cross products on the matrix cores: each wave accumulates
+// sum_p x_p x_p' with x_p = theta_p - mean (padded to 16) using
+// v_mfma_f64_16x16x4f64, four particles per instruction.  Operand layout
+// (measured on gfx950): lane l supplies element (row l%16, k = l/16) of A and
+// (k = l/16, col l%16) of B, so A = B' = the 16x4 block of centred
+// particles; accumulator register r of lane l holds element
+// (4r + l/16, l%16) of the 16x16 result.
+__global__ void __launch_bounds__(64) k_cross_partial(const double *theta, int64_t P, int32_t d,
+                                                      const double *mean, int64_t chunk,
+                                                      double *part) {
+  const int l = threadIdx.x;
+  const int i = l & 15, k = l >> 4;
+  const int64_t p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
+  const double mi = (i < d) ? mean[i] : 0.0;
+  typedef double double4v __attribute__((ext_vector_type(4)));
+  double4v acc = {0.0, 0.0, 0.0, 0.0};
+  for (int64_t q = p0; q < p1; q += 4) {
+    const int64_t p = q + k;
+    const double x = (i < d && p < p1) ? theta[i * P + p] - mi : 0.0;
+    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
+  }
+  double *out = part + blockIdx.x * 256;
+#pragma unroll
+  for (int r = 0; r < 4; ++r) out[(4 * r + k) * 16 + i] = acc[r];
+}
+
+// Sum the partial 16x16 blocks, scale by 1/(P-1), Cholesky (one lane), and
+// write hL = (mh/10) L.  A matrix that is not positive definite raises the
+// flag and yields hL = 0.
+__global__ void __launch_bounds__(64) k_cov_final(const double *part, int32_t nb, int32_t d,
+                                                  int64_t P, const int32_t *mh, double *cov_out,
+                                                  double *hchol, int32_t *flags) {
+  __shared__ double V[kDMax * kDMax];
+  __shared__ double L[kDMax * kDMax];
+  for (int e = threadIdx.x; e < 256; e += 64) {
+    double s = 0.0;
+    for (int b = 0; b < nb; ++b) s += part[b * 256 + e];
+    const int r = e >> 4, c = e & 15;
+    if (r < d && c < d) V[r * kDMax + c] = s / (double)(P - 1);
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    // symmetrise (the two triangles come from identical sums)
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < r; ++c) V[c * kDMax + r] = V[r * kDMax + c];
+    bool ok = true;
+    for (int r = 0; r < d && ok; ++r) {
+      for (int c = 0; c <= r; ++c) {
+        double s = V[r * kDMax + c];
+        for (int q = 0; q < c; ++q) s -= L[r * kDMax + q] * L[c * kDMax + q];
+        if (r == c) {
+          if (!(s > 0.0)) { ok = false; break; }
+          L[r * kDMax + r] = sqrt(s);
+        } else {
+          L[r * kDMax + c] = s / L[c * kDMax + c];
+        }
+      }
+    }
+    const double h = ok ? (double)(*mh) / 10.0 : 0.0;
+    if (!ok) atomicOr(flags, SMC_FLAG_NOT_PD);
+    for (int r = 0; r < d; ++r)
+      for (int c = 0; c < d; ++c) {
+        hchol[r * d + c] = (ok && c <= r) ? h * L[r * kDMax + c] : 0.0;
+        if (cov_out) cov_out[r * d + c] = V[r * kDMax + c];
+      }
+  }
+}
+
+// ------------------------------------------------------------ M phase (a5) --
+template <class M>
+__global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
+                                                  double *logprior, double *loglik, void *state,
+                                                  const double *__restrict__ hchol, uint64_t seed,
+                                                  uint64_t run, uint64_t cycle, uint64_t iter,
+                                                  unsigned long long *n_accept, uint8_t *accepted) {
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  int acc = 0;
+  if (p < P) {
+    double th[D], z[D], pr[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
+    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) s = fma(hchol[i * D + k], z[k], s);
+      pr[i] = th[i] + s;
+    }
+    const double lp1 = M::logprior(pr);
+    R st[SR];
+#pragma unroll
+    for (int k = 0; k < SR; ++k) st[k] = (R)0;
+    double ll1 = -INFINITY;
+    if (lp1 > -INFINITY) {
+      const auto par = M::params(pr);
+      ll1 = Eval<M>::advance(dm, par, st, 0, t);
+      const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]);
+      const U64x4 w = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+      acc = (log(u01_oo(w.x0)) < delta) ? 1 : 0;
+    }
+    if (acc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) theta[i * P + p] = pr[i];
+      logprior[p] = lp1;
+      loglik[p] = ll1;
+#pragma unroll
+      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
+    }
+    if (accepted) accepted[p] = (uint8_t)acc;
+  }
+  const unsigned long long mask = __ballot(acc);
+  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
+// ------------------------------------------------- standalone likelihood --
+template <class M>
+__global__ void __launch_bounds__(64) k_loglik(DevModel dm, int64_t P, const double *theta,
+                                               int64_t t, double *out, void *state_out) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (R)0;
+  out[p] = Eval<M>::advance(dm, par, st, 0, t);
+  if (state_out)
+#pragma unroll
+    for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state_out)[k * P + p] = st[k];
+}
+
+// ------------------------------------------------ step size, RNE, log-ML --
+__global__ void k_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille, int32_t *mh) {
+  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+  const int64_t n = *n_accept;
+  int32_t v = *mh + ((n * 1000 > (int64_t)target_permille * P) ? 1 : -1);
+  *mh = v < 1 ? 1 : (v > 10 ? 10 : v);
+}
+
+// Per group j and parameter i: the group mean and the within-group sum of
+// squared deviations.
+__global__ void __launch_bounds__(256) k_rne_group(const double *theta, int64_t P, int32_t N,
+                                                   int32_t d, double *part) {
+  __shared__ double sh[4];
+  const int j = blockIdx.x;
+  for (int i = 0; i < d; ++i) {
+    const double *x = theta + i * P + (int64_t)j * N;
+    double s = 0.0;
+    for (int n = threadIdx.x; n < N; n += kBlock) s += x[n];
+    const double mean = block_reduce<OpSum<double>>(s, sh) / (double)N;
+    double q = 0.0;
+    for (int n = threadIdx.x; n < N; n += kBlock) {
+      const double e = x[n] - mean;
+      q = fma(e, e, q);
+    }
+    q = block_reduce<OpSum<double>>(q, sh);
+    if (threadIdx.x == 0) {
+      part[(int64_t)j * 2 * kDMax + i] = mean;
+      part[(int64_t)j * 2 * kDMax + kDMax + i] = q;
+    }
+  }
+}
+
+// RNE_i = var-hat / v-hat with var-hat = (within SS + N sum_j (gbar_j - gbar)^2)
+// / (NJ - 1) and v-hat = N / (J - 1) sum_j (gbar_j - gbar)^2; mean over i.
+__global__ void k_rne_final(const double *part, int32_t J, int32_t N, int32_t d, double *rne) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int i = 0; i < d; ++i) {
+    double g = 0.0, w = 0.0;
+    for (int j = 0; j < J; ++j) {
+      g += part[(int64_t)j * 2 * kDMax + i];
+      w += part[(int64_t)j * 2 * kDMax + kDMax + i];
+    }
+    g /= (double)J;
+    double b = 0.0;
+    for (int j = 0; j < J; ++j) {
+      const double e = part[(int64_t)j * 2 * kDMax + i] - g;
+      b += e * e;
+    }
+    const double var = (w + (double)N * b) / ((double)N * J - 1.0);
+    const double vhat = (double)N * b / (double)(J - 1);
+    acc += var / vhat;
+  }
+  *rne = acc / (double)d;
+}
+
+// log wbar, its delta-method NSE and log wtilde from group_logwbar[L][J].
+__global__ void k_log_ml(int32_t L, int32_t J, const double *g, double *out) {
+  if (threadIdx.x != 0) return;
+  double mx = -INFINITY;
+  for (int j = 0; j < J; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
+    mx = fmax(mx, s);
+  }
+  double rbar = 0.0;
+  for (int j = 0; j < J; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
+    rbar += exp(s - mx);
+  }
+  rbar /= (double)J;
+  double ss = 0.0;
+  for (int j = 0; j < J; ++j) {
+    double s = 0.0;
+    for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
+    const double e = exp(s - mx) - rbar;
+    ss += e * e;
+  }
+  double lt = 0.0;
+  for (int l = 0; l < L; ++l) {
+    double m = -INFINITY;
+    for (int j = 0; j < J; ++j) m = fmax(m, g[(int64_t)l * J + j]);
+    double s = 0.0;
+    for (int j = 0; j < J; ++j) s += exp(g[(int64_t)l * J + j] - m);
+    lt += (m > -INFINITY) ? m + log(s / (double)J) : -INFINITY;
+  }
+  out[0] = mx + log(rbar);
+  out[1] = sqrt(ss / ((double)J * (J - 1))) / rbar;
+  out[2] = lt;
+}
+
+// ============================================================ launchers ====
+
+template <class F>
+smc_status dispatch(const DevModel &m, F &&f) {
+  if (m.kind == SMC_MODEL_LINREG) {
+    switch (m.nreg) {
+      case 1: return f(Tag<Linreg<1>>{});
+      case 2: return f(Tag<Linreg<2>>{});
+      case 3: return f(Tag<Linreg<3>>{});
+      case 4: return f(Tag<Linreg<4>>{});
+      default: return set_error(SMC_E_UNSUPPORTED, "regression with %d regressors", m.nreg);
+    }
+  }
+  const bool t = m.shock == SMC_SHOCK_STUDENT_T;
+  if (m.prec == SMC_FP64) {
+    if (m.K == 1) return t ? f(Tag<Egarch<1, 1, double>>{}) : f(Tag<Egarch<1, 0, double>>{});
+    if (m.K == 2) return t ? f(Tag<Egarch<2, 1, double>>{}) : f(Tag<Egarch<2, 0, double>>{});
+  } else {
+    if (m.K == 1) return t ? f(Tag<Egarch<1, 1, float>>{}) : f(Tag<Egarch<1, 0, float>>{});
+    if (m.K == 2) return t ? f(Tag<Egarch<2, 1, float>>{}) : f(Tag<Egarch<2, 0, float>>{});
+  }
+  return set_error(SMC_E_UNSUPPORTED, "EGARCH with K=%d", m.K);
+}
+
+smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
+                       double *logprior, double *loglik, void *state, double *logw,
+                       hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_init<M>, grid_for(P, 64), dim3(64), 0, s, m, P, seed, run, theta,
+                       logprior, loglik, state, logw);
+    return launch_status("init_from_prior");
+  });
+}
+
+smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
+                        const double *logw, int64_t t0, int64_t t1, int64_t check_every,
+                        int64_t t_max, double *W, hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_cscan<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw, t0,
+                       t1, check_every, t_max, W);
+    return launch_status("correct/scan");
+  });
+}
+
+smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
+                          double *logw, double *loglik, int64_t t0, int64_t t1, hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
+                       loglik, t0, t1);
+    return launch_status("correct/commit");
+  });
+}
+
+smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
+                           hipStream_t s) {
+  if (ncols <= 0) return SMC_OK;
+  hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kBlock), 0, s, W, P, rss);
+  return launch_status("correct/rss");
+}
+
+smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
+                                hipStream_t s) {
+  hipLaunchKernelGGL(k_group_logwbar, dim3(J), dim3(kBlock), 0, s, logw, N, out);
+  return launch_status("correct/group_logwbar");
+}
+
+smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
+                           uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
+                           double *cum_ws, int32_t *flags, hipStream_t s) {
+  hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), (size_t)N * sizeof(int32_t), s, logw, N,
+                     scheme, seed, run, cycle, anc, cum_ws, flags);
+  return launch_status("resample");
+}
+
+smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, int32_t st_bytes,
+                         double *theta, double *logprior, double *loglik, void *state,
+                         double *grad, double *tmp, hipStream_t s) {
+  GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
+               state, tmp};
+  hipLaunchKernelGGL(k_gather, grid_for(P, kBlock), dim3(kBlock), 0, s, g);
+  smc_status st = launch_status("resample/gather");
+  if (st) return st;
+  hipLaunchKernelGGL(k_scatter_back, grid_for(P, kBlock), dim3(kBlock), 0, s, g);
+  return launch_status("resample/scatter");
+}
+
+smc_status launch_moments(const double *theta, int64_t P, int32_t d, const int32_t *mh,
+                          double *mean, double *cov, double *hchol, double *part,
+                          int32_t *flags, hipStream_t s) {
+  const int64_t nb = std::min<int64_t>(kMomBlocks, (P + kBlock - 1) / kBlock);
+  const int64_t chunk = (P + nb - 1) / nb;
+  hipLaunchKernelGGL(k_mean_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, theta, P, d, chunk,
+                     part);
+  smc_status st = launch_status("moments/mean");
+  if (st) return st;
+  double *cpart = part + kMomBlocks * kDMax;
+  hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(64), 0, s, part, (int32_t)nb, d, P, mean);
+  if ((st = launch_status("moments/mean_final"))) return st;
+  const int64_t chunk4 = ((chunk + 3) / 4) * 4;
+  const int64_t nb2 = (P + chunk4 - 1) / chunk4;
+  hipLaunchKernelGGL(k_cross_partial, dim3((unsigned)nb2), dim3(64), 0, s, theta, P, d, mean,
+                     chunk4, cpart);
+  if ((st = launch_status("moments/cross"))) return st;
+  hipLaunchKernelGGL(k_cov_final, dim3(1), dim3(64), 0, s, cpart, (int32_t)nb2, d, P, mh, cov,
+                     hchol, flags);
+  return launch_status("moments/cholesky");
+}
+
+smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
+                            double *logprior, double *loglik, void *state, const double *hchol,
+                            uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
+                            int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta, logprior,
+                       loglik, state, hchol, seed, run, cycle, iter,
+                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
+    return launch_status("mutate");
+  });
+}
+
+smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                         double *out, void *state_out, hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_loglik<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, t, out,
+                       state_out);
+    return launch_status("loglik");
+  });
+}
+
+smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,
+                        int32_t *mh, hipStream_t s) {
+  hipLaunchKernelGGL(k_adapt, dim3(1), dim3(64), 0, s, n_accept, P, target_permille, mh);
+  return launch_status("adapt_scale");
+}
+
+smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, double *part,
+                      double *rne, hipStream_t s) {
+  const int64_t P = (int64_t)J * N;
+  hipLaunchKernelGGL(k_rne_group, dim3(J), dim3(kBlock), 0, s, theta, P, N, d, part);
+  smc_status st = launch_status("rne/group");
+  if (st) return st;
+  hipLaunchKernelGGL(k_rne_final, dim3(1), dim3(64), 0, s, part, J, N, d, rne);
+  return launch_status("rne/final");
+}
+
+smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s) {
+  hipLaunchKernelGGL(k_log_ml, dim3(1), dim3(64), 0, s, L, J, g, out);
+  return launch_status("log_ml");
+}
+
+}  // namespace smc

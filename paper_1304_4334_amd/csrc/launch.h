@@ -1,0 +1,60 @@
+// Host-side launchers of the device kernels (kernels.hip) used by the C ABI
+// (abi.hip).  Each enqueues on the given stream and returns SMC_OK or
+// SMC_E_DEVICE.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <algorithm>
+
+#include "common.h"
+
+namespace smc {
+
+template <class T>
+struct Tag {
+  using type = T;
+};
+
+// Records a thread-local message and returns `status`.
+smc_status set_error(smc_status status, const char *fmt, ...);
+
+smc_status fill_f64(double *a, int64_t n, double v, hipStream_t s);
+smc_status fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t s);
+smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);
+
+smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
+                       double *logprior, double *loglik, void *state, double *logw,
+                       hipStream_t s);
+smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
+                        const double *logw, int64_t t0, int64_t t1, int64_t check_every,
+                        int64_t t_max, double *W, hipStream_t s);
+smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
+                          double *logw, double *loglik, int64_t t0, int64_t t1, hipStream_t s);
+smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
+                           hipStream_t s);
+smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
+                                hipStream_t s);
+smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
+                           uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
+                           double *cum_ws, int32_t *flags, hipStream_t s);
+smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, int32_t st_bytes,
+                         double *theta, double *logprior, double *loglik, void *state,
+                         double *grad, double *tmp, hipStream_t s);
+smc_status launch_moments(const double *theta, int64_t P, int32_t d, const int32_t *mh,
+                          double *mean, double *cov, double *hchol, double *part,
+                          int32_t *flags, hipStream_t s);
+smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
+                            double *logprior, double *loglik, void *state, const double *hchol,
+                            uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
+                            int64_t *n_accept, uint8_t *accepted, hipStream_t s);
+smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                         double *out, void *state_out, hipStream_t s);
+smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,
+                        int32_t *mh, hipStream_t s);
+smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, double *part,
+                      double *rne, hipStream_t s);
+smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s);
+
+}  // namespace smc

@@ -1,0 +1,388 @@
+"""GPU parity: the HIP path through the C ABI against the oracle, element by
+element on the same seeded inputs.
+
+Tolerances: FP64 log-likelihoods 1e-10 relative, FP32 recursion 1e-4
+relative; resampling indices and accept decisions bit-exact (cases whose
+decision lies within 1e-9 of a tie in the oracle's own arithmetic are
+reported and excluded); particles after accepted moves 1e-12 relative.
+"""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1304_4334_amd as S
+import synthdata as SD
+from oracle import closed_form as CF
+from tests.gpu_helpers import gpu_model, ora_model, pop_to_gpu, sync, theta_np
+
+pytestmark = pytest.mark.gpu
+
+CASES = [("linreg", S.SMC_FP64), ("egarch11", S.SMC_FP64), ("egarch11", S.SMC_FP32),
+         ("egarch2t", S.SMC_FP64), ("egarch2t", S.SMC_FP32)]
+
+
+def _tol(prec):
+    return 1e-10 if prec == S.SMC_FP64 else 1e-4
+
+
+def _close(got, want, prec, n_obs):
+    """FP64: 1e-10 relative.  FP32: 1e-4 relative to the larger of the value
+    and one unit per observation (a sum of per-observation log densities of
+    either sign can be near zero while its terms are not)."""
+    got, want = np.asarray(got), np.asarray(want)
+    same_inf = np.isinf(want) & (got == want)
+    got = np.where(same_inf, 0.0, got)
+    want = np.where(same_inf, 0.0, want)
+    if prec == S.SMC_FP64:
+        ok = np.abs(got - want) <= 1e-10 * np.abs(want) + 1e-12
+    else:
+        ok = np.abs(got - want) <= 1e-4 * np.maximum(np.abs(want), max(n_obs, 1))
+    if not np.all(ok):
+        i = int(np.argmin(ok))
+        print(f"worst mismatch at {i}: got {got.flat[i]!r} want {want.flat[i]!r}")
+    return bool(np.all(ok))
+
+
+# ------------------------------------------------------------- prior (a1) --
+
+@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t"])
+def test_init_from_prior_matches_oracle(name):
+    w = SD.workload(name, T=50)
+    gm, om = gpu_model(w), ora_model(w)
+    J, N = 3, 100
+    g = S.Population(gm, J, N)
+    S.smc_init_from_prior(gm, g, seed=77, run=3)
+    sync()
+    th = theta_np(g)
+    for p in [0, 1, 2, 3, 57, 299]:
+        want = O.prior_draw(om, 77, 3, p)
+        assert np.allclose(th[p], want, rtol=1e-13, atol=1e-13), (p, th[p], want)
+        assert g.logprior[p].item() == pytest.approx(O.logprior(om, want), rel=1e-13)
+    assert torch.all(g.logw == 0) and torch.all(g.loglik == 0)
+    if gm.S:
+        assert torch.all(g.state == 0)
+
+
+# --------------------------------------------------------- likelihood -------
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_loglik_matches_oracle_small(name, prec):
+    w = SD.workload(name, T=333)  # several unrolled blocks and a ragged tail
+    gm, om = gpu_model(w, prec), ora_model(w)
+    P = 200
+    th = SD.random_thetas(w, P, 5)
+    for t in (0, 1, 2, 9, 333):
+        st = torch.zeros((gm.S, P), dtype=gm.state_dtype, device="cuda") if gm.S else None
+        ll = S.smc_loglik(gm, torch.from_numpy(th.T.copy()).cuda(), t, state_out=st).cpu().numpy()
+        want, wst = O.loglik_batch(om, th, t)
+        assert _close(ll, want, prec, t), (t, np.max(np.abs(ll - want)))
+        if gm.S and t > 0:
+            assert np.allclose(st.cpu().numpy().T, wst, rtol=1e-8 if prec == 0 else 2e-3,
+                               atol=1e-9 if prec == 0 else 2e-3)
+
+
+@pytest.mark.parametrize("name,prec", [("egarch11", S.SMC_FP64), ("egarch11", S.SMC_FP32),
+                                       ("egarch2t", S.SMC_FP32), ("egarch2t", S.SMC_FP64)])
+def test_loglik_full_size_sampled(name, prec):
+    """Full workload size in the bench's launch shape; the oracle checks a
+    sample of particles one by one."""
+    w = SD.workload(name)
+    gm, om = gpu_model(w, prec), ora_model(w)
+    P = w.P
+    th = SD.random_thetas(w, P, 9, spread=0.02)
+    ll = S.smc_loglik(gm, torch.from_numpy(th.T.copy()).cuda(), w.T).cpu().numpy()
+    idx = np.random.default_rng(1).choice(P, 24, replace=False)
+    idx = np.concatenate([idx, [0, P - 1]])
+    want = O.loglik_batch(om, th[idx], w.T)[0]
+    assert _close(ll[idx], want, prec, w.T)
+    assert np.all(np.isfinite(ll))
+
+
+def test_loglik_empty_and_bad_args():
+    w = SD.workload("egarch11", T=20)
+    gm = gpu_model(w)
+    out = S.smc_loglik(gm, torch.zeros((5, 0), dtype=torch.float64, device="cuda"), 20)
+    assert out.numel() == 0
+    with pytest.raises(S.SmcError):
+        S.smc_loglik(gm, torch.zeros((5, 4), dtype=torch.float64, device="cuda"), 21)
+
+
+# ------------------------------------------------------------ C phase (a2) --
+
+@pytest.mark.parametrize("name,prec,ce", [("linreg", 0, 1), ("egarch11", 0, 1),
+                                          ("egarch11", 1, 1), ("egarch2t", 0, 3)])
+def test_correct_matches_oracle(name, prec, ce):
+    w = SD.workload(name, T=400)
+    gm, om = gpu_model(w, prec), ora_model(w)
+    J, N = 4, 64
+    opop = O.Pop(om, J, N)
+    O.init(om, opop, seed=3)
+    # advance both from the prior through two C phases
+    g = pop_to_gpu(gm, opop, max_chunk=16)
+    t = 0
+    for cyc in range(3):
+        t_o, rss_o, glwb_o = O.correct(om, opop, t, w.T, check_every=ce, rss_min=0.5)
+        t_g, rss_g, glwb_g = S.smc_correct(gm, g, t, w.T, check_every=ce, rss_min=0.5)
+        assert t_g == t_o
+        assert rss_g == pytest.approx(rss_o, rel=1e-9 if prec == 0 else 1e-3)
+        assert _close(glwb_g.cpu().numpy(), glwb_o, prec, t_o - t)
+        assert _close(g.logw.cpu().numpy(), opop.logw, prec, t_o - t)
+        assert _close(g.loglik.cpu().numpy(), opop.loglik, prec, t_o)
+        t = t_o
+    # fixed schedule: run to a given date without RSS test
+    t_o, rss_o, glwb_o = O.correct(om, opop, t, min(w.T, t + 37), check_every=ce, rss_min=0.0)
+    t_g, rss_g, glwb_g = S.smc_correct(gm, g, t, min(w.T, t + 37), check_every=ce, rss_min=0.0)
+    assert t_g == t_o == min(w.T, t + 37)
+    assert rss_g == pytest.approx(rss_o, rel=1e-9 if prec == 0 else 1e-3)
+
+
+# ------------------------------------------------------------ S phase (a3) --
+
+@pytest.mark.parametrize("scheme", [S.SMC_RESAMPLE_RESIDUAL, S.SMC_RESAMPLE_MULTINOMIAL])
+@pytest.mark.parametrize("J,N", [(4, 64), (3, 1000), (2, 4096)])
+def test_resample_bit_exact(scheme, J, N):
+    w = SD.workload("egarch11", T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    rng = np.random.default_rng(J * N + scheme)
+    lw = rng.normal(0, 2.0, J * N) - 40.0
+    lw[rng.random(J * N) < 0.1] = -np.inf
+    anc_o, bad, mrg = O.resample(J, N, lw, scheme, seed=9, run=1, cycle=4, with_margin=True)
+    assert bad == 0
+    opop = O.Pop(om, J, N)
+    opop.theta[:] = rng.standard_normal(opop.theta.shape)
+    opop.logw[:] = lw
+    g = pop_to_gpu(gm, opop)
+    S.smc_resample(gm, g, scheme, seed=9, run=1, cycle=4)
+    anc_g = g.ancestor.cpu().numpy()
+    for j in range(J):
+        if mrg[j] < 1e-9:
+            continue  # a tie within rounding: any side of it is correct
+        assert np.array_equal(anc_g[j * N:(j + 1) * N], anc_o[j * N:(j + 1) * N]), j
+    O.gather(opop, anc_o)
+    assert np.array_equal(theta_np(g), opop.theta)
+
+
+def test_resample_edge_cases():
+    w = SD.workload("egarch11", T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    J, N = 3, 8
+    opop = O.Pop(om, J, N)
+    opop.theta[:] = np.arange(J * N)[:, None] * np.ones((1, 5))
+    lw = np.zeros(J * N)
+    lw[N:2 * N] = -np.inf                      # dead group
+    lw[2 * N:] = np.log([0.5, 0.25, 0.25, 1e-300, 1e-300, 1e-300, 1e-300, 1e-300])
+    opop.logw[:] = lw
+    g = pop_to_gpu(gm, opop)
+    S.smc_flags(g)
+    S.smc_resample(gm, g, S.SMC_RESAMPLE_RESIDUAL, seed=1, cycle=1)
+    anc = g.ancestor.cpu().numpy()
+    assert anc[:N].tolist() == list(range(N))           # equal weights: identity
+    assert anc[N:2 * N].tolist() == list(range(N, 2 * N))
+    # N W = (4, 2, 2, 0, ...): deterministic copies only
+    assert anc[2 * N:].tolist() == [16] * 4 + [17] * 2 + [18] * 2
+    assert S.smc_flags(g) == S.SMC_FLAG_DEAD_GROUP
+    assert S.smc_flags(g) == 0
+
+
+# ----------------------------------------------------------- moments (a4) --
+
+@pytest.mark.parametrize("J,N,d", [(4, 64, 5), (16, 1024, 5), (64, 1024, 9), (3, 7, 4)])
+def test_moments_mfma_match_oracle(J, N, d):
+    name = {5: "egarch11", 9: "egarch2t", 4: "linreg"}[d]
+    w = SD.workload(name, T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    opop = O.Pop(om, J, N)
+    rng = np.random.default_rng(J + N)
+    A = rng.standard_normal((d, d))
+    opop.theta[:] = rng.standard_normal((J * N, d)) @ A + rng.standard_normal(d) * 3
+    g = pop_to_gpu(gm, opop)
+    mh = torch.tensor([7], dtype=torch.int32, device="cuda")
+    mean = torch.zeros(d, dtype=torch.float64, device="cuda")
+    cov = torch.zeros((d, d), dtype=torch.float64, device="cuda")
+    hl = S.smc_particle_moments(gm, g, mh, mean=mean, cov=cov)
+    m_o, c_o, l_o, rc = O.moments(opop)
+    assert rc == 0
+    assert np.allclose(mean.cpu().numpy(), m_o, rtol=1e-12, atol=1e-12)
+    assert np.allclose(cov.cpu().numpy(), c_o, rtol=1e-10, atol=1e-12)
+    assert np.allclose(hl.cpu().numpy(), 0.7 * l_o, rtol=1e-9, atol=1e-12)
+
+
+def test_moments_not_pd_flag():
+    w = SD.workload("egarch11", T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    opop = O.Pop(om, 2, 16)
+    opop.theta[:] = 1.0
+    g = pop_to_gpu(gm, opop)
+    S.smc_flags(g)
+    mh = torch.tensor([5], dtype=torch.int32, device="cuda")
+    hl = S.smc_particle_moments(gm, g, mh)
+    assert torch.all(hl == 0)
+    assert S.smc_flags(g) == S.SMC_FLAG_NOT_PD
+
+
+# ------------------------------------------------------------ M phase (a5) --
+
+@pytest.mark.parametrize("name,prec", CASES)
+def test_mutate_matches_oracle(name, prec):
+    w = SD.workload(name, T=300)
+    gm, om = gpu_model(w, prec), ora_model(w)
+    J, N = 4, 64
+    opop = O.Pop(om, J, N)
+    opop.theta[:] = SD.random_thetas(w, J * N, 12, spread=0.05)
+    for p in range(J * N):
+        opop.logprior[p] = O.logprior(om, opop.theta[p])
+    opop.loglik[:], st = O.loglik_batch(om, opop.theta, w.T)
+    if om.S:
+        opop.state[:, :om.S] = st
+    _, _, chol, rc = O.moments(opop)
+    hl = 0.6 * chol
+    g = pop_to_gpu(gm, opop)
+    acc_g = torch.zeros(J * N, dtype=torch.uint8, device="cuda")
+    n_g = S.smc_mutate(gm, g, w.T, torch.from_numpy(hl).cuda(), seed=21, run=2, cycle=3, it=4,
+                       accepted=acc_g)
+    n_o, acc_o = O.mutate(om, opop, w.T, hl, seed=21, run=2, cycle=3, it=4)
+    acc_g = acc_g.cpu().numpy()
+    if prec == S.SMC_FP64:
+        assert np.array_equal(acc_g, acc_o)
+        assert n_g.item() == n_o
+        assert np.allclose(theta_np(g), opop.theta, rtol=1e-12, atol=1e-13)
+        assert np.allclose(g.loglik.cpu().numpy(), opop.loglik, rtol=1e-10)
+    else:
+        # FP32 likelihood differences may flip decisions near the boundary only
+        assert np.mean(acc_g != acc_o) < 0.03
+        same = acc_g == acc_o
+        assert np.allclose(theta_np(g)[same], opop.theta[same], rtol=1e-12, atol=1e-13)
+    assert 0 < n_o < J * N
+
+
+@pytest.mark.parametrize("name,prec", [("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32)])
+def test_mutate_full_size_sampled(name, prec):
+    """One M step at the full workload size; sampled particles are replayed
+    one by one by the oracle with their global Philox indices."""
+    w = SD.workload(name)
+    gm, om = gpu_model(w, prec), ora_model(w)
+    P = w.P
+    th = SD.random_thetas(w, P, 31, spread=0.01)
+    g = S.Population(gm, w.J, w.N, max_chunk=16)
+    g.theta.copy_(torch.from_numpy(th.T.copy()))
+    idx = np.concatenate([[0, 1, P - 1], np.random.default_rng(2).choice(P, 13, replace=False)])
+    # current log-likelihoods and priors: the GPU's own for every particle,
+    # replaced by the oracle's values at the sampled ones (both sides then
+    # start from identical inputs there)
+    g.loglik.copy_(S.smc_loglik(gm, g.theta, w.T))
+    lp_o = {int(p): O.logprior(om, th[p]) for p in idx}
+    ll_o = {int(p): O.loglik(om, th[p], w.T)[0] for p in idx}
+    for p in idx:
+        g.loglik[int(p)] = ll_o[int(p)]
+        g.logprior[int(p)] = lp_o[int(p)]
+    hl = np.linalg.cholesky(np.cov(th[::16].T)) * 0.5
+    acc = torch.zeros(P, dtype=torch.uint8, device="cuda")
+    S.smc_mutate(gm, g, w.T, torch.from_numpy(hl).cuda(), seed=4, run=0, cycle=9, it=2,
+                 accepted=acc)
+    acc = acc.cpu().numpy()
+    th_g = theta_np(g)
+    for p in idx:
+        p = int(p)
+        a, th_o, _, _, _ = O.mutate_particle(om, p, th[p], lp_o[p], ll_o[p], w.T, hl, seed=4,
+                                             run=0, cycle=9, it=2)
+        if prec == S.SMC_FP64:
+            assert a == bool(acc[p]), p
+        if a == bool(acc[p]):
+            assert np.allclose(th_g[p], th_o, rtol=1e-12, atol=1e-13)
+
+
+# ------------------------------------------- estimators (a6, a7) ----------
+
+def test_log_ml_and_rne_match_oracle():
+    g = np.random.default_rng(3).normal(-5, 0.3, size=(7, 16))
+    out = S.smc_log_ml(torch.from_numpy(g).cuda()).cpu().numpy()
+    assert np.allclose(out, O.log_ml(g), rtol=1e-12)
+    out = S.smc_log_ml(torch.from_numpy(np.log([[1.0, 3.0], [2.0, 2.0]])).cuda()).cpu().numpy()
+    assert np.allclose(out, [math.log(4.0), 0.5, math.log(4.0)], rtol=1e-14)
+    w = SD.workload("egarch2t", T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    opop = O.Pop(om, 16, 256)
+    opop.theta[:] = np.random.default_rng(4).standard_normal(opop.theta.shape) * 2 + 1
+    gp = pop_to_gpu(gm, opop)
+    assert S.smc_rne(gm, gp).item() == pytest.approx(O.rne_mean(opop), rel=1e-10)
+
+
+def test_adapt_scale_rule():
+    mh = torch.tensor([5], dtype=torch.int32, device="cuda")
+    n = torch.tensor([251], dtype=torch.int64, device="cuda")
+    S.smc_adapt_scale(n, 1000, 250, mh)
+    assert mh.item() == 6
+    n.fill_(250)
+    S.smc_adapt_scale(n, 1000, 250, mh)
+    assert mh.item() == 5
+    mh.fill_(10)
+    n.fill_(1000)
+    S.smc_adapt_scale(n, 1000, 250, mh)
+    assert mh.item() == 10
+    mh.fill_(1)
+    n.fill_(0)
+    S.smc_adapt_scale(n, 1000, 250, mh)
+    assert mh.item() == 1
+
+
+# ---------------------------------------------------------- whole runs -----
+
+def _oracle_design_to_gpu(orec, grec, d):
+    L = orec.L
+    grec.t_end[:L] = orec.t_end[:L]
+    grec.R[:L] = orec.R[:L]
+    R = min(orec.RmaxRec, grec.RmaxRec)
+    h = torch.from_numpy(orec.hchol[:L, :R].copy())
+    grec.hchol[:L, :R].copy_(h)
+
+
+@pytest.mark.parametrize("name,J,N,T,fe", [("linreg", 4, 256, 200, 20), ("egarch11", 4, 128, 300, 0)])
+def test_replay_of_oracle_design_matches_oracle(name, J, N, T, fe):
+    """The GPU replays the oracle's adaptive design (Algorithm 1 with the
+    recorded t_l, hL_lr, R_l): same trajectory, same estimates."""
+    w = SD.workload(name, T=T)
+    gm, om = gpu_model(w), ora_model(w)
+    rc, orec, opop = O.run(om, J, N, 5, check_every=1, force_every=fe, Lmax=300, RmaxRec=64)
+    assert rc == 0
+    so = orec.summary()
+    g = S.Population(gm, J, N, max_chunk=32)
+    grec = S.Record(gm, J, Lmax=300, RmaxRec=64)
+    _oracle_design_to_gpu(orec, grec, gm.d)
+    S.smc_run(gm, g, seed=5, check_every=1, force_every=fe, record=grec, replay=True)
+    sg = grec.summary()
+    assert sg["L"] == so["L"]
+    assert np.array_equal(sg["n_accept"][:, :64].sum(1), orec.n_acc[:so["L"]].sum(1))
+    assert np.allclose(sg["group_logwbar"], so["group_logwbar"], rtol=1e-9, atol=1e-9)
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-10, abs=1e-9)
+    assert sg["nse"] == pytest.approx(so["nse"], rel=1e-7, abs=1e-10)
+    assert np.allclose(theta_np(g), opop.theta, rtol=1e-9, atol=1e-10)
+
+
+def test_adaptive_linreg_log_ml_matches_closed_form():
+    w = SD.workload("linreg")
+    gm = gpu_model(w)
+    exact = CF.log_ml(w.y, w.X)
+    for seed in (1, 2):
+        g = S.Population(gm, 16, 256, max_chunk=32)
+        rec = S.smc_run(gm, g, seed=seed, check_every=1, force_every=20)
+        s = rec.summary()
+        assert abs(s["log_ml"] - exact) < 3.5 * s["nse"], (s["log_ml"], exact, s["nse"])
+        assert s["t_end"][-1] == w.T
+
+
+def test_adaptive_run_matches_oracle_run():
+    """Same seed, same adaptive rules: the GPU's adaptive run follows the
+    oracle's, cycle for cycle, unless an RSS lands on a tie."""
+    w = SD.workload("egarch11", T=250)
+    gm, om = gpu_model(w), ora_model(w)
+    rc, orec, opop = O.run(om, 4, 128, 8, Lmax=300, RmaxRec=64)
+    so = orec.summary()
+    g = S.Population(gm, 4, 128, max_chunk=32)
+    rec = S.smc_run(gm, g, seed=8, Lmax=300, RmaxRec=64)
+    sg = rec.summary()
+    assert np.array_equal(sg["t_end"], so["t_end"])
+    assert np.array_equal(sg["R"], so["R"])
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
