@@ -1,0 +1,220 @@
+#!/usr/bin/env python3
+"""Throughput of the sequential posterior simulator on one MI355X.
+
+A step is one whole adaptive run of the simulator (prior draw, C/S/M cycles
+to T with the Section 3.3 rules, marginal likelihood) on a synthetic
+workload resident in HBM.  `value` is particle x observation log-likelihood
+evaluations per second over the K timed steps (C-phase and M-phase
+evaluations, divided by wall time including every host decision).
+
+The roofline object describes the dominant kernel (the Metropolis mutation
+kernel): algorithmic VALU lane-operations per particle-observation times the
+evaluations of each launch, divided by the launch durations measured with
+HIP events on the launch stream inside the timed region.
+
+The cpu_baseline object times the oracle (plain FP64 C, OpenMP over
+particles) on a bounded sample of the same work: its Metropolis step over a
+sample of particles at t = T.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+METRIC = ("particle·obs log-lik evals/s; wall time to log-ML at NSE≤0.05 "
+          "(MALA vs RW)")
+
+# MI355X: 256 CUs x 4 SIMDs x 16 lanes per clock for unpacked FP32/FP64 VALU
+# operations at 2.4 GHz.
+VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+N_SIMD = 256 * 4
+
+# Algorithmic VALU lane-operations per particle-observation of the recursion
+# (FMA = 1; FP32 exp2/log2 = 4, quarter rate; FP64 exp/log1p = 17, the
+# range reduction, degree-11 polynomial and scaling of a full-precision
+# software exponential).
+OPS_PER_EVAL = {
+    ("linreg", "fp64"): 4,
+    ("egarch11", "fp64"): 7 + 17,
+    ("egarch11", "fp32"): 7 + 1 + 4,
+    ("egarch2t", "fp64"): 10 + 17 + 3 + 17,
+    ("egarch2t", "fp32"): 10 + 1 + 4 + 3 + 4,
+}
+
+DESCR = {
+    "linreg": "conjugate Gaussian regression, k=3, T=200, J=4 x N=256",
+    "egarch11": "EGARCH(1,1) Gaussian shocks, T=5000 synthetic returns, J=16 x N=1024",
+    "egarch2t": "EGARCH 2 factors, Student-t(8) shocks, T=10000 synthetic returns, J=64 x N=1024",
+}
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def run_gpu(name, precision, steps, warmup):
+    import numpy as np
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+
+    w = SD.workload(name)
+    prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
+    m = S.Model.from_workload(w, precision=prec)
+    pop = S.Population(m, w.J, w.N, max_chunk=256)
+    rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64, time_mutate=True)
+    force = 20 if name == "linreg" else 0
+
+    def one(seed):
+        S.smc_run(m, pop, seed=seed, check_every=1, force_every=force, record=rec)
+
+    for i in range(warmup):
+        one(10_000 + i)
+        log(f"[bench] {name}/{precision} warmup {i + 1}/{warmup} done")
+    torch.cuda.synchronize()
+    evals = 0
+    mut_ms = 0.0
+    mut_evals = 0
+    n_launch = 0
+    log_mls, nses, cycles, msteps = [], [], [], []
+    t0 = time.perf_counter()
+    for k in range(steps):
+        one(1 + k)
+        s = rec.summary()
+        evals += s["evals"]
+        L = s["L"]
+        for l in range(L):
+            Rl = int(s["R"][l])
+            mut_ms += float(rec.mutate_ms[l, :Rl].astype(np.float64).sum())
+            mut_evals += Rl * w.P * int(s["t_end"][l])
+            n_launch += Rl
+        log_mls.append(s["log_ml"])
+        nses.append(s["nse"])
+        cycles.append(L)
+        msteps.append(s["mh_steps"])
+        log(f"[bench] {name}/{precision} step {k + 1}/{steps}: {L} cycles, "
+            f"{s['mh_steps']} M steps, log ML {s['log_ml']:.3f} +- {s['nse']:.3f}")
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    secs = t1 - t0
+    ops = OPS_PER_EVAL[(name, precision)]
+    achieved = ops * mut_evals / (mut_ms * 1e-3) / 1e12
+    occupied = min(1.0, math.ceil(w.P / 64) / N_SIMD)
+    return dict(
+        w=w, value=evals / secs, ms_per_step=1e3 * secs / steps, evals_per_step=evals / steps,
+        log_ml=float(np.mean(log_mls)), nse=float(np.mean(nses)), cycles=float(np.mean(cycles)),
+        mh_steps=float(np.mean(msteps)), mutate_avg_ms=mut_ms / max(n_launch, 1),
+        mutate_launches=n_launch, mutate_evals_per_s=mut_evals / (mut_ms * 1e-3),
+        roofline=dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS,
+                      unit="T VALU lane-ops/s", frac=achieved / VALU_PEAK_TOPS,
+                      traffic=None, kernel="k_mutate_rw", ops_per_eval=ops,
+                      simd_occupancy=occupied,
+                      frac_of_occupied=achieved / (VALU_PEAK_TOPS * occupied)),
+        secs=secs)
+
+
+def cpu_baseline(name, seconds):
+    import numpy as np
+
+    import oracle as O
+    import synthdata as SD
+
+    w = SD.workload(name)
+    om = O.Model.from_workload(w)
+    Ps = 1024
+    rng = np.random.default_rng(0)
+    pop = O.Pop(om, 2, Ps // 2)
+    pop.theta[:] = SD.random_thetas(w, Ps, 3, spread=0.02)
+    for p in range(Ps):
+        pop.logprior[p] = O.logprior(om, pop.theta[p])
+    pop.loglik[:] = O.loglik_batch(om, pop.theta, w.T)[0]
+    hl = np.linalg.cholesky(np.cov(pop.theta.T)) * 0.5
+    del rng
+    iters = 0
+    t0 = time.perf_counter()
+    while True:
+        O.mutate(om, pop, w.T, hl, seed=5, cycle=1, it=iters + 1)
+        iters += 1
+        el = time.perf_counter() - t0
+        if el >= seconds:
+            break
+    rate = iters * Ps * w.T / el
+    return dict(value=rate, unit="particle·obs/s", cores=O.num_threads(), kind="oracle",
+                sample=(f"oracle RW Metropolis step (FP64) over {Ps} particles at t=T={w.T}, "
+                        f"{iters} iterations in {el:.1f} s"))
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="egarch11", choices=sorted(DESCR))
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
+    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-recursion companion run")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulator "
+              "shards by groups across GPUs only in design, see DESIGN.md", file=sys.stderr)
+        sys.exit(2)
+    if args.steps < 1:
+        sys.exit("--steps must be >= 1")
+
+    main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup)
+    companion = None
+    if not args.no_fp32 and args.precision == "fp64" and args.workload != "linreg":
+        companion = run_gpu(args.workload, "fp32", args.steps, args.warmup)
+    cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
+
+    w = main_run["w"]
+    out = {
+        "metric": METRIC,
+        "value": main_run["value"],
+        "unit": "particle·obs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_run["ms_per_step"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "data": "synthetic",
+        "config": {"workload": f"{args.workload}: {DESCR[args.workload]}, RW-Metropolis, "
+                               "adaptive C/S/M (D1=0.5, D2=0.2, Rbar=7, kappa=3), residual "
+                               "resampling",
+                   "J": w.J, "N": w.N, "T": w.T, "precision": args.precision,
+                   "parallelism": "single GPU"},
+        "roofline": main_run["roofline"],
+        "cpu_baseline": cpu,
+        "run": {"log_ml": main_run["log_ml"], "nse": main_run["nse"],
+                "cycles": main_run["cycles"], "mh_steps": main_run["mh_steps"],
+                "evals_per_step": main_run["evals_per_step"],
+                "mutate_avg_ms": main_run["mutate_avg_ms"],
+                "mutate_launches": main_run["mutate_launches"],
+                "mutate_evals_per_s": main_run["mutate_evals_per_s"]},
+    }
+    if companion is not None:
+        out["fp32"] = {"value": companion["value"], "ms_per_step": companion["ms_per_step"],
+                       "log_ml": companion["log_ml"], "nse": companion["nse"],
+                       "mutate_avg_ms": companion["mutate_avg_ms"],
+                       "mutate_evals_per_s": companion["mutate_evals_per_s"],
+                       "roofline": companion["roofline"]}
+    if cpu is not None:
+        out["gpu_over_cpu"] = main_run["mutate_evals_per_s"] / cpu["value"]
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

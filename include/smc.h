@@ -253,6 +253,9 @@ typedef struct {
   double *log_ml;        /* device [3]: out, as smc_log_ml */
   int64_t evals;         /* out: particle x observation density evaluations */
   int64_t mh_steps;      /* out: Metropolis iterations */
+  float *mutate_ms;      /* host [Lmax][RmaxRec] or NULL: when given, each
+                            smc_mutate launch is bracketed by HIP events on
+                            the run's stream and its duration stored here */
 } smc_run_record;
 
 /* Runs the simulator on `pop` (which must hold a workspace for

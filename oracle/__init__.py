@@ -122,6 +122,10 @@ class Model:
         return lib().orc_state_dim(C.byref(self.c))
 
 
+def num_threads():
+    return int(lib().orc_num_threads())
+
+
 def philox(ctr, key):
     out = (C.c_uint64 * 4)()
     lib().orc_philox4x64_10((C.c_uint64 * 4)(*ctr), (C.c_uint64 * 2)(*key), out)

@@ -23,11 +23,23 @@
  * in the "parity unpinned" notes below.
  */
 #include <math.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
 
 #define ORC_DMAX 20 /* largest parameter dimension handled */
+
+/* Threads the OpenMP particle loops use (1 without OpenMP). */
+int orc_num_threads(void) {
+#ifdef _OPENMP
+  return omp_get_max_threads();
+#else
+  return 1;
+#endif
+}
 #define ORC_SMAX 8  /* largest recursion state handled */
 
 /* ------------------------------------------------------------------------ */

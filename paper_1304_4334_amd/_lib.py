@@ -55,7 +55,8 @@ class RunConfig(C.Structure):
 class RunRecord(C.Structure):
     _fields_ = [("L", C.c_int32), ("reserved", C.c_int32), ("t_end", _vp), ("R", _vp),
                 ("rss", _vp), ("n_accept", _vp), ("hchol", _vp), ("group_logwbar", _vp),
-                ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64)]
+                ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64),
+                ("mutate_ms", _vp)]
 
 
 _L = None
@@ -304,7 +305,7 @@ def smc_flags(pop, stream=None):
 class Record:
     """Host and device arrays of a run's design and outputs."""
 
-    def __init__(self, model, J, Lmax=512, RmaxRec=128):
+    def __init__(self, model, J, Lmax=512, RmaxRec=128, time_mutate=False):
         import numpy as np
         d, dev = model.d, model.device
         self.Lmax, self.RmaxRec, self.J, self.d = Lmax, RmaxRec, J, d
@@ -315,9 +316,11 @@ class Record:
         self.hchol = torch.zeros((Lmax, RmaxRec, d, d), dtype=torch.float64, device=dev)
         self.group_logwbar = torch.zeros((Lmax, J), dtype=torch.float64, device=dev)
         self.log_ml = torch.zeros(3, dtype=torch.float64, device=dev)
+        self.mutate_ms = np.zeros((Lmax, RmaxRec), dtype=np.float32) if time_mutate else None
         self.c = RunRecord(0, 0, self.t_end.ctypes.data, self.R.ctypes.data, self.rss.ctypes.data,
                            _ptr(self.n_accept), _ptr(self.hchol), _ptr(self.group_logwbar),
-                           _ptr(self.log_ml), 0, 0)
+                           _ptr(self.log_ml), 0, 0,
+                           self.mutate_ms.ctypes.data if time_mutate else None)
 
     @property
     def L(self):

@@ -400,6 +400,21 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   if ((st = smc_init_from_prior(m, pop, cfg->rng, stream))) return st;
   int64_t t = 0, evals = 0, steps = 0;
   int32_t l = 0;
+  // Optional per-launch timing of the mutation kernel: pairs of events,
+  // resolved after the run and destroyed on every exit path.
+  struct Timed {
+    hipEvent_t a = nullptr, b = nullptr;
+    int64_t slot = 0;
+  };
+  struct TimedList {
+    std::vector<Timed> v;
+    ~TimedList() {
+      for (auto &e : v) {
+        if (e.a) (void)hipEventDestroy(e.a);
+        if (e.b) (void)hipEventDestroy(e.b);
+      }
+    }
+  } timed;
   const int32_t target = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
   while (t < T) {
     if (l >= cfg->Lmax) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
@@ -430,9 +445,20 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
       if (!cfg->replay && (st = smc_particle_moments(m, pop, mh, nullptr, nullptr, hl, stream)))
         return st;
+      Timed *ev = nullptr;
+      if (rec->mutate_ms) {
+        timed.v.emplace_back();
+        ev = &timed.v.back();
+        ev->slot = (int64_t)l * cfg->RmaxRec + (r - 1);
+        if (hipEventCreate(&ev->a) != hipSuccess || hipEventCreate(&ev->b) != hipSuccess ||
+            hipEventRecord(ev->a, s) != hipSuccess)
+          return set_error(SMC_E_DEVICE, "event setup failed");
+      }
       if ((st = smc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->rng, l + 1, r, nacc, nullptr,
                            stream)))
         return st;
+      if (ev && hipEventRecord(ev->b, s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "event record failed");
       evals += P * t_new;
       ++steps;
       if (!cfg->replay && (st = smc_adapt_scale(nacc, P, target, mh, stream))) return st;
@@ -470,6 +496,16 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   rec->evals = evals;
   rec->mh_steps = steps;
   if ((st = smc_log_ml(l, pop->J, rec->group_logwbar, rec->log_ml, stream))) return st;
+  if (!timed.v.empty()) {
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return set_error(SMC_E_DEVICE, "synchronising for the timings failed");
+    for (auto &e : timed.v) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, e.a, e.b) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "reading a kernel timing failed");
+      rec->mutate_ms[e.slot] = ms;
+    }
+  }
   return SMC_OK;
 }
 
