@@ -94,7 +94,27 @@ int64_t chunk_capacity(const smc_model *m, const smc_particles *pop) {
 
 int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8; }
 
+// Page-locked host buffer for the C-phase RSS readbacks (one per host
+// thread, kept for the life of the process); NULL if it cannot be had.
+double *pinned_rss_buffer() {
+  thread_local double *buf = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, kMaxChunk * sizeof(double), hipHostMallocDefault) == hipSuccess)
+      buf = static_cast<double *>(p);
+  }
+  return buf;
+}
+
+
 }  // namespace
+
+smc_status correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
+                        int64_t check_every, double rss_min, double *group_logwbar,
+                        int64_t *t_to, double *rss, void *stream, int64_t first_chunk);
+
 }  // namespace smc
 
 using namespace smc;
@@ -187,6 +207,18 @@ smc_status smc_init_from_prior(const smc_model *m, smc_particles *pop, smc_rng r
 smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
                        int64_t check_every, double rss_min, double *group_logwbar,
                        int64_t *t_to, double *rss, void *stream) {
+  return correct_impl(m, pop, t_from, t_max, check_every, rss_min, group_logwbar, t_to, rss,
+                      stream, 16);
+}
+
+}  // extern "C"
+
+// The C phase with a first speculative chunk of `first_chunk` observations
+// (the driver passes a length predicted from the previous cycle).
+smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from,
+                             int64_t t_max, int64_t check_every, double rss_min,
+                             double *group_logwbar, int64_t *t_to, double *rss, void *stream,
+                             int64_t first_chunk) {
   smc_status st;
   if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
   if (!group_logwbar || !t_to) return set_error(SMC_E_INVALID_ARG, "NULL output");
@@ -217,10 +249,15 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
   } else {
     const int64_t cap = chunk_capacity(m, pop);
     if (cap < 1) return set_error(SMC_E_WORKSPACE, "workspace has no room for C-phase chunks");
-    int64_t chunk = std::min<int64_t>(16, cap);
+    int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(first_chunk, cap));
     int64_t t = t_from;
     std::vector<int64_t> dates;
-    std::vector<double> host_rss;
+    std::vector<double> host_vec;
+    double *host_rss = pinned_rss_buffer();
+    if (!host_rss) {
+      host_vec.resize(kMaxChunk);
+      host_rss = host_vec.data();
+    }
     bool stopped = false;
     while (!stopped) {
       const int64_t t1 = std::min(t + chunk, t_max);
@@ -240,8 +277,7 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
         return st;
       const int64_t nc = (int64_t)dates.size();
       if ((st = launch_rss_cols(W, P, nc, rsscols, s))) return st;
-      host_rss.resize(nc);
-      if (hipMemcpyAsync(host_rss.data(), rsscols, nc * sizeof(double), hipMemcpyDeviceToHost,
+      if (hipMemcpyAsync(host_rss, rsscols, nc * sizeof(double), hipMemcpyDeviceToHost,
                          s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
         return set_error(SMC_E_DEVICE, "correct: reading the RSS failed");
@@ -268,6 +304,8 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
   return SMC_OK;
 }
 
+extern "C" {
+
 smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, smc_rng rng,
                         int32_t cycle, void *stream) {
   smc_status st;
@@ -293,10 +331,18 @@ smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, co
   if (!mh || !hchol) return set_error(SMC_E_INVALID_ARG, "mh and hchol are required");
   const int64_t P = (int64_t)pop->J * pop->N;
   const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
-  double *mean_ws = mean ? mean : ws_at<double>(pop, L.small + kSmallMean);
-  return launch_moments(pop->theta, P, m->dev.d, mh, mean_ws, cov, hchol,
-                        ws_at<double>(pop, L.mpart), ws_at<int32_t>(pop, L.small + kSmallFlags),
-                        as_stream(stream));
+  MomArgs a{};
+  a.theta = pop->theta;
+  a.P = P;
+  a.d = m->dev.d;
+  a.part = ws_at<double>(pop, L.mpart);
+  a.counter = ws_at<int32_t>(pop, L.small + kSmallTicket);
+  a.mh = const_cast<int32_t *>(mh);
+  a.mean_out = mean;
+  a.cov_out = cov;
+  a.hchol = hchol;
+  a.flags = ws_at<int32_t>(pop, L.small + kSmallFlags);
+  return launch_moments(a, true, as_stream(stream));
 }
 
 smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t kernel,
@@ -395,10 +441,22 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
   int32_t *mh = ws_at<int32_t>(pop, L.small + kSmallMh);
   int32_t *dflags = ws_at<int32_t>(pop, L.small + kSmallFlags);
-  if ((st = fill_i32(dflags, 1, 0, s))) return st;
+  int32_t *ticket = ws_at<int32_t>(pop, L.small + kSmallTicket);
+  if ((st = fill_i32(dflags, 1, 0, s)) || (st = fill_i32(ticket, 1, 0, s))) return st;
   if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
+  // The moments kernel leaves its ticket at zero, so after this fill every
+  // iteration needs a single launch for the step-size rule, V and h L.
+  MomArgs ma{};
+  ma.theta = pop->theta;
+  ma.P = P;
+  ma.d = d;
+  ma.target_permille = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
+  ma.part = ws_at<double>(pop, L.mpart);
+  ma.counter = ticket;
+  ma.mh = mh;
+  ma.flags = dflags;
   if ((st = smc_init_from_prior(m, pop, cfg->rng, stream))) return st;
-  int64_t t = 0, evals = 0, steps = 0;
+  int64_t t = 0, evals = 0, steps = 0, last_len = 0;
   int32_t l = 0;
   // Optional per-launch timing of the mutation kernel: pairs of events,
   // resolved after the run and destroyed on every exit path.
@@ -415,7 +473,6 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       }
     }
   } timed;
-  const int32_t target = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
   while (t < T) {
     if (l >= cfg->Lmax) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
     int64_t t_stop = T;
@@ -427,15 +484,18 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     }
     int64_t t_new = t;
     double rss = NAN;
-    if ((st = smc_correct(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
-                          rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
-                          cfg->replay ? nullptr : &rss, stream)))
+    // Speculate on a cycle a little longer than the previous one, so most C
+    // phases need a single host round trip.
+    const int64_t hint = std::max<int64_t>(16, last_len + last_len / 4 + 8);
+    if ((st = correct_impl(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
+                           rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
+                           cfg->replay ? nullptr : &rss, stream, hint)))
       return st;
+    last_len = t_new - t;
     evals += P * (t_new - t);
     if ((st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream))) return st;
     int32_t R = cfg->replay ? rec->R[l] : (rss < cfg->D2 ? cfg->kappa * cfg->Rbar : cfg->Rbar);
     if (R < 1) return set_error(SMC_E_INVALID_ARG, "R_l < 1 in cycle %d", l);
-    if ((st = fill_i32(mh, 1, 5, s))) return st;
     int32_t r = 0;
     for (;;) {
       ++r;
@@ -443,8 +503,14 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         return set_error(SMC_E_INVALID_ARG, "record holds only %d iterations", cfg->RmaxRec);
       double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
       int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
-      if (!cfg->replay && (st = smc_particle_moments(m, pop, mh, nullptr, nullptr, hl, stream)))
-        return st;
+      if (!cfg->replay) {
+        // h starts at 0.5 in each M phase; later iterations first apply the
+        // step-size rule to the previous iteration's acceptances.
+        ma.mh_reset = (r == 1) ? 5 : 0;
+        ma.prev_nacc = (r == 1) ? nullptr : nacc - 1;
+        ma.hchol = hl;
+        if ((st = launch_moments(ma, false, s))) return st;
+      }
       Timed *ev = nullptr;
       if (rec->mutate_ms) {
         timed.v.emplace_back();
@@ -461,7 +527,6 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         return set_error(SMC_E_DEVICE, "event record failed");
       evals += P * t_new;
       ++steps;
-      if (!cfg->replay && (st = smc_adapt_scale(nacc, P, target, mh, stream))) return st;
       if (cfg->replay || cfg->stop_rule == 0) {
         if (r >= R) break;
       } else {

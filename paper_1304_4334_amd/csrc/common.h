@@ -38,7 +38,7 @@ struct WsLayout {
   size_t rsscols;  // [kMaxChunk] doubles
   size_t gather;   // [2d + S + 2][P] doubles
   size_t cum;      // [P] doubles (resample running sums)
-  size_t mpart;    // [kMomBlocks][16 + 256] doubles (moments)
+  size_t mpart;    // [kMomBlocks][256] doubles (moments)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
   size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
   size_t fixed;    // bytes before wcols
@@ -52,6 +52,7 @@ constexpr int kMomBlocks = 256;
 constexpr size_t kSmallFlags = 0;    // int32
 constexpr size_t kSmallMh = 16;      // int32
 constexpr size_t kSmallNacc = 32;    // int64
+constexpr size_t kSmallTicket = 48;  // int32 completion ticket of the moments kernel
 constexpr size_t kSmallRss = 64;     // double
 constexpr size_t kSmallRne = 72;     // double
 constexpr size_t kSmallMean = 256;   // double[16]

@@ -143,23 +143,58 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 }
 
 // RSS of each recorded column: (sum e)^2 / (P sum e^2), e = exp(w - max w).
-__global__ void __launch_bounds__(256) k_rss_cols(const double *W, int64_t P, double *rss) {
-  __shared__ double sh[4];
+// One block of 1024 threads per column, one pass: each thread keeps a running
+// maximum m with s1 = sum exp(w - m), s2 = sum exp(2(w - m)), rescaled when
+// m grows; the block merges the triples the same way in a fixed order.
+struct Lse3 {
+  double m, s1, s2;
+};
+__device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
+  const double m = fmax(a.m, b.m);
+  if (!(m > -INFINITY)) return Lse3{m, 0.0, 0.0};
+  const double ea = exp(a.m - m), eb = exp(b.m - m);
+  return Lse3{m, a.s1 * ea + b.s1 * eb, a.s2 * ea * ea + b.s2 * eb * eb};
+}
+
+constexpr int kRssBlock = 1024;
+
+__global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss) {
+  __shared__ Lse3 sh[kRssBlock / 64];
   const double *w = W + blockIdx.x * P;
-  double mx = -INFINITY;
-  for (int64_t p = threadIdx.x; p < P; p += kBlock) mx = fmax(mx, w[p]);
-  mx = block_reduce<OpMax<double>>(mx, sh);
-  double s1 = 0.0, s2 = 0.0;
-  if (mx > -INFINITY) {
-    for (int64_t p = threadIdx.x; p < P; p += kBlock) {
-      const double e = exp(w[p] - mx);
-      s1 += e;
-      s2 = fma(e, e, s2);
+  Lse3 acc{-INFINITY, 0.0, 0.0};
+  for (int64_t p0 = threadIdx.x; p0 < P; p0 += 8 * kRssBlock) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) {
+      const int64_t p = p0 + (int64_t)u * kRssBlock;
+      v[u] = p < P ? w[p] : -INFINITY;
     }
+    double m = v[0];
+#pragma unroll
+    for (int u = 1; u < 8; ++u) m = fmax(m, v[u]);
+    Lse3 c{m, 0.0, 0.0};
+    if (m > -INFINITY) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) {
+        const double e = exp(v[u] - m);
+        c.s1 += e;
+        c.s2 = fma(e, e, c.s2);
+      }
+    }
+    acc = lse3_merge(acc, c);
   }
-  s1 = block_reduce<OpSum<double>>(s1, sh);
-  s2 = block_reduce<OpSum<double>>(s2, sh);
-  if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) {
+    Lse3 o{__shfl_xor(acc.m, off, 64), __shfl_xor(acc.s1, off, 64), __shfl_xor(acc.s2, off, 64)};
+    acc = lse3_merge(acc, o);
+  }
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    Lse3 t = sh[0];
+    for (int q = 1; q < kRssBlock / 64; ++q) t = lse3_merge(t, sh[q]);
+    rss[blockIdx.x] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
+  }
 }
 
 // log wbar_j = log(N^-1 sum_n exp(logw_jn)) per group (Section 4.2).
@@ -293,92 +328,105 @@ __global__ void __launch_bounds__(256) k_scatter_back(GatherArgs g) {
 }
 
 // ----------------------------------------------- particle moments (a4) ----
-__global__ void __launch_bounds__(256) k_mean_partial(const double *theta, int64_t P, int32_t d,
-                                                      int64_t chunk, double *part) {
-  __shared__ double sh[4];
-  const int64_t p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
-  for (int i = 0; i < d; ++i) {
-    double s = 0.0;
-    for (int64_t p = p0 + threadIdx.x; p < p1; p += kBlock) s += theta[i * P + p];
-    s = block_reduce<OpSum<double>>(s, sh);
-    if (threadIdx.x == 0) part[blockIdx.x * kDMax + i] = s;
-  }
-}
-
-__global__ void k_mean_final(const double *part, int32_t nb, int32_t d, int64_t P, double *mean) {
-  const int i = threadIdx.x;
-  if (i >= d) return;
-  double s = 0.0;
-  for (int b = 0; b < nb; ++b) s += part[b * kDMax + i];
-  mean[i] = s / (double)P;
-}
-
-// Centred cross products on the matrix cores: each wave accumulates
-// sum_p x_p x_p' with x_p = theta_p - mean (padded to 16) using
-// v_mfma_f64_16x16x4f64, four particles per instruction.  Operand layout
-// (measured on gfx950): lane l supplies element (row l%16, k = l/16) of A and
-// (k = l/16, col l%16) of B, so A = B' = the 16x4 block of centred
-// particles; accumulator register r of lane l holds element
-// (4r + l/16, l%16) of the 16x16 result.
-__global__ void __launch_bounds__(64) k_cross_partial(const double *theta, int64_t P, int32_t d,
-                                                      const double *mean, int64_t chunk,
-                                                      double *part) {
-  const int l = threadIdx.x;
-  const int i = l & 15, k = l >> 4;
-  const int64_t p0 = blockIdx.x * chunk, p1 = min(P, p0 + chunk);
-  const double mi = (i < d) ? mean[i] : 0.0;
+// One launch: every wave accumulates sum_p x_p x_p' on the matrix cores with
+// x_p = (theta_p - s, 1, 0, ...) padded to 16 (s = particle 0, a shift that
+// keeps the one-pass sums well conditioned; the constant slot d carries the
+// first moments and the count).  v_mfma_f64_16x16x4f64 takes four particles
+// per instruction.  Operand layout (measured on gfx950): lane l supplies
+// element (row l%16, k = l/16) of A and (k = l/16, col l%16) of B, so
+// A = B' = the 16x4 block of shifted particles; accumulator register r of
+// lane l holds element (4r + l/16, l%16) of the 16x16 result.
+// Blocks write their partial matrices; the last block to finish (atomic
+// ticket) adds them in block order, optionally applies the step-size rule to
+// mh, forms mean and V (divisor P - 1), factors V = L L' and writes h L.
+__global__ void __launch_bounds__(256) k_moments(MomArgs a) {
+  __shared__ double red[4][256];
+  __shared__ double Ms[256];
+  __shared__ double Ls[kDMax * kDMax];
+  __shared__ double sh_h;
+  __shared__ int sh_last, sh_ok;
   typedef double double4v __attribute__((ext_vector_type(4)));
+  const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
+  const int i = l & 15, k = l >> 4;
+  const int d = a.d;
+  const int64_t P = a.P;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wv) * a.chunk;
+  const int64_t p1 = min(P, p0 + a.chunk);
+  const double si = (i < d) ? a.theta[(int64_t)i * P] : 0.0;
   double4v acc = {0.0, 0.0, 0.0, 0.0};
-  for (int64_t q = p0; q < p1; q += 4) {
-    const int64_t p = q + k;
-    const double x = (i < d && p < p1) ? theta[i * P + p] - mi : 0.0;
-    acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x, x, acc, 0, 0, 0);
-  }
-  double *out = part + blockIdx.x * 256;
+  // Eight MFMA steps per batch with their loads issued first, so the wave
+  // waits for memory once per 32 particles.
+  for (int64_t q0 = p0; q0 < p1; q0 += 32) {
+    double x[8];
 #pragma unroll
-  for (int r = 0; r < 4; ++r) out[(4 * r + k) * 16 + i] = acc[r];
-}
-
-// Sum the partial 16x16 blocks, scale by 1/(P-1), Cholesky (one lane), and
-// write hL = (mh/10) L.  A matrix that is not positive definite raises the
-// flag and yields hL = 0.
-__global__ void __launch_bounds__(64) k_cov_final(const double *part, int32_t nb, int32_t d,
-                                                  int64_t P, const int32_t *mh, double *cov_out,
-                                                  double *hchol, int32_t *flags) {
-  __shared__ double V[kDMax * kDMax];
-  __shared__ double L[kDMax * kDMax];
-  for (int e = threadIdx.x; e < 256; e += 64) {
-    double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += part[b * 256 + e];
-    const int r = e >> 4, c = e & 15;
-    if (r < d && c < d) V[r * kDMax + c] = s / (double)(P - 1);
+    for (int u = 0; u < 8; ++u) {
+      const int64_t p = q0 + 4 * u + k;
+      x[u] = 0.0;
+      if (p < p1) x[u] = (i < d) ? a.theta[(int64_t)i * P + p] - si : (i == d ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+  }
+#pragma unroll
+  for (int r = 0; r < 4; ++r) red[wv][(4 * r + k) * 16 + i] = acc[r];
+  __syncthreads();
+  a.part[blockIdx.x * 256 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  __threadfence();
+  __syncthreads();
+  if (tid == 0) sh_last = (atomicAdd(a.counter, 1) == (int)gridDim.x - 1);
+  __syncthreads();
+  if (!sh_last) return;
+  __threadfence();
+  double sum = 0.0;
+#pragma unroll 8
+  for (int b = 0; b < (int)gridDim.x; ++b) sum += a.part[b * 256 + tid];
+  Ms[tid] = sum;
+  if (tid == 0) {
+    *a.counter = 0;  // every other block has taken its ticket
+    int32_t m = *a.mh;
+    if (a.mh_reset > 0) {
+      m = a.mh_reset;
+    } else if (a.prev_nacc) {
+      m += ((*a.prev_nacc) * 1000 > (int64_t)a.target_permille * P) ? 1 : -1;
+      m = m < 1 ? 1 : (m > 10 ? 10 : m);
+    }
+    *a.mh = m;
+    sh_h = (double)m / 10.0;
+    sh_ok = 1;
   }
   __syncthreads();
-  if (threadIdx.x == 0) {
-    // symmetrise (the two triangles come from identical sums)
-    for (int r = 0; r < d; ++r)
-      for (int c = 0; c < r; ++c) V[c * kDMax + r] = V[r * kDMax + c];
-    bool ok = true;
-    for (int r = 0; r < d && ok; ++r) {
-      for (int c = 0; c <= r; ++c) {
-        double s = V[r * kDMax + c];
-        for (int q = 0; q < c; ++q) s -= L[r * kDMax + q] * L[c * kDMax + q];
-        if (r == c) {
-          if (!(s > 0.0)) { ok = false; break; }
-          L[r * kDMax + r] = sqrt(s);
-        } else {
-          L[r * kDMax + c] = s / L[c * kDMax + c];
-        }
-      }
-    }
-    const double h = ok ? (double)(*mh) / 10.0 : 0.0;
-    if (!ok) atomicOr(flags, SMC_FLAG_NOT_PD);
-    for (int r = 0; r < d; ++r)
-      for (int c = 0; c < d; ++c) {
-        hchol[r * d + c] = (ok && c <= r) ? h * L[r * kDMax + c] : 0.0;
-        if (cov_out) cov_out[r * d + c] = V[r * kDMax + c];
-      }
+  // V and the mean from the shifted sums; V kept in Ms (row stride 16).
+  const double invP = 1.0 / (double)P;
+  const int r = tid >> 4, c = tid & 15;
+  double v = 0.0;
+  if (r < d && c < d) {
+    v = (Ms[r * 16 + c] - Ms[r * 16 + d] * Ms[c * 16 + d] * invP) / (double)(P - 1);
+    if (a.cov_out) a.cov_out[r * d + c] = v;
   }
+  if (a.mean_out && tid < d) a.mean_out[tid] = a.theta[(int64_t)tid * P] + Ms[tid * 16 + d] * invP;
+  __syncthreads();
+  if (r < d && c < d) Ms[r * 16 + c] = v;
+  if (tid < kDMax * kDMax) Ls[tid] = 0.0;
+  __syncthreads();
+  // Cholesky, column by column: the diagonal by one thread, the column below
+  // it by one thread per row.
+  for (int col = 0; col < d; ++col) {
+    if (tid == 0) {
+      double q = Ms[col * 16 + col];
+      for (int t = 0; t < col; ++t) q -= Ls[col * kDMax + t] * Ls[col * kDMax + t];
+      if (q > 0.0 && sh_ok) Ls[col * kDMax + col] = sqrt(q);
+      else sh_ok = 0;
+    }
+    __syncthreads();
+    if (sh_ok && tid > col && tid < d) {
+      double q = Ms[tid * 16 + col];
+      for (int t = 0; t < col; ++t) q -= Ls[tid * kDMax + t] * Ls[col * kDMax + t];
+      Ls[tid * kDMax + col] = q / Ls[col * kDMax + col];
+    }
+    __syncthreads();
+  }
+  if (r < d && c < d) a.hchol[r * d + c] = (sh_ok && c <= r) ? sh_h * Ls[r * kDMax + c] : 0.0;
+  if (tid == 0 && !sh_ok) atomicOr(a.flags, SMC_FLAG_NOT_PD);
 }
 
 // ------------------------------------------------------------ M phase (a5) --
@@ -604,7 +652,7 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s) {
   if (ncols <= 0) return SMC_OK;
-  hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kBlock), 0, s, W, P, rss);
+  hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
   return launch_status("correct/rss");
 }
 
@@ -634,26 +682,21 @@ smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, in
   return launch_status("resample/scatter");
 }
 
-smc_status launch_moments(const double *theta, int64_t P, int32_t d, const int32_t *mh,
-                          double *mean, double *cov, double *hchol, double *part,
-                          int32_t *flags, hipStream_t s) {
-  const int64_t nb = std::min<int64_t>(kMomBlocks, (P + kBlock - 1) / kBlock);
-  const int64_t chunk = (P + nb - 1) / nb;
-  hipLaunchKernelGGL(k_mean_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, theta, P, d, chunk,
-                     part);
-  smc_status st = launch_status("moments/mean");
-  if (st) return st;
-  double *cpart = part + kMomBlocks * kDMax;
-  hipLaunchKernelGGL(k_mean_final, dim3(1), dim3(64), 0, s, part, (int32_t)nb, d, P, mean);
-  if ((st = launch_status("moments/mean_final"))) return st;
-  const int64_t chunk4 = ((chunk + 3) / 4) * 4;
-  const int64_t nb2 = (P + chunk4 - 1) / chunk4;
-  hipLaunchKernelGGL(k_cross_partial, dim3((unsigned)nb2), dim3(64), 0, s, theta, P, d, mean,
-                     chunk4, cpart);
-  if ((st = launch_status("moments/cross"))) return st;
-  hipLaunchKernelGGL(k_cov_final, dim3(1), dim3(64), 0, s, cpart, (int32_t)nb2, d, P, mh, cov,
-                     hchol, flags);
-  return launch_status("moments/cholesky");
+smc_status launch_moments(const MomArgs &args_in, bool reset_counter, hipStream_t s) {
+  MomArgs a = args_in;
+  if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < 16");
+  // About 64 particles per wave (two load batches); at most kMomBlocks
+  // blocks of four waves.
+  int64_t waves = std::max<int64_t>(1, (a.P + 63) / 64);
+  int64_t nb = std::min<int64_t>(kMomBlocks, (waves + 3) / 4);
+  int64_t chunk = (a.P + 4 * nb - 1) / (4 * nb);
+  chunk = ((chunk + 31) / 32) * 32;
+  nb = (a.P + 4 * chunk - 1) / (4 * chunk);
+  a.chunk = chunk;
+  smc_status st;
+  if (reset_counter && (st = fill_i32(a.counter, 1, 0, s))) return st;
+  hipLaunchKernelGGL(k_moments, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
+  return launch_status("particle_moments");
 }
 
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,

@@ -42,9 +42,22 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
 smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, int32_t st_bytes,
                          double *theta, double *logprior, double *loglik, void *state,
                          double *grad, double *tmp, hipStream_t s);
-smc_status launch_moments(const double *theta, int64_t P, int32_t d, const int32_t *mh,
-                          double *mean, double *cov, double *hchol, double *part,
-                          int32_t *flags, hipStream_t s);
+struct MomArgs {
+  const double *theta;
+  int64_t P;
+  int32_t d;
+  int32_t target_permille;  // step-size rule target when prev_nacc is given
+  int64_t chunk;            // particles per wave (set by the launcher)
+  double *part;             // [kMomBlocks][256] partial sums (workspace)
+  int32_t *counter;         // completion ticket (workspace, zero between launches)
+  int32_t *mh;              // step size in tenths (device)
+  const int64_t *prev_nacc; // accepts of the previous iteration, or NULL
+  int32_t mh_reset;         // > 0: set mh to this value first
+  int32_t pad;
+  double *mean_out, *cov_out, *hchol;
+  int32_t *flags;
+};
+smc_status launch_moments(const MomArgs &a, bool reset_counter, hipStream_t s);
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,

@@ -26,16 +26,36 @@ constexpr double kSqrt2OverPi = 0.79788456080286535588;
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr int kUnroll = 8;
 
-// exp(-v/2): FP64 by the device libm; FP32 by the hardware base-2 exponential.
-__device__ __forceinline__ double exp_neg_half(double v) { return exp(-0.5 * v); }
-__device__ __forceinline__ float exp_neg_half(float v) {
-  return __builtin_amdgcn_exp2f(v * -0.721347520444481703680f);  // -log2(e)/2
+// 2^x.  FP32: the hardware base-2 exponential.  FP64: x = n + f with
+// n = rint(x), |f| <= 1/2, 2^f by its Taylor series in f ln 2 to degree 13
+// (truncation below 5e-18 relative) evaluated in Estrin's scheme, which keeps
+// the dependency chain about five operations deep, then scaled by 2^n.
+// Arguments beyond the double range give 0 or inf through the final scaling.
+__device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ double exp2_fast(double x) {
+  constexpr double c0 = 1.0, c1 = 6.931471805599453094e-01, c2 = 2.402265069591007123e-01,
+                   c3 = 5.550410866482157995e-02, c4 = 9.618129107628477232e-03,
+                   c5 = 1.333355814642844343e-03, c6 = 1.540353039338160995e-04,
+                   c7 = 1.525273380405984028e-05, c8 = 1.321548679014430951e-06,
+                   c9 = 1.017808600923969859e-07, c10 = 7.054911620801123330e-09,
+                   c11 = 4.445538271870811631e-10, c12 = 2.567843599348820271e-11,
+                   c13 = 1.369148885390524890e-12;
+  const double n = __builtin_rint(x);
+  const double f = x - n;
+  const double f2 = f * f, f4 = f2 * f2, f8 = f4 * f4;
+  const double p01 = fma(c1, f, c0), p23 = fma(c3, f, c2), p45 = fma(c5, f, c4);
+  const double p67 = fma(c7, f, c6), p89 = fma(c9, f, c8), pab = fma(c11, f, c10);
+  const double pcd = fma(c13, f, c12);
+  const double q0 = fma(p23, f2, p01), q1 = fma(p67, f2, p45), q2 = fma(pab, f2, p89);
+  const double r0 = fma(q1, f4, q0), r1 = fma(pcd, f4, q2);
+  return __builtin_ldexp(fma(r1, f8, r0), (int)n);
 }
 
-// Student-t kernel term: FP64 log1p(q); FP32 log2(1 + q) (scaled by ln 2 at the end).
-__device__ __forceinline__ double t_term(double e, double inu2) { return log1p(e * e * inu2); }
-__device__ __forceinline__ float t_term(float e, float inu2) {
-  return __builtin_amdgcn_logf(fmaf(e * inu2, e, 1.0f));
+// Student-t kernel term log(1 + e^2/(nu - 2)): FP64 log1p; FP32 log2 (scaled
+// by ln 2 at the end).
+__device__ __forceinline__ double t_term(double e2, double inu2) { return log1p(e2 * inu2); }
+__device__ __forceinline__ float t_term(float e2, float inu2) {
+  return __builtin_amdgcn_logf(fmaf(e2, inu2, 1.0f));
 }
 template <typename R>
 __device__ __forceinline__ double t_scale();
@@ -59,14 +79,23 @@ struct Egarch {
   using R = R_;
   using Y = R_;
 
+  // Exponent form of the recursion.  With kappa = -log2(e)/2 and
+  // w_k = kappa v_k, the scale factor is E_s = sigma_Y / h_s = 2^(sum_k w_ks),
+  // the standardised shock is eps_s = z_s E_s with z_s = (y_s - mu_Y)/sigma_Y,
+  // and since E_s > 0, |eps_s| = |z_s| E_s.  So eq EGARCH_mod1 reads
+  //   w_k,s+1 = alpha_k w_ks - kappa beta_k sqrt(2/pi)
+  //             + kappa (beta_k |z_s| + gamma_k z_s) E_s,
+  // whose loop-carried chain is one exp2 and one fma; z_s and the bracket do
+  // not depend on the recursion.  log h_s = log sigma_Y - ln2 sum_k w_ks.
   struct Par {
-    R al[K], be[K], ga[K], bc[K];  // alpha, beta, gamma, -beta sqrt(2/pi)
-    R isig, mus;                   // 1/sigma_Y, mu_Y/sigma_Y
-    R inu2;                        // 1/(nu - 2)
-    double lsig;                   // log sigma_Y
-    double cst;                    // per-observation log-density constant
-    double hnu1;                   // (nu + 1)/2
+    R a[K], c0[K], kb[K], kg[K];  // alpha, -kappa beta c, kappa beta, kappa gamma
+    R isig, mus;                  // 1/sigma_Y, mu_Y/sigma_Y
+    R inu2;                       // 1/(nu - 2)
+    double lsig;                  // log sigma_Y
+    double cst;                   // per-observation log-density constant
+    double hnu1;                  // (nu + 1)/2
   };
+  static constexpr double kKappa = -0.72134752044448170368;  // -log2(e)/2
 
   __device__ static const Y *ydata(const DevModel &m) {
     if constexpr (sizeof(R) == 4) return m.y32;
@@ -78,10 +107,10 @@ struct Egarch {
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const double b = exp(th[2 + K + k]);
-      p.al[k] = (R)tanh(th[2 + k]);
-      p.be[k] = (R)b;
-      p.ga[k] = (R)th[2 + 2 * K + k];
-      p.bc[k] = (R)(-b * kSqrt2OverPi);
+      p.a[k] = (R)tanh(th[2 + k]);
+      p.c0[k] = (R)(-kKappa * b * kSqrt2OverPi);
+      p.kb[k] = (R)(kKappa * b);
+      p.kg[k] = (R)(kKappa * th[2 + 2 * K + k]);
     }
     const double isig = exp(-th[1]);
     p.isig = (R)isig;
@@ -100,23 +129,29 @@ struct Egarch {
     return p;
   }
 
-  __device__ static void prior_moments(int i, double &mean, double &sd) {
-    if (i == 0) { mean = 0.0; sd = 1.0; }
-    else if (i == 1) { mean = log(0.01); sd = 1.0; }
-    else if (i < 2 + K) { mean = atanh(0.95); sd = 1.0; }
-    else if (i < 2 + 2 * K) { mean = log(0.10); sd = 1.0; }
-    else if (i < 2 + 3 * K) { mean = 0.0; sd = 0.2; }
-    else { mean = log(10.0); sd = 1.0; }
+  // Table 1 (and the nu extension): prior mean, standard deviation and its
+  // logarithm of parameter i.  Hexadecimal literals are the correctly rounded
+  // log(0.01), atanh(0.95), log(0.10), log(10) and log(0.2).
+  __device__ __forceinline__ static void prior_moments(int i, double &mean, double &sd,
+                                                       double &lsd) {
+    sd = 1.0;
+    lsd = 0.0;
+    if (i == 0) mean = 0.0;
+    else if (i == 1) mean = -0x1.26bb1bbb55515p+2;
+    else if (i < 2 + K) mean = 0x1.d4ef968880dd4p+0;
+    else if (i < 2 + 2 * K) mean = -0x1.26bb1bbb55515p+1;
+    else if (i < 2 + 3 * K) { mean = 0.0; sd = 0.2; lsd = -0x1.9c041f7ed8d33p+0; }
+    else mean = 0x1.26bb1bbb55516p+1;
   }
 
   __device__ static double logprior(const double *th) {
     double lp = 0.0;
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      double m, sd;
-      prior_moments(i, m, sd);
+      double m, sd, lsd;
+      prior_moments(i, m, sd, lsd);
       const double z = (th[i] - m) / sd;
-      lp += normal_logpdf_std(z) - log(sd);
+      lp += normal_logpdf_std(z) - lsd;
     }
     return lp;
   }
@@ -126,70 +161,108 @@ struct Egarch {
     normals<D>(seed, run, p, 0, 0, kPrior, z, D);
 #pragma unroll
     for (int i = 0; i < D; ++i) {
-      double m, sd;
-      prior_moments(i, m, sd);
+      double m, sd, lsd;
+      prior_moments(i, m, sd, lsd);
       th[i] = m + sd * z[i];
     }
   }
 
-  // One observation at s >= 2: v_k <- alpha_k v_k + beta_k(|e| - c) + gamma_k e,
-  // e <- (y - mu_Y) / (sigma_Y exp(sum v / 2)).  Accumulates sum v and the
-  // shock term.
-  __device__ __forceinline__ static void step(const Par &p, R y, R (&v)[K], R &e, R &av, R &ae) {
-    const R a = fabs(e);
-    R vs = (R)0;
+  // Loop state: the exponents w_k of the observation about to be processed
+  // and their sum.
+  struct Run {
+    R w[K];
+    R sw;
+  };
+
+  // One observation: returns the exponent sum used (for log h), adds eps^2
+  // (Gaussian) or the Student-t term to ae, reports E and z, and advances r
+  // to the next observation's exponents.
+  __device__ __forceinline__ static R step(const Par &p, R y, Run &r, R &ae, R &E_out, R &z_out) {
+    const R sw = r.sw;
+    const R E = exp2_fast(sw);
+    const R z = fma(y, p.isig, -p.mus);
+    R kk = (R)0, AA = (R)0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
-      v[k] = fma(p.ga[k], e, fma(p.be[k], a, fma(p.al[k], v[k], p.bc[k])));
-      vs += v[k];
+      const R A = fma(p.a[k], r.w[k], p.c0[k]);
+      const R kz = fma(p.kb[k], fabs(z), p.kg[k] * z);
+      r.w[k] = fma(kz, E, A);
+      if (K > 1) {
+        kk += kz;
+        AA += A;
+      } else {
+        kk = kz;
+        AA = A;
+      }
     }
-    const R ex = exp_neg_half(vs);
-    const R z = fma(y, p.isig, -p.mus);
-    e = z * ex;
-    av += vs;
-    if constexpr (kT) ae += t_term(e, p.inu2);
+    r.sw = (K > 1) ? fma(kk, E, AA) : r.w[0];
+    const R e = z * E;
+    if constexpr (kT) ae += t_term(e * e, p.inu2);
     else ae = fma(e, e, ae);
+    E_out = E;
+    z_out = z;
+    return sw;
   }
 
-  // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1 with the state at
-  // t0 in st (advanced to t1).  The factors take no innovation at s = 1.
+  // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1.  st holds the
+  // state at t0 in the API's units, (v_1..v_K, eps_t0), and receives the
+  // state at t1.  The factors take no innovation at s = 1.
   __device__ static double advance(const Par &p, R (&st)[S], int64_t t0, int64_t t1,
                                    const Y *__restrict__ y) {
-    R v[K];
+    if (t1 <= t0) return 0.0;
+    Run r;
+    const R kap = (R)kKappa;
+    if (t0 == 0) {
 #pragma unroll
-    for (int k = 0; k < K; ++k) v[k] = st[k];
-    R e = st[K];
-    double sv = 0.0, se = 0.0;
-    int64_t s = t0;
-    if (s == 0 && t1 > 0) {
-      e = fma(y[0], p.isig, -p.mus);
-      if constexpr (kT) se += (double)t_term(e, p.inu2);
-      else se += (double)(e * e);
-      s = 1;
+      for (int k = 0; k < K; ++k) r.w[k] = (R)0;
+    } else {
+      // w_k at t0+1 from (v_k, eps) at t0, in the model's own form
+      const R e = st[K];
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        r.w[k] = fma(p.kb[k], fabs(e), fma(p.kg[k], e, fma(p.a[k], kap * st[k], p.c0[k])));
     }
-    for (; s + kUnroll <= t1; s += kUnroll) {
+    R sw0 = r.w[0];
+#pragma unroll
+    for (int k = 1; k < K; ++k) sw0 += r.w[k];
+    r.sw = sw0;
+    double sv = 0.0, se = 0.0;
+    const Y *yp = y + t0;
+    const int n = (int)(t1 - t0);
+    const int nm = n - 1;  // all but the last observation
+    const int nb = nm / kUnroll;
+    for (int b = 0; b < nb; ++b, yp += kUnroll) {
       R yb[kUnroll];
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) yb[i] = y[s + i];
-      R av = (R)0, ae = (R)0;
+      for (int i = 0; i < kUnroll; ++i) yb[i] = yp[i];
+      R av, ae = (R)0, Ed, zd;
+      av = step(p, yb[0], r, ae, Ed, zd);
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) step(p, yb[i], v, e, av, ae);
+      for (int i = 1; i < kUnroll; ++i) av += step(p, yb[i], r, ae, Ed, zd);
       sv += (double)av;
       se += (double)ae;
     }
-    for (; s < t1; ++s) {
-      R av = (R)0, ae = (R)0;
-      step(p, y[s], v, e, av, ae);
+    for (int i = nb * kUnroll; i < nm; ++i, ++yp) {
+      R ae = (R)0, Ed, zd;
+      const R av = step(p, *yp, r, ae, Ed, zd);
       sv += (double)av;
       se += (double)ae;
     }
+    // The last observation: keep its exponents and shock for the state.
+    R wl[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) st[k] = v[k];
-    st[K] = e;
-    const double n = (double)(t1 - t0);
-    // log h_s = log sigma_Y + sum_k v_ks / 2
-    if constexpr (kT) return n * (p.cst - p.lsig) - 0.5 * sv - p.hnu1 * t_scale<R>() * se;
-    else return n * (p.cst - p.lsig) - 0.5 * sv - 0.5 * se;
+    for (int k = 0; k < K; ++k) wl[k] = r.w[k];
+    R ae = (R)0, E, z;
+    const R av = step(p, *yp, r, ae, E, z);
+    sv += (double)av;
+    se += (double)ae;
+#pragma unroll
+    for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
+    st[K] = z * E;
+    const double nd = (double)n;
+    // log h_s = log sigma_Y - ln2 * sum_k w_ks
+    if constexpr (kT) return nd * (p.cst - p.lsig) + kLn2 * sv - p.hnu1 * t_scale<R>() * se;
+    else return nd * (p.cst - p.lsig) + kLn2 * sv - 0.5 * se;
   }
 };
 

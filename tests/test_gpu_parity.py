@@ -34,6 +34,10 @@ def _close(got, want, prec, n_obs):
     either sign can be near zero while its terms are not)."""
     got, want = np.asarray(got), np.asarray(want)
     same_inf = np.isinf(want) & (got == want)
+    if prec != S.SMC_FP64:
+        # beyond the float range a log density is -inf in FP32; its weight is
+        # zero in either precision
+        same_inf |= (want < -1e30) & (got < -1e30)
     got = np.where(same_inf, 0.0, got)
     want = np.where(same_inf, 0.0, want)
     if prec == S.SMC_FP64:
