@@ -230,14 +230,17 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
   const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
   double *rsscols = ws_at<double>(pop, L.rsscols);
   double *W = ws_at<double>(pop, L.wcols);
-  if ((st = fill_f64(pop->logw, P, 0.0, s))) return st;
   int64_t t_stop = t_max;
   double rss_at_stop = 1.0;
   const bool adaptive = rss_min > 0.0 && t_from < t_max;
+  // logw = 0 at the start of the phase: folded into the first kernel that
+  // touches the weights (or a fill when no observation is added).
+  if (t_max == t_from && (st = fill_f64(pop->logw, P, 0.0, s))) return st;
+  bool zero_first = true;
   if (!adaptive) {
     if (t_max > t_from &&
         (st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t_from,
-                             t_max, s)))
+                             t_max, true, s)))
       return st;
     if (rss) {
       if ((st = launch_rss_cols(pop->logw, P, 1, rsscols, s))) return st;
@@ -266,14 +269,15 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
         if (u % check_every == 0 || u == t_max) dates.push_back(u);
       if (dates.empty()) {
         if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
-                                 t1, s)))
+                                 t1, zero_first, s)))
           return st;
+        zero_first = false;
         t = t1;
         chunk = std::min(2 * chunk, cap);
         continue;
       }
       if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, t, t1, check_every,
-                             t_max, W, s)))
+                             t_max, zero_first, W, s)))
         return st;
       const int64_t nc = (int64_t)dates.size();
       if ((st = launch_rss_cols(W, P, nc, rsscols, s))) return st;
@@ -289,8 +293,9 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
         }
       const int64_t t_commit = stop_col >= 0 ? dates[stop_col] : t1;
       if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
-                               t_commit, s)))
+                               t_commit, zero_first, s)))
         return st;
+      zero_first = false;
       rss_at_stop = stop_col >= 0 ? host_rss[stop_col] : host_rss[nc - 1];
       t = t_commit;
       if (stop_col >= 0 || t >= t_max) stopped = true;
@@ -315,13 +320,12 @@ smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, 
   hipStream_t s = as_stream(stream);
   const int64_t P = (int64_t)pop->J * pop->N;
   const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
-  if ((st = launch_resample(pop->logw, pop->J, pop->N, scheme, rng.seed, rng.run,
-                            (uint64_t)cycle, pop->ancestor, ws_at<double>(pop, L.cum),
-                            ws_at<int32_t>(pop, L.small + kSmallFlags), s)))
-    return st;
-  return launch_gather(pop->ancestor, P, m->dev.d, m->dev.S, state_bytes(m), pop->theta,
-                       pop->logprior, pop->loglik, pop->state, pop->grad,
-                       ws_at<double>(pop, L.gather), s);
+  (void)P;
+  return launch_resample(pop->logw, pop->J, pop->N, scheme, rng.seed, rng.run, (uint64_t)cycle,
+                         pop->ancestor, ws_at<double>(pop, L.cum),
+                         ws_at<int32_t>(pop, L.small + kSmallFlags), m->dev.d, m->dev.S,
+                         state_bytes(m), pop->theta, pop->logprior, pop->loglik, pop->state,
+                         pop->grad, ws_at<double>(pop, L.gather), s);
 }
 
 smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, const int32_t *mh,
@@ -336,13 +340,12 @@ smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, co
   a.P = P;
   a.d = m->dev.d;
   a.part = ws_at<double>(pop, L.mpart);
-  a.counter = ws_at<int32_t>(pop, L.small + kSmallTicket);
   a.mh = const_cast<int32_t *>(mh);
   a.mean_out = mean;
   a.cov_out = cov;
   a.hchol = hchol;
   a.flags = ws_at<int32_t>(pop, L.small + kSmallFlags);
-  return launch_moments(a, true, as_stream(stream));
+  return launch_moments(a, as_stream(stream));
 }
 
 smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t kernel,
@@ -441,18 +444,15 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
   int32_t *mh = ws_at<int32_t>(pop, L.small + kSmallMh);
   int32_t *dflags = ws_at<int32_t>(pop, L.small + kSmallFlags);
-  int32_t *ticket = ws_at<int32_t>(pop, L.small + kSmallTicket);
-  if ((st = fill_i32(dflags, 1, 0, s)) || (st = fill_i32(ticket, 1, 0, s))) return st;
+  if ((st = fill_i32(dflags, 1, 0, s))) return st;
   if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
-  // The moments kernel leaves its ticket at zero, so after this fill every
-  // iteration needs a single launch for the step-size rule, V and h L.
+  // Moments with the step-size rule folded in: no separate launch for it.
   MomArgs ma{};
   ma.theta = pop->theta;
   ma.P = P;
   ma.d = d;
   ma.target_permille = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
   ma.part = ws_at<double>(pop, L.mpart);
-  ma.counter = ticket;
   ma.mh = mh;
   ma.flags = dflags;
   if ((st = smc_init_from_prior(m, pop, cfg->rng, stream))) return st;
@@ -509,7 +509,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         ma.mh_reset = (r == 1) ? 5 : 0;
         ma.prev_nacc = (r == 1) ? nullptr : nacc - 1;
         ma.hchol = hl;
-        if ((st = launch_moments(ma, false, s))) return st;
+        if ((st = launch_moments(ma, s))) return st;
       }
       Timed *ev = nullptr;
       if (rec->mutate_ms) {

@@ -52,7 +52,6 @@ constexpr int kMomBlocks = 256;
 constexpr size_t kSmallFlags = 0;    // int32
 constexpr size_t kSmallMh = 16;      // int32
 constexpr size_t kSmallNacc = 32;    // int64
-constexpr size_t kSmallTicket = 48;  // int32 completion ticket of the moments kernel
 constexpr size_t kSmallRss = 64;     // double
 constexpr size_t kSmallRne = 72;     // double
 constexpr size_t kSmallMean = 256;   // double[16]

@@ -92,7 +92,7 @@ template <class M>
 __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
                                               const void *state, const double *logw, int64_t t0,
                                               int64_t t1, int64_t check_every, int64_t t_max,
-                                              double *W) {
+                                              int32_t zero_first, double *W) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
   using R = typename M::R;
@@ -104,7 +104,7 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
   R st[SR];
 #pragma unroll
   for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
-  double lw = logw[p];
+  double lw = zero_first ? 0.0 : logw[p];
   int64_t col = 0;
   for (int64_t s = t0 + 1; s <= t1; ++s) {
     double lp = Eval<M>::advance(dm, par, st, s - 1, s);
@@ -121,7 +121,7 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
 template <class M>
 __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
                                                 void *state, double *logw, double *loglik,
-                                                int64_t t0, int64_t t1) {
+                                                int64_t t0, int64_t t1, int32_t zero_first) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
   using R = typename M::R;
@@ -136,7 +136,7 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
   for (int k = 0; k < SR; ++k) st[k] = (k < SS) ? typed<R>(state)[k * P + p] : (R)0;
   double lp = Eval<M>::advance(dm, par, st, t0, t1);
   if (isnan(lp)) lp = -INFINITY;
-  logw[p] += lp;
+  logw[p] = (zero_first ? 0.0 : logw[p]) + lp;
   loglik[p] += lp;
 #pragma unroll
   for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
@@ -215,9 +215,19 @@ __global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32
 // ------------------------------------------------------------ S phase (a3) --
 // One block per group.  Counts live in LDS (dynamic, N int32); the running
 // residual sums in the workspace.
+struct GatherArgs {
+  const int32_t *anc;
+  int64_t P;
+  int32_t d, S, st_bytes, has_grad;
+  double *theta, *logprior, *loglik, *grad;
+  void *state;
+  double *tmp;  // [2d + S + 2][P]
+};
+
 __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
                                                   uint64_t seed, uint64_t run, uint64_t cycle,
-                                                  int32_t *anc, double *cum_ws, int32_t *flags) {
+                                                  int32_t *anc, double *cum_ws, int32_t *flags,
+                                                  GatherArgs g) {
   extern __shared__ int32_t cnt[];
   __shared__ double shd[kBlock];
   __shared__ int64_t shi[kBlock];
@@ -284,105 +294,101 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   int64_t pos = block_inclusive_scan<int64_t>(my, shi, tot2) - my;
   for (int n = lo; n < hi; ++n)
     for (int c = 0; c < cnt[n] && pos < N; ++c) anc[base + pos++] = (int32_t)(base + n);
-}
-
-struct GatherArgs {
-  const int32_t *anc;
-  int64_t P;
-  int32_t d, S, st_bytes, has_grad;
-  double *theta, *logprior, *loglik, *grad;
-  void *state;
-  double *tmp;  // [2d + S + 2][P]
-};
-
-__global__ void __launch_bounds__(256) k_gather(GatherArgs g) {
-  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (p >= g.P) return;
-  const int64_t a = g.anc[p];
+  __syncthreads();
+  // Replace the group's particles by their ancestors (all inside this
+  // group): copy the ancestors' values to the workspace, then back.
   const int64_t P = g.P;
-  int r = 0;
-  for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.theta[i * P + a];
-  g.tmp[r++ * P + p] = g.logprior[a];
-  g.tmp[r++ * P + p] = g.loglik[a];
-  for (int k = 0; k < g.S; ++k, ++r)
-    g.tmp[r * P + p] = g.st_bytes == 8 ? typed<double>(g.state)[k * P + a]
-                                       : (double)typed<float>(g.state)[k * P + a];
-  if (g.has_grad)
-    for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.grad[i * P + a];
-}
-
-__global__ void __launch_bounds__(256) k_scatter_back(GatherArgs g) {
-  const int64_t p = blockIdx.x * (int64_t)kBlock + threadIdx.x;
-  if (p >= g.P) return;
-  const int64_t P = g.P;
-  int r = 0;
-  for (int i = 0; i < g.d; ++i, ++r) g.theta[i * P + p] = g.tmp[r * P + p];
-  g.logprior[p] = g.tmp[r++ * P + p];
-  g.loglik[p] = g.tmp[r++ * P + p];
-  for (int k = 0; k < g.S; ++k, ++r) {
-    if (g.st_bytes == 8) typed<double>(g.state)[k * P + p] = g.tmp[r * P + p];
-    else typed<float>(g.state)[k * P + p] = (float)g.tmp[r * P + p];
+  for (int n = tid; n < N; n += kBlock) {
+    const int64_t p = base + n;
+    const int64_t a = anc[p];
+    int r = 0;
+    for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.theta[i * P + a];
+    g.tmp[r++ * P + p] = g.logprior[a];
+    g.tmp[r++ * P + p] = g.loglik[a];
+    for (int k = 0; k < g.S; ++k, ++r)
+      g.tmp[r * P + p] = g.st_bytes == 8 ? typed<double>(g.state)[k * P + a]
+                                         : (double)typed<float>(g.state)[k * P + a];
+    if (g.has_grad)
+      for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.grad[i * P + a];
   }
-  if (g.has_grad)
-    for (int i = 0; i < g.d; ++i, ++r) g.grad[i * P + p] = g.tmp[r * P + p];
+  __syncthreads();
+  for (int n = tid; n < N; n += kBlock) {
+    const int64_t p = base + n;
+    int r = 0;
+    for (int i = 0; i < g.d; ++i, ++r) g.theta[i * P + p] = g.tmp[r * P + p];
+    g.logprior[p] = g.tmp[r++ * P + p];
+    g.loglik[p] = g.tmp[r++ * P + p];
+    for (int k = 0; k < g.S; ++k, ++r) {
+      if (g.st_bytes == 8) typed<double>(g.state)[k * P + p] = g.tmp[r * P + p];
+      else typed<float>(g.state)[k * P + p] = (float)g.tmp[r * P + p];
+    }
+    if (g.has_grad)
+      for (int i = 0; i < g.d; ++i, ++r) g.grad[i * P + p] = g.tmp[r * P + p];
+  }
 }
 
 // ----------------------------------------------- particle moments (a4) ----
-// One launch: every wave accumulates sum_p x_p x_p' on the matrix cores with
+// Pass 1: every wave accumulates sum_p x_p x_p' on the matrix cores with
 // x_p = (theta_p - s, 1, 0, ...) padded to 16 (s = particle 0, a shift that
 // keeps the one-pass sums well conditioned; the constant slot d carries the
 // first moments and the count).  v_mfma_f64_16x16x4f64 takes four particles
 // per instruction.  Operand layout (measured on gfx950): lane l supplies
 // element (row l%16, k = l/16) of A and (k = l/16, col l%16) of B, so
 // A = B' = the 16x4 block of shifted particles; accumulator register r of
-// lane l holds element (4r + l/16, l%16) of the 16x16 result.
-// Blocks write their partial matrices; the last block to finish (atomic
-// ticket) adds them in block order, optionally applies the step-size rule to
-// mh, forms mean and V (divisor P - 1), factors V = L L' and writes h L.
-__global__ void __launch_bounds__(256) k_moments(MomArgs a) {
+// lane l holds element (4r + l/16, l%16) of the 16x16 result.  Each block
+// writes one partial matrix.
+__global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_t P, int32_t d,
+                                                     int64_t chunk, double *part) {
   __shared__ double red[4][256];
-  __shared__ double Ms[256];
-  __shared__ double Ls[kDMax * kDMax];
-  __shared__ double sh_h;
-  __shared__ int sh_last, sh_ok;
   typedef double double4v __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
   const int i = l & 15, k = l >> 4;
-  const int d = a.d;
-  const int64_t P = a.P;
-  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wv) * a.chunk;
-  const int64_t p1 = min(P, p0 + a.chunk);
-  const double si = (i < d) ? a.theta[(int64_t)i * P] : 0.0;
+  const int64_t p0 = ((int64_t)blockIdx.x * 4 + wv) * chunk;
+  const int64_t p1 = min(P, p0 + chunk);
+  const int ir = i < d ? i : 0;  // a valid row to load from when i >= d
+  const double si = theta[(int64_t)ir * P];
   double4v acc = {0.0, 0.0, 0.0, 0.0};
-  // Eight MFMA steps per batch with their loads issued first, so the wave
-  // waits for memory once per 32 particles.
+  // Eight MFMA steps per batch with all loads issued first (addresses are
+  // clamped into the wave's range and masked afterwards).
   for (int64_t q0 = p0; q0 < p1; q0 += 32) {
     double x[8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t p = q0 + 4 * u + k;
-      x[u] = 0.0;
-      if (p < p1) x[u] = (i < d) ? a.theta[(int64_t)i * P + p] - si : (i == d ? 1.0 : 0.0);
+      const int64_t pc = p < p1 ? p : p1 - 1;
+      x[u] = theta[(int64_t)ir * P + pc];
     }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64(x[u], x[u], acc, 0, 0, 0);
+    for (int u = 0; u < 8; ++u) {
+      const int64_t p = q0 + 4 * u + k;
+      const double v = (i < d) ? x[u] - si : (i == d ? 1.0 : 0.0);
+      const double xm = p < p1 ? v : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xm, xm, acc, 0, 0, 0);
+    }
   }
 #pragma unroll
   for (int r = 0; r < 4; ++r) red[wv][(4 * r + k) * 16 + i] = acc[r];
   __syncthreads();
-  a.part[blockIdx.x * 256 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
-  __threadfence();
-  __syncthreads();
-  if (tid == 0) sh_last = (atomicAdd(a.counter, 1) == (int)gridDim.x - 1);
-  __syncthreads();
-  if (!sh_last) return;
-  __threadfence();
+  part[blockIdx.x * 256 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+}
+
+// Pass 2 (one block): add the partial matrices in block order, optionally
+// apply the step-size rule to mh, form the mean and V (divisor P - 1),
+// factor V = L L' and write h L.  A variance that is not positive definite
+// raises the flag and yields h L = 0.
+__global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
+  __shared__ double Ms[256];
+  __shared__ double Ls[kDMax * kDMax];
+  __shared__ double sh_h;
+  __shared__ int sh_ok;
+  const int tid = threadIdx.x;
+  const int d = a.d;
+  const int64_t P = a.P;
   double sum = 0.0;
-#pragma unroll 8
-  for (int b = 0; b < (int)gridDim.x; ++b) sum += a.part[b * 256 + tid];
+#pragma unroll 16
+  for (int b = 0; b < nb; ++b) sum += a.part[b * 256 + tid];
   Ms[tid] = sum;
   if (tid == 0) {
-    *a.counter = 0;  // every other block has taken its ticket
     int32_t m = *a.mh;
     if (a.mh_reset > 0) {
       m = a.mh_reset;
@@ -395,7 +401,6 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a) {
     sh_ok = 1;
   }
   __syncthreads();
-  // V and the mean from the shifted sums; V kept in Ms (row stride 16).
   const double invP = 1.0 / (double)P;
   const int r = tid >> 4, c = tid & 15;
   double v = 0.0;
@@ -406,7 +411,7 @@ __global__ void __launch_bounds__(256) k_moments(MomArgs a) {
   if (a.mean_out && tid < d) a.mean_out[tid] = a.theta[(int64_t)tid * P] + Ms[tid * 16 + d] * invP;
   __syncthreads();
   if (r < d && c < d) Ms[r * 16 + c] = v;
-  if (tid < kDMax * kDMax) Ls[tid] = 0.0;
+  Ls[tid] = 0.0;
   __syncthreads();
   // Cholesky, column by column: the diagonal by one thread, the column below
   // it by one thread per row.
@@ -630,21 +635,22 @@ smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run
 
 smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                         const double *logw, int64_t t0, int64_t t1, int64_t check_every,
-                        int64_t t_max, double *W, hipStream_t s) {
+                        int64_t t_max, bool zero_first, double *W, hipStream_t s) {
   return dispatch(m, [&](auto tag) {
     using M = typename decltype(tag)::type;
     hipLaunchKernelGGL(k_cscan<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw, t0,
-                       t1, check_every, t_max, W);
+                       t1, check_every, t_max, (int32_t)zero_first, W);
     return launch_status("correct/scan");
   });
 }
 
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
-                          double *logw, double *loglik, int64_t t0, int64_t t1, hipStream_t s) {
+                          double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
+                          hipStream_t s) {
   return dispatch(m, [&](auto tag) {
     using M = typename decltype(tag)::type;
     hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
-                       loglik, t0, t1);
+                       loglik, t0, t1, (int32_t)zero_first);
     return launch_status("correct/commit");
   });
 }
@@ -664,39 +670,32 @@ smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double
 
 smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
-                           double *cum_ws, int32_t *flags, hipStream_t s) {
+                           double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
+                           double *theta, double *logprior, double *loglik, void *state,
+                           double *grad, double *tmp, hipStream_t s) {
+  const int64_t P = (int64_t)J * N;
+  GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
+               state, tmp};
   hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), (size_t)N * sizeof(int32_t), s, logw, N,
-                     scheme, seed, run, cycle, anc, cum_ws, flags);
+                     scheme, seed, run, cycle, anc, cum_ws, flags, g);
   return launch_status("resample");
 }
 
-smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, int32_t st_bytes,
-                         double *theta, double *logprior, double *loglik, void *state,
-                         double *grad, double *tmp, hipStream_t s) {
-  GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
-               state, tmp};
-  hipLaunchKernelGGL(k_gather, grid_for(P, kBlock), dim3(kBlock), 0, s, g);
-  smc_status st = launch_status("resample/gather");
-  if (st) return st;
-  hipLaunchKernelGGL(k_scatter_back, grid_for(P, kBlock), dim3(kBlock), 0, s, g);
-  return launch_status("resample/scatter");
-}
-
-smc_status launch_moments(const MomArgs &args_in, bool reset_counter, hipStream_t s) {
-  MomArgs a = args_in;
+smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < 16");
   // About 64 particles per wave (two load batches); at most kMomBlocks
   // blocks of four waves.
-  int64_t waves = std::max<int64_t>(1, (a.P + 63) / 64);
+  const int64_t waves = std::max<int64_t>(1, (a.P + 63) / 64);
   int64_t nb = std::min<int64_t>(kMomBlocks, (waves + 3) / 4);
   int64_t chunk = (a.P + 4 * nb - 1) / (4 * nb);
   chunk = ((chunk + 31) / 32) * 32;
   nb = (a.P + 4 * chunk - 1) / (4 * chunk);
-  a.chunk = chunk;
-  smc_status st;
-  if (reset_counter && (st = fill_i32(a.counter, 1, 0, s))) return st;
-  hipLaunchKernelGGL(k_moments, dim3((unsigned)nb), dim3(kBlock), 0, s, a);
-  return launch_status("particle_moments");
+  hipLaunchKernelGGL(k_mom_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
+                     chunk, a.part);
+  smc_status st = launch_status("particle_moments/partial");
+  if (st) return st;
+  hipLaunchKernelGGL(k_mom_final, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
+  return launch_status("particle_moments/final");
 }
 
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,

@@ -27,29 +27,31 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);
 smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
                        double *logprior, double *loglik, void *state, double *logw,
                        hipStream_t s);
+// zero_first: treat the log weights as zero on entry (the first call of a C
+// phase), which saves a separate fill.
 smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                         const double *logw, int64_t t0, int64_t t1, int64_t check_every,
-                        int64_t t_max, double *W, hipStream_t s);
+                        int64_t t_max, bool zero_first, double *W, hipStream_t s);
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
-                          double *logw, double *loglik, int64_t t0, int64_t t1, hipStream_t s);
+                          double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
+                          hipStream_t s);
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
+// Resampling and the replacement of every particle by its ancestor, one block
+// per group.
 smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
-                           double *cum_ws, int32_t *flags, hipStream_t s);
-smc_status launch_gather(const int32_t *anc, int64_t P, int32_t d, int32_t S, int32_t st_bytes,
-                         double *theta, double *logprior, double *loglik, void *state,
-                         double *grad, double *tmp, hipStream_t s);
+                           double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
+                           double *theta, double *logprior, double *loglik, void *state,
+                           double *grad, double *tmp, hipStream_t s);
 struct MomArgs {
   const double *theta;
   int64_t P;
   int32_t d;
   int32_t target_permille;  // step-size rule target when prev_nacc is given
-  int64_t chunk;            // particles per wave (set by the launcher)
   double *part;             // [kMomBlocks][256] partial sums (workspace)
-  int32_t *counter;         // completion ticket (workspace, zero between launches)
   int32_t *mh;              // step size in tenths (device)
   const int64_t *prev_nacc; // accepts of the previous iteration, or NULL
   int32_t mh_reset;         // > 0: set mh to this value first
@@ -57,7 +59,7 @@ struct MomArgs {
   double *mean_out, *cov_out, *hchol;
   int32_t *flags;
 };
-smc_status launch_moments(const MomArgs &a, bool reset_counter, hipStream_t s);
+smc_status launch_moments(const MomArgs &a, hipStream_t s);
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
