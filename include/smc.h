@@ -182,12 +182,24 @@ smc_status smc_loglik(const smc_model *m, int64_t P, const double *theta, int64_
 
 /* Adjoint of smc_loglik: dtheta[i][p] = dloglik[p] * d log p(y_{1:t}|theta_p)
  * / d theta_ip.  The forward recursion is checkpointed every 64 observations
- * into the workspace ws (>= smc_backward_ws_bytes bytes) and replayed
- * segment by segment in reverse.  d|x|/dx is taken as 0 at x = 0. */
+ * (FP32 models; 32 for FP64) into ws (>= smc_backward_ws_bytes bytes, device)
+ * and replayed segment by segment in reverse through a per-lane LDS buffer.
+ * d|x|/dx is taken as 0 at x = 0. */
 smc_status smc_loglik_backward(const smc_model *m, int64_t P, const double *theta, int64_t t,
                                const double *dloglik, double *dtheta, void *ws,
                                size_t ws_bytes, void *stream);
 size_t smc_backward_ws_bytes(const smc_model *m, int64_t P, int64_t t);
+
+/* grad[i][p] = d/dtheta_i [log p(theta_p) + log p(y_{1:t} | theta_p)] for every
+ * particle (pop->grad must be set; uses the workspace tail for checkpoints,
+ * see smc_mala_workspace_bytes).  The Langevin kernel needs it at each new
+ * date before its first iteration. */
+smc_status smc_posterior_grad(const smc_model *m, smc_particles *pop, int64_t t, void *stream);
+
+/* Workspace bytes for a population that also runs the Langevin kernel or
+ * smc_posterior_grad at any date up to T (the checkpoints share the tail of
+ * the workspace with the C-phase chunks). */
+size_t smc_mala_workspace_bytes(const smc_model *m, int32_t J, int32_t N, int64_t max_chunk);
 
 /* Marginal likelihood from the per-cycle group mean weights (Section 4.2):
  * group_logwbar: device [L][J] (log wbar_j(l-1)); out: device [3] =

@@ -87,6 +87,10 @@ def lib():
         L.smc_workspace_bytes.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64]
         L.smc_backward_ws_bytes.restype = C.c_size_t
         L.smc_backward_ws_bytes.argtypes = [_vp, C.c_int64, C.c_int64]
+        L.smc_mala_workspace_bytes.restype = C.c_size_t
+        L.smc_mala_workspace_bytes.argtypes = [_vp, C.c_int32, C.c_int32, C.c_int64]
+        L.smc_posterior_grad.restype = st
+        L.smc_posterior_grad.argtypes = [_vp, P(Particles), C.c_int64, _vp]
         L.smc_init_from_prior.restype = st
         L.smc_init_from_prior.argtypes = [_vp, P(Particles), Rng, _vp]
         L.smc_correct.restype = st
@@ -204,7 +208,8 @@ class Population:
         self.grad = torch.zeros((model.d, P), **f64) if with_grad else None
         self.ancestor = torch.zeros(P, dtype=torch.int32, device=dev)
         self.max_chunk = max_chunk
-        nb = lib().smc_workspace_bytes(model.h, J, N, max_chunk)
+        nb = (lib().smc_mala_workspace_bytes(model.h, J, N, max_chunk) if with_grad
+              else lib().smc_workspace_bytes(model.h, J, N, max_chunk))
         if nb == 0:
             raise SmcError(-1, "smc_workspace_bytes")
         self.ws = torch.empty(nb + 256, dtype=torch.uint8, device=dev)
@@ -275,6 +280,13 @@ def smc_loglik_backward(model, theta, t, dloglik, stream=None):
     _check(lib().smc_loglik_backward(model.h, P, _ptr(theta), t, _ptr(dloglik), _ptr(dtheta),
                                      _ptr(ws), nb, _stream(stream)), "smc_loglik_backward")
     return dtheta
+
+
+def smc_posterior_grad(model, pop, t, stream=None):
+    """pop.grad <- gradient of log prior + log likelihood over 1..t."""
+    _check(lib().smc_posterior_grad(model.h, C.byref(pop.c), t, _stream(stream)),
+           "smc_posterior_grad")
+    return pop.grad
 
 
 def smc_log_ml(group_logwbar, stream=None):

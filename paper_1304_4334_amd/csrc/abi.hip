@@ -360,8 +360,19 @@ smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t
     return launch_mutate_rw(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
                             hchol, rng.seed, rng.run, (uint64_t)cycle, (uint64_t)iter, n_accept,
                             accepted, as_stream(stream));
-  if (kernel == SMC_KERNEL_MALA)
-    return set_error(SMC_E_UNSUPPORTED, "Langevin kernel not built");
+  if (kernel == SMC_KERNEL_MALA) {
+    if (!pop->grad) return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
+    if ((st = check_pop(m, pop))) return st;
+    const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+    const size_t need = adjoint_ckpt_bytes(m->dev, P, t);
+    if (pop->ws_bytes < L.wcols + need)
+      return set_error(SMC_E_WORKSPACE, "Langevin step needs %zu workspace bytes",
+                       L.wcols + need);
+    return launch_mutate_mala(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
+                              pop->grad, hchol, rng.seed, rng.run, (uint64_t)cycle,
+                              (uint64_t)iter, n_accept, accepted, ws_at<char>(pop, L.wcols),
+                              as_stream(stream));
+  }
   return set_error(SMC_E_INVALID_ARG, "kernel %d", kernel);
 }
 
@@ -376,18 +387,46 @@ smc_status smc_loglik(const smc_model *m, int64_t P, const double *theta, int64_
 }
 
 size_t smc_backward_ws_bytes(const smc_model *m, int64_t P, int64_t t) {
-  (void)m;
-  (void)P;
-  (void)t;
-  return 0;
+  if (!m || P < 0 || t < 0) return 0;
+  return adjoint_ckpt_bytes(m->dev, P, t);
 }
 
 smc_status smc_loglik_backward(const smc_model *m, int64_t P, const double *theta, int64_t t,
                                const double *dloglik, double *dtheta, void *ws, size_t ws_bytes,
                                void *stream) {
-  (void)m; (void)P; (void)theta; (void)t; (void)dloglik; (void)dtheta; (void)ws;
-  (void)ws_bytes; (void)stream;
-  return set_error(SMC_E_UNSUPPORTED, "adjoint kernel not built");
+  smc_status st;
+  if ((st = check_model(m))) return st;
+  if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date t out of range");
+  if (P == 0) return SMC_OK;
+  if (P < 0 || !theta || !dloglik || !dtheta)
+    return set_error(SMC_E_INVALID_ARG, "bad loglik_backward arguments");
+  const size_t need = adjoint_ckpt_bytes(m->dev, P, t);
+  if (need > 0 && (!ws || ws_bytes < need))
+    return set_error(SMC_E_WORKSPACE, "adjoint needs %zu workspace bytes", need);
+  return launch_loglik_backward(m->dev, P, theta, t, dloglik, dtheta, ws, as_stream(stream));
+}
+
+size_t smc_mala_workspace_bytes(const smc_model *m, int32_t J, int32_t N, int64_t max_chunk) {
+  if (!m || J < 1 || N < 1) return 0;
+  const size_t base = smc_workspace_bytes(m, J, N, max_chunk);
+  const WsLayout L = ws_layout(m->dev, J, N);
+  const size_t ck = L.wcols + adjoint_ckpt_bytes(m->dev, (int64_t)J * N, m->dev.T);
+  return base > ck ? base : ck;
+}
+
+smc_status smc_posterior_grad(const smc_model *m, smc_particles *pop, int64_t t, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!pop->grad) return set_error(SMC_E_INVALID_ARG, "pop->grad is NULL");
+  if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date t out of range");
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  const size_t need = adjoint_ckpt_bytes(m->dev, P, t);
+  if (pop->ws_bytes < L.wcols + need)
+    return set_error(SMC_E_WORKSPACE, "posterior gradient needs %zu workspace bytes",
+                     L.wcols + need);
+  return launch_grad_post(m->dev, P, pop->theta, t, pop->grad, ws_at<char>(pop, L.wcols),
+                          as_stream(stream));
 }
 
 smc_status smc_log_ml(int32_t L, int32_t J, const double *group_logwbar, double *out,
@@ -435,8 +474,10 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     return set_error(SMC_E_INVALID_ARG, "a record array is NULL");
   if (cfg->Lmax < 1 || cfg->RmaxRec < 1 || cfg->check_every < 1 || cfg->force_every < 0)
     return set_error(SMC_E_INVALID_ARG, "bad record capacity or check spacing");
-  if (cfg->kernel != SMC_KERNEL_RW)
-    return set_error(SMC_E_UNSUPPORTED, "only the random-walk kernel is built");
+  if (cfg->kernel != SMC_KERNEL_RW && cfg->kernel != SMC_KERNEL_MALA)
+    return set_error(SMC_E_INVALID_ARG, "kernel %d", cfg->kernel);
+  if (cfg->kernel == SMC_KERNEL_MALA && !pop->grad)
+    return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
   hipStream_t s = as_stream(stream);
   const int64_t P = (int64_t)pop->J * pop->N;
   const int32_t d = m->dev.d;
@@ -496,6 +537,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     if ((st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream))) return st;
     int32_t R = cfg->replay ? rec->R[l] : (rss < cfg->D2 ? cfg->kappa * cfg->Rbar : cfg->Rbar);
     if (R < 1) return set_error(SMC_E_INVALID_ARG, "R_l < 1 in cycle %d", l);
+    // The Langevin drift needs the posterior gradient at the new date.
+    if (cfg->kernel == SMC_KERNEL_MALA && (st = smc_posterior_grad(m, pop, t_new, stream)))
+      return st;
     int32_t r = 0;
     for (;;) {
       ++r;

@@ -10,6 +10,9 @@
 #include <hip/hip_runtime.h>
 #include <math.h>
 
+#include <type_traits>
+
+#include "adjoint.h"
 #include "common.h"
 #include "launch.h"
 #include "model.h"
@@ -598,6 +601,168 @@ __global__ void k_log_ml(int32_t L, int32_t J, const double *g, double *out) {
   out[2] = lt;
 }
 
+// ------------------------------------- gradients and the Langevin step (a8) --
+template <class M>
+struct IsLinreg : std::false_type {};
+template <int NREG>
+struct IsLinreg<Linreg<NREG>> : std::true_type {};
+
+// Value of log p(y_{1:t} | theta) with its gradient added (times scale) to
+// g, and the state at t.  ckpt: this call's checkpoint area; lds: this lane's
+// column of the block's LDS buffer.
+template <class M>
+__device__ __forceinline__ double ll_and_grad(const DevModel &dm, const double *th, int64_t t,
+                                              void *ckpt, int64_t P, int64_t p, void *lds,
+                                              double scale, double *g,
+                                              typename M::R (&st)[Eval<M>::SR]) {
+  if constexpr (IsLinreg<M>::value) {
+    st[0] = 0.0;
+    return Adjoint<M>::value_and_grad(dm, th, t, scale, g);
+  } else {
+    using R = typename M::R;
+    const auto par = M::params(th);
+    return Adjoint<M>::value_and_grad(par, th, t, M::ydata(dm), typed<R>(ckpt), P, p,
+                                      typed<R>(lds) + threadIdx.x, scale, g, st);
+  }
+}
+
+template <class M>
+constexpr size_t lds_bytes_of() {
+  if constexpr (IsLinreg<M>::value) return 0;
+  else return (size_t)Adjoint<M>::kLdsPerLane * 64 * sizeof(typename M::R);
+}
+
+template <class M>
+__global__ void __launch_bounds__(64) k_loglik_backward(DevModel dm, int64_t P, const double *theta,
+                                                        int64_t t, const double *dloglik,
+                                                        double *dtheta, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D], g[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) {
+    th[i] = theta[i * P + p];
+    g[i] = 0.0;
+  }
+  typename M::R st[Eval<M>::SR];
+  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, dloglik[p], g, st);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) dtheta[i * P + p] = g[i];
+}
+
+// grad = d/dtheta [log p(theta) + log p(y_{1:t} | theta)] for every particle.
+template <class M>
+__global__ void __launch_bounds__(64) k_grad_post(DevModel dm, int64_t P, const double *theta,
+                                                  int64_t t, double *grad, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D], g[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  PriorGradOf<M>::run(th, g);
+  typename M::R st[Eval<M>::SR];
+  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, 1.0, g, st);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) grad[i * P + p] = g[i];
+}
+
+// One preconditioned Langevin (MALA) Metropolis iteration: proposal mean
+// theta + (1/2)(hL)(hL)' grad, noise hL z; the acceptance test adds
+// log q(theta | theta') - log q(theta' | theta) = -|w|^2/2 + |z|^2/2 with
+// (hL) w = theta - theta' - (1/2)(hL)(hL)' grad'.
+template <class M>
+__global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int64_t t, double *theta,
+                                                    double *logprior, double *loglik, void *state,
+                                                    double *grad, const double *__restrict__ hchol,
+                                                    uint64_t seed, uint64_t run, uint64_t cycle,
+                                                    uint64_t iter, unsigned long long *n_accept,
+                                                    uint8_t *accepted, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  int acc = 0;
+  if (p < P) {
+    double th[D], z[D], pr[D], g0[D], g1[D], u[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      th[i] = theta[i * P + p];
+      g0[i] = grad[i * P + p];
+    }
+    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+    // u = (hL)' g0
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g0[i], s);
+      u[k] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double dr = 0.0, st = 0.0;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) {
+        dr = fma(hchol[i * D + k], u[k], dr);
+        st = fma(hchol[i * D + k], z[k], st);
+      }
+      pr[i] = th[i] + 0.5 * dr + st;
+    }
+    const double lp1 = M::logprior(pr);
+    R stv[SR];
+#pragma unroll
+    for (int k = 0; k < SR; ++k) stv[k] = (R)0;
+    double ll1 = -INFINITY;
+    if (lp1 > -INFINITY) {
+      PriorGradOf<M>::run(pr, g1);
+      ll1 = ll_and_grad<M>(dm, pr, t, ckpt, P, p, lds_dyn, 1.0, g1, stv);
+      // reverse move
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g1[i], s);
+        u[k] = s;
+      }
+      double ww = 0.0, zz = 0.0, w[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double dr = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) dr = fma(hchol[i * D + k], u[k], dr);
+        double a = th[i] - pr[i] - 0.5 * dr;
+#pragma unroll
+        for (int k = 0; k < i; ++k) a = fma(-hchol[i * D + k], w[k], a);
+        w[i] = a / hchol[i * D + i];
+        ww = fma(w[i], w[i], ww);
+        zz = fma(z[i], z[i], zz);
+      }
+      const double delta =
+          (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
+      const U64x4 wr = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+      acc = (log(u01_oo(wr.x0)) < delta) ? 1 : 0;
+    }
+    if (acc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        theta[i * P + p] = pr[i];
+        grad[i * P + p] = g1[i];
+      }
+      logprior[p] = lp1;
+      loglik[p] = ll1;
+#pragma unroll
+      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = stv[k];
+    }
+    if (accepted) accepted[p] = (uint8_t)acc;
+  }
+  const unsigned long long mask = __ballot(acc);
+  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
 // ============================================================ launchers ====
 
 template <class F>
@@ -740,6 +905,55 @@ smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, doub
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_log_ml, dim3(1), dim3(64), 0, s, L, J, g, out);
   return launch_status("log_ml");
+}
+
+size_t adjoint_ckpt_bytes(const DevModel &m, int64_t P, int64_t t) {
+  size_t out = 0;
+  (void)dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    if constexpr (!IsLinreg<M>::value) {
+      using A = Adjoint<M>;
+      const int64_t ns = (t + A::SEG - 1) / A::SEG;
+      out = (size_t)ns * M::K * (size_t)P * sizeof(typename M::R);
+    }
+    return SMC_OK;
+  });
+  return out;
+}
+
+smc_status launch_loglik_backward(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                                  const double *dloglik, double *dtheta, void *ckpt,
+                                  hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_loglik_backward<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m,
+                       P, theta, t, dloglik, dtheta, ckpt);
+    return launch_status("loglik_backward");
+  });
+}
+
+smc_status launch_grad_post(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                            double *grad, void *ckpt, hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_grad_post<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P,
+                       theta, t, grad, ckpt);
+    return launch_status("posterior_grad");
+  });
+}
+
+smc_status launch_mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
+                              double *logprior, double *loglik, void *state, double *grad,
+                              const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
+                              uint64_t iter, int64_t *n_accept, uint8_t *accepted, void *ckpt,
+                              hipStream_t s) {
+  return dispatch(m, [&](auto tag) {
+    using M = typename decltype(tag)::type;
+    hipLaunchKernelGGL(k_mutate_mala<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P, t,
+                       theta, logprior, loglik, state, grad, hchol, seed, run, cycle, iter,
+                       reinterpret_cast<unsigned long long *>(n_accept), accepted, ckpt);
+    return launch_status("mutate/mala");
+  });
 }
 
 }  // namespace smc

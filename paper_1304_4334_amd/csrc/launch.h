@@ -72,4 +72,17 @@ smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, doub
                       double *rne, hipStream_t s);
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s);
 
+// Bytes of the adjoint checkpoints of P particles over t observations.
+size_t adjoint_ckpt_bytes(const DevModel &m, int64_t P, int64_t t);
+smc_status launch_loglik_backward(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                                  const double *dloglik, double *dtheta, void *ckpt,
+                                  hipStream_t s);
+smc_status launch_grad_post(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                            double *grad, void *ckpt, hipStream_t s);
+smc_status launch_mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
+                              double *logprior, double *loglik, void *state, double *grad,
+                              const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
+                              uint64_t iter, int64_t *n_accept, uint8_t *accepted, void *ckpt,
+                              hipStream_t s);
+
 }  // namespace smc

@@ -89,7 +89,12 @@ def test_host_side_argument_errors():
     pop.ws_bytes = 16
     assert L.smc_resample(h, C.byref(pop), 0, S._lib.Rng(1, 0), 1, None) == -5  # too small
     assert L.smc_mutate(h, C.byref(pop), 5, 1, C.c_void_p(0x1000), S._lib.Rng(1, 0), 1, 1,
-                        C.c_void_p(0x1000), None, None) == -2  # Langevin not built
+                        C.c_void_p(0x1000), None, None) == -5  # no room for checkpoints
+    pop.grad = None
+    assert L.smc_mutate(h, C.byref(pop), 5, 1, C.c_void_p(0x1000), S._lib.Rng(1, 0), 1, 1,
+                        C.c_void_p(0x1000), None, None) == -1  # Langevin needs the gradient
+    assert L.smc_mutate(h, C.byref(pop), 5, 7, C.c_void_p(0x1000), S._lib.Rng(1, 0), 1, 1,
+                        C.c_void_p(0x1000), None, None) == -1  # unknown kernel
     assert L.smc_loglik(h, 4, C.c_void_p(0x1000), 11, C.c_void_p(0x1000), None, None) == -1
     assert L.smc_status_string(-4) == b"numerical failure"
     L.smc_model_destroy(h)
