@@ -60,6 +60,40 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55), seed=1):
+    """Wall time of one whole adaptive run at the smallest Rbar on the
+    Fibonacci ladder (as in the paper's Table 3) whose log-ML NSE <= target."""
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+
+    w = SD.workload(name)
+    prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
+    kern = S.SMC_KERNEL_MALA if kernel == "mala" else S.SMC_KERNEL_RW
+    m = S.Model.from_workload(w, precision=prec)
+    pop = S.Population(m, w.J, w.N, max_chunk=256, with_grad=kern == S.SMC_KERNEL_MALA)
+    tried = []
+    for Rbar in ladder:
+        rec = S.Record(m, w.J, Lmax=2048, RmaxRec=3 * Rbar + 1)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        S.smc_run(m, pop, seed=seed, Rbar=Rbar, kernel=kern, record=rec)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        s = rec.summary()
+        tried.append(dict(Rbar=Rbar, secs=el, nse=s["nse"], log_ml=s["log_ml"],
+                          mh_steps=s["mh_steps"]))
+        log(f"[bench] time-to-NSE {name}/{precision}/{kernel} Rbar={Rbar}: {el:.3f} s, "
+            f"NSE {s['nse']:.4f}")
+        if s["nse"] <= target:
+            return dict(kernel=kernel, precision=precision, Rbar=Rbar, secs=el, nse=s["nse"],
+                        log_ml=s["log_ml"], precision_per_time=1.0 / (s["nse"] ** 2 * el),
+                        ladder=tried)
+    return dict(kernel=kernel, precision=precision, Rbar=None, secs=None, nse=None,
+                ladder=tried)
+
+
 def run_gpu(name, precision, steps, warmup):
     import numpy as np
     import torch
@@ -122,6 +156,36 @@ def run_gpu(name, precision, steps, warmup):
         secs=secs)
 
 
+def run_batched(steps):
+    """The batched workload: 32 independent adaptive runs (EGARCH(1,1)-N and
+    EGARCH(2)-t alternating, T in [1000, 20000], J*N in 4096..65536), FP32
+    recursion, one persistent M-step launch per batch step."""
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+    from paper_1304_4334_amd import tune
+
+    specs = SD.batched_specs()
+    models = [S.Model.from_workload(w, precision=S.SMC_FP32) for w in specs]
+    pops = [S.Population(m, w.J, w.N, max_chunk=256) for m, w in zip(models, specs)]
+    waves = tune.tuned_waves()
+    S.smc_run_batch(models, pops, list(range(100, 132)), waves=waves, Lmax=2048, RmaxRec=64)
+    torch.cuda.synchronize()
+    evals = 0
+    t0 = time.perf_counter()
+    for k in range(steps):
+        recs = S.smc_run_batch(models, pops, [1 + 32 * k + i for i in range(32)], waves=waves,
+                               Lmax=2048, RmaxRec=64)
+        evals += sum(r.c.evals for r in recs)
+        log(f"[bench] batched step {k + 1}/{steps} done")
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    return dict(value=evals / secs, ms_per_step=1e3 * secs / steps, runs=len(specs),
+                total_particles=sum(w.P for w in specs), waves=waves,
+                evals_per_step=evals / steps)
+
+
 def cpu_baseline(name, seconds):
     import numpy as np
 
@@ -163,6 +227,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-recursion companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--no-companions", action="store_true",
+                    help="skip the EGARCH(2)-t roofline run and the time-to-NSE comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulator "
@@ -175,6 +241,12 @@ def main():
     companion = None
     if not args.no_fp32 and args.precision == "fp64" and args.workload != "linreg":
         companion = run_gpu(args.workload, "fp32", args.steps, args.warmup)
+    roof2t = tnse = batched = None
+    if not args.no_companions and args.workload == "egarch11":
+        batched = run_batched(2)
+        roof2t = run_gpu("egarch2t", "fp32", max(2, min(args.steps, 3)), 1)
+        tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "mala"),
+                time_to_nse("egarch2t", "fp32", "rw")]
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
 
     w = main_run["w"]
@@ -211,6 +283,21 @@ def main():
                        "mutate_avg_ms": companion["mutate_avg_ms"],
                        "mutate_evals_per_s": companion["mutate_evals_per_s"],
                        "roofline": companion["roofline"]}
+    if roof2t is not None:
+        out["egarch2t_fp32"] = {
+            "workload": "egarch2t: " + DESCR["egarch2t"] + ", RW, FP32 recursion, FP64 weights",
+            "value": roof2t["value"], "ms_per_step": roof2t["ms_per_step"],
+            "log_ml": roof2t["log_ml"], "nse": roof2t["nse"],
+            "mutate_avg_ms": roof2t["mutate_avg_ms"],
+            "mutate_evals_per_s": roof2t["mutate_evals_per_s"], "roofline": roof2t["roofline"]}
+    if batched is not None:
+        out["batched"] = dict(batched, workload="32 independent adaptive runs: EGARCH(1,1)-N / "
+                              "EGARCH(2)-t alternating, T in [1000, 20000], J=16, J*N in "
+                              "4096..65536, FP32 recursion, RW")
+    if tnse is not None:
+        out["time_to_nse_0.05"] = {
+            "workload": "egarch2t: " + DESCR["egarch2t"] + ", adaptive, deterministic Rbar ladder",
+            "runs": tnse}
     if cpu is not None:
         out["gpu_over_cpu"] = main_run["mutate_evals_per_s"] / cpu["value"]
     print(json.dumps(out), flush=True)

@@ -276,6 +276,29 @@ typedef struct {
 smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                    smc_run_record *rec, void *stream);
 
+/* --- many runs at once (extension: batching) -------------------------- */
+
+/* Device workspace bytes of a batch of n_runs runs (1..32). */
+size_t smc_batch_ws_bytes(int32_t n_runs);
+
+/* Runs n independent simulators (each with its own model, population and
+ * workspace, configuration and record, as for smc_run) together.  The runs
+ * must share one recursion precision, use EGARCH(1) Gaussian or EGARCH(2)
+ * Student-t models, the random walk and the deterministic R_l rule, and
+ * either all adapt or all replay.  At every step of the batch, the M
+ * iterations of all runs then in their M phase go to one persistent kernel
+ * launch in which each wave takes (run, 64-particle block) items, longest
+ * date first, from a device counter until they are exhausted; their moments
+ * go to one pair of launches; C-phase chunks of different runs share one
+ * host synchronisation.  `waves` is the number of persistent waves (0 =
+ * 2048).  bws: device, >= smc_batch_ws_bytes(n), 256-byte aligned.  A replay
+ * batch never synchronises the stream (capturable in a graph); an adaptive
+ * one synchronises once per batch step that evaluates C-phase chunks.  Each
+ * run's results equal those of smc_run with the same arguments. */
+smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particles *const *pops,
+                         const smc_run_config *cfgs, smc_run_record *recs, void *bws,
+                         size_t bws_bytes, int32_t waves, void *stream);
+
 /* --- diagnostics ------------------------------------------------------- */
 const char *smc_status_string(smc_status s);
 const char *smc_last_error(void);

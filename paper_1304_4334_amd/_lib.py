@@ -116,6 +116,11 @@ def lib():
         L.smc_rne.argtypes = [_vp, P(Particles), _vp, _vp]
         L.smc_flags.restype = st
         L.smc_flags.argtypes = [P(Particles), P(C.c_int32), _vp]
+        L.smc_batch_ws_bytes.restype = C.c_size_t
+        L.smc_batch_ws_bytes.argtypes = [C.c_int32]
+        L.smc_run_batch.restype = st
+        L.smc_run_batch.argtypes = [C.c_int32, P(_vp), P(P(Particles)), P(RunConfig), P(RunRecord),
+                                    _vp, C.c_size_t, C.c_int32, _vp]
         L.smc_run.restype = st
         L.smc_run.argtypes = [_vp, P(Particles), P(RunConfig), P(RunRecord), _vp]
         _L = L
@@ -360,3 +365,36 @@ def smc_run(model, pop, seed, run=0, check_every=1, force_every=0, D1=0.5, D2=0.
     _check(lib().smc_run(model.h, C.byref(pop.c), C.byref(cfg), C.byref(rec.c), _stream(stream)),
            "smc_run")
     return rec
+
+
+def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, waves=0,
+                  Rbar=7, kappa=3, D1=0.5, D2=0.2, Lmax=1024, RmaxRec=64, bws=None,
+                  stream=None):
+    """Many runs together (see smc_run_batch in include/smc.h); returns the
+    records.  With replay=True the records' designs are replayed.  `bws`
+    (a device uint8 tensor of smc_batch_ws_bytes(n) + 256 bytes) may be
+    given to keep the batch workspace alive, e.g. across graph replays."""
+    n = len(models)
+    runs = runs if runs is not None else [0] * n
+    if records is None:
+        records = [Record(m, p.J, Lmax, RmaxRec) for m, p in zip(models, pops)]
+    cfgs = (RunConfig * n)()
+    recs = (RunRecord * n)()
+    for i in range(n):
+        r = records[i]
+        cfgs[i] = RunConfig(pops[i].J, pops[i].N, Rng(seeds[i], runs[i]), 1, 0, D1, D2, Rbar,
+                            kappa, 0, 0.35, 100, SMC_RESAMPLE_RESIDUAL, SMC_KERNEL_RW,
+                            1 if replay else 0, r.Lmax, r.RmaxRec, pops[i].max_chunk)
+        recs[i] = r.c
+    hs = (_vp * n)(*[m.h.value for m in models])
+    ps = (C.POINTER(Particles) * n)(*[C.pointer(p.c) for p in pops])
+    nb = lib().smc_batch_ws_bytes(n)
+    if bws is None:
+        bws = torch.empty(nb + 256, dtype=torch.uint8, device=models[0].device)
+    off = (-bws.data_ptr()) % 256
+    _check(lib().smc_run_batch(n, hs, ps, cfgs, recs, C.c_void_p(bws.data_ptr() + off), nb, waves,
+                               _stream(stream)), "smc_run_batch")
+    for i in range(n):
+        records[i].c = recs[i]
+        records[i].batch_ws = bws  # the stream may still read it
+    return records

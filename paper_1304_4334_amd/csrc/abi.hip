@@ -619,3 +619,324 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
 }
 
 }  // extern "C"
+
+// ------------------------------------------------------------ batched runs --
+#include "batch.h"
+
+extern "C" {
+
+size_t smc_batch_ws_bytes(int32_t n_runs) {
+  if (n_runs < 1 || n_runs > kMaxBatch) return 0;
+  return align256((size_t)n_runs * sizeof(BatchStatic)) + 256;
+}
+
+smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particles *const *pops,
+                         const smc_run_config *cfgs, smc_run_record *recs, void *bws,
+                         size_t bws_bytes, int32_t waves, void *stream) {
+  smc_status st;
+  if (n < 1 || n > kMaxBatch)
+    return set_error(SMC_E_INVALID_ARG, "a batch holds 1..%d runs", kMaxBatch);
+  if (!models || !pops || !cfgs || !recs || !bws)
+    return set_error(SMC_E_INVALID_ARG, "NULL batch argument");
+  if (bws_bytes < smc_batch_ws_bytes(n) || (reinterpret_cast<uintptr_t>(bws) & 255))
+    return set_error(SMC_E_WORKSPACE, "batch workspace too small or misaligned");
+  hipStream_t s = as_stream(stream);
+  const bool replay = cfgs[0].replay != 0;
+  int32_t family = -1;
+  for (int i = 0; i < n; ++i) {
+    const smc_model *m = models[i];
+    if ((st = check_model(m)) || (st = check_pop(m, pops[i]))) return st;
+    const smc_run_config &c = cfgs[i];
+    const smc_run_record &r = recs[i];
+    if (c.J != pops[i]->J || c.N != pops[i]->N)
+      return set_error(SMC_E_INVALID_ARG, "run %d: config and population shapes differ", i);
+    if (!r.t_end || !r.R || !r.rss || !r.n_accept || !r.hchol || !r.group_logwbar || !r.log_ml)
+      return set_error(SMC_E_INVALID_ARG, "run %d: a record array is NULL", i);
+    if (c.Lmax < 1 || c.RmaxRec < 1 || c.check_every < 1 || c.force_every < 0)
+      return set_error(SMC_E_INVALID_ARG, "run %d: bad record capacity", i);
+    if (c.kernel != SMC_KERNEL_RW || c.stop_rule != 0)
+      return set_error(SMC_E_UNSUPPORTED, "batched runs use the random walk and fixed R_l");
+    if ((c.replay != 0) != replay)
+      return set_error(SMC_E_INVALID_ARG, "all runs of a batch adapt, or all replay");
+    const DevModel &dm = m->dev;
+    const bool ok_model = dm.kind == SMC_MODEL_EGARCH &&
+                          ((dm.K == 1 && dm.shock == SMC_SHOCK_GAUSS) ||
+                           (dm.K == 2 && dm.shock == SMC_SHOCK_STUDENT_T));
+    if (!ok_model)
+      return set_error(SMC_E_UNSUPPORTED, "batched runs: EGARCH(1) Gaussian or EGARCH(2)-t");
+    const int32_t fam = dm.prec == SMC_FP32 ? kFamilyFp32 : kFamilyFp64;
+    if (family >= 0 && fam != family)
+      return set_error(SMC_E_UNSUPPORTED, "batched runs share one precision");
+    family = fam;
+  }
+  BatchStatic *table = reinterpret_cast<BatchStatic *>(bws);
+  unsigned int *queue = reinterpret_cast<unsigned int *>(reinterpret_cast<char *>(bws) +
+                                                         align256((size_t)n * sizeof(BatchStatic)));
+  // Static table, written by a kernel from its arguments.
+  BatchStaticArgs sa{};
+  sa.dst = table;
+  sa.n = n;
+  for (int i = 0; i < n; ++i) {
+    const DevModel &dm = models[i]->dev;
+    const WsLayout L = ws_layout(dm, pops[i]->J, pops[i]->N);
+    BatchStatic &b = sa.src[i];
+    b.theta = pops[i]->theta;
+    b.logprior = pops[i]->logprior;
+    b.loglik = pops[i]->loglik;
+    b.state = pops[i]->state;
+    b.part = ws_at<double>(pops[i], L.mpart);
+    b.mh = ws_at<int32_t>(pops[i], L.small + kSmallMh);
+    b.flags = ws_at<int32_t>(pops[i], L.small + kSmallFlags);
+    b.y = dm.prec == SMC_FP32 ? static_cast<const void *>(dm.y32) : static_cast<const void *>(dm.y);
+    b.seed = cfgs[i].rng.seed;
+    b.run = cfgs[i].rng.run;
+    b.P = (int64_t)pops[i]->J * pops[i]->N;
+    b.tag = dm.K == 1 ? 0 : 1;
+    b.d = dm.d;
+  }
+  if ((st = launch_batch_static(sa, s))) return st;
+
+  enum Phase { kCStart, kCNext, kCPend, kM, kDone };
+  struct Run {
+    Phase ph = kCStart;
+    int64_t t = 0;        // start of the current cycle
+    int64_t tc = 0;       // C-phase position
+    int64_t t_stop = 0;   // this C phase's last possible date
+    int64_t t_new = 0;    // end of the C phase
+    int64_t chunk = 16, last_len = 0;
+    bool zero_first = true;
+    std::vector<int64_t> dates;
+    int32_t l = 0, r = 0, R = 0;
+    double rss = NAN;
+    int64_t evals = 0, steps = 0;
+  };
+  std::vector<Run> run(n);
+  for (int i = 0; i < n; ++i) {
+    const WsLayout L = ws_layout(models[i]->dev, pops[i]->J, pops[i]->N);
+    if ((st = fill_i32(ws_at<int32_t>(pops[i], L.small + kSmallFlags), 1, 0, s)) ||
+        (st = fill_i64(recs[i].n_accept, (int64_t)cfgs[i].Lmax * cfgs[i].RmaxRec, 0, s)) ||
+        (st = smc_init_from_prior(models[i], pops[i], cfgs[i].rng, stream)))
+      return st;
+  }
+  // Pinned readback area of the adaptive C phases (a replay reads nothing
+  // back and allocates nothing, so it can be captured).
+  double *host_rss = nullptr;
+  if (!replay &&
+      hipHostMalloc(reinterpret_cast<void **>(&host_rss), (size_t)n * kMaxChunk * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "pinned host buffer for the batch failed");
+  struct HostFree {
+    double *p;
+    ~HostFree() {
+      if (p) (void)hipHostFree(p);
+    }
+  } host_free{host_rss};
+
+  auto end_c_phase = [&](int i) -> smc_status {
+    Run &u = run[i];
+    const smc_model *m = models[i];
+    smc_particles *pop = pops[i];
+    const smc_run_config &c = cfgs[i];
+    smc_status e;
+    if ((e = launch_group_logwbar(pop->logw, pop->J, pop->N,
+                                  recs[i].group_logwbar + (int64_t)u.l * c.J, s)))
+      return e;
+    if ((e = smc_resample(m, pop, c.scheme, c.rng, u.l + 1, stream))) return e;
+    u.t_new = u.tc;
+    u.last_len = u.t_new - u.t;
+    u.R = c.replay ? recs[i].R[u.l] : (u.rss < c.D2 ? c.kappa * c.Rbar : c.Rbar);
+    if (u.R < 1 || u.R > c.RmaxRec)
+      return set_error(SMC_E_INVALID_ARG, "run %d: R_l out of the record's range", i);
+    u.r = 0;
+    u.ph = kM;
+    return SMC_OK;
+  };
+
+  for (;;) {
+    bool all_done = true;
+    for (int i = 0; i < n; ++i) all_done = all_done && run[i].ph == kDone;
+    if (all_done) break;
+    std::vector<int> pend;
+    // (a) C phases: start or continue a chunk
+    for (int i = 0; i < n; ++i) {
+      Run &u = run[i];
+      const smc_run_config &c = cfgs[i];
+      const smc_model *m = models[i];
+      smc_particles *pop = pops[i];
+      const int64_t P = (int64_t)pop->J * pop->N;
+      const int64_t T = m->dev.T;
+      if (u.ph == kCStart) {
+        if (u.l >= c.Lmax) return set_error(SMC_E_INVALID_ARG, "run %d: record full", i);
+        u.t_stop = T;
+        if (c.force_every > 0)
+          u.t_stop = std::min(u.t_stop, (u.t / c.force_every + 1) * c.force_every);
+        if (c.replay) {
+          u.t_stop = recs[i].t_end[u.l];
+          if (u.t_stop <= u.t || u.t_stop > T)
+            return set_error(SMC_E_INVALID_ARG, "run %d: replayed date out of order", i);
+        }
+        u.tc = u.t;
+        u.zero_first = true;
+        if (c.replay) {
+          if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik,
+                                   u.t, u.t_stop, true, s)))
+            return st;
+          u.evals += P * (u.t_stop - u.t);
+          u.tc = u.t_stop;
+          if ((st = end_c_phase(i))) return st;
+          continue;
+        }
+        const int64_t cap = chunk_capacity(m, pop);
+        if (cap < 1) return set_error(SMC_E_WORKSPACE, "run %d: no room for C-phase chunks", i);
+        u.chunk = std::min<int64_t>(cap, std::max<int64_t>(16, u.last_len + u.last_len / 4 + 8));
+        u.ph = kCNext;
+      }
+      if (u.ph == kCNext) {
+        const int64_t t1 = std::min(u.tc + u.chunk, u.t_stop);
+        u.dates.clear();
+        for (int64_t q = u.tc + 1; q <= t1; ++q)
+          if (q % c.check_every == 0 || q == u.t_stop) u.dates.push_back(q);
+        const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+        if (u.dates.empty()) {
+          if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik,
+                                   u.tc, t1, u.zero_first, s)))
+            return st;
+          u.evals += P * (t1 - u.tc);
+          u.zero_first = false;
+          u.tc = t1;
+          continue;
+        }
+        if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, u.tc, t1,
+                               c.check_every, u.t_stop, u.zero_first, ws_at<double>(pop, L.wcols),
+                               s)) ||
+            (st = launch_rss_cols(ws_at<double>(pop, L.wcols), P, (int64_t)u.dates.size(),
+                                  ws_at<double>(pop, L.rsscols), s)))
+          return st;
+        if (hipMemcpyAsync(host_rss + (size_t)i * kMaxChunk, ws_at<double>(pop, L.rsscols),
+                           u.dates.size() * sizeof(double), hipMemcpyDeviceToHost,
+                           s) != hipSuccess)
+          return set_error(SMC_E_DEVICE, "run %d: RSS readback failed", i);
+        u.ph = kCPend;
+        pend.push_back(i);
+      }
+    }
+    // (b) one M iteration of every run in its M phase
+    std::vector<int> act;
+    for (int i = 0; i < n; ++i)
+      if (run[i].ph == kM) act.push_back(i);
+    if (!act.empty()) {
+      std::stable_sort(act.begin(), act.end(),
+                       [&](int a, int b) { return run[a].t_new > run[b].t_new; });
+      BatchArgs ba{};
+      ba.runs = table;
+      ba.queue = queue;
+      ba.n_active = (int32_t)act.size();
+      ba.target_permille = 250;
+      int32_t mut = 0, mom = 0;
+      for (size_t q = 0; q < act.size(); ++q) {
+        const int i = act[q];
+        Run &u = run[i];
+        const smc_run_config &c = cfgs[i];
+        const int64_t P = (int64_t)pops[i]->J * pops[i]->N;
+        const int32_t d = models[i]->dev.d;
+        BatchDyn &dy = ba.dyn[q];
+        const int64_t slot = (int64_t)u.l * c.RmaxRec + u.r;
+        dy.hchol = recs[i].hchol + slot * d * d;
+        dy.n_accept = reinterpret_cast<unsigned long long *>(recs[i].n_accept + slot);
+        dy.prev_nacc = u.r == 0 ? nullptr : recs[i].n_accept + slot - 1;
+        dy.t = u.t_new;
+        dy.idx = i;
+        dy.cycle = u.l + 1;
+        dy.iter = u.r + 1;
+        dy.mh_reset = u.r == 0 ? 5 : 0;
+        dy.mut_begin = mut;
+        mut += (int32_t)((P + 63) / 64);
+        const int64_t waves_r = std::max<int64_t>(1, (P + 63) / 64);
+        int64_t nb = std::min<int64_t>(kMomBlocks, (waves_r + 3) / 4);
+        int64_t ch = (P + 4 * nb - 1) / (4 * nb);
+        ch = ((ch + 31) / 32) * 32;
+        nb = (P + 4 * ch - 1) / (4 * ch);
+        dy.mom_begin = mom;
+        dy.mom_nb = (int32_t)nb;
+        dy.mom_chunk = (int32_t)ch;
+        mom += (int32_t)nb;
+        u.evals += P * u.t_new;
+        u.steps += 1;
+      }
+      ba.n_mut_items = mut;
+      ba.n_mom_items = mom;
+      if ((st = launch_batch_m(ba, !replay, family, waves > 0 ? waves : 2048, s))) return st;
+      for (int i : act) {
+        Run &u = run[i];
+        if (++u.r >= u.R) {
+          if (!cfgs[i].replay) {
+            recs[i].t_end[u.l] = u.t_new;
+            recs[i].R[u.l] = u.R;
+          }
+          recs[i].rss[u.l] = u.rss;
+          u.t = u.t_new;
+          ++u.l;
+          u.ph = u.t < models[i]->dev.T ? kCStart : kDone;
+        }
+      }
+    }
+    // (c) one synchronisation for every pending C-phase chunk
+    if (!pend.empty()) {
+      if (hipStreamSynchronize(s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "batch synchronisation failed");
+      for (int i : pend) {
+        Run &u = run[i];
+        const smc_run_config &c = cfgs[i];
+        const smc_model *m = models[i];
+        smc_particles *pop = pops[i];
+        const int64_t P = (int64_t)pop->J * pop->N;
+        const double *hr = host_rss + (size_t)i * kMaxChunk;
+        const int64_t nc = (int64_t)u.dates.size();
+        int64_t stop_col = -1;
+        for (int64_t q = 0; q < nc; ++q)
+          if (hr[q] < c.D1) {
+            stop_col = q;
+            break;
+          }
+        const int64_t t1 = u.dates.back() < u.t_stop ? std::min(u.tc + u.chunk, u.t_stop)
+                                                      : u.t_stop;
+        const int64_t t_commit = stop_col >= 0 ? u.dates[stop_col] : t1;
+        if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik,
+                                 u.tc, t_commit, u.zero_first, s)))
+          return st;
+        u.evals += P * (t_commit - u.tc);
+        u.zero_first = false;
+        u.rss = stop_col >= 0 ? hr[stop_col] : hr[nc - 1];
+        u.tc = t_commit;
+        if (stop_col >= 0 || u.tc >= u.t_stop) {
+          if ((st = end_c_phase(i))) return st;
+        } else {
+          u.chunk = std::min(2 * u.chunk, chunk_capacity(m, pop));
+          u.ph = kCNext;
+        }
+      }
+    }
+  }
+  for (int i = 0; i < n; ++i) {
+    recs[i].L = run[i].l;
+    recs[i].evals = run[i].evals;
+    recs[i].mh_steps = run[i].steps;
+    if ((st = smc_log_ml(run[i].l, pops[i]->J, recs[i].group_logwbar, recs[i].log_ml, stream)))
+      return st;
+  }
+  if (!replay) {
+    // numerical flags of every run (adaptive batches synchronise anyway)
+    for (int i = 0; i < n; ++i) {
+      int32_t fl = 0;
+      const WsLayout L = ws_layout(models[i]->dev, pops[i]->J, pops[i]->N);
+      if (hipMemcpyAsync(&fl, ws_at<int32_t>(pops[i], L.small + kSmallFlags), sizeof fl,
+                         hipMemcpyDeviceToHost, s) != hipSuccess ||
+          hipStreamSynchronize(s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "reading flags failed");
+      if (fl) return set_error(SMC_E_NUMERIC, "run %d: numerical flags 0x%x", i, fl);
+    }
+  }
+  return SMC_OK;
+}
+
+}  // extern "C"

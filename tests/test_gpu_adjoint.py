@@ -106,15 +106,18 @@ def test_mala_step_matches_oracle(name, prec):
     gm, om = gpu_model(w, prec), ora_model(w)
     J, N = 4, 32
     opop = O.Pop(om, J, N)
-    opop.theta[:] = SD.random_thetas(w, J * N, 12, spread=0.05)
+    if name == "linreg":
+        # exact posterior draws: the step is then on the posterior's own scale
+        opop.theta[:] = CF.posterior_draws(w.y[:w.T], w.X[:w.T], J * N, np.random.default_rng(12))
+    else:
+        opop.theta[:] = SD.random_thetas(w, J * N, 12, spread=0.05)
     for p in range(J * N):
         opop.logprior[p] = O.logprior(om, opop.theta[p])
     opop.loglik[:], st = O.loglik_batch(om, opop.theta, w.T)
     if om.S:
         opop.state[:, :om.S] = st
     _, _, chol, rc = O.moments(opop)
-    # the regression's posterior is much wider than this cloud: larger steps
-    hl = (3.0 if name == "linreg" else 0.3) * chol
+    hl = (1.0 if name == "linreg" else 0.3) * chol
     g = pop_to_gpu(gm, opop, with_grad=True)
     S.smc_posterior_grad(gm, g, w.T)
     acc_g = torch.zeros(J * N, dtype=torch.uint8, device="cuda")

@@ -1,0 +1,83 @@
+"""Batched runs (many independent simulators advanced together with one
+persistent M-step launch): each run equals the same run on its own, and a
+replayed batch captured in a graph reproduces the eager replay on every
+graph replay."""
+import numpy as np
+import pytest
+import torch
+
+import paper_1304_4334_amd as S
+import synthdata as SD
+from tests.gpu_helpers import theta_np
+
+pytestmark = pytest.mark.gpu
+
+
+def _runs(prec, specs):
+    out = []
+    for name, T, J, N, seed_off in specs:
+        w = SD.workload(name, T=T, J=J, N=N, seed_offset=seed_off)
+        m = S.Model(w.kind, w.y[:T], K=w.K, shock=w.shock, precision=prec)
+        out.append((w, m, S.Population(m, J, N, max_chunk=64)))
+    return out
+
+
+SPECS = [("egarch11", 400, 4, 64, 0), ("egarch2t", 250, 4, 96, 1), ("egarch11", 700, 2, 200, 2),
+         ("egarch2t", 333, 8, 32, 3)]
+
+
+@pytest.mark.parametrize("prec", [S.SMC_FP64, S.SMC_FP32])
+@pytest.mark.parametrize("waves", [0, 3])
+def test_batch_equals_single_runs(prec, waves):
+    runs = _runs(prec, SPECS)
+    models = [m for _, m, _ in runs]
+    pops = [p for _, _, p in runs]
+    seeds = [11, 12, 13, 14]
+    recs = S.smc_run_batch(models, pops, seeds, waves=waves, Lmax=400, RmaxRec=64)
+    torch.cuda.synchronize()
+    for i, (w, m, _) in enumerate(runs):
+        p1 = S.Population(m, w.J, w.N, max_chunk=64)
+        r1 = S.smc_run(m, p1, seed=seeds[i], Lmax=400, RmaxRec=64)
+        a, b = recs[i].summary(), r1.summary()
+        assert a["L"] == b["L"] and a["L"] > 1
+        assert np.array_equal(a["t_end"], b["t_end"]) and np.array_equal(a["R"], b["R"])
+        assert np.array_equal(a["n_accept"], b["n_accept"])
+        assert np.array_equal(a["group_logwbar"], b["group_logwbar"])
+        assert a["log_ml"] == b["log_ml"] and a["nse"] == b["nse"]
+        assert a["evals"] == b["evals"] and a["mh_steps"] == b["mh_steps"]
+        assert np.array_equal(theta_np(pops[i]), theta_np(p1))
+
+
+def test_batch_replay_in_a_graph():
+    runs = _runs(S.SMC_FP64, SPECS[:3])
+    models = [m for _, m, _ in runs]
+    pops = [p for _, _, p in runs]
+    seeds = [5, 6, 7]
+    design = S.smc_run_batch(models, pops, seeds, Lmax=400, RmaxRec=64)
+    torch.cuda.synchronize()
+    # eager replay with new seeds (step 2 of Algorithm 3)
+    new = [21, 22, 23]
+    eager = S.smc_run_batch(models, pops, new, records=design, replay=True)
+    torch.cuda.synchronize()
+    want_ml = [r.log_ml.clone() for r in eager]
+    want_th = [p.theta.clone() for p in pops]
+    nb = S._lib.lib().smc_batch_ws_bytes(3)
+    bws = torch.empty(nb + 256, dtype=torch.uint8, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream's side, as torch requires
+        S.smc_run_batch(models, pops, new, records=design, replay=True, bws=bws)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.smc_run_batch(models, pops, new, records=design, replay=True, bws=bws)
+    for rep in range(3):
+        for p in pops:  # unrelated eager work between replays
+            p.theta.add_(1.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        for i in range(3):
+            assert torch.equal(design[i].log_ml, want_ml[i]), rep
+            assert torch.equal(pops[i].theta, want_th[i]), rep
