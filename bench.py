@@ -60,6 +60,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mutate_traffic_pmc.md")
+TRAFFIC_KEYS = {("egarch11", "fp64"): "k_mutate_rw egarch11 fp64 P=16384 t=5000 bytes",
+                ("egarch2t", "fp32"): "k_mutate_rw egarch2t fp32 P=65536 t=10000 bytes"}
+
+
+def measured_traffic(name, precision):
+    """HBM bytes per mutation launch (at t = T) from the committed counter
+    passes, or None when the kernel sources changed since they were taken."""
+    import hashlib
+
+    key = TRAFFIC_KEYS.get((name, precision))
+    if key is None or not os.path.exists(TRAFFIC_FILE):
+        return None
+    text = open(TRAFFIC_FILE).read()
+    try:
+        block = text.split("```json", 1)[1].split("```", 1)[0]
+        rec = json.loads(block)
+    except (IndexError, ValueError):
+        return None
+    h = hashlib.sha256()
+    for src in rec["sources"]:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    if h.hexdigest() != rec["sources_sha256"]:
+        return None
+    return rec.get(key)
+
+
 def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55), seed=1):
     """Wall time of one whole adaptive run at the smallest Rbar on the
     Fibonacci ladder (as in the paper's Table 3) whose log-ML NSE <= target."""
@@ -150,7 +178,8 @@ def run_gpu(name, precision, steps, warmup):
         mutate_launches=n_launch, mutate_evals_per_s=mut_evals / (mut_ms * 1e-3),
         roofline=dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS,
                       unit="T VALU lane-ops/s", frac=achieved / VALU_PEAK_TOPS,
-                      traffic=None, kernel="k_mutate_rw", ops_per_eval=ops,
+                      traffic=measured_traffic(name, precision), traffic_unit="bytes per launch at t=T",
+                      kernel="k_mutate_rw", ops_per_eval=ops,
                       simd_occupancy=occupied,
                       frac_of_occupied=achieved / (VALU_PEAK_TOPS * occupied)),
         secs=secs)
@@ -217,6 +246,38 @@ def cpu_baseline(name, seconds):
                         f"{iters} iterations in {el:.1f} s"))
 
 
+def kernel_probe():
+    """A short fixed sequence for hardware-counter passes: a 256 MiB device
+    copy (calibration of the byte counters), then three M steps at t = T of
+    each roofline workload (EGARCH(1,1) FP64 16,384 particles; EGARCH(2)-t
+    FP32 65,536 particles)."""
+    import numpy as np
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+
+    a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
+    b = torch.empty_like(a)
+    for _ in range(3):
+        b.copy_(a)
+    torch.cuda.synchronize()
+    log("[probe] copies done")
+    for name, prec in (("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32)):
+        w = SD.workload(name)
+        m = S.Model.from_workload(w, precision=prec)
+        pop = S.Population(m, w.J, w.N, max_chunk=16)
+        th = SD.random_thetas(w, w.P, 1, spread=0.01)
+        pop.theta.copy_(torch.from_numpy(th.T.copy()))
+        pop.loglik.copy_(S.smc_loglik(m, pop.theta, w.T))
+        hl = torch.from_numpy(np.linalg.cholesky(np.cov(th[::8].T)) * 0.3).cuda()
+        for it in range(3):
+            S.smc_mutate(m, pop, w.T, hl, seed=1, it=it + 1)
+        torch.cuda.synchronize()
+        log(f"[probe] {name} done")
+    print(json.dumps({"probe": "done", "copy_bytes": 2 * a.numel() * 4}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -227,6 +288,8 @@ def main():
     ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-recursion companion run")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--kernel-probe", action="store_true",
+                    help="run only the short fixed sequence used for counter passes")
     ap.add_argument("--no-companions", action="store_true",
                     help="skip the EGARCH(2)-t roofline run and the time-to-NSE comparison")
     args = ap.parse_args()
@@ -236,6 +299,9 @@ def main():
         sys.exit(2)
     if args.steps < 1:
         sys.exit("--steps must be >= 1")
+    if args.kernel_probe:
+        kernel_probe()
+        return
 
     main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup)
     companion = None
