@@ -60,6 +60,8 @@ typedef int32_t smc_status;
 
 #define SMC_RESAMPLE_RESIDUAL 0    /* Section 3.3 default */
 #define SMC_RESAMPLE_MULTINOMIAL 1
+#define SMC_RESAMPLE_STRATIFIED 2  /* Section 3.3, experimental (Kitagawa 1996) */
+#define SMC_RESAMPLE_SYSTEMATIC 3  /* Section 3.3, experimental (Carpenter et al. 1999) */
 
 #define SMC_KERNEL_RW 0   /* Gaussian random walk, Section 3.3 (default) */
 #define SMC_KERNEL_MALA 1 /* preconditioned Langevin proposal (extension) */
@@ -153,7 +155,9 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
  * running residual sum exceeds u times the total.  Ancestors are written in
  * ascending order to pop->ancestor; theta, logprior, loglik, state and grad
  * (if not NULL) are replaced by the ancestors'.  A group without positive
- * weight keeps its particles and raises SMC_FLAG_DEAD_GROUP (smc_flags). */
+ * weight keeps its particles and raises SMC_FLAG_DEAD_GROUP (smc_flags).
+ * Stratified and systematic schemes take the k-th of N draws at (k + U_k)/N,
+ * respectively (k + U)/N, of the running sum of W_n (U: draw 0's uniform). */
 smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, smc_rng rng,
                         int32_t cycle, void *stream);
 

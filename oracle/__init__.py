@@ -28,7 +28,7 @@ from . import build as _build
 
 _LIB = None
 
-RESIDUAL, MULTINOMIAL = 0, 1
+RESIDUAL, MULTINOMIAL, STRATIFIED, SYSTEMATIC = 0, 1, 2, 3
 RW, MALA = 0, 1
 LINREG, EGARCH = 1, 2
 GAUSS, STUDENT_T = 0, 1

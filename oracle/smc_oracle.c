@@ -471,7 +471,7 @@ int64_t orc_correct(const orc_model *m, orc_pop *pop, int64_t t_from, int64_t t_
   return s;
 }
 
-enum { ORC_RESIDUAL = 0, ORC_MULTINOMIAL = 1 };
+enum { ORC_RESIDUAL = 0, ORC_MULTINOMIAL = 1, ORC_STRATIFIED = 2, ORC_SYSTEMATIC = 3 };
 
 /* S phase (Algorithm 1, step 2b) for every group independently.
  *
@@ -533,10 +533,15 @@ int orc_resample(const int32_t J, const int32_t N, const double *logw, int schem
       cum[n] = run_sum;
     }
     int64_t R = N - copies;
+    uint64_t x0[4];
+    draw4(seed, run, (uint64_t)j, cycle, 0, ORC_RESAMPLE, x0);
     for (int64_t k = 0; k < R; ++k) {
       uint64_t x[4];
       draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k / 4), ORC_RESAMPLE, x);
-      double target = u01_co(x[k % 4]) * cum[N - 1];
+      double u = u01_co(x[k % 4]);
+      if (scheme == ORC_STRATIFIED) u = ((double)k + u) / (double)N;
+      if (scheme == ORC_SYSTEMATIC) u = ((double)k + u01_co(x0[0])) / (double)N;
+      double target = u * cum[N - 1];
       int a = -1;
       for (int n = 0; n < N; ++n)
         if (cum[n] > target) { a = n; break; }
@@ -819,7 +824,7 @@ typedef struct {
   int32_t stop_rule;    /* 0 deterministic, 1 RNE-based */
   double E1;            /* RNE threshold */
   int32_t Rmax;         /* cap on M iterations */
-  int32_t scheme;       /* ORC_RESIDUAL or ORC_MULTINOMIAL */
+  int32_t scheme;       /* ORC_RESIDUAL, ORC_MULTINOMIAL, ORC_STRATIFIED, ORC_SYSTEMATIC */
   int32_t kernel;       /* ORC_RW or ORC_MALA */
   int32_t replay;       /* 0 adaptive, 1 replay the record */
   int32_t Lmax;         /* capacity of the record, cycles */

@@ -20,6 +20,7 @@ SMC_MODEL_LINREG, SMC_MODEL_EGARCH = 1, 2
 SMC_SHOCK_GAUSS, SMC_SHOCK_STUDENT_T = 0, 1
 SMC_FP64, SMC_FP32 = 0, 1
 SMC_RESAMPLE_RESIDUAL, SMC_RESAMPLE_MULTINOMIAL = 0, 1
+SMC_RESAMPLE_STRATIFIED, SMC_RESAMPLE_SYSTEMATIC = 2, 3
 SMC_KERNEL_RW, SMC_KERNEL_MALA = 0, 1
 SMC_FLAG_DEAD_GROUP, SMC_FLAG_NOT_PD = 1, 2
 

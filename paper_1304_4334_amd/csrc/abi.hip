@@ -315,7 +315,7 @@ smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, 
                         int32_t cycle, void *stream) {
   smc_status st;
   if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
-  if (scheme != SMC_RESAMPLE_RESIDUAL && scheme != SMC_RESAMPLE_MULTINOMIAL)
+  if (scheme < SMC_RESAMPLE_RESIDUAL || scheme > SMC_RESAMPLE_SYSTEMATIC)
     return set_error(SMC_E_INVALID_ARG, "resampling scheme %d", scheme);
   hipStream_t s = as_stream(stream);
   const int64_t P = (int64_t)pop->J * pop->N;

@@ -217,7 +217,10 @@ __global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32
 
 // ------------------------------------------------------------ S phase (a3) --
 // One block per group.  Counts live in LDS (dynamic, N int32); the running
-// residual sums in the workspace.
+// residual sums in the workspace.  Residual: floor(N W_n) copies, then the
+// remaining draws from the residuals; multinomial: N draws from W_n;
+// stratified / systematic (Section 3.3's experimental schemes): the k-th of N
+// draws at (k + U_k)/N, respectively (k + U)/N, of the running sum.
 struct GatherArgs {
   const int32_t *anc;
   int64_t P;
@@ -273,10 +276,14 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   __syncthreads();
   const double total = cum[N - 1];
   const int64_t R = (int64_t)N - ctot;
+  const double u_sys = u01_co(draw4(seed, run, (uint64_t)j, cycle, 0, kResample).x0);
   for (int64_t k = tid; k < R; k += kBlock) {
     const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k >> 2), kResample);
     const uint64_t x = (k & 3) == 0 ? w.x0 : (k & 3) == 1 ? w.x1 : (k & 3) == 2 ? w.x2 : w.x3;
-    const double target = u01_co(x) * total;
+    double u = u01_co(x);
+    if (scheme == SMC_RESAMPLE_STRATIFIED) u = ((double)k + u) / (double)N;
+    else if (scheme == SMC_RESAMPLE_SYSTEMATIC) u = ((double)k + u_sys) / (double)N;
+    const double target = u * total;
     int a_lo = 0, a_hi = N;  // first n with cum[n] > target
     while (a_lo < a_hi) {
       const int mid = (a_lo + a_hi) >> 1;

@@ -145,7 +145,8 @@ def test_correct_matches_oracle(name, prec, ce):
 
 # ------------------------------------------------------------ S phase (a3) --
 
-@pytest.mark.parametrize("scheme", [S.SMC_RESAMPLE_RESIDUAL, S.SMC_RESAMPLE_MULTINOMIAL])
+@pytest.mark.parametrize("scheme", [S.SMC_RESAMPLE_RESIDUAL, S.SMC_RESAMPLE_MULTINOMIAL,
+                                    S.SMC_RESAMPLE_STRATIFIED, S.SMC_RESAMPLE_SYSTEMATIC])
 @pytest.mark.parametrize("J,N", [(4, 64), (3, 1000), (2, 4096)])
 def test_resample_bit_exact(scheme, J, N):
     w = SD.workload("egarch11", T=10)
@@ -343,19 +344,25 @@ def _oracle_design_to_gpu(orec, grec, d):
     grec.hchol[:L, :R].copy_(h)
 
 
-@pytest.mark.parametrize("name,J,N,T,fe", [("linreg", 4, 256, 200, 20), ("egarch11", 4, 128, 300, 0)])
-def test_replay_of_oracle_design_matches_oracle(name, J, N, T, fe):
+@pytest.mark.parametrize("name,J,N,T,fe,scheme", [("linreg", 4, 256, 200, 20, 0),
+                                                  ("egarch11", 4, 128, 300, 0, 0),
+                                                  ("linreg", 4, 256, 200, 20, 2),
+                                                  ("egarch11", 4, 128, 300, 0, 3)])
+def test_replay_of_oracle_design_matches_oracle(name, J, N, T, fe, scheme):
     """The GPU replays the oracle's adaptive design (Algorithm 1 with the
-    recorded t_l, hL_lr, R_l): same trajectory, same estimates."""
+    recorded t_l, hL_lr, R_l): same trajectory, same estimates, under each
+    resampling scheme."""
     w = SD.workload(name, T=T)
     gm, om = gpu_model(w), ora_model(w)
-    rc, orec, opop = O.run(om, J, N, 5, check_every=1, force_every=fe, Lmax=300, RmaxRec=64)
+    rc, orec, opop = O.run(om, J, N, 5, check_every=1, force_every=fe, Lmax=300, RmaxRec=64,
+                           scheme=scheme)
     assert rc == 0
     so = orec.summary()
     g = S.Population(gm, J, N, max_chunk=32)
     grec = S.Record(gm, J, Lmax=300, RmaxRec=64)
     _oracle_design_to_gpu(orec, grec, gm.d)
-    S.smc_run(gm, g, seed=5, check_every=1, force_every=fe, record=grec, replay=True)
+    S.smc_run(gm, g, seed=5, check_every=1, force_every=fe, record=grec, replay=True,
+              scheme=scheme)
     sg = grec.summary()
     assert sg["L"] == so["L"]
     assert np.array_equal(sg["n_accept"][:, :64].sum(1), orec.n_acc[:so["L"]].sum(1))

@@ -62,7 +62,8 @@ def test_rne_hand_value_and_iid():
 # -------------------------------------------------------------- S phase -----
 
 def test_resample_equal_weights_is_identity():
-    for scheme in (O.RESIDUAL,):
+    # residual: one copy each; stratified / systematic: draw k lies in [k, k+1)
+    for scheme in (O.RESIDUAL, O.STRATIFIED, O.SYSTEMATIC):
         anc, bad = O.resample(3, 64, np.full(192, -7.0), scheme, seed=4)
         assert bad == 0
         assert np.array_equal(anc, np.arange(192))
@@ -87,7 +88,7 @@ def test_resample_dead_group_reported():
     assert anc[4:].tolist() == [4, 5, 6, 7]
 
 
-@pytest.mark.parametrize("scheme", [O.RESIDUAL, O.MULTINOMIAL])
+@pytest.mark.parametrize("scheme", [O.RESIDUAL, O.MULTINOMIAL, O.STRATIFIED, O.SYSTEMATIC])
 def test_resample_counts_unbiased(scheme):
     N = 16
     w = np.random.default_rng(8).gamma(0.7, size=N)
@@ -102,11 +103,38 @@ def test_resample_counts_unbiased(scheme):
         assert c.sum() == N
         if scheme == O.RESIDUAL:
             assert np.all(c >= np.floor(N * W))
+        if scheme in (O.STRATIFIED, O.SYSTEMATIC):
+            # one draw per stratum [k, k+1) of the running sum N sum_{m<=n} W_m:
+            # the running count sits in {floor, floor + 1} of it
+            x = N * np.cumsum(W)
+            cc = np.cumsum(c)
+            assert np.all((cc >= np.floor(x - 1e-9)) & (cc <= np.floor(x + 1e-9) + 1))
+        if scheme == O.SYSTEMATIC:
+            # a common offset: every count is floor or ceil of N W_n
+            assert np.all((c >= np.floor(N * W - 1e-9)) & (c <= np.ceil(N * W + 1e-9)))
         counts += c
     # E[count_n] = N W_n; multinomial variance bounds the residual one
     mean = counts / n_rep
     sd = np.sqrt(N * W * (1 - W) / n_rep)
     assert np.all(np.abs(mean - N * W) < 4.5 * sd + 1e-12)
+
+
+def test_stratified_brute_force_tiny():
+    """Ancestors from the definition: the k-th draw is the first n whose
+    running sum of N W exceeds k + U_k (U_k the k-th uniform of the stream)."""
+    N = 5
+    lw = np.log(np.array([0.05, 0.4, 0.15, 0.3, 0.1]))
+    for seed in range(50):
+        # counter (group, cycle, k / 4, purpose 2 = resampling), key (seed, run)
+        u = np.array([O.philox([0, 3, k // 4, 2], [seed, 0])[k % 4] for k in range(N)],
+                     dtype=np.uint64)
+        uf = (u >> np.uint64(11)).astype(np.float64) * 2.0 ** -53
+        x = N * np.cumsum(np.exp(lw) / np.exp(lw).sum())
+        for scheme, pts in ((O.STRATIFIED, np.arange(N) + uf),
+                            (O.SYSTEMATIC, np.arange(N) + uf[0])):
+            want = np.searchsorted(x, pts, side="right")
+            anc, _ = O.resample(1, N, lw, scheme, seed=seed, cycle=3)
+            assert anc.tolist() == want.tolist(), (seed, scheme)
 
 
 # ---------------------------------------------------------------- moments ---
