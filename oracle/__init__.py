@@ -31,14 +31,15 @@ _LIB = None
 RESIDUAL, MULTINOMIAL, STRATIFIED, SYSTEMATIC = 0, 1, 2, 3
 RW, MALA = 0, 1
 LINREG, EGARCH = 1, 2
-GAUSS, STUDENT_T = 0, 1
+GAUSS, STUDENT_T, MIXTURE = 0, 1, 2
 PRIOR, RESAMPLE, PROPOSAL, ACCEPT = 1, 2, 3, 4
 
 
 class OrcModel(C.Structure):
     _fields_ = [("kind", C.c_int32), ("K", C.c_int32), ("shock", C.c_int32),
                 ("nreg", C.c_int32), ("T", C.c_int64),
-                ("y", C.POINTER(C.c_double)), ("X", C.POINTER(C.c_double))]
+                ("y", C.POINTER(C.c_double)), ("X", C.POINTER(C.c_double)),
+                ("I", C.c_int32), ("pad", C.c_int32)]
 
 
 class OrcPop(C.Structure):
@@ -100,18 +101,18 @@ def _f64(a):
 class Model:
     """Holds the numpy data alive for the C struct."""
 
-    def __init__(self, kind, T, y, K=0, shock=GAUSS, nreg=0, X=None):
+    def __init__(self, kind, T, y, K=0, shock=GAUSS, nreg=0, X=None, I=0):
         self.y = _f64(y)
         self.X = _f64(X) if X is not None else None
         self.c = OrcModel(kind, K, shock, nreg, T, _dp(self.y),
-                          _dp(self.X) if self.X is not None else C.POINTER(C.c_double)())
-        self.kind, self.K, self.shock, self.nreg, self.T = kind, K, shock, nreg, T
+                          _dp(self.X) if self.X is not None else C.POINTER(C.c_double)(), I, 0)
+        self.kind, self.K, self.shock, self.nreg, self.T, self.I = kind, K, shock, nreg, T, I
 
     @classmethod
     def from_workload(cls, w, T=None):
         T = T or w.T
         return cls(w.kind, T, w.y[:T], K=w.K, shock=w.shock, nreg=w.nreg,
-                   X=None if w.X is None else w.X[:T])
+                   X=None if w.X is None else w.X[:T], I=w.I)
 
     @property
     def d(self):
@@ -137,6 +138,14 @@ def normals(seed, run, c0, c1, c2, purpose, n):
     lib().orc_normals(C.c_uint64(seed), C.c_uint64(run), C.c_uint64(c0), C.c_uint64(c1),
                       C.c_uint64(c2), C.c_uint64(purpose), C.c_int(n), _dp(z))
     return z
+
+
+def mixture_params(m: Model, theta):
+    """(p, mu, sigma) of the shock mixture at theta (eqs EGARCH_tran1/2)."""
+    p, mu, sg = np.zeros(m.I), np.zeros(m.I), np.zeros(m.I)
+    th = _f64(theta)
+    lib().orc_mixture_params(C.byref(m.c), _dp(th), _dp(p), _dp(mu), _dp(sg))
+    return p, mu, sg
 
 
 def logprior(m: Model, theta):

@@ -30,7 +30,7 @@
 #include <stdlib.h>
 #include <string.h>
 
-#define ORC_DMAX 20 /* largest parameter dimension handled */
+#define ORC_DMAX 32 /* largest parameter dimension handled */
 
 /* Threads the OpenMP particle loops use (1 without OpenMP). */
 int orc_num_threads(void) {
@@ -116,23 +116,31 @@ void orc_normals(uint64_t seed, uint64_t run, uint64_t c0, uint64_t c1, uint64_t
 /* Models (Section 5.1 and the conjugate regression workload).              */
 /* ------------------------------------------------------------------------ */
 enum { ORC_LINREG = 1, ORC_EGARCH = 2 };
-enum { ORC_GAUSS = 0, ORC_STUDENT_T = 1 };
+enum { ORC_GAUSS = 0, ORC_STUDENT_T = 1, ORC_MIXTURE = 2 };
 
 typedef struct {
   int32_t kind;    /* ORC_LINREG or ORC_EGARCH */
   int32_t K;       /* EGARCH volatility factors */
-  int32_t shock;   /* ORC_GAUSS or ORC_STUDENT_T */
+  int32_t shock;   /* ORC_GAUSS, ORC_STUDENT_T or ORC_MIXTURE */
   int32_t nreg;    /* regressors (LINREG) */
   int64_t T;       /* observations */
   const double *y; /* [T] */
   const double *X; /* [T][nreg] (LINREG) */
+  int32_t I;       /* normal-mixture components (ORC_MIXTURE, I >= 2) */
+  int32_t pad_;
 } orc_model;
+
+/* Lower truncation point of theta_8i (Table 1) and log P(Z >= -3) for the
+ * normalising constant of the truncated prior. */
+static const double MIX_TRUNC = -3.0;
+static double mix_log_mass(void) { return log(0.5 * erfc(MIX_TRUNC / sqrt(2.0))); }
 
 /* Conjugate prior of the regression: beta | s2 ~ N(0, c0 s2 I), s2 ~ IG(a0, b0). */
 static const double LR_A0 = 2.0, LR_B0 = 1.0, LR_C0 = 100.0;
 
 int orc_dim(const orc_model *m) {
   if (m->kind == ORC_LINREG) return m->nreg + 1;
+  if (m->shock == ORC_MIXTURE) return 2 + 3 * m->K + 3 * m->I;
   return 2 + 3 * m->K + (m->shock == ORC_STUDENT_T ? 1 : 0);
 }
 
@@ -142,7 +150,8 @@ int orc_state_dim(const orc_model *m) {
 }
 
 /* Table 1 prior means and standard deviations on the transformed parameters,
- * in the order (th1, th2, th3_k.., th4_k.., th5_k.., [th9 = log(nu - 2)]). */
+ * in the order (th1, th2, th3_k.., th4_k.., th5_k.., then either
+ * th9 = log(nu - 2) or th6_i.., th7_i.., th8_i..). */
 static void egarch_prior_moments(const orc_model *m, double *mean, double *sd) {
   int K = m->K, i = 0;
   mean[i] = 0.0; sd[i] = 1.0; ++i;                        /* mu_Y = th1/1000 */
@@ -151,6 +160,13 @@ static void egarch_prior_moments(const orc_model *m, double *mean, double *sd) {
   for (int k = 0; k < K; ++k, ++i) { mean[i] = log(0.10); sd[i] = 1.0; }   /* beta */
   for (int k = 0; k < K; ++k, ++i) { mean[i] = 0.0; sd[i] = 0.2; }         /* gamma */
   if (m->shock == ORC_STUDENT_T) { mean[i] = log(10.0); sd[i] = 1.0; ++i; } /* nu */
+  if (m->shock == ORC_MIXTURE)  /* p*_i, mu*_i, sigma*_i: all N(0, 1) */
+    for (int r = 0; r < 3 * m->I; ++r, ++i) { mean[i] = 0.0; sd[i] = 1.0; }
+}
+
+/* Index of the first theta_8i (mixture scales), or -1. */
+static int mix_sigma_index(const orc_model *m) {
+  return m->shock == ORC_MIXTURE ? 2 + 3 * m->K + 2 * m->I : -1;
 }
 
 double orc_logprior(const orc_model *m, const double *th) {
@@ -172,6 +188,13 @@ double orc_logprior(const orc_model *m, const double *th) {
     double z = (th[i] - mean[i]) / sd[i];
     lp += -0.5 * log(2.0 * M_PI) - log(sd[i]) - 0.5 * z * z;
   }
+  /* theta_8i ~ N(0, 1) truncated to [-3, inf) */
+  int i8 = mix_sigma_index(m);
+  if (i8 >= 0)
+    for (int i = 0; i < m->I; ++i) {
+      if (th[i8 + i] < MIX_TRUNC) return -INFINITY;
+      lp -= mix_log_mass();
+    }
   return lp;
 }
 
@@ -198,6 +221,39 @@ void orc_prior_draw(const orc_model *m, uint64_t seed, uint64_t run, int64_t p, 
   egarch_prior_moments(m, mean, sd);
   normals(seed, run, (uint64_t)p, 0, 0, ORC_PRIOR, d, z);
   for (int i = 0; i < d; ++i) th[i] = mean[i] + sd[i] * z[i];
+  /* Truncated theta_8i by rejection: attempt a = 1, 2, ... redraws the whole
+   * normal vector on counter (p, 0, a, PRIOR | block) and takes its entry
+   * for that parameter.  After 32 failed attempts (probability 1e-92) the
+   * truncation point itself is used. */
+  int i8 = mix_sigma_index(m);
+  if (i8 >= 0)
+    for (int i = i8; i < i8 + m->I; ++i) {
+      for (uint64_t a = 1; th[i] < MIX_TRUNC && a <= 32; ++a) {
+        normals(seed, run, (uint64_t)p, 0, a, ORC_PRIOR, d, z);
+        th[i] = mean[i] + sd[i] * z[i];
+      }
+      if (th[i] < MIX_TRUNC) th[i] = MIX_TRUNC;
+    }
+}
+
+/* Mixture components from theta (eqs EGARCH_tran1 and EGARCH_tran2):
+ * p*_i = tanh(th6i) + 1, mu*_i = th7i, sigma*_i = exp(th8i); p_i = p*_i /
+ * sum p*; mu**_i = mu*_i - sum_j p_j mu*_j; c = [sum p_i (mu**_i^2 +
+ * sigma*_i^2)]^(-1/2); mu_i = c mu**_i, sigma_i = c sigma*_i.  The result
+ * has mean sum p_i mu_i = 0 and variance 1 (eq EGARCH_normalization). */
+void orc_mixture_params(const orc_model *m, const double *th, double *pw, double *mu,
+                        double *sg) {
+  int I = m->I, b = 2 + 3 * m->K;
+  double ps = 0.0, pm = 0.0, q = 0.0;
+  for (int i = 0; i < I; ++i) { pw[i] = tanh(th[b + i]) + 1.0; ps += pw[i]; }
+  for (int i = 0; i < I; ++i) { pw[i] /= ps; pm += pw[i] * th[b + I + i]; }
+  for (int i = 0; i < I; ++i) {
+    mu[i] = th[b + I + i] - pm;
+    sg[i] = exp(th[b + 2 * I + i]);
+    q += pw[i] * (mu[i] * mu[i] + sg[i] * sg[i]);
+  }
+  double c = 1.0 / sqrt(q);
+  for (int i = 0; i < I; ++i) { mu[i] *= c; sg[i] *= c; }
 }
 
 void orc_state_init(const orc_model *m, double *state) {
@@ -217,6 +273,9 @@ void orc_state_init(const orc_model *m, double *state) {
  *   4. Gaussian shocks: log phi(eps_s) - log h_s.  Student-t shocks are
  *      rescaled to unit variance, so eps has density
  *      Gamma((nu+1)/2) / (Gamma(nu/2) sqrt(pi (nu-2))) (1 + eps^2/(nu-2))^(-(nu+1)/2).
+ *      Normal-mixture shocks (eq normal_mixture): the density of eps is
+ *      sum_i p_i phi(eps; mu_i, sigma_i^2), its logarithm taken as a
+ *      log-sum-exp over the components (shifted by the largest term).
  * Regression: log N(y_s; x_s' beta, exp(eta)).
  */
 static double obs_logdens(const orc_model *m, const double *th, int64_t s, double *state) {
@@ -246,6 +305,18 @@ static double obs_logdens(const orc_model *m, const double *th, int64_t s, doubl
   double eps = (y - mu) / h;
   state[K] = eps;
   if (m->shock == ORC_GAUSS) return -0.5 * log(2.0 * M_PI) - log(h) - 0.5 * eps * eps;
+  if (m->shock == ORC_MIXTURE) {
+    double pw[ORC_DMAX], mc[ORC_DMAX], sg[ORC_DMAX], a[ORC_DMAX];
+    orc_mixture_params(m, th, pw, mc, sg);
+    double mx = -INFINITY, sum = 0.0;
+    for (int i = 0; i < m->I; ++i) {
+      double u = (eps - mc[i]) / sg[i];
+      a[i] = log(pw[i]) - log(sg[i]) - 0.5 * u * u;
+      if (a[i] > mx) mx = a[i];
+    }
+    for (int i = 0; i < m->I; ++i) sum += exp(a[i] - mx);
+    return -0.5 * log(2.0 * M_PI) - log(h) + mx + log(sum);
+  }
   double nu = 2.0 + exp(th[2 + 3 * K]);
   double c = lgamma((nu + 1.0) / 2.0) - lgamma(nu / 2.0) - 0.5 * log(M_PI * (nu - 2.0));
   return c - log(h) - (nu + 1.0) / 2.0 * log(1.0 + eps * eps / (nu - 2.0));
@@ -337,6 +408,31 @@ static dual obs_logdens_dual(const orc_model *m, const dual *th, int64_t s, dual
   state[K] = eps;
   if (m->shock == ORC_GAUSS)
     return dsub(dsub(dconst(-0.5 * log(2.0 * M_PI)), dlog(h)), dscale(dmul(eps, eps), 0.5));
+  if (m->shock == ORC_MIXTURE) {
+    /* the same transforms and log-sum-exp on dual numbers */
+    int I = m->I, b = 2 + 3 * K;
+    dual pw[ORC_DMAX], mc[ORC_DMAX], sg[ORC_DMAX], a[ORC_DMAX];
+    dual ps = dconst(0.0), pm = dconst(0.0), q = dconst(0.0);
+    for (int i = 0; i < I; ++i) { pw[i] = dadd(dtanh(th[b + i]), dconst(1.0)); ps = dadd(ps, pw[i]); }
+    for (int i = 0; i < I; ++i) { pw[i] = ddiv(pw[i], ps); pm = dadd(pm, dmul(pw[i], th[b + I + i])); }
+    for (int i = 0; i < I; ++i) {
+      mc[i] = dsub(th[b + I + i], pm);
+      sg[i] = dexp(th[b + 2 * I + i]);
+      q = dadd(q, dmul(pw[i], dadd(dmul(mc[i], mc[i]), dmul(sg[i], sg[i]))));
+    }
+    dual c = ddiv(dconst(1.0), dchain(q, sqrt(q.v), 0.5 / sqrt(q.v)));
+    double mx = -INFINITY;
+    for (int i = 0; i < I; ++i) {
+      mc[i] = dmul(mc[i], c);
+      sg[i] = dmul(sg[i], c);
+      dual u = ddiv(dsub(eps, mc[i]), sg[i]);
+      a[i] = dsub(dsub(dlog(pw[i]), dlog(sg[i])), dscale(dmul(u, u), 0.5));
+      if (a[i].v > mx) mx = a[i].v;
+    }
+    dual sum = dconst(0.0);
+    for (int i = 0; i < I; ++i) sum = dadd(sum, dexp(dsub(a[i], dconst(mx))));
+    return dadd(dsub(dconst(-0.5 * log(2.0 * M_PI) + mx), dlog(h)), dlog(sum));
+  }
   dual nu = dadd(dconst(2.0), dexp(th[2 + 3 * K]));
   dual nu2 = dsub(nu, dconst(2.0));
   dual c = dsub(dsub(dlgamma(dscale(dadd(nu, dconst(1.0)), 0.5)), dlgamma(dscale(nu, 0.5))),
@@ -364,6 +460,12 @@ static dual logprior_dual(const orc_model *m, const dual *th) {
     dual z = dscale(dsub(th[i], dconst(mean[i])), 1.0 / sd[i]);
     lp = dsub(dadd(lp, dconst(-0.5 * log(2.0 * M_PI) - log(sd[i]))), dscale(dmul(z, z), 0.5));
   }
+  int i8 = mix_sigma_index(m);
+  if (i8 >= 0)
+    for (int i = 0; i < m->I; ++i) {
+      if (th[i8 + i].v < MIX_TRUNC) return dconst(-INFINITY);
+      lp = dsub(lp, dconst(mix_log_mass()));
+    }
   return lp;
 }
 

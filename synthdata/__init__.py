@@ -18,6 +18,10 @@ for it):
                   parameterisation, see ``EGARCH11_TRUTH``).
 * ``egarch2t``    EGARCH with K = 2 factors and standardised Student-t(8)
                   shocks, T = 10,000, J = 64 x N = 1,024.
+* ``egarch23``    EGARCH with K = 2 factors and a 3-component normal-mixture
+                  shock (the paper's featured specification), T = 5,100,
+                  J = 64 x N = 1,024.  Other ``egarchKI`` names (K in 1..4,
+                  I in 2..4) give the rest of the family at that size.
 * ``batched``     32 independent runs mixing the two EGARCH forms with
                   T in [1,000, 20,000] and J*N in {4096 ... 65536}.
 """
@@ -35,6 +39,7 @@ LINREG = 1
 EGARCH = 2
 GAUSS = 0
 STUDENT_T = 1
+MIXTURE = 2
 
 # Nelson (1991) form of the EGARCH(1,1) truth: log s2_t = omega + b log s2_{t-1}
 #   + a (|z| - sqrt(2/pi)) + g z.  In the paper's form (EGARCH_mod1/2) the
@@ -68,6 +73,40 @@ def egarch2t_truth() -> np.ndarray:
     ])
 
 
+# Mixture truth for the egarchKI workloads: a fat-tailed, slightly
+# left-skewed shock built from I components, given directly in the
+# normalised form (weights, means, scales with mean 0 and variance 1) and in
+# Table 1's coordinates theta_6..8 with sum p* = 1 (th6 = atanh(p - 1)), sum
+# p mu* = 0 (so mu** = mu*) and c = 1 (sum p (mu^2 + s^2) = 1).
+def mixture_truth(I: int):
+    if I == 2:
+        p = np.array([0.85, 0.15])
+        mu = np.array([0.06, -0.34])
+    elif I == 3:
+        p = np.array([0.6, 0.3, 0.1])
+        mu = np.array([0.08, 0.02, -0.54])
+    else:
+        p = np.array([0.5, 0.25, 0.15, 0.1])
+        mu = np.array([0.1, -0.02, 0.05, -0.525])
+    mu = mu - (p * mu).sum()
+    s_raw = np.linspace(0.7, 1.9, I)
+    scale = math.sqrt((1.0 - (p * mu ** 2).sum()) / (p * s_raw ** 2).sum())
+    sg = s_raw * scale
+    return p, mu, sg
+
+
+def egarch_mixture_truth(K: int, I: int) -> np.ndarray:
+    """theta_true for egarchKI: the K-factor part from the 2-factor truth
+    (factors beyond 2 get weaker persistence), then th6_i = atanh(p_i - 1),
+    th7_i = mu_i, th8_i = log sigma_i for the normalised mixture above."""
+    alphas = [0.98, 0.80, 0.6, 0.4][:K]
+    betas = [0.08, 0.15, 0.1, 0.1][:K]
+    gammas = [-0.04, -0.08, -0.02, -0.02][:K]
+    p, mu, sg = mixture_truth(I)
+    return np.concatenate([[0.3, math.log(0.01)], np.arctanh(alphas), np.log(betas), gammas,
+                           np.arctanh(p - 1.0), mu, np.log(sg)])
+
+
 def linreg_series(T: int = 200, k: int = 3, beta=(1.0, -0.5, 0.25),
                   sigma: float = 0.8, seed: int = DATA_SEED_BASE + 1):
     """y = X beta + sigma * eps with X, eps iid N(0, 1).  Returns (y[T], X[T,k])."""
@@ -85,7 +124,9 @@ def egarch_series(theta: np.ndarray, T: int, K: int, shock: int,
     Factor states start at zero and take no innovation at t = 1 (so the
     first return has scale sigma_Y); from t = 2 on each factor follows
     v_kt = alpha_k v_k,t-1 + beta_k (|z_{t-1}| - sqrt(2/pi)) + gamma_k z_{t-1}.
-    Shocks are N(0,1) or Student-t(nu) rescaled to unit variance.
+    Shocks are N(0,1), Student-t(nu) rescaled to unit variance, or (for the
+    mixture, whose truth is given with mean 0 and variance 1 already) a
+    draw from component i with probability p_i.
     With ``return_path`` the shocks z and scales h are returned too.
     """
     theta = np.asarray(theta, dtype=np.float64)
@@ -97,6 +138,13 @@ def egarch_series(theta: np.ndarray, T: int, K: int, shock: int,
     rng = np.random.default_rng(seed)
     if shock == GAUSS:
         z = rng.standard_normal(T)
+    elif shock == MIXTURE:
+        I = (theta.size - 2 - 3 * K) // 3
+        b = 2 + 3 * K
+        p = np.tanh(theta[b:b + I]) + 1.0
+        p = p / p.sum()
+        comp = rng.choice(I, size=T, p=p)
+        z = theta[b + I + comp] + np.exp(theta[b + 2 * I + comp]) * rng.standard_normal(T)
     else:
         nu = 2.0 + math.exp(theta[2 + 3 * K])
         z = rng.standard_t(nu, T) * math.sqrt((nu - 2.0) / nu)
@@ -126,6 +174,7 @@ class Workload:
     J: int = 0
     N: int = 0
     check_every: int = 1
+    I: int = 0
     y: np.ndarray = field(default=None, repr=False)
     X: np.ndarray = field(default=None, repr=False)
     theta_true: np.ndarray = field(default=None, repr=False)
@@ -138,6 +187,8 @@ class Workload:
     def d(self) -> int:
         if self.kind == LINREG:
             return self.nreg + 1
+        if self.shock == MIXTURE:
+            return 2 + 3 * self.K + 3 * self.I
         return 2 + 3 * self.K + (1 if self.shock == STUDENT_T else 0)
 
 
@@ -161,6 +212,14 @@ def workload(name: str, T: int | None = None, J: int | None = None,
         y = egarch_series(th, T, 2, STUDENT_T, DATA_SEED_BASE + 3 + seed_offset)
         return Workload(name, EGARCH, K=2, shock=STUDENT_T, T=T, J=J or 64,
                         N=N or 1024, y=y, theta_true=th)
+    if len(name) == 8 and name.startswith("egarch") and name[6:].isdigit():
+        K, I = int(name[6]), int(name[7])
+        if 1 <= K <= 4 and 2 <= I <= 4:
+            T = T or 5100
+            th = egarch_mixture_truth(K, I)
+            y = egarch_series(th, T, K, MIXTURE, DATA_SEED_BASE + 10 * K + I + seed_offset)
+            return Workload(name, EGARCH, K=K, shock=MIXTURE, I=I, T=T, J=J or 64,
+                            N=N or 1024, y=y, theta_true=th)
     raise KeyError(name)
 
 

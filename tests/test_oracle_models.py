@@ -141,7 +141,7 @@ def test_egarch_factors_are_exchangeable():
     assert O.logprior(m, sw) == pytest.approx(O.logprior(m, th), rel=1e-13)
 
 
-@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t"])
+@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t", "egarch23"])
 def test_loglik_splits_over_dates(name):
     w = SD.workload(name, T=300)
     m = O.Model.from_workload(w)
@@ -156,7 +156,7 @@ def test_loglik_splits_over_dates(name):
 
 # -------------------------------------------------------------- gradients ---
 
-@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t"])
+@pytest.mark.parametrize("name", ["linreg", "egarch11", "egarch2t", "egarch23", "egarch44"])
 def test_gradient_matches_central_differences(name):
     w = SD.workload(name, T=250)
     m = O.Model.from_workload(w)
@@ -185,3 +185,160 @@ def test_linreg_gradient_closed_form():
     s2 = math.exp(th[3])
     assert np.allclose(g[:3], X.T @ r / s2, rtol=1e-12)
     assert g[3] == pytest.approx(-len(y) / 2 + (r @ r) / (2 * s2), rel=1e-12)
+
+
+# -------------------------------------------------- normal-mixture shocks ---
+# egarch_KI (Section 5.1): eq normal_mixture with the transforms of eqs
+# EGARCH_tran1/2 and Table 1's theta_6..8 priors.
+
+MIX = [(1, 2), (2, 3), (3, 4), (4, 4)]
+
+
+def _mix_model(K, I, T=400, seed=5):
+    th = SD.egarch_mixture_truth(K, I)
+    y, z, h = SD.egarch_series(th, T, K, SD.MIXTURE, seed, return_path=True)
+    return O.Model(O.EGARCH, T, y, K=K, shock=O.MIXTURE, I=I), th, z, h
+
+
+def _mix_pdf(x, p, mu, sg):
+    return sum(p[i] * stats.norm.pdf(x, mu[i], sg[i]) for i in range(len(p)))
+
+
+@pytest.mark.parametrize("K,I", MIX)
+def test_mixture_logprior_is_table1_with_truncation(K, I):
+    """Table 1: all Gaussian, theta_8i truncated below at -3 (scipy's
+    truncnorm carries the normalising constant)."""
+    t1 = _table1()
+    m, th, _, _ = _mix_model(K, I, T=10)
+    means = ([t1["theta1_mu"]["mean"], math.log(t1["theta2_sigma"]["mean_log_of"])]
+             + [math.atanh(t1["theta3_alpha"]["mean_atanh_of"])] * K
+             + [math.log(t1["theta4_beta"]["mean_log_of"])] * K
+             + [t1["theta5_gamma"]["mean"]] * K
+             + [t1["theta6_p"]["mean"]] * I + [t1["theta7_mu"]["mean"]] * I)
+    sds = ([t1["theta1_mu"]["sd"], t1["theta2_sigma"]["sd"]] + [t1["theta3_alpha"]["sd"]] * K
+           + [t1["theta4_beta"]["sd"]] * K + [t1["theta5_gamma"]["sd"]] * K
+           + [t1["theta6_p"]["sd"]] * I + [t1["theta7_mu"]["sd"]] * I)
+    lo = t1["theta8_sigma"]["truncated_below"]
+    rng = np.random.default_rng(K * 10 + I)
+    n8 = 2 + 3 * K + 2 * I
+    for _ in range(6):
+        x = th + rng.standard_normal(th.size)
+        x[n8:] = np.maximum(x[n8:], lo + 0.01)
+        want = (stats.norm.logpdf(x[:n8], means, sds).sum()
+                + stats.truncnorm.logpdf(x[n8:], lo, np.inf).sum())
+        assert O.logprior(m, x) == pytest.approx(want, rel=1e-13, abs=1e-12)
+    x = th.copy()
+    x[n8 + I - 1] = lo - 1e-9
+    assert O.logprior(m, x) == -math.inf
+
+
+def test_mixture_prior_draws_respect_truncation():
+    w = SD.workload("egarch23", T=10)
+    m = O.Model.from_workload(w)
+    draws = np.array([O.prior_draw(m, 4, 0, p) for p in range(4000)])
+    n8 = 2 + 3 * 2 + 2 * 3
+    assert draws[:, n8:].min() >= -3.0
+    for i in range(3):
+        assert stats.kstest(draws[:, n8 + i], stats.truncnorm(-3.0, np.inf).cdf).pvalue > 1e-3
+        assert stats.kstest(draws[:, 2 + 6 + i], "norm").pvalue > 1e-3
+    assert np.all(np.isfinite([O.logprior(m, d) for d in draws[:200]]))
+
+
+@pytest.mark.parametrize("K,I", MIX)
+def test_mixture_filter_recovers_simulated_shocks(K, I):
+    """At the generating parameters (given in normalised form) eps_t is the
+    simulated shock and log p = sum_t log f(z_t) - log h_t with f the mixture
+    density evaluated by scipy."""
+    T = 400
+    m, th, z, h = _mix_model(K, I, T=T)
+    p, mu, sg = SD.mixture_truth(I)
+    ll, st = O.loglik(m, th)
+    assert st[K] == pytest.approx(z[-1], rel=1e-9)
+    want = (np.log(_mix_pdf(z, p, mu, sg)) - np.log(h)).sum()
+    assert ll == pytest.approx(want, rel=1e-11)
+
+
+def test_mixture_transforms_satisfy_normalisation():
+    """eq EGARCH_normalization at arbitrary theta: mean 0, variance 1."""
+    m, th, _, _ = _mix_model(2, 4, T=10)
+    rng = np.random.default_rng(3)
+    for _ in range(20):
+        x = th + rng.standard_normal(th.size)
+        p, mu, sg = O.mixture_params(m, x)
+        assert np.all(p > 0) and np.all(sg > 0)
+        assert p.sum() == pytest.approx(1.0, abs=1e-14)
+        assert (p * mu).sum() == pytest.approx(0.0, abs=1e-14)
+        assert (p * (mu ** 2 + sg ** 2)).sum() == pytest.approx(1.0, abs=1e-13)
+
+
+@pytest.mark.parametrize("K,I", [(1, 2), (2, 3)])
+def test_mixture_conditional_density_by_quadrature(K, I):
+    """p(y_t | y_{1:t-1}, theta) at generic theta, as a function of y_t:
+    integrates to one, has mean mu_Y, variance h_t^2 and third central
+    moment h_t^3 sum p_i (mu_i^3 + 3 mu_i sigma_i^2)."""
+    T = 60
+    m, th, _, _ = _mix_model(K, I, T=T)
+    x = th + 0.4 * np.random.default_rng(9).standard_normal(th.size)
+    ll_prev, st = O.loglik(m, x, t=T - 1)
+    vs = st[:K]
+    eprev = st[K]
+    alpha = np.tanh(x[2:2 + K])
+    beta = np.exp(x[2 + K:2 + 2 * K])
+    gamma = x[2 + 2 * K:2 + 3 * K]
+    v = alpha * vs + beta * (abs(eprev) - math.sqrt(2 / math.pi)) + gamma * eprev
+    h = math.exp(x[1]) * math.exp(0.5 * v.sum())
+    muY = x[0] / 1000
+    grid = muY + h * np.linspace(-14, 14, 8001)
+    dens = []
+    for yv in grid:
+        y2 = m.y.copy()
+        y2[T - 1] = yv
+        mm = O.Model(O.EGARCH, T, y2, K=K, shock=O.MIXTURE, I=I)
+        dens.append(math.exp(O.loglik(mm, x)[0] - ll_prev))
+    dens = np.array(dens)
+    mass = np.trapezoid(dens, grid)
+    mean = np.trapezoid(grid * dens, grid)
+    var = np.trapezoid((grid - muY) ** 2 * dens, grid)
+    m3 = np.trapezoid((grid - muY) ** 3 * dens, grid)
+    p, mu, sg = O.mixture_params(m, x)
+    assert mass == pytest.approx(1.0, abs=1e-9)
+    assert mean == pytest.approx(muY, abs=1e-9 * h)
+    assert var == pytest.approx(h * h, rel=1e-8)
+    assert m3 == pytest.approx(h ** 3 * (p * (mu ** 3 + 3 * mu * sg ** 2)).sum(), rel=1e-6, abs=1e-9 * h ** 3)
+
+
+def test_mixture_with_equal_components_is_gaussian():
+    """Identical components collapse to a standard normal shock: the
+    likelihood equals the Gaussian-shock model's."""
+    K, I = 2, 3
+    m, th, _, _ = _mix_model(K, I, T=300)
+    x = th.copy()
+    b = 2 + 3 * K
+    x[b:b + I] = 0.3
+    x[b + I:b + 2 * I] = -0.7
+    x[b + 2 * I:] = 0.2
+    mg = O.Model(O.EGARCH, 300, m.y, K=K, shock=O.GAUSS)
+    assert O.loglik(m, x)[0] == pytest.approx(O.loglik(mg, x[:b])[0], rel=1e-12)
+
+
+def test_mixture_location_scale_and_label_invariance():
+    """The normalisation removes the location and scale of (mu*, sigma*),
+    and components are exchangeable (the label-switching symmetry of
+    Section 5.1)."""
+    K, I = 2, 3
+    m, th, _, _ = _mix_model(K, I, T=300)
+    x = th + 0.3 * np.random.default_rng(4).standard_normal(th.size)
+    b = 2 + 3 * K
+    base = O.loglik(m, x)[0]
+    sh = x.copy()
+    sh[b + I:b + 2 * I] += 0.37
+    assert O.loglik(m, sh)[0] == pytest.approx(base, rel=1e-12)
+    sc = x.copy()
+    sc[b + I:b + 2 * I] *= 1.6
+    sc[b + 2 * I:] += math.log(1.6)
+    assert O.loglik(m, sc)[0] == pytest.approx(base, rel=1e-12)
+    perm = [2, 0, 1]
+    pm = x.copy()
+    for r in range(3):
+        pm[b + r * I:b + (r + 1) * I] = x[b + r * I:b + (r + 1) * I][perm]
+    assert O.loglik(m, pm)[0] == pytest.approx(base, rel=1e-12)
