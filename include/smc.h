@@ -52,6 +52,7 @@ typedef int32_t smc_status;
 #define SMC_MODEL_EGARCH 2 /* eqs EGARCH_mod1/2 with K factors */
 #define SMC_SHOCK_GAUSS 0
 #define SMC_SHOCK_STUDENT_T 1 /* unit-variance Student-t(nu) shocks */
+#define SMC_SHOCK_MIXTURE 2   /* I-component normal mixture, eq normal_mixture */
 /* Arithmetic of the likelihood recursion.  Log weights, log-likelihood sums,
  * logsumexp, covariance, Cholesky, the marginal likelihood and its NSE are
  * FP64 in both cases. */
@@ -72,17 +73,23 @@ typedef int32_t smc_status;
 /* Model description.  The parameter vector theta (dimension d) is:
  *   LINREG: (beta_1..beta_k, log s2), d = k + 1, prior beta | s2 ~
  *           N(0, 100 s2 I), s2 ~ InvGamma(2, 1) (conjugate);
- *   EGARCH: (theta_1, theta_2, theta_3k.., theta_4k.., theta_5k..
- *           [, log(nu - 2)]) with Table 1's transforms and Gaussian priors,
- *           d = 2 + 3K (+1 for Student-t); state S = K + 1 (the K factors
- *           and the previous standardised shock). */
+ *   EGARCH: (theta_1, theta_2, theta_3k.., theta_4k.., theta_5k..) with
+ *           Table 1's transforms and Gaussian priors, followed by log(nu - 2)
+ *           ~ N(log 10, 1) for Student-t shocks, or by theta_6i.., theta_7i..,
+ *           theta_8i.. (i = 1..I) for normal-mixture shocks, transformed by
+ *           eqs EGARCH_tran1/2 and with theta_8i ~ N(0, 1) truncated below
+ *           at -3 (Table 1; egarch_KI of Section 5.1).  d = 2 + 3K, +1 for
+ *           Student-t, +3I for mixtures; state S = K + 1 (the K factors and
+ *           the previous standardised shock).  Gaussian and Student-t
+ *           shocks: K in {1, 2}; mixtures: K in 1..4, I in 2..4 (FP64 or
+ *           FP32). */
 typedef struct {
   int32_t kind;      /* SMC_MODEL_* */
-  int32_t K;         /* EGARCH factors, 1 or 2 */
+  int32_t K;         /* EGARCH factors (see above) */
   int32_t shock;     /* SMC_SHOCK_* (EGARCH) */
   int32_t nreg;      /* regressors k, 1..8 (LINREG) */
   int32_t precision; /* SMC_FP64 or SMC_FP32 (FP32: EGARCH only) */
-  int32_t reserved;  /* must be 0 */
+  int32_t ncomp;     /* mixture components I (SMC_SHOCK_MIXTURE), else 0 */
   int64_t T;         /* observations, >= 1 */
   const double *y;   /* device [T] */
   const float *y32;  /* device [T], y as float; required for SMC_FP32 */

@@ -16,8 +16,9 @@ LIB_PATH = os.path.join(HERE, "libsmc.so")
 
 # Enums (values fixed by include/smc.h).
 SMC_OK = 0
+SMC_E_INVALID_ARG, SMC_E_UNSUPPORTED, SMC_E_DEVICE, SMC_E_NUMERIC, SMC_E_WORKSPACE = -1, -2, -3, -4, -5
 SMC_MODEL_LINREG, SMC_MODEL_EGARCH = 1, 2
-SMC_SHOCK_GAUSS, SMC_SHOCK_STUDENT_T = 0, 1
+SMC_SHOCK_GAUSS, SMC_SHOCK_STUDENT_T, SMC_SHOCK_MIXTURE = 0, 1, 2
 SMC_FP64, SMC_FP32 = 0, 1
 SMC_RESAMPLE_RESIDUAL, SMC_RESAMPLE_MULTINOMIAL = 0, 1
 SMC_RESAMPLE_STRATIFIED, SMC_RESAMPLE_SYSTEMATIC = 2, 3
@@ -29,7 +30,7 @@ _vp = C.c_void_p
 
 class ModelDesc(C.Structure):
     _fields_ = [("kind", C.c_int32), ("K", C.c_int32), ("shock", C.c_int32),
-                ("nreg", C.c_int32), ("precision", C.c_int32), ("reserved", C.c_int32),
+                ("nreg", C.c_int32), ("precision", C.c_int32), ("ncomp", C.c_int32),
                 ("T", C.c_int64), ("y", _vp), ("y32", _vp), ("X", _vp)]
 
 
@@ -156,16 +157,16 @@ class Model:
     """A model handle plus the device copies of its data."""
 
     def __init__(self, kind, y, X=None, K=1, shock=SMC_SHOCK_GAUSS, precision=SMC_FP64,
-                 device="cuda"):
+                 device="cuda", I=0):
         self.y = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
         self.y32 = self.y.float().contiguous() if precision == SMC_FP32 else None
         self.X = (torch.as_tensor(X, dtype=torch.float64).to(device).contiguous()
                   if X is not None else None)
         nreg = int(self.X.shape[1]) if self.X is not None else 0
-        self.kind, self.K, self.shock, self.precision = kind, K, shock, precision
+        self.kind, self.K, self.shock, self.precision, self.I = kind, K, shock, precision, I
         self.T = int(self.y.numel())
         self.device = device
-        self.desc = ModelDesc(kind, K, shock, nreg, precision, 0, self.T, _ptr(self.y),
+        self.desc = ModelDesc(kind, K, shock, nreg, precision, I, self.T, _ptr(self.y),
                               _ptr(self.y32), _ptr(self.X))
         h = C.c_void_p()
         _check(lib().smc_model_create(C.byref(self.desc), C.byref(h)), "smc_model_create")
@@ -174,7 +175,7 @@ class Model:
     @classmethod
     def from_workload(cls, w, precision=SMC_FP64, device="cuda"):
         return cls(w.kind, w.y, X=w.X, K=w.K, shock=w.shock, precision=precision,
-                   device=device)
+                   device=device, I=w.I)
 
     @property
     def d(self):

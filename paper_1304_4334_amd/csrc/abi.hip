@@ -50,7 +50,8 @@ WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
   L.cum = off;
   off += align256(P * sizeof(double));
   L.mpart = off;
-  off += align256((size_t)kMomBlocks * (16 + 256) * sizeof(double));
+  const size_t mw = m.d + 1 <= 16 ? 16 : 32;  // padded moments width
+  off += align256((size_t)kMomBlocks * mw * mw * sizeof(double));
   L.rpart = off;
   off += align256((size_t)J * 2 * kDMax * sizeof(double));
   L.wcols = off;
@@ -138,7 +139,6 @@ const char *smc_last_error(void) { return g_err; }
 smc_status smc_model_create(const smc_model_desc *desc, smc_model **out) {
   if (!desc || !out) return set_error(SMC_E_INVALID_ARG, "NULL description or output");
   *out = nullptr;
-  if (desc->reserved != 0) return set_error(SMC_E_INVALID_ARG, "reserved field must be 0");
   if (desc->T < 1) return set_error(SMC_E_INVALID_ARG, "T must be >= 1");
   if (!desc->y) return set_error(SMC_E_INVALID_ARG, "y is NULL");
   if (desc->precision != SMC_FP64 && desc->precision != SMC_FP32)
@@ -154,6 +154,7 @@ smc_status smc_model_create(const smc_model_desc *desc, smc_model **out) {
   d.y32 = desc->y32;
   d.X = desc->X;
   if (desc->kind == SMC_MODEL_LINREG) {
+    if (desc->ncomp != 0) return set_error(SMC_E_INVALID_ARG, "ncomp must be 0 for the regression");
     if (desc->nreg < 1 || desc->nreg > 4)
       return set_error(SMC_E_UNSUPPORTED, "regression needs 1..4 regressors");
     if (!desc->X) return set_error(SMC_E_INVALID_ARG, "X is NULL");
@@ -162,13 +163,23 @@ smc_status smc_model_create(const smc_model_desc *desc, smc_model **out) {
     d.d = desc->nreg + 1;
     d.S = 0;
   } else if (desc->kind == SMC_MODEL_EGARCH) {
-    if (desc->K < 1 || desc->K > 2) return set_error(SMC_E_UNSUPPORTED, "EGARCH needs K in {1,2}");
-    if (desc->shock != SMC_SHOCK_GAUSS && desc->shock != SMC_SHOCK_STUDENT_T)
+    if (desc->shock != SMC_SHOCK_GAUSS && desc->shock != SMC_SHOCK_STUDENT_T &&
+        desc->shock != SMC_SHOCK_MIXTURE)
       return set_error(SMC_E_INVALID_ARG, "shock %d", desc->shock);
+    if (desc->shock == SMC_SHOCK_MIXTURE) {
+      if (desc->K < 1 || desc->K > 4) return set_error(SMC_E_UNSUPPORTED, "mixture needs K in 1..4");
+      if (desc->ncomp < 2 || desc->ncomp > 4)
+        return set_error(SMC_E_UNSUPPORTED, "mixture needs I in 2..4 components");
+    } else {
+      if (desc->K < 1 || desc->K > 2) return set_error(SMC_E_UNSUPPORTED, "EGARCH needs K in {1,2}");
+      if (desc->ncomp != 0) return set_error(SMC_E_INVALID_ARG, "ncomp must be 0 without a mixture");
+    }
     if (desc->precision == SMC_FP32 && !desc->y32)
       return set_error(SMC_E_INVALID_ARG, "FP32 recursion needs y32");
-    d.d = 2 + 3 * desc->K + (desc->shock == SMC_SHOCK_STUDENT_T ? 1 : 0);
+    d.d = 2 + 3 * desc->K + (desc->shock == SMC_SHOCK_STUDENT_T ? 1 : 0) +
+          (desc->shock == SMC_SHOCK_MIXTURE ? 3 * desc->ncomp : 0);
     d.S = desc->K + 1;
+    d.ncomp = desc->shock == SMC_SHOCK_MIXTURE ? desc->ncomp : 0;
   } else {
     return set_error(SMC_E_INVALID_ARG, "model kind %d", desc->kind);
   }

@@ -92,11 +92,11 @@ struct Adjoint<Egarch<K, SH, R>> {
 #pragma unroll
       for (int k = 0; k < K; ++k) ckpt[(sg * K + k) * P + pidx] = r.w[k];
       const int64_t s0 = sg * SEG, s1 = min(t, s0 + SEG);
-      R av = (R)0, ae = (R)0;
+      R av = (R)0, ae = (R)0, pm = (R)1;
       for (int64_t s = s0; s < s1; ++s) {
 #pragma unroll
         for (int k = 0; k < K; ++k) wl[k] = r.w[k];
-        av += Md::step(p, y[s], r, ae, lastE, lastz);
+        av += Md::step(p, y[s], r, ae, pm, lastE, lastz);
       }
       sv += (double)av;
       se += (double)ae;
@@ -132,8 +132,8 @@ struct Adjoint<Egarch<K, SH, R>> {
       for (int j = 0; j < len; ++j) {
 #pragma unroll
         for (int k = 0; k < K; ++k) lds[(j * K + k) * 64] = r.w[k];
-        R ae = (R)0, Ed, zd;
-        (void)Md::step(p, y[s0 + j], r, ae, Ed, zd);
+        R ae = (R)0, pm = (R)1, Ed, zd;
+        (void)Md::step(p, y[s0 + j], r, ae, pm, Ed, zd);
       }
       R a_ab[K], a_c0b[K], a_kbb[K], a_kgb[K];
 #pragma unroll

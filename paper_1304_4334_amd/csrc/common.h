@@ -8,8 +8,8 @@
 
 namespace smc {
 
-constexpr int kDMax = 16;      // largest parameter dimension (padded MFMA tile)
-constexpr int kSMax = 4;       // largest recursion state
+constexpr int kDMax = 32;      // parameter dimension bound: d + 1 <= 32 (padded MFMA tiles)
+constexpr int kSMax = 5;       // largest recursion state (K <= 4 factors and the shock)
 constexpr int kBlock = 256;    // threads per block of the bandwidth-shaped kernels
 
 // Philox purposes (counter word 3, low byte).
@@ -24,7 +24,7 @@ struct DevModel {
   int32_t prec;
   int32_t d;
   int32_t S;
-  int32_t pad;
+  int32_t ncomp;  // normal-mixture components I (mixture shocks), else 0
   int64_t T;
   const double *y;
   const float *y32;
@@ -38,7 +38,7 @@ struct WsLayout {
   size_t rsscols;  // [kMaxChunk] doubles
   size_t gather;   // [2d + S + 2][P] doubles
   size_t cum;      // [P] doubles (resample running sums)
-  size_t mpart;    // [kMomBlocks][256] doubles (moments)
+  size_t mpart;    // [kMomBlocks][kDMax^2] doubles (moments)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
   size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
   size_t fixed;    // bytes before wcols
@@ -54,11 +54,11 @@ constexpr size_t kSmallMh = 16;      // int32
 constexpr size_t kSmallNacc = 32;    // int64
 constexpr size_t kSmallRss = 64;     // double
 constexpr size_t kSmallRne = 72;     // double
-constexpr size_t kSmallMean = 256;   // double[16]
-constexpr size_t kSmallCov = 512;    // double[256]
-constexpr size_t kSmallHchol = 2560; // double[256]
-constexpr size_t kSmallStop = 4608;  // int64: first stop column
-constexpr size_t kSmallBytes = 8192;
+constexpr size_t kSmallMean = 256;    // double[32]
+constexpr size_t kSmallCov = 512;     // double[32 * 32]
+constexpr size_t kSmallHchol = 8704;  // double[32 * 32]
+constexpr size_t kSmallStop = 16896;  // int64: first stop column
+constexpr size_t kSmallBytes = 17152;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 

@@ -1,18 +1,15 @@
-// HIP kernels of the sequential posterior simulator for gfx950 (CDNA4) and
-// their host-side launchers.
+// Model-independent HIP kernels of the sequential posterior simulator for
+// gfx950 (CDNA4) and the host-side launchers, including the routing of the
+// model-templated launchers (model_kernels.h) to each model's table.
 //
-// Geometry: the likelihood kernels map one particle to one lane and launch
-// 64-thread blocks (one wave each), so a population spreads over as many
-// compute units as it has waves; observations are wave-uniform and reach the
-// lanes through scalar loads into SGPRs.  The bandwidth-shaped kernels
-// (reductions, resampling, gathers) use 256-thread blocks.  Every reduction
-// combines in a fixed order, so results do not depend on timing.
+// The bandwidth-shaped kernels (reductions, resampling, gathers) use
+// 256-thread blocks.  Every reduction combines in a fixed order, so results
+// do not depend on timing.
 #include <hip/hip_runtime.h>
 #include <math.h>
 
 #include <type_traits>
 
-#include "adjoint.h"
 #include "common.h"
 #include "launch.h"
 #include "model.h"
@@ -33,8 +30,6 @@ inline smc_status launch_status(const char *what) {
 
 template <typename T>
 __device__ __forceinline__ T *typed(void *p) { return reinterpret_cast<T *>(p); }
-template <typename T>
-__device__ __forceinline__ const T *typed(const void *p) { return reinterpret_cast<const T *>(p); }
 
 }  // namespace
 
@@ -66,83 +61,6 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
   if (n <= 0) return SMC_OK;
   hipLaunchKernelGGL(k_fill_i32, grid_for(n, kBlock), dim3(kBlock), 0, s, a, n, v);
   return launch_status("fill_i32");
-}
-
-// --------------------------------------------------------- prior (a1) ------
-template <class M>
-__global__ void __launch_bounds__(64) k_init(DevModel dm, int64_t P, uint64_t seed, uint64_t run,
-                                             double *theta, double *logprior, double *loglik,
-                                             void *state, double *logw) {
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  double th[M::D];
-  M::prior_draw(seed, run, (uint64_t)p, th);
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) theta[i * P + p] = th[i];
-  logprior[p] = M::logprior(th);
-  loglik[p] = 0.0;
-  logw[p] = 0.0;
-  using R = typename M::R;
-#pragma unroll
-  for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state)[k * P + p] = (R)0;
-}
-
-// ------------------------------------------------------------ C phase (a2) --
-// Speculative pass: from the committed state at t0, evaluate observations
-// t0+1..t1 and record the running log weight at every check date, without
-// committing anything.
-template <class M>
-__global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
-                                              const void *state, const double *logw, int64_t t0,
-                                              int64_t t1, int64_t check_every, int64_t t_max,
-                                              int32_t zero_first, double *W) {
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  double th[M::D];
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
-  const auto par = M::params(th);
-  R st[SR];
-#pragma unroll
-  for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
-  double lw = zero_first ? 0.0 : logw[p];
-  int64_t col = 0;
-  for (int64_t s = t0 + 1; s <= t1; ++s) {
-    double lp = Eval<M>::advance(dm, par, st, s - 1, s);
-    if (isnan(lp)) lp = -INFINITY;
-    lw += lp;
-    if (s % check_every == 0 || s == t_max) {
-      W[col * P + p] = lw;
-      ++col;
-    }
-  }
-}
-
-// Commit: advance from t0 to t1, adding the log densities to logw and loglik.
-template <class M>
-__global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
-                                                void *state, double *logw, double *loglik,
-                                                int64_t t0, int64_t t1, int32_t zero_first) {
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  constexpr int SS = StoredS<M>::value;
-  double th[M::D];
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
-  const auto par = M::params(th);
-  R st[SR];
-#pragma unroll
-  for (int k = 0; k < SR; ++k) st[k] = (k < SS) ? typed<R>(state)[k * P + p] : (R)0;
-  double lp = Eval<M>::advance(dm, par, st, t0, t1);
-  if (isnan(lp)) lp = -INFINITY;
-  logw[p] = (zero_first ? 0.0 : logw[p]) + lp;
-  loglik[p] += lp;
-#pragma unroll
-  for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
 }
 
 // RSS of each recorded column: (sum e)^2 / (P sum e^2), e = exp(w - max w).
@@ -339,65 +257,100 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
 
 // ----------------------------------------------- particle moments (a4) ----
 // Pass 1: every wave accumulates sum_p x_p x_p' on the matrix cores with
-// x_p = (theta_p - s, 1, 0, ...) padded to 16 (s = particle 0, a shift that
-// keeps the one-pass sums well conditioned; the constant slot d carries the
-// first moments and the count).  v_mfma_f64_16x16x4f64 takes four particles
-// per instruction.  Operand layout (measured on gfx950): lane l supplies
-// element (row l%16, k = l/16) of A and (k = l/16, col l%16) of B, so
-// A = B' = the 16x4 block of shifted particles; accumulator register r of
-// lane l holds element (4r + l/16, l%16) of the 16x16 result.  Each block
-// writes one partial matrix.
+// x_p = (theta_p - s, 1, 0, ...) padded to W = 16 or 32 (s = particle 0, a
+// shift that keeps the one-pass sums well conditioned; the constant slot d
+// carries the first moments and the count).  v_mfma_f64_16x16x4f64 takes four
+// particles per instruction.  Operand layout (measured on gfx950): lane l
+// supplies element (row l%16, k = l/16) of A and (k = l/16, col l%16) of B,
+// so A = B' = a 16x4 block of shifted particles; accumulator register r of
+// lane l holds element (4r + l/16, l%16) of the 16x16 result.  With W = 32
+// each lane holds rows i and 16 + i, and three products per step give the
+// (0,0), (1,0) and (1,1) tiles of the symmetric result.  Each block writes
+// one W x W partial matrix.
+template <int W>
 __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_t P, int32_t d,
                                                      int64_t chunk, double *part) {
-  __shared__ double red[4][256];
+  constexpr int NT = W / 16;
+  constexpr int NA = NT == 1 ? 1 : 3;  // tiles accumulated
+  __shared__ double red[4][W * W];
   typedef double double4v __attribute__((ext_vector_type(4)));
   const int tid = threadIdx.x, wv = tid >> 6, l = tid & 63;
   const int i = l & 15, k = l >> 4;
   const int64_t p0 = ((int64_t)blockIdx.x * 4 + wv) * chunk;
   const int64_t p1 = min(P, p0 + chunk);
-  const int ir = i < d ? i : 0;  // a valid row to load from when i >= d
-  const double si = theta[(int64_t)ir * P];
-  double4v acc = {0.0, 0.0, 0.0, 0.0};
+  int ir[NT];
+  double si[NT];
+#pragma unroll
+  for (int t = 0; t < NT; ++t) {
+    ir[t] = 16 * t + i < d ? 16 * t + i : 0;  // a valid row to load from
+    si[t] = theta[(int64_t)ir[t] * P];
+  }
+  double4v acc[NA];
+#pragma unroll
+  for (int a = 0; a < NA; ++a) acc[a] = double4v{0.0, 0.0, 0.0, 0.0};
   // Eight MFMA steps per batch with all loads issued first (addresses are
   // clamped into the wave's range and masked afterwards).
   for (int64_t q0 = p0; q0 < p1; q0 += 32) {
-    double x[8];
+    double x[NT][8];
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t p = q0 + 4 * u + k;
       const int64_t pc = p < p1 ? p : p1 - 1;
-      x[u] = theta[(int64_t)ir * P + pc];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) x[t][u] = theta[(int64_t)ir[t] * P + pc];
     }
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t p = q0 + 4 * u + k;
-      const double v = (i < d) ? x[u] - si : (i == d ? 1.0 : 0.0);
-      const double xm = p < p1 ? v : 0.0;
-      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(xm, xm, acc, 0, 0, 0);
+      double xm[NT];
+#pragma unroll
+      for (int t = 0; t < NT; ++t) {
+        const int row = 16 * t + i;
+        const double v = (row < d) ? x[t][u] - si[t] : (row == d ? 1.0 : 0.0);
+        xm[t] = p < p1 ? v : 0.0;
+      }
+      acc[0] = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[0], xm[0], acc[0], 0, 0, 0);
+      if constexpr (NT == 2) {
+        acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[1], xm[0], acc[1], 0, 0, 0);
+        acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[1], xm[1], acc[2], 0, 0, 0);
+      }
     }
   }
 #pragma unroll
-  for (int r = 0; r < 4; ++r) red[wv][(4 * r + k) * 16 + i] = acc[r];
+  for (int r = 0; r < 4; ++r) {
+    const int row = 4 * r + k;
+    red[wv][row * W + i] = acc[0][r];
+    if constexpr (NT == 2) {
+      red[wv][(16 + row) * W + i] = acc[1][r];   // tile (1,0)
+      red[wv][i * W + 16 + row] = acc[1][r];     // its mirror (0,1)
+      red[wv][(16 + row) * W + 16 + i] = acc[2][r];
+    }
+  }
   __syncthreads();
-  part[blockIdx.x * 256 + tid] = (red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]);
+  for (int e = tid; e < W * W; e += 256)
+    part[(int64_t)blockIdx.x * W * W + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
 // Pass 2 (one block): add the partial matrices in block order, optionally
 // apply the step-size rule to mh, form the mean and V (divisor P - 1),
 // factor V = L L' and write h L.  A variance that is not positive definite
 // raises the flag and yields h L = 0.
+template <int W>
 __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
-  __shared__ double Ms[256];
-  __shared__ double Ls[kDMax * kDMax];
+  __shared__ double Ms[W * W];
+  __shared__ double Ls[W * W];
   __shared__ double sh_h;
   __shared__ int sh_ok;
   const int tid = threadIdx.x;
   const int d = a.d;
   const int64_t P = a.P;
-  double sum = 0.0;
+  for (int e = tid; e < W * W; e += 256) {
+    double sum = 0.0;
 #pragma unroll 16
-  for (int b = 0; b < nb; ++b) sum += a.part[b * 256 + tid];
-  Ms[tid] = sum;
+    for (int b = 0; b < nb; ++b) sum += a.part[(int64_t)b * W * W + e];
+    Ms[e] = sum;
+    Ls[e] = 0.0;
+  }
   if (tid == 0) {
     int32_t m = *a.mh;
     if (a.mh_reset > 0) {
@@ -412,108 +365,47 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
   }
   __syncthreads();
   const double invP = 1.0 / (double)P;
-  const int r = tid >> 4, c = tid & 15;
-  double v = 0.0;
-  if (r < d && c < d) {
-    v = (Ms[r * 16 + c] - Ms[r * 16 + d] * Ms[c * 16 + d] * invP) / (double)(P - 1);
-    if (a.cov_out) a.cov_out[r * d + c] = v;
+  double v[W * W / 256];
+#pragma unroll
+  for (int q = 0; q < W * W / 256; ++q) {
+    const int e = tid + 256 * q, r = e / W, c = e % W;
+    v[q] = 0.0;
+    if (r < d && c < d) {
+      v[q] = (Ms[r * W + c] - Ms[r * W + d] * Ms[c * W + d] * invP) / (double)(P - 1);
+      if (a.cov_out) a.cov_out[r * d + c] = v[q];
+    }
   }
-  if (a.mean_out && tid < d) a.mean_out[tid] = a.theta[(int64_t)tid * P] + Ms[tid * 16 + d] * invP;
+  if (a.mean_out && tid < d) a.mean_out[tid] = a.theta[(int64_t)tid * P] + Ms[tid * W + d] * invP;
   __syncthreads();
-  if (r < d && c < d) Ms[r * 16 + c] = v;
-  Ls[tid] = 0.0;
+#pragma unroll
+  for (int q = 0; q < W * W / 256; ++q) {
+    const int e = tid + 256 * q, r = e / W, c = e % W;
+    if (r < d && c < d) Ms[e] = v[q];
+  }
   __syncthreads();
   // Cholesky, column by column: the diagonal by one thread, the column below
   // it by one thread per row.
   for (int col = 0; col < d; ++col) {
     if (tid == 0) {
-      double q = Ms[col * 16 + col];
-      for (int t = 0; t < col; ++t) q -= Ls[col * kDMax + t] * Ls[col * kDMax + t];
-      if (q > 0.0 && sh_ok) Ls[col * kDMax + col] = sqrt(q);
+      double q = Ms[col * W + col];
+      for (int t = 0; t < col; ++t) q -= Ls[col * W + t] * Ls[col * W + t];
+      if (q > 0.0 && sh_ok) Ls[col * W + col] = sqrt(q);
       else sh_ok = 0;
     }
     __syncthreads();
     if (sh_ok && tid > col && tid < d) {
-      double q = Ms[tid * 16 + col];
-      for (int t = 0; t < col; ++t) q -= Ls[tid * kDMax + t] * Ls[col * kDMax + t];
-      Ls[tid * kDMax + col] = q / Ls[col * kDMax + col];
+      double q = Ms[tid * W + col];
+      for (int t = 0; t < col; ++t) q -= Ls[tid * W + t] * Ls[col * W + t];
+      Ls[tid * W + col] = q / Ls[col * W + col];
     }
     __syncthreads();
   }
-  if (r < d && c < d) a.hchol[r * d + c] = (sh_ok && c <= r) ? sh_h * Ls[r * kDMax + c] : 0.0;
-  if (tid == 0 && !sh_ok) atomicOr(a.flags, SMC_FLAG_NOT_PD);
-}
-
-// ------------------------------------------------------------ M phase (a5) --
-template <class M>
-__global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
-                                                  double *logprior, double *loglik, void *state,
-                                                  const double *__restrict__ hchol, uint64_t seed,
-                                                  uint64_t run, uint64_t cycle, uint64_t iter,
-                                                  unsigned long long *n_accept, uint8_t *accepted) {
-  constexpr int D = M::D;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  constexpr int SS = StoredS<M>::value;
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  int acc = 0;
-  if (p < P) {
-    double th[D], z[D], pr[D];
 #pragma unroll
-    for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
-    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double s = 0.0;
-#pragma unroll
-      for (int k = 0; k <= i; ++k) s = fma(hchol[i * D + k], z[k], s);
-      pr[i] = th[i] + s;
-    }
-    const double lp1 = M::logprior(pr);
-    R st[SR];
-#pragma unroll
-    for (int k = 0; k < SR; ++k) st[k] = (R)0;
-    double ll1 = -INFINITY;
-    if (lp1 > -INFINITY) {
-      const auto par = M::params(pr);
-      ll1 = Eval<M>::advance(dm, par, st, 0, t);
-      const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]);
-      const U64x4 w = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
-      acc = (log(u01_oo(w.x0)) < delta) ? 1 : 0;
-    }
-    if (acc) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) theta[i * P + p] = pr[i];
-      logprior[p] = lp1;
-      loglik[p] = ll1;
-#pragma unroll
-      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
-    }
-    if (accepted) accepted[p] = (uint8_t)acc;
+  for (int q = 0; q < W * W / 256; ++q) {
+    const int e = tid + 256 * q, r = e / W, c = e % W;
+    if (r < d && c < d) a.hchol[r * d + c] = (sh_ok && c <= r) ? sh_h * Ls[r * W + c] : 0.0;
   }
-  const unsigned long long mask = __ballot(acc);
-  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
-}
-
-// ------------------------------------------------- standalone likelihood --
-template <class M>
-__global__ void __launch_bounds__(64) k_loglik(DevModel dm, int64_t P, const double *theta,
-                                               int64_t t, double *out, void *state_out) {
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  double th[M::D];
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
-  const auto par = M::params(th);
-  R st[SR];
-#pragma unroll
-  for (int k = 0; k < SR; ++k) st[k] = (R)0;
-  out[p] = Eval<M>::advance(dm, par, st, 0, t);
-  if (state_out)
-#pragma unroll
-    for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state_out)[k * P + p] = st[k];
+  if (tid == 0 && !sh_ok) atomicOr(a.flags, SMC_FLAG_NOT_PD);
 }
 
 // ------------------------------------------------ step size, RNE, log-ML --
@@ -608,225 +500,90 @@ __global__ void k_log_ml(int32_t L, int32_t J, const double *g, double *out) {
   out[2] = lt;
 }
 
-// ------------------------------------- gradients and the Langevin step (a8) --
-template <class M>
-struct IsLinreg : std::false_type {};
-template <int NREG>
-struct IsLinreg<Linreg<NREG>> : std::true_type {};
-
-// Value of log p(y_{1:t} | theta) with its gradient added (times scale) to
-// g, and the state at t.  ckpt: this call's checkpoint area; lds: this lane's
-// column of the block's LDS buffer.
-template <class M>
-__device__ __forceinline__ double ll_and_grad(const DevModel &dm, const double *th, int64_t t,
-                                              void *ckpt, int64_t P, int64_t p, void *lds,
-                                              double scale, double *g,
-                                              typename M::R (&st)[Eval<M>::SR]) {
-  if constexpr (IsLinreg<M>::value) {
-    st[0] = 0.0;
-    return Adjoint<M>::value_and_grad(dm, th, t, scale, g);
-  } else {
-    using R = typename M::R;
-    const auto par = M::params(th);
-    return Adjoint<M>::value_and_grad(par, th, t, M::ydata(dm), typed<R>(ckpt), P, p,
-                                      typed<R>(lds) + threadIdx.x, scale, g, st);
-  }
-}
-
-template <class M>
-constexpr size_t lds_bytes_of() {
-  if constexpr (IsLinreg<M>::value) return 0;
-  else return (size_t)Adjoint<M>::kLdsPerLane * 64 * sizeof(typename M::R);
-}
-
-template <class M>
-__global__ void __launch_bounds__(64) k_loglik_backward(DevModel dm, int64_t P, const double *theta,
-                                                        int64_t t, const double *dloglik,
-                                                        double *dtheta, void *ckpt) {
-  extern __shared__ double lds_dyn[];
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  double th[M::D], g[M::D];
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) {
-    th[i] = theta[i * P + p];
-    g[i] = 0.0;
-  }
-  typename M::R st[Eval<M>::SR];
-  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, dloglik[p], g, st);
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) dtheta[i * P + p] = g[i];
-}
-
-// grad = d/dtheta [log p(theta) + log p(y_{1:t} | theta)] for every particle.
-template <class M>
-__global__ void __launch_bounds__(64) k_grad_post(DevModel dm, int64_t P, const double *theta,
-                                                  int64_t t, double *grad, void *ckpt) {
-  extern __shared__ double lds_dyn[];
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
-  double th[M::D], g[M::D];
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
-  PriorGradOf<M>::run(th, g);
-  typename M::R st[Eval<M>::SR];
-  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, 1.0, g, st);
-#pragma unroll
-  for (int i = 0; i < M::D; ++i) grad[i * P + p] = g[i];
-}
-
-// One preconditioned Langevin (MALA) Metropolis iteration: proposal mean
-// theta + (1/2)(hL)(hL)' grad, noise hL z; the acceptance test adds
-// log q(theta | theta') - log q(theta' | theta) = -|w|^2/2 + |z|^2/2 with
-// (hL) w = theta - theta' - (1/2)(hL)(hL)' grad'.
-template <class M>
-__global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int64_t t, double *theta,
-                                                    double *logprior, double *loglik, void *state,
-                                                    double *grad, const double *__restrict__ hchol,
-                                                    uint64_t seed, uint64_t run, uint64_t cycle,
-                                                    uint64_t iter, unsigned long long *n_accept,
-                                                    uint8_t *accepted, void *ckpt) {
-  extern __shared__ double lds_dyn[];
-  constexpr int D = M::D;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  constexpr int SS = StoredS<M>::value;
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  int acc = 0;
-  if (p < P) {
-    double th[D], z[D], pr[D], g0[D], g1[D], u[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      th[i] = theta[i * P + p];
-      g0[i] = grad[i * P + p];
-    }
-    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
-    // u = (hL)' g0
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g0[i], s);
-      u[k] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double dr = 0.0, st = 0.0;
-#pragma unroll
-      for (int k = 0; k <= i; ++k) {
-        dr = fma(hchol[i * D + k], u[k], dr);
-        st = fma(hchol[i * D + k], z[k], st);
-      }
-      pr[i] = th[i] + 0.5 * dr + st;
-    }
-    const double lp1 = M::logprior(pr);
-    R stv[SR];
-#pragma unroll
-    for (int k = 0; k < SR; ++k) stv[k] = (R)0;
-    double ll1 = -INFINITY;
-    if (lp1 > -INFINITY) {
-      PriorGradOf<M>::run(pr, g1);
-      ll1 = ll_and_grad<M>(dm, pr, t, ckpt, P, p, lds_dyn, 1.0, g1, stv);
-      // reverse move
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g1[i], s);
-        u[k] = s;
-      }
-      double ww = 0.0, zz = 0.0, w[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double dr = 0.0;
-#pragma unroll
-        for (int k = 0; k <= i; ++k) dr = fma(hchol[i * D + k], u[k], dr);
-        double a = th[i] - pr[i] - 0.5 * dr;
-#pragma unroll
-        for (int k = 0; k < i; ++k) a = fma(-hchol[i * D + k], w[k], a);
-        w[i] = a / hchol[i * D + i];
-        ww = fma(w[i], w[i], ww);
-        zz = fma(z[i], z[i], zz);
-      }
-      const double delta =
-          (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
-      const U64x4 wr = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
-      acc = (log(u01_oo(wr.x0)) < delta) ? 1 : 0;
-    }
-    if (acc) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        theta[i * P + p] = pr[i];
-        grad[i * P + p] = g1[i];
-      }
-      logprior[p] = lp1;
-      loglik[p] = ll1;
-#pragma unroll
-      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = stv[k];
-    }
-    if (accepted) accepted[p] = (uint8_t)acc;
-  }
-  const unsigned long long mask = __ballot(acc);
-  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
-}
-
 // ============================================================ launchers ====
 
-template <class F>
-smc_status dispatch(const DevModel &m, F &&f) {
-  if (m.kind == SMC_MODEL_LINREG) {
-    switch (m.nreg) {
-      case 1: return f(Tag<Linreg<1>>{});
-      case 2: return f(Tag<Linreg<2>>{});
-      case 3: return f(Tag<Linreg<3>>{});
-      case 4: return f(Tag<Linreg<4>>{});
-      default: return set_error(SMC_E_UNSUPPORTED, "regression with %d regressors", m.nreg);
-    }
-  }
-  const bool t = m.shock == SMC_SHOCK_STUDENT_T;
-  if (m.prec == SMC_FP64) {
-    if (m.K == 1) return t ? f(Tag<Egarch<1, 1, double>>{}) : f(Tag<Egarch<1, 0, double>>{});
-    if (m.K == 2) return t ? f(Tag<Egarch<2, 1, double>>{}) : f(Tag<Egarch<2, 0, double>>{});
-  } else {
-    if (m.K == 1) return t ? f(Tag<Egarch<1, 1, float>>{}) : f(Tag<Egarch<1, 0, float>>{});
-    if (m.K == 2) return t ? f(Tag<Egarch<2, 1, float>>{}) : f(Tag<Egarch<2, 0, float>>{});
-  }
-  return set_error(SMC_E_UNSUPPORTED, "EGARCH with K=%d", m.K);
+// ---------------------------------------------- model-templated launchers --
+const ModelOps *ops_for(const DevModel &m) {
+  const ModelOps *o = nullptr;
+  if (m.kind == SMC_MODEL_LINREG) o = ops_linreg(m);
+  else if (m.shock != SMC_SHOCK_MIXTURE) o = ops_egarch(m);
+  else if (m.prec == SMC_FP64) o = ops_mixture64(m);
+  else o = ops_mixture32(m);
+  if (!o)
+    set_error(SMC_E_UNSUPPORTED, "model kind %d, K=%d, shock %d, I=%d, nreg %d", m.kind, m.K,
+              m.shock, m.ncomp, m.nreg);
+  return o;
 }
 
 smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
                        double *logprior, double *loglik, void *state, double *logw,
                        hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_init<M>, grid_for(P, 64), dim3(64), 0, s, m, P, seed, run, theta,
-                       logprior, loglik, state, logw);
-    return launch_status("init_from_prior");
-  });
+  const ModelOps *o = ops_for(m);
+  return o ? o->init(m, P, seed, run, theta, logprior, loglik, state, logw, s) : SMC_E_UNSUPPORTED;
 }
 
 smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                         const double *logw, int64_t t0, int64_t t1, int64_t check_every,
                         int64_t t_max, bool zero_first, double *W, hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_cscan<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw, t0,
-                       t1, check_every, t_max, (int32_t)zero_first, W);
-    return launch_status("correct/scan");
-  });
+  const ModelOps *o = ops_for(m);
+  return o ? o->cscan(m, P, theta, state, logw, t0, t1, check_every, t_max, zero_first, W, s)
+           : SMC_E_UNSUPPORTED;
 }
 
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
                           double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
                           hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
-                       loglik, t0, t1, (int32_t)zero_first);
-    return launch_status("correct/commit");
-  });
+  const ModelOps *o = ops_for(m);
+  return o ? o->ccommit(m, P, theta, state, logw, loglik, t0, t1, zero_first, s)
+           : SMC_E_UNSUPPORTED;
 }
 
+smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
+                            double *logprior, double *loglik, void *state, const double *hchol,
+                            uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
+                            int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->mutate_rw(m, P, t, theta, logprior, loglik, state, hchol, seed, run, cycle, iter,
+                          n_accept, accepted, s)
+           : SMC_E_UNSUPPORTED;
+}
+
+smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                         double *out, void *state_out, hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->loglik(m, P, theta, t, out, state_out, s) : SMC_E_UNSUPPORTED;
+}
+
+size_t adjoint_ckpt_bytes(const DevModel &m, int64_t P, int64_t t) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->ckpt_bytes(m, P, t) : 0;
+}
+
+smc_status launch_loglik_backward(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                                  const double *dloglik, double *dtheta, void *ckpt,
+                                  hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->loglik_backward(m, P, theta, t, dloglik, dtheta, ckpt, s) : SMC_E_UNSUPPORTED;
+}
+
+smc_status launch_grad_post(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                            double *grad, void *ckpt, hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->grad_post(m, P, theta, t, grad, ckpt, s) : SMC_E_UNSUPPORTED;
+}
+
+smc_status launch_mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
+                              double *logprior, double *loglik, void *state, double *grad,
+                              const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
+                              uint64_t iter, int64_t *n_accept, uint8_t *accepted, void *ckpt,
+                              hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->mutate_mala(m, P, t, theta, logprior, loglik, state, grad, hchol, seed, run,
+                            cycle, iter, n_accept, accepted, ckpt, s)
+           : SMC_E_UNSUPPORTED;
+}
+
+// ------------------------------------------------- model-independent ones --
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s) {
   if (ncols <= 0) return SMC_OK;
@@ -854,7 +611,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
 }
 
 smc_status launch_moments(const MomArgs &a, hipStream_t s) {
-  if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < 16");
+  if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < %d", kDMax);
   // About 64 particles per wave (two load batches); at most kMomBlocks
   // blocks of four waves.
   const int64_t waves = std::max<int64_t>(1, (a.P + 63) / 64);
@@ -862,35 +619,18 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   int64_t chunk = (a.P + 4 * nb - 1) / (4 * nb);
   chunk = ((chunk + 31) / 32) * 32;
   nb = (a.P + 4 * chunk - 1) / (4 * chunk);
-  hipLaunchKernelGGL(k_mom_partial, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
-                     chunk, a.part);
+  if (a.d + 1 <= 16) {
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
+                       a.d, chunk, a.part);
+  } else {
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
+                       a.d, chunk, a.part);
+  }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
-  hipLaunchKernelGGL(k_mom_final, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
+  if (a.d + 1 <= 16) hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
+  else hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
   return launch_status("particle_moments/final");
-}
-
-smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
-                            double *logprior, double *loglik, void *state, const double *hchol,
-                            uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
-                            int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta, logprior,
-                       loglik, state, hchol, seed, run, cycle, iter,
-                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
-    return launch_status("mutate");
-  });
-}
-
-smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
-                         double *out, void *state_out, hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_loglik<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, t, out,
-                       state_out);
-    return launch_status("loglik");
-  });
 }
 
 smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,
@@ -912,55 +652,6 @@ smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, doub
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s) {
   hipLaunchKernelGGL(k_log_ml, dim3(1), dim3(64), 0, s, L, J, g, out);
   return launch_status("log_ml");
-}
-
-size_t adjoint_ckpt_bytes(const DevModel &m, int64_t P, int64_t t) {
-  size_t out = 0;
-  (void)dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    if constexpr (!IsLinreg<M>::value) {
-      using A = Adjoint<M>;
-      const int64_t ns = (t + A::SEG - 1) / A::SEG;
-      out = (size_t)ns * M::K * (size_t)P * sizeof(typename M::R);
-    }
-    return SMC_OK;
-  });
-  return out;
-}
-
-smc_status launch_loglik_backward(const DevModel &m, int64_t P, const double *theta, int64_t t,
-                                  const double *dloglik, double *dtheta, void *ckpt,
-                                  hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_loglik_backward<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m,
-                       P, theta, t, dloglik, dtheta, ckpt);
-    return launch_status("loglik_backward");
-  });
-}
-
-smc_status launch_grad_post(const DevModel &m, int64_t P, const double *theta, int64_t t,
-                            double *grad, void *ckpt, hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_grad_post<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P,
-                       theta, t, grad, ckpt);
-    return launch_status("posterior_grad");
-  });
-}
-
-smc_status launch_mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
-                              double *logprior, double *loglik, void *state, double *grad,
-                              const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
-                              uint64_t iter, int64_t *n_accept, uint8_t *accepted, void *ckpt,
-                              hipStream_t s) {
-  return dispatch(m, [&](auto tag) {
-    using M = typename decltype(tag)::type;
-    hipLaunchKernelGGL(k_mutate_mala<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P, t,
-                       theta, logprior, loglik, state, grad, hchol, seed, run, cycle, iter,
-                       reinterpret_cast<unsigned long long *>(n_accept), accepted, ckpt);
-    return launch_status("mutate/mala");
-  });
 }
 
 }  // namespace smc

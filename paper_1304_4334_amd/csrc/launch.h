@@ -24,6 +24,37 @@ smc_status fill_f64(double *a, int64_t n, double v, hipStream_t s);
 smc_status fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t s);
 smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);
 
+// Launchers of the kernels templated on the model, one table per model type
+// (model_kernels.h); the family tables below return NULL for a description
+// they do not cover.
+struct ModelOps {
+  smc_status (*init)(const DevModel &, int64_t, uint64_t, uint64_t, double *, double *, double *,
+                     void *, double *, hipStream_t);
+  smc_status (*cscan)(const DevModel &, int64_t, const double *, const void *, const double *,
+                      int64_t, int64_t, int64_t, int64_t, bool, double *, hipStream_t);
+  smc_status (*ccommit)(const DevModel &, int64_t, const double *, void *, double *, double *,
+                        int64_t, int64_t, bool, hipStream_t);
+  smc_status (*mutate_rw)(const DevModel &, int64_t, int64_t, double *, double *, double *,
+                          void *, const double *, uint64_t, uint64_t, uint64_t, uint64_t,
+                          int64_t *, uint8_t *, hipStream_t);
+  smc_status (*loglik)(const DevModel &, int64_t, const double *, int64_t, double *, void *,
+                       hipStream_t);
+  size_t (*ckpt_bytes)(const DevModel &, int64_t, int64_t);
+  smc_status (*loglik_backward)(const DevModel &, int64_t, const double *, int64_t,
+                                const double *, double *, void *, hipStream_t);
+  smc_status (*grad_post)(const DevModel &, int64_t, const double *, int64_t, double *, void *,
+                          hipStream_t);
+  smc_status (*mutate_mala)(const DevModel &, int64_t, int64_t, double *, double *, double *,
+                            void *, double *, const double *, uint64_t, uint64_t, uint64_t,
+                            uint64_t, int64_t *, uint8_t *, void *, hipStream_t);
+};
+const ModelOps *ops_linreg(const DevModel &m);     // ops_linreg.hip
+const ModelOps *ops_egarch(const DevModel &m);     // ops_egarch.hip: Gaussian, Student-t
+const ModelOps *ops_mixture64(const DevModel &m);  // ops_mixture64.hip
+const ModelOps *ops_mixture32(const DevModel &m);  // ops_mixture32.hip
+// The table for a model description, or NULL (error recorded) if none.
+const ModelOps *ops_for(const DevModel &m);
+
 smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
                        double *logprior, double *loglik, void *state, double *logw,
                        hipStream_t s);
@@ -51,7 +82,7 @@ struct MomArgs {
   int64_t P;
   int32_t d;
   int32_t target_permille;  // step-size rule target when prev_nacc is given
-  double *part;             // [kMomBlocks][256] partial sums (workspace)
+  double *part;             // [kMomBlocks][W*W] partial sums, W = 16 or 32 (workspace)
   int32_t *mh;              // step size in tenths (device)
   const int64_t *prev_nacc; // accepts of the previous iteration, or NULL
   int32_t mh_reset;         // > 0: set mh to this value first

@@ -24,6 +24,7 @@ namespace smc {
 constexpr double kLog2Pi = 1.8378770664093453390819;
 constexpr double kSqrt2OverPi = 0.79788456080286535588;
 constexpr double kLn2 = 0.69314718055994530942;
+constexpr double kLog2e = 1.4426950408889634074;
 constexpr int kUnroll = 8;
 
 // 2^x.  FP32: the hardware base-2 exponential.  FP64: x = n + f with
@@ -51,6 +52,10 @@ __device__ __forceinline__ double exp2_fast(double x) {
   return __builtin_ldexp(fma(r1, f8, r0), (int)n);
 }
 
+// log2 x.  FP32: the hardware base-2 logarithm; FP64: the library's.
+__device__ __forceinline__ float log2_fast(float x) { return __builtin_amdgcn_logf(x); }
+__device__ __forceinline__ double log2_fast(double x) { return log2(x); }
+
 // Student-t kernel term log(1 + e^2/(nu - 2)): FP64 log1p; FP32 log2 (scaled
 // by ln 2 at the end).
 __device__ __forceinline__ double t_term(double e2, double inu2) { return log1p(e2 * inu2); }
@@ -67,15 +72,26 @@ __device__ __forceinline__ double t_scale<float>() { return kLn2; }
 __device__ __forceinline__ double normal_logpdf_std(double z) { return -0.5 * kLog2Pi - 0.5 * z * z; }
 
 // ---------------------------------------------------------------- EGARCH --
-// theta = (th1, th2, th3_1..K, th4_1..K, th5_1..K [, th9 = log(nu - 2)]),
+// theta = (th1, th2, th3_1..K, th4_1..K, th5_1..K, then th9 = log(nu - 2) for
+// Student-t shocks or th6_1..I, th7_1..I, th8_1..I for normal-mixture shocks),
 // mu_Y = th1/1000, sigma_Y = exp(th2), alpha_k = tanh(th3k), beta_k = exp(th4k),
-// gamma_k = th5k, nu = 2 + exp(th9) (Table 1; nu is an extension).
-template <int K_, int SHOCK_, typename R_>
+// gamma_k = th5k (Table 1), nu = 2 + exp(th9) (an extension), and the mixture
+// from p*_i = tanh(th6i) + 1, mu*_i = th7i, sigma*_i = exp(th8i) through the
+// normalisation of eqs EGARCH_tran1/2.
+constexpr double kMixTrunc = -3.0;  // Table 1: th8i truncated below here
+// log P(Z >= -3) for a standard normal Z (correctly rounded).
+constexpr double kLogMixMass = -0x1.621b527ca016fp-10;
+
+template <int K_, int SHOCK_, typename R_, int I_ = 1>
 struct Egarch {
   static constexpr int K = K_;
+  static constexpr int I = I_;
   static constexpr bool kT = (SHOCK_ == SMC_SHOCK_STUDENT_T);
-  static constexpr int D = 2 + 3 * K + (kT ? 1 : 0);
+  static constexpr bool kMix = (SHOCK_ == SMC_SHOCK_MIXTURE);
+  static_assert(!kMix || (I_ >= 2 && I_ <= 4), "mixtures of 2..4 components");
+  static constexpr int D = 2 + 3 * K + (kT ? 1 : 0) + (kMix ? 3 * I : 0);
   static constexpr int S = K + 1;
+  static constexpr int kNM = kMix ? I : 1;  // component arrays (unused if no mixture)
   using R = R_;
   using Y = R_;
 
@@ -87,10 +103,18 @@ struct Egarch {
   //             + kappa (beta_k |z_s| + gamma_k z_s) E_s,
   // whose loop-carried chain is one exp2 and one fma; z_s and the bracket do
   // not depend on the recursion.  log h_s = log sigma_Y - ln2 sum_k w_ks.
+  //
+  // Mixture shocks: log2 of p_i phi(eps; mu_i, sigma_i^2) sqrt(2 pi) is
+  // x_i = lw_i + nb_i (eps - mu_i)^2 with lw_i = log2(p_i / sigma_i) and
+  // nb_i = -log2(e) / (2 sigma_i^2); the density's log2 is
+  // m + log2 sum_i 2^(x_i - m), m = max_i x_i.  The sums are multiplied
+  // over each block of observations (each lies in [1, I]) and one log2 is
+  // taken per block.
   struct Par {
     R a[K], c0[K], kb[K], kg[K];  // alpha, -kappa beta c, kappa beta, kappa gamma
     R isig, mus;                  // 1/sigma_Y, mu_Y/sigma_Y
     R inu2;                       // 1/(nu - 2)
+    R lw[kNM], nb[kNM], mu[kNM];  // mixture components (see above)
     double lsig;                  // log sigma_Y
     double cst;                   // per-observation log-density constant
     double hnu1;                  // (nu + 1)/2
@@ -121,6 +145,36 @@ struct Egarch {
       p.inu2 = (R)exp(-th[2 + 3 * K]);
       p.hnu1 = 0.5 * (nu + 1.0);
       p.cst = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * (nu - 2.0));
+    } else if constexpr (kMix) {
+      constexpr int b = 2 + 3 * K;
+      double pw[I], mc[I], sg[I], ps = 0.0, pm = 0.0, q = 0.0;
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        pw[i] = tanh(th[b + i]) + 1.0;
+        ps += pw[i];
+      }
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        pw[i] /= ps;
+        pm += pw[i] * th[b + I + i];
+      }
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        mc[i] = th[b + I + i] - pm;
+        sg[i] = exp(th[b + 2 * I + i]);
+        q += pw[i] * (mc[i] * mc[i] + sg[i] * sg[i]);
+      }
+      const double c = 1.0 / sqrt(q);
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const double si = c * sg[i];
+        p.mu[i] = (R)(c * mc[i]);
+        p.lw[i] = (R)(log2(pw[i]) - log2(si));
+        p.nb[i] = (R)(-kLog2e / (2.0 * si * si));
+      }
+      p.inu2 = (R)0;
+      p.hnu1 = 0.5;
+      p.cst = -0.5 * kLog2Pi;
     } else {
       p.inu2 = (R)0;
       p.hnu1 = 0.5;
@@ -141,7 +195,8 @@ struct Egarch {
     else if (i < 2 + K) mean = 0x1.d4ef968880dd4p+0;
     else if (i < 2 + 2 * K) mean = -0x1.26bb1bbb55515p+1;
     else if (i < 2 + 3 * K) { mean = 0.0; sd = 0.2; lsd = -0x1.9c041f7ed8d33p+0; }
-    else mean = 0x1.26bb1bbb55516p+1;
+    else if (kT) mean = 0x1.26bb1bbb55516p+1;
+    else mean = 0.0;  // th6i, th7i, th8i
   }
 
   __device__ static double logprior(const double *th) {
@@ -152,6 +207,13 @@ struct Egarch {
       prior_moments(i, m, sd, lsd);
       const double z = (th[i] - m) / sd;
       lp += normal_logpdf_std(z) - lsd;
+    }
+    if constexpr (kMix) {
+#pragma unroll
+      for (int i = 2 + 3 * K + 2 * I; i < D; ++i) {
+        if (th[i] < kMixTrunc) return -INFINITY;
+        lp -= kLogMixMass;
+      }
     }
     return lp;
   }
@@ -165,6 +227,18 @@ struct Egarch {
       prior_moments(i, m, sd, lsd);
       th[i] = m + sd * z[i];
     }
+    if constexpr (kMix) {
+      // Truncated th8i by rejection: attempt a redraws the normal vector on
+      // counter (p, 0, a, PRIOR | block) and takes this parameter's entry;
+      // after 32 failures the truncation point itself.
+      for (int i = 2 + 3 * K + 2 * I; i < D; ++i) {
+        for (uint64_t a = 1; th[i] < kMixTrunc && a <= 32; ++a) {
+          normals<D>(seed, run, p, 0, a, kPrior, z, D);
+          th[i] = z[i];
+        }
+        if (th[i] < kMixTrunc) th[i] = kMixTrunc;
+      }
+    }
   }
 
   // Loop state: the exponents w_k of the observation about to be processed
@@ -175,9 +249,11 @@ struct Egarch {
   };
 
   // One observation: returns the exponent sum used (for log h), adds eps^2
-  // (Gaussian) or the Student-t term to ae, reports E and z, and advances r
-  // to the next observation's exponents.
-  __device__ __forceinline__ static R step(const Par &p, R y, Run &r, R &ae, R &E_out, R &z_out) {
+  // (Gaussian), the Student-t term or the mixture's largest log2 term m to
+  // ae (and multiplies the mixture's sum of 2^(x_i - m) into pm), reports E
+  // and z, and advances r to the next observation's exponents.
+  __device__ __forceinline__ static R step(const Par &p, R y, Run &r, R &ae, R &pm, R &E_out,
+                                           R &z_out) {
     const R sw = r.sw;
     const R E = exp2_fast(sw);
     const R z = fma(y, p.isig, -p.mus);
@@ -197,8 +273,26 @@ struct Egarch {
     }
     r.sw = (K > 1) ? fma(kk, E, AA) : r.w[0];
     const R e = z * E;
-    if constexpr (kT) ae += t_term(e * e, p.inu2);
-    else ae = fma(e, e, ae);
+    if constexpr (kT) {
+      ae += t_term(e * e, p.inu2);
+    } else if constexpr (kMix) {
+      R x[I];
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        const R dd = e - p.mu[i];
+        x[i] = fma(p.nb[i] * dd, dd, p.lw[i]);
+      }
+      R mx = x[0];
+#pragma unroll
+      for (int i = 1; i < I; ++i) mx = fmax(mx, x[i]);
+      R sm = exp2_fast(x[0] - mx);
+#pragma unroll
+      for (int i = 1; i < I; ++i) sm += exp2_fast(x[i] - mx);
+      ae += mx;
+      pm *= sm;
+    } else {
+      ae = fma(e, e, ae);
+    }
     E_out = E;
     z_out = z;
     return sw;
@@ -235,33 +329,37 @@ struct Egarch {
       R yb[kUnroll];
 #pragma unroll
       for (int i = 0; i < kUnroll; ++i) yb[i] = yp[i];
-      R av, ae = (R)0, Ed, zd;
-      av = step(p, yb[0], r, ae, Ed, zd);
+      R av, ae = (R)0, pm = (R)1, Ed, zd;
+      av = step(p, yb[0], r, ae, pm, Ed, zd);
 #pragma unroll
-      for (int i = 1; i < kUnroll; ++i) av += step(p, yb[i], r, ae, Ed, zd);
+      for (int i = 1; i < kUnroll; ++i) av += step(p, yb[i], r, ae, pm, Ed, zd);
       sv += (double)av;
       se += (double)ae;
+      if constexpr (kMix) se += (double)log2_fast(pm);
     }
     for (int i = nb * kUnroll; i < nm; ++i, ++yp) {
-      R ae = (R)0, Ed, zd;
-      const R av = step(p, *yp, r, ae, Ed, zd);
+      R ae = (R)0, pm = (R)1, Ed, zd;
+      const R av = step(p, *yp, r, ae, pm, Ed, zd);
       sv += (double)av;
       se += (double)ae;
+      if constexpr (kMix) se += (double)log2_fast(pm);
     }
     // The last observation: keep its exponents and shock for the state.
     R wl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) wl[k] = r.w[k];
-    R ae = (R)0, E, z;
-    const R av = step(p, *yp, r, ae, E, z);
+    R ae = (R)0, pm = (R)1, E, z;
+    const R av = step(p, *yp, r, ae, pm, E, z);
     sv += (double)av;
     se += (double)ae;
+    if constexpr (kMix) se += (double)log2_fast(pm);
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
     st[K] = z * E;
     const double nd = (double)n;
     // log h_s = log sigma_Y - ln2 * sum_k w_ks
     if constexpr (kT) return nd * (p.cst - p.lsig) + kLn2 * sv - p.hnu1 * t_scale<R>() * se;
+    else if constexpr (kMix) return nd * (p.cst - p.lsig) + kLn2 * (sv + se);
     else return nd * (p.cst - p.lsig) + kLn2 * sv - 0.5 * se;
   }
 };

@@ -1,0 +1,461 @@
+// Kernels templated on the model type, and the table of their launchers.
+//
+// Each ops_*.hip translation unit instantiates the table (ModelOps) for a set
+// of models, so the model families compile in parallel; kernels.hip routes a
+// model description to its table.  Geometry: one particle per lane, 64-thread
+// blocks (one wave each), so a population spreads over as many compute units
+// as it has waves; observations are wave-uniform and reach the lanes through
+// scalar loads.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <math.h>
+
+#include <type_traits>
+
+#include "adjoint.h"
+#include "common.h"
+#include "launch.h"
+#include "model.h"
+#include "rng.h"
+
+namespace smc {
+
+namespace {
+
+inline dim3 grid_for(int64_t n, int block) { return dim3((unsigned)((n + block - 1) / block)); }
+
+inline smc_status launch_status(const char *what) {
+  const hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return set_error(SMC_E_DEVICE, "%s: %s", what, hipGetErrorString(e));
+  return SMC_OK;
+}
+
+template <typename T>
+__device__ __forceinline__ T *typed(void *p) { return reinterpret_cast<T *>(p); }
+template <typename T>
+__device__ __forceinline__ const T *typed(const void *p) { return reinterpret_cast<const T *>(p); }
+
+}  // namespace
+
+// --------------------------------------------------------- prior (a1) ------
+template <class M>
+__global__ void __launch_bounds__(64) k_init(DevModel dm, int64_t P, uint64_t seed, uint64_t run,
+                                             double *theta, double *logprior, double *loglik,
+                                             void *state, double *logw) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D];
+  M::prior_draw(seed, run, (uint64_t)p, th);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) theta[i * P + p] = th[i];
+  logprior[p] = M::logprior(th);
+  loglik[p] = 0.0;
+  logw[p] = 0.0;
+  using R = typename M::R;
+#pragma unroll
+  for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state)[k * P + p] = (R)0;
+}
+
+// ------------------------------------------------------------ C phase (a2) --
+// Speculative pass: from the committed state at t0, evaluate observations
+// t0+1..t1 and record the running log weight at every check date, without
+// committing anything.
+template <class M>
+__global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
+                                              const void *state, const double *logw, int64_t t0,
+                                              int64_t t1, int64_t check_every, int64_t t_max,
+                                              int32_t zero_first, double *W) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
+  double lw = zero_first ? 0.0 : logw[p];
+  int64_t col = 0;
+  for (int64_t s = t0 + 1; s <= t1; ++s) {
+    double lp = Eval<M>::advance(dm, par, st, s - 1, s);
+    if (isnan(lp)) lp = -INFINITY;
+    lw += lp;
+    if (s % check_every == 0 || s == t_max) {
+      W[col * P + p] = lw;
+      ++col;
+    }
+  }
+}
+
+// Commit: advance from t0 to t1, adding the log densities to logw and loglik.
+template <class M>
+__global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
+                                                void *state, double *logw, double *loglik,
+                                                int64_t t0, int64_t t1, int32_t zero_first) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (k < SS) ? typed<R>(state)[k * P + p] : (R)0;
+  double lp = Eval<M>::advance(dm, par, st, t0, t1);
+  if (isnan(lp)) lp = -INFINITY;
+  logw[p] = (zero_first ? 0.0 : logw[p]) + lp;
+  loglik[p] += lp;
+#pragma unroll
+  for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
+}
+
+// ------------------------------------------------------------ M phase (a5) --
+template <class M>
+__global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
+                                                  double *logprior, double *loglik, void *state,
+                                                  const double *__restrict__ hchol, uint64_t seed,
+                                                  uint64_t run, uint64_t cycle, uint64_t iter,
+                                                  unsigned long long *n_accept, uint8_t *accepted) {
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  int acc = 0;
+  if (p < P) {
+    double th[D], z[D], pr[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
+    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double s = 0.0;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) s = fma(hchol[i * D + k], z[k], s);
+      pr[i] = th[i] + s;
+    }
+    const double lp1 = M::logprior(pr);
+    R st[SR];
+#pragma unroll
+    for (int k = 0; k < SR; ++k) st[k] = (R)0;
+    double ll1 = -INFINITY;
+    if (lp1 > -INFINITY) {
+      const auto par = M::params(pr);
+      ll1 = Eval<M>::advance(dm, par, st, 0, t);
+      const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]);
+      const U64x4 w = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+      acc = (log(u01_oo(w.x0)) < delta) ? 1 : 0;
+    }
+    if (acc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) theta[i * P + p] = pr[i];
+      logprior[p] = lp1;
+      loglik[p] = ll1;
+#pragma unroll
+      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
+    }
+    if (accepted) accepted[p] = (uint8_t)acc;
+  }
+  const unsigned long long mask = __ballot(acc);
+  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
+// ------------------------------------------------- standalone likelihood --
+template <class M>
+__global__ void __launch_bounds__(64) k_loglik(DevModel dm, int64_t P, const double *theta,
+                                               int64_t t, double *out, void *state_out) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  const auto par = M::params(th);
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (R)0;
+  out[p] = Eval<M>::advance(dm, par, st, 0, t);
+  if (state_out)
+#pragma unroll
+    for (int k = 0; k < StoredS<M>::value; ++k) typed<R>(state_out)[k * P + p] = st[k];
+}
+
+// ------------------------------------- gradients and the Langevin step (a8) --
+template <class M>
+struct IsLinreg : std::false_type {};
+template <int NREG>
+struct IsLinreg<Linreg<NREG>> : std::true_type {};
+
+// Value of log p(y_{1:t} | theta) with its gradient added (times scale) to
+// g, and the state at t.  ckpt: this call's checkpoint area; lds: this lane's
+// column of the block's LDS buffer.
+template <class M>
+__device__ __forceinline__ double ll_and_grad(const DevModel &dm, const double *th, int64_t t,
+                                              void *ckpt, int64_t P, int64_t p, void *lds,
+                                              double scale, double *g,
+                                              typename M::R (&st)[Eval<M>::SR]) {
+  if constexpr (IsLinreg<M>::value) {
+    st[0] = 0.0;
+    return Adjoint<M>::value_and_grad(dm, th, t, scale, g);
+  } else {
+    using R = typename M::R;
+    const auto par = M::params(th);
+    return Adjoint<M>::value_and_grad(par, th, t, M::ydata(dm), typed<R>(ckpt), P, p,
+                                      typed<R>(lds) + threadIdx.x, scale, g, st);
+  }
+}
+
+template <class M>
+constexpr size_t lds_bytes_of() {
+  if constexpr (IsLinreg<M>::value) return 0;
+  else return (size_t)Adjoint<M>::kLdsPerLane * 64 * sizeof(typename M::R);
+}
+
+template <class M>
+__global__ void __launch_bounds__(64) k_loglik_backward(DevModel dm, int64_t P, const double *theta,
+                                                        int64_t t, const double *dloglik,
+                                                        double *dtheta, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D], g[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) {
+    th[i] = theta[i * P + p];
+    g[i] = 0.0;
+  }
+  typename M::R st[Eval<M>::SR];
+  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, dloglik[p], g, st);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) dtheta[i * P + p] = g[i];
+}
+
+// grad = d/dtheta [log p(theta) + log p(y_{1:t} | theta)] for every particle.
+template <class M>
+__global__ void __launch_bounds__(64) k_grad_post(DevModel dm, int64_t P, const double *theta,
+                                                  int64_t t, double *grad, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D], g[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  PriorGradOf<M>::run(th, g);
+  typename M::R st[Eval<M>::SR];
+  (void)ll_and_grad<M>(dm, th, t, ckpt, P, p, lds_dyn, 1.0, g, st);
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) grad[i * P + p] = g[i];
+}
+
+// One preconditioned Langevin (MALA) Metropolis iteration: proposal mean
+// theta + (1/2)(hL)(hL)' grad, noise hL z; the acceptance test adds
+// log q(theta | theta') - log q(theta' | theta) = -|w|^2/2 + |z|^2/2 with
+// (hL) w = theta - theta' - (1/2)(hL)(hL)' grad'.
+template <class M>
+__global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int64_t t, double *theta,
+                                                    double *logprior, double *loglik, void *state,
+                                                    double *grad, const double *__restrict__ hchol,
+                                                    uint64_t seed, uint64_t run, uint64_t cycle,
+                                                    uint64_t iter, unsigned long long *n_accept,
+                                                    uint8_t *accepted, void *ckpt) {
+  extern __shared__ double lds_dyn[];
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  int acc = 0;
+  if (p < P) {
+    double th[D], z[D], pr[D], g0[D], g1[D], u[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      th[i] = theta[i * P + p];
+      g0[i] = grad[i * P + p];
+    }
+    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+    // u = (hL)' g0
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g0[i], s);
+      u[k] = s;
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double dr = 0.0, st = 0.0;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) {
+        dr = fma(hchol[i * D + k], u[k], dr);
+        st = fma(hchol[i * D + k], z[k], st);
+      }
+      pr[i] = th[i] + 0.5 * dr + st;
+    }
+    const double lp1 = M::logprior(pr);
+    R stv[SR];
+#pragma unroll
+    for (int k = 0; k < SR; ++k) stv[k] = (R)0;
+    double ll1 = -INFINITY;
+    if (lp1 > -INFINITY) {
+      PriorGradOf<M>::run(pr, g1);
+      ll1 = ll_and_grad<M>(dm, pr, t, ckpt, P, p, lds_dyn, 1.0, g1, stv);
+      // reverse move
+#pragma unroll
+      for (int k = 0; k < D; ++k) {
+        double s = 0.0;
+#pragma unroll
+        for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g1[i], s);
+        u[k] = s;
+      }
+      double ww = 0.0, zz = 0.0, w[D];
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double dr = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) dr = fma(hchol[i * D + k], u[k], dr);
+        double a = th[i] - pr[i] - 0.5 * dr;
+#pragma unroll
+        for (int k = 0; k < i; ++k) a = fma(-hchol[i * D + k], w[k], a);
+        w[i] = a / hchol[i * D + i];
+        ww = fma(w[i], w[i], ww);
+        zz = fma(z[i], z[i], zz);
+      }
+      const double delta =
+          (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
+      const U64x4 wr = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+      acc = (log(u01_oo(wr.x0)) < delta) ? 1 : 0;
+    }
+    if (acc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        theta[i * P + p] = pr[i];
+        grad[i * P + p] = g1[i];
+      }
+      logprior[p] = lp1;
+      loglik[p] = ll1;
+#pragma unroll
+      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = stv[k];
+    }
+    if (accepted) accepted[p] = (uint8_t)acc;
+  }
+  const unsigned long long mask = __ballot(acc);
+  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
+// Models with a hand-written adjoint (the normal-mixture shock has none).
+template <class M>
+struct HasAdjoint : std::true_type {};
+template <int K, int SH, typename R, int I>
+struct HasAdjoint<Egarch<K, SH, R, I>> : std::bool_constant<SH != SMC_SHOCK_MIXTURE> {};
+
+// ============================================================ launchers ====
+template <class M>
+struct OpsOf {
+  static smc_status init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run, double *theta,
+                         double *logprior, double *loglik, void *state, double *logw,
+                         hipStream_t s) {
+    hipLaunchKernelGGL(k_init<M>, grid_for(P, 64), dim3(64), 0, s, m, P, seed, run, theta,
+                       logprior, loglik, state, logw);
+    return launch_status("init_from_prior");
+  }
+
+  static smc_status cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
+                          const double *logw, int64_t t0, int64_t t1, int64_t check_every,
+                          int64_t t_max, bool zero_first, double *W, hipStream_t s) {
+    hipLaunchKernelGGL(k_cscan<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw, t0,
+                       t1, check_every, t_max, (int32_t)zero_first, W);
+    return launch_status("correct/scan");
+  }
+
+  static smc_status ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
+                            double *logw, double *loglik, int64_t t0, int64_t t1,
+                            bool zero_first, hipStream_t s) {
+    hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
+                       loglik, t0, t1, (int32_t)zero_first);
+    return launch_status("correct/commit");
+  }
+
+  static smc_status mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
+                              double *logprior, double *loglik, void *state, const double *hchol,
+                              uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
+                              int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
+    hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta, logprior,
+                       loglik, state, hchol, seed, run, cycle, iter,
+                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
+    return launch_status("mutate");
+  }
+
+  static smc_status loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                           double *out, void *state_out, hipStream_t s) {
+    hipLaunchKernelGGL(k_loglik<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, t, out,
+                       state_out);
+    return launch_status("loglik");
+  }
+
+  static size_t ckpt_bytes(const DevModel &, int64_t P, int64_t t) {
+    if constexpr (IsLinreg<M>::value || !HasAdjoint<M>::value) {
+      return 0;
+    } else {
+      using A = Adjoint<M>;
+      const int64_t ns = (t + A::SEG - 1) / A::SEG;
+      return (size_t)ns * M::K * (size_t)P * sizeof(typename M::R);
+    }
+  }
+
+  static smc_status loglik_backward(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                                    const double *dloglik, double *dtheta, void *ckpt,
+                                    hipStream_t s) {
+    if constexpr (!HasAdjoint<M>::value) {
+      return set_error(SMC_E_UNSUPPORTED, "no adjoint for normal-mixture shocks");
+    } else {
+      hipLaunchKernelGGL(k_loglik_backward<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m,
+                         P, theta, t, dloglik, dtheta, ckpt);
+      return launch_status("loglik_backward");
+    }
+  }
+
+  static smc_status grad_post(const DevModel &m, int64_t P, const double *theta, int64_t t,
+                              double *grad, void *ckpt, hipStream_t s) {
+    if constexpr (!HasAdjoint<M>::value) {
+      return set_error(SMC_E_UNSUPPORTED, "no adjoint for normal-mixture shocks");
+    } else {
+      hipLaunchKernelGGL(k_grad_post<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P,
+                         theta, t, grad, ckpt);
+      return launch_status("posterior_grad");
+    }
+  }
+
+  static smc_status mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
+                                double *logprior, double *loglik, void *state, double *grad,
+                                const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
+                                uint64_t iter, int64_t *n_accept, uint8_t *accepted, void *ckpt,
+                                hipStream_t s) {
+    if constexpr (!HasAdjoint<M>::value) {
+      return set_error(SMC_E_UNSUPPORTED, "no adjoint for normal-mixture shocks");
+    } else {
+      hipLaunchKernelGGL(k_mutate_mala<M>, grid_for(P, 64), dim3(64), lds_bytes_of<M>(), s, m, P,
+                         t, theta, logprior, loglik, state, grad, hchol, seed, run, cycle, iter,
+                         reinterpret_cast<unsigned long long *>(n_accept), accepted, ckpt);
+      return launch_status("mutate/mala");
+    }
+  }
+};
+
+template <class M>
+const ModelOps *ops_table() {
+  static const ModelOps o{&OpsOf<M>::init,       &OpsOf<M>::cscan,
+                          &OpsOf<M>::ccommit,    &OpsOf<M>::mutate_rw,
+                          &OpsOf<M>::loglik,     &OpsOf<M>::ckpt_bytes,
+                          &OpsOf<M>::loglik_backward, &OpsOf<M>::grad_post,
+                          &OpsOf<M>::mutate_mala};
+  return &o;
+}
+
+}  // namespace smc

@@ -11,7 +11,7 @@ def gpu_model(w, precision=S.SMC_FP64, T=None):
     if T is not None and T != w.T:
         y = w.y[:T]
         X = None if w.X is None else w.X[:T]
-        return S.Model(w.kind, y, X=X, K=w.K, shock=w.shock, precision=precision)
+        return S.Model(w.kind, y, X=X, K=w.K, shock=w.shock, precision=precision, I=w.I)
     return S.Model.from_workload(w, precision=precision)
 
 

@@ -39,7 +39,7 @@ def test_struct_sizes_match_header_layout():
 
 
 def _desc(**kw):
-    base = dict(kind=S.SMC_MODEL_EGARCH, K=1, shock=0, nreg=0, precision=0, reserved=0, T=10,
+    base = dict(kind=S.SMC_MODEL_EGARCH, K=1, shock=0, nreg=0, precision=0, ncomp=0, T=10,
                 y=C.c_void_p(0x1000), y32=None, X=None)
     base.update(kw)
     return S._lib.ModelDesc(**base)
@@ -47,7 +47,9 @@ def _desc(**kw):
 
 @pytest.mark.parametrize("kw,status", [
     (dict(T=0), -1), (dict(y=None), -1), (dict(kind=7), -1), (dict(K=3), -2),
-    (dict(precision=1), -1), (dict(reserved=1), -1), (dict(shock=5), -1),
+    (dict(precision=1), -1), (dict(ncomp=1), -1), (dict(shock=5), -1),
+    (dict(shock=2, ncomp=1), -2), (dict(shock=2, ncomp=5), -2), (dict(shock=2, K=5, ncomp=3), -2),
+    (dict(kind=1, nreg=3, X=C.c_void_p(0x1000), ncomp=2), -1),
     (dict(kind=1, nreg=3, X=None), -1), (dict(kind=1, nreg=9, X=C.c_void_p(0x1000)), -2),
     (dict(kind=1, nreg=3, X=C.c_void_p(0x1000), precision=1), -2),
 ])
@@ -61,6 +63,7 @@ def test_model_create_validates(kw, status):
 def test_model_dims_and_workspace():
     L = S._lib.lib()
     for kw, d, s in [(dict(), 5, 2), (dict(K=2, shock=1), 9, 3),
+                     (dict(K=2, shock=2, ncomp=3), 17, 3), (dict(K=4, shock=2, ncomp=4), 26, 5),
                      (dict(kind=1, nreg=3, X=C.c_void_p(0x1000)), 4, 0)]:
         h = C.c_void_p()
         assert L.smc_model_create(C.byref(_desc(**kw)), C.byref(h)) == 0
