@@ -41,8 +41,22 @@ N_SIMD = 256 * 4
 # (FMA = 1; FP32 exp2/log2 = 4, quarter rate; FP64 exp/log1p = 17, the
 # range reduction, degree-11 polynomial and scaling of a full-precision
 # software exponential).
+def mixture_ops(K, I, exp_cost):
+    """Lane-operations per particle-observation of egarch_KI with an
+    I-component normal mixture: the K factor updates (4 each, plus 3 per
+    extra factor for the cross-factor sums), z, eps = z E and the exponent
+    sum (3); per component eps - mu_i and the quadratic (3), the shift by the
+    maximum and the sum (about 2 each), the running maximum term and product
+    (2); one exp2 for E and one per component."""
+    rec = 4 * K + (3 * (K - 1) if K > 1 else 0) + 3
+    mix = 3 * I + 2 * (I - 1) + I + 2
+    return rec + mix + (1 + I) * exp_cost
+
+
 OPS_PER_EVAL = {
     ("linreg", "fp64"): 4,
+    ("egarch23", "fp64"): mixture_ops(2, 3, 17),
+    ("egarch23", "fp32"): mixture_ops(2, 3, 4),
     ("egarch11", "fp64"): 7 + 17,
     ("egarch11", "fp32"): 7 + 1 + 4,
     ("egarch2t", "fp64"): 10 + 17 + 3 + 17,
@@ -53,6 +67,8 @@ DESCR = {
     "linreg": "conjugate Gaussian regression, k=3, T=200, J=4 x N=256",
     "egarch11": "EGARCH(1,1) Gaussian shocks, T=5000 synthetic returns, J=16 x N=1024",
     "egarch2t": "EGARCH 2 factors, Student-t(8) shocks, T=10000 synthetic returns, J=64 x N=1024",
+    "egarch23": ("egarch_23: EGARCH 2 factors, 3-component normal-mixture shocks, T=5100 "
+                 "synthetic returns, J=64 x N=1024"),
 }
 
 
@@ -100,7 +116,7 @@ def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 
     prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
     kern = S.SMC_KERNEL_MALA if kernel == "mala" else S.SMC_KERNEL_RW
     m = S.Model.from_workload(w, precision=prec)
-    pop = S.Population(m, w.J, w.N, max_chunk=256, with_grad=kern == S.SMC_KERNEL_MALA)
+    pop = S.Population(m, w.J, w.N, max_chunk=1024, with_grad=kern == S.SMC_KERNEL_MALA)
     tried = []
     for Rbar in ladder:
         rec = S.Record(m, w.J, Lmax=2048, RmaxRec=3 * Rbar + 1)
@@ -132,7 +148,7 @@ def run_gpu(name, precision, steps, warmup):
     w = SD.workload(name)
     prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
     m = S.Model.from_workload(w, precision=prec)
-    pop = S.Population(m, w.J, w.N, max_chunk=256)
+    pop = S.Population(m, w.J, w.N, max_chunk=1024)
     rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64, time_mutate=True)
     force = 20 if name == "linreg" else 0
 
@@ -291,7 +307,7 @@ def main():
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run only the short fixed sequence used for counter passes")
     ap.add_argument("--no-companions", action="store_true",
-                    help="skip the EGARCH(2)-t roofline run and the time-to-NSE comparison")
+                    help="skip the EGARCH(2)-t and egarch_23 runs and the time-to-NSE comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulator "
@@ -308,9 +324,12 @@ def main():
     if not args.no_fp32 and args.precision == "fp64" and args.workload != "linreg":
         companion = run_gpu(args.workload, "fp32", args.steps, args.warmup)
     roof2t = tnse = batched = None
+    mix = {}
     if not args.no_companions and args.workload == "egarch11":
         batched = run_batched(2)
         roof2t = run_gpu("egarch2t", "fp32", max(2, min(args.steps, 3)), 1)
+        for prec in ("fp32", "fp64"):
+            mix[prec] = run_gpu("egarch23", prec, 2, 1)
         tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "mala"),
                 time_to_nse("egarch2t", "fp32", "rw")]
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
@@ -356,6 +375,13 @@ def main():
             "log_ml": roof2t["log_ml"], "nse": roof2t["nse"],
             "mutate_avg_ms": roof2t["mutate_avg_ms"],
             "mutate_evals_per_s": roof2t["mutate_evals_per_s"], "roofline": roof2t["roofline"]}
+    for prec, r in mix.items():
+        out[f"egarch23_{prec}"] = {
+            "workload": DESCR["egarch23"] + f", RW, {prec.upper()} recursion, FP64 weights",
+            "value": r["value"], "ms_per_step": r["ms_per_step"], "log_ml": r["log_ml"],
+            "nse": r["nse"], "cycles": r["cycles"], "mh_steps": r["mh_steps"],
+            "mutate_avg_ms": r["mutate_avg_ms"], "mutate_evals_per_s": r["mutate_evals_per_s"],
+            "roofline": r["roofline"]}
     if batched is not None:
         out["batched"] = dict(batched, workload="32 independent adaptive runs: EGARCH(1,1)-N / "
                               "EGARCH(2)-t alternating, T in [1000, 20000], J=16, J*N in "

@@ -536,9 +536,11 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     }
     int64_t t_new = t;
     double rss = NAN;
-    // Speculate on a cycle a little longer than the previous one, so most C
-    // phases need a single host round trip.
-    const int64_t hint = std::max<int64_t>(16, last_len + last_len / 4 + 8);
+    // Speculate on a cycle twice as long as the previous one, so most C
+    // phases need a single host round trip (cycles lengthen as the posterior
+    // concentrates; evaluations past the stop date are cheap beside the M
+    // phase's).
+    const int64_t hint = std::max<int64_t>(16, 2 * last_len + 16);
     if ((st = correct_impl(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
                            rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
                            cfg->replay ? nullptr : &rss, stream, hint)))
@@ -799,7 +801,7 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         }
         const int64_t cap = chunk_capacity(m, pop);
         if (cap < 1) return set_error(SMC_E_WORKSPACE, "run %d: no room for C-phase chunks", i);
-        u.chunk = std::min<int64_t>(cap, std::max<int64_t>(16, u.last_len + u.last_len / 4 + 8));
+        u.chunk = std::min<int64_t>(cap, std::max<int64_t>(16, 2 * u.last_len + 16));
         u.ph = kCNext;
       }
       if (u.ph == kCNext) {

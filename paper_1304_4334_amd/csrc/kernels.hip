@@ -134,11 +134,20 @@ __global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32
 }
 
 // ------------------------------------------------------------ S phase (a3) --
-// One block per group.  Counts live in LDS (dynamic, N int32); the running
-// residual sums in the workspace.  Residual: floor(N W_n) copies, then the
-// remaining draws from the residuals; multinomial: N draws from W_n;
-// stratified / systematic (Section 3.3's experimental schemes): the k-th of N
-// draws at (k + U_k)/N, respectively (k + U)/N, of the running sum.
+// One block per group.  The group's weights, then their running residual
+// sums, live in LDS when they fit (kCumLdsMax), else in the workspace; the
+// copy counts in LDS.  Residual: floor(N W_n) copies, then the remaining
+// draws from the residuals; multinomial: N draws from W_n; stratified /
+// systematic (Section 3.3's experimental schemes): the k-th of N draws at
+// (k + U_k)/N, respectively (k + U)/N, of the running sum.  Each phase keeps
+// its global accesses in flight together, since a block of one group is
+// latency-bound.
+constexpr int kCumLdsMax = 2048;      // groups up to this size keep their sums in LDS
+constexpr int kResampleMaxN = 16384;  // the counts alone fill 64 KB of LDS here
+constexpr int kGatherQ = 4;           // particles per thread per gather pass (global path)
+constexpr int kGatherRows = 12;       // rows per batch of gather loads (global path)
+constexpr int kGatherLdsBytes = 24576;  // LDS staging of source rows (groups <= kCumLdsMax)
+
 struct GatherArgs {
   const int32_t *anc;
   int64_t P;
@@ -148,21 +157,90 @@ struct GatherArgs {
   double *tmp;  // [2d + S + 2][P]
 };
 
+// Row r of the particle arrays in gather order: theta rows, log prior, log
+// likelihood, state rows, gradient rows (rows are wave-uniform).
+__device__ __forceinline__ double gather_load(const GatherArgs &g, int r, int64_t i) {
+  if (r < g.d) return g.theta[r * g.P + i];
+  r -= g.d;
+  if (r == 0) return g.logprior[i];
+  if (r == 1) return g.loglik[i];
+  r -= 2;
+  if (r < g.S)
+    return g.st_bytes == 8 ? typed<double>(g.state)[r * g.P + i]
+                           : (double)typed<float>(g.state)[r * g.P + i];
+  r -= g.S;
+  return g.grad[r * g.P + i];
+}
+__device__ __forceinline__ void gather_store(const GatherArgs &g, int r, int64_t i, double v) {
+  if (r < g.d) { g.theta[r * g.P + i] = v; return; }
+  r -= g.d;
+  if (r == 0) { g.logprior[i] = v; return; }
+  if (r == 1) { g.loglik[i] = v; return; }
+  r -= 2;
+  if (r < g.S) {
+    if (g.st_bytes == 8) typed<double>(g.state)[r * g.P + i] = v;
+    else typed<float>(g.state)[r * g.P + i] = (float)v;
+    return;
+  }
+  r -= g.S;
+  g.grad[r * g.P + i] = v;
+}
+
+// In-place gather held in registers: every thread loads all rows of its
+// PER particles' ancestors, the block synchronises, then every thread stores
+// them at its own positions (rows <= kRegRows).
+constexpr int kRegRows = 16;
+template <int PER>
+__device__ __forceinline__ void gather_in_registers(const GatherArgs &g, int64_t base, int32_t N,
+                                                    int rows, const int32_t *anc_l) {
+  double v[PER][kRegRows];
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int n = tid + q * kBlock;
+    const int64_t a = base + (n < N ? anc_l[n] : 0);
+#pragma unroll
+    for (int r = 0; r < kRegRows; ++r)
+      if (r < rows) v[q][r] = gather_load(g, r, a);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < PER; ++q) {
+    const int n = tid + q * kBlock;
+    if (n < N)
+#pragma unroll
+      for (int r = 0; r < kRegRows; ++r)
+        if (r < rows) gather_store(g, r, base + n, v[q][r]);
+  }
+}
+
 __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
                                                   uint64_t seed, uint64_t run, uint64_t cycle,
                                                   int32_t *anc, double *cum_ws, int32_t *flags,
                                                   GatherArgs g) {
-  extern __shared__ int32_t cnt[];
+  extern __shared__ double lds_dyn[];
   __shared__ double shd[kBlock];
   __shared__ int64_t shi[kBlock];
   const int j = blockIdx.x;
   const int64_t base = (int64_t)j * N;
   const double *lw = logw + base;
-  double *cum = cum_ws + base;
+  // LDS layout for groups up to kCumLdsMax: [N] doubles (weights, then the
+  // running sums), [kGatherLdsBytes] of row staging, [N] int32 counts, [N]
+  // int32 ancestors; larger groups keep the sums in the workspace and only
+  // the counts in LDS.
+  const bool in_lds = N <= kCumLdsMax;
+  double *ev = in_lds ? lds_dyn : cum_ws + base;  // e_n, then the running sums
+  double *stage = lds_dyn + N;
+  int32_t *cnt = reinterpret_cast<int32_t *>(in_lds ? stage + kGatherLdsBytes / 8 : lds_dyn);
+  int32_t *anc_l = cnt + N;  // group-local ancestors (LDS path only)
   const int tid = threadIdx.x;
 
   double mx = -INFINITY;
-  for (int n = tid; n < N; n += kBlock) mx = fmax(mx, lw[n]);
+  for (int n = tid; n < N; n += kBlock) {
+    const double v = lw[n];
+    ev[n] = v;
+    mx = fmax(mx, v);
+  }
   mx = block_reduce<OpMax<double>>(mx, shd);
   if (!(mx > -INFINITY)) {
     for (int n = tid; n < N; n += kBlock) anc[base + n] = (int32_t)(base + n);
@@ -170,8 +248,12 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
     return;
   }
   double se = 0.0;
-  for (int n = tid; n < N; n += kBlock) se += exp(lw[n] - mx);
-  se = block_reduce<OpSum<double>>(se, shd);
+  for (int n = tid; n < N; n += kBlock) {
+    const double e = exp(ev[n] - mx);
+    ev[n] = e;
+    se += e;
+  }
+  se = block_reduce<OpSum<double>>(se, shd);  // its barriers publish ev
 
   // Thread-contiguous chunks for the scans.
   const int m = (N + kBlock - 1) / kBlock;
@@ -179,41 +261,50 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   double rsum = 0.0;
   int64_t csum = 0;
   for (int n = lo; n < hi; ++n) {
-    const double nw = ((double)N * exp(lw[n] - mx)) / se;  // N W_n
+    const double nw = ((double)N * ev[n]) / se;  // N W_n
     const double c = (scheme == SMC_RESAMPLE_RESIDUAL) ? floor(nw) : 0.0;
     rsum += nw - c;
-    cum[n] = rsum;
+    ev[n] = rsum;
     cnt[n] = (int32_t)c;
     csum += (int64_t)c;
   }
   double rtot;
   const double roff = block_inclusive_scan<double>(rsum, shd, rtot) - rsum;
-  for (int n = lo; n < hi; ++n) cum[n] += roff;
+  for (int n = lo; n < hi; ++n) ev[n] += roff;
   int64_t ctot;
   (void)block_inclusive_scan<int64_t>(csum, shi, ctot);
   __syncthreads();
+  const double *cum = ev;
   const double total = cum[N - 1];
   const int64_t R = (int64_t)N - ctot;
-  const double u_sys = u01_co(draw4(seed, run, (uint64_t)j, cycle, 0, kResample).x0);
-  for (int64_t k = tid; k < R; k += kBlock) {
-    const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k >> 2), kResample);
-    const uint64_t x = (k & 3) == 0 ? w.x0 : (k & 3) == 1 ? w.x1 : (k & 3) == 2 ? w.x2 : w.x3;
-    double u = u01_co(x);
-    if (scheme == SMC_RESAMPLE_STRATIFIED) u = ((double)k + u) / (double)N;
-    else if (scheme == SMC_RESAMPLE_SYSTEMATIC) u = ((double)k + u_sys) / (double)N;
-    const double target = u * total;
-    int a_lo = 0, a_hi = N;  // first n with cum[n] > target
-    while (a_lo < a_hi) {
-      const int mid = (a_lo + a_hi) >> 1;
-      if (cum[mid] > target) a_hi = mid;
-      else a_lo = mid + 1;
+  // Draws k = 4q..4q+3 share the Philox block q.
+  const double u_sys = scheme == SMC_RESAMPLE_SYSTEMATIC
+                           ? u01_co(draw4(seed, run, (uint64_t)j, cycle, 0, kResample).x0)
+                           : 0.0;
+  for (int64_t k0 = 4 * (int64_t)tid; k0 < R; k0 += 4 * kBlock) {
+    const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k0 >> 2), kResample);
+    const uint64_t xs[4] = {w.x0, w.x1, w.x2, w.x3};
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int64_t k = k0 + q;
+      if (k >= R) break;
+      double u = u01_co(xs[q]);
+      if (scheme == SMC_RESAMPLE_STRATIFIED) u = ((double)k + u) / (double)N;
+      else if (scheme == SMC_RESAMPLE_SYSTEMATIC) u = ((double)k + u_sys) / (double)N;
+      const double target = u * total;
+      int a_lo = 0, a_hi = N;  // first n with cum[n] > target
+      while (a_lo < a_hi) {
+        const int mid = (a_lo + a_hi) >> 1;
+        if (cum[mid] > target) a_hi = mid;
+        else a_lo = mid + 1;
+      }
+      int a = a_lo;
+      if (a >= N) {
+        a = N - 1;
+        while (a > 0 && !(cum[a] > cum[a - 1])) --a;
+      }
+      atomicAdd(&cnt[a], 1);
     }
-    int a = a_lo;
-    if (a >= N) {
-      a = N - 1;
-      while (a > 0 && !(cum[a] > cum[a - 1])) --a;
-    }
-    atomicAdd(&cnt[a], 1);
   }
   __syncthreads();
   int64_t my = 0;
@@ -221,37 +312,88 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   int64_t tot2;
   int64_t pos = block_inclusive_scan<int64_t>(my, shi, tot2) - my;
   for (int n = lo; n < hi; ++n)
-    for (int c = 0; c < cnt[n] && pos < N; ++c) anc[base + pos++] = (int32_t)(base + n);
+    for (int c = 0; c < cnt[n] && pos < N; ++c) {
+      if (in_lds) anc_l[pos] = n;
+      anc[base + pos++] = (int32_t)(base + n);
+    }
   __syncthreads();
-  // Replace the group's particles by their ancestors (all inside this
-  // group): copy the ancestors' values to the workspace, then back.
   const int64_t P = g.P;
-  for (int n = tid; n < N; n += kBlock) {
-    const int64_t p = base + n;
-    const int64_t a = anc[p];
-    int r = 0;
-    for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.theta[i * P + a];
-    g.tmp[r++ * P + p] = g.logprior[a];
-    g.tmp[r++ * P + p] = g.loglik[a];
-    for (int k = 0; k < g.S; ++k, ++r)
-      g.tmp[r * P + p] = g.st_bytes == 8 ? typed<double>(g.state)[k * P + a]
-                                         : (double)typed<float>(g.state)[k * P + a];
-    if (g.has_grad)
-      for (int i = 0; i < g.d; ++i, ++r) g.tmp[r * P + p] = g.grad[i * P + a];
+  const int rows = g.d + 2 + g.S + (g.has_grad ? g.d : 0);
+  if (in_lds && rows <= kRegRows && N <= 4 * kBlock) {
+    if (N <= kBlock) gather_in_registers<1>(g, base, N, rows, anc_l);
+    else if (N <= 2 * kBlock) gather_in_registers<2>(g, base, N, rows, anc_l);
+    else gather_in_registers<4>(g, base, N, rows, anc_l);
+    return;
+  }
+  if (in_lds) {
+    // Replace the group's particles by their ancestors through LDS: stage
+    // B source rows of the whole group (coalesced loads), then write every
+    // particle's row values from its ancestor's slot.
+    const int B = max(1, min(rows, kGatherLdsBytes / (8 * N)));
+    for (int r0 = 0; r0 < rows; r0 += B) {
+      const int nr = min(B, rows - r0);
+      for (int rr = 0; rr < nr; ++rr)  // rows outermost: the row choice stays uniform
+        for (int n = tid; n < N; n += kBlock) stage[rr * N + n] = gather_load(g, r0 + rr, base + n);
+      __syncthreads();
+      for (int rr = 0; rr < nr; ++rr)
+        for (int n = tid; n < N; n += kBlock)
+          gather_store(g, r0 + rr, base + n, stage[rr * N + anc_l[n]]);
+      __syncthreads();
+    }
+    return;
+  }
+  // Larger groups: copy the ancestors' values to the workspace, then back,
+  // with kGatherQ particles x kGatherRows rows of loads in flight per batch.
+  for (int n0 = 0; n0 < N; n0 += kBlock * kGatherQ) {
+    int64_t pp[kGatherQ], aa[kGatherQ];
+    bool ok[kGatherQ];
+#pragma unroll
+    for (int q = 0; q < kGatherQ; ++q) {
+      const int n = n0 + q * kBlock + tid;
+      ok[q] = n < N;
+      pp[q] = base + (ok[q] ? n : 0);
+    }
+#pragma unroll
+    for (int q = 0; q < kGatherQ; ++q) aa[q] = anc[pp[q]];
+    for (int r0 = 0; r0 < rows; r0 += kGatherRows) {
+      double v[kGatherRows][kGatherQ];
+#pragma unroll
+      for (int rr = 0; rr < kGatherRows; ++rr)
+        if (r0 + rr < rows)
+#pragma unroll
+          for (int q = 0; q < kGatherQ; ++q) v[rr][q] = gather_load(g, r0 + rr, aa[q]);
+#pragma unroll
+      for (int rr = 0; rr < kGatherRows; ++rr)
+        if (r0 + rr < rows)
+#pragma unroll
+          for (int q = 0; q < kGatherQ; ++q)
+            if (ok[q]) g.tmp[(r0 + rr) * P + pp[q]] = v[rr][q];
+    }
   }
   __syncthreads();
-  for (int n = tid; n < N; n += kBlock) {
-    const int64_t p = base + n;
-    int r = 0;
-    for (int i = 0; i < g.d; ++i, ++r) g.theta[i * P + p] = g.tmp[r * P + p];
-    g.logprior[p] = g.tmp[r++ * P + p];
-    g.loglik[p] = g.tmp[r++ * P + p];
-    for (int k = 0; k < g.S; ++k, ++r) {
-      if (g.st_bytes == 8) typed<double>(g.state)[k * P + p] = g.tmp[r * P + p];
-      else typed<float>(g.state)[k * P + p] = (float)g.tmp[r * P + p];
+  for (int n0 = 0; n0 < N; n0 += kBlock * kGatherQ) {
+    int64_t pp[kGatherQ];
+    bool ok[kGatherQ];
+#pragma unroll
+    for (int q = 0; q < kGatherQ; ++q) {
+      const int n = n0 + q * kBlock + tid;
+      ok[q] = n < N;
+      pp[q] = base + (ok[q] ? n : 0);
     }
-    if (g.has_grad)
-      for (int i = 0; i < g.d; ++i, ++r) g.grad[i * P + p] = g.tmp[r * P + p];
+    for (int r0 = 0; r0 < rows; r0 += kGatherRows) {
+      double v[kGatherRows][kGatherQ];
+#pragma unroll
+      for (int rr = 0; rr < kGatherRows; ++rr)
+        if (r0 + rr < rows)
+#pragma unroll
+          for (int q = 0; q < kGatherQ; ++q) v[rr][q] = g.tmp[(r0 + rr) * P + pp[q]];
+#pragma unroll
+      for (int rr = 0; rr < kGatherRows; ++rr)
+        if (r0 + rr < rows)
+#pragma unroll
+          for (int q = 0; q < kGatherQ; ++q)
+            if (ok[q]) gather_store(g, r0 + rr, pp[q], v[rr][q]);
+    }
   }
 }
 
@@ -344,19 +486,26 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
   const int tid = threadIdx.x;
   const int d = a.d;
   const int64_t P = a.P;
+  // the step-size inputs are read first so their latency overlaps the sums
+  int32_t m = 0;
+  int64_t nacc = 0;
+  if (tid == 0) {
+    m = *a.mh;
+    if (a.mh_reset <= 0 && a.prev_nacc) nacc = *a.prev_nacc;
+  }
   for (int e = tid; e < W * W; e += 256) {
+    const double *pp = a.part + e;
     double sum = 0.0;
 #pragma unroll 16
-    for (int b = 0; b < nb; ++b) sum += a.part[(int64_t)b * W * W + e];
+    for (int b = 0; b < nb; ++b, pp += W * W) sum += *pp;
     Ms[e] = sum;
     Ls[e] = 0.0;
   }
   if (tid == 0) {
-    int32_t m = *a.mh;
     if (a.mh_reset > 0) {
       m = a.mh_reset;
     } else if (a.prev_nacc) {
-      m += ((*a.prev_nacc) * 1000 > (int64_t)a.target_permille * P) ? 1 : -1;
+      m += (nacc * 1000 > (int64_t)a.target_permille * P) ? 1 : -1;
       m = m < 1 ? 1 : (m > 10 ? 10 : m);
     }
     *a.mh = m;
@@ -465,39 +614,45 @@ __global__ void k_rne_final(const double *part, int32_t J, int32_t N, int32_t d,
 }
 
 // log wbar, its delta-method NSE and log wtilde from group_logwbar[L][J].
-__global__ void k_log_ml(int32_t L, int32_t J, const double *g, double *out) {
-  if (threadIdx.x != 0) return;
-  double mx = -INFINITY;
-  for (int j = 0; j < J; ++j) {
+__global__ void __launch_bounds__(256) k_log_ml(int32_t L, int32_t J, const double *g,
+                                                double *out) {
+  __shared__ double sh[4];
+  const int tid = threadIdx.x;
+  // log wbar_j = sum_l log wbar_j(l): each thread owns groups j = tid + 256 k
+  // and sums over the cycles in order.
+  auto lw = [&](int j) {
     double s = 0.0;
     for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
-    mx = fmax(mx, s);
+    return s;
+  };
+  double m = -INFINITY;
+  for (int j = tid; j < J; j += kBlock) m = fmax(m, lw(j));
+  const double mx = block_reduce<OpMax<double>>(m, sh);
+  double r = 0.0;
+  for (int j = tid; j < J; j += kBlock) r += exp(lw(j) - mx);
+  const double rbar = block_reduce<OpSum<double>>(r, sh) / (double)J;
+  double q = 0.0;
+  for (int j = tid; j < J; j += kBlock) {
+    const double e = exp(lw(j) - mx) - rbar;
+    q = fma(e, e, q);
   }
-  double rbar = 0.0;
-  for (int j = 0; j < J; ++j) {
-    double s = 0.0;
-    for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
-    rbar += exp(s - mx);
-  }
-  rbar /= (double)J;
-  double ss = 0.0;
-  for (int j = 0; j < J; ++j) {
-    double s = 0.0;
-    for (int l = 0; l < L; ++l) s += g[(int64_t)l * J + j];
-    const double e = exp(s - mx) - rbar;
-    ss += e * e;
-  }
+  const double ss = block_reduce<OpSum<double>>(q, sh);
+  // log wtilde = sum_l log mean_j wbar_j(l): each thread owns cycles.
   double lt = 0.0;
-  for (int l = 0; l < L; ++l) {
-    double m = -INFINITY;
-    for (int j = 0; j < J; ++j) m = fmax(m, g[(int64_t)l * J + j]);
-    double s = 0.0;
-    for (int j = 0; j < J; ++j) s += exp(g[(int64_t)l * J + j] - m);
-    lt += (m > -INFINITY) ? m + log(s / (double)J) : -INFINITY;
+  for (int l = tid; l < L; l += kBlock) {
+    const double *gl = g + (int64_t)l * J;
+    double ml = -INFINITY;
+    for (int j = 0; j < J; ++j) ml = fmax(ml, gl[j]);
+    double sl = 0.0;
+    for (int j = 0; j < J; ++j) sl += exp(gl[j] - ml);
+    lt += (ml > -INFINITY) ? ml + log(sl / (double)J) : -INFINITY;
   }
-  out[0] = mx + log(rbar);
-  out[1] = sqrt(ss / ((double)J * (J - 1))) / rbar;
-  out[2] = lt;
+  lt = block_reduce<OpSum<double>>(lt, sh);
+  if (tid == 0) {
+    out[0] = mx + log(rbar);
+    out[1] = sqrt(ss / ((double)J * (J - 1))) / rbar;
+    out[2] = lt;
+  }
 }
 
 // ============================================================ launchers ====
@@ -605,8 +760,13 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
   const int64_t P = (int64_t)J * N;
   GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
                state, tmp};
-  hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), (size_t)N * sizeof(int32_t), s, logw, N,
-                     scheme, seed, run, cycle, anc, cum_ws, flags, g);
+  if (N > kResampleMaxN)
+    return set_error(SMC_E_UNSUPPORTED, "resampling needs N <= %d", kResampleMaxN);
+  const size_t lds = N <= kCumLdsMax ? (size_t)N * (sizeof(double) + 2 * sizeof(int32_t)) +
+                                           kGatherLdsBytes
+                                     : (size_t)N * sizeof(int32_t);
+  hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), lds, s, logw, N, scheme, seed, run, cycle,
+                     anc, cum_ws, flags, g);
   return launch_status("resample");
 }
 
@@ -650,7 +810,7 @@ smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, doub
 }
 
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s) {
-  hipLaunchKernelGGL(k_log_ml, dim3(1), dim3(64), 0, s, L, J, g, out);
+  hipLaunchKernelGGL(k_log_ml, dim3(1), dim3(kBlock), 0, s, L, J, g, out);
   return launch_status("log_ml");
 }
 

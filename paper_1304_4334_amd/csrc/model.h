@@ -298,13 +298,10 @@ struct Egarch {
     return sw;
   }
 
-  // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1.  st holds the
-  // state at t0 in the API's units, (v_1..v_K, eps_t0), and receives the
-  // state at t1.  The factors take no innovation at s = 1.
-  __device__ static double advance(const Par &p, R (&st)[S], int64_t t0, int64_t t1,
-                                   const Y *__restrict__ y) {
-    if (t1 <= t0) return 0.0;
-    Run r;
+  // Exponents of observation t0+1 from the state at t0 in the API's units,
+  // (v_1..v_K, eps_t0).  The factors take no innovation at s = 1.
+  __device__ __forceinline__ static void start(const Par &p, const R (&st)[S], int64_t t0,
+                                               Run &r) {
     const R kap = (R)kKappa;
     if (t0 == 0) {
 #pragma unroll
@@ -320,6 +317,55 @@ struct Egarch {
 #pragma unroll
     for (int k = 1; k < K; ++k) sw0 += r.w[k];
     r.sw = sw0;
+  }
+
+  // Observation by observation: f(s, log p(y_s | y_{1:s-1}, theta)) for
+  // s = t0+1..t1 (the C phase records running weights at check dates), with
+  // the recursion kept in registers; st receives the state at t1.
+  template <class F>
+  __device__ static void scan(const Par &p, R (&st)[S], int64_t t0, int64_t t1,
+                              const Y *__restrict__ y, F &&f) {
+    if (t1 <= t0) return;
+    Run r;
+    start(p, st, t0, r);
+    const double base = p.cst - p.lsig;
+    R wl[K], E = (R)1, z = (R)0;
+    auto one = [&](int64_t s, R yv) {
+#pragma unroll
+      for (int k = 0; k < K; ++k) wl[k] = r.w[k];
+      R ae = (R)0, pm = (R)1;
+      const R sw = step(p, yv, r, ae, pm, E, z);
+      double ld;
+      if constexpr (kT) ld = base + kLn2 * (double)sw - p.hnu1 * t_scale<R>() * (double)ae;
+      else if constexpr (kMix) ld = base + kLn2 * ((double)sw + (double)ae + (double)log2_fast(pm));
+      else ld = base + kLn2 * (double)sw - 0.5 * (double)ae;
+      f(s, ld);
+    };
+    // Observations in blocks of kUnroll whose loads are issued together.
+    int64_t s = t0 + 1;
+    for (; s + kUnroll - 1 <= t1; s += kUnroll) {
+      R yb[kUnroll];
+#pragma unroll
+      for (int i = 0; i < kUnroll; ++i) yb[i] = y[s - 1 + i];
+#pragma unroll
+      for (int i = 0; i < kUnroll; ++i) one(s + i, yb[i]);
+    }
+    for (; s <= t1; ++s) one(s, y[s - 1]);
+    const R kap = (R)kKappa;
+#pragma unroll
+    for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
+    st[K] = z * E;
+  }
+
+  // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1.  st holds the
+  // state at t0 in the API's units, (v_1..v_K, eps_t0), and receives the
+  // state at t1.
+  __device__ static double advance(const Par &p, R (&st)[S], int64_t t0, int64_t t1,
+                                   const Y *__restrict__ y) {
+    if (t1 <= t0) return 0.0;
+    Run r;
+    const R kap = (R)kKappa;
+    start(p, st, t0, r);
     double sv = 0.0, se = 0.0;
     const Y *yp = y + t0;
     const int n = (int)(t1 - t0);
@@ -440,6 +486,11 @@ struct Eval {
                                                    R (&st)[SR], int64_t t0, int64_t t1) {
     return M::advance(p, st, t0, t1, M::ydata(dm));
   }
+  template <class F>
+  __device__ __forceinline__ static void scan(const DevModel &dm, const typename M::Par &p,
+                                              R (&st)[SR], int64_t t0, int64_t t1, F &&f) {
+    M::scan(p, st, t0, t1, M::ydata(dm), f);
+  }
 };
 
 template <int NREG>
@@ -451,6 +502,13 @@ struct Eval<Linreg<NREG>> {
                                                    double (&st)[1], int64_t t0, int64_t t1) {
     (void)st;
     return Linreg<NREG>::advance_x(p, t0, t1, dm.y, dm.X);
+  }
+  template <class F>
+  __device__ __forceinline__ static void scan(const DevModel &dm,
+                                              const typename Linreg<NREG>::Par &p,
+                                              double (&st)[1], int64_t t0, int64_t t1, F &&f) {
+    (void)st;
+    for (int64_t s = t0 + 1; s <= t1; ++s) f(s, Linreg<NREG>::advance_x(p, s - 1, s, dm.y, dm.X));
   }
 };
 

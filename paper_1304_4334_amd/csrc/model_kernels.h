@@ -79,15 +79,17 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
   for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
   double lw = zero_first ? 0.0 : logw[p];
   int64_t col = 0;
-  for (int64_t s = t0 + 1; s <= t1; ++s) {
-    double lp = Eval<M>::advance(dm, par, st, s - 1, s);
+  int64_t next_check = (t0 / check_every + 1) * check_every;  // first multiple after t0
+  Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t s, double lp) {
     if (isnan(lp)) lp = -INFINITY;
     lw += lp;
-    if (s % check_every == 0 || s == t_max) {
+    const bool at_check = s == next_check;
+    if (at_check || s == t_max) {
       W[col * P + p] = lw;
       ++col;
     }
-  }
+    if (at_check) next_check += check_every;
+  });
 }
 
 // Commit: advance from t0 to t1, adding the log densities to logw and loglik.
