@@ -33,6 +33,7 @@ RW, MALA = 0, 1
 LINREG, EGARCH = 1, 2
 GAUSS, STUDENT_T, MIXTURE = 0, 1, 2
 PRIOR, RESAMPLE, PROPOSAL, ACCEPT = 1, 2, 3, 4
+TEST_PARAMS, TEST_MODEL = 0, 1
 
 
 class OrcModel(C.Structure):
@@ -55,7 +56,8 @@ class OrcCfg(C.Structure):
                 ("Rbar", C.c_int32), ("kappa", C.c_int32), ("stop_rule", C.c_int32),
                 ("E1", C.c_double), ("Rmax", C.c_int32), ("scheme", C.c_int32),
                 ("kernel", C.c_int32), ("replay", C.c_int32), ("Lmax", C.c_int32),
-                ("RmaxRec", C.c_int32)]
+                ("RmaxRec", C.c_int32), ("test_fn", C.c_int32), ("pad", C.c_int32),
+                ("E2", C.c_double), ("burn_in", C.c_int64)]
 
 
 class OrcRecord(C.Structure):
@@ -63,7 +65,9 @@ class OrcRecord(C.Structure):
                 ("hchol", C.POINTER(C.c_double)), ("rss", C.POINTER(C.c_double)),
                 ("n_acc", C.POINTER(C.c_int64)), ("group_logwbar", C.POINTER(C.c_double)),
                 ("log_ml", C.c_double), ("nse", C.c_double), ("log_ml_tilde", C.c_double),
-                ("evals", C.c_int64)]
+                ("evals", C.c_int64), ("moments", C.POINTER(C.c_double)),
+                ("log_score", C.c_double), ("log_score_nse", C.c_double),
+                ("log_score_tilde", C.c_double)]
 
 
 def lib():
@@ -146,6 +150,33 @@ def mixture_params(m: Model, theta):
     th = _f64(theta)
     lib().orc_mixture_params(C.byref(m.c), _dp(th), _dp(p), _dp(mu), _dp(sg))
     return p, mu, sg
+
+
+def num_test_fns(m: Model, which=TEST_MODEL):
+    return int(lib().orc_num_test_fns(C.byref(m.c), C.c_int(which)))
+
+
+def test_fns(m: Model, theta, state, t, which=TEST_MODEL):
+    """Test functions at one particle (Section 5.2's g1..g3 for EGARCH)."""
+    g = np.zeros(num_test_fns(m, which))
+    th, st = _f64(theta), _f64(state if state is not None and len(state) else np.zeros(8))
+    lib().orc_test_fns(C.byref(m.c), C.c_int(which), _dp(th), _dp(st), C.c_int64(t), _dp(g))
+    return g
+
+
+def report(J, N, g):
+    """Posterior moment report of g[P, G]: rows (mean, sd, NSE, RNE)."""
+    g = _f64(g)
+    G = g.shape[1]
+    out = np.zeros((G, 4))
+    lib().orc_report(C.c_int32(J), C.c_int32(N), C.c_int(G), _dp(g), _dp(out))
+    return out
+
+
+def test_report(m: Model, pop, t, which=TEST_MODEL):
+    out = np.zeros((num_test_fns(m, which), 4))
+    lib().orc_test_report(C.byref(m.c), C.byref(pop.c), C.c_int(which), C.c_int64(t), _dp(out))
+    return out
 
 
 def logprior(m: Model, theta):
@@ -305,18 +336,21 @@ def log_ml(group_logwbar):
 
 
 class Record:
-    def __init__(self, J, d, Lmax=400, RmaxRec=128):
-        self.Lmax, self.RmaxRec, self.J, self.d = Lmax, RmaxRec, J, d
+    def __init__(self, J, d, Lmax=400, RmaxRec=128, G=0):
+        self.Lmax, self.RmaxRec, self.J, self.d, self.G = Lmax, RmaxRec, J, d, G
         self.t_end = np.zeros(Lmax, dtype=np.int64)
         self.R = np.zeros(Lmax, dtype=np.int32)
         self.hchol = np.zeros((Lmax, RmaxRec, d, d))
         self.rss = np.zeros(Lmax)
         self.n_acc = np.zeros((Lmax, RmaxRec), dtype=np.int64)
         self.group_logwbar = np.zeros((Lmax, J))
+        self.moments = np.zeros((Lmax, max(G, 1), 4))
         self.c = OrcRecord(0, self.t_end.ctypes.data_as(C.POINTER(C.c_int64)),
                            self.R.ctypes.data_as(C.POINTER(C.c_int32)), _dp(self.hchol),
                            _dp(self.rss), self.n_acc.ctypes.data_as(C.POINTER(C.c_int64)),
-                           _dp(self.group_logwbar), 0.0, 0.0, 0.0, 0)
+                           _dp(self.group_logwbar), 0.0, 0.0, 0.0, 0,
+                           _dp(self.moments) if G else C.POINTER(C.c_double)(),
+                           float("nan"), float("nan"), float("nan"))
 
     @property
     def L(self):
@@ -327,22 +361,27 @@ class Record:
         return dict(L=L, t_end=self.t_end[:L].copy(), R=self.R[:L].copy(),
                     rss=self.rss[:L].copy(), log_ml=self.c.log_ml, nse=self.c.nse,
                     log_ml_tilde=self.c.log_ml_tilde, evals=self.c.evals,
-                    group_logwbar=self.group_logwbar[:L].copy())
+                    group_logwbar=self.group_logwbar[:L].copy(),
+                    moments=self.moments[:L, :self.G].copy() if self.G else None,
+                    log_score=self.c.log_score, log_score_nse=self.c.log_score_nse,
+                    log_score_tilde=self.c.log_score_tilde)
 
 
 def run(m: Model, J, N, seed, run_id=0, check_every=1, force_every=0, D1=0.5, D2=0.2, Rbar=7, kappa=3,
         stop_rule=0, E1=0.35, Rmax=100, scheme=RESIDUAL, kernel=RW, record=None,
-        Lmax=400, RmaxRec=128):
+        Lmax=400, RmaxRec=128, test_fn=TEST_PARAMS, E2=0.90, burn_in=0, moments=False):
     """Whole simulator.  With ``record`` given (a Record filled by an earlier
-    run) the design {t_l, hL_lr, R_l} is replayed (Algorithm 1)."""
+    run) the design {t_l, hL_lr, R_l} is replayed (Algorithm 1).  With
+    ``moments`` the record keeps the test-function report of every cycle."""
     replay = record is not None
-    rec = record if replay else Record(J, m.d, Lmax, RmaxRec)
+    G = num_test_fns(m, test_fn) if moments else 0
+    rec = record if replay else Record(J, m.d, Lmax, RmaxRec, G)
     cfg = OrcCfg(J, N, seed, run_id, check_every, force_every, D1, D2, Rbar, kappa, stop_rule, E1, Rmax,
-                 scheme, kernel, 1 if replay else 0, rec.Lmax, rec.RmaxRec)
+                 scheme, kernel, 1 if replay else 0, rec.Lmax, rec.RmaxRec, test_fn, 0, E2, burn_in)
     pop = Pop(m, J, N)
     if replay:
         # replay writes into a fresh record that shares the design arrays
-        out = Record(J, m.d, rec.Lmax, rec.RmaxRec)
+        out = Record(J, m.d, rec.Lmax, rec.RmaxRec, G)
         out.t_end[:] = rec.t_end
         out.R[:] = rec.R
         out.hchol[:] = rec.hchol

@@ -882,6 +882,115 @@ double orc_rne_mean(const orc_pop *pop) {
   return acc / d;
 }
 
+/* ------------------------------------------------------------------------ */
+/* Functions of interest and their posterior moments (Sections 2.3, 5.2)   */
+/* ------------------------------------------------------------------------ */
+enum { ORC_TEST_PARAMS = 0, ORC_TEST_MODEL = 1 };
+
+/* Number of test functions: the parameters (d), or the model's functions of
+ * interest.  For EGARCH those are Section 5.2's g1 (log volatility), g2 (the
+ * shock's third moment, mixtures only: it is zero for the symmetric shocks)
+ * and g3 (the 3% loss probability; not for Student-t shocks, whose
+ * distribution function is not provided).  The regression uses its
+ * parameters. */
+int orc_num_test_fns(const orc_model *m, int which) {
+  if (which == ORC_TEST_PARAMS || m->kind == ORC_LINREG) return orc_dim(m);
+  if (m->shock == ORC_MIXTURE) return 3;
+  if (m->shock == ORC_GAUSS) return 2;
+  return 1;
+}
+
+static double std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+/* The test functions at parameter theta and state (v_1..v_K, eps_t) at date t:
+ *   g1 = log sigma_Y + sum_k v_kt / 2 = log h_t;
+ *   g2 = E(eps^3) = sum_i p_i (mu_i^3 + 3 mu_i sigma_i^2);
+ *   g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) = F((-0.03 - mu_Y) / h_{t+1}),
+ * F the shock distribution (Phi, or sum_i p_i Phi((x - mu_i) / sigma_i)),
+ * h_{t+1} from eq EGARCH_mod1 one step ahead (no innovation when t = 0). */
+void orc_test_fns(const orc_model *m, int which, const double *th, const double *state, int64_t t,
+                  double *g) {
+  int d = orc_dim(m);
+  if (which == ORC_TEST_PARAMS || m->kind == ORC_LINREG) {
+    for (int i = 0; i < d; ++i) g[i] = th[i];
+    return;
+  }
+  int K = m->K, q = 0;
+  double vs = 0.0, vn = 0.0;
+  double eprev = state[K];
+  for (int k = 0; k < K; ++k) {
+    vs += state[k];
+    double alpha = tanh(th[2 + k]), beta = exp(th[2 + K + k]), gamma = th[2 + 2 * K + k];
+    vn += (t >= 1) ? alpha * state[k] + beta * (fabs(eprev) - sqrt(2.0 / M_PI)) + gamma * eprev : 0.0;
+  }
+  g[q++] = th[1] + vs / 2.0;
+  double pw[ORC_DMAX], mc[ORC_DMAX], sg[ORC_DMAX];
+  if (m->shock == ORC_MIXTURE) {
+    orc_mixture_params(m, th, pw, mc, sg);
+    double m3 = 0.0;
+    for (int i = 0; i < m->I; ++i) m3 += pw[i] * (mc[i] * mc[i] * mc[i] + 3.0 * mc[i] * sg[i] * sg[i]);
+    g[q++] = m3;
+  }
+  if (m->shock == ORC_STUDENT_T) return;
+  double h1 = exp(th[1]) * exp(vn / 2.0);
+  double x = (-0.03 - th[0] / 1000.0) / h1;
+  if (m->shock == ORC_GAUSS) {
+    g[q++] = std_normal_cdf(x);
+  } else {
+    double F = 0.0;
+    for (int i = 0; i < m->I; ++i) F += pw[i] * std_normal_cdf((x - mc[i]) / sg[i]);
+    g[q++] = F;
+  }
+}
+
+/* Posterior moment report of G functions from their values g[P][G] over J
+ * groups of N (Section 2.3): grand mean, standard deviation
+ * (var-hat with divisor NJ - 1), NSE (eq NSE_def) and RNE = var-hat / v-hat
+ * (eq vhat); out[G][4]. */
+void orc_report(int32_t J, int32_t N, int G, const double *g, double *out) {
+  int64_t P = (int64_t)J * N;
+  double *gj = (double *)malloc(sizeof(double) * J);
+  for (int i = 0; i < G; ++i) {
+    double gbar = 0.0;
+    for (int j = 0; j < J; ++j) {
+      double s = 0.0;
+      for (int n = 0; n < N; ++n) s += g[((int64_t)j * N + n) * G + i];
+      gj[j] = s / N;
+      gbar += gj[j];
+    }
+    gbar /= J;
+    double b = 0.0;
+    for (int j = 0; j < J; ++j) b += (gj[j] - gbar) * (gj[j] - gbar);
+    double var = 0.0;
+    for (int64_t p = 0; p < P; ++p) {
+      double e = g[p * G + i] - gbar;
+      var += e * e;
+    }
+    var /= (double)(P - 1);
+    double vhat = (double)N / (double)(J - 1) * b;
+    out[i * 4 + 0] = gbar;
+    out[i * 4 + 1] = sqrt(var);
+    out[i * 4 + 2] = sqrt(b / ((double)J * (J - 1)));
+    out[i * 4 + 3] = var / vhat;
+  }
+  free(gj);
+}
+
+/* The report of the population's test functions at date t (out[G][4]);
+ * returns G. */
+int orc_test_report(const orc_model *m, const orc_pop *pop, int which, int64_t t, double *out) {
+  int G = orc_num_test_fns(m, which);
+  int64_t P = (int64_t)pop->J * pop->N;
+  double *g = (double *)malloc(sizeof(double) * P * G);
+  double zero[ORC_SMAX] = {0};
+  for (int64_t p = 0; p < P; ++p)
+    orc_test_fns(m, which, pop->theta + p * pop->d, pop->S ? pop->state + p * pop->S : zero, t,
+                 g + p * G);
+  orc_report(pop->J, pop->N, G, g, out);
+  free(g);
+  return G;
+}
+
 /* Marginal likelihood from the per-cycle group mean weights (Section 4.2):
  *   log wbar_j = sum_l log wbar_j(l-1),  wbar = J^-1 sum_j wbar_j,
  *   wtilde = prod_l J^-1 sum_j wbar_j(l-1),
@@ -931,6 +1040,10 @@ typedef struct {
   int32_t replay;       /* 0 adaptive, 1 replay the record */
   int32_t Lmax;         /* capacity of the record, cycles */
   int32_t RmaxRec;      /* capacity of the record, iterations per cycle */
+  int32_t test_fn;      /* RNE rule and moment report: ORC_TEST_PARAMS or ORC_TEST_MODEL */
+  int32_t pad_;
+  double E2;            /* RNE threshold after a C phase ending at a date of interest */
+  int64_t burn_in;      /* log-score burn-in date b (a date of interest; 0: none) */
 } orc_cfg;
 
 typedef struct {
@@ -943,6 +1056,8 @@ typedef struct {
   double *group_logwbar; /* [Lmax][J] */
   double log_ml, nse, log_ml_tilde;
   int64_t evals;         /* particle x observation log-density evaluations */
+  double *moments;       /* [Lmax][G][4] report at each cycle end, or NULL */
+  double log_score, log_score_nse, log_score_tilde; /* over (burn_in, T] */
 } orc_record;
 
 /* Returns 0, or a negative code: -1 record too small, -2 non-PD variance,
@@ -952,6 +1067,7 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
   int64_t P = (int64_t)cfg->J * cfg->N;
   int64_t T = m->T;
   double mean[ORC_DMAX], cov[ORC_DMAX * ORC_DMAX], chol[ORC_DMAX * ORC_DMAX];
+  double rep[ORC_DMAX * 4];
   int32_t *anc = (int32_t *)malloc(sizeof(int32_t) * P);
   int status = 0;
   int64_t evals = 0;
@@ -968,6 +1084,7 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
       int64_t next = (t / cfg->force_every + 1) * cfg->force_every;
       if (next < t_stop) t_stop = next;
     }
+    if (cfg->burn_in > t && cfg->burn_in < t_stop) t_stop = cfg->burn_in;
     if (cfg->replay) t_stop = rec->t_end[l];
     double rss_min = cfg->replay ? 0.0 : cfg->D1;
     int64_t t_new = orc_correct(m, pop, t, t_stop, cfg->check_every, rss_min, &rss,
@@ -1002,10 +1119,21 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
       if (cfg->replay || cfg->stop_rule == 0) {
         if (r >= R) break;
       } else {
-        if (orc_rne_mean(pop) > cfg->E1 || r >= cfg->Rmax) break;
+        /* Section 3.3: the higher threshold E2 at dates of interest */
+        int at_date = t_new == T || t_new == cfg->burn_in ||
+                      (cfg->force_every > 0 && t_new % cfg->force_every == 0);
+        double rne_bar = 0.0;
+        int G = orc_test_report(m, pop, cfg->test_fn, t_new, rep);
+        for (int i = 0; i < G; ++i) rne_bar += rep[i * 4 + 3];
+        rne_bar /= G;
+        if (rne_bar > (at_date ? cfg->E2 : cfg->E1) || r >= cfg->Rmax) break;
       }
     }
     if (status) break;
+    if (rec->moments) {
+      int G = orc_num_test_fns(m, cfg->test_fn);
+      orc_test_report(m, pop, cfg->test_fn, t_new, rec->moments + (int64_t)l * G * 4);
+    }
     rec->R[l] = r;
     t = t_new;
     ++l;
@@ -1018,6 +1146,18 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
     rec->log_ml = out[0];
     rec->nse = out[1];
     rec->log_ml_tilde = out[2];
+    /* log score over (b, T]: the cycles starting at or after b */
+    rec->log_score = rec->log_score_nse = rec->log_score_tilde = NAN;
+    if (cfg->burn_in > 0 && cfg->burn_in < T) {
+      int l0 = 0;
+      while (l0 < l && (l0 == 0 ? 0 : rec->t_end[l0 - 1]) < cfg->burn_in) ++l0;
+      if (l0 > 0 && l0 < l && rec->t_end[l0 - 1] == cfg->burn_in) {
+        orc_log_ml(l - l0, cfg->J, rec->group_logwbar + (int64_t)l0 * cfg->J, out);
+        rec->log_score = out[0];
+        rec->log_score_nse = out[1];
+        rec->log_score_tilde = out[2];
+      }
+    }
   }
   free(anc);
   return status;

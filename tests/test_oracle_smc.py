@@ -299,3 +299,129 @@ def test_nse_calibration_proposition1():
         assert rc == 0
         z.append((rec.c.log_ml - exact) / rec.c.nse)
     assert stats.kstest(z, "t", args=(J - 1,)).pvalue > 1e-3
+
+
+# ------------------------------------------- functions of interest (f2) ---
+
+def test_report_is_calibrated_on_iid_and_clustered_draws():
+    """Section 2.3: for independent draws RNE is about 1 and the NSE matches
+    the sampling sd of the grand mean; with every group made of copies of
+    one draw (N copies), RNE is about 1/N."""
+    J, N, G = 8, 64, 2
+    rng = np.random.default_rng(0)
+    nse2, rne, err2 = [], [], []
+    for _ in range(300):
+        g = rng.standard_normal((J * N, G)) * np.array([1.0, 3.0]) + np.array([0.5, -2.0])
+        out = O.report(J, N, g)
+        assert np.allclose(out[:, 0], g.mean(0), rtol=1e-12)
+        nse2.append(out[:, 2] ** 2)
+        rne.append(out[:, 3])
+        err2.append((out[:, 0] - np.array([0.5, -2.0])) ** 2)
+    sd_mean2 = np.array([1.0, 9.0]) / (J * N)
+    assert np.allclose(np.mean(nse2, 0), sd_mean2, rtol=0.1)
+    assert np.allclose(np.mean(err2, 0), sd_mean2, rtol=0.2)
+    # v-hat / var-hat has expectation one (RNE itself is a ratio of them)
+    assert np.allclose(np.mean(1.0 / np.array(rne), 0), 1.0, atol=0.06)
+    # clustered: each group holds N identical values, so var-hat and v-hat
+    # share the between-group sum of squares and RNE = (J - 1) / (NJ - 1)
+    for _ in range(3):
+        g = np.repeat(rng.standard_normal((J, 1)), N, axis=0)
+        assert O.report(J, N, g)[0, 3] == pytest.approx((J - 1) / (N * J - 1), rel=1e-12)
+
+
+def test_report_hand_values():
+    # J = 2 groups of N = 2: group means 1 and 3, grand mean 2
+    g = np.array([[0.0], [2.0], [3.0], [3.0]])
+    out = O.report(2, 2, g)[0]
+    var = ((0 - 2) ** 2 + 0 + 1 + 1) / 3.0
+    assert out[0] == pytest.approx(2.0)
+    assert out[1] == pytest.approx(math.sqrt(var))
+    assert out[2] == pytest.approx(math.sqrt(((1 - 2) ** 2 + (3 - 2) ** 2) / 2.0))
+    assert out[3] == pytest.approx(var / (2.0 / 1.0 * 2.0))
+
+
+@pytest.mark.parametrize("name", ["egarch11", "egarch23"])
+def test_log_volatility_is_the_simulated_path(name):
+    """g1 at the generating parameters is log h_t of the data-generating
+    process, at every date."""
+    w = SD.workload(name, T=300)
+    m = O.Model.from_workload(w)
+    _, _, h = SD.egarch_series(w.theta_true, 300, w.K, w.shock,
+                               SD.DATA_SEED_BASE + (2 if name == "egarch11" else 10 * w.K + w.I),
+                               return_path=True)
+    assert np.allclose(h[:300], np.abs(w.y - w.theta_true[0] / 1000) /
+                       np.abs(SD.egarch_series(w.theta_true, 300, w.K, w.shock,
+                                               SD.DATA_SEED_BASE + (2 if name == "egarch11" else 10 * w.K + w.I),
+                                               return_path=True)[1]), rtol=1e-9)
+    for t in (1, 2, 50, 300):
+        _, st = O.loglik(m, w.theta_true, t=t)
+        g = O.test_fns(m, w.theta_true, st, t)
+        assert g[0] == pytest.approx(math.log(h[t - 1]), rel=1e-10)
+
+
+@pytest.mark.parametrize("name", ["egarch11", "egarch23"])
+def test_loss_probability_and_skewness_by_quadrature(name):
+    """g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) from the conditional density
+    of the next observation (the oracle's likelihood as a function of
+    y_{t+1}, integrated); g2 = its standardised third moment."""
+    T = 41
+    w = SD.workload(name, T=T)
+    m = O.Model.from_workload(w)
+    x = w.theta_true + 0.1 * np.random.default_rng(2).standard_normal(w.d)
+    x[1] = math.log(0.02)  # a scale at which -3% is in the body of the density
+    t = T - 1
+    ll_prev, st = O.loglik(m, x, t=t)
+    g = O.test_fns(m, x, st, t)
+    # conditional density of y_T on a grid
+    muY = x[0] / 1000
+    grid = np.linspace(muY - 1.0, -0.03, 20001)
+    dens = []
+    for yv in grid:
+        y2 = m.y.copy()
+        y2[T - 1] = yv
+        mm = O.Model(O.EGARCH, T, y2, K=w.K, shock=w.shock, I=w.I)
+        dens.append(math.exp(O.loglik(mm, x)[0] - ll_prev))
+    assert g[-1] == pytest.approx(np.trapezoid(dens, grid), rel=5e-6, abs=1e-9)
+    assert 0.001 < g[-1] < 0.999
+    if name == "egarch23":
+        p, mu, sg = O.mixture_params(m, x)
+        # third moment by quadrature of the mixture density
+        z = np.linspace(-15, 15, 60001)
+        f = sum(p[i] * stats.norm.pdf(z, mu[i], sg[i]) for i in range(len(p)))
+        assert g[1] == pytest.approx(np.trapezoid(z ** 3 * f, z), rel=1e-6, abs=1e-9)
+
+
+def test_log_score_matches_closed_form():
+    """log p(y_{b+1:T} | y_{1:b}) with a burn-in b that is a date of interest."""
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    exact = CF.log_predictive(w.y, w.X, 100, w.T)
+    hits = 0
+    for seed in (1, 2, 3):
+        rc, rec, _ = O.run(m, 16, 256, seed, check_every=1, burn_in=100)
+        assert rc == 0
+        s = rec.summary()
+        assert 100 in s["t_end"].tolist()
+        assert abs(s["log_score"] - exact) < 4.0 * s["log_score_nse"]
+        assert s["log_score_nse"] < s["nse"]
+        hits += abs(s["log_score"] - exact) < 2.5 * s["log_score_nse"]
+    assert hits >= 2
+
+
+def test_rne_rule_uses_e2_at_dates_of_interest():
+    w = SD.workload("egarch23", T=120, J=8, N=64)
+    m = O.Model.from_workload(w)
+    rc, rec, _ = O.run(m, 8, 64, 3, check_every=1, force_every=40, stop_rule=1, E1=0.2,
+                       E2=0.6, Rmax=30, test_fn=O.TEST_MODEL, moments=True)
+    assert rc == 0
+    s = rec.summary()
+    for l in range(s["L"]):
+        at_date = s["t_end"][l] % 40 == 0 or s["t_end"][l] == 120
+        rne = s["moments"][l, :, 3].mean()
+        if s["R"][l] < 30:
+            assert rne > (0.6 if at_date else 0.2), (l, rne)
+        if not at_date and s["R"][l] > 1:
+            # one iteration fewer would not have passed E1 at the time (checked
+            # only through the recorded R: the rule stops at the first pass)
+            assert s["R"][l] <= 30
+    assert any(s["t_end"][l] % 40 == 0 for l in range(s["L"]))
