@@ -218,6 +218,35 @@ size_t smc_mala_workspace_bytes(const smc_model *m, int32_t J, int32_t N, int64_
 smc_status smc_log_ml(int32_t L, int32_t J, const double *group_logwbar, double *out,
                       void *stream);
 
+/* Log score over a burn-in (Section 3.3's software outputs; Section 4.2):
+ * log p(y_{b+1:T} | y_{1:b}) from the cycles that start at or after the
+ * burn-in date b, which must be a cycle end (t_end: host [L], the dates of
+ * the L cycles).  out: device [3] as for smc_log_ml.  SMC_E_INVALID_ARG if no
+ * cycle ends at b. */
+smc_status smc_log_score(int32_t L, int32_t J, const double *group_logwbar, const int64_t *t_end,
+                         int64_t burn_in, double *out, void *stream);
+
+/* --- functions of interest (Sections 2.3 and 5.2) ------------------------ */
+
+#define SMC_TEST_PARAMS 0 /* g_i(theta) = theta_i */
+#define SMC_TEST_MODEL 1  /* the model's functions of interest, see below */
+
+/* Number of test functions: d for SMC_TEST_PARAMS; for SMC_TEST_MODEL, EGARCH
+ * has Section 5.2's g1 = log sigma_Y + sum_k v_kt / 2 (log volatility at the
+ * current date), g2 = E(eps^3) (mixture shocks only; zero for symmetric
+ * shocks) and g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) (not for Student-t
+ * shocks), in that order; the regression uses its parameters.  -1 for a NULL
+ * model or a bad `which`. */
+int32_t smc_num_test_functions(const smc_model *m, int32_t which);
+
+/* Posterior moments of the test functions over the (equally weighted)
+ * population at date t: out device [G][4] = (mean, standard deviation with
+ * divisor NJ - 1, NSE of eq NSE_def, RNE = var-hat / v-hat of eq vhat), from
+ * the J group means (Section 2.3).  The state must be the one at date t.
+ * Uses the workspace. */
+smc_status smc_test_moments(const smc_model *m, smc_particles *pop, int64_t t, int32_t which,
+                            double *out, void *stream);
+
 /* --- helpers of the M phase -------------------------------------------- */
 
 /* Pooled particle mean (device [d]), variance V with divisor P - 1 (device
@@ -262,6 +291,11 @@ typedef struct {
   int32_t Lmax;         /* record capacity in cycles */
   int32_t RmaxRec;      /* record capacity in iterations per cycle */
   int64_t max_chunk;    /* C-phase chunk bound, as given to smc_workspace_bytes */
+  int32_t test_fn;      /* SMC_TEST_*: the RNE rule's functions and the moment reports */
+  int32_t reserved;     /* must be 0 */
+  double E2;            /* 0.90: RNE threshold after a C phase that ends at a date of
+                           interest (a multiple of force_every, burn_in or T) */
+  int64_t burn_in;      /* log-score burn-in date b, a date of interest (0 = none) */
 } smc_run_config;
 
 typedef struct {
@@ -279,6 +313,9 @@ typedef struct {
   float *mutate_ms;      /* host [Lmax][RmaxRec] or NULL: when given, each
                             smc_mutate launch is bracketed by HIP events on
                             the run's stream and its duration stored here */
+  double *moments;       /* device [Lmax][G][4] or NULL: smc_test_moments of
+                            cfg->test_fn at the end of every cycle */
+  double *log_score;     /* device [3] or NULL: smc_log_score over cfg->burn_in */
 } smc_run_record;
 
 /* Runs the simulator on `pop` (which must hold a workspace for

@@ -20,6 +20,7 @@ SMC_E_INVALID_ARG, SMC_E_UNSUPPORTED, SMC_E_DEVICE, SMC_E_NUMERIC, SMC_E_WORKSPA
 SMC_MODEL_LINREG, SMC_MODEL_EGARCH = 1, 2
 SMC_SHOCK_GAUSS, SMC_SHOCK_STUDENT_T, SMC_SHOCK_MIXTURE = 0, 1, 2
 SMC_FP64, SMC_FP32 = 0, 1
+SMC_TEST_PARAMS, SMC_TEST_MODEL = 0, 1
 SMC_RESAMPLE_RESIDUAL, SMC_RESAMPLE_MULTINOMIAL = 0, 1
 SMC_RESAMPLE_STRATIFIED, SMC_RESAMPLE_SYSTEMATIC = 2, 3
 SMC_KERNEL_RW, SMC_KERNEL_MALA = 0, 1
@@ -51,14 +52,15 @@ class RunConfig(C.Structure):
                 ("kappa", C.c_int32), ("stop_rule", C.c_int32), ("E1", C.c_double),
                 ("Rmax", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
                 ("replay", C.c_int32), ("Lmax", C.c_int32), ("RmaxRec", C.c_int32),
-                ("max_chunk", C.c_int64)]
+                ("max_chunk", C.c_int64), ("test_fn", C.c_int32), ("reserved", C.c_int32),
+                ("E2", C.c_double), ("burn_in", C.c_int64)]
 
 
 class RunRecord(C.Structure):
     _fields_ = [("L", C.c_int32), ("reserved", C.c_int32), ("t_end", _vp), ("R", _vp),
                 ("rss", _vp), ("n_accept", _vp), ("hchol", _vp), ("group_logwbar", _vp),
                 ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64),
-                ("mutate_ms", _vp)]
+                ("mutate_ms", _vp), ("moments", _vp), ("log_score", _vp)]
 
 
 _L = None
@@ -125,6 +127,12 @@ def lib():
                                     _vp, C.c_size_t, C.c_int32, _vp]
         L.smc_run.restype = st
         L.smc_run.argtypes = [_vp, P(Particles), P(RunConfig), P(RunRecord), _vp]
+        L.smc_num_test_functions.restype = C.c_int32
+        L.smc_num_test_functions.argtypes = [_vp, C.c_int32]
+        L.smc_test_moments.restype = st
+        L.smc_test_moments.argtypes = [_vp, P(Particles), C.c_int64, C.c_int32, _vp, _vp]
+        L.smc_log_score.restype = st
+        L.smc_log_score.argtypes = [C.c_int32, C.c_int32, _vp, _vp, C.c_int64, _vp, _vp]
         _L = L
     return _L
 
@@ -324,10 +332,14 @@ def smc_flags(pop, stream=None):
 class Record:
     """Host and device arrays of a run's design and outputs."""
 
-    def __init__(self, model, J, Lmax=512, RmaxRec=128, time_mutate=False):
+    def __init__(self, model, J, Lmax=512, RmaxRec=128, time_mutate=False, test_fn=None):
+        """``test_fn`` (SMC_TEST_*) also keeps the moment report of every cycle
+        and the log score."""
         import numpy as np
         d, dev = model.d, model.device
         self.Lmax, self.RmaxRec, self.J, self.d = Lmax, RmaxRec, J, d
+        self.test_fn = test_fn
+        self.G = smc_num_test_functions(model, test_fn) if test_fn is not None else 0
         self.t_end = np.zeros(Lmax, dtype=np.int64)
         self.R = np.zeros(Lmax, dtype=np.int32)
         self.rss = np.zeros(Lmax, dtype=np.float64)
@@ -336,10 +348,15 @@ class Record:
         self.group_logwbar = torch.zeros((Lmax, J), dtype=torch.float64, device=dev)
         self.log_ml = torch.zeros(3, dtype=torch.float64, device=dev)
         self.mutate_ms = np.zeros((Lmax, RmaxRec), dtype=np.float32) if time_mutate else None
+        self.moments = (torch.zeros((Lmax, self.G, 4), dtype=torch.float64, device=dev)
+                        if self.G else None)
+        self.log_score = (torch.full((3,), float("nan"), dtype=torch.float64, device=dev)
+                          if self.G else None)
         self.c = RunRecord(0, 0, self.t_end.ctypes.data, self.R.ctypes.data, self.rss.ctypes.data,
                            _ptr(self.n_accept), _ptr(self.hchol), _ptr(self.group_logwbar),
                            _ptr(self.log_ml), 0, 0,
-                           self.mutate_ms.ctypes.data if time_mutate else None)
+                           self.mutate_ms.ctypes.data if time_mutate else None,
+                           _ptr(self.moments), _ptr(self.log_score))
 
     @property
     def L(self):
@@ -352,18 +369,55 @@ class Record:
                     log_ml=float(lm[0]), nse=float(lm[1]), log_ml_tilde=float(lm[2]),
                     evals=self.c.evals, mh_steps=self.c.mh_steps,
                     group_logwbar=self.group_logwbar[:L].cpu().numpy(),
-                    n_accept=self.n_accept[:L].cpu().numpy())
+                    n_accept=self.n_accept[:L].cpu().numpy(),
+                    moments=self.moments[:L].cpu().numpy() if self.G else None,
+                    log_score=(self.log_score.cpu().numpy().tolist() if self.G
+                               else [float("nan")] * 3))
+
+
+def smc_num_test_functions(model, which=SMC_TEST_MODEL):
+    return int(lib().smc_num_test_functions(model.h, which))
+
+
+def smc_test_moments(model, pop, t, which=SMC_TEST_MODEL, out=None, stream=None):
+    """Posterior moments of the test functions at date t: [G, 4] device
+    tensor of (mean, sd, NSE, RNE)."""
+    G = smc_num_test_functions(model, which)
+    if G < 1:
+        raise SmcError(SMC_E_INVALID_ARG, "smc_test_moments")
+    out = out if out is not None else torch.empty((G, 4), dtype=torch.float64, device=model.device)
+    _check(lib().smc_test_moments(model.h, C.byref(pop.c), C.c_int64(t), which, _ptr(out),
+                                  _stream(stream)), "smc_test_moments")
+    return out
+
+
+def smc_log_score(group_logwbar, t_end, burn_in, out=None, stream=None):
+    """Log score over (burn_in, T] from a record's group weights (device [L, J])
+    and cycle dates (host int64 [L])."""
+    import numpy as np
+    L, J = group_logwbar.shape
+    te = np.ascontiguousarray(t_end[:L], dtype=np.int64)
+    out = out if out is not None else torch.empty(3, dtype=torch.float64,
+                                                  device=group_logwbar.device)
+    _check(lib().smc_log_score(L, J, _ptr(group_logwbar.contiguous()), te.ctypes.data,
+                               C.c_int64(burn_in), _ptr(out), _stream(stream)), "smc_log_score")
+    return out
 
 
 def smc_run(model, pop, seed, run=0, check_every=1, force_every=0, D1=0.5, D2=0.2, Rbar=7,
             kappa=3, stop_rule=0, E1=0.35, Rmax=100, scheme=SMC_RESAMPLE_RESIDUAL,
             kernel=SMC_KERNEL_RW, record=None, replay=False, Lmax=512, RmaxRec=128,
-            stream=None):
-    """Whole simulator (adaptive, or replay of ``record``'s design)."""
+            test_fn=SMC_TEST_PARAMS, E2=0.90, burn_in=0, stream=None):
+    """Whole simulator (adaptive, or replay of ``record``'s design).  The RNE
+    rule (stop_rule=1) uses ``test_fn``'s functions, with E2 after a C phase
+    that ends at a date of interest; a record made with ``test_fn`` also
+    receives the moment reports and the log score over ``burn_in``."""
     rec = record if record is not None else Record(model, pop.J, Lmax, RmaxRec)
+    if rec.G and rec.test_fn != test_fn:
+        raise ValueError("the record's test functions differ from test_fn")
     cfg = RunConfig(pop.J, pop.N, Rng(seed, run), check_every, force_every, D1, D2, Rbar, kappa,
                     stop_rule, E1, Rmax, scheme, kernel, 1 if replay else 0, rec.Lmax,
-                    rec.RmaxRec, pop.max_chunk)
+                    rec.RmaxRec, pop.max_chunk, test_fn, 0, E2, burn_in)
     _check(lib().smc_run(model.h, C.byref(pop.c), C.byref(cfg), C.byref(rec.c), _stream(stream)),
            "smc_run")
     return rec
@@ -386,7 +440,8 @@ def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, wa
         r = records[i]
         cfgs[i] = RunConfig(pops[i].J, pops[i].N, Rng(seeds[i], runs[i]), 1, 0, D1, D2, Rbar,
                             kappa, 0, 0.35, 100, SMC_RESAMPLE_RESIDUAL, SMC_KERNEL_RW,
-                            1 if replay else 0, r.Lmax, r.RmaxRec, pops[i].max_chunk)
+                            1 if replay else 0, r.Lmax, r.RmaxRec, pops[i].max_chunk,
+                            SMC_TEST_PARAMS, 0, 0.90, 0)
         recs[i] = r.c
     hs = (_vp * n)(*[m.h.value for m in models])
     ps = (C.POINTER(Particles) * n)(*[C.pointer(p.c) for p in pops])

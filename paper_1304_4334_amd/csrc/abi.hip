@@ -454,6 +454,39 @@ smc_status smc_adapt_scale(const int64_t *n_accept, int64_t P, int32_t target_pe
   return launch_adapt(n_accept, P, target_permille, mh, as_stream(stream));
 }
 
+int32_t smc_num_test_functions(const smc_model *m, int32_t which) {
+  if (!m || (which != SMC_TEST_PARAMS && which != SMC_TEST_MODEL)) return -1;
+  return num_test_fns(m->dev, which);
+}
+
+smc_status smc_test_moments(const smc_model *m, smc_particles *pop, int64_t t, int32_t which,
+                            double *out, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!out) return set_error(SMC_E_INVALID_ARG, "NULL output");
+  if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date %lld", (long long)t);
+  const int32_t G = smc_num_test_functions(m, which);
+  if (G < 1) return set_error(SMC_E_INVALID_ARG, "test functions %d", which);
+  hipStream_t s = as_stream(stream);
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  double *g = ws_at<double>(pop, L.gather);  // [G][P], G <= 2d + S + 2 rows
+  if ((st = launch_test_fns(m->dev, P, pop->theta, pop->state, t, which, g, s))) return st;
+  return launch_report(g, pop->J, pop->N, G, ws_at<double>(pop, L.rpart), out, nullptr, s);
+}
+
+smc_status smc_log_score(int32_t L, int32_t J, const double *group_logwbar, const int64_t *t_end,
+                         int64_t burn_in, double *out, void *stream) {
+  if (L < 1 || J < 2 || !group_logwbar || !t_end || !out)
+    return set_error(SMC_E_INVALID_ARG, "log score needs L >= 1, J >= 2 and arrays");
+  int32_t l0 = 0;
+  while (l0 < L && (l0 == 0 ? 0 : t_end[l0 - 1]) < burn_in) ++l0;
+  if (l0 == 0 || l0 >= L || t_end[l0 - 1] != burn_in)
+    return set_error(SMC_E_INVALID_ARG, "no cycle ends at the burn-in date %lld",
+                     (long long)burn_in);
+  return smc_log_ml(L - l0, J, group_logwbar + (int64_t)l0 * J, out, stream);
+}
+
 smc_status smc_rne(const smc_model *m, const smc_particles *pop, double *rne, void *stream) {
   smc_status st;
   if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
@@ -489,6 +522,11 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     return set_error(SMC_E_INVALID_ARG, "kernel %d", cfg->kernel);
   if (cfg->kernel == SMC_KERNEL_MALA && !pop->grad)
     return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
+  if (cfg->reserved != 0) return set_error(SMC_E_INVALID_ARG, "reserved field must be 0");
+  const int32_t G = smc_num_test_functions(m, cfg->test_fn);
+  if (G < 1) return set_error(SMC_E_INVALID_ARG, "test functions %d", cfg->test_fn);
+  if (cfg->burn_in < 0 || cfg->burn_in >= m->dev.T)
+    return set_error(SMC_E_INVALID_ARG, "burn-in date %lld", (long long)cfg->burn_in);
   hipStream_t s = as_stream(stream);
   const int64_t P = (int64_t)pop->J * pop->N;
   const int32_t d = m->dev.d;
@@ -529,6 +567,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     if (l >= cfg->Lmax) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
     int64_t t_stop = T;
     if (cfg->force_every > 0) t_stop = std::min(t_stop, (t / cfg->force_every + 1) * cfg->force_every);
+    if (cfg->burn_in > t) t_stop = std::min(t_stop, cfg->burn_in);
     if (cfg->replay) {
       t_stop = rec->t_end[l];
       if (t_stop <= t || t_stop > T)
@@ -587,15 +626,28 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       if (cfg->replay || cfg->stop_rule == 0) {
         if (r >= R) break;
       } else {
+        // mean RNE of the test functions; the higher threshold E2 after a C
+        // phase that ended at a date of interest (Section 3.3)
         double *rne_d = ws_at<double>(pop, L.small + kSmallRne);
-        if ((st = smc_rne(m, pop, rne_d, stream))) return st;
+        double *g = ws_at<double>(pop, L.gather);
+        double *rep = ws_at<double>(pop, L.small + kSmallCov);  // [G][4] scratch
+        if ((st = launch_test_fns(m->dev, P, pop->theta, pop->state, t_new, cfg->test_fn, g, s)) ||
+            (st = launch_report(g, pop->J, pop->N, G, ws_at<double>(pop, L.rpart), rep, rne_d,
+                                s)))
+          return st;
         double rne = 0.0;
         if (hipMemcpyAsync(&rne, rne_d, sizeof(double), hipMemcpyDeviceToHost, s) != hipSuccess ||
             hipStreamSynchronize(s) != hipSuccess)
           return set_error(SMC_E_DEVICE, "reading the RNE failed");
-        if (rne > cfg->E1 || r >= cfg->Rmax) break;
+        const bool at_date = t_new == T || t_new == cfg->burn_in ||
+                             (cfg->force_every > 0 && t_new % cfg->force_every == 0);
+        if (rne > (at_date ? cfg->E2 : cfg->E1) || r >= cfg->Rmax) break;
       }
     }
+    if (rec->moments &&
+        (st = smc_test_moments(m, pop, t_new, cfg->test_fn, rec->moments + (int64_t)l * G * 4,
+                               stream)))
+      return st;
     if (!cfg->replay) {
       rec->t_end[l] = t_new;
       rec->R[l] = r;
@@ -618,6 +670,10 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   rec->evals = evals;
   rec->mh_steps = steps;
   if ((st = smc_log_ml(l, pop->J, rec->group_logwbar, rec->log_ml, stream))) return st;
+  if (rec->log_score && cfg->burn_in > 0 &&
+      (st = smc_log_score(l, pop->J, rec->group_logwbar, rec->t_end, cfg->burn_in, rec->log_score,
+                          stream)))
+    return st;
   if (!timed.v.empty()) {
     if (hipStreamSynchronize(s) != hipSuccess)
       return set_error(SMC_E_DEVICE, "synchronising for the timings failed");
@@ -669,6 +725,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
       return set_error(SMC_E_INVALID_ARG, "run %d: bad record capacity", i);
     if (c.kernel != SMC_KERNEL_RW || c.stop_rule != 0)
       return set_error(SMC_E_UNSUPPORTED, "batched runs use the random walk and fixed R_l");
+    if (c.burn_in != 0 || r.moments || r.log_score || c.reserved != 0)
+      return set_error(SMC_E_UNSUPPORTED, "batched runs: no burn-in, moment reports or log score");
     if ((c.replay != 0) != replay)
       return set_error(SMC_E_INVALID_ARG, "all runs of a batch adapt, or all replay");
     const DevModel &dm = m->dev;

@@ -613,6 +613,36 @@ __global__ void k_rne_final(const double *part, int32_t J, int32_t N, int32_t d,
   *rne = acc / (double)d;
 }
 
+// Moment report from k_rne_group's group means and within-group sums of
+// squares (Section 2.3): mean, sd = var-hat^(1/2), NSE (eq NSE_def), RNE =
+// var-hat / v-hat (eq vhat); and the mean RNE over the G functions.
+__global__ void k_report_final(const double *part, int32_t J, int32_t N, int32_t G, double *out,
+                               double *rne_mean) {
+  if (threadIdx.x != 0) return;
+  double acc = 0.0;
+  for (int i = 0; i < G; ++i) {
+    double g = 0.0, w = 0.0;
+    for (int j = 0; j < J; ++j) {
+      g += part[(int64_t)j * 2 * kDMax + i];
+      w += part[(int64_t)j * 2 * kDMax + kDMax + i];
+    }
+    g /= (double)J;
+    double b = 0.0;
+    for (int j = 0; j < J; ++j) {
+      const double e = part[(int64_t)j * 2 * kDMax + i] - g;
+      b += e * e;
+    }
+    const double var = (w + (double)N * b) / ((double)N * J - 1.0);
+    const double vhat = (double)N * b / (double)(J - 1);
+    out[i * 4 + 0] = g;
+    out[i * 4 + 1] = sqrt(var);
+    out[i * 4 + 2] = sqrt(b / ((double)J * (J - 1)));
+    out[i * 4 + 3] = var / vhat;
+    acc += var / vhat;
+  }
+  if (rne_mean) *rne_mean = acc / (double)G;
+}
+
 // log wbar, its delta-method NSE and log wtilde from group_logwbar[L][J].
 __global__ void __launch_bounds__(256) k_log_ml(int32_t L, int32_t J, const double *g,
                                                 double *out) {
@@ -738,6 +768,17 @@ smc_status launch_mutate_mala(const DevModel &m, int64_t P, int64_t t, double *t
            : SMC_E_UNSUPPORTED;
 }
 
+int32_t num_test_fns(const DevModel &m, int32_t which) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->num_tests(which) : -1;
+}
+
+smc_status launch_test_fns(const DevModel &m, int64_t P, const double *theta, const void *state,
+                           int64_t t, int32_t which, double *out, hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->test_fns(m, P, theta, state, t, which, out, s) : SMC_E_UNSUPPORTED;
+}
+
 // ------------------------------------------------- model-independent ones --
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s) {
@@ -807,6 +848,17 @@ smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, doub
   if (st) return st;
   hipLaunchKernelGGL(k_rne_final, dim3(1), dim3(64), 0, s, part, J, N, d, rne);
   return launch_status("rne/final");
+}
+
+smc_status launch_report(const double *g, int32_t J, int32_t N, int32_t G, double *part,
+                         double *out, double *rne_mean, hipStream_t s) {
+  if (G < 1 || G > kDMax) return set_error(SMC_E_UNSUPPORTED, "report of %d functions", G);
+  const int64_t P = (int64_t)J * N;
+  hipLaunchKernelGGL(k_rne_group, dim3(J), dim3(kBlock), 0, s, g, P, N, G, part);
+  smc_status st = launch_status("report/group");
+  if (st) return st;
+  hipLaunchKernelGGL(k_report_final, dim3(1), dim3(64), 0, s, part, J, N, G, out, rne_mean);
+  return launch_status("report/final");
 }
 
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s) {

@@ -47,6 +47,9 @@ struct ModelOps {
   smc_status (*mutate_mala)(const DevModel &, int64_t, int64_t, double *, double *, double *,
                             void *, double *, const double *, uint64_t, uint64_t, uint64_t,
                             uint64_t, int64_t *, uint8_t *, void *, hipStream_t);
+  int32_t (*num_tests)(int32_t which);
+  smc_status (*test_fns)(const DevModel &, int64_t, const double *, const void *, int64_t,
+                         int32_t, double *, hipStream_t);
 };
 const ModelOps *ops_linreg(const DevModel &m);     // ops_linreg.hip
 const ModelOps *ops_egarch(const DevModel &m);     // ops_egarch.hip: Gaussian, Student-t
@@ -102,6 +105,13 @@ smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permi
 smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, double *part,
                       double *rne, hipStream_t s);
 smc_status launch_log_ml(int32_t L, int32_t J, const double *g, double *out, hipStream_t s);
+// Posterior moment report of G rows g[G][P] (J groups of N): out[G][4] =
+// (mean, sd, NSE, RNE); rne_mean (device scalar, may be NULL) = mean RNE.
+smc_status launch_report(const double *g, int32_t J, int32_t N, int32_t G, double *part,
+                         double *out, double *rne_mean, hipStream_t s);
+int32_t num_test_fns(const DevModel &m, int32_t which);  // -1 if unsupported
+smc_status launch_test_fns(const DevModel &m, int64_t P, const double *theta, const void *state,
+                           int64_t t, int32_t which, double *out, hipStream_t s);
 
 // Bytes of the adjoint checkpoints of P particles over t observations.
 size_t adjoint_ckpt_bytes(const DevModel &m, int64_t P, int64_t t);

@@ -126,6 +126,73 @@ struct Egarch {
     else return m.y;
   }
 
+  // Normalised mixture components (eqs EGARCH_tran1/2): weights p_i, means
+  // mu_i and scales sigma_i, with mean 0 and variance 1.
+  __device__ static void mixture(const double *th, double *pw, double *mu, double *sg) {
+    constexpr int b = 2 + 3 * K;
+    double ps = 0.0, pm = 0.0, q = 0.0;
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      pw[i] = tanh(th[b + i]) + 1.0;
+      ps += pw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      pw[i] /= ps;
+      pm += pw[i] * th[b + I + i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      mu[i] = th[b + I + i] - pm;
+      sg[i] = exp(th[b + 2 * I + i]);
+      q += pw[i] * (mu[i] * mu[i] + sg[i] * sg[i]);
+    }
+    const double c = 1.0 / sqrt(q);
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      mu[i] *= c;
+      sg[i] *= c;
+    }
+  }
+
+  // Functions of interest of Section 5.2 at date t, from theta and the state
+  // (v_1..v_K, eps_t): g1 = log sigma_Y + sum_k v_kt / 2 (log volatility);
+  // for mixtures g2 = E(eps^3) = sum_i p_i (mu_i^3 + 3 mu_i sigma_i^2); and
+  // (not for Student-t shocks) g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) =
+  // F((-0.03 - mu_Y) / h_{t+1}) with h_{t+1} one step of eq EGARCH_mod1 ahead
+  // (no innovation when t = 0) and F the shock's distribution function.
+  static constexpr int kTests = kMix ? 3 : (kT ? 1 : 2);
+  __device__ static void test_fns(const double *th, const R (&st)[S], int64_t t, double *g) {
+    double vs = 0.0, vn = 0.0;
+    const double e = (double)st[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const double v = (double)st[k];
+      vs += v;
+      if (t >= 1)
+        vn += tanh(th[2 + k]) * v + exp(th[2 + K + k]) * (fabs(e) - kSqrt2OverPi) +
+              th[2 + 2 * K + k] * e;
+    }
+    int q = 0;
+    g[q++] = th[1] + 0.5 * vs;
+    if constexpr (kT) return;
+    const double x = (-0.03 - th[0] * 1e-3) / (exp(th[1]) * exp(0.5 * vn));
+    if constexpr (kMix) {
+      double pw[I], mu[I], sg[I];
+      mixture(th, pw, mu, sg);
+      double m3 = 0.0, F = 0.0;
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        m3 += pw[i] * (mu[i] * mu[i] * mu[i] + 3.0 * mu[i] * sg[i] * sg[i]);
+        F += pw[i] * (0.5 * erfc(-(x - mu[i]) / (sg[i] * M_SQRT2)));
+      }
+      g[q++] = m3;
+      g[q++] = F;
+    } else {
+      g[q++] = 0.5 * erfc(-x / M_SQRT2);
+    }
+  }
+
   __device__ static Par params(const double *th) {
     Par p;
 #pragma unroll
@@ -146,31 +213,13 @@ struct Egarch {
       p.hnu1 = 0.5 * (nu + 1.0);
       p.cst = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * (nu - 2.0));
     } else if constexpr (kMix) {
-      constexpr int b = 2 + 3 * K;
-      double pw[I], mc[I], sg[I], ps = 0.0, pm = 0.0, q = 0.0;
+      double pw[I], mu[I], sg[I];
+      mixture(th, pw, mu, sg);
 #pragma unroll
       for (int i = 0; i < I; ++i) {
-        pw[i] = tanh(th[b + i]) + 1.0;
-        ps += pw[i];
-      }
-#pragma unroll
-      for (int i = 0; i < I; ++i) {
-        pw[i] /= ps;
-        pm += pw[i] * th[b + I + i];
-      }
-#pragma unroll
-      for (int i = 0; i < I; ++i) {
-        mc[i] = th[b + I + i] - pm;
-        sg[i] = exp(th[b + 2 * I + i]);
-        q += pw[i] * (mc[i] * mc[i] + sg[i] * sg[i]);
-      }
-      const double c = 1.0 / sqrt(q);
-#pragma unroll
-      for (int i = 0; i < I; ++i) {
-        const double si = c * sg[i];
-        p.mu[i] = (R)(c * mc[i]);
-        p.lw[i] = (R)(log2(pw[i]) - log2(si));
-        p.nb[i] = (R)(-kLog2e / (2.0 * si * si));
+        p.mu[i] = (R)mu[i];
+        p.lw[i] = (R)(log2(pw[i]) - log2(sg[i]));
+        p.nb[i] = (R)(-kLog2e / (2.0 * sg[i] * sg[i]));
       }
       p.inu2 = (R)0;
       p.hnu1 = 0.5;
@@ -428,6 +477,15 @@ struct Linreg {
   };
 
   __device__ static const Y *ydata(const DevModel &m) { return m.y; }
+
+  // Functions of interest: the parameters themselves.
+  static constexpr int kTests = D;
+  __device__ static void test_fns(const double *th, const double (&st)[S], int64_t t, double *g) {
+    (void)st;
+    (void)t;
+#pragma unroll
+    for (int i = 0; i < D; ++i) g[i] = th[i];
+  }
 
   __device__ static Par params(const double *th) {
     Par p;

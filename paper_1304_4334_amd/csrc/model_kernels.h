@@ -351,6 +351,34 @@ __global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int6
   if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
 }
 
+// ---------------------------------------------- functions of interest (f) --
+// out[i][p]: the parameters (which = 0) or the model's functions of interest
+// (which = 1) of every particle at date t.
+template <class M>
+__global__ void __launch_bounds__(64) k_test_fns(DevModel dm, int64_t P, const double *theta,
+                                                 const void *state, int64_t t, int32_t which,
+                                                 double *out) {
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  if (p >= P) return;
+  double th[M::D];
+#pragma unroll
+  for (int i = 0; i < M::D; ++i) th[i] = theta[i * P + p];
+  if (which == 0) {
+#pragma unroll
+    for (int i = 0; i < M::D; ++i) out[i * P + p] = th[i];
+    return;
+  }
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  R st[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
+  double g[M::kTests];
+  M::test_fns(th, st, t, g);
+#pragma unroll
+  for (int q = 0; q < M::kTests; ++q) out[q * P + p] = g[q];
+}
+
 // Models with a hand-written adjoint (the normal-mixture shock has none).
 template <class M>
 struct HasAdjoint : std::true_type {};
@@ -434,6 +462,15 @@ struct OpsOf {
     }
   }
 
+  static int32_t num_tests(int32_t which) { return which == 0 ? M::D : M::kTests; }
+
+  static smc_status test_fns(const DevModel &m, int64_t P, const double *theta, const void *state,
+                             int64_t t, int32_t which, double *out, hipStream_t s) {
+    hipLaunchKernelGGL(k_test_fns<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, t,
+                       which, out);
+    return launch_status("test_functions");
+  }
+
   static smc_status mutate_mala(const DevModel &m, int64_t P, int64_t t, double *theta,
                                 double *logprior, double *loglik, void *state, double *grad,
                                 const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
@@ -456,7 +493,8 @@ const ModelOps *ops_table() {
                           &OpsOf<M>::ccommit,    &OpsOf<M>::mutate_rw,
                           &OpsOf<M>::loglik,     &OpsOf<M>::ckpt_bytes,
                           &OpsOf<M>::loglik_backward, &OpsOf<M>::grad_post,
-                          &OpsOf<M>::mutate_mala};
+                          &OpsOf<M>::mutate_mala, &OpsOf<M>::num_tests,
+                          &OpsOf<M>::test_fns};
   return &o;
 }
 

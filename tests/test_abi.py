@@ -35,7 +35,9 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(S._lib.ModelDesc) == 6 * 4 + 8 + 3 * 8
     assert C.sizeof(S._lib.Particles) == 8 + 8 * 8 + 8
     assert C.sizeof(S._lib.Rng) == 16
-    assert S._lib.RunConfig.max_chunk.offset == C.sizeof(S._lib.RunConfig) - 8
+    assert S._lib.RunConfig.max_chunk.offset % 8 == 0
+    assert S._lib.RunConfig.burn_in.offset == C.sizeof(S._lib.RunConfig) - 8
+    assert S._lib.RunRecord.log_score.offset == C.sizeof(S._lib.RunRecord) - 8
 
 
 def _desc(**kw):
@@ -74,6 +76,28 @@ def test_model_dims_and_workspace():
         assert L.smc_workspace_bytes(h, 0, 256, 16) == 0
         L.smc_model_destroy(h)
     assert L.smc_model_dim(None) == -1
+
+
+def test_number_of_test_functions():
+    L = S._lib.lib()
+    for kw, want in [(dict(), 2), (dict(K=2, shock=1), 1), (dict(K=2, shock=2, ncomp=3), 3),
+                     (dict(kind=1, nreg=3, X=C.c_void_p(0x1000)), 4)]:
+        h = C.c_void_p()
+        assert L.smc_model_create(C.byref(_desc(**kw)), C.byref(h)) == 0
+        assert L.smc_num_test_functions(h, S.SMC_TEST_MODEL) == want
+        assert L.smc_num_test_functions(h, S.SMC_TEST_PARAMS) == L.smc_model_dim(h)
+        assert L.smc_num_test_functions(h, 7) == -1
+        L.smc_model_destroy(h)
+    assert L.smc_num_test_functions(None, 0) == -1
+
+
+def test_log_score_needs_a_cycle_ending_at_the_burn_in():
+    L = S._lib.lib()
+    t_end = (C.c_int64 * 3)(40, 100, 200)
+    fake = C.c_void_p(0x1000)
+    assert L.smc_log_score(3, 4, fake, t_end, 70, fake, None) == -1
+    assert L.smc_log_score(3, 4, fake, t_end, 200, fake, None) == -1
+    assert L.smc_log_score(0, 4, fake, t_end, 40, fake, None) == -1
 
 
 def test_host_side_argument_errors():

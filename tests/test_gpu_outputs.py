@@ -1,0 +1,91 @@
+"""GPU parity of the simulator's reported outputs against the oracle: the
+functions of interest and their posterior moments with NSE and RNE
+(Sections 2.3, 5.2), the RNE stopping rule with E2 at dates of interest
+(Section 3.3) and the log score over a burn-in (Section 4.2).
+
+Tolerances: moments 1e-9 relative (FP64 everywhere; the loss probability
+goes through erfc on both sides); adaptive decisions (cycle ends and M-phase
+lengths) exact; log scores 1e-10 relative on a replayed design and within
+3.5 NSE of the regression's closed form.
+"""
+import numpy as np
+import pytest
+import torch
+
+import oracle as O
+import paper_1304_4334_amd as S
+import synthdata as SD
+from oracle import closed_form as CF
+from tests.gpu_helpers import gpu_model, ora_model, pop_to_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("name,which", [("egarch11", 1), ("egarch23", 1), ("egarch2t", 1),
+                                        ("linreg", 1), ("egarch23", 0), ("egarch34", 1)])
+def test_test_moments_match_oracle(name, which):
+    w = SD.workload(name, T=120)
+    gm, om = gpu_model(w), ora_model(w)
+    J, N = 8, 128
+    opop = O.Pop(om, J, N)
+    opop.theta[:] = SD.random_thetas(w, J * N, 4, spread=0.05)
+    t = 97
+    _, st = O.loglik_batch(om, opop.theta, t)
+    if om.S:
+        opop.state[:, :om.S] = st
+    want = O.test_report(om, opop, t, which)
+    g = pop_to_gpu(gm, opop)
+    got = S.smc_test_moments(gm, g, t, which).cpu().numpy()
+    assert got.shape == want.shape == (S.smc_num_test_functions(gm, which), 4)
+    assert np.allclose(got, want, rtol=1e-9, atol=1e-14), (got, want)
+
+
+def test_rne_rule_with_e2_matches_oracle_run():
+    """Adaptive run with the RNE rule over the model's functions of interest,
+    dates of interest every 40 observations: the same cycle ends, M-phase
+    lengths, reports and log-ML as the oracle's run."""
+    w = SD.workload("egarch23", T=120)
+    gm, om = gpu_model(w), ora_model(w)
+    J, N = 8, 64
+    rc, orec, _ = O.run(om, J, N, 3, check_every=1, force_every=40, stop_rule=1, E1=0.2, E2=0.6,
+                        Rmax=30, test_fn=O.TEST_MODEL, moments=True, Lmax=300, RmaxRec=64)
+    assert rc == 0
+    so = orec.summary()
+    g = S.Population(gm, J, N, max_chunk=32)
+    rec = S.Record(gm, J, Lmax=300, RmaxRec=64, test_fn=S.SMC_TEST_MODEL)
+    S.smc_run(gm, g, seed=3, check_every=1, force_every=40, stop_rule=1, E1=0.2, E2=0.6, Rmax=30,
+              test_fn=S.SMC_TEST_MODEL, record=rec)
+    sg = rec.summary()
+    assert np.array_equal(sg["t_end"], so["t_end"])
+    assert np.array_equal(sg["R"], so["R"])
+    assert np.allclose(sg["moments"], so["moments"], rtol=1e-8, atol=1e-12)
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
+
+
+def test_log_score_replay_matches_oracle_and_closed_form():
+    w = SD.workload("linreg")
+    gm, om = gpu_model(w), ora_model(w)
+    exact = CF.log_predictive(w.y, w.X, 100, w.T)
+    rc, orec, _ = O.run(om, 16, 256, 2, check_every=1, burn_in=100, Lmax=300, RmaxRec=64)
+    assert rc == 0
+    so = orec.summary()
+    L = orec.L
+    g = S.Population(gm, 16, 256, max_chunk=32)
+    rec = S.Record(gm, 16, Lmax=300, RmaxRec=64, test_fn=S.SMC_TEST_PARAMS)
+    rec.t_end[:L] = orec.t_end[:L]
+    rec.R[:L] = orec.R[:L]
+    rec.hchol[:L].copy_(torch.from_numpy(orec.hchol[:L].copy()))
+    S.smc_run(gm, g, seed=2, check_every=1, burn_in=100, record=rec, replay=True)
+    ls = rec.summary()["log_score"]
+    assert ls[0] == pytest.approx(so["log_score"], rel=1e-10)
+    assert ls[1] == pytest.approx(so["log_score_nse"], rel=1e-7)
+    # and an adaptive GPU run against the closed form
+    rec2 = S.Record(gm, 16, Lmax=300, RmaxRec=64, test_fn=S.SMC_TEST_PARAMS)
+    g2 = S.Population(gm, 16, 256, max_chunk=32)
+    S.smc_run(gm, g2, seed=5, check_every=1, burn_in=100, record=rec2)
+    s2 = rec2.summary()
+    assert 100 in s2["t_end"].tolist()
+    assert abs(s2["log_score"][0] - exact) < 3.5 * s2["log_score"][1]
+    # the standalone call agrees with the driver's
+    ls3 = S.smc_log_score(rec2.group_logwbar[:rec2.L], rec2.t_end, 100).cpu().numpy()
+    assert np.allclose(ls3, s2["log_score"], rtol=1e-14)
