@@ -66,6 +66,7 @@ typedef int32_t smc_status;
 
 #define SMC_KERNEL_RW 0   /* Gaussian random walk, Section 3.3 (default) */
 #define SMC_KERNEL_MALA 1 /* preconditioned Langevin proposal (extension) */
+#define SMC_KERNEL_INDEPENDENT 2 /* independent Gaussian sampler, Section 3.3 (experimental) */
 
 #define SMC_FLAG_DEAD_GROUP 1 /* a group had no positive weight (S phase) */
 #define SMC_FLAG_NOT_PD 2     /* particle variance not positive definite */
@@ -178,6 +179,9 @@ smc_status smc_resample(const smc_model *m, smc_particles *pop, int32_t scheme, 
  * state at t.  With kernel = SMC_KERNEL_MALA the proposal mean adds
  * (1/2) hL hL' grad and the acceptance includes the proposal-density ratio;
  * pop->grad must hold the gradient at the current particles and is updated.
+ * With kernel = SMC_KERNEL_INDEPENDENT, hchol holds L (d x d, V = L L') followed
+ * by the particle mean m [d]: theta' = m + L z whatever the current particle,
+ * and the acceptance includes log q(theta) - log q(theta') for q = N(m, V).
  * The number accepted is ADDED to *n_accept (device int64); accepted
  * (device [P] bytes, may be NULL) receives the 0/1 decisions. */
 smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t kernel,
@@ -316,6 +320,8 @@ typedef struct {
   double *moments;       /* device [Lmax][G][4] or NULL: smc_test_moments of
                             cfg->test_fn at the end of every cycle */
   double *log_score;     /* device [3] or NULL: smc_log_score over cfg->burn_in */
+  double *mean;          /* device [Lmax][RmaxRec][d]: the particle means of the
+                            independent sampler (out / in); NULL otherwise */
 } smc_run_record;
 
 /* Runs the simulator on `pop` (which must hold a workspace for
@@ -323,6 +329,17 @@ typedef struct {
  * M iteration under the RNE rule). */
 smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                    smc_run_record *rec, void *stream);
+
+/* Algorithm 3 (hybrid): step 1 runs the adaptive simulator with cfg (cfg->replay
+ * must be 0) into rec1 and retains its design {t_l, Sigma_lr, R_l}; step 2
+ * replays that design into rec2 with the new Philox key (seed2, cfg->rng.run)
+ * for every draw, so step 2 is a run of Algorithm 1 (Proposition 3).  The two
+ * records need the same capacities; rec2's design arrays are overwritten.
+ * seconds (host double [2], may be NULL) receives each step's wall time,
+ * stream synchronised.  pop ends with step 2's particles. */
+smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                          uint64_t seed2, smc_run_record *rec1, smc_run_record *rec2,
+                          double *seconds, void *stream);
 
 /* --- many runs at once (extension: batching) -------------------------- */
 

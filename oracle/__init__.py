@@ -29,7 +29,7 @@ from . import build as _build
 _LIB = None
 
 RESIDUAL, MULTINOMIAL, STRATIFIED, SYSTEMATIC = 0, 1, 2, 3
-RW, MALA = 0, 1
+RW, MALA, INDEP = 0, 1, 2
 LINREG, EGARCH = 1, 2
 GAUSS, STUDENT_T, MIXTURE = 0, 1, 2
 PRIOR, RESAMPLE, PROPOSAL, ACCEPT = 1, 2, 3, 4
@@ -66,7 +66,7 @@ class OrcRecord(C.Structure):
                 ("n_acc", C.POINTER(C.c_int64)), ("group_logwbar", C.POINTER(C.c_double)),
                 ("log_ml", C.c_double), ("nse", C.c_double), ("log_ml_tilde", C.c_double),
                 ("evals", C.c_int64), ("moments", C.POINTER(C.c_double)),
-                ("log_score", C.c_double), ("log_score_nse", C.c_double),
+                ("mean", C.POINTER(C.c_double)), ("log_score", C.c_double), ("log_score_nse", C.c_double),
                 ("log_score_tilde", C.c_double)]
 
 
@@ -129,6 +129,18 @@ class Model:
 
 def num_threads():
     return int(lib().orc_num_threads())
+
+
+def run_hybrid(m: Model, J, N, seed, seed2, **kw):
+    """Algorithm 3: an adaptive run (key (seed, run)), then Algorithm 1 on its
+    design {t_l, hL_lr, R_l} with the new key (seed2, run).  Returns
+    (rc, record1, record2, population after step 2)."""
+    rc, r1, _ = run(m, J, N, seed, **kw)
+    if rc:
+        return rc, r1, None, None
+    kw = {k: v for k, v in kw.items() if k not in ("Lmax", "RmaxRec")}
+    rc, r2, pop = run(m, J, N, seed2, record=r1, **kw)
+    return rc, r1, r2, pop
 
 
 def philox(ctr, key):
@@ -345,12 +357,13 @@ class Record:
         self.n_acc = np.zeros((Lmax, RmaxRec), dtype=np.int64)
         self.group_logwbar = np.zeros((Lmax, J))
         self.moments = np.zeros((Lmax, max(G, 1), 4))
+        self.mean = np.zeros((Lmax, RmaxRec, d))
         self.c = OrcRecord(0, self.t_end.ctypes.data_as(C.POINTER(C.c_int64)),
                            self.R.ctypes.data_as(C.POINTER(C.c_int32)), _dp(self.hchol),
                            _dp(self.rss), self.n_acc.ctypes.data_as(C.POINTER(C.c_int64)),
                            _dp(self.group_logwbar), 0.0, 0.0, 0.0, 0,
                            _dp(self.moments) if G else C.POINTER(C.c_double)(),
-                           float("nan"), float("nan"), float("nan"))
+                           _dp(self.mean), float("nan"), float("nan"), float("nan"))
 
     @property
     def L(self):
@@ -385,6 +398,7 @@ def run(m: Model, J, N, seed, run_id=0, check_every=1, force_every=0, D1=0.5, D2
         out.t_end[:] = rec.t_end
         out.R[:] = rec.R
         out.hchol[:] = rec.hchol
+        out.mean[:] = rec.mean
         rec = out
     rc = lib().orc_run(C.byref(m.c), C.byref(cfg), C.byref(pop.c), C.byref(rec.c))
     return rc, rec, pop

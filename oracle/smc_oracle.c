@@ -726,7 +726,7 @@ int orc_moments(const orc_pop *pop, double *mean, double *cov, double *chol) {
   return 0;
 }
 
-enum { ORC_RW = 0, ORC_MALA = 1 };
+enum { ORC_RW = 0, ORC_MALA = 1, ORC_INDEP = 2 };
 
 /* One M-phase Metropolis iteration (Algorithm 1, step 2c with the Gaussian
  * random walk of Section 3.3) over every particle at date t:
@@ -736,7 +736,11 @@ enum { ORC_RW = 0, ORC_MALA = 1 };
  *   u in (0,1) from counter (p, l, r, ACCEPT), first word.
  * The Langevin variant (kernel = ORC_MALA) adds the drift (1/2)(hL)(hL)' grad
  * log posterior to the proposal mean and the proposal-density ratio to the
- * acceptance test.  `hchol` is hL, d x d row-major lower triangular.
+ * acceptance test.  The independent Gaussian sampler of Section 3.3
+ * (kernel = ORC_INDEP) proposes theta' = mean + L z from the particle mean
+ * and variance, whatever the current particle, and adds
+ * log q(theta) - log q(theta') to the acceptance test.  `hchol` is hL,
+ * d x d row-major lower triangular, followed for ORC_INDEP by the mean [d].
  * Writes accept flags (optional) and returns the number accepted. */
 /* The M step of one particle with global index p (its Philox counters use
  * p): theta (d), lp and ll are updated in place on acceptance, state (S)
@@ -766,10 +770,13 @@ int orc_mutate_particle(const orc_model *m, int64_t p, double *th, double *lp, d
       for (int k = 0; k <= i; ++k) drift[i] += 0.5 * hchol[i * d + k] * w[k];
     }
   }
+  /* the independent sampler centres its proposal on the particle mean, which
+   * follows the d x d factor in hchol */
+  const double *centre = (kernel == ORC_INDEP) ? hchol + d * d : th;
   for (int i = 0; i < d; ++i) {
     double step = 0.0;
     for (int k = 0; k <= i; ++k) step += hchol[i * d + k] * z[k];
-    prop[i] = th[i] + drift[i] + step;
+    prop[i] = centre[i] + drift[i] + step;
   }
   double lp_new = orc_logprior(m, prop);
   int acc = 0;
@@ -805,6 +812,19 @@ int orc_mutate_particle(const orc_model *m, int64_t p, double *th, double *lp, d
     } else {
       orc_state_init(m, st);
       ll_new = orc_loglik_range(m, prop, 0, t, st);
+      if (kernel == ORC_INDEP) {
+        /* q(theta) / q(theta') with q = N(mean, L L'): w = L^-1 (theta - mean),
+         * and L^-1 (theta' - mean) = z */
+        double wv[ORC_DMAX], zz = 0.0, ww = 0.0;
+        for (int i = 0; i < d; ++i) {
+          double s = th[i] - centre[i];
+          for (int k = 0; k < i; ++k) s -= hchol[i * d + k] * wv[k];
+          wv[i] = s / hchol[i * d + i];
+          ww += wv[i] * wv[i];
+          zz += z[i] * z[i];
+        }
+        logq_ratio = -0.5 * ww + 0.5 * zz;
+      }
     }
     double delta = (lp_new + ll_new) - (*lp + *ll) + logq_ratio;
     uint64_t x[4];
@@ -829,7 +849,11 @@ int orc_mutate_particle(const orc_model *m, int64_t p, double *th, double *lp, d
  *   u in (0,1) from counter (p, l, r, ACCEPT), first word.
  * The Langevin variant (kernel = ORC_MALA) adds the drift (1/2)(hL)(hL)' grad
  * log posterior to the proposal mean and the proposal-density ratio to the
- * acceptance test.  `hchol` is hL, d x d row-major lower triangular.
+ * acceptance test.  The independent Gaussian sampler of Section 3.3
+ * (kernel = ORC_INDEP) proposes theta' = mean + L z from the particle mean
+ * and variance, whatever the current particle, and adds
+ * log q(theta) - log q(theta') to the acceptance test.  `hchol` is hL,
+ * d x d row-major lower triangular, followed for ORC_INDEP by the mean [d].
  * Writes accept flags (optional) and returns the number accepted. */
 int64_t orc_mutate(const orc_model *m, orc_pop *pop, int64_t t, int kernel, const double *hchol,
                    uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter, uint8_t *accepted) {
@@ -1036,7 +1060,7 @@ typedef struct {
   double E1;            /* RNE threshold */
   int32_t Rmax;         /* cap on M iterations */
   int32_t scheme;       /* ORC_RESIDUAL, ORC_MULTINOMIAL, ORC_STRATIFIED, ORC_SYSTEMATIC */
-  int32_t kernel;       /* ORC_RW or ORC_MALA */
+  int32_t kernel;       /* ORC_RW, ORC_MALA or ORC_INDEP */
   int32_t replay;       /* 0 adaptive, 1 replay the record */
   int32_t Lmax;         /* capacity of the record, cycles */
   int32_t RmaxRec;      /* capacity of the record, iterations per cycle */
@@ -1057,6 +1081,7 @@ typedef struct {
   double log_ml, nse, log_ml_tilde;
   int64_t evals;         /* particle x observation log-density evaluations */
   double *moments;       /* [Lmax][G][4] report at each cycle end, or NULL */
+  double *mean;          /* [Lmax][RmaxRec][d] particle means (independent sampler), or NULL */
   double log_score, log_score_nse, log_score_tilde; /* over (burn_in, T] */
 } orc_record;
 
@@ -1104,11 +1129,24 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
       ++r;
       if (r > cfg->RmaxRec) { status = -1; break; }
       double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
+      double *mrec = rec->mean ? rec->mean + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d : NULL;
       if (!cfg->replay) {
         if (orc_moments(pop, mean, cov, chol)) { status = -2; break; }
-        for (int i = 0; i < d * d; ++i) hl[i] = (mh / 10.0) * chol[i];
+        /* the independent sampler uses the particle variance unscaled */
+        double h = (cfg->kernel == ORC_INDEP) ? 1.0 : mh / 10.0;
+        for (int i = 0; i < d * d; ++i) hl[i] = h * chol[i];
+        if (mrec)
+          for (int i = 0; i < d; ++i) mrec[i] = mean[i];
       }
-      int64_t acc = orc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->seed, cfg->run,
+      const double *kern_arg = hl;
+      double lm[ORC_DMAX * ORC_DMAX + ORC_DMAX];
+      if (cfg->kernel == ORC_INDEP) {
+        if (!mrec) { status = -1; break; }
+        for (int i = 0; i < d * d; ++i) lm[i] = hl[i];
+        for (int i = 0; i < d; ++i) lm[d * d + i] = mrec[i];
+        kern_arg = lm;
+      }
+      int64_t acc = orc_mutate(m, pop, t_new, cfg->kernel, kern_arg, cfg->seed, cfg->run,
                                (uint64_t)(l + 1), (uint64_t)r, NULL);
       evals += P * t_new;
       rec->n_acc[(int64_t)l * cfg->RmaxRec + (r - 1)] = acc;

@@ -23,7 +23,7 @@ SMC_FP64, SMC_FP32 = 0, 1
 SMC_TEST_PARAMS, SMC_TEST_MODEL = 0, 1
 SMC_RESAMPLE_RESIDUAL, SMC_RESAMPLE_MULTINOMIAL = 0, 1
 SMC_RESAMPLE_STRATIFIED, SMC_RESAMPLE_SYSTEMATIC = 2, 3
-SMC_KERNEL_RW, SMC_KERNEL_MALA = 0, 1
+SMC_KERNEL_RW, SMC_KERNEL_MALA, SMC_KERNEL_INDEPENDENT = 0, 1, 2
 SMC_FLAG_DEAD_GROUP, SMC_FLAG_NOT_PD = 1, 2
 
 _vp = C.c_void_p
@@ -60,7 +60,7 @@ class RunRecord(C.Structure):
     _fields_ = [("L", C.c_int32), ("reserved", C.c_int32), ("t_end", _vp), ("R", _vp),
                 ("rss", _vp), ("n_accept", _vp), ("hchol", _vp), ("group_logwbar", _vp),
                 ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64),
-                ("mutate_ms", _vp), ("moments", _vp), ("log_score", _vp)]
+                ("mutate_ms", _vp), ("moments", _vp), ("log_score", _vp), ("mean", _vp)]
 
 
 _L = None
@@ -127,6 +127,9 @@ def lib():
                                     _vp, C.c_size_t, C.c_int32, _vp]
         L.smc_run.restype = st
         L.smc_run.argtypes = [_vp, P(Particles), P(RunConfig), P(RunRecord), _vp]
+        L.smc_run_hybrid.restype = st
+        L.smc_run_hybrid.argtypes = [_vp, P(Particles), P(RunConfig), C.c_uint64, P(RunRecord),
+                                     P(RunRecord), _vp, _vp]
         L.smc_num_test_functions.restype = C.c_int32
         L.smc_num_test_functions.argtypes = [_vp, C.c_int32]
         L.smc_test_moments.restype = st
@@ -352,11 +355,12 @@ class Record:
                         if self.G else None)
         self.log_score = (torch.full((3,), float("nan"), dtype=torch.float64, device=dev)
                           if self.G else None)
+        self.mean = torch.zeros((Lmax, RmaxRec, d), dtype=torch.float64, device=dev)
         self.c = RunRecord(0, 0, self.t_end.ctypes.data, self.R.ctypes.data, self.rss.ctypes.data,
                            _ptr(self.n_accept), _ptr(self.hchol), _ptr(self.group_logwbar),
                            _ptr(self.log_ml), 0, 0,
                            self.mutate_ms.ctypes.data if time_mutate else None,
-                           _ptr(self.moments), _ptr(self.log_score))
+                           _ptr(self.moments), _ptr(self.log_score), _ptr(self.mean))
 
     @property
     def L(self):
@@ -421,6 +425,44 @@ def smc_run(model, pop, seed, run=0, check_every=1, force_every=0, D1=0.5, D2=0.
     _check(lib().smc_run(model.h, C.byref(pop.c), C.byref(cfg), C.byref(rec.c), _stream(stream)),
            "smc_run")
     return rec
+
+
+def smc_run_hybrid(model, pop, seed, seed2, run=0, check_every=1, force_every=0, D1=0.5, D2=0.2,
+                   Rbar=7, kappa=3, stop_rule=0, E1=0.35, Rmax=100,
+                   scheme=SMC_RESAMPLE_RESIDUAL, kernel=SMC_KERNEL_RW, Lmax=512, RmaxRec=128,
+                   test_fn=None, E2=0.90, burn_in=0, stream=None):
+    """Algorithm 3: an adaptive run with key (seed, run), then its design
+    replayed with key (seed2, run).  Returns (record1, record2, seconds[2])."""
+    import numpy as np
+    tf = SMC_TEST_PARAMS if test_fn is None else test_fn
+    r1 = Record(model, pop.J, Lmax, RmaxRec, test_fn=test_fn)
+    r2 = Record(model, pop.J, Lmax, RmaxRec, test_fn=test_fn)
+    cfg = RunConfig(pop.J, pop.N, Rng(seed, run), check_every, force_every, D1, D2, Rbar, kappa,
+                    stop_rule, E1, Rmax, scheme, kernel, 0, Lmax, RmaxRec, pop.max_chunk, tf, 0,
+                    E2, burn_in)
+    secs = np.zeros(2)
+    _check(lib().smc_run_hybrid(model.h, C.byref(pop.c), C.byref(cfg), C.c_uint64(seed2),
+                                C.byref(r1.c), C.byref(r2.c), secs.ctypes.data, _stream(stream)),
+           "smc_run_hybrid")
+    return r1, r2, secs
+
+
+def hybrid_report(r1, r2, secs=None):
+    """Table 2's rows for the two steps, and the standardised differences of
+    their log-ML (and log score) estimates, |a - b| / sqrt(NSE_a^2 + NSE_b^2)."""
+    import math
+    rows = []
+    for k, r in enumerate((r1, r2)):
+        s = r.summary()
+        rows.append(dict(step=k + 1, seconds=None if secs is None else float(secs[k]),
+                         cycles=s["L"], metropolis_steps=s["mh_steps"], log_ml=s["log_ml"],
+                         nse=s["nse"], log_score=s["log_score"][0],
+                         log_score_nse=s["log_score"][1]))
+    a, b = rows
+    z_ml = abs(a["log_ml"] - b["log_ml"]) / math.hypot(a["nse"], b["nse"])
+    z_ls = (abs(a["log_score"] - b["log_score"]) / math.hypot(a["log_score_nse"], b["log_score_nse"])
+            if not math.isnan(a["log_score"]) else float("nan"))
+    return dict(steps=rows, z_log_ml=z_ml, z_log_score=z_ls)
 
 
 def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, waves=0,

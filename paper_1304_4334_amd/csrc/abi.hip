@@ -7,6 +7,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <vector>
 
 #include "common.h"
@@ -384,6 +385,12 @@ smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t
                               (uint64_t)iter, n_accept, accepted, ws_at<char>(pop, L.wcols),
                               as_stream(stream));
   }
+  if (kernel == SMC_KERNEL_INDEPENDENT) {
+    const int32_t d = m->dev.d;
+    return launch_mutate_indep(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
+                               hchol, hchol + (int64_t)d * d, rng.seed, rng.run, (uint64_t)cycle,
+                               (uint64_t)iter, n_accept, accepted, as_stream(stream));
+  }
   return set_error(SMC_E_INVALID_ARG, "kernel %d", kernel);
 }
 
@@ -518,8 +525,12 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     return set_error(SMC_E_INVALID_ARG, "a record array is NULL");
   if (cfg->Lmax < 1 || cfg->RmaxRec < 1 || cfg->check_every < 1 || cfg->force_every < 0)
     return set_error(SMC_E_INVALID_ARG, "bad record capacity or check spacing");
-  if (cfg->kernel != SMC_KERNEL_RW && cfg->kernel != SMC_KERNEL_MALA)
+  if (cfg->kernel != SMC_KERNEL_RW && cfg->kernel != SMC_KERNEL_MALA &&
+      cfg->kernel != SMC_KERNEL_INDEPENDENT)
     return set_error(SMC_E_INVALID_ARG, "kernel %d", cfg->kernel);
+  const bool indep = cfg->kernel == SMC_KERNEL_INDEPENDENT;
+  if (indep && !rec->mean)
+    return set_error(SMC_E_INVALID_ARG, "the independent sampler records its means");
   if (cfg->kernel == SMC_KERNEL_MALA && !pop->grad)
     return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
   if (cfg->reserved != 0) return set_error(SMC_E_INVALID_ARG, "reserved field must be 0");
@@ -598,13 +609,16 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       if (r > cfg->RmaxRec)
         return set_error(SMC_E_INVALID_ARG, "record holds only %d iterations", cfg->RmaxRec);
       double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
+      double *mslot = indep ? rec->mean + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d : nullptr;
       int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
       if (!cfg->replay) {
         // h starts at 0.5 in each M phase; later iterations first apply the
-        // step-size rule to the previous iteration's acceptances.
-        ma.mh_reset = (r == 1) ? 5 : 0;
-        ma.prev_nacc = (r == 1) ? nullptr : nacc - 1;
+        // step-size rule to the previous iteration's acceptances.  The
+        // independent sampler takes the particle variance unscaled (h = 1).
+        ma.mh_reset = indep ? 10 : ((r == 1) ? 5 : 0);
+        ma.prev_nacc = (r == 1 || indep) ? nullptr : nacc - 1;
         ma.hchol = hl;
+        ma.mean_out = mslot;
         if ((st = launch_moments(ma, s))) return st;
       }
       Timed *ev = nullptr;
@@ -616,9 +630,15 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
             hipEventRecord(ev->a, s) != hipSuccess)
           return set_error(SMC_E_DEVICE, "event setup failed");
       }
-      if ((st = smc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->rng, l + 1, r, nacc, nullptr,
-                           stream)))
+      if (indep) {
+        if ((st = launch_mutate_indep(m->dev, P, t_new, pop->theta, pop->logprior, pop->loglik,
+                                      pop->state, hl, mslot, cfg->rng.seed, cfg->rng.run,
+                                      (uint64_t)(l + 1), (uint64_t)r, nacc, nullptr, s)))
+          return st;
+      } else if ((st = smc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->rng, l + 1, r, nacc,
+                                  nullptr, stream))) {
         return st;
+      }
       if (ev && hipEventRecord(ev->b, s) != hipSuccess)
         return set_error(SMC_E_DEVICE, "event record failed");
       evals += P * t_new;
@@ -683,6 +703,52 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         return set_error(SMC_E_DEVICE, "reading a kernel timing failed");
       rec->mutate_ms[e.slot] = ms;
     }
+  }
+  return SMC_OK;
+}
+
+smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                          uint64_t seed2, smc_run_record *rec1, smc_run_record *rec2,
+                          double *seconds, void *stream) {
+  smc_status st;
+  if ((st = check_model(m))) return st;
+  if (!cfg || !rec1 || !rec2) return set_error(SMC_E_INVALID_ARG, "NULL config or record");
+  if (cfg->replay) return set_error(SMC_E_INVALID_ARG, "step 1 of the hybrid method adapts");
+  if (!rec2->t_end || !rec2->R || !rec2->hchol || !rec1->hchol)
+    return set_error(SMC_E_INVALID_ARG, "a record array is NULL");
+  hipStream_t s = as_stream(stream);
+  const int32_t d = m->dev.d;
+  using clock = std::chrono::steady_clock;
+  auto t0 = clock::now();
+  if ((st = smc_run(m, pop, cfg, rec1, stream))) return st;
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "hybrid: synchronising after step 1 failed");
+  auto t1 = clock::now();
+  // retain the design of step 1 and replay it with the new key
+  const int32_t L = rec1->L;
+  for (int32_t l = 0; l < L; ++l) {
+    rec2->t_end[l] = rec1->t_end[l];
+    rec2->R[l] = rec1->R[l];
+  }
+  if (hipMemcpyAsync(rec2->hchol, rec1->hchol,
+                     (size_t)L * cfg->RmaxRec * d * d * sizeof(double), hipMemcpyDeviceToDevice,
+                     s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "hybrid: copying the design failed");
+  if (cfg->kernel == SMC_KERNEL_INDEPENDENT &&
+      (!rec1->mean || !rec2->mean ||
+       hipMemcpyAsync(rec2->mean, rec1->mean, (size_t)L * cfg->RmaxRec * d * sizeof(double),
+                      hipMemcpyDeviceToDevice, s) != hipSuccess))
+    return set_error(SMC_E_DEVICE, "hybrid: copying the sampler's means failed");
+  smc_run_config c2 = *cfg;
+  c2.replay = 1;
+  c2.rng.seed = seed2;
+  if ((st = smc_run(m, pop, &c2, rec2, stream))) return st;
+  if (hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "hybrid: synchronising after step 2 failed");
+  auto t2 = clock::now();
+  if (seconds) {
+    seconds[0] = std::chrono::duration<double>(t1 - t0).count();
+    seconds[1] = std::chrono::duration<double>(t2 - t1).count();
   }
   return SMC_OK;
 }

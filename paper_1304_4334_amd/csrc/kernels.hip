@@ -733,6 +733,17 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
            : SMC_E_UNSUPPORTED;
 }
 
+smc_status launch_mutate_indep(const DevModel &m, int64_t P, int64_t t, double *theta,
+                               double *logprior, double *loglik, void *state, const double *chol,
+                               const double *mean, uint64_t seed, uint64_t run, uint64_t cycle,
+                               uint64_t iter, int64_t *n_accept, uint8_t *accepted,
+                               hipStream_t s) {
+  const ModelOps *o = ops_for(m);
+  return o ? o->mutate_indep(m, P, t, theta, logprior, loglik, state, chol, mean, seed, run,
+                             cycle, iter, n_accept, accepted, s)
+           : SMC_E_UNSUPPORTED;
+}
+
 smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
                          double *out, void *state_out, hipStream_t s) {
   const ModelOps *o = ops_for(m);

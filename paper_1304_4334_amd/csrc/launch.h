@@ -50,6 +50,9 @@ struct ModelOps {
   int32_t (*num_tests)(int32_t which);
   smc_status (*test_fns)(const DevModel &, int64_t, const double *, const void *, int64_t,
                          int32_t, double *, hipStream_t);
+  smc_status (*mutate_indep)(const DevModel &, int64_t, int64_t, double *, double *, double *,
+                             void *, const double *, const double *, uint64_t, uint64_t,
+                             uint64_t, uint64_t, int64_t *, uint8_t *, hipStream_t);
 };
 const ModelOps *ops_linreg(const DevModel &m);     // ops_linreg.hip
 const ModelOps *ops_egarch(const DevModel &m);     // ops_egarch.hip: Gaussian, Student-t
@@ -100,6 +103,12 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
                             int64_t *n_accept, uint8_t *accepted, hipStream_t s);
 smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
                          double *out, void *state_out, hipStream_t s);
+// The independent Gaussian sampler: chol = L (d x d), mean [d].
+smc_status launch_mutate_indep(const DevModel &m, int64_t P, int64_t t, double *theta,
+                               double *logprior, double *loglik, void *state, const double *chol,
+                               const double *mean, uint64_t seed, uint64_t run, uint64_t cycle,
+                               uint64_t iter, int64_t *n_accept, uint8_t *accepted,
+                               hipStream_t s);
 smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,
                         int32_t *mh, hipStream_t s);
 smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, double *part,

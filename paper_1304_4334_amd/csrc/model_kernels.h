@@ -168,6 +168,72 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
   if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
 }
 
+// The independent Gaussian Metropolis sampler (Section 3.3's alternative):
+// theta' = mean + L z whatever the current particle, accepted with the
+// proposal-density ratio q(theta) / q(theta') = exp(|z|^2/2 - |w|^2/2),
+// L w = theta - mean.
+template <class M>
+__global__ void __launch_bounds__(64) k_mutate_indep(DevModel dm, int64_t P, int64_t t,
+                                                     double *theta, double *logprior,
+                                                     double *loglik, void *state,
+                                                     const double *__restrict__ chol,
+                                                     const double *__restrict__ mean,
+                                                     uint64_t seed, uint64_t run, uint64_t cycle,
+                                                     uint64_t iter, unsigned long long *n_accept,
+                                                     uint8_t *accepted) {
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  int acc = 0;
+  if (p < P) {
+    double th[D], z[D], pr[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
+    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+    double ww = 0.0, zz = 0.0, w[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double s = 0.0, a = th[i] - mean[i];
+#pragma unroll
+      for (int k = 0; k < i; ++k) {
+        s = fma(chol[i * D + k], z[k], s);
+        a = fma(-chol[i * D + k], w[k], a);
+      }
+      s = fma(chol[i * D + i], z[i], s);
+      pr[i] = mean[i] + s;
+      w[i] = a / chol[i * D + i];
+      ww = fma(w[i], w[i], ww);
+      zz = fma(z[i], z[i], zz);
+    }
+    const double lp1 = M::logprior(pr);
+    R st[SR];
+#pragma unroll
+    for (int k = 0; k < SR; ++k) st[k] = (R)0;
+    double ll1 = -INFINITY;
+    if (lp1 > -INFINITY) {
+      const auto par = M::params(pr);
+      ll1 = Eval<M>::advance(dm, par, st, 0, t);
+      const double delta =
+          (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
+      const U64x4 u = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+      acc = (log(u01_oo(u.x0)) < delta) ? 1 : 0;
+    }
+    if (acc) {
+#pragma unroll
+      for (int i = 0; i < D; ++i) theta[i * P + p] = pr[i];
+      logprior[p] = lp1;
+      loglik[p] = ll1;
+#pragma unroll
+      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = st[k];
+    }
+    if (accepted) accepted[p] = (uint8_t)acc;
+  }
+  const unsigned long long mask = __ballot(acc);
+  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
 // ------------------------------------------------- standalone likelihood --
 template <class M>
 __global__ void __launch_bounds__(64) k_loglik(DevModel dm, int64_t P, const double *theta,
@@ -422,6 +488,17 @@ struct OpsOf {
     return launch_status("mutate");
   }
 
+  static smc_status mutate_indep(const DevModel &m, int64_t P, int64_t t, double *theta,
+                                 double *logprior, double *loglik, void *state,
+                                 const double *chol, const double *mean, uint64_t seed,
+                                 uint64_t run, uint64_t cycle, uint64_t iter, int64_t *n_accept,
+                                 uint8_t *accepted, hipStream_t s) {
+    hipLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
+                       logprior, loglik, state, chol, mean, seed, run, cycle, iter,
+                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
+    return launch_status("mutate/independent");
+  }
+
   static smc_status loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
                            double *out, void *state_out, hipStream_t s) {
     hipLaunchKernelGGL(k_loglik<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, t, out,
@@ -494,7 +571,7 @@ const ModelOps *ops_table() {
                           &OpsOf<M>::loglik,     &OpsOf<M>::ckpt_bytes,
                           &OpsOf<M>::loglik_backward, &OpsOf<M>::grad_post,
                           &OpsOf<M>::mutate_mala, &OpsOf<M>::num_tests,
-                          &OpsOf<M>::test_fns};
+                          &OpsOf<M>::test_fns,   &OpsOf<M>::mutate_indep};
   return &o;
 }
 

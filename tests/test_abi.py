@@ -37,7 +37,7 @@ def test_struct_sizes_match_header_layout():
     assert C.sizeof(S._lib.Rng) == 16
     assert S._lib.RunConfig.max_chunk.offset % 8 == 0
     assert S._lib.RunConfig.burn_in.offset == C.sizeof(S._lib.RunConfig) - 8
-    assert S._lib.RunRecord.log_score.offset == C.sizeof(S._lib.RunRecord) - 8
+    assert S._lib.RunRecord.mean.offset == C.sizeof(S._lib.RunRecord) - 8
 
 
 def _desc(**kw):

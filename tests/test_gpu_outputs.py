@@ -89,3 +89,27 @@ def test_log_score_replay_matches_oracle_and_closed_form():
     # the standalone call agrees with the driver's
     ls3 = S.smc_log_score(rec2.group_logwbar[:rec2.L], rec2.t_end, 100).cpu().numpy()
     assert np.allclose(ls3, s2["log_score"], rtol=1e-14)
+
+
+@pytest.mark.parametrize("name,T,J,N", [("linreg", 200, 4, 256), ("egarch11", 300, 4, 128)])
+def test_hybrid_matches_oracle_hybrid(name, T, J, N):
+    """Algorithm 3 on the GPU (adaptive step, then its design replayed with a
+    new key) against the oracle's two steps with the same keys."""
+    w = SD.workload(name, T=T)
+    gm, om = gpu_model(w), ora_model(w)
+    fe = 20 if name == "linreg" else 0
+    rc, o1, o2, opop = O.run_hybrid(om, J, N, 21, 22, check_every=1, force_every=fe, burn_in=100,
+                                    Lmax=300, RmaxRec=64)
+    assert rc == 0
+    g = S.Population(gm, J, N, max_chunk=32)
+    r1, r2, secs = S.smc_run_hybrid(gm, g, 21, 22, check_every=1, force_every=fe, burn_in=100,
+                                    Lmax=300, RmaxRec=64, test_fn=S.SMC_TEST_PARAMS)
+    for r, o in ((r1, o1), (r2, o2)):
+        sg, so = r.summary(), o.summary()
+        assert np.array_equal(sg["t_end"], so["t_end"]) and np.array_equal(sg["R"], so["R"])
+        assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
+        assert sg["log_score"][0] == pytest.approx(so["log_score"], rel=1e-9)
+    rep = S.hybrid_report(r1, r2, secs)
+    assert rep["steps"][0]["cycles"] == rep["steps"][1]["cycles"]
+    assert np.all(secs > 0)
+    assert np.isfinite(rep["z_log_ml"])

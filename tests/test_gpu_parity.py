@@ -397,3 +397,58 @@ def test_adaptive_run_matches_oracle_run():
     assert np.array_equal(sg["t_end"], so["t_end"])
     assert np.array_equal(sg["R"], so["R"])
     assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
+
+
+# --------------------------------------- independent Gaussian sampler (f4) --
+
+@pytest.mark.parametrize("name,prec", [("linreg", 0), ("egarch11", 0), ("egarch23", 0),
+                                       ("egarch2t", 1)])
+def test_independent_sampler_matches_oracle(name, prec):
+    w = SD.workload(name, T=200)
+    gm, om = gpu_model(w, prec), ora_model(w)
+    J, N = 4, 64
+    opop = O.Pop(om, J, N)
+    if name == "linreg":
+        opop.theta[:] = CF.posterior_draws(w.y[:w.T], w.X[:w.T], J * N, np.random.default_rng(3))
+    else:
+        opop.theta[:] = SD.random_thetas(w, J * N, 13, spread=0.02)
+    for p in range(J * N):
+        opop.logprior[p] = O.logprior(om, opop.theta[p])
+    opop.loglik[:], st = O.loglik_batch(om, opop.theta, w.T)
+    if om.S:
+        opop.state[:, :om.S] = st
+    mean, _, chol, rc = O.moments(opop)
+    assert rc == 0
+    arg = np.concatenate([chol.ravel(), mean])
+    g = pop_to_gpu(gm, opop)
+    acc_g = torch.zeros(J * N, dtype=torch.uint8, device="cuda")
+    S.smc_mutate(gm, g, w.T, torch.from_numpy(arg).cuda(), seed=6, run=1, cycle=2, it=5,
+                 kernel=S.SMC_KERNEL_INDEPENDENT, accepted=acc_g)
+    n_o, acc_o = O.mutate(om, opop, w.T, arg, seed=6, run=1, cycle=2, it=5, kernel=O.INDEP)
+    acc_g = acc_g.cpu().numpy()
+    assert 0 < n_o < J * N
+    if prec == S.SMC_FP64:
+        assert np.array_equal(acc_g, acc_o)
+        assert np.allclose(theta_np(g), opop.theta, rtol=1e-12, atol=1e-13)
+    else:
+        assert np.mean(acc_g != acc_o) < 0.05
+        same = acc_g == acc_o
+        assert np.allclose(theta_np(g)[same], opop.theta[same], rtol=1e-12, atol=1e-13)
+
+
+def test_independent_sampler_run_matches_oracle_run():
+    w = SD.workload("linreg")
+    gm, om = gpu_model(w), ora_model(w)
+    rc, orec, opop = O.run(om, 4, 256, 8, check_every=1, force_every=20, kernel=O.INDEP,
+                           Lmax=300, RmaxRec=64)
+    assert rc == 0
+    so = orec.summary()
+    g = S.Population(gm, 4, 256, max_chunk=32)
+    rec = S.smc_run(gm, g, seed=8, check_every=1, force_every=20, kernel=S.SMC_KERNEL_INDEPENDENT,
+                    Lmax=300, RmaxRec=64)
+    sg = rec.summary()
+    assert np.array_equal(sg["t_end"], so["t_end"]) and np.array_equal(sg["R"], so["R"])
+    assert np.allclose(rec.mean[:sg["L"]].cpu().numpy(), orec.mean[:so["L"]], rtol=1e-10,
+                       atol=1e-12)
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
+    assert np.allclose(theta_np(g), opop.theta, rtol=1e-9, atol=1e-10)

@@ -157,10 +157,13 @@ def test_moments_match_numpy():
 
 # ---------------------------------------------------------------- M phase ---
 
-@pytest.mark.parametrize("kernel", [O.RW, O.MALA])
+@pytest.mark.parametrize("kernel", [O.RW, O.MALA, O.INDEP])
 def test_metropolis_leaves_posterior_invariant(kernel):
     """Start from exact posterior draws of the conjugate regression; after
-    several Metropolis iterations the marginals are still the posterior."""
+    several Metropolis iterations the marginals are still the posterior.  The
+    independent sampler gets a deliberately mismatched Gaussian (shifted by
+    0.7 sd, scaled 1.3x), so only a correct proposal-density ratio keeps the
+    posterior invariant."""
     w = SD.workload("linreg")
     m = O.Model.from_workload(w)
     rng = np.random.default_rng(21)
@@ -175,7 +178,10 @@ def test_metropolis_leaves_posterior_invariant(kernel):
     for it in range(1, 7):
         mean, cov, chol, rc = O.moments(pop)
         assert rc == 0
-        n_acc, acc = O.mutate(m, pop, w.T, 0.5 * chol, seed=5, cycle=1, it=it, kernel=kernel)
+        arg = 0.5 * chol
+        if kernel == O.INDEP:
+            arg = np.concatenate([(1.3 * chol).ravel(), mean + 0.7 * np.sqrt(np.diag(cov))])
+        n_acc, acc = O.mutate(m, pop, w.T, arg, seed=5, cycle=1, it=it, kernel=kernel)
         n_acc_tot += n_acc
     assert n_acc_tot > 0.2 * 6 * J * N
     assert np.mean(np.any(pop.theta != start, axis=1)) > 0.8
@@ -425,3 +431,36 @@ def test_rne_rule_uses_e2_at_dates_of_interest():
             # only through the recorded R: the rule stops at the first pass)
             assert s["R"][l] <= 30
     assert any(s["t_end"][l] % 40 == 0 for l in range(s["L"]))
+
+
+def test_hybrid_two_steps_agree_with_closed_form():
+    """Algorithm 3: step 2 replays step 1's design with a new key; both
+    estimate the regression's marginal likelihood and log score."""
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    rc, r1, r2, _ = O.run_hybrid(m, 16, 256, 11, 12, check_every=1, burn_in=100)
+    assert rc == 0
+    s1, s2 = r1.summary(), r2.summary()
+    assert s1["L"] == s2["L"]
+    assert np.array_equal(s1["t_end"], s2["t_end"]) and np.array_equal(s1["R"], s2["R"])
+    assert s1["log_ml"] != s2["log_ml"]  # new particles
+    exact = CF.log_ml(w.y, w.X)
+    exact_ls = CF.log_predictive(w.y, w.X, 100, w.T)
+    for s in (s1, s2):
+        assert abs(s["log_ml"] - exact) < 3.5 * s["nse"]
+        assert abs(s["log_score"] - exact_ls) < 3.5 * s["log_score_nse"]
+    z = abs(s1["log_ml"] - s2["log_ml"]) / math.hypot(s1["nse"], s2["nse"])
+    assert z < 4.0
+
+
+def test_independent_sampler_run_matches_closed_form():
+    """The independent Gaussian sampler (Section 3.3) inside the whole
+    simulator: the regression's marginal likelihood within 3.5 NSE."""
+    w = SD.workload("linreg")
+    m = O.Model.from_workload(w)
+    rc, rec, _ = O.run(m, 16, 256, 4, check_every=1, force_every=20, kernel=O.INDEP)
+    assert rc == 0
+    s = rec.summary()
+    assert abs(s["log_ml"] - CF.log_ml(w.y, w.X)) < 3.5 * s["nse"]
+    # the recorded means are the particle means that centred the proposals
+    assert np.all(np.isfinite(rec.mean[:s["L"], 0]))
