@@ -98,16 +98,22 @@ int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8
 
 // Page-locked host buffer for the C-phase RSS readbacks (one per host
 // thread, kept for the life of the process); NULL if it cannot be had.
+// Pinned host staging for the C-phase RSS columns ([kMaxChunk] doubles),
+// followed by one slot for the flags word the driver reads along with them.
 double *pinned_rss_buffer() {
   thread_local double *buf = nullptr;
   thread_local bool tried = false;
   if (!tried) {
     tried = true;
     void *p = nullptr;
-    if (hipHostMalloc(&p, kMaxChunk * sizeof(double), hipHostMallocDefault) == hipSuccess)
+    if (hipHostMalloc(&p, (kMaxChunk + 1) * sizeof(double), hipHostMallocDefault) == hipSuccess)
       buf = static_cast<double *>(p);
   }
   return buf;
+}
+int32_t *pinned_flags_slot() {
+  double *b = pinned_rss_buffer();
+  return b ? reinterpret_cast<int32_t *>(b + kMaxChunk) : nullptr;
 }
 
 
@@ -584,6 +590,13 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       if (t_stop <= t || t_stop > T)
         return set_error(SMC_E_INVALID_ARG, "replayed date %lld out of order", (long long)t_stop);
     }
+    // The flags raised by the previous cycle's S and M phases travel back
+    // with this cycle's first RSS readback (one host synchronisation fewer
+    // per cycle); a raised flag ends the run after that readback.
+    int32_t *fl_host = cfg->replay ? nullptr : pinned_flags_slot();
+    if (fl_host && l > 0 &&
+        hipMemcpyAsync(fl_host, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
+      return set_error(SMC_E_DEVICE, "reading flags failed");
     int64_t t_new = t;
     double rss = NAN;
     // Speculate on a cycle twice as long as the previous one, so most C
@@ -595,6 +608,10 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
                            rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
                            cfg->replay ? nullptr : &rss, stream, hint)))
       return st;
+    if (fl_host && l > 0 && *fl_host) {  // correct_impl has synchronised the stream
+      rec->L = l;
+      return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", *fl_host, l);
+    }
     last_len = t_new - t;
     evals += P * (t_new - t);
     if ((st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream))) return st;
@@ -675,8 +692,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     rec->rss[l] = rss;
     t = t_new;
     ++l;
-    int32_t fl = 0;
-    if (!cfg->replay) {
+    // without the pinned slot (or after the last cycle) the flags are read here
+    if (!cfg->replay && (!pinned_flags_slot() || t >= T)) {
+      int32_t fl = 0;
       if (hipMemcpyAsync(&fl, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)
         return set_error(SMC_E_DEVICE, "reading flags failed");

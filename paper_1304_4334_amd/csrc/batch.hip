@@ -14,6 +14,7 @@
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
+#include "chol.h"
 #include "model.h"
 #include "rng.h"
 
@@ -82,9 +83,7 @@ __global__ void __launch_bounds__(256) k_batch_mom_partial(BatchArgs a) {
 
 __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   __shared__ double Ms[256];
-  __shared__ double Ls[kDMax * kDMax];
   __shared__ double sh_h;
-  __shared__ int sh_ok;
   const BatchDyn &dy = a.dyn[blockIdx.x];
   const BatchStatic &st = a.runs[dy.idx];
   const int tid = threadIdx.x;
@@ -103,7 +102,6 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
     }
     *st.mh = m;
     sh_h = (double)m / 10.0;
-    sh_ok = 1;
   }
   __syncthreads();
   const double invP = 1.0 / (double)P;
@@ -113,25 +111,8 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
     v = (Ms[r * 16 + c] - Ms[r * 16 + d] * Ms[c * 16 + d] * invP) / (double)(P - 1);
   __syncthreads();
   if (r < d && c < d) Ms[r * 16 + c] = v;
-  Ls[tid] = 0.0;
   __syncthreads();
-  for (int col = 0; col < d; ++col) {
-    if (tid == 0) {
-      double q = Ms[col * 16 + col];
-      for (int t = 0; t < col; ++t) q -= Ls[col * kDMax + t] * Ls[col * kDMax + t];
-      if (q > 0.0 && sh_ok) Ls[col * kDMax + col] = sqrt(q);
-      else sh_ok = 0;
-    }
-    __syncthreads();
-    if (sh_ok && tid > col && tid < d) {
-      double q = Ms[tid * 16 + col];
-      for (int t = 0; t < col; ++t) q -= Ls[tid * kDMax + t] * Ls[col * kDMax + t];
-      Ls[tid * kDMax + col] = q / Ls[col * kDMax + col];
-    }
-    __syncthreads();
-  }
-  if (r < d && c < d) dy.hchol[r * d + c] = (sh_ok && c <= r) ? sh_h * Ls[r * kDMax + c] : 0.0;
-  if (tid == 0 && !sh_ok) atomicOr(st.flags, SMC_FLAG_NOT_PD);
+  if (tid < 64) wave_cholesky<16>(Ms, d, sh_h, dy.hchol, st.flags);
 }
 
 // The random-walk M step of one particle of run `st` (as k_mutate_rw).

@@ -13,6 +13,7 @@
 #include "common.h"
 #include "launch.h"
 #include "model.h"
+#include "chol.h"
 #include "reduce.h"
 #include "rng.h"
 
@@ -480,9 +481,7 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
 template <int W>
 __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
   __shared__ double Ms[W * W];
-  __shared__ double Ls[W * W];
   __shared__ double sh_h;
-  __shared__ int sh_ok;
   const int tid = threadIdx.x;
   const int d = a.d;
   const int64_t P = a.P;
@@ -493,13 +492,21 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
     m = *a.mh;
     if (a.mh_reset <= 0 && a.prev_nacc) nacc = *a.prev_nacc;
   }
+  // Partials are added in block order; up to 64 loads per thread are issued
+  // together (the sums are latency-bound).
+  constexpr int kBatch = 64;
   for (int e = tid; e < W * W; e += 256) {
     const double *pp = a.part + e;
     double sum = 0.0;
-#pragma unroll 16
-    for (int b = 0; b < nb; ++b, pp += W * W) sum += *pp;
+    for (int b0 = 0; b0 < nb; b0 += kBatch) {
+      double x[kBatch];
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q) x[q] = (b0 + q < nb) ? pp[(int64_t)(b0 + q) * W * W] : 0.0;
+#pragma unroll
+      for (int q = 0; q < kBatch; ++q)
+        if (b0 + q < nb) sum += x[q];
+    }
     Ms[e] = sum;
-    Ls[e] = 0.0;
   }
   if (tid == 0) {
     if (a.mh_reset > 0) {
@@ -510,7 +517,6 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
     }
     *a.mh = m;
     sh_h = (double)m / 10.0;
-    sh_ok = 1;
   }
   __syncthreads();
   const double invP = 1.0 / (double)P;
@@ -532,29 +538,7 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
     if (r < d && c < d) Ms[e] = v[q];
   }
   __syncthreads();
-  // Cholesky, column by column: the diagonal by one thread, the column below
-  // it by one thread per row.
-  for (int col = 0; col < d; ++col) {
-    if (tid == 0) {
-      double q = Ms[col * W + col];
-      for (int t = 0; t < col; ++t) q -= Ls[col * W + t] * Ls[col * W + t];
-      if (q > 0.0 && sh_ok) Ls[col * W + col] = sqrt(q);
-      else sh_ok = 0;
-    }
-    __syncthreads();
-    if (sh_ok && tid > col && tid < d) {
-      double q = Ms[tid * W + col];
-      for (int t = 0; t < col; ++t) q -= Ls[tid * W + t] * Ls[col * W + t];
-      Ls[tid * W + col] = q / Ls[col * W + col];
-    }
-    __syncthreads();
-  }
-#pragma unroll
-  for (int q = 0; q < W * W / 256; ++q) {
-    const int e = tid + 256 * q, r = e / W, c = e % W;
-    if (r < d && c < d) a.hchol[r * d + c] = (sh_ok && c <= r) ? sh_h * Ls[r * W + c] : 0.0;
-  }
-  if (tid == 0 && !sh_ok) atomicOr(a.flags, SMC_FLAG_NOT_PD);
+  if (tid < 64) wave_cholesky<W>(Ms, d, sh_h, a.hchol, a.flags);
 }
 
 // ------------------------------------------------ step size, RNE, log-ML --
