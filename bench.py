@@ -78,14 +78,18 @@ def log(msg):
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "mutate_traffic_pmc.md")
 TRAFFIC_KEYS = {("egarch11", "fp64"): "k_mutate_rw egarch11 fp64 P=16384 t=5000 bytes",
-                ("egarch2t", "fp32"): "k_mutate_rw egarch2t fp32 P=65536 t=10000 bytes"}
+                ("egarch2t", "fp32"): "k_mutate_rw egarch2t fp32 P=65536 t=10000 bytes",
+                ("egarch23", "fp32"): "k_mutate_rw egarch23 fp32 P=65536 t=5100 bytes"}
+# Sources whose text defines the mutation kernels the traffic was measured on.
+TRAFFIC_SOURCES = ["paper_1304_4334_amd/csrc/model_kernels.h", "paper_1304_4334_amd/csrc/model.h",
+                   "paper_1304_4334_amd/csrc/rng.h", "paper_1304_4334_amd/csrc/common.h",
+                   "paper_1304_4334_amd/csrc/ops_egarch.hip",
+                   "paper_1304_4334_amd/csrc/ops_mixture32.hip"]
 
 
 def measured_traffic(name, precision):
     """HBM bytes per mutation launch (at t = T) from the committed counter
     passes, or None when the kernel sources changed since they were taken."""
-    import hashlib
-
     key = TRAFFIC_KEYS.get((name, precision))
     if key is None or not os.path.exists(TRAFFIC_FILE):
         return None
@@ -95,13 +99,20 @@ def measured_traffic(name, precision):
         rec = json.loads(block)
     except (IndexError, ValueError):
         return None
-    h = hashlib.sha256()
-    for src in rec["sources"]:
-        with open(os.path.join(ROOT, src), "rb") as f:
-            h.update(f.read())
-    if h.hexdigest() != rec["sources_sha256"]:
+    if rec.get("sources") != TRAFFIC_SOURCES or sources_sha256() != rec["sources_sha256"]:
         return None
     return rec.get(key)
+
+
+def sources_sha256():
+    """Hash of the mutation kernels' sources (the traffic record's key)."""
+    import hashlib
+
+    h = hashlib.sha256()
+    for src in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, src), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
 
 
 def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55), seed=1):
@@ -266,7 +277,7 @@ def kernel_probe():
     """A short fixed sequence for hardware-counter passes: a 256 MiB device
     copy (calibration of the byte counters), then three M steps at t = T of
     each roofline workload (EGARCH(1,1) FP64 16,384 particles; EGARCH(2)-t
-    FP32 65,536 particles)."""
+    FP32 and egarch_23 FP32, 65,536 particles)."""
     import numpy as np
     import torch
 
@@ -279,7 +290,8 @@ def kernel_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     log("[probe] copies done")
-    for name, prec in (("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32)):
+    for name, prec in (("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32),
+                       ("egarch23", S.SMC_FP32)):
         w = SD.workload(name)
         m = S.Model.from_workload(w, precision=prec)
         pop = S.Population(m, w.J, w.N, max_chunk=16)
@@ -291,7 +303,8 @@ def kernel_probe():
             S.smc_mutate(m, pop, w.T, hl, seed=1, it=it + 1)
         torch.cuda.synchronize()
         log(f"[probe] {name} done")
-    print(json.dumps({"probe": "done", "copy_bytes": 2 * a.numel() * 4}), flush=True)
+    print(json.dumps({"probe": "done", "copy_bytes": 2 * a.numel() * 4,
+                      "sources_sha256": sources_sha256()}), flush=True)
 
 
 def main():

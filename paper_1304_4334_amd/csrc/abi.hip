@@ -1006,11 +1006,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         dy.mh_reset = u.r == 0 ? 5 : 0;
         dy.mut_begin = mut;
         mut += (int32_t)((P + 63) / 64);
-        const int64_t waves_r = std::max<int64_t>(1, (P + 63) / 64);
-        int64_t nb = std::min<int64_t>(kMomBlocks, (waves_r + 3) / 4);
-        int64_t ch = (P + 4 * nb - 1) / (4 * nb);
-        ch = ((ch + 31) / 32) * 32;
-        nb = (P + 4 * ch - 1) / (4 * ch);
+        int64_t ch = 0, nb = 0;
+        moment_partition(P, d, ch, nb);
         dy.mom_begin = mom;
         dy.mom_nb = (int32_t)nb;
         dy.mom_chunk = (int32_t)ch;

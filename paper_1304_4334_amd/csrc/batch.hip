@@ -83,6 +83,7 @@ __global__ void __launch_bounds__(256) k_batch_mom_partial(BatchArgs a) {
 
 __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   __shared__ double Ms[256];
+  __shared__ double Ls[256];
   __shared__ double sh_h;
   const BatchDyn &dy = a.dyn[blockIdx.x];
   const BatchStatic &st = a.runs[dy.idx];
@@ -112,7 +113,7 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   __syncthreads();
   if (r < d && c < d) Ms[r * 16 + c] = v;
   __syncthreads();
-  if (tid < 64) wave_cholesky<16>(Ms, d, sh_h, dy.hchol, st.flags);
+  if (tid < 64) wave_cholesky<16>(Ms, Ls, d, sh_h, dy.hchol, st.flags);
 }
 
 // The random-walk M step of one particle of run `st` (as k_mutate_rw).

@@ -46,7 +46,7 @@ struct WsLayout {
 
 constexpr int64_t kMaxChunk = 4096;
 constexpr int64_t kDefaultChunk = 256;
-constexpr int kMomBlocks = 256;
+constexpr int kMomBlocks = 128;  // moment partial blocks (moment_partition keeps nb <= 128)
 
 // Offsets inside the `small` region.
 constexpr size_t kSmallFlags = 0;    // int32

@@ -431,10 +431,11 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
   double4v acc[NA];
 #pragma unroll
   for (int a = 0; a < NA; ++a) acc[a] = double4v{0.0, 0.0, 0.0, 0.0};
-  // Eight MFMA steps per batch with all loads issued first (addresses are
-  // clamped into the wave's range and masked afterwards).
-  for (int64_t q0 = p0; q0 < p1; q0 += 32) {
-    double x[NT][8];
+  // Batches of eight MFMA steps (32 particles).  Each batch's loads are
+  // issued before the previous batch is consumed, so their latency overlaps
+  // the matrix-core work (addresses are clamped into the wave's range and
+  // the values masked afterwards).
+  auto load = [&](int64_t q0, double (&x)[NT][8]) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t p = q0 + 4 * u + k;
@@ -442,6 +443,8 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
 #pragma unroll
       for (int t = 0; t < NT; ++t) x[t][u] = theta[(int64_t)ir[t] * P + pc];
     }
+  };
+  auto consume = [&](int64_t q0, const double (&x)[NT][8]) {
 #pragma unroll
     for (int u = 0; u < 8; ++u) {
       const int64_t p = q0 + 4 * u + k;
@@ -457,6 +460,17 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
         acc[1] = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[1], xm[0], acc[1], 0, 0, 0);
         acc[2] = __builtin_amdgcn_mfma_f64_16x16x4f64(xm[1], xm[1], acc[2], 0, 0, 0);
       }
+    }
+  };
+  double xa[NT][8], xb[NT][8];
+  if (p0 < p1) load(p0, xa);
+  for (int64_t q0 = p0; q0 < p1; q0 += 64) {
+    const int64_t q1 = q0 + 32;
+    if (q1 < p1) load(q1, xb);
+    consume(q0, xa);
+    if (q1 < p1) {
+      if (q1 + 32 < p1) load(q1 + 32, xa);
+      consume(q1, xb);
     }
   }
 #pragma unroll
@@ -474,41 +488,39 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
     part[(int64_t)blockIdx.x * W * W + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
-// Pass 2 (one block): add the partial matrices in block order, optionally
-// apply the step-size rule to mh, form the mean and V (divisor P - 1),
-// factor V = L L' and write h L.  A variance that is not positive definite
-// raises the flag and yields h L = 0.
+// Pass 2 (one block of W * W threads, one entry each): add the partial
+// matrices in block order, optionally apply the step-size rule to mh, form
+// the mean and V (divisor P - 1), factor V = L L' and write h L.  A variance
+// that is not positive definite raises the flag and yields h L = 0.
 template <int W>
-__global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
+__global__ void __launch_bounds__(W * W) k_mom_final(MomArgs a, int32_t nb) {
   __shared__ double Ms[W * W];
+  __shared__ double Ls[W * W];
   __shared__ double sh_h;
-  const int tid = threadIdx.x;
+  const int e = threadIdx.x;  // entry (r, c) = (e / W, e % W)
   const int d = a.d;
   const int64_t P = a.P;
   // the step-size inputs are read first so their latency overlaps the sums
   int32_t m = 0;
   int64_t nacc = 0;
-  if (tid == 0) {
+  if (e == 0) {
     m = *a.mh;
     if (a.mh_reset <= 0 && a.prev_nacc) nacc = *a.prev_nacc;
   }
-  // Partials are added in block order; up to 64 loads per thread are issued
-  // together (the sums are latency-bound).
-  constexpr int kBatch = 64;
-  for (int e = tid; e < W * W; e += 256) {
-    const double *pp = a.part + e;
-    double sum = 0.0;
-    for (int b0 = 0; b0 < nb; b0 += kBatch) {
-      double x[kBatch];
+  // Partials are added in block order, up to 32 loads in flight per thread.
+  constexpr int kBatch = 32;
+  const double *pp = a.part + e;
+  double sum = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += kBatch) {
+    double x[kBatch];
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q) x[q] = (b0 + q < nb) ? pp[(int64_t)(b0 + q) * W * W] : 0.0;
+    for (int q = 0; q < kBatch; ++q) x[q] = (b0 + q < nb) ? pp[(int64_t)(b0 + q) * W * W] : 0.0;
 #pragma unroll
-      for (int q = 0; q < kBatch; ++q)
-        if (b0 + q < nb) sum += x[q];
-    }
-    Ms[e] = sum;
+    for (int q = 0; q < kBatch; ++q)
+      if (b0 + q < nb) sum += x[q];
   }
-  if (tid == 0) {
+  Ms[e] = sum;
+  if (e == 0) {
     if (a.mh_reset > 0) {
       m = a.mh_reset;
     } else if (a.prev_nacc) {
@@ -520,25 +532,17 @@ __global__ void __launch_bounds__(256) k_mom_final(MomArgs a, int32_t nb) {
   }
   __syncthreads();
   const double invP = 1.0 / (double)P;
-  double v[W * W / 256];
-#pragma unroll
-  for (int q = 0; q < W * W / 256; ++q) {
-    const int e = tid + 256 * q, r = e / W, c = e % W;
-    v[q] = 0.0;
-    if (r < d && c < d) {
-      v[q] = (Ms[r * W + c] - Ms[r * W + d] * Ms[c * W + d] * invP) / (double)(P - 1);
-      if (a.cov_out) a.cov_out[r * d + c] = v[q];
-    }
+  const int r = e / W, c = e % W;
+  double v = 0.0;
+  if (r < d && c < d) {
+    v = (Ms[r * W + c] - Ms[r * W + d] * Ms[c * W + d] * invP) / (double)(P - 1);
+    if (a.cov_out) a.cov_out[r * d + c] = v;
   }
-  if (a.mean_out && tid < d) a.mean_out[tid] = a.theta[(int64_t)tid * P] + Ms[tid * W + d] * invP;
+  if (a.mean_out && e < d) a.mean_out[e] = a.theta[(int64_t)e * P] + Ms[e * W + d] * invP;
   __syncthreads();
-#pragma unroll
-  for (int q = 0; q < W * W / 256; ++q) {
-    const int e = tid + 256 * q, r = e / W, c = e % W;
-    if (r < d && c < d) Ms[e] = v[q];
-  }
+  if (r < d && c < d) Ms[e] = v;
   __syncthreads();
-  if (tid < 64) wave_cholesky<W>(Ms, d, sh_h, a.hchol, a.flags);
+  if (e < 64) wave_cholesky<W>(Ms, Ls, d, sh_h, a.hchol, a.flags);
 }
 
 // ------------------------------------------------ step size, RNE, log-ML --
@@ -806,15 +810,25 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
   return launch_status("resample");
 }
 
+// Blocks of four waves (their loads pipelined), few enough that the final
+// block adds few partial matrices; each wave takes `chunk` particles (a
+// multiple of 32).  The batched moments use the same partition, so a run
+// gives the same sums alone or in a batch.
+void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb) {
+  // 16-wide matrices: about 32 blocks; 32-wide ones (four times the data per
+  // partial, three products per step): about 128 blocks, read by a final
+  // block of 1,024 threads.
+  const int64_t target = d + 1 <= 16 ? 32 : 128;
+  chunk = (P + 4 * target - 1) / (4 * target);
+  chunk = ((chunk + 31) / 32) * 32;
+  nb = (P + 4 * chunk - 1) / (4 * chunk);
+}
+
 smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < %d", kDMax);
-  // About 64 particles per wave (two load batches); at most kMomBlocks
-  // blocks of four waves.
-  const int64_t waves = std::max<int64_t>(1, (a.P + 63) / 64);
-  int64_t nb = std::min<int64_t>(kMomBlocks, (waves + 3) / 4);
-  int64_t chunk = (a.P + 4 * nb - 1) / (4 * nb);
-  chunk = ((chunk + 31) / 32) * 32;
-  nb = (a.P + 4 * chunk - 1) / (4 * chunk);
+  int64_t chunk = 0, nb = 0;
+  moment_partition(a.P, a.d, chunk, nb);
+  if (nb > kMomBlocks) return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
   if (a.d + 1 <= 16) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
                        a.d, chunk, a.part);
@@ -824,8 +838,8 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
-  if (a.d + 1 <= 16) hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
-  else hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(kBlock), 0, s, a, (int32_t)nb);
+  if (a.d + 1 <= 16) hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(256), 0, s, a, (int32_t)nb);
+  else hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(1024), 0, s, a, (int32_t)nb);
   return launch_status("particle_moments/final");
 }
 

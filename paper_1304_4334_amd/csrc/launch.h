@@ -97,6 +97,9 @@ struct MomArgs {
   int32_t *flags;
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
+// Particles per wave (chunk) and blocks (nb <= kMomBlocks) of the moment
+// partials of P particles of dimension d.
+void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb);
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
