@@ -52,7 +52,7 @@ WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
   off += align256(P * sizeof(double));
   L.mpart = off;
   const size_t mw = m.d + 1 <= 16 ? 16 : 32;  // padded moments width
-  off += align256((size_t)kMomBlocks * mw * mw * sizeof(double));
+  off += align256((size_t)(kMomBlocks + 1) * mw * mw * sizeof(double));  // + the sums
   L.rpart = off;
   off += align256((size_t)J * 2 * kDMax * sizeof(double));
   L.wcols = off;

@@ -20,19 +20,30 @@ __device__ __forceinline__ void wave_cholesky(const double *Ms, double *Ls, int 
                                               double *hchol, int32_t *flags) {
   const int r = threadIdx.x & 63;
   bool ok = true;
+  constexpr int kU = 8;  // LDS loads issued together (terms past col add 0 exactly)
   for (int col = 0; col < d; ++col) {
-    // the diagonal, computed identically by every lane from row col
+    // the diagonal, computed identically by every lane from row col, and
+    // lane r's entry below it
     double q = Ms[col * W + col];
-    for (int t = 0; t < col; ++t) q -= Ls[col * W + t] * Ls[col * W + t];
+    double b = Ms[(r < d ? r : 0) * W + col];
+    for (int t0 = 0; t0 < col; t0 += kU) {
+      double lc[kU], lr[kU];
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        const bool in = t0 + u < col;
+        lc[u] = in ? Ls[col * W + t0 + u] : 0.0;
+        lr[u] = (in && r > col && r < d) ? Ls[r * W + t0 + u] : 0.0;
+      }
+#pragma unroll
+      for (int u = 0; u < kU; ++u) {
+        q -= lc[u] * lc[u];
+        b -= lr[u] * lc[u];
+      }
+    }
     ok = ok && q > 0.0;
     const double dg = ok ? sqrt(q) : 1.0;
-    if (r > col && r < d) {
-      double b = Ms[r * W + col];
-      for (int t = 0; t < col; ++t) b -= Ls[r * W + t] * Ls[col * W + t];
-      Ls[r * W + col] = b / dg;
-    } else if (r == col) {
-      Ls[col * W + col] = dg;
-    }
+    if (r > col && r < d) Ls[r * W + col] = b / dg;
+    else if (r == col) Ls[col * W + col] = dg;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
   if (r < d)

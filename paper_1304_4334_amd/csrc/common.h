@@ -38,7 +38,7 @@ struct WsLayout {
   size_t rsscols;  // [kMaxChunk] doubles
   size_t gather;   // [2d + S + 2][P] doubles
   size_t cum;      // [P] doubles (resample running sums)
-  size_t mpart;    // [kMomBlocks][kDMax^2] doubles (moments)
+  size_t mpart;    // [kMomBlocks + 1][W^2] doubles (moment partials and their sum)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
   size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
   size_t fixed;    // bytes before wcols

@@ -488,6 +488,26 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
     part[(int64_t)blockIdx.x * W * W + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
+// For 32-wide matrices the partial matrices are first added entry by entry
+// across many blocks (64 entries per block, partials in block order), so the
+// final block reads one matrix.
+__global__ void __launch_bounds__(64) k_mom_sum(const double *part, int32_t nb, int32_t n,
+                                                double *out) {
+  const int e = blockIdx.x * 64 + threadIdx.x;
+  if (e >= n) return;
+  constexpr int kBatch = 32;
+  double sum = 0.0;
+  for (int b0 = 0; b0 < nb; b0 += kBatch) {
+    double x[kBatch];
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q) x[q] = (b0 + q < nb) ? part[(int64_t)(b0 + q) * n + e] : 0.0;
+#pragma unroll
+    for (int q = 0; q < kBatch; ++q)
+      if (b0 + q < nb) sum += x[q];
+  }
+  out[e] = sum;
+}
+
 // Pass 2 (one block of W * W threads, one entry each): add the partial
 // matrices in block order, optionally apply the step-size rule to mh, form
 // the mean and V (divisor P - 1), factor V = L L' and write h L.  A variance
@@ -838,8 +858,17 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
-  if (a.d + 1 <= 16) hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(256), 0, s, a, (int32_t)nb);
-  else hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(1024), 0, s, a, (int32_t)nb);
+  if (a.d + 1 <= 16) {
+    hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(256), 0, s, a, (int32_t)nb);
+  } else {
+    // sums into the slot after the partials, then the final block reads them
+    double *sums = a.part + nb * 1024;
+    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(64), 0, s, a.part, (int32_t)nb, 1024, sums);
+    if ((st = launch_status("particle_moments/sum"))) return st;
+    MomArgs f = a;
+    f.part = sums;
+    hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(1024), 0, s, f, 1);
+  }
   return launch_status("particle_moments/final");
 }
 
