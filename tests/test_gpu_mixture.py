@@ -166,3 +166,36 @@ def test_adjoint_is_unsupported_for_mixtures():
     with pytest.raises(S.SmcError) as e:
         S.smc_loglik_backward(gm, th, 20, torch.ones(4, dtype=torch.float64, device="cuda"))
     assert e.value.status == S.SMC_E_UNSUPPORTED
+
+
+def test_mutate_full_size_sampled():
+    """One M step of egarch_23 at the paper's size (65,536 particles, T =
+    5,100, FP64): sampled particles replayed one by one by the oracle with
+    their global Philox indices."""
+    w = SD.workload("egarch23")
+    gm, om = gpu_model(w), ora_model(w)
+    P = w.P
+    th = _thetas(w, P, 31)
+    g = S.Population(gm, w.J, w.N, max_chunk=16)
+    g.theta.copy_(torch.from_numpy(th.T.copy()))
+    idx = np.concatenate([[0, 1, P - 1], np.random.default_rng(2).choice(P, 9, replace=False)])
+    g.loglik.copy_(S.smc_loglik(gm, g.theta, w.T))
+    lp_o = {int(p): O.logprior(om, th[p]) for p in idx}
+    ll_o = {int(p): O.loglik(om, th[p], w.T)[0] for p in idx}
+    for p in idx:
+        g.loglik[int(p)] = ll_o[int(p)]
+        g.logprior[int(p)] = lp_o[int(p)]
+    hl = np.linalg.cholesky(np.cov(th[::16].T)) * 0.3
+    acc = torch.zeros(P, dtype=torch.uint8, device="cuda")
+    S.smc_mutate(gm, g, w.T, torch.from_numpy(hl).cuda(), seed=4, run=0, cycle=9, it=2,
+                 accepted=acc)
+    acc = acc.cpu().numpy()
+    th_g = theta_np(g)
+    for p in idx:
+        p = int(p)
+        a, th_o, _, ll1, _ = O.mutate_particle(om, p, th[p], lp_o[p], ll_o[p], w.T, hl, seed=4,
+                                               run=0, cycle=9, it=2)
+        assert a == bool(acc[p]), p
+        assert np.allclose(th_g[p], th_o, rtol=1e-12, atol=1e-13)
+        if a:
+            assert g.loglik[p].item() == pytest.approx(ll1, rel=1e-10)
