@@ -33,10 +33,12 @@ __device__ inline double digamma_dev(double x) {
 template <class M>
 __device__ inline void logprior_grad(const double *th, double *g);
 
-template <int K, int SH, typename R>
+// (Within the support of the truncated theta_8i the truncation only adds a
+// constant, so every term is Gaussian.)
+template <int K, int SH, typename R, int I>
 struct PriorGrad {
   __device__ static void run(const double *th, double *g) {
-    using E = Egarch<K, SH, R>;
+    using E = Egarch<K, SH, R, I>;
 #pragma unroll
     for (int i = 0; i < E::D; ++i) {
       double m, sd, lsd;
@@ -56,17 +58,77 @@ struct SegLen {
 template <class M>
 struct Adjoint;
 
-template <int K, int SH, typename R>
-struct Adjoint<Egarch<K, SH, R>> {
-  using Md = Egarch<K, SH, R>;
+template <int K, int SH, typename R, int I>
+struct Adjoint<Egarch<K, SH, R, I>> {
+  using Md = Egarch<K, SH, R, I>;
   using Y = typename Md::Y;
   using Par = typename Md::Par;
   static constexpr int D = Md::D;
   static constexpr int SEG = SegLen<R>::value;
   static constexpr bool kT = Md::kT;
+  static constexpr bool kMix = Md::kMix;
+  static constexpr int kNM = Md::kNM;
   static constexpr int kLdsPerLane = SEG * K;  // values of type R
 
   __device__ static int64_t nseg(int64_t t) { return (t + SEG - 1) / SEG; }
+
+  // Chain rule from the adjoints of the components' constants (lw_i =
+  // log2(p_i / sigma_i), nb_i = -log2(e) / (2 sigma_i^2), mu_i) back through
+  // eqs EGARCH_tran1/2 to theta_6i, theta_7i, theta_8i.
+  __device__ static void mixture_chain(const double *th, const double *lwb, const double *nbb,
+                                       const double *mub, double scale, double *g) {
+    constexpr int b = 2 + 3 * K;
+    double ps[kNM], pw[kNM], mss[kNM], ss[kNM], S = 0.0, mbar = 0.0, q = 0.0;
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      ps[i] = tanh(th[b + i]) + 1.0;
+      S += ps[i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      pw[i] = ps[i] / S;
+      mbar += pw[i] * th[b + I + i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      mss[i] = th[b + I + i] - mbar;  // mu**
+      ss[i] = exp(th[b + 2 * I + i]);  // sigma*
+      q += pw[i] * (mss[i] * mss[i] + ss[i] * ss[i]);
+    }
+    const double c = 1.0 / sqrt(q);
+    // adjoints of the normalised p_i, mu_i, sigma_i
+    double pb[kNM], mb[kNM], sb[kNM], cb = 0.0;
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      const double si = c * ss[i];
+      pb[i] = lwb[i] / (pw[i] * kLn2);
+      sb[i] = -lwb[i] / (si * kLn2) + nbb[i] * kLog2e / (si * si * si);
+      mb[i] = mub[i];
+      cb += mb[i] * mss[i] + sb[i] * ss[i];
+    }
+    const double qb = cb * (-0.5 * c * c * c);
+    double mbarb = 0.0, pdot = 0.0;
+    double mssb[kNM], pbt[kNM];
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      mssb[i] = c * mb[i] + qb * 2.0 * pw[i] * mss[i];
+      mbarb -= mssb[i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      pbt[i] = pb[i] + qb * (mss[i] * mss[i] + ss[i] * ss[i]) + mbarb * th[b + I + i];
+      pdot += pbt[i] * pw[i];
+    }
+#pragma unroll
+    for (int i = 0; i < I; ++i) {
+      const double ssb = c * sb[i] + qb * 2.0 * pw[i] * ss[i];
+      const double psb = (pbt[i] - pdot) / S;
+      const double tn = tanh(th[b + i]);
+      g[b + i] += scale * psb * (1.0 - tn * tn);
+      g[b + I + i] += scale * (mssb[i] + mbarb * pw[i]);
+      g[b + 2 * I + i] += scale * ssb * ss[i];
+    }
+  }
 
   // Log-likelihood over 1..t from s0 and its gradient g[D] (accumulated into
   // g, times `scale`).  ckpt: [nseg][K][P] of R; lds: this lane's column
@@ -97,9 +159,17 @@ struct Adjoint<Egarch<K, SH, R>> {
 #pragma unroll
         for (int k = 0; k < K; ++k) wl[k] = r.w[k];
         av += Md::step(p, y[s], r, ae, pm, lastE, lastz);
+        if constexpr (kMix) {
+          // the mixture sums' product, folded into log2 every 8 observations
+          if (((s - s0) & 7) == 7) {
+            se += (double)log2_fast(pm);
+            pm = (R)1;
+          }
+        }
       }
       sv += (double)av;
       se += (double)ae;
+      if constexpr (kMix) se += (double)log2_fast(pm);
     }
     const R kap = (R)Md::kKappa;
 #pragma unroll
@@ -108,6 +178,7 @@ struct Adjoint<Egarch<K, SH, R>> {
     const double n = (double)t;
     double ll;
     if constexpr (kT) ll = n * (p.cst - p.lsig) + kLn2 * sv - p.hnu1 * t_scale<R>() * se;
+    else if constexpr (kMix) ll = n * (p.cst - p.lsig) + kLn2 * (sv + se);
     else ll = n * (p.cst - p.lsig) + kLn2 * sv - 0.5 * se;
 
     // ---- reverse sweep
@@ -118,6 +189,10 @@ struct Adjoint<Egarch<K, SH, R>> {
 #pragma unroll
     for (int k = 0; k < K; ++k) ab[k] = c0b[k] = kbb[k] = kgb[k] = 0.0;
     double isigb = 0.0, musb = 0.0, inu2b = 0.0, hnu1b = 0.0;
+    // mixture: adjoints of lw_i, nb_i and mu_i (the components' constants)
+    double lwb[kNM], nbb[kNM], mub[kNM];
+#pragma unroll
+    for (int i = 0; i < kNM; ++i) lwb[i] = nbb[i] = mub[i] = 0.0;
     const R ln2 = (R)kLn2;
     for (int64_t sg = ns - 1; sg >= 0; --sg) {
       const int64_t s0 = sg * SEG, s1 = min(t, s0 + SEG);
@@ -139,6 +214,9 @@ struct Adjoint<Egarch<K, SH, R>> {
 #pragma unroll
       for (int k = 0; k < K; ++k) a_ab[k] = a_c0b[k] = a_kbb[k] = a_kgb[k] = (R)0;
       R a_isigb = (R)0, a_musb = (R)0, a_inu2b = (R)0, a_hnu1b = (R)0;
+      R a_lwb[kNM], a_nbb[kNM], a_mub[kNM];
+#pragma unroll
+      for (int i = 0; i < kNM; ++i) a_lwb[i] = a_nbb[i] = a_mub[i] = (R)0;
       for (int j = len - 1; j >= 0; --j) {
         const R yv = y[s0 + j];
         R w[K];
@@ -176,6 +254,35 @@ struct Adjoint<Egarch<K, SH, R>> {
           eb = -h * (R)2 * e * p.inu2 / q1;
           a_inu2b = fma(-h, e * e / q1, a_inu2b);
           a_hnu1b -= t_term(e * e, p.inu2);
+        } else if constexpr (kMix) {
+          // log density ln2 log2 sum_i 2^x_i, x_i = lw_i + nb_i (e - mu_i)^2:
+          // d/dx_i = ln2 pi_i with pi_i = 2^(x_i - m) / sum_j 2^(x_j - m)
+          R dm[kNM], x[kNM];
+#pragma unroll
+          for (int i = 0; i < kNM; ++i) {
+            dm[i] = e - p.mu[i];
+            x[i] = fma(p.nb[i] * dm[i], dm[i], p.lw[i]);
+          }
+          R mx = x[0];
+#pragma unroll
+          for (int i = 1; i < kNM; ++i) mx = fmax(mx, x[i]);
+          R ex[kNM], sm = (R)0;
+#pragma unroll
+          for (int i = 0; i < kNM; ++i) {
+            ex[i] = exp2_fast(x[i] - mx);
+            sm += ex[i];
+          }
+          const R inv = ln2 / sm;
+          eb = (R)0;
+#pragma unroll
+          for (int i = 0; i < kNM; ++i) {
+            const R pi = ex[i] * inv;  // ln2 pi_i
+            a_lwb[i] += pi;
+            a_nbb[i] = fma(pi * dm[i], dm[i], a_nbb[i]);
+            const R g2 = (R)2 * pi * p.nb[i] * dm[i];
+            a_mub[i] -= g2;
+            eb += g2;
+          }
         } else {
           eb = -e;
         }
@@ -198,6 +305,12 @@ struct Adjoint<Egarch<K, SH, R>> {
       musb += (double)a_musb;
       inu2b += (double)a_inu2b;
       hnu1b += (double)a_hnu1b;
+#pragma unroll
+      for (int i = 0; i < kNM; ++i) {
+        lwb[i] += (double)a_lwb[i];
+        nbb[i] += (double)a_nbb[i];
+        mub[i] += (double)a_mub[i];
+      }
     }
     // ---- chain rule to theta (Table 1 transforms)
     const double isig = exp(-th[1]);
@@ -219,6 +332,7 @@ struct Adjoint<Egarch<K, SH, R>> {
       const double hb = hnu1b * t_scale<R>();
       g[2 + 3 * K] += scale * (inu2b * (-1.0 / en) + hb * 0.5 * en + n * dcst);
     }
+    if constexpr (kMix) mixture_chain(th, lwb, nbb, mub, scale, g);
     return ll;
   }
 };
@@ -267,9 +381,9 @@ struct PriorGradLin {
 
 template <class M>
 struct PriorGradOf;
-template <int K, int SH, typename R>
-struct PriorGradOf<Egarch<K, SH, R>> {
-  __device__ static void run(const double *th, double *g) { PriorGrad<K, SH, R>::run(th, g); }
+template <int K, int SH, typename R, int I>
+struct PriorGradOf<Egarch<K, SH, R, I>> {
+  __device__ static void run(const double *th, double *g) { PriorGrad<K, SH, R, I>::run(th, g); }
 };
 template <int NREG>
 struct PriorGradOf<Linreg<NREG>> {

@@ -445,11 +445,9 @@ __global__ void __launch_bounds__(64) k_test_fns(DevModel dm, int64_t P, const d
   for (int q = 0; q < M::kTests; ++q) out[q * P + p] = g[q];
 }
 
-// Models with a hand-written adjoint (the normal-mixture shock has none).
+// Every model has a hand-written adjoint.
 template <class M>
 struct HasAdjoint : std::true_type {};
-template <int K, int SH, typename R, int I>
-struct HasAdjoint<Egarch<K, SH, R, I>> : std::bool_constant<SH != SMC_SHOCK_MIXTURE> {};
 
 // ============================================================ launchers ====
 template <class M>

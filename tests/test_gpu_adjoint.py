@@ -21,7 +21,8 @@ from tests.gpu_helpers import gpu_model, ora_model, pop_to_gpu, theta_np
 pytestmark = pytest.mark.gpu
 
 CASES = [("linreg", S.SMC_FP64), ("egarch11", S.SMC_FP64), ("egarch11", S.SMC_FP32),
-         ("egarch2t", S.SMC_FP64), ("egarch2t", S.SMC_FP32)]
+         ("egarch2t", S.SMC_FP64), ("egarch2t", S.SMC_FP32), ("egarch23", S.SMC_FP64),
+         ("egarch23", S.SMC_FP32), ("egarch12", S.SMC_FP64), ("egarch44", S.SMC_FP64)]
 
 
 def _gtol(prec):
@@ -51,7 +52,7 @@ def test_loglik_backward_matches_oracle_gradient(name, prec, t):
     assert _grad_close(got, want, prec)
 
 
-@pytest.mark.parametrize("name", ["egarch11", "egarch2t", "linreg"])
+@pytest.mark.parametrize("name", ["egarch11", "egarch2t", "linreg", "egarch23"])
 def test_gpu_gradient_matches_finite_differences(name):
     """Central differences (h = 1e-5) of the GPU's own FP64 log-likelihood."""
     w = SD.workload(name, T=500)
@@ -85,7 +86,8 @@ def test_autograd_function():
     assert np.allclose(ll.detach().cpu().numpy(), O.loglik_batch(om, thn, 200)[0], rtol=1e-10)
 
 
-@pytest.mark.parametrize("name,prec", [("linreg", 0), ("egarch11", 0), ("egarch2t", 1)])
+@pytest.mark.parametrize("name,prec", [("linreg", 0), ("egarch11", 0), ("egarch2t", 1),
+                                       ("egarch23", 0), ("egarch23", 1)])
 def test_posterior_grad_matches_oracle(name, prec):
     w = SD.workload(name, T=300)
     gm, om = gpu_model(w, prec), ora_model(w)
@@ -100,7 +102,7 @@ def test_posterior_grad_matches_oracle(name, prec):
 
 
 @pytest.mark.parametrize("name,prec", [("linreg", 0), ("egarch11", 0), ("egarch2t", 0),
-                                       ("egarch2t", 1)])
+                                       ("egarch2t", 1), ("egarch23", 0)])
 def test_mala_step_matches_oracle(name, prec):
     w = SD.workload(name, T=250)
     gm, om = gpu_model(w, prec), ora_model(w)
@@ -117,7 +119,7 @@ def test_mala_step_matches_oracle(name, prec):
     if om.S:
         opop.state[:, :om.S] = st
     _, _, chol, rc = O.moments(opop)
-    hl = (1.0 if name == "linreg" else 0.3) * chol
+    hl = {"linreg": 1.0, "egarch23": 1.5}.get(name, 0.3) * chol
     g = pop_to_gpu(gm, opop, with_grad=True)
     S.smc_posterior_grad(gm, g, w.T)
     acc_g = torch.zeros(J * N, dtype=torch.uint8, device="cuda")

@@ -159,13 +159,24 @@ def test_replay_of_oracle_design():
     assert np.allclose(theta_np(g), opop.theta, rtol=1e-9, atol=1e-10)
 
 
-def test_adjoint_is_unsupported_for_mixtures():
-    w = SD.workload("egarch23", T=20)
-    gm = gpu_model(w)
-    th = torch.from_numpy(SD.random_thetas(w, 4, 1).T.copy()).cuda()
-    with pytest.raises(S.SmcError) as e:
-        S.smc_loglik_backward(gm, th, 20, torch.ones(4, dtype=torch.float64, device="cuda"))
-    assert e.value.status == S.SMC_E_UNSUPPORTED
+def test_mala_run_replays_oracle_design():
+    """The Langevin kernel on the mixture family: the GPU replays the oracle's
+    adaptive MALA run of egarch_23 (gradients through eqs EGARCH_tran1/2)."""
+    w = SD.workload("egarch23", T=120)
+    gm, om = gpu_model(w), ora_model(w)
+    rc, orec, opop = O.run(om, 2, 64, 4, kernel=O.MALA, Lmax=200, RmaxRec=64)
+    assert rc == 0
+    L = orec.L
+    g = S.Population(gm, 2, 64, max_chunk=32, with_grad=True)
+    grec = S.Record(gm, 2, Lmax=200, RmaxRec=64)
+    grec.t_end[:L] = orec.t_end[:L]
+    grec.R[:L] = orec.R[:L]
+    grec.hchol[:L].copy_(torch.from_numpy(orec.hchol[:L].copy()))
+    S.smc_run(gm, g, seed=4, record=grec, replay=True, kernel=S.SMC_KERNEL_MALA)
+    sg, so = grec.summary(), orec.summary()
+    assert sg["L"] == so["L"]
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9, abs=1e-8)
+    assert np.allclose(theta_np(g), opop.theta, rtol=1e-8, atol=1e-9)
 
 
 def test_mutate_full_size_sampled():
