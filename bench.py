@@ -242,6 +242,82 @@ def run_batched(steps):
                 evals_per_step=evals / steps)
 
 
+def run_variants(name, precision, steps):
+    """Whole adaptive runs of one workload under each option of the method
+    beside the default (residual resampling, deterministic R, RW steps):
+    the other resamplers, the RNE stop rule, the independent sampler, the
+    moment reports and log score of every cycle, the fixed-design replay and
+    the two-step hybrid.  Each entry: mean ms per run over `steps` runs after
+    one warm-up, particle-observation evaluations per second, log ML and NSE."""
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+
+    w = SD.workload(name)
+    prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
+    m = S.Model.from_workload(w, precision=prec)
+    pop = S.Population(m, w.J, w.N, max_chunk=1024)
+    burn = w.T // 2
+    variants = {
+        "resample_multinomial": dict(scheme=S.SMC_RESAMPLE_MULTINOMIAL),
+        "resample_stratified": dict(scheme=S.SMC_RESAMPLE_STRATIFIED),
+        "resample_systematic": dict(scheme=S.SMC_RESAMPLE_SYSTEMATIC),
+        "rne_stop_E1_0.35": dict(stop_rule=1, E1=0.35, test_fn=S.SMC_TEST_MODEL),
+        "independent_sampler": dict(kernel=S.SMC_KERNEL_INDEPENDENT),
+        "reports_and_log_score": dict(test_fn=S.SMC_TEST_MODEL, burn_in=burn, report=True),
+    }
+    out = {}
+    for key, kw in variants.items():
+        kw = dict(kw)
+        rep = kw.pop("report", False)
+        tf = kw.get("test_fn", S.SMC_TEST_PARAMS)
+        rec = S.Record(m, w.J, Lmax=2048, RmaxRec=128, test_fn=tf if rep else None)
+        S.smc_run(m, pop, seed=20_000, record=rec, **kw)
+        torch.cuda.synchronize()
+        evals, lm, nse = 0, 0.0, 0.0
+        t0 = time.perf_counter()
+        for k in range(steps):
+            S.smc_run(m, pop, seed=1 + k, record=rec, **kw)
+            s = rec.summary()
+            evals += s["evals"]
+            lm += s["log_ml"] / steps
+            nse += s["nse"] / steps
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        out[key] = dict(ms_per_run=1e3 * secs / steps, value=evals / secs, log_ml=lm, nse=nse)
+        if rep:
+            out[key]["log_score"] = s["log_score"][:2]
+        log(f"[bench] {name}/{precision} {key}: {1e3 * secs / steps:.1f} ms per run")
+    # The fixed-design replay of an adaptive run's design, with a new key.
+    rec = S.Record(m, w.J, Lmax=2048, RmaxRec=128)
+    S.smc_run(m, pop, seed=30_000, record=rec)
+    S.smc_run(m, pop, seed=30_001, record=rec, replay=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    evals = 0
+    for k in range(steps):
+        S.smc_run(m, pop, seed=30_002 + k, record=rec, replay=True)
+        evals += rec.summary()["evals"]
+    torch.cuda.synchronize()
+    secs = time.perf_counter() - t0
+    s = rec.summary()
+    out["replay"] = dict(ms_per_run=1e3 * secs / steps, value=evals / secs, log_ml=s["log_ml"],
+                         nse=s["nse"])
+    log(f"[bench] {name}/{precision} replay: {1e3 * secs / steps:.1f} ms per run")
+    # Algorithm 3: adaptive run, then its design replayed with a second key.
+    t0 = time.perf_counter()
+    r1, r2, hs = S.smc_run_hybrid(m, pop, seed=40_000, seed2=40_001, test_fn=S.SMC_TEST_MODEL,
+                                  burn_in=burn)
+    torch.cuda.synchronize()
+    rep = S.hybrid_report(r1, r2, hs)
+    out["hybrid"] = dict(ms_total=1e3 * (time.perf_counter() - t0),
+                         step_ms=[1e3 * float(x) for x in hs], z_log_ml=rep["z_log_ml"],
+                         z_log_score=rep["z_log_score"])
+    log(f"[bench] {name}/{precision} hybrid: {out['hybrid']['ms_total']:.1f} ms")
+    return out
+
+
 def cpu_baseline(name, seconds):
     import numpy as np
 
@@ -336,7 +412,7 @@ def main():
     companion = None
     if not args.no_fp32 and args.precision == "fp64" and args.workload != "linreg":
         companion = run_gpu(args.workload, "fp32", args.steps, args.warmup)
-    roof2t = tnse = batched = None
+    roof2t = tnse = batched = variants = None
     mix = {}
     if not args.no_companions and args.workload == "egarch11":
         batched = run_batched(2)
@@ -345,6 +421,7 @@ def main():
             mix[prec] = run_gpu("egarch23", prec, 2, 1)
         tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "mala"),
                 time_to_nse("egarch2t", "fp32", "rw")]
+        variants = run_variants(args.workload, args.precision, 2)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
 
     w = main_run["w"]
@@ -403,6 +480,9 @@ def main():
         out["time_to_nse_0.05"] = {
             "workload": "egarch2t: " + DESCR["egarch2t"] + ", adaptive, deterministic Rbar ladder",
             "runs": tnse}
+    if variants is not None:
+        out["variants"] = dict(variants, workload=f"{args.workload}: {DESCR[args.workload]}, "
+                               f"{args.precision.upper()} recursion; defaults otherwise")
     if cpu is not None:
         out["gpu_over_cpu"] = main_run["mutate_evals_per_s"] / cpu["value"]
     print(json.dumps(out), flush=True)

@@ -734,10 +734,11 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
-                            int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
+                            int64_t *n_accept, uint8_t *accepted, hipStream_t s,
+                            const KernelTimer *timer) {
   const ModelOps *o = ops_for(m);
   return o ? o->mutate_rw(m, P, t, theta, logprior, loglik, state, hchol, seed, run, cycle, iter,
-                          n_accept, accepted, s)
+                          n_accept, accepted, timer, s)
            : SMC_E_UNSUPPORTED;
 }
 
@@ -745,10 +746,10 @@ smc_status launch_mutate_indep(const DevModel &m, int64_t P, int64_t t, double *
                                double *logprior, double *loglik, void *state, const double *chol,
                                const double *mean, uint64_t seed, uint64_t run, uint64_t cycle,
                                uint64_t iter, int64_t *n_accept, uint8_t *accepted,
-                               hipStream_t s) {
+                               hipStream_t s, const KernelTimer *timer) {
   const ModelOps *o = ops_for(m);
   return o ? o->mutate_indep(m, P, t, theta, logprior, loglik, state, chol, mean, seed, run,
-                             cycle, iter, n_accept, accepted, s)
+                             cycle, iter, n_accept, accepted, timer, s)
            : SMC_E_UNSUPPORTED;
 }
 

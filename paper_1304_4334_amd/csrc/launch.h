@@ -24,6 +24,13 @@ smc_status fill_f64(double *a, int64_t n, double v, hipStream_t s);
 smc_status fill_i64(int64_t *a, int64_t n, int64_t v, hipStream_t s);
 smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s);
 
+// Optional timing of one launch: the two events take the start and end
+// stamps of the kernel's own dispatch (no packets of their own on the
+// stream).  Both created by the caller with timing enabled; NULL = untimed.
+struct KernelTimer {
+  hipEvent_t start, stop;
+};
+
 // Launchers of the kernels templated on the model, one table per model type
 // (model_kernels.h); the family tables below return NULL for a description
 // they do not cover.
@@ -36,7 +43,7 @@ struct ModelOps {
                         int64_t, int64_t, bool, hipStream_t);
   smc_status (*mutate_rw)(const DevModel &, int64_t, int64_t, double *, double *, double *,
                           void *, const double *, uint64_t, uint64_t, uint64_t, uint64_t,
-                          int64_t *, uint8_t *, hipStream_t);
+                          int64_t *, uint8_t *, const KernelTimer *, hipStream_t);
   smc_status (*loglik)(const DevModel &, int64_t, const double *, int64_t, double *, void *,
                        hipStream_t);
   size_t (*ckpt_bytes)(const DevModel &, int64_t, int64_t);
@@ -52,7 +59,8 @@ struct ModelOps {
                          int32_t, double *, hipStream_t);
   smc_status (*mutate_indep)(const DevModel &, int64_t, int64_t, double *, double *, double *,
                              void *, const double *, const double *, uint64_t, uint64_t,
-                             uint64_t, uint64_t, int64_t *, uint8_t *, hipStream_t);
+                             uint64_t, uint64_t, int64_t *, uint8_t *, const KernelTimer *,
+                             hipStream_t);
 };
 const ModelOps *ops_linreg(const DevModel &m);     // ops_linreg.hip
 const ModelOps *ops_egarch(const DevModel &m);     // ops_egarch.hip: Gaussian, Student-t
@@ -103,7 +111,8 @@ void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb);
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
-                            int64_t *n_accept, uint8_t *accepted, hipStream_t s);
+                            int64_t *n_accept, uint8_t *accepted, hipStream_t s,
+                            const KernelTimer *timer = nullptr);
 smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
                          double *out, void *state_out, hipStream_t s);
 // The independent Gaussian sampler: chol = L (d x d), mean [d].
@@ -111,7 +120,7 @@ smc_status launch_mutate_indep(const DevModel &m, int64_t P, int64_t t, double *
                                double *logprior, double *loglik, void *state, const double *chol,
                                const double *mean, uint64_t seed, uint64_t run, uint64_t cycle,
                                uint64_t iter, int64_t *n_accept, uint8_t *accepted,
-                               hipStream_t s);
+                               hipStream_t s, const KernelTimer *timer = nullptr);
 smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,
                         int32_t *mh, hipStream_t s);
 smc_status launch_rne(const double *theta, int32_t J, int32_t N, int32_t d, double *part,

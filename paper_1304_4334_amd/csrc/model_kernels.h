@@ -8,6 +8,7 @@
 // scalar loads.
 #pragma once
 
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 #include <math.h>
 
@@ -479,10 +480,16 @@ struct OpsOf {
   static smc_status mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                               double *logprior, double *loglik, void *state, const double *hchol,
                               uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
-                              int64_t *n_accept, uint8_t *accepted, hipStream_t s) {
-    hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta, logprior,
-                       loglik, state, hchol, seed, run, cycle, iter,
-                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
+                              int64_t *n_accept, uint8_t *accepted, const KernelTimer *timer,
+                              hipStream_t s) {
+    auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
+    if (timer)
+      hipExtLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
+                            timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
+                            run, cycle, iter, acc, accepted);
+    else
+      hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
+                         logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted);
     return launch_status("mutate");
   }
 
@@ -490,10 +497,16 @@ struct OpsOf {
                                  double *logprior, double *loglik, void *state,
                                  const double *chol, const double *mean, uint64_t seed,
                                  uint64_t run, uint64_t cycle, uint64_t iter, int64_t *n_accept,
-                                 uint8_t *accepted, hipStream_t s) {
-    hipLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
-                       logprior, loglik, state, chol, mean, seed, run, cycle, iter,
-                       reinterpret_cast<unsigned long long *>(n_accept), accepted);
+                                 uint8_t *accepted, const KernelTimer *timer, hipStream_t s) {
+    auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
+    if (timer)
+      hipExtLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
+                            timer->stop, 0, m, P, t, theta, logprior, loglik, state, chol, mean,
+                            seed, run, cycle, iter, acc, accepted);
+    else
+      hipLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
+                         logprior, loglik, state, chol, mean, seed, run, cycle, iter, acc,
+                         accepted);
     return launch_status("mutate/independent");
   }
 

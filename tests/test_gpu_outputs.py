@@ -113,3 +113,27 @@ def test_hybrid_matches_oracle_hybrid(name, T, J, N):
     assert rep["steps"][0]["cycles"] == rep["steps"][1]["cycles"]
     assert np.all(secs > 0)
     assert np.isfinite(rep["z_log_ml"])
+
+
+@pytest.mark.parametrize("kernel", [S.SMC_KERNEL_RW, S.SMC_KERNEL_INDEPENDENT, S.SMC_KERNEL_MALA])
+def test_mutation_timing_leaves_the_run_unchanged(kernel):
+    """Timing every mutation launch (events carried on the kernel's own
+    dispatch, or around the Langevin step's kernels) changes nothing the run
+    computes, and yields one positive duration per M step."""
+    w = SD.workload("egarch11", T=300)
+    gm = gpu_model(w)
+    J, N = 4, 256
+    out = []
+    for timed in (False, True):
+        g = S.Population(gm, J, N, max_chunk=64, with_grad=kernel == S.SMC_KERNEL_MALA)
+        rec = S.Record(gm, J, Lmax=200, RmaxRec=32, time_mutate=timed)
+        S.smc_run(gm, g, seed=11, kernel=kernel, record=rec)
+        out.append((rec, rec.summary(), g.theta.cpu().numpy()))
+    (_, a, th_a), (rec, b, th_b) = out
+    assert np.array_equal(a["t_end"], b["t_end"]) and np.array_equal(a["R"], b["R"])
+    assert a["log_ml"] == b["log_ml"] and a["nse"] == b["nse"]
+    assert np.array_equal(th_a, th_b)
+    for l in range(b["L"]):
+        ms = rec.mutate_ms[l, :b["R"][l]]
+        assert np.all(ms > 0) and np.all(ms < 1e3), ms
+        assert np.all(rec.mutate_ms[l, b["R"][l]:] == 0)
