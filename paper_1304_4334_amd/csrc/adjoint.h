@@ -269,7 +269,7 @@ struct Adjoint<Egarch<K, SH, R, I>> {
           R ex[kNM], sm = (R)0;
 #pragma unroll
           for (int i = 0; i < kNM; ++i) {
-            ex[i] = exp2_fast(x[i] - mx);
+            ex[i] = exp2_lean(x[i] - mx);
             sm += ex[i];
           }
           const R inv = ln2 / sm;

@@ -28,28 +28,53 @@ constexpr double kLog2e = 1.4426950408889634074;
 constexpr int kUnroll = 8;
 
 // 2^x.  FP32: the hardware base-2 exponential.  FP64: x = n + f with
-// n = rint(x), |f| <= 1/2, 2^f by its Taylor series in f ln 2 to degree 13
-// (truncation below 5e-18 relative) evaluated in Estrin's scheme, which keeps
-// the dependency chain about five operations deep, then scaled by 2^n.
+// n = rint(x), |f| <= 1/2, 2^f by the degree-11 minimax polynomial of
+// kExp2Coef (relative error 3.4e-17 on [-1/2, 1/2] with the coefficients
+// rounded to double; written by gen_exp2_coef.py), then scaled by 2^n.
 // Arguments beyond the double range give 0 or inf through the final scaling.
+//
+// exp2_fast evaluates the polynomial as two Horner chains in f^2 (even and
+// odd coefficients) joined by one fma: 12 operations, 7 deep, for values on
+// a loop-carried dependency chain.  exp2_lean is plain Horner (11 fmas, 11
+// deep) for independent values whose latencies overlap.
+__device__ constexpr double kExp2Coef[12] = {
+  0x1.0000000000000p+0,
+  0x1.62e42fefa39efp-1,
+  0x1.ebfbdff82c5adp-3,
+  0x1.c6b08d7049fd1p-5,
+  0x1.3b2ab6fb9f413p-7,
+  0x1.5d87fe78cf26dp-10,
+  0x1.43091310bf6b0p-13,
+  0x1.ffcbfba7b89b6p-17,
+  0x1.62bfc3c1c8a7cp-20,
+  0x1.b526788b3b73dp-24,
+  0x1.e620fb765be15p-28,
+  0x1.e7aa0f6005d3cp-32,
+};
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
+__device__ __forceinline__ float exp2_lean(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ double exp2_fast(double x) {
-  constexpr double c0 = 1.0, c1 = 6.931471805599453094e-01, c2 = 2.402265069591007123e-01,
-                   c3 = 5.550410866482157995e-02, c4 = 9.618129107628477232e-03,
-                   c5 = 1.333355814642844343e-03, c6 = 1.540353039338160995e-04,
-                   c7 = 1.525273380405984028e-05, c8 = 1.321548679014430951e-06,
-                   c9 = 1.017808600923969859e-07, c10 = 7.054911620801123330e-09,
-                   c11 = 4.445538271870811631e-10, c12 = 2.567843599348820271e-11,
-                   c13 = 1.369148885390524890e-12;
   const double n = __builtin_rint(x);
   const double f = x - n;
-  const double f2 = f * f, f4 = f2 * f2, f8 = f4 * f4;
-  const double p01 = fma(c1, f, c0), p23 = fma(c3, f, c2), p45 = fma(c5, f, c4);
-  const double p67 = fma(c7, f, c6), p89 = fma(c9, f, c8), pab = fma(c11, f, c10);
-  const double pcd = fma(c13, f, c12);
-  const double q0 = fma(p23, f2, p01), q1 = fma(p67, f2, p45), q2 = fma(pab, f2, p89);
-  const double r0 = fma(q1, f4, q0), r1 = fma(pcd, f4, q2);
-  return __builtin_ldexp(fma(r1, f8, r0), (int)n);
+  const double u = f * f;
+  double e = fma(kExp2Coef[10], u, kExp2Coef[8]), o = fma(kExp2Coef[11], u, kExp2Coef[9]);
+  e = fma(e, u, kExp2Coef[6]);
+  o = fma(o, u, kExp2Coef[7]);
+  e = fma(e, u, kExp2Coef[4]);
+  o = fma(o, u, kExp2Coef[5]);
+  e = fma(e, u, kExp2Coef[2]);
+  o = fma(o, u, kExp2Coef[3]);
+  e = fma(e, u, kExp2Coef[0]);
+  o = fma(o, u, kExp2Coef[1]);
+  return __builtin_ldexp(fma(o, f, e), (int)n);
+}
+__device__ __forceinline__ double exp2_lean(double x) {
+  const double n = __builtin_rint(x);
+  const double f = x - n;
+  double p = fma(kExp2Coef[11], f, kExp2Coef[10]);
+#pragma unroll
+  for (int k = 9; k >= 0; --k) p = fma(p, f, kExp2Coef[k]);
+  return __builtin_ldexp(p, (int)n);
 }
 
 // log2 x.  FP32: the hardware base-2 logarithm; FP64: the library's.
@@ -334,9 +359,9 @@ struct Egarch {
       R mx = x[0];
 #pragma unroll
       for (int i = 1; i < I; ++i) mx = fmax(mx, x[i]);
-      R sm = exp2_fast(x[0] - mx);
+      R sm = exp2_lean(x[0] - mx);
 #pragma unroll
-      for (int i = 1; i < I; ++i) sm += exp2_fast(x[i] - mx);
+      for (int i = 1; i < I; ++i) sm += exp2_lean(x[i] - mx);
       ae += mx;
       pm *= sm;
     } else {
