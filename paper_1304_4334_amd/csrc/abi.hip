@@ -96,24 +96,44 @@ int64_t chunk_capacity(const smc_model *m, const smc_particles *pop) {
 
 int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8; }
 
-// Page-locked host buffer for the C-phase RSS readbacks (one per host
-// thread, kept for the life of the process); NULL if it cannot be had.
-// Pinned host staging for the C-phase RSS columns ([kMaxChunk] doubles),
-// followed by one slot for the flags word the driver reads along with them.
-double *pinned_rss_buffer() {
-  thread_local double *buf = nullptr;
+// Page-locked host slots for what the driver reads back during a run: the
+// C-phase chunk's stopping decision and the numerical flags word (one set per
+// host thread, kept for the life of the process); NULL if it cannot be had.
+struct PinnedSlots {
+  StopInfo stop;
+  int32_t flags;
+  int32_t pad;
+};
+PinnedSlots *pinned_slots() {
+  thread_local PinnedSlots *buf = nullptr;
   thread_local bool tried = false;
   if (!tried) {
     tried = true;
     void *p = nullptr;
-    if (hipHostMalloc(&p, (kMaxChunk + 1) * sizeof(double), hipHostMallocDefault) == hipSuccess)
-      buf = static_cast<double *>(p);
+    if (hipHostMalloc(&p, sizeof(PinnedSlots), hipHostMallocDefault) == hipSuccess)
+      buf = static_cast<PinnedSlots *>(p);
   }
   return buf;
 }
 int32_t *pinned_flags_slot() {
-  double *b = pinned_rss_buffer();
-  return b ? reinterpret_cast<int32_t *>(b + kMaxChunk) : nullptr;
+  PinnedSlots *b = pinned_slots();
+  return b ? &b->flags : nullptr;
+}
+
+// An event (no timing) of the calling thread for the current device, marking
+// the completion of a readback so the host can wait for it alone while later
+// work stays queued; kept for the life of the process.
+smc_status readback_event(hipEvent_t *out) {
+  thread_local hipEvent_t ev[16] = {};
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 16)
+    return set_error(SMC_E_DEVICE, "readback event: device %d not supported", dev);
+  if (!ev[dev] && hipEventCreateWithFlags(&ev[dev], hipEventDisableTiming) != hipSuccess) {
+    ev[dev] = nullptr;
+    return set_error(SMC_E_DEVICE, "creating a readback event failed");
+  }
+  *out = ev[dev];
+  return SMC_OK;
 }
 
 // Event i of the calling thread's pool for the current device.  The pools
@@ -141,9 +161,17 @@ smc_status timing_event(size_t i, hipEvent_t *out) {
 
 }  // namespace
 
+// The S phase that an adaptive C phase may enqueue ahead of its last host
+// decision (it runs only if the phase ended; see correct_impl).
+struct ResampleAhead {
+  int32_t scheme;
+  int32_t cycle;
+  smc_rng rng;
+};
 smc_status correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
                         int64_t check_every, double rss_min, double *group_logwbar,
-                        int64_t *t_to, double *rss, void *stream, int64_t first_chunk);
+                        int64_t *t_to, double *rss, void *stream, int64_t first_chunk,
+                        const ResampleAhead *ahead = nullptr, bool *resampled = nullptr);
 
 }  // namespace smc
 
@@ -254,12 +282,19 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
 }  // extern "C"
 
 // The C phase with a first speculative chunk of `first_chunk` observations
-// (the driver passes a length predicted from the previous cycle).
+// (the driver passes a length predicted from the previous cycle).  Adaptive
+// chunks: scan every checked date, compute the RSS columns, decide the stop
+// on the device, and queue the commit to the decided date before the host
+// reads the decision back; with `ahead`, the group weights and the S phase
+// (which does nothing unless the phase ended) are queued too, so the device
+// has that work in hand while the host waits.  *resampled tells whether the
+// S phase was queued that way.
 smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from,
                              int64_t t_max, int64_t check_every, double rss_min,
                              double *group_logwbar, int64_t *t_to, double *rss, void *stream,
-                             int64_t first_chunk) {
+                             int64_t first_chunk, const ResampleAhead *ahead, bool *resampled) {
   smc_status st;
+  if (resampled) *resampled = false;
   if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
   if (!group_logwbar || !t_to) return set_error(SMC_E_INVALID_ARG, "NULL output");
   if (t_from < 0 || t_max > m->dev.T || t_from > t_max)
@@ -294,54 +329,68 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
     if (cap < 1) return set_error(SMC_E_WORKSPACE, "workspace has no room for C-phase chunks");
     int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(first_chunk, cap));
     int64_t t = t_from;
-    std::vector<int64_t> dates;
-    std::vector<double> host_vec;
-    double *host_rss = pinned_rss_buffer();
-    if (!host_rss) {
-      host_vec.resize(kMaxChunk);
-      host_rss = host_vec.data();
-    }
-    bool stopped = false;
+    StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
+    PinnedSlots *pin = pinned_slots();
+    StopInfo pageable{};
+    StopInfo *stop_host = pin ? &pin->stop : &pageable;
+    hipEvent_t ev;
+    if ((st = readback_event(&ev))) return st;
+    bool stopped = false, queued_ahead = false;
     while (!stopped) {
       const int64_t t1 = std::min(t + chunk, t_max);
-      dates.clear();
-      for (int64_t u = t + 1; u <= t1; ++u)
-        if (u % check_every == 0 || u == t_max) dates.push_back(u);
-      if (dates.empty()) {
+      // checked dates in (t, t1]: the multiples of check_every, and t_max
+      const int64_t nc = t1 / check_every - t / check_every +
+                         ((t1 == t_max && t_max % check_every != 0) ? 1 : 0);
+      if (nc == 0) {
         if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
                                  t1, zero_first, s)))
           return st;
         zero_first = false;
         t = t1;
+        stopped = t >= t_max;
+        queued_ahead = false;
         chunk = std::min(2 * chunk, cap);
         continue;
       }
       if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, t, t1, check_every,
-                             t_max, zero_first, W, s)))
+                             t_max, zero_first, W, s)) ||
+          (st = launch_rss_cols(W, P, nc, rsscols, s)) ||
+          (st = launch_find_stop(rsscols, nc, t, t1, check_every, t_max, rss_min, stop_dev, s)))
         return st;
-      const int64_t nc = (int64_t)dates.size();
-      if ((st = launch_rss_cols(W, P, nc, rsscols, s))) return st;
-      if (hipMemcpyAsync(host_rss, rsscols, nc * sizeof(double), hipMemcpyDeviceToHost,
-                         s) != hipSuccess ||
-          hipStreamSynchronize(s) != hipSuccess)
-        return set_error(SMC_E_DEVICE, "correct: reading the RSS failed");
-      int64_t stop_col = -1;
-      for (int64_t c = 0; c < nc; ++c)
-        if (host_rss[c] < rss_min) {
-          stop_col = c;
-          break;
-        }
-      const int64_t t_commit = stop_col >= 0 ? dates[stop_col] : t1;
-      if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t,
-                               t_commit, zero_first, s)))
+      if (hipMemcpyAsync(stop_host, stop_dev, sizeof(StopInfo), hipMemcpyDeviceToHost, s) !=
+              hipSuccess ||
+          hipEventRecord(ev, s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "correct: reading the stop decision failed");
+      if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t, t1,
+                               zero_first, s, &stop_dev->t_commit)))
         return st;
+      if (ahead) {
+        if ((st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s)) ||
+            (st = launch_resample(pop->logw, pop->J, pop->N, ahead->scheme, ahead->rng.seed,
+                                  ahead->rng.run, (uint64_t)ahead->cycle, pop->ancestor,
+                                  ws_at<double>(pop, L.cum),
+                                  ws_at<int32_t>(pop, L.small + kSmallFlags), m->dev.d, m->dev.S,
+                                  state_bytes(m), pop->theta, pop->logprior, pop->loglik,
+                                  pop->state, pop->grad, ws_at<double>(pop, L.gather), s,
+                                  &stop_dev->ends)))
+          return st;
+      }
+      if (hipEventSynchronize(ev) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "correct: waiting for the stop decision failed");
       zero_first = false;
-      rss_at_stop = stop_col >= 0 ? host_rss[stop_col] : host_rss[nc - 1];
-      t = t_commit;
-      if (stop_col >= 0 || t >= t_max) stopped = true;
+      rss_at_stop = stop_host->rss;
+      t = stop_host->t_commit;
+      stopped = stop_host->ends != 0;
+      queued_ahead = ahead != nullptr;
       chunk = std::min(2 * chunk, cap);
     }
     t_stop = t;
+    if (queued_ahead) {
+      *t_to = t_stop;
+      if (rss) *rss = rss_at_stop;
+      if (resampled) *resampled = true;
+      return SMC_OK;
+    }
   }
   if ((st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s))) return st;
   *t_to = t_stop;
@@ -556,6 +605,8 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   if (cfg->kernel != SMC_KERNEL_RW && cfg->kernel != SMC_KERNEL_MALA &&
       cfg->kernel != SMC_KERNEL_INDEPENDENT)
     return set_error(SMC_E_INVALID_ARG, "kernel %d", cfg->kernel);
+  if (cfg->scheme < SMC_RESAMPLE_RESIDUAL || cfg->scheme > SMC_RESAMPLE_SYSTEMATIC)
+    return set_error(SMC_E_INVALID_ARG, "resampling scheme %d", cfg->scheme);
   const bool indep = cfg->kernel == SMC_KERNEL_INDEPENDENT;
   if (indep && !rec->mean)
     return set_error(SMC_E_INVALID_ARG, "the independent sampler records its means");
@@ -620,17 +671,23 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     // concentrates; evaluations past the stop date are cheap beside the M
     // phase's).
     const int64_t hint = std::max<int64_t>(16, 2 * last_len + 16);
+    // The S phase is queued by the C phase ahead of its last readback.
+    const ResampleAhead ahead{cfg->scheme, l + 1, cfg->rng};
+    bool resampled = false;
     if ((st = correct_impl(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
                            rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
-                           cfg->replay ? nullptr : &rss, stream, hint)))
+                           cfg->replay ? nullptr : &rss, stream, hint,
+                           cfg->replay ? nullptr : &ahead, &resampled)))
       return st;
-    if (fl_host && l > 0 && *fl_host) {  // correct_impl has synchronised the stream
+    // correct_impl has waited for its last readback, which follows the flags'
+    if (fl_host && l > 0 && *fl_host) {
       rec->L = l;
       return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", *fl_host, l);
     }
     last_len = t_new - t;
     evals += P * (t_new - t);
-    if ((st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream))) return st;
+    if (!resampled && (st = smc_resample(m, pop, cfg->scheme, cfg->rng, l + 1, stream)))
+      return st;
     int32_t R = cfg->replay ? rec->R[l] : (rss < cfg->D2 ? cfg->kappa * cfg->Rbar : cfg->Rbar);
     if (R < 1) return set_error(SMC_E_INVALID_ARG, "R_l < 1 in cycle %d", l);
     // The Langevin drift needs the posterior gradient at the new date.

@@ -57,10 +57,22 @@ constexpr size_t kSmallRne = 72;     // double
 constexpr size_t kSmallMean = 256;    // double[32]
 constexpr size_t kSmallCov = 512;     // double[32 * 32]
 constexpr size_t kSmallHchol = 8704;  // double[32 * 32]
-constexpr size_t kSmallStop = 16896;  // int64: first stop column
+constexpr size_t kSmallStop = 16896;  // StopInfo
 constexpr size_t kSmallBytes = 17152;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// A C-phase chunk's outcome, decided on the device: the date the weights are
+// committed to (the first checked date whose RSS fell below the threshold, or
+// the chunk's end), the RSS there, whether it fell below, and whether the
+// phase ends with this chunk (it fell below, or the chunk reached the
+// phase's last date).
+struct StopInfo {
+  int64_t t_commit;
+  double rss;
+  int32_t below;
+  int32_t ends;
+};
 
 WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N);
 

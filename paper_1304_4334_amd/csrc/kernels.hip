@@ -119,6 +119,35 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
   }
 }
 
+// The chunk's stopping decision (Section 3.3: the first checked date whose
+// RSS is below rss_min): one wave scans the columns 64 at a time.  Column c
+// holds date first + c * check_every, the multiples of check_every after t
+// up to t1, and t_max last when it is not a multiple.
+__global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc, int64_t t,
+                                                  int64_t t1, int64_t check_every, int64_t t_max,
+                                                  double rss_min, StopInfo *out) {
+  int first = -1;
+  for (int base = 0; base < nc; base += 64) {
+    const int c = base + (int)threadIdx.x;
+    const uint64_t below = __ballot(c < nc && rss[c] < rss_min);
+    if (below) {
+      first = base + __builtin_ctzll(below);
+      break;
+    }
+  }
+  if (threadIdx.x == 0) {
+    const int64_t first_date = (t / check_every + 1) * check_every;
+    const int64_t n_regular = t1 >= first_date ? (t1 - first_date) / check_every + 1 : 0;
+    const int col = first >= 0 ? first : nc - 1;
+    StopInfo o;
+    o.t_commit = first < 0 ? t1 : (first < n_regular ? first_date + first * check_every : t_max);
+    o.rss = rss[col];
+    o.below = first >= 0;
+    o.ends = first >= 0 || t1 >= t_max;
+    *out = o;
+  }
+}
+
 // log wbar_j = log(N^-1 sum_n exp(logw_jn)) per group (Section 4.2).
 __global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32_t N,
                                                        double *out) {
@@ -218,7 +247,8 @@ __device__ __forceinline__ void gather_in_registers(const GatherArgs &g, int64_t
 __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
                                                   uint64_t seed, uint64_t run, uint64_t cycle,
                                                   int32_t *anc, double *cum_ws, int32_t *flags,
-                                                  GatherArgs g) {
+                                                  GatherArgs g, const int32_t *go) {
+  if (go && *go == 0) return;  // enqueued ahead of a C phase that did not end
   extern __shared__ double lds_dyn[];
   __shared__ double shd[kBlock];
   __shared__ int64_t shi[kBlock];
@@ -725,9 +755,9 @@ smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const
 
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
                           double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
-                          hipStream_t s) {
+                          hipStream_t s, const int64_t *t1_dev) {
   const ModelOps *o = ops_for(m);
-  return o ? o->ccommit(m, P, theta, state, logw, loglik, t0, t1, zero_first, s)
+  return o ? o->ccommit(m, P, theta, state, logw, loglik, t0, t1, zero_first, t1_dev, s)
            : SMC_E_UNSUPPORTED;
 }
 
@@ -807,6 +837,16 @@ smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rs
   return launch_status("correct/rss");
 }
 
+smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
+                            int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
+                            hipStream_t s) {
+  if (nc < 1 || nc > kMaxChunk)
+    return set_error(SMC_E_INVALID_ARG, "stop search over %lld columns", (long long)nc);
+  hipLaunchKernelGGL(k_find_stop, dim3(1), dim3(64), 0, s, rss, (int32_t)nc, t, t1, check_every,
+                     t_max, rss_min, out);
+  return launch_status("correct/find_stop");
+}
+
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s) {
   hipLaunchKernelGGL(k_group_logwbar, dim3(J), dim3(kBlock), 0, s, logw, N, out);
@@ -817,7 +857,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
-                           double *grad, double *tmp, hipStream_t s) {
+                           double *grad, double *tmp, hipStream_t s, const int32_t *go) {
   const int64_t P = (int64_t)J * N;
   GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
                state, tmp};
@@ -827,7 +867,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                                            kGatherLdsBytes
                                      : (size_t)N * sizeof(int32_t);
   hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), lds, s, logw, N, scheme, seed, run, cycle,
-                     anc, cum_ws, flags, g);
+                     anc, cum_ws, flags, g, go);
   return launch_status("resample");
 }
 

@@ -40,7 +40,7 @@ struct ModelOps {
   smc_status (*cscan)(const DevModel &, int64_t, const double *, const void *, const double *,
                       int64_t, int64_t, int64_t, int64_t, bool, double *, hipStream_t);
   smc_status (*ccommit)(const DevModel &, int64_t, const double *, void *, double *, double *,
-                        int64_t, int64_t, bool, hipStream_t);
+                        int64_t, int64_t, bool, const int64_t *, hipStream_t);
   smc_status (*mutate_rw)(const DevModel &, int64_t, int64_t, double *, double *, double *,
                           void *, const double *, uint64_t, uint64_t, uint64_t, uint64_t,
                           int64_t *, uint8_t *, const KernelTimer *, hipStream_t);
@@ -77,20 +77,27 @@ smc_status launch_init(const DevModel &m, int64_t P, uint64_t seed, uint64_t run
 smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                         const double *logw, int64_t t0, int64_t t1, int64_t check_every,
                         int64_t t_max, bool zero_first, double *W, hipStream_t s);
+// t1_dev (may be NULL): the commit's end date read on the device (at most t1).
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
                           double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
-                          hipStream_t s);
+                          hipStream_t s, const int64_t *t1_dev = nullptr);
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
+// The stopping decision over nc RSS columns of the chunk (t, t1] into *out.
+smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
+                            int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
+                            hipStream_t s);
 // Resampling and the replacement of every particle by its ancestor, one block
-// per group.
+// per group; with `go` (device flag, may be NULL) the kernel does nothing
+// while *go is 0.
 smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
-                           double *grad, double *tmp, hipStream_t s);
+                           double *grad, double *tmp, hipStream_t s,
+                           const int32_t *go = nullptr);
 struct MomArgs {
   const double *theta;
   int64_t P;

@@ -93,13 +93,16 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
   });
 }
 
-// Commit: advance from t0 to t1, adding the log densities to logw and loglik.
+// Commit: advance from t0 to t1 (or to *t1_dev when given), adding the log
+// densities to logw and loglik.
 template <class M>
 __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
                                                 void *state, double *logw, double *loglik,
-                                                int64_t t0, int64_t t1, int32_t zero_first) {
+                                                int64_t t0, int64_t t1, int32_t zero_first,
+                                                const int64_t *t1_dev) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
+  if (t1_dev) t1 = min(t1, *t1_dev);
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
   constexpr int SS = StoredS<M>::value;
@@ -471,9 +474,9 @@ struct OpsOf {
 
   static smc_status ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
                             double *logw, double *loglik, int64_t t0, int64_t t1,
-                            bool zero_first, hipStream_t s) {
+                            bool zero_first, const int64_t *t1_dev, hipStream_t s) {
     hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
-                       loglik, t0, t1, (int32_t)zero_first);
+                       loglik, t0, t1, (int32_t)zero_first, t1_dev);
     return launch_status("correct/commit");
   }
 
