@@ -701,6 +701,10 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
       double *mslot = indep ? rec->mean + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d : nullptr;
       int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
+      // The random-walk step folds the proposal scale into its own launch
+      // (d < 16); the partial sums still come from their own kernel.
+      const bool fold = !cfg->replay && cfg->kernel == SMC_KERNEL_RW && d < 16;
+      MomFuse fm{};
       if (!cfg->replay) {
         // h starts at 0.5 in each M phase; later iterations first apply the
         // step-size rule to the previous iteration's acceptances.  The
@@ -709,7 +713,23 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         ma.prev_nacc = (r == 1 || indep) ? nullptr : nacc - 1;
         ma.hchol = hl;
         ma.mean_out = mslot;
-        if ((st = launch_moments(ma, s))) return st;
+        if (fold) {
+          int64_t nb = 0;
+          if ((st = launch_moment_partials(ma, nb, s))) return st;
+          // two step-size slots, alternating, as every block reads the
+          // previous iteration's value while block 0 writes this one's
+          fm.part = ma.part;
+          fm.nb = (int32_t)nb;
+          fm.mh_reset = ma.mh_reset;
+          fm.mh_in = (r & 1) ? mh + 1 : mh;
+          fm.mh_out = (r & 1) ? mh : mh + 1;
+          fm.prev_nacc = ma.prev_nacc;
+          fm.target_permille = ma.target_permille;
+          fm.hchol_out = hl;
+          fm.flags = dflags;
+        } else if ((st = launch_moments(ma, s))) {
+          return st;
+        }
       }
       Timed *ev = nullptr;
       const bool bracket = cfg->kernel == SMC_KERNEL_MALA;
@@ -732,8 +752,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
           return st;
       } else if (cfg->kernel == SMC_KERNEL_RW) {
         if ((st = launch_mutate_rw(m->dev, P, t_new, pop->theta, pop->logprior, pop->loglik,
-                                   pop->state, hl, cfg->rng.seed, cfg->rng.run, (uint64_t)(l + 1),
-                                   (uint64_t)r, nacc, nullptr, s, tp)))
+                                   pop->state, fold ? nullptr : hl, cfg->rng.seed, cfg->rng.run,
+                                   (uint64_t)(l + 1), (uint64_t)r, nacc, nullptr, s, tp,
+                                   fold ? &fm : nullptr)))
           return st;
       } else if ((st = smc_mutate(m, pop, t_new, cfg->kernel, hl, cfg->rng, l + 1, r, nacc,
                                   nullptr, stream))) {

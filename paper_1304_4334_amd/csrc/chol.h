@@ -13,10 +13,11 @@ namespace smc {
 // written it in earlier columns.  LDS operations of one wave complete in
 // order, so the factorisation needs no block barrier; the operations and
 // their order are those of a column-by-column factorisation.  Writes h L
-// (d x d row-major) to hchol; a V that is not positive definite gives
-// hchol = 0 and raises SMC_FLAG_NOT_PD.
+// (d x d row-major) to hchol (if not NULL); a V that is not positive definite
+// gives hchol = 0 and raises SMC_FLAG_NOT_PD in flags (if not NULL).  Returns
+// whether V was positive definite (the same in every lane).
 template <int W>
-__device__ __forceinline__ void wave_cholesky(const double *Ms, double *Ls, int d, double h,
+__device__ __forceinline__ bool wave_cholesky(const double *Ms, double *Ls, int d, double h,
                                               double *hchol, int32_t *flags) {
   const int r = threadIdx.x & 63;
   bool ok = true;
@@ -46,9 +47,10 @@ __device__ __forceinline__ void wave_cholesky(const double *Ms, double *Ls, int 
     else if (r == col) Ls[col * W + col] = dg;
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   }
-  if (r < d)
+  if (hchol && r < d)
     for (int c = 0; c < d; ++c) hchol[r * d + c] = (ok && c <= r) ? h * Ls[r * W + c] : 0.0;
-  if (r == 0 && !ok) atomicOr(flags, SMC_FLAG_NOT_PD);
+  if (flags && r == 0 && !ok) atomicOr(flags, SMC_FLAG_NOT_PD);
+  return ok;
 }
 
 }  // namespace smc

@@ -50,7 +50,7 @@ constexpr int kMomBlocks = 128;  // moment partial blocks (moment_partition keep
 
 // Offsets inside the `small` region.
 constexpr size_t kSmallFlags = 0;    // int32
-constexpr size_t kSmallMh = 16;      // int32
+constexpr size_t kSmallMh = 16;      // int32[2]
 constexpr size_t kSmallNacc = 32;    // int64
 constexpr size_t kSmallRss = 64;     // double
 constexpr size_t kSmallRne = 72;     // double

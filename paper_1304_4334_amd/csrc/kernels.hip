@@ -765,10 +765,10 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
                             int64_t *n_accept, uint8_t *accepted, hipStream_t s,
-                            const KernelTimer *timer) {
+                            const KernelTimer *timer, const MomFuse *fuse) {
   const ModelOps *o = ops_for(m);
   return o ? o->mutate_rw(m, P, t, theta, logprior, loglik, state, hchol, seed, run, cycle, iter,
-                          n_accept, accepted, timer, s)
+                          n_accept, accepted, timer, fuse, s)
            : SMC_E_UNSUPPORTED;
 }
 
@@ -911,6 +911,16 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
     hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(1024), 0, s, f, 1);
   }
   return launch_status("particle_moments/final");
+}
+
+smc_status launch_moment_partials(const MomArgs &a, int64_t &nb, hipStream_t s) {
+  if (a.d + 1 > 16) return set_error(SMC_E_UNSUPPORTED, "folded moments need d < 16");
+  int64_t chunk = 0;
+  moment_partition(a.P, a.d, chunk, nb);
+  if (nb > kMomBlocks) return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
+  hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
+                     chunk, a.part);
+  return launch_status("particle_moments/partial");
 }
 
 smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,

@@ -31,6 +31,24 @@ struct KernelTimer {
   hipEvent_t start, stop;
 };
 
+// The proposal scale folded into the random-walk step for d < 16: each block
+// sums the moment partials, applies the step-size rule and factors the
+// particle variance itself, with the arithmetic of the separate moments
+// kernels (so the results agree to the bit); block 0 writes the step size and
+// h L for the record.
+struct MomFuse {
+  const double *part;        // [nb][16 * 16] partial sums; NULL: not fused
+  int32_t nb;
+  int32_t mh_reset;          // > 0: the step size is set to this value
+  const int32_t *mh_in;      // the previous iteration's step size (tenths)
+  int32_t *mh_out;           // this iteration's, written by block 0
+  const int64_t *prev_nacc;  // the previous iteration's accepts, or NULL
+  int32_t target_permille;   // step-size rule target
+  int32_t pad;
+  double *hchol_out;         // h L (d x d row-major) for the record, by block 0
+  int32_t *flags;            // SMC_FLAG_NOT_PD when the variance is not positive definite
+};
+
 // Launchers of the kernels templated on the model, one table per model type
 // (model_kernels.h); the family tables below return NULL for a description
 // they do not cover.
@@ -43,7 +61,8 @@ struct ModelOps {
                         int64_t, int64_t, bool, const int64_t *, hipStream_t);
   smc_status (*mutate_rw)(const DevModel &, int64_t, int64_t, double *, double *, double *,
                           void *, const double *, uint64_t, uint64_t, uint64_t, uint64_t,
-                          int64_t *, uint8_t *, const KernelTimer *, hipStream_t);
+                          int64_t *, uint8_t *, const KernelTimer *, const MomFuse *,
+                          hipStream_t);
   smc_status (*loglik)(const DevModel &, int64_t, const double *, int64_t, double *, void *,
                        hipStream_t);
   size_t (*ckpt_bytes)(const DevModel &, int64_t, int64_t);
@@ -112,6 +131,9 @@ struct MomArgs {
   int32_t *flags;
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
+// Only the partial sums of launch_moments (d < 16), for a step that folds the
+// rest in (MomFuse); nb receives the number of partials.
+smc_status launch_moment_partials(const MomArgs &a, int64_t &nb, hipStream_t s);
 // Particles per wave (chunk) and blocks (nb <= kMomBlocks) of the moment
 // partials of P particles of dimension d.
 void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb);
@@ -119,7 +141,7 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
                             int64_t *n_accept, uint8_t *accepted, hipStream_t s,
-                            const KernelTimer *timer = nullptr);
+                            const KernelTimer *timer = nullptr, const MomFuse *fuse = nullptr);
 smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,
                          double *out, void *state_out, hipStream_t s);
 // The independent Gaussian sampler: chol = L (d x d), mean [d].

@@ -15,6 +15,7 @@
 #include <type_traits>
 
 #include "adjoint.h"
+#include "chol.h"
 #include "common.h"
 #include "launch.h"
 #include "model.h"
@@ -122,29 +123,117 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 }
 
 // ------------------------------------------------------------ M phase (a5) --
+// The proposal scale of a random-walk step computed by the step's own wave
+// (MomFuse): the moment partials summed entry by entry in block order, the
+// step-size rule, V and its Cholesky factor in LDS, exactly as the separate
+// moments kernels do (k_mom_final).  Returns whether V was positive definite;
+// h receives the step size.
+template <int D>
+__device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double *Ms, double *Ls,
+                                            double *sh_h, double &h) {
+  constexpr int W = 16;
+  constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
+  const int lane = threadIdx.x;
+  int32_t m = 0;
+  int64_t nacc = 0;
+  if (lane == 0) {
+    m = *fm.mh_in;
+    if (fm.mh_reset <= 0 && fm.prev_nacc) nacc = *fm.prev_nacc;
+  }
+#pragma unroll
+  for (int q = 0; q < (E + 63) / 64; ++q) {
+    const int idx = lane + 64 * q;
+    if (idx < E) {
+      const int e = (idx / (D + 1)) * W + idx % (D + 1);
+      const double *pp = fm.part + e;
+      constexpr int kBatch = 16;
+      double sum = 0.0;
+      for (int b0 = 0; b0 < fm.nb; b0 += kBatch) {
+        double x[kBatch];
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          x[u] = (b0 + u < fm.nb) ? pp[(int64_t)(b0 + u) * W * W] : 0.0;
+#pragma unroll
+        for (int u = 0; u < kBatch; ++u)
+          if (b0 + u < fm.nb) sum += x[u];
+      }
+      Ms[e] = sum;
+    }
+  }
+  if (lane == 0) {
+    if (fm.mh_reset > 0) {
+      m = fm.mh_reset;
+    } else if (fm.prev_nacc) {
+      m += (nacc * 1000 > (int64_t)fm.target_permille * P) ? 1 : -1;
+      m = m < 1 ? 1 : (m > 10 ? 10 : m);
+    }
+    if (blockIdx.x == 0) *fm.mh_out = m;
+    *sh_h = (double)m / 10.0;
+  }
+  __syncthreads();
+  // V in place: entry (r, c) with r, c < D reads only itself and column D,
+  // which is not written here
+  const double invP = 1.0 / (double)P;
+#pragma unroll
+  for (int q = 0; q < (D * D + 63) / 64; ++q) {
+    const int idx = lane + 64 * q;
+    if (idx < D * D) {
+      const int r = idx / D, c = idx % D;
+      Ms[r * W + c] = (Ms[r * W + c] - Ms[r * W + D] * Ms[c * W + D] * invP) / (double)(P - 1);
+    }
+  }
+  __syncthreads();
+  h = *sh_h;
+  return wave_cholesky<W>(Ms, Ls, D, h, blockIdx.x == 0 ? fm.hchol_out : nullptr,
+                          blockIdx.x == 0 ? fm.flags : nullptr);
+}
+
 template <class M>
 __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
                                                   double *logprior, double *loglik, void *state,
                                                   const double *__restrict__ hchol, uint64_t seed,
                                                   uint64_t run, uint64_t cycle, uint64_t iter,
-                                                  unsigned long long *n_accept, uint8_t *accepted) {
+                                                  unsigned long long *n_accept, uint8_t *accepted,
+                                                  MomFuse fm) {
   constexpr int D = M::D;
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
   constexpr int SS = StoredS<M>::value;
+  constexpr bool kCanFuse = D < 16;
+  __shared__ double Ms[kCanFuse ? 256 : 1], Ls[kCanFuse ? 256 : 1], sh_h;
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  bool fused = false, chol_ok = true;
+  double h = 0.0;
+  if constexpr (kCanFuse) {
+    if (fm.part) {
+      fused = true;
+      chol_ok = fused_scale<D>(fm, P, Ms, Ls, &sh_h, h);
+    }
+  }
   int acc = 0;
   if (p < P) {
     double th[D], z[D], pr[D];
 #pragma unroll
     for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
     normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+    if (fused) {
+      // h L rounded as the moments kernels round it: h * L_ik (0 without a factor)
 #pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double s = 0.0;
+      for (int i = 0; i < D; ++i) {
+        double s = 0.0;
 #pragma unroll
-      for (int k = 0; k <= i; ++k) s = fma(hchol[i * D + k], z[k], s);
-      pr[i] = th[i] + s;
+        for (int k = 0; k <= i; ++k)
+          s = fma(chol_ok ? h * Ls[kCanFuse ? i * 16 + k : 0] : 0.0, z[k], s);
+        pr[i] = th[i] + s;
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < D; ++i) {
+        double s = 0.0;
+#pragma unroll
+        for (int k = 0; k <= i; ++k) s = fma(hchol[i * D + k], z[k], s);
+        pr[i] = th[i] + s;
+      }
     }
     const double lp1 = M::logprior(pr);
     R st[SR];
@@ -484,15 +573,21 @@ struct OpsOf {
                               double *logprior, double *loglik, void *state, const double *hchol,
                               uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
                               int64_t *n_accept, uint8_t *accepted, const KernelTimer *timer,
-                              hipStream_t s) {
+                              const MomFuse *fuse, hipStream_t s) {
     auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
+    MomFuse fm{};
+    if (fuse) {
+      if (M::D >= 16) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 16");
+      fm = *fuse;
+    }
     if (timer)
       hipExtLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
                             timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
-                            run, cycle, iter, acc, accepted);
+                            run, cycle, iter, acc, accepted, fm);
     else
       hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
-                         logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted);
+                         logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted,
+                         fm);
     return launch_status("mutate");
   }
 
