@@ -701,9 +701,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       double *hl = rec->hchol + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d;
       double *mslot = indep ? rec->mean + ((int64_t)l * cfg->RmaxRec + (r - 1)) * d : nullptr;
       int64_t *nacc = rec->n_accept + (int64_t)l * cfg->RmaxRec + (r - 1);
-      // The random-walk step folds the proposal scale into its own launch
-      // (d < 16); the partial sums still come from their own kernel.
-      const bool fold = !cfg->replay && cfg->kernel == SMC_KERNEL_RW && d < 16;
+      // The random-walk step folds the proposal scale into its own launch;
+      // the partial sums still come from their own kernel.
+      const bool fold = !cfg->replay && cfg->kernel == SMC_KERNEL_RW;
       MomFuse fm{};
       if (!cfg->replay) {
         // h starts at 0.5 in each M phase; later iterations first apply the
@@ -715,10 +715,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         ma.mean_out = mslot;
         if (fold) {
           int64_t nb = 0;
-          if ((st = launch_moment_partials(ma, nb, s))) return st;
+          if ((st = launch_moment_partials(ma, &fm.part, nb, s))) return st;
           // two step-size slots, alternating, as every block reads the
           // previous iteration's value while block 0 writes this one's
-          fm.part = ma.part;
           fm.nb = (int32_t)nb;
           fm.mh_reset = ma.mh_reset;
           fm.mh_in = (r & 1) ? mh + 1 : mh;

@@ -913,14 +913,28 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   return launch_status("particle_moments/final");
 }
 
-smc_status launch_moment_partials(const MomArgs &a, int64_t &nb, hipStream_t s) {
-  if (a.d + 1 > 16) return set_error(SMC_E_UNSUPPORTED, "folded moments need d < 16");
+smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t &nb,
+                                  hipStream_t s) {
+  if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < %d", kDMax);
   int64_t chunk = 0;
   moment_partition(a.P, a.d, chunk, nb);
   if (nb > kMomBlocks) return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
-  hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
+  *part = a.part;
+  if (a.d + 1 <= 16) {
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
+                       a.d, chunk, a.part);
+    return launch_status("particle_moments/partial");
+  }
+  hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
                      chunk, a.part);
-  return launch_status("particle_moments/partial");
+  smc_status st = launch_status("particle_moments/partial");
+  if (st) return st;
+  // summed into the slot after the partials, as launch_moments does
+  double *sums = a.part + nb * 1024;
+  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(64), 0, s, a.part, (int32_t)nb, 1024, sums);
+  *part = sums;
+  nb = 1;
+  return launch_status("particle_moments/sum");
 }
 
 smc_status launch_adapt(const int64_t *n_accept, int64_t P, int32_t target_permille,

@@ -31,13 +31,13 @@ struct KernelTimer {
   hipEvent_t start, stop;
 };
 
-// The proposal scale folded into the random-walk step for d < 16: each block
+// The proposal scale folded into the random-walk step (d < 32): each block
 // sums the moment partials, applies the step-size rule and factors the
 // particle variance itself, with the arithmetic of the separate moments
 // kernels (so the results agree to the bit); block 0 writes the step size and
 // h L for the record.
 struct MomFuse {
-  const double *part;        // [nb][16 * 16] partial sums; NULL: not fused
+  const double *part;        // [nb][W * W] partial sums, W = 16 (d < 16) or 32; NULL: unfused
   int32_t nb;
   int32_t mh_reset;          // > 0: the step size is set to this value
   const int32_t *mh_in;      // the previous iteration's step size (tenths)
@@ -131,9 +131,11 @@ struct MomArgs {
   int32_t *flags;
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
-// Only the partial sums of launch_moments (d < 16), for a step that folds the
-// rest in (MomFuse); nb receives the number of partials.
-smc_status launch_moment_partials(const MomArgs &a, int64_t &nb, hipStream_t s);
+// Only the partial sums of launch_moments, for a step that folds the rest in
+// (MomFuse): *part and nb receive the partials to add (for d >= 16 they are
+// first summed into one).
+smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t &nb,
+                                  hipStream_t s);
 // Particles per wave (chunk) and blocks (nb <= kMomBlocks) of the moment
 // partials of P particles of dimension d.
 void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb);

@@ -128,10 +128,9 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 // step-size rule, V and its Cholesky factor in LDS, exactly as the separate
 // moments kernels do (k_mom_final).  Returns whether V was positive definite;
 // h receives the step size.
-template <int D>
+template <int D, int W>
 __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double *Ms, double *Ls,
                                             double *sh_h, double &h) {
-  constexpr int W = 16;
   constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
   const int lane = threadIdx.x;
   int32_t m = 0;
@@ -199,15 +198,16 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
   constexpr int SS = StoredS<M>::value;
-  constexpr bool kCanFuse = D < 16;
-  __shared__ double Ms[kCanFuse ? 256 : 1], Ls[kCanFuse ? 256 : 1], sh_h;
+  constexpr int W = D < 16 ? 16 : 32;  // padded width of the moment matrices
+  constexpr bool kCanFuse = D < 32;
+  __shared__ double Ms[kCanFuse ? W * W : 1], Ls[kCanFuse ? W * W : 1], sh_h;
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   bool fused = false, chol_ok = true;
   double h = 0.0;
   if constexpr (kCanFuse) {
     if (fm.part) {
       fused = true;
-      chol_ok = fused_scale<D>(fm, P, Ms, Ls, &sh_h, h);
+      chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h);
     }
   }
   int acc = 0;
@@ -223,7 +223,7 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k <= i; ++k)
-          s = fma(chol_ok ? h * Ls[kCanFuse ? i * 16 + k : 0] : 0.0, z[k], s);
+          s = fma(chol_ok ? h * Ls[kCanFuse ? i * W + k : 0] : 0.0, z[k], s);
         pr[i] = th[i] + s;
       }
     } else {
@@ -577,7 +577,7 @@ struct OpsOf {
     auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
     MomFuse fm{};
     if (fuse) {
-      if (M::D >= 16) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 16");
+      if (M::D >= 32) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 32");
       fm = *fuse;
     }
     if (timer)
