@@ -330,6 +330,8 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
     int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(first_chunk, cap));
     int64_t t = t_from;
     StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
+    // With page-locked slots the decision kernel stores the decision and the
+    // flags word there itself (no copy); else the decision is copied back.
     PinnedSlots *pin = pinned_slots();
     StopInfo pageable{};
     StopInfo *stop_host = pin ? &pin->stop : &pageable;
@@ -355,10 +357,13 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
       if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, t, t1, check_every,
                              t_max, zero_first, W, s)) ||
           (st = launch_rss_cols(W, P, nc, rsscols, s)) ||
-          (st = launch_find_stop(rsscols, nc, t, t1, check_every, t_max, rss_min, stop_dev, s)))
+          (st = launch_find_stop(rsscols, nc, t, t1, check_every, t_max, rss_min, stop_dev, s,
+                                 pin ? &pin->stop : nullptr,
+                                 ws_at<int32_t>(pop, L.small + kSmallFlags),
+                                 pin ? &pin->flags : nullptr)))
         return st;
-      if (hipMemcpyAsync(stop_host, stop_dev, sizeof(StopInfo), hipMemcpyDeviceToHost, s) !=
-              hipSuccess ||
+      if ((!pin && hipMemcpyAsync(stop_host, stop_dev, sizeof(StopInfo), hipMemcpyDeviceToHost,
+                                  s) != hipSuccess) ||
           hipEventRecord(ev, s) != hipSuccess)
         return set_error(SMC_E_DEVICE, "correct: reading the stop decision failed");
       if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t, t1,
@@ -658,12 +663,10 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         return set_error(SMC_E_INVALID_ARG, "replayed date %lld out of order", (long long)t_stop);
     }
     // The flags raised by the previous cycle's S and M phases travel back
-    // with this cycle's first RSS readback (one host synchronisation fewer
-    // per cycle); a raised flag ends the run after that readback.
+    // with this cycle's C-phase decisions (the decision kernel stores them in
+    // the page-locked slot; one host synchronisation fewer per cycle); a
+    // raised flag ends the run after that readback.
     int32_t *fl_host = cfg->replay ? nullptr : pinned_flags_slot();
-    if (fl_host && l > 0 &&
-        hipMemcpyAsync(fl_host, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
-      return set_error(SMC_E_DEVICE, "reading flags failed");
     int64_t t_new = t;
     double rss = NAN;
     // Speculate on a cycle twice as long as the previous one, so most C
@@ -679,7 +682,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
                            cfg->replay ? nullptr : &rss, stream, hint,
                            cfg->replay ? nullptr : &ahead, &resampled)))
       return st;
-    // correct_impl has waited for its last readback, which follows the flags'
+    // correct_impl has waited for its last decision, which carried the flags
     if (fl_host && l > 0 && *fl_host) {
       rec->L = l;
       return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", *fl_host, l);

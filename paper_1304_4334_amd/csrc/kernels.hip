@@ -122,10 +122,14 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
 // The chunk's stopping decision (Section 3.3: the first checked date whose
 // RSS is below rss_min): one wave scans the columns 64 at a time.  Column c
 // holds date first + c * check_every, the multiples of check_every after t
-// up to t1, and t_max last when it is not a multiple.
+// up to t1, and t_max last when it is not a multiple.  The decision (and the
+// flags word, when flags_host is given) is also stored to host memory
+// (page-locked, mapped) when out_host is given.
 __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc, int64_t t,
                                                   int64_t t1, int64_t check_every, int64_t t_max,
-                                                  double rss_min, StopInfo *out) {
+                                                  double rss_min, StopInfo *out,
+                                                  StopInfo *out_host, const int32_t *flags,
+                                                  int32_t *flags_host) {
   int first = -1;
   for (int base = 0; base < nc; base += 64) {
     const int c = base + (int)threadIdx.x;
@@ -145,6 +149,8 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
     o.below = first >= 0;
     o.ends = first >= 0 || t1 >= t_max;
     *out = o;
+    if (out_host) *out_host = o;
+    if (flags_host) *flags_host = *flags;
   }
 }
 
@@ -839,11 +845,12 @@ smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rs
 
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
                             int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
-                            hipStream_t s) {
+                            hipStream_t s, StopInfo *out_host, const int32_t *flags,
+                            int32_t *flags_host) {
   if (nc < 1 || nc > kMaxChunk)
     return set_error(SMC_E_INVALID_ARG, "stop search over %lld columns", (long long)nc);
   hipLaunchKernelGGL(k_find_stop, dim3(1), dim3(64), 0, s, rss, (int32_t)nc, t, t1, check_every,
-                     t_max, rss_min, out);
+                     t_max, rss_min, out, out_host, flags, flags_host);
   return launch_status("correct/find_stop");
 }
 

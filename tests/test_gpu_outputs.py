@@ -137,3 +137,22 @@ def test_mutation_timing_leaves_the_run_unchanged(kernel):
         ms = rec.mutate_ms[l, :b["R"][l]]
         assert np.all(ms > 0) and np.all(ms < 1e3), ms
         assert np.all(rec.mutate_ms[l, b["R"][l]:] == 0)
+
+
+def test_run_stops_on_numerical_flags():
+    """An observation no parameter can explain (a NaN return) gives every
+    particle zero weight: the S phase raises the dead-group flag, which the
+    driver reads back with the next C phase's decision and turns into an
+    error naming the cycle (the record keeps the cycles before it)."""
+    w = SD.workload("egarch11", T=120)
+    y = np.array(w.y[:120], dtype=np.float64)
+    y[60] = np.nan                              # observation (date) 61
+    m = S.Model(w.kind, y, K=w.K, shock=w.shock, precision=S.SMC_FP64)
+    g = S.Population(m, 4, 64, max_chunk=64)
+    rec = S.Record(m, 4, Lmax=200, RmaxRec=32)
+    with pytest.raises(S.SmcError) as ei:
+        S.smc_run(m, g, seed=5, record=rec)
+    assert ei.value.status == S.SMC_E_NUMERIC
+    assert "flags" in str(ei.value)
+    L = rec.L
+    assert L >= 1 and rec.t_end[L - 1] == 61
