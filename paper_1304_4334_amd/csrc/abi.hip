@@ -285,10 +285,10 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
 // (the driver passes a length predicted from the previous cycle).  Adaptive
 // chunks: scan every checked date, compute the RSS columns, decide the stop
 // on the device, and queue the commit to the decided date before the host
-// reads the decision back; with `ahead`, the group weights and the S phase
-// (which does nothing unless the phase ended) are queued too, so the device
-// has that work in hand while the host waits.  *resampled tells whether the
-// S phase was queued that way.
+// reads the decision back; with `ahead`, the S phase (which does nothing
+// unless the phase ended, and then also writes the group weights) is queued
+// too, so the device has that work in hand while the host waits.
+// *resampled tells whether the S phase was queued that way.
 smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from,
                              int64_t t_max, int64_t check_every, double rss_min,
                              double *group_logwbar, int64_t *t_to, double *rss, void *stream,
@@ -370,14 +370,14 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
                                zero_first, s, &stop_dev->t_commit)))
         return st;
       if (ahead) {
-        if ((st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s)) ||
-            (st = launch_resample(pop->logw, pop->J, pop->N, ahead->scheme, ahead->rng.seed,
+        // the S phase also writes the group weights of the phase's end
+        if ((st = launch_resample(pop->logw, pop->J, pop->N, ahead->scheme, ahead->rng.seed,
                                   ahead->rng.run, (uint64_t)ahead->cycle, pop->ancestor,
                                   ws_at<double>(pop, L.cum),
                                   ws_at<int32_t>(pop, L.small + kSmallFlags), m->dev.d, m->dev.S,
                                   state_bytes(m), pop->theta, pop->logprior, pop->loglik,
                                   pop->state, pop->grad, ws_at<double>(pop, L.gather), s,
-                                  &stop_dev->ends)))
+                                  &stop_dev->ends, group_logwbar)))
           return st;
       }
       if (hipEventSynchronize(ev) != hipSuccess)

@@ -64,59 +64,59 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
   return launch_status("fill_i32");
 }
 
-// RSS of each recorded column: (sum e)^2 / (P sum e^2), e = exp(w - max w).
-// One block of 1024 threads per column, one pass: each thread keeps a running
-// maximum m with s1 = sum exp(w - m), s2 = sum exp(2(w - m)), rescaled when
-// m grows; the block merges the triples the same way in a fixed order.
-struct Lse3 {
-  double m, s1, s2;
-};
-__device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
-  const double m = fmax(a.m, b.m);
-  if (!(m > -INFINITY)) return Lse3{m, 0.0, 0.0};
-  const double ea = exp(a.m - m), eb = exp(b.m - m);
-  return Lse3{m, a.s1 * ea + b.s1 * eb, a.s2 * ea * ea + b.s2 * eb * eb};
+constexpr int kRssBlock = 1024;
+constexpr int kRssRegs = 16;  // values per thread held in registers (P <= 16,384 in one read)
+
+// Reduction over a block of kRssBlock threads, the 16 wave values combined in
+// wave order by every thread.
+template <class Op>
+__device__ __forceinline__ double rss_block_reduce(double v, double *lds /* >= 16 */) {
+  v = wave_reduce<Op>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  double r = lds[0];
+#pragma unroll
+  for (int i = 1; i < kRssBlock / 64; ++i) r = Op::apply(r, lds[i]);
+  return r;
 }
 
-constexpr int kRssBlock = 1024;
-
+// RSS of one column of running log weights (Section 3.3):
+// (sum e)^2 / (P sum e^2) with e = exp(logw - max), the maximum taken first.
+// The first kRssRegs values of each thread stay in registers between the two
+// passes; the rest are read again.
 __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss) {
-  __shared__ Lse3 sh[kRssBlock / 64];
+  __shared__ double sh[kRssBlock / 64];
   const double *w = W + blockIdx.x * P;
-  Lse3 acc{-INFINITY, 0.0, 0.0};
-  for (int64_t p0 = threadIdx.x; p0 < P; p0 += 8 * kRssBlock) {
-    double v[8];
+  const int64_t rest = (int64_t)threadIdx.x + (int64_t)kRssRegs * kRssBlock;
+  double v[kRssRegs];
+  double mx = -INFINITY;
 #pragma unroll
-    for (int u = 0; u < 8; ++u) {
-      const int64_t p = p0 + (int64_t)u * kRssBlock;
-      v[u] = p < P ? w[p] : -INFINITY;
+  for (int u = 0; u < kRssRegs; ++u) {
+    const int64_t p = threadIdx.x + (int64_t)u * kRssBlock;
+    v[u] = p < P ? w[p] : -INFINITY;
+  }
+#pragma unroll
+  for (int u = 0; u < kRssRegs; ++u) mx = fmax(mx, v[u]);
+  for (int64_t p = rest; p < P; p += kRssBlock) mx = fmax(mx, w[p]);
+  mx = rss_block_reduce<OpMax<double>>(mx, sh);
+  double s1 = 0.0, s2 = 0.0;
+  if (mx > -INFINITY) {
+#pragma unroll
+    for (int u = 0; u < kRssRegs; ++u) {
+      const double e = exp(v[u] - mx);
+      s1 += e;
+      s2 = fma(e, e, s2);
     }
-    double m = v[0];
-#pragma unroll
-    for (int u = 1; u < 8; ++u) m = fmax(m, v[u]);
-    Lse3 c{m, 0.0, 0.0};
-    if (m > -INFINITY) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) {
-        const double e = exp(v[u] - m);
-        c.s1 += e;
-        c.s2 = fma(e, e, c.s2);
-      }
+    for (int64_t p = rest; p < P; p += kRssBlock) {
+      const double e = exp(w[p] - mx);
+      s1 += e;
+      s2 = fma(e, e, s2);
     }
-    acc = lse3_merge(acc, c);
   }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) {
-    Lse3 o{__shfl_xor(acc.m, off, 64), __shfl_xor(acc.s1, off, 64), __shfl_xor(acc.s2, off, 64)};
-    acc = lse3_merge(acc, o);
-  }
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    Lse3 t = sh[0];
-    for (int q = 1; q < kRssBlock / 64; ++q) t = lse3_merge(t, sh[q]);
-    rss[blockIdx.x] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
-  }
+  s1 = rss_block_reduce<OpSum<double>>(s1, sh);
+  s2 = rss_block_reduce<OpSum<double>>(s2, sh);
+  if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
 }
 
 // The chunk's stopping decision (Section 3.3: the first checked date whose
@@ -253,7 +253,8 @@ __device__ __forceinline__ void gather_in_registers(const GatherArgs &g, int64_t
 __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
                                                   uint64_t seed, uint64_t run, uint64_t cycle,
                                                   int32_t *anc, double *cum_ws, int32_t *flags,
-                                                  GatherArgs g, const int32_t *go) {
+                                                  GatherArgs g, const int32_t *go,
+                                                  double *group_logwbar) {
   if (go && *go == 0) return;  // enqueued ahead of a C phase that did not end
   extern __shared__ double lds_dyn[];
   __shared__ double shd[kBlock];
@@ -281,7 +282,10 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   mx = block_reduce<OpMax<double>>(mx, shd);
   if (!(mx > -INFINITY)) {
     for (int n = tid; n < N; n += kBlock) anc[base + n] = (int32_t)(base + n);
-    if (tid == 0) atomicOr(flags, SMC_FLAG_DEAD_GROUP);
+    if (tid == 0) {
+      atomicOr(flags, SMC_FLAG_DEAD_GROUP);
+      if (group_logwbar) group_logwbar[j] = -INFINITY;
+    }
     return;
   }
   double se = 0.0;
@@ -291,6 +295,9 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
     se += e;
   }
   se = block_reduce<OpSum<double>>(se, shd);  // its barriers publish ev
+  // log wbar_j from the same maximum and sum, in the order k_group_logwbar
+  // takes them (so the value is the same to the bit)
+  if (group_logwbar && tid == 0) group_logwbar[j] = mx + log(se / (double)N);
 
   // Thread-contiguous chunks for the scans.
   const int m = (N + kBlock - 1) / kBlock;
@@ -864,7 +871,8 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
-                           double *grad, double *tmp, hipStream_t s, const int32_t *go) {
+                           double *grad, double *tmp, hipStream_t s, const int32_t *go,
+                           double *group_logwbar) {
   const int64_t P = (int64_t)J * N;
   GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
                state, tmp};
@@ -874,7 +882,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                                            kGatherLdsBytes
                                      : (size_t)N * sizeof(int32_t);
   hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), lds, s, logw, N, scheme, seed, run, cycle,
-                     anc, cum_ws, flags, g, go);
+                     anc, cum_ws, flags, g, go, group_logwbar);
   return launch_status("resample");
 }
 

@@ -113,13 +113,14 @@ smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1
                             const int32_t *flags = nullptr, int32_t *flags_host = nullptr);
 // Resampling and the replacement of every particle by its ancestor, one block
 // per group; with `go` (device flag, may be NULL) the kernel does nothing
-// while *go is 0.
+// while *go is 0; with group_logwbar (may be NULL) it also writes each
+// group's log mean weight, as launch_group_logwbar does.
 smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
                            double *grad, double *tmp, hipStream_t s,
-                           const int32_t *go = nullptr);
+                           const int32_t *go = nullptr, double *group_logwbar = nullptr);
 struct MomArgs {
   const double *theta;
   int64_t P;
