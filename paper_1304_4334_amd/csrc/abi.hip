@@ -96,33 +96,33 @@ int64_t chunk_capacity(const smc_model *m, const smc_particles *pop) {
 
 int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8; }
 
-// Page-locked host slots for what the driver reads back during a run: the
-// C-phase chunk's stopping decision and the numerical flags word (one set per
-// host thread, kept for the life of the process); NULL if it cannot be had.
-struct PinnedSlots {
-  StopInfo stop;
-  int32_t flags;
-  int32_t pad;
-};
-PinnedSlots *pinned_slots() {
-  thread_local PinnedSlots *buf = nullptr;
+// Page-locked, coherent host slot where the C-phase decision kernel stores
+// each chunk's decision and the numerical flags word (one per host thread,
+// kept for the life of the process); NULL if it cannot be had.  Device
+// stores to coherent host memory bypass the device caches, so the host needs
+// neither a fence nor an event: it watches the slot for both
+// sequence-tagged halves while the work queued after the kernel runs on.
+DecisionSlot *decision_slot() {
+  thread_local DecisionSlot *buf = nullptr;
   thread_local bool tried = false;
   if (!tried) {
     tried = true;
     void *p = nullptr;
-    if (hipHostMalloc(&p, sizeof(PinnedSlots), hipHostMallocDefault) == hipSuccess)
-      buf = static_cast<PinnedSlots *>(p);
+    if (hipHostMalloc(&p, sizeof(DecisionSlot), hipHostMallocCoherent) == hipSuccess) {
+      buf = static_cast<DecisionSlot *>(p);
+      *buf = DecisionSlot{};
+    }
   }
   return buf;
 }
 int32_t *pinned_flags_slot() {
-  PinnedSlots *b = pinned_slots();
+  DecisionSlot *b = decision_slot();
   return b ? &b->flags : nullptr;
 }
 
 // An event (no timing) of the calling thread for the current device, marking
-// the completion of a readback so the host can wait for it alone while later
-// work stays queued; kept for the life of the process.
+// the completion of a copy back so the host can wait for it alone while
+// later work stays queued; kept for the life of the process.
 smc_status readback_event(hipEvent_t *out) {
   thread_local hipEvent_t ev[16] = {};
   int dev = -1;
@@ -134,6 +134,39 @@ smc_status readback_event(hipEvent_t *out) {
   }
   *out = ev[dev];
   return SMC_OK;
+}
+
+// Waits until both halves of the slot carry `seq`, then reads the decision;
+// the tags are read before the data they cover, so a half is read only after
+// it landed.  The stream is polled every millisecond: once all its work has
+// completed the halves get 10 more ms, then the wait fails (false).
+bool await_decision(const DecisionSlot *slot, uint32_t seq, hipStream_t s, StopInfo *out) {
+  const volatile uint32_t *w = reinterpret_cast<const volatile uint32_t *>(slot);
+  using clock = std::chrono::steady_clock;
+  auto next_poll = clock::now() + std::chrono::milliseconds(1);
+  clock::time_point idle_since{};
+  bool idle = false;
+  while (!(w[0] == seq && w[7] == seq)) {
+    const auto now = clock::now();
+    if (now < next_poll) continue;
+    next_poll = now + std::chrono::milliseconds(1);
+    if (!idle) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipErrorNotReady) continue;
+      if (q != hipSuccess) return false;
+      idle = true;
+      idle_since = now;
+    } else if (now - idle_since > std::chrono::milliseconds(10)) {
+      return false;
+    }
+  }
+  uint32_t v[8];
+  for (int i = 1; i < 7; ++i) v[i] = w[i];
+  out->t_commit = (int64_t)(((uint64_t)v[3] << 32) | v[2]);
+  out->rss = __builtin_bit_cast(double, ((uint64_t)v[5] << 32) | v[4]);
+  out->ends = (int32_t)(v[6] & 1u);
+  out->below = (int32_t)((v[6] >> 1) & 1u);
+  return true;
 }
 
 // Event i of the calling thread's pool for the current device.  The pools
@@ -330,13 +363,13 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
     int64_t chunk = std::max<int64_t>(1, std::min<int64_t>(first_chunk, cap));
     int64_t t = t_from;
     StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
-    // With page-locked slots the decision kernel stores the decision and the
+    // With the host slot the decision kernel stores the decision and the
     // flags word there itself (no copy); else the decision is copied back.
-    PinnedSlots *pin = pinned_slots();
-    StopInfo pageable{};
-    StopInfo *stop_host = pin ? &pin->stop : &pageable;
-    hipEvent_t ev;
-    if ((st = readback_event(&ev))) return st;
+    DecisionSlot *slot = decision_slot();
+    thread_local uint32_t slot_seq = 0;
+    StopInfo got{};
+    hipEvent_t ev = nullptr;
+    if (!slot && (st = readback_event(&ev))) return st;
     bool stopped = false, queued_ahead = false;
     while (!stopped) {
       const int64_t t1 = std::min(t + chunk, t_max);
@@ -358,13 +391,11 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
                              t_max, zero_first, W, s)) ||
           (st = launch_rss_cols(W, P, nc, rsscols, s)) ||
           (st = launch_find_stop(rsscols, nc, t, t1, check_every, t_max, rss_min, stop_dev, s,
-                                 pin ? &pin->stop : nullptr,
-                                 ws_at<int32_t>(pop, L.small + kSmallFlags),
-                                 pin ? &pin->flags : nullptr)))
+                                 slot, ++slot_seq, ws_at<int32_t>(pop, L.small + kSmallFlags))))
         return st;
-      if ((!pin && hipMemcpyAsync(stop_host, stop_dev, sizeof(StopInfo), hipMemcpyDeviceToHost,
-                                  s) != hipSuccess) ||
-          hipEventRecord(ev, s) != hipSuccess)
+      if (!slot && (hipMemcpyAsync(&got, stop_dev, sizeof(StopInfo), hipMemcpyDeviceToHost, s) !=
+                        hipSuccess ||
+                    hipEventRecord(ev, s) != hipSuccess))
         return set_error(SMC_E_DEVICE, "correct: reading the stop decision failed");
       if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik, t, t1,
                                zero_first, s, &stop_dev->t_commit)))
@@ -380,12 +411,12 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
                                   &stop_dev->ends, group_logwbar)))
           return st;
       }
-      if (hipEventSynchronize(ev) != hipSuccess)
-        return set_error(SMC_E_DEVICE, "correct: waiting for the stop decision failed");
+      if (slot ? !await_decision(slot, slot_seq, s, &got) : hipEventSynchronize(ev) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "correct: the stop decision did not reach the host");
       zero_first = false;
-      rss_at_stop = stop_host->rss;
-      t = stop_host->t_commit;
-      stopped = stop_host->ends != 0;
+      rss_at_stop = got.rss;
+      t = got.t_commit;
+      stopped = got.ends != 0;
       queued_ahead = ahead != nullptr;
       chunk = std::min(2 * chunk, cap);
     }

@@ -74,6 +74,18 @@ struct StopInfo {
   int32_t ends;
 };
 
+// The same decision, with the workspace's flags word, as the decision kernel
+// stores it in page-locked host memory: two 16-byte stores, each carrying
+// the call's sequence number, so the host can tell that both have landed.
+struct alignas(16) DecisionSlot {
+  uint32_t seq_a;
+  int32_t flags;
+  int64_t t_commit;
+  double rss;
+  uint32_t ends_below;  // bit 0: the phase ends; bit 1: the RSS fell below the threshold
+  uint32_t seq_b;
+};
+
 WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N);
 
 }  // namespace smc

@@ -122,14 +122,14 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
 // The chunk's stopping decision (Section 3.3: the first checked date whose
 // RSS is below rss_min): one wave scans the columns 64 at a time.  Column c
 // holds date first + c * check_every, the multiples of check_every after t
-// up to t1, and t_max last when it is not a multiple.  The decision (and the
-// flags word, when flags_host is given) is also stored to host memory
-// (page-locked, mapped) when out_host is given.
+// up to t1, and t_max last when it is not a multiple.  With host_slot, the
+// decision and the flags word also go to host memory, in two 16-byte stores
+// tagged with seq.
 __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc, int64_t t,
                                                   int64_t t1, int64_t check_every, int64_t t_max,
                                                   double rss_min, StopInfo *out,
-                                                  StopInfo *out_host, const int32_t *flags,
-                                                  int32_t *flags_host) {
+                                                  DecisionSlot *host_slot, uint32_t seq,
+                                                  const int32_t *flags) {
   int first = -1;
   for (int base = 0; base < nc; base += 64) {
     const int c = base + (int)threadIdx.x;
@@ -149,8 +149,16 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
     o.below = first >= 0;
     o.ends = first >= 0 || t1 >= t_max;
     *out = o;
-    if (out_host) *out_host = o;
-    if (flags_host) *flags_host = *flags;
+    if (host_slot) {
+      const int32_t fl = *flags;
+      const uint64_t tc = (uint64_t)o.t_commit;
+      const uint64_t rb = __builtin_bit_cast(uint64_t, o.rss);
+      const uint4 a = make_uint4(seq, (uint32_t)fl, (uint32_t)tc, (uint32_t)(tc >> 32));
+      const uint4 b = make_uint4((uint32_t)rb, (uint32_t)(rb >> 32),
+                                 (uint32_t)(o.ends | (o.below << 1)), seq);
+      reinterpret_cast<uint4 *>(host_slot)[0] = a;
+      reinterpret_cast<uint4 *>(host_slot)[1] = b;
+    }
   }
 }
 
@@ -852,12 +860,12 @@ smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rs
 
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
                             int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
-                            hipStream_t s, StopInfo *out_host, const int32_t *flags,
-                            int32_t *flags_host) {
+                            hipStream_t s, DecisionSlot *host_slot, uint32_t seq,
+                            const int32_t *flags) {
   if (nc < 1 || nc > kMaxChunk)
     return set_error(SMC_E_INVALID_ARG, "stop search over %lld columns", (long long)nc);
   hipLaunchKernelGGL(k_find_stop, dim3(1), dim3(64), 0, s, rss, (int32_t)nc, t, t1, check_every,
-                     t_max, rss_min, out, out_host, flags, flags_host);
+                     t_max, rss_min, out, host_slot, seq, flags);
   return launch_status("correct/find_stop");
 }
 

@@ -105,12 +105,12 @@ smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rs
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
 // The stopping decision over nc RSS columns of the chunk (t, t1] into *out,
-// and into page-locked host memory out_host (with *flags into flags_host)
-// when those are not NULL.
+// and with *flags into page-locked host memory host_slot (tagged with seq)
+// when that is not NULL.
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
                             int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
-                            hipStream_t s, StopInfo *out_host = nullptr,
-                            const int32_t *flags = nullptr, int32_t *flags_host = nullptr);
+                            hipStream_t s, DecisionSlot *host_slot = nullptr, uint32_t seq = 0,
+                            const int32_t *flags = nullptr);
 // Resampling and the replacement of every particle by its ancestor, one block
 // per group; with `go` (device flag, may be NULL) the kernel does nothing
 // while *go is 0; with group_logwbar (may be NULL) it also writes each
