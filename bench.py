@@ -351,10 +351,11 @@ def cpu_baseline(name, seconds):
 
 def kernel_probe():
     """A short fixed sequence for hardware-counter passes: a 256 MiB device
-    copy (calibration of the byte counters), then three M steps at t = T of
+    copy (calibration of the byte counters), then one whole adaptive run of
     each roofline workload (EGARCH(1,1) FP64 16,384 particles; EGARCH(2)-t
-    FP32 and egarch_23 FP32, 65,536 particles)."""
-    import numpy as np
+    FP32 and egarch_23 FP32, 65,536 particles).  The last cycle of each run
+    ends at t = T; its M steps are the last `R_last` mutation dispatches of
+    the run, whose counters give the traffic per launch at t = T."""
     import torch
 
     import paper_1304_4334_amd as S
@@ -366,20 +367,21 @@ def kernel_probe():
         b.copy_(a)
     torch.cuda.synchronize()
     log("[probe] copies done")
+    runs = []
     for name, prec in (("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32),
                        ("egarch23", S.SMC_FP32)):
         w = SD.workload(name)
         m = S.Model.from_workload(w, precision=prec)
-        pop = S.Population(m, w.J, w.N, max_chunk=16)
-        th = SD.random_thetas(w, w.P, 1, spread=0.01)
-        pop.theta.copy_(torch.from_numpy(th.T.copy()))
-        pop.loglik.copy_(S.smc_loglik(m, pop.theta, w.T))
-        hl = torch.from_numpy(np.linalg.cholesky(np.cov(th[::8].T)) * 0.3).cuda()
-        for it in range(3):
-            S.smc_mutate(m, pop, w.T, hl, seed=1, it=it + 1)
+        pop = S.Population(m, w.J, w.N, max_chunk=1024)
+        rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64)
+        S.smc_run(m, pop, seed=1, record=rec)
         torch.cuda.synchronize()
+        s = rec.summary()
+        runs.append(dict(workload=name, precision="fp64" if prec == S.SMC_FP64 else "fp32",
+                         P=w.P, T=w.T, mutate_launches=int(s["mh_steps"]),
+                         R_last=int(s["R"][-1]), t_last=int(s["t_end"][-1])))
         log(f"[probe] {name} done")
-    print(json.dumps({"probe": "done", "copy_bytes": 2 * a.numel() * 4,
+    print(json.dumps({"probe": "done", "copy_bytes": 2 * a.numel() * 4, "runs": runs,
                       "sources_sha256": sources_sha256()}), flush=True)
 
 

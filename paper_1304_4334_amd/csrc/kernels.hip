@@ -65,7 +65,7 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
 }
 
 constexpr int kRssBlock = 1024;
-constexpr int kRssRegs = 16;  // values per thread held in registers (P <= 16,384 in one read)
+constexpr int kRssRegs = 16;  // values per thread held in registers: P <= 16,384 per column
 
 // Reduction over a block of kRssBlock threads, the 16 wave values combined in
 // wave order by every thread.
@@ -82,13 +82,12 @@ __device__ __forceinline__ double rss_block_reduce(double v, double *lds /* >= 1
 }
 
 // RSS of one column of running log weights (Section 3.3):
-// (sum e)^2 / (P sum e^2) with e = exp(logw - max), the maximum taken first.
-// The first kRssRegs values of each thread stay in registers between the two
-// passes; the rest are read again.
+// (sum e)^2 / (P sum e^2) with e = exp(logw - max).  Columns of up to
+// kRssRegs * kRssBlock values: the maximum first, then the sums, the values
+// held in registers between the two passes.
 __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss) {
   __shared__ double sh[kRssBlock / 64];
   const double *w = W + blockIdx.x * P;
-  const int64_t rest = (int64_t)threadIdx.x + (int64_t)kRssRegs * kRssBlock;
   double v[kRssRegs];
   double mx = -INFINITY;
 #pragma unroll
@@ -98,7 +97,6 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
   }
 #pragma unroll
   for (int u = 0; u < kRssRegs; ++u) mx = fmax(mx, v[u]);
-  for (int64_t p = rest; p < P; p += kRssBlock) mx = fmax(mx, w[p]);
   mx = rss_block_reduce<OpMax<double>>(mx, sh);
   double s1 = 0.0, s2 = 0.0;
   if (mx > -INFINITY) {
@@ -108,15 +106,65 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
       s1 += e;
       s2 = fma(e, e, s2);
     }
-    for (int64_t p = rest; p < P; p += kRssBlock) {
-      const double e = exp(w[p] - mx);
-      s1 += e;
-      s2 = fma(e, e, s2);
-    }
   }
   s1 = rss_block_reduce<OpSum<double>>(s1, sh);
   s2 = rss_block_reduce<OpSum<double>>(s2, sh);
   if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
+}
+
+// Longer columns in one pass: each thread keeps a running maximum m with
+// s1 = sum exp(w - m), s2 = sum exp(2 (w - m)), rescaled when m grows, over
+// chunks of 16 values; the block merges the triples in a fixed tree order.
+struct Lse3 {
+  double m, s1, s2;
+};
+__device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
+  const double m = fmax(a.m, b.m);
+  if (!(m > -INFINITY)) return Lse3{m, 0.0, 0.0};
+  const double ea = exp(a.m - m), eb = exp(b.m - m);
+  return Lse3{m, a.s1 * ea + b.s1 * eb, a.s2 * ea * ea + b.s2 * eb * eb};
+}
+__device__ __forceinline__ Lse3 lse3_shfl_xor(const Lse3 &a, int off) {
+  return Lse3{__shfl_xor(a.m, off, 64), __shfl_xor(a.s1, off, 64), __shfl_xor(a.s2, off, 64)};
+}
+
+__global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t P, double *rss) {
+  __shared__ Lse3 sh[kRssBlock / 64];
+  const double *w = W + blockIdx.x * P;
+  constexpr int kChunk = 16;
+  Lse3 acc{-INFINITY, 0.0, 0.0};
+  for (int64_t p0 = threadIdx.x; p0 < P; p0 += (int64_t)kChunk * kRssBlock) {
+    double v[kChunk];
+#pragma unroll
+    for (int u = 0; u < kChunk; ++u) {
+      const int64_t p = p0 + (int64_t)u * kRssBlock;
+      v[u] = p < P ? w[p] : -INFINITY;
+    }
+    double m = v[0];
+#pragma unroll
+    for (int u = 1; u < kChunk; ++u) m = fmax(m, v[u]);
+    Lse3 c{m, 0.0, 0.0};
+    if (m > -INFINITY) {
+#pragma unroll
+      for (int u = 0; u < kChunk; ++u) {
+        const double e = exp(v[u] - m);
+        c.s1 += e;
+        c.s2 = fma(e, e, c.s2);
+      }
+    }
+    acc = lse3_merge(acc, c);
+  }
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) acc = lse3_merge(acc, lse3_shfl_xor(acc, off));
+  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+  __syncthreads();
+  if (threadIdx.x < 64) {
+    Lse3 t = (threadIdx.x < kRssBlock / 64) ? sh[threadIdx.x] : Lse3{-INFINITY, 0.0, 0.0};
+#pragma unroll
+    for (int off = 8; off > 0; off >>= 1) t = lse3_merge(t, lse3_shfl_xor(t, off));
+    if (threadIdx.x == 0)
+      rss[blockIdx.x] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
+  }
 }
 
 // The chunk's stopping decision (Section 3.3: the first checked date whose
@@ -854,7 +902,10 @@ smc_status launch_test_fns(const DevModel &m, int64_t P, const double *theta, co
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s) {
   if (ncols <= 0) return SMC_OK;
-  hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
+  if (P <= (int64_t)kRssRegs * kRssBlock)
+    hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
+  else
+    hipLaunchKernelGGL(k_rss_cols_long, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
   return launch_status("correct/rss");
 }
 

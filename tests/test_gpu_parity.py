@@ -116,12 +116,13 @@ def test_loglik_empty_and_bad_args():
 
 # ------------------------------------------------------------ C phase (a2) --
 
-@pytest.mark.parametrize("name,prec,ce", [("linreg", 0, 1), ("egarch11", 0, 1),
-                                          ("egarch11", 1, 1), ("egarch2t", 0, 3)])
-def test_correct_matches_oracle(name, prec, ce):
+@pytest.mark.parametrize("name,prec,ce,J,N", [("linreg", 0, 1, 4, 64), ("egarch11", 0, 1, 4, 64),
+                                              ("egarch11", 1, 1, 4, 64), ("egarch2t", 0, 3, 4, 64),
+                                              # RSS columns longer than 16,384 (one-pass kernel)
+                                              ("egarch11", 0, 1, 8, 4096)])
+def test_correct_matches_oracle(name, prec, ce, J, N):
     w = SD.workload(name, T=400)
     gm, om = gpu_model(w, prec), ora_model(w)
-    J, N = 4, 64
     opop = O.Pop(om, J, N)
     O.init(om, opop, seed=3)
     # advance both from the prior through two C phases
