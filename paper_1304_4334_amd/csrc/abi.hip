@@ -108,7 +108,8 @@ DecisionSlot *decision_slot() {
   if (!tried) {
     tried = true;
     void *p = nullptr;
-    if (hipHostMalloc(&p, sizeof(DecisionSlot), hipHostMallocCoherent) == hipSuccess) {
+    const unsigned flags = hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable;
+    if (hipHostMalloc(&p, sizeof(DecisionSlot), flags) == hipSuccess) {
       buf = static_cast<DecisionSlot *>(p);
       *buf = DecisionSlot{};
     }

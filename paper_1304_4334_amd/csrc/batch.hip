@@ -83,7 +83,7 @@ __global__ void __launch_bounds__(256) k_batch_mom_partial(BatchArgs a) {
 
 __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   __shared__ double Ms[256];
-  __shared__ double Ls[256];
+  __shared__ double Ls[16 * chol_ld<16>()];
   __shared__ double sh_h;
   const BatchDyn &dy = a.dyn[blockIdx.x];
   const BatchStatic &st = a.runs[dy.idx];

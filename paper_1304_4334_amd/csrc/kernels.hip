@@ -614,7 +614,7 @@ __global__ void __launch_bounds__(64) k_mom_sum(const double *part, int32_t nb, 
 template <int W>
 __global__ void __launch_bounds__(W * W) k_mom_final(MomArgs a, int32_t nb) {
   __shared__ double Ms[W * W];
-  __shared__ double Ls[W * W];
+  __shared__ double Ls[W * chol_ld<W>()];
   __shared__ double sh_h;
   const int e = threadIdx.x;  // entry (r, c) = (e / W, e % W)
   const int d = a.d;

@@ -139,25 +139,34 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
     m = *fm.mh_in;
     if (fm.mh_reset <= 0 && fm.prev_nacc) nacc = *fm.prev_nacc;
   }
+  // Lane entries idx = lane + 64 q; each batch issues the loads of every
+  // entry before adding any, so the partials' latency is paid once per batch
+  // (a single round for the pre-summed 32-wide partials).
+  constexpr int Q = (E + 63) / 64;
+  constexpr int kB = Q >= 16 ? 1 : 16 / Q;  // partials per entry in flight
+  double sum[Q];
 #pragma unroll
-  for (int q = 0; q < (E + 63) / 64; ++q) {
-    const int idx = lane + 64 * q;
-    if (idx < E) {
+  for (int q = 0; q < Q; ++q) sum[q] = 0.0;
+  for (int b0 = 0; b0 < fm.nb; b0 += kB) {
+    double x[Q][kB];
+#pragma unroll
+    for (int q = 0; q < Q; ++q) {
+      const int idx = lane + 64 * q;
       const int e = (idx / (D + 1)) * W + idx % (D + 1);
-      const double *pp = fm.part + e;
-      constexpr int kBatch = 16;
-      double sum = 0.0;
-      for (int b0 = 0; b0 < fm.nb; b0 += kBatch) {
-        double x[kBatch];
 #pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-          x[u] = (b0 + u < fm.nb) ? pp[(int64_t)(b0 + u) * W * W] : 0.0;
-#pragma unroll
-        for (int u = 0; u < kBatch; ++u)
-          if (b0 + u < fm.nb) sum += x[u];
-      }
-      Ms[e] = sum;
+      for (int u = 0; u < kB; ++u)
+        x[q][u] = (idx < E && b0 + u < fm.nb) ? fm.part[(int64_t)(b0 + u) * W * W + e] : 0.0;
     }
+#pragma unroll
+    for (int q = 0; q < Q; ++q)
+#pragma unroll
+      for (int u = 0; u < kB; ++u)
+        if (b0 + u < fm.nb) sum[q] += x[q][u];
+  }
+#pragma unroll
+  for (int q = 0; q < Q; ++q) {
+    const int idx = lane + 64 * q;
+    if (idx < E) Ms[(idx / (D + 1)) * W + idx % (D + 1)] = sum[q];
   }
   if (lane == 0) {
     if (fm.mh_reset > 0) {
@@ -183,8 +192,8 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
   }
   __syncthreads();
   h = *sh_h;
-  return wave_cholesky<W>(Ms, Ls, D, h, blockIdx.x == 0 ? fm.hchol_out : nullptr,
-                          blockIdx.x == 0 ? fm.flags : nullptr);
+  return wave_cholesky_fixed<W, D>(Ms, Ls, h, blockIdx.x == 0 ? fm.hchol_out : nullptr,
+                                   blockIdx.x == 0 ? fm.flags : nullptr);
 }
 
 template <class M>
@@ -200,7 +209,7 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
   constexpr int SS = StoredS<M>::value;
   constexpr int W = D < 16 ? 16 : 32;  // padded width of the moment matrices
   constexpr bool kCanFuse = D < 32;
-  __shared__ double Ms[kCanFuse ? W * W : 1], Ls[kCanFuse ? W * W : 1], sh_h;
+  __shared__ double Ms[kCanFuse ? W * W : 1], Ls[kCanFuse ? W * chol_ld<W>() : 1], sh_h;
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   bool fused = false, chol_ok = true;
   double h = 0.0;
@@ -223,7 +232,7 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
         double s = 0.0;
 #pragma unroll
         for (int k = 0; k <= i; ++k)
-          s = fma(chol_ok ? h * Ls[kCanFuse ? i * W + k : 0] : 0.0, z[k], s);
+          s = fma(chol_ok ? h * Ls[kCanFuse ? i * chol_ld<W>() + k : 0] : 0.0, z[k], s);
         pr[i] = th[i] + s;
       }
     } else {
