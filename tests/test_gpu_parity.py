@@ -453,3 +453,35 @@ def test_independent_sampler_run_matches_oracle_run():
                        atol=1e-12)
     assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
     assert np.allclose(theta_np(g), opop.theta, rtol=1e-9, atol=1e-10)
+
+
+@pytest.mark.parametrize("name,prec", [("egarch11", S.SMC_FP64), ("egarch2t", S.SMC_FP32),
+                                       ("egarch23", S.SMC_FP32)])
+def test_replay_of_own_design_is_bitwise(name, prec):
+    """An adaptive run (C-phase decisions on the device, S phase writing the
+    group weights, proposal scale folded into the step) replayed from its
+    own record with the same key (Algorithm 1, with separate kernels for
+    each of those) makes the same Metropolis decisions and the same
+    particles to the bit: the recorded hL is the one the steps used.  The
+    weights agree to rounding only: an adaptive C phase may commit its
+    observations in more than one chunk, the replay in one."""
+    w = SD.workload(name, T=150)
+    gm = gpu_model(w, prec)
+    J, N = 4, 128
+    g1 = S.Population(gm, J, N, max_chunk=32)
+    rec = S.Record(gm, J, Lmax=200, RmaxRec=64)
+    S.smc_run(gm, g1, seed=21, record=rec)
+    a = rec.summary()
+    g2 = S.Population(gm, J, N, max_chunk=32)
+    rec2 = S.Record(gm, J, Lmax=200, RmaxRec=64)
+    rec2.t_end[:] = rec.t_end
+    rec2.R[:] = rec.R
+    rec2.hchol.copy_(rec.hchol)
+    S.smc_run(gm, g2, seed=21, record=rec2, replay=True)
+    b = rec2.summary()
+    assert a["L"] == b["L"] > 2
+    assert np.array_equal(a["n_accept"], b["n_accept"])
+    assert np.array_equal(theta_np(g1), theta_np(g2))
+    assert np.allclose(a["group_logwbar"], b["group_logwbar"], rtol=1e-12, atol=1e-12)
+    assert torch.allclose(g1.loglik, g2.loglik, rtol=1e-12, atol=1e-10)
+    assert a["log_ml"] == pytest.approx(b["log_ml"], rel=1e-12)
