@@ -4,8 +4,8 @@
 // of models, so the model families compile in parallel; kernels.hip routes a
 // model description to its table.  Geometry: one particle per lane, 64-thread
 // blocks (one wave each), so a population spreads over as many compute units
-// as it has waves; observations are wave-uniform and reach the lanes through
-// scalar loads.
+// as it has waves; observations are wave-uniform (every lane of a wave loads
+// the same ones, eight at a time).
 #pragma once
 
 #include <hip/hip_ext.h>
