@@ -485,3 +485,41 @@ def test_replay_of_own_design_is_bitwise(name, prec):
     assert np.allclose(a["group_logwbar"], b["group_logwbar"], rtol=1e-12, atol=1e-12)
     assert torch.allclose(g1.loglik, g2.loglik, rtol=1e-12, atol=1e-10)
     assert a["log_ml"] == pytest.approx(b["log_ml"], rel=1e-12)
+
+
+def test_full_size_run_matches_stored_oracle_run():
+    """The headline workload at full size (EGARCH(1,1) Gaussian, J = 16 x
+    N = 1,024, T = 5,000, FP64), run as the benchmark times it (decisions on
+    the device, folded proposal scale, timed steps): the same cycle ends,
+    M-phase lengths and accepted-move counts of every Metropolis step as the
+    stored oracle run (tests/golden/write_oracle_runs.py), the log-ML to
+    1e-9; and the stored log likelihood and log prior of sampled final
+    particles match the oracle's evaluation of them."""
+    import json
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "oracle_run_egarch11_seed1.json")
+    gold = json.load(open(path))
+    w = SD.workload("egarch11")
+    assert (w.J, w.N, w.T) == (gold["J"], gold["N"], gold["T"])
+    gm, om = gpu_model(w), ora_model(w)
+    g = S.Population(gm, w.J, w.N, max_chunk=1024)
+    rec = S.Record(gm, w.J, Lmax=2048, RmaxRec=64, time_mutate=True)
+    S.smc_run(gm, g, seed=gold["seed"], check_every=1, record=rec)
+    s = rec.summary()
+    L = s["L"]
+    assert [int(x) for x in s["t_end"]] == gold["t_end"]
+    assert [int(x) for x in s["R"]] == gold["R"]
+    got_acc = [[int(x) for x in s["n_accept"][l][:s["R"][l]]] for l in range(L)]
+    assert got_acc == gold["n_accept"]
+    assert s["log_ml"] == pytest.approx(gold["log_ml"], rel=1e-9)
+    assert s["nse"] == pytest.approx(gold["nse"], rel=1e-6)
+    assert s["log_ml_tilde"] == pytest.approx(gold["log_ml_tilde"], rel=1e-9)
+    th = theta_np(g)
+    ll = g.loglik.cpu().numpy()
+    lp = g.logprior.cpu().numpy()
+    P = w.P
+    idx = np.concatenate([[0, 1, P - 1], np.random.default_rng(5).choice(P, 9, replace=False)])
+    for p in idx:
+        p = int(p)
+        assert ll[p] == pytest.approx(O.loglik(om, th[p], w.T)[0], rel=1e-10), p
+        assert lp[p] == pytest.approx(O.logprior(om, th[p]), rel=1e-12, abs=1e-12), p
