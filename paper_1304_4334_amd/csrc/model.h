@@ -16,6 +16,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <type_traits>
+
 #include "common.h"
 #include "rng.h"
 
@@ -53,7 +55,9 @@ __device__ constexpr double kExp2Coef[12] = {
 };
 __device__ __forceinline__ float exp2_fast(float x) { return __builtin_amdgcn_exp2f(x); }
 __device__ __forceinline__ float exp2_lean(float x) { return __builtin_amdgcn_exp2f(x); }
-__device__ __forceinline__ double exp2_fast(double x) {
+// 2^(x - n) with n = rint(x) returned through n_out, so that callers can fold
+// the exact scaling by 2^n into another operand off the dependency chain.
+__device__ __forceinline__ double exp2_frac(double x, int &n_out) {
   const double n = __builtin_rint(x);
   const double f = x - n;
   const double u = f * f;
@@ -66,7 +70,13 @@ __device__ __forceinline__ double exp2_fast(double x) {
   o = fma(o, u, kExp2Coef[3]);
   e = fma(e, u, kExp2Coef[0]);
   o = fma(o, u, kExp2Coef[1]);
-  return __builtin_ldexp(fma(o, f, e), (int)n);
+  n_out = (int)n;
+  return fma(o, f, e);
+}
+__device__ __forceinline__ double exp2_fast(double x) {
+  int n;
+  const double p = exp2_frac(x, n);
+  return __builtin_ldexp(p, n);
 }
 __device__ __forceinline__ double exp2_lean(double x) {
   const double n = __builtin_rint(x);
@@ -329,14 +339,31 @@ struct Egarch {
   __device__ __forceinline__ static R step(const Par &p, R y, Run &r, R &ae, R &pm, R &E_out,
                                            R &z_out) {
     const R sw = r.sw;
-    const R E = exp2_fast(sw);
+    // E = 2^sw.  For FP64 mixtures it is kept as Ef * 2^n: the exact scaling
+    // by 2^n goes into the other factor of each product (off the
+    // loop-carried chain, which then ends at the polynomial), giving the
+    // same products.  Measured on the likelihood kernel at t = T, this is 3%
+    // faster for egarch_23 and 3% slower for EGARCH(1,1), whose loop has
+    // less to overlap the two extra scalings with.
+    constexpr bool kSplit = std::is_same<R, double>::value && kMix;
+    R Ef;
+    int n = 0;
+    if constexpr (kSplit) {
+      Ef = exp2_frac(sw, n);
+    } else {
+      Ef = exp2_fast(sw);
+    }
+    const auto scaled = [&](R v) -> R {
+      if constexpr (kSplit) return __builtin_ldexp(v, n);
+      else return v;
+    };
     const R z = fma(y, p.isig, -p.mus);
     R kk = (R)0, AA = (R)0;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R A = fma(p.a[k], r.w[k], p.c0[k]);
       const R kz = fma(p.kb[k], fabs(z), p.kg[k] * z);
-      r.w[k] = fma(kz, E, A);
+      r.w[k] = fma(scaled(kz), Ef, A);
       if (K > 1) {
         kk += kz;
         AA += A;
@@ -345,8 +372,9 @@ struct Egarch {
         AA = A;
       }
     }
-    r.sw = (K > 1) ? fma(kk, E, AA) : r.w[0];
-    const R e = z * E;
+    r.sw = (K > 1) ? fma(scaled(kk), Ef, AA) : r.w[0];
+    const R e = scaled(z) * Ef;
+    const R E = scaled(Ef);
     if constexpr (kT) {
       ae += t_term(e * e, p.inu2);
     } else if constexpr (kMix) {
