@@ -588,23 +588,33 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
 }
 
 // For 32-wide matrices the partial matrices are first added entry by entry
-// across many blocks (64 entries per block, partials in block order), so the
-// final block reads one matrix.
-__global__ void __launch_bounds__(64) k_mom_sum(const double *part, int32_t nb, int32_t n,
-                                                double *out) {
-  const int e = blockIdx.x * 64 + threadIdx.x;
-  if (e >= n) return;
+// across many blocks, so the final block reads one matrix.  A block takes 64
+// entries; each of its four waves adds a quarter of the partials in block
+// order (its loads in flight together), and the four subtotals are added in
+// wave order.
+__global__ void __launch_bounds__(256) k_mom_sum(const double *part, int32_t nb, int32_t n,
+                                                 double *out) {
+  __shared__ double sub[4][64];
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int e = blockIdx.x * 64 + lane;
+  const int per = (nb + 3) / 4;
+  const int b_lo = min(nb, wv * per), b_hi = min(nb, b_lo + per);
   constexpr int kBatch = 32;
   double sum = 0.0;
-  for (int b0 = 0; b0 < nb; b0 += kBatch) {
-    double x[kBatch];
+  if (e < n) {
+    for (int b0 = b_lo; b0 < b_hi; b0 += kBatch) {
+      double x[kBatch];
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q) x[q] = (b0 + q < nb) ? part[(int64_t)(b0 + q) * n + e] : 0.0;
+      for (int q = 0; q < kBatch; ++q)
+        x[q] = (b0 + q < b_hi) ? part[(int64_t)(b0 + q) * n + e] : 0.0;
 #pragma unroll
-    for (int q = 0; q < kBatch; ++q)
-      if (b0 + q < nb) sum += x[q];
+      for (int q = 0; q < kBatch; ++q)
+        if (b0 + q < b_hi) sum += x[q];
+    }
   }
-  out[e] = sum;
+  sub[wv][lane] = sum;
+  __syncthreads();
+  if (wv == 0 && e < n) out[e] = ((sub[0][lane] + sub[1][lane]) + sub[2][lane]) + sub[3][lane];
 }
 
 // Pass 2 (one block of W * W threads, one entry each): add the partial
@@ -978,7 +988,7 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   } else {
     // sums into the slot after the partials, then the final block reads them
     double *sums = a.part + nb * 1024;
-    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(64), 0, s, a.part, (int32_t)nb, 1024, sums);
+    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums);
     if ((st = launch_status("particle_moments/sum"))) return st;
     MomArgs f = a;
     f.part = sums;
@@ -1005,7 +1015,7 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   if (st) return st;
   // summed into the slot after the partials, as launch_moments does
   double *sums = a.part + nb * 1024;
-  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(64), 0, s, a.part, (int32_t)nb, 1024, sums);
+  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums);
   *part = sums;
   nb = 1;
   return launch_status("particle_moments/sum");
