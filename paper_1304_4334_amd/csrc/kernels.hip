@@ -238,7 +238,9 @@ constexpr int kCumLdsMax = 2048;      // groups up to this size keep their sums 
 constexpr int kResampleMaxN = 16384;  // the counts alone fill 64 KB of LDS here
 constexpr int kGatherQ = 4;           // particles per thread per gather pass (global path)
 constexpr int kGatherRows = 12;       // rows per batch of gather loads (global path)
-constexpr int kGatherLdsBytes = 24576;  // LDS staging of source rows (groups <= kCumLdsMax)
+constexpr int kGatherLdsBytes = 98304;  // LDS staging of source rows (groups <= kCumLdsMax)
+constexpr int kStageRows = 4;          // rows of staging loads in flight together
+constexpr int kStageQ = kCumLdsMax / kBlock;  // particles per thread in an LDS-held group
 
 struct GatherArgs {
   const int32_t *anc;
@@ -262,6 +264,22 @@ __device__ __forceinline__ double gather_load(const GatherArgs &g, int r, int64_
                            : (double)typed<float>(g.state)[r * g.P + i];
   r -= g.S;
   return g.grad[r * g.P + i];
+}
+// Start of row r and whether it holds floats (an FP32 model's state).
+__device__ __forceinline__ const void *gather_row(const GatherArgs &g, int r, bool &f32) {
+  f32 = false;
+  if (r < g.d) return g.theta + r * g.P;
+  r -= g.d;
+  if (r == 0) return g.logprior;
+  if (r == 1) return g.loglik;
+  r -= 2;
+  if (r < g.S) {
+    f32 = g.st_bytes == 4;
+    return f32 ? static_cast<const void *>(typed<float>(g.state) + r * g.P)
+               : static_cast<const void *>(typed<double>(g.state) + r * g.P);
+  }
+  r -= g.S;
+  return g.grad + r * g.P;
 }
 __device__ __forceinline__ void gather_store(const GatherArgs &g, int r, int64_t i, double v) {
   if (r < g.d) { g.theta[r * g.P + i] = v; return; }
@@ -427,13 +445,35 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   }
   if (in_lds) {
     // Replace the group's particles by their ancestors through LDS: stage
-    // B source rows of the whole group (coalesced loads), then write every
+    // B source rows of the whole group (coalesced loads, kStageRows rows of
+    // every particle of the thread in flight together), then write every
     // particle's row values from its ancestor's slot.
     const int B = max(1, min(rows, kGatherLdsBytes / (8 * N)));
     for (int r0 = 0; r0 < rows; r0 += B) {
       const int nr = min(B, rows - r0);
-      for (int rr = 0; rr < nr; ++rr)  // rows outermost: the row choice stays uniform
-        for (int n = tid; n < N; n += kBlock) stage[rr * N + n] = gather_load(g, r0 + rr, base + n);
+      for (int rr0 = 0; rr0 < nr; rr0 += kStageRows) {
+        const void *rp[kStageRows];
+        bool f32[kStageRows];
+#pragma unroll
+        for (int u = 0; u < kStageRows; ++u) rp[u] = gather_row(g, r0 + min(rr0 + u, nr - 1), f32[u]);
+        double v[kStageRows][kStageQ];
+#pragma unroll
+        for (int u = 0; u < kStageRows; ++u)
+#pragma unroll
+          for (int q = 0; q < kStageQ; ++q) {
+            const int n = tid + q * kBlock;
+            const int64_t i = base + (n < N ? n : 0);
+            v[u][q] = f32[u] ? (double)static_cast<const float *>(rp[u])[i]
+                             : static_cast<const double *>(rp[u])[i];
+          }
+#pragma unroll
+        for (int u = 0; u < kStageRows; ++u)
+#pragma unroll
+          for (int q = 0; q < kStageQ; ++q) {
+            const int n = tid + q * kBlock;
+            if (rr0 + u < nr && n < N) stage[(rr0 + u) * N + n] = v[u][q];
+          }
+      }
       __syncthreads();
       for (int rr = 0; rr < nr; ++rr)
         for (int n = tid; n < N; n += kBlock)
