@@ -149,8 +149,11 @@ smc_status smc_init_from_prior(const smc_model *m, smc_particles *pop, smc_rng r
  * sum_n w_jn) (device [J], Section 4.2), *t_to (host) = the end date and,
  * when rss is not NULL, *rss (host) = the RSS there.
  * With rss_min <= 0 the phase runs to t_max; if in addition rss is NULL the
- * call does not synchronise (capturable).  Otherwise it synchronises the
- * stream once per evaluated chunk of observations. */
+ * call does not synchronise (capturable).  Otherwise it waits once per
+ * evaluated chunk of observations for that chunk's stopping decision, which
+ * a kernel takes on the device and stores in a page-locked slot of the
+ * calling host thread; the commit to the decided date is queued before the
+ * wait and may still be running when the call returns. */
 smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
                        int64_t check_every, double rss_min, double *group_logwbar,
                        int64_t *t_to, double *rss, void *stream);
@@ -315,8 +318,10 @@ typedef struct {
   int64_t evals;         /* out: particle x observation density evaluations */
   int64_t mh_steps;      /* out: Metropolis iterations */
   float *mutate_ms;      /* host [Lmax][RmaxRec] or NULL: when given, each
-                            smc_mutate launch is bracketed by HIP events on
-                            the run's stream and its duration stored here */
+                            mutation launch carries HIP start and stop events
+                            on its own dispatch (a Langevin step, several
+                            kernels, is bracketed by two event records) and
+                            its duration in ms is stored here */
   double *moments;       /* device [Lmax][G][4] or NULL: smc_test_moments of
                             cfg->test_fn at the end of every cycle */
   double *log_score;     /* device [3] or NULL: smc_log_score over cfg->burn_in */
@@ -325,8 +330,14 @@ typedef struct {
 } smc_run_record;
 
 /* Runs the simulator on `pop` (which must hold a workspace for
- * cfg->max_chunk).  Synchronises the stream once per C-phase chunk (and per
- * M iteration under the RNE rule). */
+ * cfg->max_chunk): Algorithm 2 with the Section 3.3 rules, or Algorithm 1
+ * on the recorded design when cfg->replay is set.  The host waits once per
+ * C-phase chunk for the chunk's stopping decision (taken on the device; the
+ * commit and, should the phase end there, the S phase are queued before the
+ * wait), once per M iteration under the RNE rule, and once after the last
+ * cycle (for its numerical flags); the log-ML is queued after that.  In an adaptive random-walk run each Metropolis step also
+ * computes its proposal scale (the step-size rule, V and h L, recorded in
+ * rec->hchol) from the moment partials itself. */
 smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                    smc_run_record *rec, void *stream);
 
