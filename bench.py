@@ -401,8 +401,9 @@ def main():
                     help="skip the EGARCH(2)-t and egarch_23 runs and the time-to-NSE comparison")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}); the simulator "
-              "shards by groups across GPUs only in design, see DESIGN.md", file=sys.stderr)
+        print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
+              "multi-GPU path (a run would shard by whole groups, one process per GPU)",
+              file=sys.stderr)
         sys.exit(2)
     if args.steps < 1:
         sys.exit("--steps must be >= 1")
