@@ -42,7 +42,7 @@ extern "C" {
 typedef int32_t smc_status;
 #define SMC_OK 0
 #define SMC_E_INVALID_ARG (-1) /* bad pointer, size, enum or shape */
-#define SMC_E_UNSUPPORTED (-2) /* valid request this build does not provide */
+#define SMC_E_UNSUPPORTED (-2) /* valid request the library does not provide */
 #define SMC_E_DEVICE (-3)      /* a HIP call failed */
 #define SMC_E_NUMERIC (-4)     /* a group lost all weight, or V is not PD */
 #define SMC_E_WORKSPACE (-5)   /* workspace smaller than smc_workspace_bytes */
