@@ -15,9 +15,10 @@ constexpr int chol_ld() { return W + 1; }
 // V = L L' by one wave (call from lanes 0..63 of a wave, d < W).  V is Ms
 // (W x W row-major, LDS); L is built in Ls (W rows of stride chol_ld<W>(),
 // LDS): lane r writes row r only, and row `col` is read by every lane as a
-// broadcast once lane col has written it in earlier columns.  LDS operations of one wave complete in
-// order, so the factorisation needs no block barrier; the operations and
-// their order are those of a column-by-column factorisation.  Writes h L
+// broadcast once lane col has written it in earlier columns.  LDS operations
+// of one wave complete in order, so the factorisation needs no block
+// barrier; the operations and their order are those of a column-by-column
+// factorisation.  Writes h L
 // (d x d row-major) to hchol (if not NULL); a V that is not positive definite
 // gives hchol = 0 and raises SMC_FLAG_NOT_PD in flags (if not NULL).  Returns
 // whether V was positive definite (the same in every lane).

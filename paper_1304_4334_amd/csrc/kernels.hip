@@ -455,7 +455,8 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
         const void *rp[kStageRows];
         bool f32[kStageRows];
 #pragma unroll
-        for (int u = 0; u < kStageRows; ++u) rp[u] = gather_row(g, r0 + min(rr0 + u, nr - 1), f32[u]);
+        for (int u = 0; u < kStageRows; ++u)
+          rp[u] = gather_row(g, r0 + min(rr0 + u, nr - 1), f32[u]);
         double v[kStageRows][kStageQ];
 #pragma unroll
         for (int u = 0; u < kStageRows; ++u)
@@ -1013,7 +1014,8 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < %d", kDMax);
   int64_t chunk = 0, nb = 0;
   moment_partition(a.P, a.d, chunk, nb);
-  if (nb > kMomBlocks) return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
+  if (nb > kMomBlocks)
+    return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
   if (a.d + 1 <= 16) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
                        a.d, chunk, a.part);
@@ -1042,7 +1044,8 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   if (a.d + 1 > kDMax) return set_error(SMC_E_UNSUPPORTED, "moments need d < %d", kDMax);
   int64_t chunk = 0;
   moment_partition(a.P, a.d, chunk, nb);
-  if (nb > kMomBlocks) return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
+  if (nb > kMomBlocks)
+    return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
   *part = a.part;
   if (a.d + 1 <= 16) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
