@@ -84,7 +84,8 @@ TRAFFIC_KEYS = {("egarch11", "fp64"): "k_mutate_rw egarch11 fp64 P=16384 t=5000 
 TRAFFIC_SOURCES = ["paper_1304_4334_amd/csrc/model_kernels.h", "paper_1304_4334_amd/csrc/model.h",
                    "paper_1304_4334_amd/csrc/rng.h", "paper_1304_4334_amd/csrc/common.h",
                    "paper_1304_4334_amd/csrc/ops_egarch.hip",
-                   "paper_1304_4334_amd/csrc/ops_mixture32.hip"]
+                   "paper_1304_4334_amd/csrc/ops_mixture32.hip",
+                   "paper_1304_4334_amd/csrc/chol.h", "paper_1304_4334_amd/csrc/launch.h"]
 
 
 def measured_traffic(name, precision):
