@@ -62,8 +62,11 @@ __global__ void __launch_bounds__(64) k_init(DevModel dm, int64_t P, uint64_t se
 // ------------------------------------------------------------ C phase (a2) --
 // Speculative pass: from the committed state at t0, evaluate observations
 // t0+1..t1 and record the running log weight at every check date, without
-// committing anything.
-template <class M>
+// committing anything.  Column c of W holds the c-th check date's weights;
+// the wave-uniform column pointer moves by P per recorded date, and the
+// dates are counted relative to t0 in 32 bits (a chunk holds at most
+// kMaxChunk dates).  kEvery1: every date is checked (check_every = 1).
+template <class M, bool kEvery1>
 __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
                                               const void *state, const double *logw, int64_t t0,
                                               int64_t t1, int64_t check_every, int64_t t_max,
@@ -80,18 +83,35 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
 #pragma unroll
   for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
   double lw = zero_first ? 0.0 : logw[p];
-  int64_t col = 0;
-  int64_t next_check = (t0 / check_every + 1) * check_every;  // first multiple after t0
-  Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t s, double lp) {
-    if (isnan(lp)) lp = -INFINITY;
-    lw += lp;
-    const bool at_check = s == next_check;
-    if (at_check || s == t_max) {
-      W[col * P + p] = lw;
-      ++col;
-    }
-    if (at_check) next_check += check_every;
-  });
+  double *colp = W;  // the next column to record
+  if constexpr (kEvery1) {
+    Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t, double lp) {
+      if (isnan(lp)) lp = -INFINITY;
+      lw += lp;
+      colp[p] = lw;
+      colp += P;
+    });
+  } else {
+    // dates relative to t0: the next multiple of check_every, and t_max
+    // (both capped beyond the chunk, where they are never reached)
+    const int64_t span = t1 - t0 + 1;
+    const int64_t first = (t0 / check_every + 1) * check_every - t0;
+    int32_t next_rel = (int32_t)(first < span ? first : span);
+    const int32_t max_rel = (int32_t)(t_max - t0 < span ? t_max - t0 : span);
+    const int32_t every = (int32_t)(check_every < span ? check_every : span);
+    int32_t rel = 0;
+    Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t, double lp) {
+      if (isnan(lp)) lp = -INFINITY;
+      lw += lp;
+      ++rel;
+      const bool at_check = rel == next_rel;
+      if (at_check || rel == max_rel) {
+        colp[p] = lw;
+        colp += P;
+      }
+      if (at_check) next_rel += every;
+    });
+  }
 }
 
 // Commit: advance from t0 to t1 (or to *t1_dev when given), adding the log
@@ -565,8 +585,12 @@ struct OpsOf {
   static smc_status cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                           const double *logw, int64_t t0, int64_t t1, int64_t check_every,
                           int64_t t_max, bool zero_first, double *W, hipStream_t s) {
-    hipLaunchKernelGGL(k_cscan<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw, t0,
-                       t1, check_every, t_max, (int32_t)zero_first, W);
+    if (check_every == 1)
+      hipLaunchKernelGGL((k_cscan<M, true>), grid_for(P, 64), dim3(64), 0, s, m, P, theta, state,
+                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W);
+    else
+      hipLaunchKernelGGL((k_cscan<M, false>), grid_for(P, 64), dim3(64), 0, s, m, P, theta, state,
+                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W);
     return launch_status("correct/scan");
   }
 
