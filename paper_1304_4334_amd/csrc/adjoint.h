@@ -153,15 +153,19 @@ struct Adjoint<Egarch<K, SH, R, I>> {
     for (int64_t sg = 0; sg < ns; ++sg) {
 #pragma unroll
       for (int k = 0; k < K; ++k) ckpt[(sg * K + k) * P + pidx] = r.w[k];
-      const int64_t s0 = sg * SEG, s1 = min(t, s0 + SEG);
+      // 32-bit counters and a segment pointer keep the loop's bookkeeping
+      // off the scalar unit
+      const int64_t s0 = sg * SEG;
+      const int len = (int)(min(t, s0 + SEG) - s0);
+      const Y *__restrict__ ys = y + s0;
       R av = (R)0, ae = (R)0, pm = (R)1;
-      for (int64_t s = s0; s < s1; ++s) {
+      for (int j = 0; j < len; ++j) {
 #pragma unroll
         for (int k = 0; k < K; ++k) wl[k] = r.w[k];
-        av += Md::step(p, y[s], r, ae, pm, lastE, lastz);
+        av += Md::step(p, ys[j], r, ae, pm, lastE, lastz);
         if constexpr (kMix) {
           // the mixture sums' product, folded into log2 every 8 observations
-          if (((s - s0) & 7) == 7) {
+          if ((j & 7) == 7) {
             se += (double)log2_fast(pm);
             pm = (R)1;
           }
@@ -195,8 +199,9 @@ struct Adjoint<Egarch<K, SH, R, I>> {
     for (int i = 0; i < kNM; ++i) lwb[i] = nbb[i] = mub[i] = 0.0;
     const R ln2 = (R)kLn2;
     for (int64_t sg = ns - 1; sg >= 0; --sg) {
-      const int64_t s0 = sg * SEG, s1 = min(t, s0 + SEG);
-      const int len = (int)(s1 - s0);
+      const int64_t s0 = sg * SEG;
+      const int len = (int)(min(t, s0 + SEG) - s0);
+      const Y *__restrict__ ys = y + s0;
       // recompute the segment, keeping each observation's exponents
 #pragma unroll
       for (int k = 0; k < K; ++k) r.w[k] = ckpt[(sg * K + k) * P + pidx];
@@ -208,7 +213,7 @@ struct Adjoint<Egarch<K, SH, R, I>> {
 #pragma unroll
         for (int k = 0; k < K; ++k) lds[(j * K + k) * 64] = r.w[k];
         R ae = (R)0, pm = (R)1, Ed, zd;
-        (void)Md::step(p, y[s0 + j], r, ae, pm, Ed, zd);
+        (void)Md::step(p, ys[j], r, ae, pm, Ed, zd);
       }
       R a_ab[K], a_c0b[K], a_kbb[K], a_kgb[K];
 #pragma unroll
@@ -218,7 +223,7 @@ struct Adjoint<Egarch<K, SH, R, I>> {
 #pragma unroll
       for (int i = 0; i < kNM; ++i) a_lwb[i] = a_nbb[i] = a_mub[i] = (R)0;
       for (int j = len - 1; j >= 0; --j) {
-        const R yv = y[s0 + j];
+        const R yv = ys[j];
         R w[K];
         R sw = (R)0;
 #pragma unroll
