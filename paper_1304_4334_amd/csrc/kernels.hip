@@ -64,6 +64,23 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
   return launch_status("fill_i32");
 }
 
+// e^x for x <= 0 or -inf (weights relative to their maximum; -inf gives 0): x =
+// n ln 2 + r with n = rint(x log2 e) and r reduced against ln 2 split in two
+// doubles (|r| <= ln2/2, the first fma exact to one rounding of r), then
+// 2^(r log2 e) by the minimax polynomial of kExp2Coef and the scaling by 2^n.
+// About 20 operations against the library's 45; error within 2 ulp.
+constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
+__device__ __forceinline__ double exp_nonpos(double x) {
+  const double xc = fmax(x, -1100.0);  // keeps -inf out of the reduction
+  const double n = __builtin_rint(xc * kLog2e);
+  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, xc));
+  const double f = r * kLog2e;
+  double p = fma(kExp2Coef[11], f, kExp2Coef[10]);
+#pragma unroll
+  for (int k = 9; k >= 0; --k) p = fma(p, f, kExp2Coef[k]);
+  return x < -1100.0 ? 0.0 : __builtin_ldexp(p, (int)n);
+}
+
 constexpr int kRssBlock = 1024;
 constexpr int kRssRegs = 16;  // values per thread held in registers: P <= 16,384 per column
 
@@ -80,13 +97,32 @@ __device__ __forceinline__ double rss_block_reduce(double v, double *lds /* >= 1
   for (int i = 1; i < kRssBlock / 64; ++i) r = Op::apply(r, lds[i]);
   return r;
 }
+// Two sums at once (one pair of barriers), each in the order above.
+__device__ __forceinline__ void rss_block_sum2(double &a, double &b, double *lds /* >= 32 */) {
+  a = wave_reduce<OpSum<double>>(a);
+  b = wave_reduce<OpSum<double>>(b);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) {
+    lds[threadIdx.x >> 6] = a;
+    lds[kRssBlock / 64 + (threadIdx.x >> 6)] = b;
+  }
+  __syncthreads();
+  double ra = lds[0], rb = lds[kRssBlock / 64];
+#pragma unroll
+  for (int i = 1; i < kRssBlock / 64; ++i) {
+    ra += lds[i];
+    rb += lds[kRssBlock / 64 + i];
+  }
+  a = ra;
+  b = rb;
+}
 
 // RSS of one column of running log weights (Section 3.3):
 // (sum e)^2 / (P sum e^2) with e = exp(logw - max).  Columns of up to
 // kRssRegs * kRssBlock values: the maximum first, then the sums, the values
 // held in registers between the two passes.
 __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss) {
-  __shared__ double sh[kRssBlock / 64];
+  __shared__ double sh[2 * (kRssBlock / 64)];
   const double *w = W + blockIdx.x * P;
   double v[kRssRegs];
   double mx = -INFINITY;
@@ -102,13 +138,12 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
   if (mx > -INFINITY) {
 #pragma unroll
     for (int u = 0; u < kRssRegs; ++u) {
-      const double e = exp(v[u] - mx);
+      const double e = exp_nonpos(v[u] - mx);
       s1 += e;
       s2 = fma(e, e, s2);
     }
   }
-  s1 = rss_block_reduce<OpSum<double>>(s1, sh);
-  s2 = rss_block_reduce<OpSum<double>>(s2, sh);
+  rss_block_sum2(s1, s2, sh);
   if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
 }
 
@@ -121,7 +156,7 @@ struct Lse3 {
 __device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
   const double m = fmax(a.m, b.m);
   if (!(m > -INFINITY)) return Lse3{m, 0.0, 0.0};
-  const double ea = exp(a.m - m), eb = exp(b.m - m);
+  const double ea = exp_nonpos(a.m - m), eb = exp_nonpos(b.m - m);
   return Lse3{m, a.s1 * ea + b.s1 * eb, a.s2 * ea * ea + b.s2 * eb * eb};
 }
 __device__ __forceinline__ Lse3 lse3_shfl_xor(const Lse3 &a, int off) {
@@ -147,7 +182,7 @@ __global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t
     if (m > -INFINITY) {
 #pragma unroll
       for (int u = 0; u < kChunk; ++u) {
-        const double e = exp(v[u] - m);
+        const double e = exp_nonpos(v[u] - m);
         c.s1 += e;
         c.s2 = fma(e, e, c.s2);
       }
@@ -210,37 +245,101 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
   }
 }
 
-// log wbar_j = log(N^-1 sum_n exp(logw_jn)) per group (Section 4.2).
-__global__ void __launch_bounds__(256) k_group_logwbar(const double *logw, int32_t N,
-                                                       double *out) {
-  __shared__ double sh[4];
-  const double *w = logw + (int64_t)blockIdx.x * N;
-  double mx = -INFINITY;
-  for (int n = threadIdx.x; n < N; n += kBlock) mx = fmax(mx, w[n]);
-  mx = block_reduce<OpMax<double>>(mx, sh);
-  double s = 0.0;
-  if (mx > -INFINITY)
-    for (int n = threadIdx.x; n < N; n += kBlock) s += exp(w[n] - mx);
-  s = block_reduce<OpSum<double>>(s, sh);
-  if (threadIdx.x == 0) out[blockIdx.x] = (mx > -INFINITY) ? mx + log(s / (double)N) : -INFINITY;
-}
-
 // ------------------------------------------------------------ S phase (a3) --
-// One block per group.  The group's weights, then their running residual
-// sums, live in LDS when they fit (kCumLdsMax), else in the workspace; the
-// copy counts in LDS.  Residual: floor(N W_n) copies, then the remaining
-// draws from the residuals; multinomial: N draws from W_n; stratified /
-// systematic (Section 3.3's experimental schemes): the k-th of N draws at
-// (k + U_k)/N, respectively (k + U)/N, of the running sum.  Each phase keeps
-// its global accesses in flight together, since a block of one group is
-// latency-bound.
+// One block of kSBlock threads (16 waves) per group.  The group's weights,
+// then their running residual sums, live in LDS when they fit (kCumLdsMax),
+// else in the workspace; the copy counts, then the ancestors' first output
+// slots, in LDS.  Residual: floor(N W_n) copies, then the remaining draws
+// from the residuals; multinomial: N draws from W_n; stratified / systematic
+// (Section 3.3's experimental schemes): the k-th of N draws at (k + U_k)/N,
+// respectively (k + U)/N, of the running sum.  A group's block is
+// latency-bound, so the scans work within waves and every search runs a
+// fixed number of steps, four of them interleaved per thread.
+constexpr int kSBlock = 1024;         // threads per group
+constexpr int kSWaves = kSBlock / 64;
 constexpr int kCumLdsMax = 2048;      // groups up to this size keep their sums in LDS
 constexpr int kResampleMaxN = 16384;  // the counts alone fill 64 KB of LDS here
-constexpr int kGatherQ = 4;           // particles per thread per gather pass (global path)
-constexpr int kGatherRows = 12;       // rows per batch of gather loads (global path)
+constexpr int kGatherQ = 2;           // particles per thread per gather pass (global path)
+constexpr int kGatherRows = 6;        // rows per batch of gather loads (global path)
 constexpr int kGatherLdsBytes = 98304;  // LDS staging of source rows (groups <= kCumLdsMax)
-constexpr int kStageRows = 4;          // rows of staging loads in flight together
-constexpr int kStageQ = kCumLdsMax / kBlock;  // particles per thread in an LDS-held group
+constexpr int kStageRows = 8;          // rows of staging loads in flight together
+constexpr int kStageQ = kCumLdsMax / kSBlock;  // particles per thread in an LDS-held group
+
+// Reduction over the group's block: a butterfly within each wave, then the
+// wave values combined in one fixed pairwise tree, the same in every thread.
+template <class Op, typename T>
+__device__ __forceinline__ T sblock_reduce(T v, T *lds /* >= kSWaves */) {
+  v = wave_reduce<Op>(v);
+  __syncthreads();
+  if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
+  __syncthreads();
+  T x[kSWaves];
+#pragma unroll
+  for (int i = 0; i < kSWaves; ++i) x[i] = lds[i];
+#pragma unroll
+  for (int s = 1; s < kSWaves; s <<= 1)
+#pragma unroll
+    for (int i = 0; i < kSWaves; i += 2 * s) x[i] = Op::apply(x[i], x[i + s]);
+  return x[0];
+}
+
+// Exclusive scan over the group's block (DPP scans within the waves, then the
+// totals of the preceding waves); `total` receives the block sum.
+template <typename T>
+__device__ __forceinline__ T sblock_exclusive_scan(T v, T *lds /* >= kSWaves */, T &total) {
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const T inc = wave_inclusive_scan(v);
+  const T up = __shfl_up(inc, 1, 64);
+  const T ex = lane ? up : T(0);  // the wave's exclusive prefix
+  __syncthreads();
+  if (lane == 63) lds[w] = inc;
+  __syncthreads();
+  T pre = T(0), tot = T(0);
+#pragma unroll
+  for (int i = 0; i < kSWaves; ++i) {
+    const T x = lds[i];
+    if (i < w) pre += x;
+    tot += x;
+  }
+  total = tot;
+  return pre + ex;
+}
+
+// Largest power of two not above n (n >= 1): the first step of the searches.
+__device__ __forceinline__ int top_step(int n) { return 1 << (31 - __clz(n)); }
+
+// Group maximum of logw and sum of exp(logw - max), in one order that the
+// S-phase kernel and k_group_logwbar share (so both give the same bits).
+// `keep`, when given, receives the log weights, then their exponentials.
+__device__ __forceinline__ void group_max_sum(const double *lw, int32_t N, double *keep,
+                                              double *sh, double &mx, double &se) {
+  const int tid = threadIdx.x;
+  double m = -INFINITY;
+  for (int n = tid; n < N; n += kSBlock) {
+    const double v = lw[n];
+    if (keep) keep[n] = v;
+    m = fmax(m, v);
+  }
+  m = sblock_reduce<OpMax<double>>(m, sh);
+  double s = 0.0;
+  if (m > -INFINITY)
+    for (int n = tid; n < N; n += kSBlock) {
+      const double e = exp_nonpos((keep ? keep[n] : lw[n]) - m);
+      if (keep) keep[n] = e;
+      s += e;
+    }
+  se = sblock_reduce<OpSum<double>>(s, sh);  // its barriers publish `keep`
+  mx = m;
+}
+
+// log wbar_j = log(N^-1 sum_n exp(logw_jn)) per group (Section 4.2).
+__global__ void __launch_bounds__(kSBlock) k_group_logwbar(const double *logw, int32_t N,
+                                                           double *out) {
+  __shared__ double sh[kSWaves];
+  double mx, s;
+  group_max_sum(logw + (int64_t)blockIdx.x * N, N, nullptr, sh, mx, s);
+  if (threadIdx.x == 0) out[blockIdx.x] = (mx > -INFINITY) ? mx + log(s / (double)N) : -INFINITY;
+}
 
 struct GatherArgs {
   const int32_t *anc;
@@ -296,128 +395,106 @@ __device__ __forceinline__ void gather_store(const GatherArgs &g, int r, int64_t
   g.grad[r * g.P + i] = v;
 }
 
-// In-place gather held in registers: every thread loads all rows of its
-// PER particles' ancestors, the block synchronises, then every thread stores
-// them at its own positions (rows <= kRegRows).
+// In-place gather held in registers (N <= kSBlock, rows <= kRegRows): every
+// thread loads all rows of its particle's ancestor, the block synchronises,
+// then every thread stores them at its own position.
 constexpr int kRegRows = 16;
-template <int PER>
 __device__ __forceinline__ void gather_in_registers(const GatherArgs &g, int64_t base, int32_t N,
                                                     int rows, const int32_t *anc_l) {
-  double v[PER][kRegRows];
-  const int tid = threadIdx.x;
+  double v[kRegRows];
+  const int n = threadIdx.x;
+  const int64_t a = base + (n < N ? anc_l[n] : 0);
 #pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int n = tid + q * kBlock;
-    const int64_t a = base + (n < N ? anc_l[n] : 0);
+  for (int r = 0; r < kRegRows; ++r)
+    if (r < rows) v[r] = gather_load(g, r, a);
+  __syncthreads();
+  if (n < N)
 #pragma unroll
     for (int r = 0; r < kRegRows; ++r)
-      if (r < rows) v[q][r] = gather_load(g, r, a);
-  }
-  __syncthreads();
-#pragma unroll
-  for (int q = 0; q < PER; ++q) {
-    const int n = tid + q * kBlock;
-    if (n < N)
-#pragma unroll
-      for (int r = 0; r < kRegRows; ++r)
-        if (r < rows) gather_store(g, r, base + n, v[q][r]);
-  }
+      if (r < rows) gather_store(g, r, base + n, v[r]);
 }
 
-__global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N, int32_t scheme,
-                                                  uint64_t seed, uint64_t run, uint64_t cycle,
-                                                  int32_t *anc, double *cum_ws, int32_t *flags,
-                                                  GatherArgs g, const int32_t *go,
-                                                  double *group_logwbar) {
-  if (go && *go == 0) return;  // enqueued ahead of a C phase that did not end
-  extern __shared__ double lds_dyn[];
-  __shared__ double shd[kBlock];
-  __shared__ int64_t shi[kBlock];
-  const int j = blockIdx.x;
-  const int64_t base = (int64_t)j * N;
-  const double *lw = logw + base;
-  // LDS layout for groups up to kCumLdsMax: [N] doubles (weights, then the
-  // running sums), [kGatherLdsBytes] of row staging, [N] int32 counts, [N]
-  // int32 ancestors; larger groups keep the sums in the workspace and only
-  // the counts in LDS.
-  const bool in_lds = N <= kCumLdsMax;
-  double *ev = in_lds ? lds_dyn : cum_ws + base;  // e_n, then the running sums
-  double *stage = lds_dyn + N;
-  int32_t *cnt = reinterpret_cast<int32_t *>(in_lds ? stage + kGatherLdsBytes / 8 : lds_dyn);
-  int32_t *anc_l = cnt + N;  // group-local ancestors (LDS path only)
+// Copy counts and ancestors of group j.  Its weights, then their running
+// sums, go to ev (LDS, or the workspace for large groups), the counts, then
+// every n's first output slot, to cnt (LDS), and the group-local ancestors
+// also to anc_l when given.  Returns false for a dead group (no positive
+// weight), whose ancestors are the identity.
+__device__ __forceinline__ bool select_ancestors(const double *lw, int32_t N, int32_t scheme,
+                                                 uint64_t seed, uint64_t run, uint64_t cycle,
+                                                 int j, int64_t base, int32_t *anc,
+                                                 int32_t *flags, double *group_logwbar,
+                                                 double *ev, int32_t *cnt, int32_t *anc_l,
+                                                 double *shd, int32_t *shi) {
   const int tid = threadIdx.x;
-
-  double mx = -INFINITY;
-  for (int n = tid; n < N; n += kBlock) {
-    const double v = lw[n];
-    ev[n] = v;
-    mx = fmax(mx, v);
-  }
-  mx = block_reduce<OpMax<double>>(mx, shd);
+  double mx, se;
+  group_max_sum(lw, N, ev, shd, mx, se);
   if (!(mx > -INFINITY)) {
-    for (int n = tid; n < N; n += kBlock) anc[base + n] = (int32_t)(base + n);
+    for (int n = tid; n < N; n += kSBlock) anc[base + n] = (int32_t)(base + n);
     if (tid == 0) {
       atomicOr(flags, SMC_FLAG_DEAD_GROUP);
       if (group_logwbar) group_logwbar[j] = -INFINITY;
     }
-    return;
+    return false;
   }
-  double se = 0.0;
-  for (int n = tid; n < N; n += kBlock) {
-    const double e = exp(ev[n] - mx);
-    ev[n] = e;
-    se += e;
-  }
-  se = block_reduce<OpSum<double>>(se, shd);  // its barriers publish ev
-  // log wbar_j from the same maximum and sum, in the order k_group_logwbar
-  // takes them (so the value is the same to the bit)
+  // log wbar_j from the same maximum and sum as k_group_logwbar
   if (group_logwbar && tid == 0) group_logwbar[j] = mx + log(se / (double)N);
 
-  // Thread-contiguous chunks for the scans.
-  const int m = (N + kBlock - 1) / kBlock;
+  // Thread-contiguous chunks: copy counts and running residual sums.
+  const int m = (N + kSBlock - 1) / kSBlock;
   const int lo = min(tid * m, N), hi = min(lo + m, N);
   double rsum = 0.0;
-  int64_t csum = 0;
+  int32_t csum = 0;
   for (int n = lo; n < hi; ++n) {
     const double nw = ((double)N * ev[n]) / se;  // N W_n
     const double c = (scheme == SMC_RESAMPLE_RESIDUAL) ? floor(nw) : 0.0;
     rsum += nw - c;
     ev[n] = rsum;
     cnt[n] = (int32_t)c;
-    csum += (int64_t)c;
+    csum += (int32_t)c;
   }
   double rtot;
-  const double roff = block_inclusive_scan<double>(rsum, shd, rtot) - rsum;
+  const double roff = sblock_exclusive_scan<double>(rsum, shd, rtot);
   for (int n = lo; n < hi; ++n) ev[n] += roff;
-  int64_t ctot;
-  (void)block_inclusive_scan<int64_t>(csum, shi, ctot);
+  int32_t ctot;
+  (void)sblock_exclusive_scan<int32_t>(csum, shi, ctot);
   __syncthreads();
   const double *cum = ev;
   const double total = cum[N - 1];
-  const int64_t R = (int64_t)N - ctot;
-  // Draws k = 4q..4q+3 share the Philox block q.
+  const int R = N - ctot;
+  const int top = top_step(N);
+  // Draws k = 4q..4q+3 share the Philox block q; each draw's ancestor is the
+  // first n with cum[n] > u * total, found in top_step(N) halvings with the
+  // four draws' loads issued together.
   const double u_sys = scheme == SMC_RESAMPLE_SYSTEMATIC
                            ? u01_co(draw4(seed, run, (uint64_t)j, cycle, 0, kResample).x0)
                            : 0.0;
-  for (int64_t k0 = 4 * (int64_t)tid; k0 < R; k0 += 4 * kBlock) {
-    const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)(k0 >> 2), kResample);
+  for (int q = tid; 4 * q < R; q += kSBlock) {
+    const U64x4 w = draw4(seed, run, (uint64_t)j, cycle, (uint64_t)q, kResample);
     const uint64_t xs[4] = {w.x0, w.x1, w.x2, w.x3};
+    double tg[4];
+    int pos[4];
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int64_t k = k0 + q;
-      if (k >= R) break;
-      double u = u01_co(xs[q]);
+    for (int i = 0; i < 4; ++i) {
+      const int k = 4 * q + i;
+      double u = u01_co(xs[i]);
       if (scheme == SMC_RESAMPLE_STRATIFIED) u = ((double)k + u) / (double)N;
       else if (scheme == SMC_RESAMPLE_SYSTEMATIC) u = ((double)k + u_sys) / (double)N;
-      const double target = u * total;
-      int a_lo = 0, a_hi = N;  // first n with cum[n] > target
-      while (a_lo < a_hi) {
-        const int mid = (a_lo + a_hi) >> 1;
-        if (cum[mid] > target) a_hi = mid;
-        else a_lo = mid + 1;
-      }
-      int a = a_lo;
-      if (a >= N) {
+      tg[i] = u * total;
+      pos[i] = 0;
+    }
+    for (int step = top; step > 0; step >>= 1) {
+      double c[4];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) c[i] = cum[min(pos[i] + step, N) - 1];
+#pragma unroll
+      for (int i = 0; i < 4; ++i)
+        if (pos[i] + step <= N && !(c[i] > tg[i])) pos[i] += step;
+    }
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      if (4 * q + i >= R) break;
+      int a = pos[i];
+      if (a >= N) {  // u * total rounded up to the last sum: the last positive residual
         a = N - 1;
         while (a > 0 && !(cum[a] > cum[a - 1])) --a;
       }
@@ -425,22 +502,68 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
     }
   }
   __syncthreads();
-  int64_t my = 0;
+  // Copy counts -> first output slot of every n (in place); the ancestor of
+  // slot s is the last n whose first slot is <= s.
+  int32_t my = 0;
   for (int n = lo; n < hi; ++n) my += cnt[n];
-  int64_t tot2;
-  int64_t pos = block_inclusive_scan<int64_t>(my, shi, tot2) - my;
-  for (int n = lo; n < hi; ++n)
-    for (int c = 0; c < cnt[n] && pos < N; ++c) {
-      if (in_lds) anc_l[pos] = n;
-      anc[base + pos++] = (int32_t)(base + n);
-    }
+  int32_t tot2;
+  int32_t at = sblock_exclusive_scan<int32_t>(my, shi, tot2);
+  for (int n = lo; n < hi; ++n) {
+    const int32_t c = cnt[n];
+    cnt[n] = at;
+    at += c;
+  }
   __syncthreads();
+  for (int s = tid; s < N; s += kSBlock) {
+    int a = 0;
+    for (int step = top; step > 0; step >>= 1) {
+      const int nx = a + step;
+      const int32_t first = cnt[min(nx, N) - 1];
+      if (nx <= N && first <= s) a = nx;
+    }
+    --a;
+    if (anc_l) anc_l[s] = a;
+    anc[base + s] = (int32_t)(base + a);
+  }
+  __syncthreads();
+  return true;
+}
+
+__global__ void __launch_bounds__(kSBlock) k_resample(const double *logw, int32_t N,
+                                                      int32_t scheme, uint64_t seed, uint64_t run,
+                                                      uint64_t cycle, int32_t *anc,
+                                                      double *cum_ws, int32_t *flags,
+                                                      GatherArgs g, const int32_t *go,
+                                                      double *group_logwbar) {
+  if (go && *go == 0) return;  // enqueued ahead of a C phase that did not end
+  extern __shared__ double lds_dyn[];
+  __shared__ double shd[kSWaves];
+  __shared__ int32_t shi[kSWaves];
+  const int j = blockIdx.x;
+  const int64_t base = (int64_t)j * N;
+  // LDS layout for groups up to kCumLdsMax: [N] doubles (weights, then the
+  // running sums), [kGatherLdsBytes] of row staging, [N] int32 counts, [N]
+  // int32 ancestors; larger groups keep the sums in the workspace and only
+  // the counts in LDS.  The two cases are separate calls, so that every LDS
+  // access compiles to an LDS instruction.
+  const bool in_lds = N <= kCumLdsMax;
+  double *stage = lds_dyn + N;
+  int32_t *anc_l = reinterpret_cast<int32_t *>(stage + kGatherLdsBytes / 8) + N;
+  if (in_lds) {
+    if (!select_ancestors(logw + base, N, scheme, seed, run, cycle, j, base, anc, flags,
+                          group_logwbar, lds_dyn, anc_l - N, anc_l, shd, shi))
+      return;
+  } else {
+    if (!select_ancestors(logw + base, N, scheme, seed, run, cycle, j, base, anc, flags,
+                          group_logwbar, cum_ws + base, reinterpret_cast<int32_t *>(lds_dyn),
+                          nullptr, shd, shi))
+      return;
+  }
+  const int tid = threadIdx.x;
   const int64_t P = g.P;
   const int rows = g.d + 2 + g.S + (g.has_grad ? g.d : 0);
-  if (in_lds && rows <= kRegRows && N <= 4 * kBlock) {
-    if (N <= kBlock) gather_in_registers<1>(g, base, N, rows, anc_l);
-    else if (N <= 2 * kBlock) gather_in_registers<2>(g, base, N, rows, anc_l);
-    else gather_in_registers<4>(g, base, N, rows, anc_l);
+  if (in_lds && rows <= kRegRows && N <= kSBlock) {
+    gather_in_registers(g, base, N, rows, anc_l);
     return;
   }
   if (in_lds) {
@@ -462,7 +585,7 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
         for (int u = 0; u < kStageRows; ++u)
 #pragma unroll
           for (int q = 0; q < kStageQ; ++q) {
-            const int n = tid + q * kBlock;
+            const int n = tid + q * kSBlock;
             const int64_t i = base + (n < N ? n : 0);
             v[u][q] = f32[u] ? (double)static_cast<const float *>(rp[u])[i]
                              : static_cast<const double *>(rp[u])[i];
@@ -471,13 +594,13 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
         for (int u = 0; u < kStageRows; ++u)
 #pragma unroll
           for (int q = 0; q < kStageQ; ++q) {
-            const int n = tid + q * kBlock;
+            const int n = tid + q * kSBlock;
             if (rr0 + u < nr && n < N) stage[(rr0 + u) * N + n] = v[u][q];
           }
       }
       __syncthreads();
       for (int rr = 0; rr < nr; ++rr)
-        for (int n = tid; n < N; n += kBlock)
+        for (int n = tid; n < N; n += kSBlock)
           gather_store(g, r0 + rr, base + n, stage[rr * N + anc_l[n]]);
       __syncthreads();
     }
@@ -485,12 +608,12 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
   }
   // Larger groups: copy the ancestors' values to the workspace, then back,
   // with kGatherQ particles x kGatherRows rows of loads in flight per batch.
-  for (int n0 = 0; n0 < N; n0 += kBlock * kGatherQ) {
+  for (int n0 = 0; n0 < N; n0 += kSBlock * kGatherQ) {
     int64_t pp[kGatherQ], aa[kGatherQ];
     bool ok[kGatherQ];
 #pragma unroll
     for (int q = 0; q < kGatherQ; ++q) {
-      const int n = n0 + q * kBlock + tid;
+      const int n = n0 + q * kSBlock + tid;
       ok[q] = n < N;
       pp[q] = base + (ok[q] ? n : 0);
     }
@@ -512,12 +635,12 @@ __global__ void __launch_bounds__(256) k_resample(const double *logw, int32_t N,
     }
   }
   __syncthreads();
-  for (int n0 = 0; n0 < N; n0 += kBlock * kGatherQ) {
+  for (int n0 = 0; n0 < N; n0 += kSBlock * kGatherQ) {
     int64_t pp[kGatherQ];
     bool ok[kGatherQ];
 #pragma unroll
     for (int q = 0; q < kGatherQ; ++q) {
-      const int n = n0 + q * kBlock + tid;
+      const int n = n0 + q * kSBlock + tid;
       ok[q] = n < N;
       pp[q] = base + (ok[q] ? n : 0);
     }
@@ -973,7 +1096,7 @@ smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1
 
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s) {
-  hipLaunchKernelGGL(k_group_logwbar, dim3(J), dim3(kBlock), 0, s, logw, N, out);
+  hipLaunchKernelGGL(k_group_logwbar, dim3(J), dim3(kSBlock), 0, s, logw, N, out);
   return launch_status("correct/group_logwbar");
 }
 
@@ -991,7 +1114,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
   const size_t lds = N <= kCumLdsMax ? (size_t)N * (sizeof(double) + 2 * sizeof(int32_t)) +
                                            kGatherLdsBytes
                                      : (size_t)N * sizeof(int32_t);
-  hipLaunchKernelGGL(k_resample, dim3(J), dim3(kBlock), lds, s, logw, N, scheme, seed, run, cycle,
+  hipLaunchKernelGGL(k_resample, dim3(J), dim3(kSBlock), lds, s, logw, N, scheme, seed, run, cycle,
                      anc, cum_ws, flags, g, go, group_logwbar);
   return launch_status("resample");
 }
