@@ -148,7 +148,7 @@ def test_correct_matches_oracle(name, prec, ce, J, N):
 
 @pytest.mark.parametrize("scheme", [S.SMC_RESAMPLE_RESIDUAL, S.SMC_RESAMPLE_MULTINOMIAL,
                                     S.SMC_RESAMPLE_STRATIFIED, S.SMC_RESAMPLE_SYSTEMATIC])
-@pytest.mark.parametrize("J,N", [(4, 64), (3, 1000), (2, 4096)])
+@pytest.mark.parametrize("J,N", [(4, 64), (3, 1000), (2, 2048), (2, 4096)])
 def test_resample_bit_exact(scheme, J, N):
     w = SD.workload("egarch11", T=10)
     gm, om = gpu_model(w), ora_model(w)
@@ -169,6 +169,52 @@ def test_resample_bit_exact(scheme, J, N):
         assert np.array_equal(anc_g[j * N:(j + 1) * N], anc_o[j * N:(j + 1) * N]), j
     O.gather(opop, anc_o)
     assert np.array_equal(theta_np(g), opop.theta)
+
+
+@pytest.mark.parametrize("name,J,N,with_grad", [
+    ("egarch11", 2, 7, False),       # one ragged wave
+    ("egarch11", 2, 1500, False),    # LDS staging of a group larger than the block
+    ("egarch11", 2, 2048, False),    # largest group held in LDS
+    ("egarch11", 2, 16384, False),   # largest group (workspace path)
+    ("egarch23", 3, 1000, False),    # 22 rows: LDS staging
+    ("egarch23", 2, 4096, False),    # 22 rows through the workspace
+    ("egarch2t", 3, 1000, True),     # gradient rows
+])
+def test_resample_gathers_every_row(name, J, N, with_grad):
+    """Ancestors equal to the oracle's (ties within rounding excepted); every
+    particle row (theta, log prior, log likelihood, state, gradient) replaced
+    by its ancestor's."""
+    w = SD.workload(name, T=10)
+    gm, om = gpu_model(w), ora_model(w)
+    rng = np.random.default_rng(N + 31 * J)
+    lw = rng.normal(0, 2.0, J * N) - 40.0
+    lw[rng.random(J * N) < 0.1] = -np.inf
+    anc_o, bad, mrg = O.resample(J, N, lw, S.SMC_RESAMPLE_RESIDUAL, seed=5, run=2, cycle=7,
+                                 with_margin=True)
+    assert bad == 0
+    opop = O.Pop(om, J, N)
+    opop.theta[:] = rng.standard_normal(opop.theta.shape)
+    opop.logprior[:] = rng.standard_normal(J * N)
+    opop.loglik[:] = rng.standard_normal(J * N)
+    opop.state[:] = rng.standard_normal(opop.state.shape)
+    opop.logw[:] = lw
+    g = pop_to_gpu(gm, opop, with_grad=with_grad)
+    if with_grad:
+        g.grad.copy_(torch.randn_like(g.grad))
+    rows_in = {k: getattr(g, k).cpu().numpy().copy() for k in ("theta", "logprior", "loglik", "state")}
+    if with_grad:
+        rows_in["grad"] = g.grad.cpu().numpy().copy()
+    S.smc_resample(gm, g, S.SMC_RESAMPLE_RESIDUAL, seed=5, run=2, cycle=7)
+    anc_g = g.ancestor.cpu().numpy()
+    for j in range(J):
+        if mrg[j] >= 1e-9:
+            assert np.array_equal(anc_g[j * N:(j + 1) * N], anc_o[j * N:(j + 1) * N]), j
+    # ancestors stay in their group, in ascending order
+    grp = np.arange(J * N) // N
+    assert np.array_equal(anc_g // N, grp)
+    assert np.all(np.diff(anc_g.reshape(J, N), axis=1) >= 0)
+    for k, a in rows_in.items():
+        assert np.array_equal(getattr(g, k).cpu().numpy(), a[..., anc_g]), k
 
 
 def test_resample_edge_cases():
