@@ -267,13 +267,13 @@ constexpr int kStageQ = kCumLdsMax / kSBlock;  // particles per thread in an LDS
 
 // Reduction over the group's block: a butterfly within each wave, then the
 // wave values combined in one fixed pairwise tree, the same in every thread.
-template <class Op, typename T>
-__device__ __forceinline__ T sblock_reduce(T v, T *lds /* >= kSWaves */) {
+template <class Op>
+__device__ __forceinline__ double sblock_reduce(double v, double *lds /* >= kSWaves */) {
   v = wave_reduce<Op>(v);
   __syncthreads();
   if ((threadIdx.x & 63) == 0) lds[threadIdx.x >> 6] = v;
   __syncthreads();
-  T x[kSWaves];
+  double x[kSWaves];
 #pragma unroll
   for (int i = 0; i < kSWaves; ++i) x[i] = lds[i];
 #pragma unroll
