@@ -265,7 +265,7 @@ constexpr int kGatherLdsBytes = 98304;  // LDS staging of source rows (groups <=
 constexpr int kStageRows = 8;          // rows of staging loads in flight together
 constexpr int kStageQ = kCumLdsMax / kSBlock;  // particles per thread in an LDS-held group
 
-// Reduction over the group's block: a butterfly within each wave, then the
+// Reduction over the group's block: wave_reduce within each wave, then the
 // wave values combined in one fixed pairwise tree, the same in every thread.
 template <class Op>
 __device__ __forceinline__ double sblock_reduce(double v, double *lds /* >= kSWaves */) {
