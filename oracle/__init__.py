@@ -15,7 +15,8 @@ natural CPU layout; the HIP path stores ``[d, P]`` and tests transpose.
 Parity-unpinned functions: the EGARCH log-likelihood for generic parameter
 values has no external value to compare with beyond the special cases and
 invariants in the tests (shock recovery on simulated data, the iid special
-case, factor exchange, finite-difference gradients); see the test modules.
+case, factor exchange, location-scale equivariance, finite-difference
+gradients); see the test modules.
 """
 from __future__ import annotations
 

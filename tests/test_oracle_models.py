@@ -132,6 +132,32 @@ def test_egarch_filter_recovers_simulated_shocks(K, shock):
     assert ll == pytest.approx(want, rel=1e-11)
 
 
+@pytest.mark.parametrize("K,shock,I", [(1, 0, 0), (2, 0, 0), (1, 1, 0), (2, 1, 0), (2, 2, 3),
+                                     (1, 2, 2)])
+def test_egarch_loglik_location_scale_equivariance(K, shock, I):
+    """y -> a + c y with mu -> a + c mu and sigma_Y -> c sigma_Y leaves every
+    standardised shock, hence the volatility recursion, unchanged, so the
+    log-likelihood drops by exactly T log c (the Jacobian of the change of
+    variables).  The parameters are moved well away from those that generated
+    the data, so this pins the recursion where shock recovery cannot."""
+    T = 300
+    if shock == SD.MIXTURE:
+        m, th, _, _ = _mix_model(K, I, T=T)
+    else:
+        m, th, _, _ = _egarch_model(K, shock, T=T)
+    x = th + 0.3 * np.random.default_rng(K * 10 + shock + I).standard_normal(th.size)
+    a, c = 0.37, 2.5
+    y2 = a + c * m.y
+    m2 = O.Model(O.EGARCH, T, y2, K=K, shock=shock, I=I) if shock == SD.MIXTURE else \
+        O.Model(O.EGARCH, T, y2, K=K, shock=shock)
+    x2 = x.copy()
+    x2[0] = 1000.0 * a + c * x[0]   # mu = theta_0 / 1000
+    x2[1] = x[1] + math.log(c)      # log sigma_Y
+    base = O.loglik(m, x)[0]
+    assert np.isfinite(base)
+    assert O.loglik(m2, x2)[0] == pytest.approx(base - T * math.log(c), rel=1e-11)
+
+
 def test_egarch_factors_are_exchangeable():
     m, th, _, _ = _egarch_model(2, 1, T=400)
     sw = th.copy()
