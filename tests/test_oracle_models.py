@@ -158,6 +158,34 @@ def test_egarch_loglik_location_scale_equivariance(K, shock, I):
     assert O.loglik(m2, x2)[0] == pytest.approx(base - T * math.log(c), rel=1e-11)
 
 
+@pytest.mark.parametrize("K,shock,I", [(1, 0, 0), (2, 0, 0), (2, 1, 0), (2, 2, 3)])
+def test_egarch_loglik_reflection_symmetry(K, shock, I):
+    """Reflecting the data about mu (y -> 2 mu - y) while negating the
+    asymmetry coefficients gamma_k (and, for mixtures, the component
+    locations) negates every standardised shock and leaves |eps|, gamma eps
+    and hence the volatility path unchanged; with symmetric shock laws the
+    log-likelihood is unchanged, at parameters away from the generating ones.
+    Using eps where |eps| belongs (or the reverse) fails it."""
+    T = 300
+    if shock == SD.MIXTURE:
+        m, th, _, _ = _mix_model(K, I, T=T)
+    else:
+        m, th, _, _ = _egarch_model(K, shock, T=T)
+    x = th + 0.3 * np.random.default_rng(7 + K * 10 + shock + I).standard_normal(th.size)
+    mu = x[0] / 1000.0
+    y2 = 2.0 * mu - m.y
+    m2 = O.Model(O.EGARCH, T, y2, K=K, shock=shock, I=I) if shock == SD.MIXTURE else \
+        O.Model(O.EGARCH, T, y2, K=K, shock=shock)
+    x2 = x.copy()
+    x2[2 + 2 * K:2 + 3 * K] = -x[2 + 2 * K:2 + 3 * K]   # gamma_k
+    if shock == SD.MIXTURE:
+        b = 2 + 3 * K
+        x2[b + I:b + 2 * I] = -x[b + I:b + 2 * I]         # component locations
+    base = O.loglik(m, x)[0]
+    assert np.isfinite(base)
+    assert O.loglik(m2, x2)[0] == pytest.approx(base, rel=1e-11)
+
+
 def test_egarch_factors_are_exchangeable():
     m, th, _, _ = _egarch_model(2, 1, T=400)
     sw = th.copy()
