@@ -4,6 +4,9 @@ mathematics they stand for.
 kExp2Coef (model.h): the FP64 base-2 exponential's polynomial on
 [-1/2, 1/2]; its relative error against 2^f (50-digit arithmetic) must stay
 below 4e-17, a third of an ulp, and it must be exact at f = 0.
+
+kLn2Hi / kLn2Lo (kernels.hip): ln 2 split over two doubles for the weights'
+exponential, whose arithmetic is replayed here against long double.
 """
 import os
 import re
@@ -45,3 +48,74 @@ def test_exp2_coefficients_near_taylor():
     for k, ck in enumerate(c):
         taylor = math.log(2) ** k / math.factorial(k)
         assert abs(ck / taylor - 1) < bound[k], (k, ck, taylor)
+
+
+KERNELS_HIP = os.path.join(ROOT, "paper_1304_4334_amd", "csrc", "kernels.hip")
+
+
+def _ln2_split():
+    src = open(KERNELS_HIP).read()
+    m = re.search(r"kLn2Hi\s*=\s*([0-9a-fA-Fx.p+-]+)\s*,\s*kLn2Lo\s*=\s*([0-9a-fA-Fx.p+-]+)\s*;", src)
+    assert m, "kLn2Hi / kLn2Lo not found"
+    return float.fromhex(m.group(1)), float.fromhex(m.group(2))
+
+
+def test_ln2_split_sums_to_ln2():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 50
+    hi, lo = _ln2_split()
+    assert hi == float(mp.log(2))
+    assert abs(mp.mpf(hi) + mp.mpf(lo) - mp.log(2)) < mp.mpf(2) ** -105
+
+
+def test_exp_nonpos_error_within_two_ulp(tmp_path):
+    """The weights' exponential (kernels.hip, exp_nonpos), replayed on the CPU
+    with the same constants and fused multiply-adds, against long double
+    expl on [-708, 0]; -inf gives 0 and 0 gives 1."""
+    import shutil
+    import subprocess
+    if shutil.which("gcc") is None:
+        pytest.skip("gcc not available")
+    hi, lo = _ln2_split()
+    m = re.search(r"kLog2e\s*=\s*([0-9.]+)\s*;", open(MODEL_H).read())
+    assert m, "kLog2e not found"
+    log2e = float(m.group(1)).hex()
+    coef = ", ".join(c.hex() for c in _exp2_coefficients())
+    src = f"""
+#include <math.h>
+#include <stdio.h>
+static const double C[12] = {{{coef}}};
+static double e_np(double x) {{
+  double xc = fmax(x, -1100.0);
+  double n = rint(xc * {log2e});
+  double r = fma(-n, {lo.hex()}, fma(-n, {hi.hex()}, xc));
+  double f = r * {log2e};
+  double p = fma(C[11], f, C[10]);
+  for (int k = 9; k >= 0; --k) p = fma(p, f, C[k]);
+  return x < -1100.0 ? 0.0 : ldexp(p, (int)n);
+}}
+int main(void) {{
+  double worst = 0.0;
+  unsigned long long s = 12345;
+  for (int i = 0; i < 2000000; ++i) {{
+    s = s * 6364136223846793005ull + 1442695040888963407ull;
+    double u = (double)(s >> 11) * 0x1.0p-53;
+    double x = (i & 3) ? -708.0 * u : -2.0 * u;
+    long double ref = expl((long double)x);
+    double y = e_np(x);
+    double ulp = nextafter((double)ref, INFINITY) - (double)ref;
+    double err = fabs((double)((long double)y - ref)) / ulp;
+    if (err > worst) worst = err;
+  }}
+  printf("%.6f %.17g %.17g\\n", worst, e_np(-INFINITY), e_np(0.0));
+  return 0;
+}}
+"""
+    c_file = tmp_path / "e.c"
+    c_file.write_text(src)
+    exe = tmp_path / "e"
+    subprocess.run(["gcc", "-O2", "-o", str(exe), str(c_file), "-lm"], check=True)
+    worst, at_neg_inf, at_zero = map(float, subprocess.run(
+        [str(exe)], check=True, capture_output=True, text=True).stdout.split())
+    assert worst < 2.0, worst
+    assert at_neg_inf == 0.0 and at_zero == 1.0
