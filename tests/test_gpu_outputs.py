@@ -156,3 +156,25 @@ def test_run_stops_on_numerical_flags():
     assert "flags" in str(ei.value)
     L = rec.L
     assert L >= 1 and rec.t_end[L - 1] == 61
+
+
+def test_run_stops_when_the_particle_variance_is_singular():
+    """Two groups of 16 particles of the four-parameter regression: the
+    oracle's run stops when the particle variance is no longer positive
+    definite, and so does the GPU's, with a numerical error naming the flags
+    and the same cycles recorded before it."""
+    w = SD.workload("linreg", T=60)
+    om = O.Model.from_workload(w)
+    rc, orec, _ = O.run(om, 2, 16, 21, Lmax=62, RmaxRec=64)
+    assert rc != 0
+    m = S.Model.from_workload(w)
+    g = S.Population(m, 2, 16, max_chunk=16)
+    rec = S.Record(m, 2, Lmax=62, RmaxRec=64)
+    with pytest.raises(S.SmcError) as ei:
+        S.smc_run(m, g, seed=21, record=rec)
+    assert ei.value.status == S.SMC_E_NUMERIC
+    assert "flags" in str(ei.value)
+    # the device raises the flag in the failing cycle; the driver reads it
+    # back with the next decision, so the record may hold that cycle too
+    assert orec.L <= rec.L <= orec.L + 1
+    assert np.array_equal(rec.t_end[:orec.L], orec.t_end[:orec.L])

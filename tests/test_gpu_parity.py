@@ -446,6 +446,24 @@ def test_adaptive_run_matches_oracle_run():
     assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
 
 
+@pytest.mark.parametrize("name,J,N,T", [("linreg", 2, 32, 60), ("egarch11", 2, 16, 80)])
+def test_smallest_adaptive_runs_match_oracle_runs(name, J, N, T):
+    """The fewest groups (J = 2) and groups of a few particles, each smaller
+    than one wave: the same cycle ends, M-phase lengths and log-ML as the
+    oracle's run."""
+    w = SD.workload(name, T=T)
+    gm, om = gpu_model(w), ora_model(w)
+    rc, orec, _ = O.run(om, J, N, 21, Lmax=T + 2, RmaxRec=64)
+    assert rc == 0
+    so = orec.summary()
+    g = S.Population(gm, J, N, max_chunk=16)
+    rec = S.smc_run(gm, g, seed=21, Lmax=T + 2, RmaxRec=64)
+    sg = rec.summary()
+    assert np.array_equal(sg["t_end"], so["t_end"])
+    assert np.array_equal(sg["R"], so["R"])
+    assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9)
+
+
 # --------------------------------------- independent Gaussian sampler (f4) --
 
 @pytest.mark.parametrize("name,prec", [("linreg", 0), ("egarch11", 0), ("egarch23", 0),
