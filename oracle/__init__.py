@@ -68,7 +68,8 @@ class OrcRecord(C.Structure):
                 ("log_ml", C.c_double), ("nse", C.c_double), ("log_ml_tilde", C.c_double),
                 ("evals", C.c_int64), ("moments", C.POINTER(C.c_double)),
                 ("mean", C.POINTER(C.c_double)), ("log_score", C.c_double), ("log_score_nse", C.c_double),
-                ("log_score_tilde", C.c_double)]
+                ("log_score_tilde", C.c_double), ("mh", C.POINTER(C.c_int32)),
+                ("chol", C.POINTER(C.c_double))]
 
 
 def lib():
@@ -359,12 +360,15 @@ class Record:
         self.group_logwbar = np.zeros((Lmax, J))
         self.moments = np.zeros((Lmax, max(G, 1), 4))
         self.mean = np.zeros((Lmax, RmaxRec, d))
+        self.mh = np.zeros((Lmax, RmaxRec), dtype=np.int32)
+        self.chol = np.zeros((Lmax, RmaxRec, d, d))
         self.c = OrcRecord(0, self.t_end.ctypes.data_as(C.POINTER(C.c_int64)),
                            self.R.ctypes.data_as(C.POINTER(C.c_int32)), _dp(self.hchol),
                            _dp(self.rss), self.n_acc.ctypes.data_as(C.POINTER(C.c_int64)),
                            _dp(self.group_logwbar), 0.0, 0.0, 0.0, 0,
                            _dp(self.moments) if G else C.POINTER(C.c_double)(),
-                           _dp(self.mean), float("nan"), float("nan"), float("nan"))
+                           _dp(self.mean), float("nan"), float("nan"), float("nan"),
+                           self.mh.ctypes.data_as(C.POINTER(C.c_int32)), _dp(self.chol))
 
     @property
     def L(self):
@@ -378,7 +382,9 @@ class Record:
                     group_logwbar=self.group_logwbar[:L].copy(),
                     moments=self.moments[:L, :self.G].copy() if self.G else None,
                     log_score=self.c.log_score, log_score_nse=self.c.log_score_nse,
-                    log_score_tilde=self.c.log_score_tilde)
+                    log_score_tilde=self.c.log_score_tilde,
+                    n_acc=self.n_acc[:L].copy(), mh=self.mh[:L].copy(),
+                    chol=self.chol[:L].copy(), hchol=self.hchol[:L].copy())
 
 
 def run(m: Model, J, N, seed, run_id=0, check_every=1, force_every=0, D1=0.5, D2=0.2, Rbar=7, kappa=3,

@@ -1083,6 +1083,8 @@ typedef struct {
   double *moments;       /* [Lmax][G][4] report at each cycle end, or NULL */
   double *mean;          /* [Lmax][RmaxRec][d] particle means (independent sampler), or NULL */
   double log_score, log_score_nse, log_score_tilde; /* over (burn_in, T] */
+  int32_t *mh;           /* [Lmax][RmaxRec] step size in tenths used by each iteration, or NULL */
+  double *chol;          /* [Lmax][RmaxRec][d*d] unscaled Cholesky factor of V_lr, or NULL */
 } orc_record;
 
 /* Returns 0, or a negative code: -1 record too small, -2 non-PD variance,
@@ -1135,6 +1137,10 @@ int orc_run(const orc_model *m, const orc_cfg *cfg, orc_pop *pop, orc_record *re
         /* the independent sampler uses the particle variance unscaled */
         double h = (cfg->kernel == ORC_INDEP) ? 1.0 : mh / 10.0;
         for (int i = 0; i < d * d; ++i) hl[i] = h * chol[i];
+        if (rec->mh) rec->mh[(int64_t)l * cfg->RmaxRec + (r - 1)] = (cfg->kernel == ORC_INDEP) ? 10 : mh;
+        if (rec->chol)
+          for (int i = 0; i < d * d; ++i)
+            rec->chol[((int64_t)l * cfg->RmaxRec + (r - 1)) * d * d + i] = chol[i];
         if (mrec)
           for (int i = 0; i < d; ++i) mrec[i] = mean[i];
       }
