@@ -100,8 +100,8 @@ int32_t state_bytes(const smc_model *m) { return m->dev.prec == SMC_FP32 ? 4 : 8
 // each chunk's decision and the numerical flags word (one per host thread,
 // kept for the life of the process); NULL if it cannot be had.  Device
 // stores to coherent host memory bypass the device caches, so the host needs
-// neither a fence nor an event: it watches the slot for both
-// sequence-tagged halves while the work queued after the kernel runs on.
+// neither a fence nor an event: it watches the slot until every word carries
+// the call's sequence number while the work queued after the kernel runs on.
 DecisionSlot *decision_slot() {
   thread_local DecisionSlot *buf = nullptr;
   thread_local bool tried = false;
@@ -115,10 +115,6 @@ DecisionSlot *decision_slot() {
     }
   }
   return buf;
-}
-int32_t *pinned_flags_slot() {
-  DecisionSlot *b = decision_slot();
-  return b ? &b->flags : nullptr;
 }
 
 // An event (no timing) of the calling thread for the current device, marking
@@ -137,17 +133,19 @@ smc_status readback_event(hipEvent_t *out) {
   return SMC_OK;
 }
 
-// Waits until both halves of the slot carry `seq`, then reads the decision;
-// the tags are read before the data they cover, so a half is read only after
-// it landed.  The stream is polled every millisecond: once all its work has
-// completed the halves get 10 more ms, then the wait fails (false).
-bool await_decision(const DecisionSlot *slot, uint32_t seq, hipStream_t s, StopInfo *out) {
-  const volatile uint32_t *w = reinterpret_cast<const volatile uint32_t *>(slot);
+// Waits until the slot holds this call's whole decision for the chunk
+// (t, t1] (read_decision: every word tagged with `seq`, two reads agreeing,
+// the date inside the chunk).  The stream is polled every millisecond: once
+// all its work has completed the slot gets 10 more ms, then the wait fails
+// (false).
+bool await_decision(const DecisionSlot *slot, uint32_t seq, int64_t t, int64_t t1, hipStream_t s,
+                    StopInfo *out, int32_t *flags) {
+  const volatile DecisionSlot *v = slot;
   using clock = std::chrono::steady_clock;
   auto next_poll = clock::now() + std::chrono::milliseconds(1);
   clock::time_point idle_since{};
   bool idle = false;
-  while (!(w[0] == seq && w[7] == seq)) {
+  while (!read_decision(v, seq, t, t1, out, flags)) {
     const auto now = clock::now();
     if (now < next_poll) continue;
     next_poll = now + std::chrono::milliseconds(1);
@@ -161,12 +159,6 @@ bool await_decision(const DecisionSlot *slot, uint32_t seq, hipStream_t s, StopI
       return false;
     }
   }
-  uint32_t v[8];
-  for (int i = 1; i < 7; ++i) v[i] = w[i];
-  out->t_commit = (int64_t)(((uint64_t)v[3] << 32) | v[2]);
-  out->rss = __builtin_bit_cast(double, ((uint64_t)v[5] << 32) | v[4]);
-  out->ends = (int32_t)(v[6] & 1u);
-  out->below = (int32_t)((v[6] >> 1) & 1u);
   return true;
 }
 
@@ -205,7 +197,8 @@ struct ResampleAhead {
 smc_status correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from, int64_t t_max,
                         int64_t check_every, double rss_min, double *group_logwbar,
                         int64_t *t_to, double *rss, void *stream, int64_t first_chunk,
-                        const ResampleAhead *ahead = nullptr, bool *resampled = nullptr);
+                        const ResampleAhead *ahead = nullptr, bool *resampled = nullptr,
+                        int32_t *flags_seen = nullptr);
 
 }  // namespace smc
 
@@ -322,13 +315,17 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
 // reads the decision back; with `ahead`, the S phase (which does nothing
 // unless the phase ended, and then also writes the group weights) is queued
 // too, so the device has that work in hand while the host waits.
-// *resampled tells whether the S phase was queued that way.
+// *resampled tells whether the S phase was queued that way; *flags_seen
+// receives the workspace's flags word as the last decision carried it (-1
+// when no decision came through the host slot).
 smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from,
                              int64_t t_max, int64_t check_every, double rss_min,
                              double *group_logwbar, int64_t *t_to, double *rss, void *stream,
-                             int64_t first_chunk, const ResampleAhead *ahead, bool *resampled) {
+                             int64_t first_chunk, const ResampleAhead *ahead, bool *resampled,
+                             int32_t *flags_seen) {
   smc_status st;
   if (resampled) *resampled = false;
+  if (flags_seen) *flags_seen = -1;
   if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
   if (!group_logwbar || !t_to) return set_error(SMC_E_INVALID_ARG, "NULL output");
   if (t_from < 0 || t_max > m->dev.T || t_from > t_max)
@@ -412,8 +409,11 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
                                   &stop_dev->ends, group_logwbar)))
           return st;
       }
-      if (slot ? !await_decision(slot, slot_seq, s, &got) : hipEventSynchronize(ev) != hipSuccess)
+      int32_t fl = -1;
+      if (slot ? !await_decision(slot, slot_seq, t, t1, s, &got, &fl)
+               : hipEventSynchronize(ev) != hipSuccess)
         return set_error(SMC_E_DEVICE, "correct: the stop decision did not reach the host");
+      if (flags_seen) *flags_seen = fl;
       zero_first = false;
       rss_at_stop = got.rss;
       t = got.t_commit;
@@ -698,7 +698,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     // with this cycle's C-phase decisions (the decision kernel stores them in
     // the page-locked slot; one host synchronisation fewer per cycle); a
     // raised flag ends the run after that readback.
-    int32_t *fl_host = cfg->replay ? nullptr : pinned_flags_slot();
+    int32_t fl_seen = -1;
     int64_t t_new = t;
     double rss = NAN;
     // Speculate on a cycle twice as long as the previous one, so most C
@@ -712,12 +712,12 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     if ((st = correct_impl(m, pop, t, t_stop, cfg->check_every, cfg->replay ? 0.0 : cfg->D1,
                            rec->group_logwbar + (int64_t)l * cfg->J, &t_new,
                            cfg->replay ? nullptr : &rss, stream, hint,
-                           cfg->replay ? nullptr : &ahead, &resampled)))
+                           cfg->replay ? nullptr : &ahead, &resampled, &fl_seen)))
       return st;
     // correct_impl has waited for its last decision, which carried the flags
-    if (fl_host && l > 0 && *fl_host) {
+    if (fl_seen > 0 && l > 0) {
       rec->L = l;
-      return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", *fl_host, l);
+      return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", fl_seen, l);
     }
     last_len = t_new - t;
     evals += P * (t_new - t);
@@ -831,7 +831,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     t = t_new;
     ++l;
     // without the pinned slot (or after the last cycle) the flags are read here
-    if (!cfg->replay && (!pinned_flags_slot() || t >= T)) {
+    if (!cfg->replay && (!decision_slot() || t >= T)) {
       int32_t fl = 0;
       if (hipMemcpyAsync(&fl, dflags, sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
           hipStreamSynchronize(s) != hipSuccess)

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include "decision.h"
 #include "smc.h"
 
 namespace smc {
@@ -61,30 +62,6 @@ constexpr size_t kSmallStop = 16896;  // StopInfo
 constexpr size_t kSmallBytes = 17152;
 
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
-
-// A C-phase chunk's outcome, decided on the device: the date the weights are
-// committed to (the first checked date whose RSS fell below the threshold, or
-// the chunk's end), the RSS there, whether it fell below, and whether the
-// phase ends with this chunk (it fell below, or the chunk reached the
-// phase's last date).
-struct StopInfo {
-  int64_t t_commit;
-  double rss;
-  int32_t below;
-  int32_t ends;
-};
-
-// The same decision, with the workspace's flags word, as the decision kernel
-// stores it in page-locked host memory: two 16-byte stores, each carrying
-// the call's sequence number, so the host can tell that both have landed.
-struct alignas(16) DecisionSlot {
-  uint32_t seq_a;
-  int32_t flags;
-  int64_t t_commit;
-  double rss;
-  uint32_t ends_below;  // bit 0: the phase ends; bit 1: the RSS fell below the threshold
-  uint32_t seq_b;
-};
 
 WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N);
 

@@ -206,8 +206,8 @@ __global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t
 // RSS is below rss_min): one wave scans the columns 64 at a time.  Column c
 // holds date first + c * check_every, the multiples of check_every after t
 // up to t1, and t_max last when it is not a multiple.  With host_slot, the
-// decision and the flags word also go to host memory, in two 16-byte stores
-// tagged with seq.
+// decision and the flags word also go to host memory, every 32-bit word of
+// them paired with seq in an 8-byte word (DecisionSlot).
 __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc, int64_t t,
                                                   int64_t t1, int64_t check_every, int64_t t_max,
                                                   double rss_min, StopInfo *out,
@@ -236,11 +236,10 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
       const int32_t fl = *flags;
       const uint64_t tc = (uint64_t)o.t_commit;
       const uint64_t rb = __builtin_bit_cast(uint64_t, o.rss);
-      const uint4 a = make_uint4(seq, (uint32_t)fl, (uint32_t)tc, (uint32_t)(tc >> 32));
-      const uint4 b = make_uint4((uint32_t)rb, (uint32_t)(rb >> 32),
-                                 (uint32_t)(o.ends | (o.below << 1)), seq);
-      reinterpret_cast<uint4 *>(host_slot)[0] = a;
-      reinterpret_cast<uint4 *>(host_slot)[1] = b;
+      uint4 *dst = reinterpret_cast<uint4 *>(host_slot);
+      dst[0] = make_uint4(seq, (uint32_t)tc, seq, (uint32_t)(tc >> 32));
+      dst[1] = make_uint4(seq, (uint32_t)rb, seq, (uint32_t)(rb >> 32));
+      dst[2] = make_uint4(seq, (uint32_t)fl, seq, (uint32_t)(o.ends | (o.below << 1)));
     }
   }
 }
