@@ -16,7 +16,7 @@ import paper_1304_4334_amd as S
 import synthdata as SD
 from oracle import closed_form as CF
 from paper_1304_4334_amd import autograd as SA
-from tests.gpu_helpers import gpu_model, ora_model, pop_to_gpu, theta_np
+from tests.gpu_helpers import accept_audit, gpu_model, ora_model, pop_to_gpu, theta_np
 
 pytestmark = pytest.mark.gpu
 
@@ -122,6 +122,8 @@ def test_mala_step_matches_oracle(name, prec):
     hl = {"linreg": 1.0, "egarch23": 1.5}.get(name, 0.3) * chol
     g = pop_to_gpu(gm, opop, with_grad=True)
     S.smc_posterior_grad(gm, g, w.T)
+    before = (opop.theta.copy(), opop.logprior.copy(), opop.loglik.copy())
+    g0 = g.grad.cpu().numpy().T.copy()
     acc_g = torch.zeros(J * N, dtype=torch.uint8, device="cuda")
     S.smc_mutate(gm, g, w.T, torch.from_numpy(hl).cuda(), seed=2, cycle=1, it=3,
                  kernel=S.SMC_KERNEL_MALA, accepted=acc_g)
@@ -132,7 +134,9 @@ def test_mala_step_matches_oracle(name, prec):
         assert np.array_equal(acc_g, acc_o)
         assert np.allclose(theta_np(g), opop.theta, rtol=1e-11, atol=1e-12)
     else:
-        assert np.mean(acc_g != acc_o) < 0.05
+        err, _ = accept_audit(gm, om, *before, w.T, hl, 2, 0, 1, 3, acc_g, acc_o,
+                              kernel=S.SMC_KERNEL_MALA, g0_gpu=g0)
+        assert err < 2e-2
         same = acc_g == acc_o
         assert np.allclose(theta_np(g)[same], opop.theta[same], rtol=1e-5, atol=1e-6)
     # the stored gradient follows the particle
@@ -167,3 +171,63 @@ def test_mala_replay_of_oracle_design():
     assert sg["L"] == so["L"]
     assert sg["log_ml"] == pytest.approx(so["log_ml"], rel=1e-9, abs=1e-8)
     assert np.allclose(theta_np(g), opop.theta, rtol=1e-8, atol=1e-9)
+
+
+# --------------------------------------- the Langevin workload at full size --
+# EGARCH(2) Student-t, FP32 recursion, 64 x 1,024 particles, T = 10,000: the
+# adjoint's forward sweep keeps 157 checkpoints of 64 observations per
+# particle.  Sampled particles are checked one by one against the oracle.
+
+def _full_2t():
+    w = SD.workload("egarch2t")
+    gm, om = gpu_model(w, S.SMC_FP32), ora_model(w)
+    P = w.P
+    idx = np.concatenate([[0, 1, 63, 64, P - 64, P - 1],
+                          np.random.default_rng(9).choice(np.arange(65, P - 64), 10, replace=False)])
+    return w, gm, om, P, idx
+
+
+def test_loglik_backward_full_size_sampled():
+    w, gm, om, P, idx = _full_2t()
+    assert (P, w.T, -(-w.T // 64)) == (65536, 10000, 157)
+    th = SD.random_thetas(w, P, 51, spread=0.01)
+    dl = np.random.default_rng(5).uniform(0.5, 2.0, P)
+    got = S.smc_loglik_backward(gm, torch.from_numpy(th.T.copy()).cuda(), w.T,
+                                torch.from_numpy(dl).cuda()).cpu().numpy().T
+    want = np.array([dl[p] * O.loglik_grad(om, th[p], w.T)[1] for p in idx])
+    rel = np.abs(got[idx] - want) / (np.linalg.norm(want, axis=1, keepdims=True))
+    print(f"[fp32] gradient egarch2t T=10000 P=65536: max error {rel.max():.3e} of the norm")
+    assert _grad_close(got[idx], want, S.SMC_FP32)
+
+
+def test_mala_step_full_size_sampled():
+    w, gm, om, P, idx = _full_2t()
+    th = SD.random_thetas(w, P, 52, spread=0.01)
+    g = S.Population(gm, w.J, w.N, max_chunk=16, with_grad=True)
+    g.theta.copy_(torch.from_numpy(th.T.copy()))
+    g.loglik.copy_(S.smc_loglik(gm, g.theta, w.T))
+    lp_o = np.array([O.logprior(om, th[p]) for p in idx])
+    ll_o = np.array([O.loglik(om, th[p], w.T)[0] for p in idx])
+    for k, p in enumerate(idx):
+        g.loglik[int(p)] = ll_o[k]
+        g.logprior[int(p)] = lp_o[k]
+    S.smc_posterior_grad(gm, g, w.T)
+    g0 = g.grad.cpu().numpy().T[idx].copy()
+    hl = np.linalg.cholesky(np.cov(th[::16].T)) * 0.3
+    acc = torch.zeros(P, dtype=torch.uint8, device="cuda")
+    S.smc_mutate(gm, g, w.T, torch.from_numpy(hl).cuda(), seed=6, run=0, cycle=4, it=2,
+                 kernel=S.SMC_KERNEL_MALA, accepted=acc)
+    acc = acc.cpu().numpy()[idx]
+    th_g = theta_np(g)[idx]
+    acc_o = np.zeros(len(idx), bool)
+    for k, p in enumerate(idx):
+        a, th_o, _, _, _ = O.mutate_particle(om, int(p), th[p], lp_o[k], ll_o[k], w.T, hl,
+                                             seed=6, run=0, cycle=4, it=2, kernel=O.MALA)
+        acc_o[k] = a
+        if a == bool(acc[k]):
+            # the proposal's drift uses the FP32 gradient
+            assert np.allclose(th_g[k], th_o, rtol=1e-5, atol=1e-6), int(p)
+    err, _ = accept_audit(gm, om, th[idx], lp_o, ll_o, w.T, hl, 6, 0, 4, 2, acc, acc_o,
+                          pidx=idx, kernel=S.SMC_KERNEL_MALA, g0_gpu=g0)
+    assert err < 0.5
+    assert acc_o.sum() > 0
