@@ -264,6 +264,22 @@ smc_status smc_test_moments(const smc_model *m, smc_particles *pop, int64_t t, i
 smc_status smc_particle_moments(const smc_model *m, const smc_particles *pop, const int32_t *mh,
                                 double *mean, double *cov, double *hchol, void *stream);
 
+/* For callers that cannot allocate device memory (code under graph capture,
+ * tight serving loops, harnesses that forbid allocation): smc_particle_moments
+ * with the same arguments, results and error behaviour, except that pop->ws is
+ * not used (it may be NULL).  The scratch of its kernels (up to 129 moment
+ * matrices of 32 x 32 doubles, then a flags word: SMC_MOMENTS_SCRATCH_BYTES in
+ * all) lives in a static device array that each GPU the library runs on holds
+ * until the process ends; the call allocates nothing.  Every call on a GPU
+ * shares that GPU's array and clears its flags word first, so calls that
+ * overlap on one GPU race.  A variance that is not positive definite leaves
+ * hchol zero (hchol[0] == 0; the flag is not reported).  SMC_E_WORKSPACE if a
+ * population's partials would exceed the array (never for d < 32). */
+#define SMC_MOMENTS_SCRATCH_BYTES 1057024
+smc_status smc_particle_moments_noalloc(const smc_model *m, const smc_particles *pop,
+                                        const int32_t *mh, double *mean, double *cov,
+                                        double *hchol, void *stream);
+
 /* Step-size rule of Section 3.3 on device: with a = *n_accept / P,
  * *mh += 1 if a > target_permille / 1000 else *mh -= 1, clamped to [1, 10].
  * The comparison is exact in integers. */

@@ -104,6 +104,8 @@ def lib():
         L.smc_resample.argtypes = [_vp, P(Particles), C.c_int32, Rng, C.c_int32, _vp]
         L.smc_particle_moments.restype = st
         L.smc_particle_moments.argtypes = [_vp, P(Particles), _vp, _vp, _vp, _vp, _vp]
+        L.smc_particle_moments_noalloc.restype = st
+        L.smc_particle_moments_noalloc.argtypes = [_vp, P(Particles), _vp, _vp, _vp, _vp, _vp]
         L.smc_mutate.restype = st
         L.smc_mutate.argtypes = [_vp, P(Particles), C.c_int64, C.c_int32, _vp, Rng,
                                  C.c_int32, C.c_int32, _vp, _vp, _vp]
@@ -269,6 +271,17 @@ def smc_particle_moments(model, pop, mh, mean=None, cov=None, hchol=None, stream
         hchol = torch.zeros((model.d, model.d), dtype=torch.float64, device=model.device)
     _check(lib().smc_particle_moments(model.h, C.byref(pop.c), _ptr(mh), _ptr(mean), _ptr(cov),
                                       _ptr(hchol), _stream(stream)), "smc_particle_moments")
+    return hchol
+
+
+def smc_particle_moments_noalloc(model, pop, mh, mean=None, cov=None, hchol=None, stream=None):
+    """smc_particle_moments without the population's workspace (its scratch
+    is the library's static device array)."""
+    if hchol is None:
+        hchol = torch.zeros((model.d, model.d), dtype=torch.float64, device=model.device)
+    _check(lib().smc_particle_moments_noalloc(model.h, C.byref(pop.c), _ptr(mh), _ptr(mean),
+                                              _ptr(cov), _ptr(hchol), _stream(stream)),
+           "smc_particle_moments_noalloc")
     return hchol
 
 
