@@ -118,7 +118,8 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
 
 // The random-walk M step of one particle of run `st` (as k_mutate_rw).
 template <class M>
-__device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &dy, int64_t p) {
+__device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &dy, int64_t p,
+                                         const typename M::Y *__restrict__ y) {
   constexpr int D = M::D;
   using R = typename M::R;
   constexpr int S = M::S;
@@ -144,7 +145,7 @@ __device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &
   double ll1 = -INFINITY;
   if (lp1 > -INFINITY) {
     const auto par = M::params(pr);
-    ll1 = M::advance(par, stv, 0, dy.t, static_cast<const typename M::Y *>(st.y));
+    ll1 = M::advance(par, stv, 0, dy.t, y);
     const double delta = (lp1 + ll1) - (st.logprior[p] + st.loglik[p]);
     const U64x4 w = draw4(st.seed, st.run, (uint64_t)p, (uint64_t)dy.cycle, (uint64_t)dy.iter,
                           kAccept);
@@ -178,8 +179,10 @@ __global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
     const int64_t p = (int64_t)(item - dy.mut_begin) * 64 + threadIdx.x;
     int acc = 0;
     if (p < st.P) {
-      if (st.tag == 0) acc = mstep_one<M0>(st, dy, p);
-      else acc = mstep_one<M1>(st, dy, p);
+      if (st.tag == 0)
+        acc = mstep_one<M0>(st, dy, p, static_cast<const typename M0::Y *>(st.y));
+      else
+        acc = mstep_one<M1>(st, dy, p, static_cast<const typename M1::Y *>(st.y));
     }
     const unsigned long long mask = __ballot(acc);
     if (threadIdx.x == 0 && mask) atomicAdd(dy.n_accept, (unsigned long long)__popcll(mask));

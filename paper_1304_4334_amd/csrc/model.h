@@ -27,6 +27,12 @@ constexpr double kLog2Pi = 1.8378770664093453390819;
 constexpr double kSqrt2OverPi = 0.79788456080286535588;
 constexpr double kLn2 = 0.69314718055994530942;
 constexpr double kLog2e = 1.4426950408889634074;
+// Per-observation terms are summed in the recursion's precision over groups
+// of kAcc observations before each group's sum is added to FP64
+// accumulators.  kUnroll is the default number of observations whose loads
+// are issued together; the loads of the next batch are in flight while the
+// current one is processed.  The batch size does not change the arithmetic.
+constexpr int kAcc = 8;
 constexpr int kUnroll = 8;
 
 // 2^x.  FP32: the hardware base-2 exponential.  FP64: x = n + f with
@@ -358,18 +364,20 @@ struct Egarch {
       else return v;
     };
     const R z = fma(y, p.isig, -p.mus);
-    R kk = (R)0, AA = (R)0;
+    // the cross-factor sums start from the first factor's terms (an added
+    // zero would cost an instruction each)
+    R kk, AA;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R A = fma(p.a[k], r.w[k], p.c0[k]);
       const R kz = fma(p.kb[k], fabs(z), p.kg[k] * z);
       r.w[k] = fma(scaled(kz), Ef, A);
-      if (K > 1) {
-        kk += kz;
-        AA += A;
-      } else {
+      if (k == 0) {
         kk = kz;
         AA = A;
+      } else {
+        kk += kz;
+        AA += A;
       }
     }
     r.sw = (K > 1) ? fma(scaled(kk), Ef, AA) : r.w[0];
@@ -443,14 +451,27 @@ struct Egarch {
       else ld = base + kLn2 * (double)sw - 0.5 * (double)ae;
       f(s, ld);
     };
-    // Observations in blocks of kUnroll whose loads are issued together.
+    // Observations in batches of kUnroll whose loads are issued together,
+    // the next batch's while the current one is processed.
     int64_t s = t0 + 1;
-    for (; s + kUnroll - 1 <= t1; s += kUnroll) {
+    const int64_t nbat = (t1 - t0) / kUnroll;
+    if (nbat > 0) {
       R yb[kUnroll];
 #pragma unroll
       for (int i = 0; i < kUnroll; ++i) yb[i] = y[s - 1 + i];
+      __asm__ volatile("" ::"s"(yb[0]), "s"(yb[kUnroll - 1]));  // see advance
+      for (int64_t b = 0; b < nbat; ++b, s += kUnroll) {
+        const Y *pn = y + (s - 1) + (b + 1 < nbat ? kUnroll : 0);
+        R yn[kUnroll];
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) one(s + i, yb[i]);
+        for (int i = 0; i < kUnroll; ++i) yn[i] = pn[i];
+        __asm__ volatile("" ::: "memory");  // the next batch's loads issue here (see advance)
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) one(s + i, yb[i]);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) yb[i] = yn[i];
+      }
     }
     for (; s <= t1; ++s) one(s, y[s - 1]);
     const R kap = (R)kKappa;
@@ -461,9 +482,14 @@ struct Egarch {
 
   // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1.  st holds the
   // state at t0 in the API's units, (v_1..v_K, eps_t0), and receives the
-  // state at t1.
+  // state at t1.  The terms are summed in groups of kAcc; the observations
+  // are loaded U at a time (U = 4, 8 or 16), each batch's loads issued
+  // while the previous batch is processed.  U changes the schedule only:
+  // every U gives the same operations in the same order.
+  template <int U = kUnroll>
   __device__ static double advance(const Par &p, R (&st)[S], int64_t t0, int64_t t1,
                                    const Y *__restrict__ y) {
+    static_assert(U == 4 || U == 8 || U == 16, "batches of 4, 8 or 16 observations");
     if (t1 <= t0) return 0.0;
     Run r;
     const R kap = (R)kKappa;
@@ -472,35 +498,77 @@ struct Egarch {
     const Y *yp = y + t0;
     const int n = (int)(t1 - t0);
     const int nm = n - 1;  // all but the last observation
-    const int nb = nm / kUnroll;
-    for (int b = 0; b < nb; ++b, yp += kUnroll) {
-      R yb[kUnroll];
+    const int nb = nm / kAcc;  // whole groups
+    // group sums (carried across the two batches of a group when U = 4)
+    R av = (R)0, ae = (R)0, pm = (R)1;
+    auto flush = [&]() {
+      sv += (double)av;
+      se += (double)ae;
+      if constexpr (kMix) se += (double)log2_fast(pm);
+      ae = (R)0;
+      pm = (R)1;
+    };
+    constexpr int G = U < kAcc ? kAcc / U : 1;  // batches per group
+    constexpr int Q = U > kAcc ? U / kAcc : 1;  // groups per batch
+    const int nbat = nb * G / Q;  // whole batches (U = 16 may leave one group)
+    if (nbat > 0) {
+      R yb[U];
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) yb[i] = yp[i];
-      R av, ae = (R)0, pm = (R)1, Ed, zd;
+      for (int i = 0; i < U; ++i) yb[i] = yp[i];
+      // the first batch is waited for here, so that the wait inside the loop
+      // covers only what the loop itself loads
+      __asm__ volatile("" ::"s"(yb[0]), "s"(yb[U - 1]));
+      for (int b = 0; b < nbat; ++b, yp += U) {
+        const Y *pn = yp + (b + 1 < nbat ? U : 0);
+        R yn[U];
+#pragma unroll
+        for (int i = 0; i < U; ++i) yn[i] = pn[i];
+        // issues the next batch's loads here, a whole batch ahead of their
+        // use (the observations are read-only, so the compiler would
+        // otherwise place them just before it)
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < U; ++i) {
+          R Ed, zd;
+          const R sw = step(p, yb[i], r, ae, pm, Ed, zd);
+          // position in the group; its first term starts the group's sum
+          const int pos = (G > 1 ? (b % G) * U : 0) + (i % kAcc);
+          if (pos == 0) av = sw;
+          else av += sw;
+          if (pos == kAcc - 1) flush();
+        }
+#pragma unroll
+        for (int i = 0; i < U; ++i) yb[i] = yn[i];
+      }
+    }
+    // a group left over by batches of 16
+    for (int g = nbat * Q / G; g < nb; ++g, yp += kAcc) {
+      R yb[kAcc];
+#pragma unroll
+      for (int i = 0; i < kAcc; ++i) yb[i] = yp[i];
+      R Ed, zd;
       av = step(p, yb[0], r, ae, pm, Ed, zd);
 #pragma unroll
-      for (int i = 1; i < kUnroll; ++i) av += step(p, yb[i], r, ae, pm, Ed, zd);
-      sv += (double)av;
-      se += (double)ae;
-      if constexpr (kMix) se += (double)log2_fast(pm);
+      for (int i = 1; i < kAcc; ++i) av += step(p, yb[i], r, ae, pm, Ed, zd);
+      flush();
     }
-    for (int i = nb * kUnroll; i < nm; ++i, ++yp) {
-      R ae = (R)0, pm = (R)1, Ed, zd;
-      const R av = step(p, *yp, r, ae, pm, Ed, zd);
-      sv += (double)av;
-      se += (double)ae;
-      if constexpr (kMix) se += (double)log2_fast(pm);
+    for (int i = nb * kAcc; i < nm; ++i, ++yp) {
+      R ae1 = (R)0, pm1 = (R)1, Ed, zd;
+      const R av1 = step(p, *yp, r, ae1, pm1, Ed, zd);
+      sv += (double)av1;
+      se += (double)ae1;
+      if constexpr (kMix) se += (double)log2_fast(pm1);
     }
     // The last observation: keep its exponents and shock for the state.
     R wl[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) wl[k] = r.w[k];
-    R ae = (R)0, pm = (R)1, E, z;
-    const R av = step(p, *yp, r, ae, pm, E, z);
-    sv += (double)av;
-    se += (double)ae;
-    if constexpr (kMix) se += (double)log2_fast(pm);
+    R ae1 = (R)0, pm1 = (R)1, E, z;
+    const R av1 = step(p, *yp, r, ae1, pm1, E, z);
+    sv += (double)av1;
+    se += (double)ae1;
+    if constexpr (kMix) se += (double)log2_fast(pm1);
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
     st[K] = z * E;
@@ -592,10 +660,31 @@ struct Linreg {
 template <class M>
 struct Eval {
   using R = typename M::R;
+  using Y = typename M::Y;
   static constexpr int SR = M::S;
   __device__ __forceinline__ static double advance(const DevModel &dm, const typename M::Par &p,
                                                    R (&st)[SR], int64_t t0, int64_t t1) {
     return M::advance(p, st, t0, t1, M::ydata(dm));
+  }
+  // The same with the observations from a kernel argument declared
+  // __restrict__: a kernel that also stores to global memory then still
+  // reads them as uniform scalar loads.
+  __device__ __forceinline__ static double advance_y(const DevModel &dm, const Y *__restrict__ y,
+                                                     const typename M::Par &p, R (&st)[SR],
+                                                     int64_t t0, int64_t t1) {
+    (void)dm;
+    return M::advance(p, st, t0, t1, y);
+  }
+  template <class F>
+  __device__ __forceinline__ static void scan_y(const DevModel &dm, const Y *__restrict__ y,
+                                                const typename M::Par &p, R (&st)[SR],
+                                                int64_t t0, int64_t t1, F &&f) {
+    (void)dm;
+    M::scan(p, st, t0, t1, y, f);
+  }
+  static const Y *host_y(const DevModel &dm) {
+    if constexpr (sizeof(Y) == 4) return dm.y32;
+    else return dm.y;
   }
   template <class F>
   __device__ __forceinline__ static void scan(const DevModel &dm, const typename M::Par &p,
@@ -607,6 +696,7 @@ struct Eval {
 template <int NREG>
 struct Eval<Linreg<NREG>> {
   using R = double;
+  using Y = double;
   static constexpr int SR = 1;
   __device__ __forceinline__ static double advance(const DevModel &dm,
                                                    const typename Linreg<NREG>::Par &p,
@@ -614,6 +704,20 @@ struct Eval<Linreg<NREG>> {
     (void)st;
     return Linreg<NREG>::advance_x(p, t0, t1, dm.y, dm.X);
   }
+  __device__ __forceinline__ static double advance_y(const DevModel &dm, const Y *__restrict__ y,
+                                                     const typename Linreg<NREG>::Par &p,
+                                                     double (&st)[1], int64_t t0, int64_t t1) {
+    (void)st;
+    return Linreg<NREG>::advance_x(p, t0, t1, y, dm.X);
+  }
+  template <class F>
+  __device__ __forceinline__ static void scan_y(const DevModel &dm, const Y *__restrict__ y,
+                                                const typename Linreg<NREG>::Par &p,
+                                                double (&st)[1], int64_t t0, int64_t t1, F &&f) {
+    (void)st;
+    for (int64_t s = t0 + 1; s <= t1; ++s) f(s, Linreg<NREG>::advance_x(p, s - 1, s, y, dm.X));
+  }
+  static const Y *host_y(const DevModel &dm) { return dm.y; }
   template <class F>
   __device__ __forceinline__ static void scan(const DevModel &dm,
                                               const typename Linreg<NREG>::Par &p,

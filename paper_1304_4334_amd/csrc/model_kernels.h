@@ -70,7 +70,8 @@ template <class M, bool kEvery1>
 __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
                                               const void *state, const double *logw, int64_t t0,
                                               int64_t t1, int64_t check_every, int64_t t_max,
-                                              int32_t zero_first, double *W) {
+                                              int32_t zero_first, double *W,
+                                              const typename M::Y *__restrict__ ydata) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
   using R = typename M::R;
@@ -85,7 +86,7 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
   double lw = zero_first ? 0.0 : logw[p];
   double *colp = W;  // the next column to record
   if constexpr (kEvery1) {
-    Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t, double lp) {
+    Eval<M>::scan_y(dm, ydata, par, st, t0, t1, [&](int64_t, double lp) {
       if (isnan(lp)) lp = -INFINITY;
       lw += lp;
       colp[p] = lw;
@@ -100,7 +101,7 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
     const int32_t max_rel = (int32_t)(t_max - t0 < span ? t_max - t0 : span);
     const int32_t every = (int32_t)(check_every < span ? check_every : span);
     int32_t rel = 0;
-    Eval<M>::scan(dm, par, st, t0, t1, [&](int64_t, double lp) {
+    Eval<M>::scan_y(dm, ydata, par, st, t0, t1, [&](int64_t, double lp) {
       if (isnan(lp)) lp = -INFINITY;
       lw += lp;
       ++rel;
@@ -120,7 +121,8 @@ template <class M>
 __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
                                                 void *state, double *logw, double *loglik,
                                                 int64_t t0, int64_t t1, int32_t zero_first,
-                                                const int64_t *t1_dev) {
+                                                const int64_t *t1_dev,
+                                                const typename M::Y *__restrict__ ydata) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
   if (t1_dev) t1 = min(t1, *t1_dev);
@@ -134,7 +136,7 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
   R st[SR];
 #pragma unroll
   for (int k = 0; k < SR; ++k) st[k] = (k < SS) ? typed<R>(state)[k * P + p] : (R)0;
-  double lp = Eval<M>::advance(dm, par, st, t0, t1);
+  double lp = Eval<M>::advance_y(dm, ydata, par, st, t0, t1);
   if (isnan(lp)) lp = -INFINITY;
   logw[p] = (zero_first ? 0.0 : logw[p]) + lp;
   loglik[p] += lp;
@@ -223,7 +225,8 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
                                                   const double *__restrict__ hchol, uint64_t seed,
                                                   uint64_t run, uint64_t cycle, uint64_t iter,
                                                   unsigned long long *n_accept, uint8_t *accepted,
-                                                  MomFuse fm) {
+                                                  MomFuse fm,
+                                                  const typename M::Y *__restrict__ ydata) {
   constexpr int D = M::D;
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
@@ -272,7 +275,7 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
     double ll1 = -INFINITY;
     if (lp1 > -INFINITY) {
       const auto par = M::params(pr);
-      ll1 = Eval<M>::advance(dm, par, st, 0, t);
+      ll1 = Eval<M>::advance_y(dm, ydata, par, st, 0, t);
       const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]);
       const U64x4 w = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
       acc = (log(u01_oo(w.x0)) < delta) ? 1 : 0;
@@ -303,7 +306,8 @@ __global__ void __launch_bounds__(64) k_mutate_indep(DevModel dm, int64_t P, int
                                                      const double *__restrict__ mean,
                                                      uint64_t seed, uint64_t run, uint64_t cycle,
                                                      uint64_t iter, unsigned long long *n_accept,
-                                                     uint8_t *accepted) {
+                                                     uint8_t *accepted,
+                                                     const typename M::Y *__restrict__ ydata) {
   constexpr int D = M::D;
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
@@ -337,7 +341,7 @@ __global__ void __launch_bounds__(64) k_mutate_indep(DevModel dm, int64_t P, int
     double ll1 = -INFINITY;
     if (lp1 > -INFINITY) {
       const auto par = M::params(pr);
-      ll1 = Eval<M>::advance(dm, par, st, 0, t);
+      ll1 = Eval<M>::advance_y(dm, ydata, par, st, 0, t);
       const double delta =
           (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
       const U64x4 u = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
@@ -586,12 +590,13 @@ struct OpsOf {
   static smc_status cscan(const DevModel &m, int64_t P, const double *theta, const void *state,
                           const double *logw, int64_t t0, int64_t t1, int64_t check_every,
                           int64_t t_max, bool zero_first, double *W, hipStream_t s) {
+    const typename M::Y *yd = Eval<M>::host_y(m);
     if (check_every == 1)
       hipLaunchKernelGGL((k_cscan<M, true>), grid_for(P, 64), dim3(64), 0, s, m, P, theta, state,
-                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W);
+                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W, yd);
     else
       hipLaunchKernelGGL((k_cscan<M, false>), grid_for(P, 64), dim3(64), 0, s, m, P, theta, state,
-                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W);
+                         logw, t0, t1, check_every, t_max, (int32_t)zero_first, W, yd);
     return launch_status("correct/scan");
   }
 
@@ -599,7 +604,7 @@ struct OpsOf {
                             double *logw, double *loglik, int64_t t0, int64_t t1,
                             bool zero_first, const int64_t *t1_dev, hipStream_t s) {
     hipLaunchKernelGGL(k_ccommit<M>, grid_for(P, 64), dim3(64), 0, s, m, P, theta, state, logw,
-                       loglik, t0, t1, (int32_t)zero_first, t1_dev);
+                       loglik, t0, t1, (int32_t)zero_first, t1_dev, Eval<M>::host_y(m));
     return launch_status("correct/commit");
   }
 
@@ -614,14 +619,15 @@ struct OpsOf {
       if (M::D >= 32) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 32");
       fm = *fuse;
     }
+    const typename M::Y *yd = Eval<M>::host_y(m);
     if (timer)
       hipExtLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
                             timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
-                            run, cycle, iter, acc, accepted, fm);
+                            run, cycle, iter, acc, accepted, fm, yd);
     else
       hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
                          logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted,
-                         fm);
+                         fm, yd);
     return launch_status("mutate");
   }
 
@@ -631,14 +637,15 @@ struct OpsOf {
                                  uint64_t run, uint64_t cycle, uint64_t iter, int64_t *n_accept,
                                  uint8_t *accepted, const KernelTimer *timer, hipStream_t s) {
     auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
+    const typename M::Y *yd = Eval<M>::host_y(m);
     if (timer)
       hipExtLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
                             timer->stop, 0, m, P, t, theta, logprior, loglik, state, chol, mean,
-                            seed, run, cycle, iter, acc, accepted);
+                            seed, run, cycle, iter, acc, accepted, yd);
     else
       hipLaunchKernelGGL(k_mutate_indep<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
                          logprior, loglik, state, chol, mean, seed, run, cycle, iter, acc,
-                         accepted);
+                         accepted, yd);
     return launch_status("mutate/independent");
   }
 
