@@ -133,6 +133,11 @@ struct Egarch {
   static constexpr int D = 2 + 3 * K + (kT ? 1 : 0) + (kMix ? 3 * I : 0);
   static constexpr int S = K + 1;
   static constexpr int kNM = kMix ? I : 1;  // component arrays (unused if no mixture)
+  // FP32 Student-t shocks: the factors 1 + eps^2/(nu - 2) of two observations
+  // are multiplied before one log2 is taken (the log2 runs at a quarter of
+  // the FP32 rate).  A pair whose product exceeds the float range (shocks
+  // beyond about 1e9 standard deviations) counts as a zero density.
+  static constexpr bool kTPair = kT && sizeof(R_) == 4;
   using R = R_;
   using Y = R_;
 
@@ -364,26 +369,46 @@ struct Egarch {
       else return v;
     };
     const R z = fma(y, p.isig, -p.mus);
-    // the cross-factor sums start from the first factor's terms (an added
-    // zero would cost an instruction each)
+    // The next exponent sum.  FP64 forms it as one fma from the factors'
+    // bracket and constant sums, which keeps the loop-carried chain at an
+    // exp2 and an fma.  The FP32 loop is bound by instruction issue (the
+    // exp2 and log2 run at a quarter of the rate), so it adds the new
+    // exponents instead: K - 1 additions in place of 2K - 1 operations, at
+    // the cost of one more dependent addition on the chain.  (The sums
+    // start from the first factor's terms; an added zero would cost an
+    // instruction.)
+    constexpr bool kSumW = sizeof(R) == 4;
     R kk, AA;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
       const R A = fma(p.a[k], r.w[k], p.c0[k]);
       const R kz = fma(p.kb[k], fabs(z), p.kg[k] * z);
       r.w[k] = fma(scaled(kz), Ef, A);
-      if (k == 0) {
-        kk = kz;
-        AA = A;
-      } else {
-        kk += kz;
-        AA += A;
+      if constexpr (!kSumW) {
+        if (k == 0) {
+          kk = kz;
+          AA = A;
+        } else {
+          kk += kz;
+          AA += A;
+        }
       }
     }
-    r.sw = (K > 1) ? fma(scaled(kk), Ef, AA) : r.w[0];
+    if constexpr (K == 1) {
+      r.sw = r.w[0];
+    } else if constexpr (kSumW) {
+      R sw1 = r.w[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) sw1 += r.w[k];
+      r.sw = sw1;
+    } else {
+      r.sw = fma(scaled(kk), Ef, AA);
+    }
     const R e = scaled(z) * Ef;
     const R E = scaled(Ef);
-    if constexpr (kT) {
+    if constexpr (kTPair) {
+      pm *= fma(e * e, p.inu2, (R)1);  // the caller takes the log2 (see kTPair)
+    } else if constexpr (kT) {
       ae += t_term(e * e, p.inu2);
     } else if constexpr (kMix) {
       R x[I];
@@ -445,6 +470,7 @@ struct Egarch {
       for (int k = 0; k < K; ++k) wl[k] = r.w[k];
       R ae = (R)0, pm = (R)1;
       const R sw = step(p, yv, r, ae, pm, E, z);
+      if constexpr (kTPair) ae = log2_fast(pm);
       double ld;
       if constexpr (kT) ld = base + kLn2 * (double)sw - p.hnu1 * t_scale<R>() * (double)ae;
       else if constexpr (kMix) ld = base + kLn2 * ((double)sw + (double)ae + (double)log2_fast(pm));
@@ -536,6 +562,12 @@ struct Egarch {
           const int pos = (G > 1 ? (b % G) * U : 0) + (i % kAcc);
           if (pos == 0) av = sw;
           else av += sw;
+          if constexpr (kTPair) {
+            if (pos & 1) {
+              ae += log2_fast(pm);
+              pm = (R)1;
+            }
+          }
           if (pos == kAcc - 1) flush();
         }
 #pragma unroll
@@ -547,15 +579,25 @@ struct Egarch {
       R yb[kAcc];
 #pragma unroll
       for (int i = 0; i < kAcc; ++i) yb[i] = yp[i];
-      R Ed, zd;
-      av = step(p, yb[0], r, ae, pm, Ed, zd);
 #pragma unroll
-      for (int i = 1; i < kAcc; ++i) av += step(p, yb[i], r, ae, pm, Ed, zd);
+      for (int i = 0; i < kAcc; ++i) {
+        R Ed, zd;
+        const R sw = step(p, yb[i], r, ae, pm, Ed, zd);
+        if (i == 0) av = sw;
+        else av += sw;
+        if constexpr (kTPair) {
+          if (i & 1) {
+            ae += log2_fast(pm);
+            pm = (R)1;
+          }
+        }
+      }
       flush();
     }
     for (int i = nb * kAcc; i < nm; ++i, ++yp) {
       R ae1 = (R)0, pm1 = (R)1, Ed, zd;
       const R av1 = step(p, *yp, r, ae1, pm1, Ed, zd);
+      if constexpr (kTPair) ae1 = log2_fast(pm1);
       sv += (double)av1;
       se += (double)ae1;
       if constexpr (kMix) se += (double)log2_fast(pm1);
@@ -566,6 +608,7 @@ struct Egarch {
     for (int k = 0; k < K; ++k) wl[k] = r.w[k];
     R ae1 = (R)0, pm1 = (R)1, E, z;
     const R av1 = step(p, *yp, r, ae1, pm1, E, z);
+    if constexpr (kTPair) ae1 = log2_fast(pm1);
     sv += (double)av1;
     se += (double)ae1;
     if constexpr (kMix) se += (double)log2_fast(pm1);
