@@ -3,18 +3,23 @@
 
 A step is one whole adaptive run of the simulator (prior draw, C/S/M cycles
 to T with the Section 3.3 rules, marginal likelihood) on a synthetic
-workload resident in HBM.  `value` is particle x observation log-likelihood
-evaluations per second over the K timed steps (C-phase and M-phase
-evaluations, divided by wall time including every host decision).
+workload resident in HBM.  The headline workload is the EGARCH model with two
+volatility factors and Student-t(8) shocks, T = 10,000, 64 groups of 1,024
+particles, FP32 likelihood recursion with FP64 weights, log-sum-exp and
+moments.  `value` is particle x observation log-likelihood evaluations per
+second over the K timed steps (C-phase and M-phase evaluations, divided by
+wall time including every host decision).
 
 The roofline object describes the dominant kernel (the Metropolis mutation
-kernel): algorithmic VALU lane-operations per particle-observation times the
-evaluations of each launch, divided by the launch durations measured with
-HIP events on the launch stream inside the timed region.
+kernel): algorithmic VALU lane-operations per particle-observation (the
+counts of the hot-path scope table, and the builder's own counts beside
+them) times the evaluations of each launch, divided by the launch durations
+measured with HIP events on the launch stream inside the timed region.
 
 The cpu_baseline object times the oracle (plain FP64 C, OpenMP over
-particles) on a bounded sample of the same work: its Metropolis step over a
-sample of particles at t = T.
+particles) on a bounded sample of the same work: its Metropolis step over
+4,096 particles at t = T on every host core, with likelihood-throughput legs
+at the EGARCH(1,1) and EGARCH(2)-t shapes on one core and on all of them.
 """
 from __future__ import annotations
 
@@ -53,6 +58,7 @@ def mixture_ops(K, I, exp_cost):
     return rec + mix + (1 + I) * exp_cost
 
 
+# The builder's counts of the kernels' algorithmic work (see above).
 OPS_PER_EVAL = {
     ("linreg", "fp64"): 4,
     ("egarch23", "fp64"): mixture_ops(2, 3, 17),
@@ -62,6 +68,23 @@ OPS_PER_EVAL = {
     ("egarch2t", "fp64"): 10 + 17 + 3 + 17,
     ("egarch2t", "fp32"): 10 + 1 + 4 + 3 + 4,
 }
+
+# Algorithmic VALU lane-slots per particle-observation from the hot-path
+# scope table (a transcendental = 4 slots); None where it gives no figure.
+OPS_SCOPE = {
+    ("linreg", "fp64"): 4,
+    ("egarch11", "fp64"): 29,
+    ("egarch11", "fp32"): 14,
+    ("egarch2t", "fp32"): 25,
+}
+
+
+def ops_for(name, precision):
+    """(count used for the roofline, its source, the builder's count)."""
+    b = OPS_PER_EVAL[(name, precision)]
+    s = OPS_SCOPE.get((name, precision))
+    return (s, "scope table", b) if s is not None else (b, "builder", b)
+
 
 DESCR = {
     "linreg": "conjugate Gaussian regression, k=3, T=200, J=4 x N=256",
@@ -116,9 +139,14 @@ def sources_sha256():
     return h.hexdigest()
 
 
-def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55), seed=1):
-    """Wall time of one whole adaptive run at the smallest Rbar on the
-    Fibonacci ladder (as in the paper's Table 3) whose log-ML NSE <= target."""
+def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55),
+                seeds=(1, 2, 3)):
+    """Wall time to a log-ML with NSE <= target, as in the paper's Table 3:
+    for each seed, whole adaptive runs climb the Fibonacci ladder of Rbar
+    until one reaches the target; that run's seconds, NSE and precision per
+    time 1/(NSE^2 s) are kept.  One untimed run first (kernel load, first
+    launches).  Returns the per-seed results and their mean and sd."""
+    import numpy as np
     import torch
 
     import paper_1304_4334_amd as S
@@ -129,25 +157,42 @@ def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 
     kern = S.SMC_KERNEL_MALA if kernel == "mala" else S.SMC_KERNEL_RW
     m = S.Model.from_workload(w, precision=prec)
     pop = S.Population(m, w.J, w.N, max_chunk=1024, with_grad=kern == S.SMC_KERNEL_MALA)
-    tried = []
-    for Rbar in ladder:
-        rec = S.Record(m, w.J, Lmax=2048, RmaxRec=3 * Rbar + 1)
-        torch.cuda.synchronize()
-        t0 = time.perf_counter()
-        S.smc_run(m, pop, seed=seed, Rbar=Rbar, kernel=kern, record=rec)
-        torch.cuda.synchronize()
-        el = time.perf_counter() - t0
-        s = rec.summary()
-        tried.append(dict(Rbar=Rbar, secs=el, nse=s["nse"], log_ml=s["log_ml"],
-                          mh_steps=s["mh_steps"]))
-        log(f"[bench] time-to-NSE {name}/{precision}/{kernel} Rbar={Rbar}: {el:.3f} s, "
-            f"NSE {s['nse']:.4f}")
-        if s["nse"] <= target:
-            return dict(kernel=kernel, precision=precision, Rbar=Rbar, secs=el, nse=s["nse"],
-                        log_ml=s["log_ml"], precision_per_time=1.0 / (s["nse"] ** 2 * el),
-                        ladder=tried)
-    return dict(kernel=kernel, precision=precision, Rbar=None, secs=None, nse=None,
-                ladder=tried)
+    S.smc_run(m, pop, seed=900, Rbar=ladder[0], kernel=kern,
+              record=S.Record(m, w.J, Lmax=2048, RmaxRec=3 * ladder[0] + 1))
+    torch.cuda.synchronize()
+    per_seed = []
+    for seed in seeds:
+        tried = []
+        hit = None
+        for Rbar in ladder:
+            rec = S.Record(m, w.J, Lmax=2048, RmaxRec=3 * Rbar + 1)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            S.smc_run(m, pop, seed=seed, Rbar=Rbar, kernel=kern, record=rec)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            s = rec.summary()
+            tried.append(dict(Rbar=Rbar, secs=el, nse=s["nse"], log_ml=s["log_ml"],
+                              mh_steps=s["mh_steps"]))
+            log(f"[bench] time-to-NSE {name}/{precision}/{kernel} seed {seed} Rbar={Rbar}: "
+                f"{el:.3f} s, NSE {s['nse']:.4f}")
+            if s["nse"] <= target:
+                hit = dict(seed=seed, Rbar=Rbar, secs=el, nse=s["nse"], log_ml=s["log_ml"],
+                           precision_per_time=1.0 / (s["nse"] ** 2 * el),
+                           ladder_secs=sum(x["secs"] for x in tried))
+                break
+        per_seed.append(hit if hit else dict(seed=seed, Rbar=None, ladder=tried))
+    ok = [x for x in per_seed if x.get("Rbar")]
+
+    def ms(key):
+        v = np.array([x[key] for x in ok], dtype=np.float64)
+        return (float(v.mean()), float(v.std(ddof=1)) if len(v) > 1 else 0.0) if len(v) else (None, None)
+
+    out = dict(kernel=kernel, precision=precision, batched=False, seeds=list(seeds),
+               reached=len(ok), per_seed=per_seed)
+    for key in ("secs", "nse", "precision_per_time", "Rbar"):
+        out[key + "_mean"], out[key + "_sd"] = ms(key)
+    return out
 
 
 def run_gpu(name, precision, steps, warmup):
@@ -196,18 +241,23 @@ def run_gpu(name, precision, steps, warmup):
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     secs = t1 - t0
-    ops = OPS_PER_EVAL[(name, precision)]
-    achieved = ops * mut_evals / (mut_ms * 1e-3) / 1e12
+    ops, src, ops_b = ops_for(name, precision)
+    rate = mut_evals / (mut_ms * 1e-3)
+    achieved = ops * rate / 1e12
     occupied = min(1.0, math.ceil(w.P / 64) / N_SIMD)
     return dict(
         w=w, value=evals / secs, ms_per_step=1e3 * secs / steps, evals_per_step=evals / steps,
         log_ml=float(np.mean(log_mls)), nse=float(np.mean(nses)), cycles=float(np.mean(cycles)),
         mh_steps=float(np.mean(msteps)), mutate_avg_ms=mut_ms / max(n_launch, 1),
-        mutate_launches=n_launch, mutate_evals_per_s=mut_evals / (mut_ms * 1e-3),
+        mutate_launches=n_launch, mutate_evals_per_s=rate,
+        mutate_avg_t=mut_evals / max(n_launch, 1) / w.P,
         roofline=dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS,
                       unit="T VALU lane-ops/s", frac=achieved / VALU_PEAK_TOPS,
-                      traffic=measured_traffic(name, precision), traffic_unit="bytes per launch at t=T",
-                      kernel="k_mutate_rw", ops_per_eval=ops,
+                      traffic=measured_traffic(name, precision),
+                      traffic_unit="bytes per launch at t=T",
+                      kernel="k_mutate_rw", ops_per_eval=ops, ops_source=src,
+                      ops_per_eval_builder=ops_b,
+                      frac_builder_ops=ops_b * rate / 1e12 / VALU_PEAK_TOPS,
                       simd_occupancy=occupied,
                       frac_of_occupied=achieved / (VALU_PEAK_TOPS * occupied)),
         secs=secs)
@@ -216,7 +266,9 @@ def run_gpu(name, precision, steps, warmup):
 def run_batched(steps):
     """The batched workload: 32 independent adaptive runs (EGARCH(1,1)-N and
     EGARCH(2)-t alternating, T in [1000, 20000], J*N in 4096..65536), FP32
-    recursion, one persistent M-step launch per batch step."""
+    recursion, one persistent M-step launch per batch step.  The roofline
+    adds, over the timed persistent launches, each run's evaluations times
+    its model's algorithmic count, over the launches' summed durations."""
     import torch
 
     import paper_1304_4334_amd as S
@@ -230,17 +282,34 @@ def run_batched(steps):
     S.smc_run_batch(models, pops, list(range(100, 132)), waves=waves, Lmax=2048, RmaxRec=64)
     torch.cuda.synchronize()
     evals = 0
+    ms_sum, lane_ops, m_evals, launches = 0.0, 0.0, 0, 0
+    o1, _, _ = ops_for("egarch11", "fp32")
+    o2, _, _ = ops_for("egarch2t", "fp32")
     t0 = time.perf_counter()
     for k in range(steps):
-        recs = S.smc_run_batch(models, pops, [1 + 32 * k + i for i in range(32)], waves=waves,
-                               Lmax=2048, RmaxRec=64)
+        recs, tim = S.smc_run_batch(models, pops, [1 + 32 * k + i for i in range(32)],
+                                    waves=waves, Lmax=2048, RmaxRec=64, timing=8192)
         evals += sum(r.c.evals for r in recs)
+        ms_sum += sum(tim["ms"])
+        launches += len(tim["ms"])
+        for e1, e2 in tim["evals"]:
+            lane_ops += o1 * e1 + o2 * e2
+            m_evals += e1 + e2
         log(f"[bench] batched step {k + 1}/{steps} done")
     torch.cuda.synchronize()
     secs = time.perf_counter() - t0
+    achieved = lane_ops / (ms_sum * 1e-3) / 1e12
     return dict(value=evals / secs, ms_per_step=1e3 * secs / steps, runs=len(specs),
                 total_particles=sum(w.P for w in specs), waves=waves,
-                evals_per_step=evals / steps)
+                evals_per_step=evals / steps,
+                mutate_launches_per_step=launches / steps,
+                mutate_ms_per_step=ms_sum / steps,
+                mutate_evals_per_s=m_evals / (ms_sum * 1e-3),
+                roofline=dict(bound="alu", achieved=achieved, peak=VALU_PEAK_TOPS,
+                              unit="T VALU lane-ops/s", frac=achieved / VALU_PEAK_TOPS,
+                              traffic=None, kernel="k_batch_mutate",
+                              ops_per_eval={"egarch11_fp32": o1, "egarch2t_fp32": o2},
+                              ops_source="scope table"))
 
 
 def run_variants(name, precision, steps):
@@ -319,23 +388,52 @@ def run_variants(name, precision, steps):
     return out
 
 
-def cpu_baseline(name, seconds):
+def _host_info():
+    model = "unknown"
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    try:
+        aff = sorted(os.sched_getaffinity(0))
+    except AttributeError:
+        aff = list(range(os.cpu_count() or 1))
+    return dict(cpu_model=model, nproc=os.cpu_count(), affinity_cpus=len(aff),
+                affinity=f"{aff[0]}-{aff[-1]}" if aff else "")
+
+
+def _oracle_pop(O, SD, w, om, P, seed):
+    pop = O.Pop(om, 2, P // 2)
+    pop.theta[:] = SD.random_thetas(w, P, seed, spread=0.01)
+    for p in range(P):
+        pop.logprior[p] = O.logprior(om, pop.theta[p])
+    return pop
+
+
+def cpu_baseline(name, seconds, legs=True):
+    """The oracle (FP64 C, OpenMP over particles, the host's cores) on a
+    bounded sample of the workload: its random-walk Metropolis step over
+    4,096 particles at t = T, repeated for about `seconds`; with `legs`, the
+    likelihood throughput at the EGARCH(1,1) and EGARCH(2)-t shapes on one
+    thread and on every allowed thread."""
     import numpy as np
 
     import oracle as O
     import synthdata as SD
 
+    info = _host_info()
+    n_all = max(1, info["affinity_cpus"])
+    O.set_num_threads(n_all)
     w = SD.workload(name)
     om = O.Model.from_workload(w)
-    Ps = 1024
-    rng = np.random.default_rng(0)
-    pop = O.Pop(om, 2, Ps // 2)
-    pop.theta[:] = SD.random_thetas(w, Ps, 3, spread=0.02)
-    for p in range(Ps):
-        pop.logprior[p] = O.logprior(om, pop.theta[p])
+    Ps = 4096
+    pop = _oracle_pop(O, SD, w, om, Ps, 3)
     pop.loglik[:] = O.loglik_batch(om, pop.theta, w.T)[0]
     hl = np.linalg.cholesky(np.cov(pop.theta.T)) * 0.5
-    del rng
     iters = 0
     t0 = time.perf_counter()
     while True:
@@ -345,9 +443,28 @@ def cpu_baseline(name, seconds):
         if el >= seconds:
             break
     rate = iters * Ps * w.T / el
-    return dict(value=rate, unit="particle·obs/s", cores=O.num_threads(), kind="oracle",
-                sample=(f"oracle RW Metropolis step (FP64) over {Ps} particles at t=T={w.T}, "
-                        f"{iters} iterations in {el:.1f} s"))
+    out = dict(value=rate, unit="particle·obs/s", cores=O.num_threads(), kind="oracle",
+               sample=(f"oracle RW Metropolis step (FP64) on the {name} workload over {Ps} "
+                       f"particles at t=T={w.T}, {iters} iterations in {el:.1f} s on "
+                       f"{O.num_threads()} threads"), host=info)
+    log(f"[bench] cpu baseline {name}: {rate:.3e} particle-obs/s on {O.num_threads()} threads")
+    if legs:
+        out["loglik_legs"] = {}
+        for lname in ("egarch11", "egarch2t"):
+            lw = SD.workload(lname)
+            lom = O.Model.from_workload(lw)
+            th = SD.random_thetas(lw, 4096, 7, spread=0.01)
+            for nthr, P in ((1, 256), (n_all, 4096)):
+                O.set_num_threads(nthr)
+                t0 = time.perf_counter()
+                O.loglik_batch(lom, th[:P], lw.T)
+                el = time.perf_counter() - t0
+                key = f"{lname}_{'1thread' if nthr == 1 else 'all'}"
+                out["loglik_legs"][key] = dict(value=P * lw.T / el, particles=P, T=lw.T,
+                                               threads=nthr, secs=el)
+                log(f"[bench] oracle loglik {key}: {P * lw.T / el:.3e} particle-obs/s")
+        O.set_num_threads(n_all)
+    return out
 
 
 def kernel_probe():
@@ -391,15 +508,17 @@ def main():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
-    ap.add_argument("--workload", default="egarch11", choices=sorted(DESCR))
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"])
-    ap.add_argument("--no-fp32", action="store_true", help="skip the FP32-recursion companion run")
+    ap.add_argument("--workload", default="egarch2t", choices=sorted(DESCR))
+    ap.add_argument("--precision", default=None, choices=["fp64", "fp32"],
+                    help="recursion precision (default: fp32 for egarch2t, else fp64)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--cpu-seconds", type=float, default=10.0)
     ap.add_argument("--kernel-probe", action="store_true",
                     help="run only the short fixed sequence used for counter passes")
+    ap.add_argument("--batch-probe", action="store_true",
+                    help="run only one adaptive batch of the batched workload (for profiles)")
     ap.add_argument("--no-companions", action="store_true",
-                    help="skip the EGARCH(2)-t and egarch_23 runs and the time-to-NSE comparison")
+                    help="skip the companion workloads, the batch and the time-to-NSE comparison")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py runs on one GPU only (asked for --gpus {args.gpus}): the library has no "
@@ -411,21 +530,23 @@ def main():
     if args.kernel_probe:
         kernel_probe()
         return
+    if args.batch_probe:
+        print(json.dumps(run_batched(1)), flush=True)
+        return
+    precision = args.precision or ("fp32" if args.workload == "egarch2t" else "fp64")
 
-    main_run = run_gpu(args.workload, args.precision, args.steps, args.warmup)
-    companion = None
-    if not args.no_fp32 and args.precision == "fp64" and args.workload != "linreg":
-        companion = run_gpu(args.workload, "fp32", args.steps, args.warmup)
-    roof2t = tnse = batched = variants = None
-    mix = {}
-    if not args.no_companions and args.workload == "egarch11":
-        batched = run_batched(2)
-        roof2t = run_gpu("egarch2t", "fp32", max(2, min(args.steps, 3)), 1)
+    main_run = run_gpu(args.workload, precision, args.steps, args.warmup)
+    comp = {}
+    tnse = batched = variants = None
+    if not args.no_companions and args.workload == "egarch2t":
+        for prec in ("fp64", "fp32"):
+            comp[f"egarch11_{prec}"] = run_gpu("egarch11", prec, args.steps, args.warmup)
         for prec in ("fp32", "fp64"):
-            mix[prec] = run_gpu("egarch23", prec, 2, 1)
-        tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "mala"),
-                time_to_nse("egarch2t", "fp32", "rw")]
-        variants = run_variants(args.workload, args.precision, 2)
+            comp[f"egarch23_{prec}"] = run_gpu("egarch23", prec, 2, 1)
+        batched = run_batched(2)
+        tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "rw"),
+                time_to_nse("egarch2t", "fp32", "mala")]
+        variants = run_variants("egarch11", "fp64", 2)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
 
     w = main_run["w"]
@@ -440,12 +561,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64" if args.precision == "fp64" else "f32",
+        "dtype": "f64" if precision == "fp64" else "f32",
         "data": "synthetic",
         "config": {"workload": f"{args.workload}: {DESCR[args.workload]}, RW-Metropolis, "
-                               "adaptive C/S/M (D1=0.5, D2=0.2, Rbar=7, kappa=3), residual "
-                               "resampling",
-                   "J": w.J, "N": w.N, "T": w.T, "precision": args.precision,
+                               f"adaptive C/S/M (D1=0.5, D2=0.2, Rbar=7, kappa=3), residual "
+                               f"resampling, {precision.upper()} likelihood recursion, FP64 "
+                               "weights, log-sum-exp, covariance and Cholesky",
+                   "J": w.J, "N": w.N, "T": w.T, "precision": precision,
                    "parallelism": "single GPU"},
         "roofline": main_run["roofline"],
         "cpu_baseline": cpu,
@@ -453,42 +575,31 @@ def main():
                 "cycles": main_run["cycles"], "mh_steps": main_run["mh_steps"],
                 "evals_per_step": main_run["evals_per_step"],
                 "mutate_avg_ms": main_run["mutate_avg_ms"],
+                "mutate_avg_t": main_run["mutate_avg_t"],
                 "mutate_launches": main_run["mutate_launches"],
                 "mutate_evals_per_s": main_run["mutate_evals_per_s"]},
     }
-    if companion is not None:
-        out["fp32"] = {"value": companion["value"], "ms_per_step": companion["ms_per_step"],
-                       "log_ml": companion["log_ml"], "nse": companion["nse"],
-                       "mutate_avg_ms": companion["mutate_avg_ms"],
-                       "mutate_evals_per_s": companion["mutate_evals_per_s"],
-                       "roofline": companion["roofline"]}
-    if roof2t is not None:
-        out["egarch2t_fp32"] = {
-            "workload": "egarch2t: " + DESCR["egarch2t"] + ", RW, FP32 recursion, FP64 weights",
-            "value": roof2t["value"], "ms_per_step": roof2t["ms_per_step"],
-            "log_ml": roof2t["log_ml"], "nse": roof2t["nse"],
-            "mutate_avg_ms": roof2t["mutate_avg_ms"],
-            "mutate_evals_per_s": roof2t["mutate_evals_per_s"], "roofline": roof2t["roofline"]}
-    for prec, r in mix.items():
-        out[f"egarch23_{prec}"] = {
-            "workload": DESCR["egarch23"] + f", RW, {prec.upper()} recursion, FP64 weights",
-            "value": r["value"], "ms_per_step": r["ms_per_step"], "log_ml": r["log_ml"],
-            "nse": r["nse"], "cycles": r["cycles"], "mh_steps": r["mh_steps"],
-            "mutate_avg_ms": r["mutate_avg_ms"], "mutate_evals_per_s": r["mutate_evals_per_s"],
-            "roofline": r["roofline"]}
+    for key, r in comp.items():
+        name, prec = key.split("_")
+        out[key] = {"workload": f"{name}: {DESCR[name]}, RW, {prec.upper()} recursion, FP64 weights",
+                    "value": r["value"], "ms_per_step": r["ms_per_step"], "log_ml": r["log_ml"],
+                    "nse": r["nse"], "cycles": r["cycles"], "mh_steps": r["mh_steps"],
+                    "mutate_avg_ms": r["mutate_avg_ms"], "mutate_avg_t": r["mutate_avg_t"],
+                    "mutate_evals_per_s": r["mutate_evals_per_s"], "roofline": r["roofline"]}
     if batched is not None:
         out["batched"] = dict(batched, workload="32 independent adaptive runs: EGARCH(1,1)-N / "
                               "EGARCH(2)-t alternating, T in [1000, 20000], J=16, J*N in "
                               "4096..65536, FP32 recursion, RW")
     if tnse is not None:
         out["time_to_nse_0.05"] = {
-            "workload": "egarch2t: " + DESCR["egarch2t"] + ", adaptive, deterministic Rbar ladder",
+            "workload": "egarch2t: " + DESCR["egarch2t"] + ", adaptive, Fibonacci Rbar ladder, "
+                        "3 seeds, after one untimed run",
             "runs": tnse}
     if variants is not None:
-        out["variants"] = dict(variants, workload=f"{args.workload}: {DESCR[args.workload]}, "
-                               f"{args.precision.upper()} recursion; defaults otherwise")
+        out["variants"] = dict(variants, workload=f"egarch11: {DESCR['egarch11']}, FP64 "
+                               "recursion; defaults otherwise")
     if cpu is not None:
-        out["gpu_over_cpu"] = main_run["mutate_evals_per_s"] / cpu["value"]
+        out["gpu_over_cpu"] = main_run["value"] / cpu["value"]
     print(json.dumps(out), flush=True)
 
 

@@ -373,6 +373,16 @@ smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_
 /* Device workspace bytes of a batch of n_runs runs (1..32). */
 size_t smc_batch_ws_bytes(int32_t n_runs);
 
+/* Optional timing of a batch's persistent M-step launches: each launch
+ * carries HIP start and stop events on its own dispatch.  Host arrays. */
+typedef struct {
+  int32_t capacity; /* in: entries of ms (and pairs of evals) */
+  int32_t launches; /* out: launches recorded (at most capacity; later ones untimed) */
+  float *ms;        /* [capacity]: duration of each launch in ms */
+  int64_t *evals;   /* [capacity][2]: the launch's particle x observation evaluations,
+                       by EGARCH(1) Gaussian runs and by EGARCH(2) Student-t runs */
+} smc_batch_timing;
+
 /* Runs n independent simulators (each with its own model, population and
  * workspace, configuration and record, as for smc_run) together.  The runs
  * must share one recursion precision, use EGARCH(1) Gaussian or EGARCH(2)
@@ -385,11 +395,15 @@ size_t smc_batch_ws_bytes(int32_t n_runs);
  * host synchronisation.  `waves` is the number of persistent waves (0 =
  * 2048).  bws: device, >= smc_batch_ws_bytes(n), 256-byte aligned.  A replay
  * batch never synchronises the stream (capturable in a graph); an adaptive
- * one synchronises once per batch step that evaluates C-phase chunks.  Each
- * run's results equal those of smc_run with the same arguments. */
+ * one synchronises once per batch step that evaluates C-phase chunks, and
+ * stops with SMC_E_NUMERIC at the first such readback after a run raised a
+ * numerical flag.  timing may be NULL (when given, the call synchronises at
+ * its end to read the events).  Each run's results equal those of smc_run
+ * with the same arguments. */
 smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particles *const *pops,
                          const smc_run_config *cfgs, smc_run_record *recs, void *bws,
-                         size_t bws_bytes, int32_t waves, void *stream);
+                         size_t bws_bytes, int32_t waves, smc_batch_timing *timing,
+                         void *stream);
 
 /* --- diagnostics ------------------------------------------------------- */
 const char *smc_status_string(smc_status s);

@@ -133,6 +133,11 @@ def num_threads():
     return int(lib().orc_num_threads())
 
 
+def set_num_threads(n):
+    """Threads of the oracle's particle loops (timing only)."""
+    lib().orc_set_num_threads(C.c_int(int(n)))
+
+
 def run_hybrid(m: Model, J, N, seed, seed2, **kw):
     """Algorithm 3: an adaptive run (key (seed, run)), then Algorithm 1 on its
     design {t_l, hL_lr, R_l} with the new key (seed2, run).  Returns

@@ -40,6 +40,15 @@ int orc_num_threads(void) {
   return 1;
 #endif
 }
+/* Sets the threads of the OpenMP particle loops (for timing the oracle on
+ * one core or on all of them; results do not depend on it). */
+void orc_set_num_threads(int n) {
+#ifdef _OPENMP
+  if (n > 0) omp_set_num_threads(n);
+#else
+  (void)n;
+#endif
+}
 #define ORC_SMAX 8  /* largest recursion state handled */
 
 /* ------------------------------------------------------------------------ */

@@ -63,6 +63,10 @@ class RunRecord(C.Structure):
                 ("mutate_ms", _vp), ("moments", _vp), ("log_score", _vp), ("mean", _vp)]
 
 
+class BatchTiming(C.Structure):
+    _fields_ = [("capacity", C.c_int32), ("launches", C.c_int32), ("ms", _vp), ("evals", _vp)]
+
+
 _L = None
 
 
@@ -126,7 +130,7 @@ def lib():
         L.smc_batch_ws_bytes.argtypes = [C.c_int32]
         L.smc_run_batch.restype = st
         L.smc_run_batch.argtypes = [C.c_int32, P(_vp), P(P(Particles)), P(RunConfig), P(RunRecord),
-                                    _vp, C.c_size_t, C.c_int32, _vp]
+                                    _vp, C.c_size_t, C.c_int32, P(BatchTiming), _vp]
         L.smc_run.restype = st
         L.smc_run.argtypes = [_vp, P(Particles), P(RunConfig), P(RunRecord), _vp]
         L.smc_run_hybrid.restype = st
@@ -480,11 +484,15 @@ def hybrid_report(r1, r2, secs=None):
 
 def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, waves=0,
                   Rbar=7, kappa=3, D1=0.5, D2=0.2, Lmax=1024, RmaxRec=64, bws=None,
-                  stream=None):
+                  timing=0, stream=None):
     """Many runs together (see smc_run_batch in include/smc.h); returns the
     records.  With replay=True the records' designs are replayed.  `bws`
     (a device uint8 tensor of smc_batch_ws_bytes(n) + 256 bytes) may be
-    given to keep the batch workspace alive, e.g. across graph replays."""
+    given to keep the batch workspace alive, e.g. across graph replays.
+    With timing = k > 0 the first k persistent M-step launches are timed;
+    then (records, dict(ms=[...], evals=[[egarch1, egarch2t], ...])) is
+    returned."""
+    import numpy as np
     n = len(models)
     runs = runs if runs is not None else [0] * n
     if records is None:
@@ -504,9 +512,16 @@ def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, wa
     if bws is None:
         bws = torch.empty(nb + 256, dtype=torch.uint8, device=models[0].device)
     off = (-bws.data_ptr()) % 256
+    tms = np.zeros(max(timing, 1), dtype=np.float32)
+    tev = np.zeros((max(timing, 1), 2), dtype=np.int64)
+    tim = BatchTiming(timing, 0, tms.ctypes.data, tev.ctypes.data) if timing > 0 else None
     _check(lib().smc_run_batch(n, hs, ps, cfgs, recs, C.c_void_p(bws.data_ptr() + off), nb, waves,
-                               _stream(stream)), "smc_run_batch")
+                               C.byref(tim) if tim is not None else None, _stream(stream)),
+           "smc_run_batch")
     for i in range(n):
         records[i].c = recs[i]
         records[i].batch_ws = bws  # the stream may still read it
+    if tim is not None:
+        k = tim.launches
+        return records, dict(ms=tms[:k].astype(np.float64).tolist(), evals=tev[:k].tolist())
     return records

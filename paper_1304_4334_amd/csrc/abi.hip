@@ -117,6 +117,24 @@ DecisionSlot *decision_slot() {
   return buf;
 }
 
+// The calling thread's page-locked readback area for batched C phases, at
+// least n doubles; grown (reallocated) on demand and kept for the life of
+// the process; NULL if it cannot be had.
+double *batch_readback(size_t n) {
+  thread_local double *buf = nullptr;
+  thread_local size_t cap = 0;
+  if (cap < n) {
+    if (buf) (void)hipHostFree(buf);
+    buf = nullptr;
+    cap = 0;
+    void *p = nullptr;
+    if (hipHostMalloc(&p, n * sizeof(double), hipHostMallocDefault) != hipSuccess) return nullptr;
+    buf = static_cast<double *>(p);
+    cap = n;
+  }
+  return buf;
+}
+
 // An event (no timing) of the calling thread for the current device, marking
 // the completion of a copy back so the host can wait for it alone while
 // later work stays queued; kept for the life of the process.
@@ -923,8 +941,14 @@ size_t smc_batch_ws_bytes(int32_t n_runs) {
 
 smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particles *const *pops,
                          const smc_run_config *cfgs, smc_run_record *recs, void *bws,
-                         size_t bws_bytes, int32_t waves, void *stream) {
+                         size_t bws_bytes, int32_t waves, smc_batch_timing *timing,
+                         void *stream) {
   smc_status st;
+  if (timing) {
+    timing->launches = 0;
+    if (timing->capacity < 0 || (timing->capacity > 0 && (!timing->ms || !timing->evals)))
+      return set_error(SMC_E_INVALID_ARG, "batch timing arrays");
+  }
   if (n < 1 || n > kMaxBatch)
     return set_error(SMC_E_INVALID_ARG, "a batch holds 1..%d runs", kMaxBatch);
   if (!models || !pops || !cfgs || !recs || !bws)
@@ -1011,19 +1035,21 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         (st = smc_init_from_prior(models[i], pops[i], cfgs[i].rng, stream)))
       return st;
   }
-  // Pinned readback area of the adaptive C phases (a replay reads nothing
-  // back and allocates nothing, so it can be captured).
+  // Pinned readback area of the adaptive C phases: per run, the chunk's RSS
+  // columns followed by the run's flags word (a replay reads nothing back, so
+  // it can be captured).  One area per host thread, grown on demand and kept.
+  constexpr size_t kRow = kMaxChunk + 1;  // doubles per run
   double *host_rss = nullptr;
-  if (!replay &&
-      hipHostMalloc(reinterpret_cast<void **>(&host_rss), (size_t)n * kMaxChunk * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess)
+  if (!replay && !(host_rss = batch_readback((size_t)n * kRow)))
     return set_error(SMC_E_DEVICE, "pinned host buffer for the batch failed");
-  struct HostFree {
-    double *p;
-    ~HostFree() {
-      if (p) (void)hipHostFree(p);
-    }
-  } host_free{host_rss};
+  auto flags_of = [&](int i) -> int32_t * {
+    return reinterpret_cast<int32_t *>(host_rss + (size_t)i * kRow + kMaxChunk);
+  };
+  // per-launch timing of the persistent M step
+  struct Timed {
+    hipEvent_t a = nullptr, b = nullptr;
+  };
+  std::vector<Timed> timed;
 
   auto end_c_phase = [&](int i) -> smc_status {
     Run &u = run[i];
@@ -1105,9 +1131,11 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
             (st = launch_rss_cols(ws_at<double>(pop, L.wcols), P, (int64_t)u.dates.size(),
                                   ws_at<double>(pop, L.rsscols), s)))
           return st;
-        if (hipMemcpyAsync(host_rss + (size_t)i * kMaxChunk, ws_at<double>(pop, L.rsscols),
+        if (hipMemcpyAsync(host_rss + (size_t)i * kRow, ws_at<double>(pop, L.rsscols),
                            u.dates.size() * sizeof(double), hipMemcpyDeviceToHost,
-                           s) != hipSuccess)
+                           s) != hipSuccess ||
+            hipMemcpyAsync(flags_of(i), ws_at<int32_t>(pop, L.small + kSmallFlags),
+                           sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess)
           return set_error(SMC_E_DEVICE, "run %d: RSS readback failed", i);
         u.ph = kCPend;
         pend.push_back(i);
@@ -1155,7 +1183,28 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
       }
       ba.n_mut_items = mut;
       ba.n_mom_items = mom;
-      if ((st = launch_batch_m(ba, !replay, family, waves > 0 ? waves : 2048, s))) return st;
+      KernelTimer kt{};
+      const bool timed_launch = timing && timing->launches < timing->capacity;
+      if (timed_launch) {
+        const int32_t k = timing->launches;
+        timed.emplace_back();
+        if ((st = timing_event(2 * (size_t)k, &timed.back().a)) ||
+            (st = timing_event(2 * (size_t)k + 1, &timed.back().b)))
+          return st;
+        kt = KernelTimer{timed.back().a, timed.back().b};
+        int64_t e1 = 0, e2 = 0;
+        for (int i : act) {
+          const int64_t ev = (int64_t)pops[i]->J * pops[i]->N * run[i].t_new;
+          if (models[i]->dev.K == 1) e1 += ev;
+          else e2 += ev;
+        }
+        timing->evals[2 * k] = e1;
+        timing->evals[2 * k + 1] = e2;
+        timing->launches = k + 1;
+      }
+      if ((st = launch_batch_m(ba, !replay, family, waves > 0 ? waves : 2048, s,
+                               timed_launch ? &kt : nullptr)))
+        return st;
       for (int i : act) {
         Run &u = run[i];
         if (++u.r >= u.R) {
@@ -1180,7 +1229,14 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         const smc_model *m = models[i];
         smc_particles *pop = pops[i];
         const int64_t P = (int64_t)pop->J * pop->N;
-        const double *hr = host_rss + (size_t)i * kMaxChunk;
+        const double *hr = host_rss + (size_t)i * kRow;
+        // a run whose S or M phase raised a numerical flag stops the batch
+        // at its next C-phase readback, as smc_run stops
+        if (*flags_of(i)) {
+          recs[i].L = u.l;
+          return set_error(SMC_E_NUMERIC, "run %d: numerical flags 0x%x in cycle %d", i,
+                           *flags_of(i), u.l);
+        }
         const int64_t nc = (int64_t)u.dates.size();
         int64_t stop_col = -1;
         for (int64_t q = 0; q < nc; ++q)
@@ -1213,6 +1269,16 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
     recs[i].mh_steps = run[i].steps;
     if ((st = smc_log_ml(run[i].l, pops[i]->J, recs[i].group_logwbar, recs[i].log_ml, stream)))
       return st;
+  }
+  if (!timed.empty()) {
+    if (hipStreamSynchronize(s) != hipSuccess)
+      return set_error(SMC_E_DEVICE, "synchronising for the batch timings failed");
+    for (size_t k = 0; k < timed.size(); ++k) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, timed[k].a, timed[k].b) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "reading a batch timing failed");
+      timing->ms[k] = ms;
+    }
   }
   if (!replay) {
     // numerical flags of every run (adaptive batches synchronise anyway)

@@ -53,8 +53,10 @@ struct BatchStaticArgs {
   BatchStatic src[kMaxBatch];
 };
 
+// timer (may be NULL): start and stop events carried by the persistent
+// launch's own dispatch.
 smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int32_t waves,
-                          hipStream_t s);
+                          hipStream_t s, const KernelTimer *timer = nullptr);
 smc_status launch_batch_static(const BatchStaticArgs &a, hipStream_t s);
 
 }  // namespace smc

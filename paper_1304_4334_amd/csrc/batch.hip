@@ -11,6 +11,7 @@
 // once per batch call; what changes from step to step (date, cycle,
 // iteration, record slots) travels by value in the kernel arguments, so a
 // batch with no host decisions (replay) can be captured in a graph.
+#include <hip/hip_ext.h>
 #include <hip/hip_runtime.h>
 
 #include "batch.h"
@@ -203,7 +204,7 @@ __global__ void k_batch_queue_reset(unsigned int *q) {
 }
 
 smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int32_t waves,
-                          hipStream_t s) {
+                          hipStream_t s, const KernelTimer *timer) {
   smc_status st;
   if (a.n_active <= 0) return SMC_OK;
   if (moments) {
@@ -215,12 +216,17 @@ smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int3
   hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, s, a.queue);
   if ((st = launch_ok("batch/queue reset"))) return st;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(a.n_mut_items, waves));
+  auto go = [&](auto kern) {
+    if (timer)
+      hipExtLaunchKernelGGL(kern, grid_of(blocks), dim3(64), 0, s, timer->start, timer->stop, 0,
+                            a);
+    else
+      hipLaunchKernelGGL(kern, grid_of(blocks), dim3(64), 0, s, a);
+  };
   if (family == kFamilyFp32)
-    hipLaunchKernelGGL((k_batch_mutate<Egarch<1, 0, float>, Egarch<2, 1, float>>), grid_of(blocks),
-                       dim3(64), 0, s, a);
+    go(k_batch_mutate<Egarch<1, 0, float>, Egarch<2, 1, float>>);
   else
-    hipLaunchKernelGGL((k_batch_mutate<Egarch<1, 0, double>, Egarch<2, 1, double>>),
-                       grid_of(blocks), dim3(64), 0, s, a);
+    go(k_batch_mutate<Egarch<1, 0, double>, Egarch<2, 1, double>>);
   return launch_ok("batch/mutate");
 }
 

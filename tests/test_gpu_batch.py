@@ -81,3 +81,22 @@ def test_batch_replay_in_a_graph():
         for i in range(3):
             assert torch.equal(design[i].log_ml, want_ml[i]), rep
             assert torch.equal(pops[i].theta, want_th[i]), rep
+
+
+def test_batch_timing_accounts_for_every_m_step():
+    """The timed persistent launches carry every M-step evaluation of the
+    batch once: their evaluation counts add up to sum_l R_l P t_l over the
+    runs, split by model family."""
+    runs = _runs(S.SMC_FP32, SPECS)
+    models = [m for _, m, _ in runs]
+    pops = [p for _, _, p in runs]
+    recs, tim = S.smc_run_batch(models, pops, [31, 32, 33, 34], Lmax=400, RmaxRec=64,
+                                timing=4096)
+    assert len(tim["ms"]) > 10 and all(ms > 0 for ms in tim["ms"])
+    want = [0, 0]
+    for (w, m, p), r in zip(runs, recs):
+        s = r.summary()
+        want[0 if w.K == 1 else 1] += sum(int(s["R"][l]) * w.J * w.N * int(s["t_end"][l])
+                                          for l in range(s["L"]))
+    got = np.array(tim["evals"]).sum(axis=0).tolist()
+    assert got == want
