@@ -195,6 +195,70 @@ def time_to_nse(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 
     return out
 
 
+def time_to_nse_batched(name, precision, kernel, target=0.05, ladder=(5, 8, 13, 21, 34, 55),
+                        seed_sets=((1, 2, 3), (4, 5, 6), (7, 8, 9))):
+    """The same criterion for B independent runs advanced together in one
+    batch (one persistent M-step launch per batch step): their J groups are
+    pooled into one estimate of the marginal likelihood with B*J groups
+    (eq ML_se over all of them, computed by smc_log_ml from the groups'
+    summed log weights), and the ladder is climbed until its NSE <= target.
+    The seconds are the whole batch call's."""
+    import numpy as np
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+
+    w = SD.workload(name)
+    prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
+    kern = S.SMC_KERNEL_MALA if kernel == "mala" else S.SMC_KERNEL_RW
+    B = len(seed_sets[0])
+    m = S.Model.from_workload(w, precision=prec)
+    models = [m] * B
+    pops = [S.Population(m, w.J, w.N, max_chunk=1024, with_grad=kern == S.SMC_KERNEL_MALA)
+            for _ in range(B)]
+
+    def batch(seeds, Rbar):
+        recs = S.smc_run_batch(models, pops, list(seeds), Rbar=Rbar, kernel=kern, Lmax=2048,
+                               RmaxRec=3 * Rbar + 1)
+        tot = torch.cat([r.group_logwbar[:r.L].sum(0) for r in recs]).reshape(1, -1)
+        out = S.smc_log_ml(tot).cpu().numpy()
+        return recs, float(out[0]), float(out[1])
+
+    batch([900 + i for i in range(B)], ladder[0])
+    torch.cuda.synchronize()
+    per_set = []
+    for seeds in seed_sets:
+        hit = None
+        spent = 0.0
+        for Rbar in ladder:
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            recs, lml, nse = batch(seeds, Rbar)
+            torch.cuda.synchronize()
+            el = time.perf_counter() - t0
+            spent += el
+            log(f"[bench] time-to-NSE batched {name}/{precision}/{kernel} seeds {seeds} "
+                f"Rbar={Rbar}: {el:.3f} s, pooled NSE {nse:.4f}")
+            if nse <= target:
+                hit = dict(seeds=list(seeds), Rbar=Rbar, secs=el, nse=nse, log_ml=lml,
+                           precision_per_time=1.0 / (nse ** 2 * el), ladder_secs=spent,
+                           run_nse=[r.summary()["nse"] for r in recs])
+                break
+        per_set.append(hit if hit else dict(seeds=list(seeds), Rbar=None))
+    ok = [x for x in per_set if x.get("Rbar")]
+
+    def ms(key):
+        v = np.array([x[key] for x in ok], dtype=np.float64)
+        return (float(v.mean()), float(v.std(ddof=1)) if len(v) > 1 else 0.0) if len(v) else (None, None)
+
+    out = dict(kernel=kernel, precision=precision, batched=True, runs_per_batch=B,
+               reached=len(ok), per_seed=per_set)
+    for key in ("secs", "nse", "precision_per_time", "Rbar"):
+        out[key + "_mean"], out[key + "_sd"] = ms(key)
+    return out
+
+
 def run_gpu(name, precision, steps, warmup):
     import numpy as np
     import torch
@@ -545,7 +609,9 @@ def main():
             comp[f"egarch23_{prec}"] = run_gpu("egarch23", prec, 2, 1)
         batched = run_batched(2)
         tnse = [time_to_nse("egarch2t", "fp64", "rw"), time_to_nse("egarch2t", "fp32", "rw"),
-                time_to_nse("egarch2t", "fp32", "mala")]
+                time_to_nse("egarch2t", "fp32", "mala"),
+                time_to_nse_batched("egarch2t", "fp32", "mala"),
+                time_to_nse_batched("egarch2t", "fp32", "rw")]
         variants = run_variants("egarch11", "fp64", 2)
     cpu = None if args.no_cpu_baseline else cpu_baseline(args.workload, args.cpu_seconds)
 
@@ -593,7 +659,8 @@ def main():
     if tnse is not None:
         out["time_to_nse_0.05"] = {
             "workload": "egarch2t: " + DESCR["egarch2t"] + ", adaptive, Fibonacci Rbar ladder, "
-                        "3 seeds, after one untimed run",
+                        "3 seeds (batched: 3 sets of 3 runs in one batch, groups pooled), after "
+                        "one untimed run",
             "runs": tnse}
     if variants is not None:
         out["variants"] = dict(variants, workload=f"egarch11: {DESCR['egarch11']}, FP64 "

@@ -385,9 +385,11 @@ typedef struct {
 
 /* Runs n independent simulators (each with its own model, population and
  * workspace, configuration and record, as for smc_run) together.  The runs
- * must share one recursion precision, use EGARCH(1) Gaussian or EGARCH(2)
- * Student-t models, the random walk and the deterministic R_l rule, and
- * either all adapt or all replay.  At every step of the batch, the M
+ * must share one recursion precision and one Metropolis kernel (the random
+ * walk, or the Langevin step: then every population needs pop->grad and a
+ * workspace of smc_mala_workspace_bytes), use EGARCH(1) Gaussian or EGARCH(2)
+ * Student-t models and the deterministic R_l rule, and either all adapt or
+ * all replay.  At every step of the batch, the M
  * iterations of all runs then in their M phase go to one persistent kernel
  * launch in which each wave takes (run, 64-particle block) items, longest
  * date first, from a device counter until they are exhausted; their moments

@@ -484,7 +484,7 @@ def hybrid_report(r1, r2, secs=None):
 
 def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, waves=0,
                   Rbar=7, kappa=3, D1=0.5, D2=0.2, Lmax=1024, RmaxRec=64, bws=None,
-                  timing=0, stream=None):
+                  timing=0, kernel=SMC_KERNEL_RW, stream=None):
     """Many runs together (see smc_run_batch in include/smc.h); returns the
     records.  With replay=True the records' designs are replayed.  `bws`
     (a device uint8 tensor of smc_batch_ws_bytes(n) + 256 bytes) may be
@@ -502,7 +502,7 @@ def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, wa
     for i in range(n):
         r = records[i]
         cfgs[i] = RunConfig(pops[i].J, pops[i].N, Rng(seeds[i], runs[i]), 1, 0, D1, D2, Rbar,
-                            kappa, 0, 0.35, 100, SMC_RESAMPLE_RESIDUAL, SMC_KERNEL_RW,
+                            kappa, 0, 0.35, 100, SMC_RESAMPLE_RESIDUAL, kernel,
                             1 if replay else 0, r.Lmax, r.RmaxRec, pops[i].max_chunk,
                             SMC_TEST_PARAMS, 0, 0.90, 0)
         recs[i] = r.c

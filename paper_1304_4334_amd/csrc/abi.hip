@@ -957,6 +957,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
     return set_error(SMC_E_WORKSPACE, "batch workspace too small or misaligned");
   hipStream_t s = as_stream(stream);
   const bool replay = cfgs[0].replay != 0;
+  const int32_t kernel = cfgs[0].kernel;
+  const bool mala = kernel == SMC_KERNEL_MALA;
   int32_t family = -1;
   for (int i = 0; i < n; ++i) {
     const smc_model *m = models[i];
@@ -969,8 +971,21 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
       return set_error(SMC_E_INVALID_ARG, "run %d: a record array is NULL", i);
     if (c.Lmax < 1 || c.RmaxRec < 1 || c.check_every < 1 || c.force_every < 0)
       return set_error(SMC_E_INVALID_ARG, "run %d: bad record capacity", i);
-    if (c.kernel != SMC_KERNEL_RW || c.stop_rule != 0)
-      return set_error(SMC_E_UNSUPPORTED, "batched runs use the random walk and fixed R_l");
+    if ((c.kernel != SMC_KERNEL_RW && c.kernel != SMC_KERNEL_MALA) || c.stop_rule != 0)
+      return set_error(SMC_E_UNSUPPORTED,
+                       "batched runs use the random walk or the Langevin step and fixed R_l");
+    if (c.kernel != kernel)
+      return set_error(SMC_E_INVALID_ARG, "the runs of a batch share one Metropolis kernel");
+    if (mala) {
+      if (!pops[i]->grad)
+        return set_error(SMC_E_INVALID_ARG, "run %d: the Langevin kernel needs pop->grad", i);
+      const WsLayout L = ws_layout(m->dev, pops[i]->J, pops[i]->N);
+      const size_t need =
+          L.wcols + adjoint_ckpt_bytes(m->dev, (int64_t)pops[i]->J * pops[i]->N, m->dev.T);
+      if (pops[i]->ws_bytes < need)
+        return set_error(SMC_E_WORKSPACE, "run %d: the Langevin kernel needs %zu workspace bytes",
+                         i, need);
+    }
     if (c.burn_in != 0 || r.moments || r.log_score || c.reserved != 0)
       return set_error(SMC_E_UNSUPPORTED, "batched runs: no burn-in, moment reports or log score");
     if ((c.replay != 0) != replay)
@@ -1005,6 +1020,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
     b.mh = ws_at<int32_t>(pops[i], L.small + kSmallMh);
     b.flags = ws_at<int32_t>(pops[i], L.small + kSmallFlags);
     b.y = dm.prec == SMC_FP32 ? static_cast<const void *>(dm.y32) : static_cast<const void *>(dm.y);
+    b.grad = mala ? pops[i]->grad : nullptr;
+    b.ckpt = mala ? static_cast<void *>(ws_at<char>(pops[i], L.wcols)) : nullptr;
     b.seed = cfgs[i].rng.seed;
     b.run = cfgs[i].rng.run;
     b.P = (int64_t)pops[i]->J * pops[i]->N;
@@ -1061,6 +1078,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
                                   recs[i].group_logwbar + (int64_t)u.l * c.J, s)))
       return e;
     if ((e = smc_resample(m, pop, c.scheme, c.rng, u.l + 1, stream))) return e;
+    // the Langevin drift needs the posterior gradient at the new date
+    if (mala && (e = smc_posterior_grad(m, pop, u.tc, stream))) return e;
     u.t_new = u.tc;
     u.last_len = u.t_new - u.t;
     u.R = c.replay ? recs[i].R[u.l] : (u.rss < c.D2 ? c.kappa * c.Rbar : c.Rbar);
@@ -1152,7 +1171,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
       ba.runs = table;
       ba.queue = queue;
       ba.n_active = (int32_t)act.size();
-      ba.target_permille = 250;
+      ba.target_permille = mala ? 574 : 250;
+      ba.kernel = kernel;
       int32_t mut = 0, mom = 0;
       for (size_t q = 0; q < act.size(); ++q) {
         const int i = act[q];

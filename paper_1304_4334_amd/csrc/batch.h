@@ -22,6 +22,8 @@ struct BatchStatic {
   int32_t *mh;      // step size in tenths (the run's workspace)
   int32_t *flags;   // numerical flags (the run's workspace)
   const void *y;    // observations in the recursion's precision
+  double *grad;     // [d][P] posterior gradient (Langevin batches), else NULL
+  void *ckpt;       // the adjoint's checkpoint area (Langevin batches), else NULL
   uint64_t seed, run;
   int64_t P;
   int32_t tag;      // 0: EGARCH(1) Gaussian, 1: EGARCH(2) Student-t
@@ -43,6 +45,8 @@ struct BatchArgs {
   const BatchStatic *runs;
   unsigned int *queue;  // work counter of the persistent kernel
   int32_t n_active, n_mut_items, n_mom_items, target_permille;
+  int32_t kernel;       // SMC_KERNEL_RW or SMC_KERNEL_MALA
+  int32_t pad;
   BatchDyn dyn[kMaxBatch];  // active runs, decreasing t
 };
 

@@ -17,6 +17,7 @@
 #include "batch.h"
 #include "chol.h"
 #include "model.h"
+#include "model_kernels.h"
 #include "rng.h"
 
 namespace smc {
@@ -163,10 +164,24 @@ __device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &
   return acc;
 }
 
+// The Langevin step of one particle of run `st` (as k_mutate_mala).
+template <class M>
+__device__ __forceinline__ int mala_batch_one(const BatchStatic &st, const BatchDyn &dy, int64_t p,
+                                              void *lds) {
+  DevModel dm{};
+  if constexpr (sizeof(typename M::Y) == 4) dm.y32 = static_cast<const float *>(st.y);
+  else dm.y = static_cast<const double *>(st.y);
+  return mala_one<M>(dm, st.P, p, dy.t, st.theta, st.logprior, st.loglik, st.state, st.grad,
+                     dy.hchol, st.seed, st.run, (uint64_t)dy.cycle, (uint64_t)dy.iter, st.ckpt,
+                     lds);
+}
+
 // Persistent M step over every active run: waves pull items until the
-// counter passes the item count (every wave reaches that exit).
-template <class M0, class M1>
+// counter passes the item count (every wave reaches that exit).  kMala: the
+// Langevin step (the block's dynamic LDS is the adjoint's buffer).
+template <class M0, class M1, bool kMala>
 __global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
+  extern __shared__ double lds_dyn[];
   __shared__ int sh_item;
   for (;;) {
     if (threadIdx.x == 0) sh_item = (int)atomicAdd(a.queue, 1u);
@@ -180,10 +195,15 @@ __global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
     const int64_t p = (int64_t)(item - dy.mut_begin) * 64 + threadIdx.x;
     int acc = 0;
     if (p < st.P) {
-      if (st.tag == 0)
-        acc = mstep_one<M0>(st, dy, p, static_cast<const typename M0::Y *>(st.y));
-      else
-        acc = mstep_one<M1>(st, dy, p, static_cast<const typename M1::Y *>(st.y));
+      if constexpr (kMala) {
+        if (st.tag == 0) acc = mala_batch_one<M0>(st, dy, p, lds_dyn);
+        else acc = mala_batch_one<M1>(st, dy, p, lds_dyn);
+      } else {
+        if (st.tag == 0)
+          acc = mstep_one<M0>(st, dy, p, static_cast<const typename M0::Y *>(st.y));
+        else
+          acc = mstep_one<M1>(st, dy, p, static_cast<const typename M1::Y *>(st.y));
+      }
     }
     const unsigned long long mask = __ballot(acc);
     if (threadIdx.x == 0 && mask) atomicAdd(dy.n_accept, (unsigned long long)__popcll(mask));
@@ -216,17 +236,25 @@ smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int3
   hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, s, a.queue);
   if ((st = launch_ok("batch/queue reset"))) return st;
   const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(a.n_mut_items, waves));
-  auto go = [&](auto kern) {
+  auto go = [&](auto kern, size_t lds) {
     if (timer)
-      hipExtLaunchKernelGGL(kern, grid_of(blocks), dim3(64), 0, s, timer->start, timer->stop, 0,
+      hipExtLaunchKernelGGL(kern, grid_of(blocks), dim3(64), lds, s, timer->start, timer->stop, 0,
                             a);
     else
-      hipLaunchKernelGGL(kern, grid_of(blocks), dim3(64), 0, s, a);
+      hipLaunchKernelGGL(kern, grid_of(blocks), dim3(64), lds, s, a);
   };
-  if (family == kFamilyFp32)
-    go(k_batch_mutate<Egarch<1, 0, float>, Egarch<2, 1, float>>);
-  else
-    go(k_batch_mutate<Egarch<1, 0, double>, Egarch<2, 1, double>>);
+  using F1 = Egarch<1, 0, float>;
+  using F2 = Egarch<2, 1, float>;
+  using D1 = Egarch<1, 0, double>;
+  using D2 = Egarch<2, 1, double>;
+  const bool mala = a.kernel == SMC_KERNEL_MALA;
+  if (family == kFamilyFp32) {
+    if (mala) go(k_batch_mutate<F1, F2, true>, std::max(lds_bytes_of<F1>(), lds_bytes_of<F2>()));
+    else go(k_batch_mutate<F1, F2, false>, 0);
+  } else {
+    if (mala) go(k_batch_mutate<D1, D2, true>, std::max(lds_bytes_of<D1>(), lds_bytes_of<D2>()));
+    else go(k_batch_mutate<D1, D2, false>, 0);
+  }
   return launch_ok("batch/mutate");
 }
 

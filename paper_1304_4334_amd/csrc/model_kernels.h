@@ -449,10 +449,96 @@ __global__ void __launch_bounds__(64) k_grad_post(DevModel dm, int64_t P, const 
   for (int i = 0; i < M::D; ++i) grad[i * P + p] = g[i];
 }
 
-// One preconditioned Langevin (MALA) Metropolis iteration: proposal mean
-// theta + (1/2)(hL)(hL)' grad, noise hL z; the acceptance test adds
-// log q(theta | theta') - log q(theta' | theta) = -|w|^2/2 + |z|^2/2 with
-// (hL) w = theta - theta' - (1/2)(hL)(hL)' grad'.
+// One preconditioned Langevin (MALA) Metropolis iteration of particle p:
+// proposal mean theta + (1/2)(hL)(hL)' grad, noise hL z; the acceptance test
+// adds log q(theta | theta') - log q(theta' | theta) = -|w|^2/2 + |z|^2/2
+// with (hL) w = theta - theta' - (1/2)(hL)(hL)' grad'.  ckpt: the adjoint's
+// checkpoint area of the population; lds: the block's LDS buffer.  Returns
+// whether the proposal was accepted (the particle's arrays are updated).
+template <class M>
+__device__ __forceinline__ int mala_one(const DevModel &dm, int64_t P, int64_t p, int64_t t,
+                                        double *theta, double *logprior, double *loglik,
+                                        void *state, double *grad,
+                                        const double *__restrict__ hchol, uint64_t seed,
+                                        uint64_t run, uint64_t cycle, uint64_t iter, void *ckpt,
+                                        void *lds) {
+  constexpr int D = M::D;
+  using R = typename M::R;
+  constexpr int SR = Eval<M>::SR;
+  constexpr int SS = StoredS<M>::value;
+  int acc = 0;
+  double th[D], z[D], pr[D], g0[D], g1[D], u[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    th[i] = theta[i * P + p];
+    g0[i] = grad[i * P + p];
+  }
+  normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+  // u = (hL)' g0
+#pragma unroll
+  for (int k = 0; k < D; ++k) {
+    double s = 0.0;
+#pragma unroll
+    for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g0[i], s);
+    u[k] = s;
+  }
+#pragma unroll
+  for (int i = 0; i < D; ++i) {
+    double dr = 0.0, st = 0.0;
+#pragma unroll
+    for (int k = 0; k <= i; ++k) {
+      dr = fma(hchol[i * D + k], u[k], dr);
+      st = fma(hchol[i * D + k], z[k], st);
+    }
+    pr[i] = th[i] + 0.5 * dr + st;
+  }
+  const double lp1 = M::logprior(pr);
+  R stv[SR];
+#pragma unroll
+  for (int k = 0; k < SR; ++k) stv[k] = (R)0;
+  double ll1 = -INFINITY;
+  if (lp1 > -INFINITY) {
+    PriorGradOf<M>::run(pr, g1);
+    ll1 = ll_and_grad<M>(dm, pr, t, ckpt, P, p, lds, 1.0, g1, stv);
+    // reverse move
+#pragma unroll
+    for (int k = 0; k < D; ++k) {
+      double s = 0.0;
+#pragma unroll
+      for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g1[i], s);
+      u[k] = s;
+    }
+    double ww = 0.0, zz = 0.0, w[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      double dr = 0.0;
+#pragma unroll
+      for (int k = 0; k <= i; ++k) dr = fma(hchol[i * D + k], u[k], dr);
+      double a = th[i] - pr[i] - 0.5 * dr;
+#pragma unroll
+      for (int k = 0; k < i; ++k) a = fma(-hchol[i * D + k], w[k], a);
+      w[i] = a / hchol[i * D + i];
+      ww = fma(w[i], w[i], ww);
+      zz = fma(z[i], z[i], zz);
+    }
+    const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
+    const U64x4 wr = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
+    acc = (log(u01_oo(wr.x0)) < delta) ? 1 : 0;
+  }
+  if (acc) {
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+      theta[i * P + p] = pr[i];
+      grad[i * P + p] = g1[i];
+    }
+    logprior[p] = lp1;
+    loglik[p] = ll1;
+#pragma unroll
+    for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = stv[k];
+  }
+  return acc;
+}
+
 template <class M>
 __global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int64_t t, double *theta,
                                                     double *logprior, double *loglik, void *state,
@@ -461,83 +547,11 @@ __global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int6
                                                     uint64_t iter, unsigned long long *n_accept,
                                                     uint8_t *accepted, void *ckpt) {
   extern __shared__ double lds_dyn[];
-  constexpr int D = M::D;
-  using R = typename M::R;
-  constexpr int SR = Eval<M>::SR;
-  constexpr int SS = StoredS<M>::value;
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   int acc = 0;
   if (p < P) {
-    double th[D], z[D], pr[D], g0[D], g1[D], u[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      th[i] = theta[i * P + p];
-      g0[i] = grad[i * P + p];
-    }
-    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
-    // u = (hL)' g0
-#pragma unroll
-    for (int k = 0; k < D; ++k) {
-      double s = 0.0;
-#pragma unroll
-      for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g0[i], s);
-      u[k] = s;
-    }
-#pragma unroll
-    for (int i = 0; i < D; ++i) {
-      double dr = 0.0, st = 0.0;
-#pragma unroll
-      for (int k = 0; k <= i; ++k) {
-        dr = fma(hchol[i * D + k], u[k], dr);
-        st = fma(hchol[i * D + k], z[k], st);
-      }
-      pr[i] = th[i] + 0.5 * dr + st;
-    }
-    const double lp1 = M::logprior(pr);
-    R stv[SR];
-#pragma unroll
-    for (int k = 0; k < SR; ++k) stv[k] = (R)0;
-    double ll1 = -INFINITY;
-    if (lp1 > -INFINITY) {
-      PriorGradOf<M>::run(pr, g1);
-      ll1 = ll_and_grad<M>(dm, pr, t, ckpt, P, p, lds_dyn, 1.0, g1, stv);
-      // reverse move
-#pragma unroll
-      for (int k = 0; k < D; ++k) {
-        double s = 0.0;
-#pragma unroll
-        for (int i = k; i < D; ++i) s = fma(hchol[i * D + k], g1[i], s);
-        u[k] = s;
-      }
-      double ww = 0.0, zz = 0.0, w[D];
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        double dr = 0.0;
-#pragma unroll
-        for (int k = 0; k <= i; ++k) dr = fma(hchol[i * D + k], u[k], dr);
-        double a = th[i] - pr[i] - 0.5 * dr;
-#pragma unroll
-        for (int k = 0; k < i; ++k) a = fma(-hchol[i * D + k], w[k], a);
-        w[i] = a / hchol[i * D + i];
-        ww = fma(w[i], w[i], ww);
-        zz = fma(z[i], z[i], zz);
-      }
-      const double delta =
-          (lp1 + ll1) - (logprior[p] + loglik[p]) + (-0.5 * ww + 0.5 * zz);
-      const U64x4 wr = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
-      acc = (log(u01_oo(wr.x0)) < delta) ? 1 : 0;
-    }
-    if (acc) {
-#pragma unroll
-      for (int i = 0; i < D; ++i) {
-        theta[i * P + p] = pr[i];
-        grad[i * P + p] = g1[i];
-      }
-      logprior[p] = lp1;
-      loglik[p] = ll1;
-#pragma unroll
-      for (int k = 0; k < SS; ++k) typed<R>(state)[k * P + p] = stv[k];
-    }
+    acc = mala_one<M>(dm, P, p, t, theta, logprior, loglik, state, grad, hchol, seed, run, cycle,
+                      iter, ckpt, lds_dyn);
     if (accepted) accepted[p] = (uint8_t)acc;
   }
   const unsigned long long mask = __ballot(acc);

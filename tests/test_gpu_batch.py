@@ -13,12 +13,12 @@ from tests.gpu_helpers import theta_np
 pytestmark = pytest.mark.gpu
 
 
-def _runs(prec, specs):
+def _runs(prec, specs, with_grad=False):
     out = []
     for name, T, J, N, seed_off in specs:
         w = SD.workload(name, T=T, J=J, N=N, seed_offset=seed_off)
         m = S.Model(w.kind, w.y[:T], K=w.K, shock=w.shock, precision=prec)
-        out.append((w, m, S.Population(m, J, N, max_chunk=64)))
+        out.append((w, m, S.Population(m, J, N, max_chunk=64, with_grad=with_grad)))
     return out
 
 
@@ -100,3 +100,27 @@ def test_batch_timing_accounts_for_every_m_step():
                                           for l in range(s["L"]))
     got = np.array(tim["evals"]).sum(axis=0).tolist()
     assert got == want
+
+
+@pytest.mark.parametrize("prec", [S.SMC_FP64, S.SMC_FP32])
+def test_langevin_batch_equals_single_runs(prec):
+    """Langevin (MALA) runs in one batch: each run's decisions, weights,
+    estimates, particles and gradients equal those of the same run on its
+    own, to the bit."""
+    runs = _runs(prec, SPECS, with_grad=True)
+    models = [m for _, m, _ in runs]
+    pops = [p for _, _, p in runs]
+    seeds = [41, 42, 43, 44]
+    recs = S.smc_run_batch(models, pops, seeds, Lmax=400, RmaxRec=64, kernel=S.SMC_KERNEL_MALA)
+    torch.cuda.synchronize()
+    for i, (w, m, _) in enumerate(runs):
+        p1 = S.Population(m, w.J, w.N, max_chunk=64, with_grad=True)
+        r1 = S.smc_run(m, p1, seed=seeds[i], Lmax=400, RmaxRec=64, kernel=S.SMC_KERNEL_MALA)
+        a, b = recs[i].summary(), r1.summary()
+        assert a["L"] == b["L"] and a["L"] > 1
+        assert np.array_equal(a["t_end"], b["t_end"]) and np.array_equal(a["R"], b["R"])
+        assert np.array_equal(a["n_accept"], b["n_accept"])
+        assert np.array_equal(a["group_logwbar"], b["group_logwbar"])
+        assert a["log_ml"] == b["log_ml"] and a["nse"] == b["nse"]
+        assert np.array_equal(theta_np(pops[i]), theta_np(p1))
+        assert torch.equal(pops[i].grad, p1.grad)
