@@ -266,9 +266,12 @@ def run_gpu(name, precision, steps, warmup):
     import paper_1304_4334_amd as S
     import synthdata as SD
 
+    from paper_1304_4334_amd import tune
+
     w = SD.workload(name)
     prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
     m = S.Model.from_workload(w, precision=prec)
+    tune.apply(m, name, precision)
     pop = S.Population(m, w.J, w.N, max_chunk=1024)
     rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64, time_mutate=True)
     force = 20 if name == "linreg" else 0
@@ -323,7 +326,9 @@ def run_gpu(name, precision, steps, warmup):
                       ops_per_eval_builder=ops_b,
                       frac_builder_ops=ops_b * rate / 1e12 / VALU_PEAK_TOPS,
                       simd_occupancy=occupied,
-                      frac_of_occupied=achieved / (VALU_PEAK_TOPS * occupied)),
+                      frac_of_occupied=achieved / (VALU_PEAK_TOPS * occupied),
+                      launch_shape=dict(zip(("block", "unroll"),
+                                            getattr(m, "launch", (0, 0))))),
         secs=secs)
 
 
@@ -341,6 +346,9 @@ def run_batched(steps):
 
     specs = SD.batched_specs()
     models = [S.Model.from_workload(w, precision=S.SMC_FP32) for w in specs]
+    bshape = tune.tuned_batch_shape()
+    for mm in models:
+        mm.set_launch(*bshape)
     pops = [S.Population(m, w.J, w.N, max_chunk=256) for m, w in zip(models, specs)]
     waves = tune.tuned_waves()
     S.smc_run_batch(models, pops, list(range(100, 132)), waves=waves, Lmax=2048, RmaxRec=64)
@@ -365,6 +373,7 @@ def run_batched(steps):
     achieved = lane_ops / (ms_sum * 1e-3) / 1e12
     return dict(value=evals / secs, ms_per_step=1e3 * secs / steps, runs=len(specs),
                 total_particles=sum(w.P for w in specs), waves=waves,
+                launch_shape={"block": bshape[0], "unroll": bshape[1]},
                 evals_per_step=evals / steps,
                 mutate_launches_per_step=launches / steps,
                 mutate_ms_per_step=ms_sum / steps,

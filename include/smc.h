@@ -125,6 +125,15 @@ typedef struct {
 /* Validates the description and creates a handle (host allocation only). */
 smc_status smc_model_create(const smc_model_desc *desc, smc_model **out);
 smc_status smc_model_destroy(smc_model *m);
+/* Launch shape of the model's random-walk step (smc_mutate, smc_run) and of
+ * its runs' share of a batch: threads (particles) per block, 64, 128 or 256,
+ * and observations per load batch of the likelihood loop, 4, 8 or 16 (0 =
+ * the defaults 64 and 8).  A shape changes only the speed: every shape gives
+ * the same results to the bit.  Shapes other than the default exist for
+ * EGARCH(1) with Gaussian shocks and EGARCH(2) with Student-t shocks
+ * (SMC_E_UNSUPPORTED otherwise).  The handle is changed: call it before the
+ * model is in use on any stream.  tune.py chooses shapes by timing them. */
+smc_status smc_model_set_launch(smc_model *m, int32_t block, int32_t unroll);
 int32_t smc_model_dim(const smc_model *m);       /* d, or -1 for NULL */
 int32_t smc_model_state_dim(const smc_model *m); /* S, or -1 for NULL */
 
@@ -391,11 +400,13 @@ typedef struct {
  * Student-t models and the deterministic R_l rule, and either all adapt or
  * all replay.  At every step of the batch, the M
  * iterations of all runs then in their M phase go to one persistent kernel
- * launch in which each wave takes (run, 64-particle block) items, longest
+ * launch in which each block takes (run, block of particles) items, longest
  * date first, from a device counter until they are exhausted; their moments
  * go to one pair of launches; C-phase chunks of different runs share one
  * host synchronisation.  `waves` is the number of persistent waves (0 =
- * 2048).  bws: device, >= smc_batch_ws_bytes(n), 256-byte aligned.  A replay
+ * 2048).  FP32 random-walk batches take the launch shape set on their first
+ * model (smc_model_set_launch: particles per block and item, observations
+ * per load batch); other batches use 64 and 8.  bws: device, >= smc_batch_ws_bytes(n), 256-byte aligned.  A replay
  * batch never synchronises the stream (capturable in a graph); an adaptive
  * one synchronises once per batch step that evaluates C-phase chunks, and
  * stops with SMC_E_NUMERIC at the first such readback after a run raised a

@@ -87,6 +87,8 @@ def lib():
         L.smc_model_create.argtypes = [P(ModelDesc), P(_vp)]
         L.smc_model_destroy.restype = st
         L.smc_model_destroy.argtypes = [_vp]
+        L.smc_model_set_launch.restype = st
+        L.smc_model_set_launch.argtypes = [_vp, C.c_int32, C.c_int32]
         L.smc_model_dim.restype = C.c_int32
         L.smc_model_dim.argtypes = [_vp]
         L.smc_model_state_dim.restype = C.c_int32
@@ -193,6 +195,11 @@ class Model:
     def from_workload(cls, w, precision=SMC_FP64, device="cuda"):
         return cls(w.kind, w.y, X=w.X, K=w.K, shock=w.shock, precision=precision,
                    device=device, I=w.I)
+
+    def set_launch(self, block=0, unroll=0):
+        """Launch shape of the random-walk step (smc_model_set_launch)."""
+        _check(lib().smc_model_set_launch(self.h, block, unroll), "smc_model_set_launch")
+        self.launch = (block, unroll)
 
     @property
     def d(self):

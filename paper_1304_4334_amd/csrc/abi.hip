@@ -297,6 +297,20 @@ smc_status smc_model_destroy(smc_model *m) {
   return SMC_OK;
 }
 
+smc_status smc_model_set_launch(smc_model *m, int32_t block, int32_t unroll) {
+  if (!m) return set_error(SMC_E_INVALID_ARG, "model handle is NULL");
+  if (block != 0 && block != 64 && block != 128 && block != 256)
+    return set_error(SMC_E_INVALID_ARG, "threads per block %d (0, 64, 128 or 256)", block);
+  if (unroll != 0 && unroll != 4 && unroll != 8 && unroll != 16)
+    return set_error(SMC_E_INVALID_ARG, "observations per load batch %d (0, 4, 8 or 16)", unroll);
+  const bool dflt = (block == 0 || block == 64) && (unroll == 0 || unroll == 8);
+  if (!dflt && !has_launch_shapes(m->dev))
+    return set_error(SMC_E_UNSUPPORTED, "no tuned launch shapes for this model");
+  m->dev.block = block == 64 ? 0 : block;
+  m->dev.unroll = unroll == 8 ? 0 : unroll;
+  return SMC_OK;
+}
+
 int32_t smc_model_dim(const smc_model *m) { return m ? m->dev.d : -1; }
 int32_t smc_model_state_dim(const smc_model *m) { return m ? m->dev.S : -1; }
 
@@ -1001,6 +1015,12 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
       return set_error(SMC_E_UNSUPPORTED, "batched runs share one precision");
     family = fam;
   }
+  // FP32 random-walk batches take their first model's launch shape; the item
+  // (a block of particles of one run) is that many particles
+  const bool shaped = family == kFamilyFp32 && !mala;
+  const int32_t bshape = shaped ? models[0]->dev.block : 0;
+  const int32_t ushape = shaped ? models[0]->dev.unroll : 0;
+  const int64_t item = bshape ? bshape : 64;
   BatchStatic *table = reinterpret_cast<BatchStatic *>(bws);
   unsigned int *queue = reinterpret_cast<unsigned int *>(reinterpret_cast<char *>(bws) +
                                                          align256((size_t)n * sizeof(BatchStatic)));
@@ -1191,7 +1211,7 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         dy.iter = u.r + 1;
         dy.mh_reset = u.r == 0 ? 5 : 0;
         dy.mut_begin = mut;
-        mut += (int32_t)((P + 63) / 64);
+        mut += (int32_t)((P + item - 1) / item);
         int64_t ch = 0, nb = 0;
         moment_partition(P, d, ch, nb);
         dy.mom_begin = mom;
@@ -1223,7 +1243,7 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         timing->launches = k + 1;
       }
       if ((st = launch_batch_m(ba, !replay, family, waves > 0 ? waves : 2048, s,
-                               timed_launch ? &kt : nullptr)))
+                               timed_launch ? &kt : nullptr, bshape, ushape)))
         return st;
       for (int i : act) {
         Run &u = run[i];

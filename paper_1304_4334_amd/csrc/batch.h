@@ -59,8 +59,12 @@ struct BatchStaticArgs {
 
 // timer (may be NULL): start and stop events carried by the persistent
 // launch's own dispatch.
+// block, unroll: launch shape of the FP32 random-walk batches (threads per
+// block and observations per load batch; 0 = 64 and 8); other batches use
+// the default.
 smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int32_t waves,
-                          hipStream_t s, const KernelTimer *timer = nullptr);
+                          hipStream_t s, const KernelTimer *timer = nullptr, int32_t block = 0,
+                          int32_t unroll = 0);
 smc_status launch_batch_static(const BatchStaticArgs &a, hipStream_t s);
 
 }  // namespace smc

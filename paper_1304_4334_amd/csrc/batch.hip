@@ -4,8 +4,8 @@
 // or in an M iteration.  The M iterations of all runs go to
 //   k_batch_mom_partial  one 256-thread block per (run, particle chunk),
 //   k_batch_mom_final    one block per run (h rule, V, Cholesky, h L),
-//   k_batch_mutate       one persistent launch: each wave takes the next
-//                        (run, 64-particle block) item from a device counter,
+//   k_batch_mutate       one persistent launch: each block takes the next
+//                        (run, block of particles) item from a device counter,
 //                        items ordered by decreasing cost t_r.
 // Static per-run data (arrays, keys, sizes) sits in a device table written
 // once per batch call; what changes from step to step (date, cycle,
@@ -119,7 +119,7 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
 }
 
 // The random-walk M step of one particle of run `st` (as k_mutate_rw).
-template <class M>
+template <class M, int U = kUnroll>
 __device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &dy, int64_t p,
                                          const typename M::Y *__restrict__ y) {
   constexpr int D = M::D;
@@ -147,7 +147,7 @@ __device__ __forceinline__ int mstep_one(const BatchStatic &st, const BatchDyn &
   double ll1 = -INFINITY;
   if (lp1 > -INFINITY) {
     const auto par = M::params(pr);
-    ll1 = M::advance(par, stv, 0, dy.t, y);
+    ll1 = M::template advance<U>(par, stv, 0, dy.t, y);
     const double delta = (lp1 + ll1) - (st.logprior[p] + st.loglik[p]);
     const U64x4 w = draw4(st.seed, st.run, (uint64_t)p, (uint64_t)dy.cycle, (uint64_t)dy.iter,
                           kAccept);
@@ -176,11 +176,12 @@ __device__ __forceinline__ int mala_batch_one(const BatchStatic &st, const Batch
                      lds);
 }
 
-// Persistent M step over every active run: waves pull items until the
-// counter passes the item count (every wave reaches that exit).  kMala: the
-// Langevin step (the block's dynamic LDS is the adjoint's buffer).
-template <class M0, class M1, bool kMala>
-__global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
+// Persistent M step over every active run: blocks of B threads pull
+// (run, B-particle block) items until the counter passes the item count
+// (every block reaches that exit).  kMala: the Langevin step (the block's
+// dynamic LDS is the adjoint's buffer); U: observations per load batch.
+template <class M0, class M1, bool kMala, int B = 64, int U = kUnroll>
+__global__ void __launch_bounds__(B) k_batch_mutate(BatchArgs a) {
   extern __shared__ double lds_dyn[];
   __shared__ int sh_item;
   for (;;) {
@@ -192,7 +193,7 @@ __global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
     const int ri = owner(a, item, false);
     const BatchDyn &dy = a.dyn[ri];
     const BatchStatic &st = a.runs[dy.idx];
-    const int64_t p = (int64_t)(item - dy.mut_begin) * 64 + threadIdx.x;
+    const int64_t p = (int64_t)(item - dy.mut_begin) * B + threadIdx.x;
     int acc = 0;
     if (p < st.P) {
       if constexpr (kMala) {
@@ -200,13 +201,14 @@ __global__ void __launch_bounds__(64) k_batch_mutate(BatchArgs a) {
         else acc = mala_batch_one<M1>(st, dy, p, lds_dyn);
       } else {
         if (st.tag == 0)
-          acc = mstep_one<M0>(st, dy, p, static_cast<const typename M0::Y *>(st.y));
+          acc = mstep_one<M0, U>(st, dy, p, static_cast<const typename M0::Y *>(st.y));
         else
-          acc = mstep_one<M1>(st, dy, p, static_cast<const typename M1::Y *>(st.y));
+          acc = mstep_one<M1, U>(st, dy, p, static_cast<const typename M1::Y *>(st.y));
       }
     }
     const unsigned long long mask = __ballot(acc);
-    if (threadIdx.x == 0 && mask) atomicAdd(dy.n_accept, (unsigned long long)__popcll(mask));
+    if ((threadIdx.x & 63) == 0 && mask)
+      atomicAdd(dy.n_accept, (unsigned long long)__popcll(mask));
   }
 }
 
@@ -224,7 +226,8 @@ __global__ void k_batch_queue_reset(unsigned int *q) {
 }
 
 smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int32_t waves,
-                          hipStream_t s, const KernelTimer *timer) {
+                          hipStream_t s, const KernelTimer *timer, int32_t block,
+                          int32_t unroll) {
   smc_status st;
   if (a.n_active <= 0) return SMC_OK;
   if (moments) {
@@ -235,25 +238,39 @@ smc_status launch_batch_m(const BatchArgs &a, bool moments, int32_t family, int3
   }
   hipLaunchKernelGGL(k_batch_queue_reset, dim3(1), dim3(64), 0, s, a.queue);
   if ((st = launch_ok("batch/queue reset"))) return st;
-  const int64_t blocks = std::max<int64_t>(1, std::min<int64_t>(a.n_mut_items, waves));
-  auto go = [&](auto kern, size_t lds) {
+  // `waves` persistent waves, in blocks of `block` threads
+  const int32_t B = block ? block : 64;
+  const int64_t blocks =
+      std::max<int64_t>(1, std::min<int64_t>(a.n_mut_items, std::max(1, waves * 64 / B)));
+  auto go = [&](auto kern, int32_t threads, size_t lds) {
     if (timer)
-      hipExtLaunchKernelGGL(kern, grid_of(blocks), dim3(64), lds, s, timer->start, timer->stop, 0,
-                            a);
+      hipExtLaunchKernelGGL(kern, grid_of(blocks), dim3(threads), lds, s, timer->start,
+                            timer->stop, 0, a);
     else
-      hipLaunchKernelGGL(kern, grid_of(blocks), dim3(64), lds, s, a);
+      hipLaunchKernelGGL(kern, grid_of(blocks), dim3(threads), lds, s, a);
   };
   using F1 = Egarch<1, 0, float>;
   using F2 = Egarch<2, 1, float>;
   using D1 = Egarch<1, 0, double>;
   using D2 = Egarch<2, 1, double>;
   const bool mala = a.kernel == SMC_KERNEL_MALA;
+  const int32_t U = unroll ? unroll : kUnroll;
   if (family == kFamilyFp32) {
-    if (mala) go(k_batch_mutate<F1, F2, true>, std::max(lds_bytes_of<F1>(), lds_bytes_of<F2>()));
-    else go(k_batch_mutate<F1, F2, false>, 0);
+    if (mala) {
+      go(k_batch_mutate<F1, F2, true>, 64, std::max(lds_bytes_of<F1>(), lds_bytes_of<F2>()));
+    } else {
+      // the tuned shapes of FP32 random-walk batches
+#define SMC_BATCH_SHAPE(b, u) \
+  if (B == b && U == u) go(k_batch_mutate<F1, F2, false, b, u>, b, 0); else
+      SMC_BATCH_SHAPE(64, 4) SMC_BATCH_SHAPE(64, 8) SMC_BATCH_SHAPE(64, 16)
+      SMC_BATCH_SHAPE(128, 4) SMC_BATCH_SHAPE(128, 8) SMC_BATCH_SHAPE(128, 16)
+      SMC_BATCH_SHAPE(256, 4) SMC_BATCH_SHAPE(256, 8) SMC_BATCH_SHAPE(256, 16)
+      return set_error(SMC_E_UNSUPPORTED, "batch launch shape %d x %d", B, U);
+#undef SMC_BATCH_SHAPE
+    }
   } else {
-    if (mala) go(k_batch_mutate<D1, D2, true>, std::max(lds_bytes_of<D1>(), lds_bytes_of<D2>()));
-    else go(k_batch_mutate<D1, D2, false>, 0);
+    if (mala) go(k_batch_mutate<D1, D2, true>, 64, std::max(lds_bytes_of<D1>(), lds_bytes_of<D2>()));
+    else go(k_batch_mutate<D1, D2, false>, 64, 0);
   }
   return launch_ok("batch/mutate");
 }

@@ -1003,11 +1003,24 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
            : SMC_E_UNSUPPORTED;
 }
 
+bool has_launch_shapes(const DevModel &m) {
+  return m.kind == SMC_MODEL_EGARCH && ((m.K == 1 && m.shock == SMC_SHOCK_GAUSS) ||
+                                        (m.K == 2 && m.shock == SMC_SHOCK_STUDENT_T));
+}
+
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
                             double *logprior, double *loglik, void *state, const double *hchol,
                             uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
                             int64_t *n_accept, uint8_t *accepted, hipStream_t s,
                             const KernelTimer *timer, const MomFuse *fuse) {
+  const bool shaped = (m.block != 0 && m.block != 64) || (m.unroll != 0 && m.unroll != kUnroll);
+  if (shaped) {
+    return m.prec == SMC_FP32
+               ? launch_mutate_rw_shaped32(m, P, t, theta, logprior, loglik, state, hchol, seed,
+                                           run, cycle, iter, n_accept, accepted, timer, fuse, s)
+               : launch_mutate_rw_shaped64(m, P, t, theta, logprior, loglik, state, hchol, seed,
+                                           run, cycle, iter, n_accept, accepted, timer, fuse, s);
+  }
   const ModelOps *o = ops_for(m);
   return o ? o->mutate_rw(m, P, t, theta, logprior, loglik, state, hchol, seed, run, cycle, iter,
                           n_accept, accepted, timer, fuse, s)

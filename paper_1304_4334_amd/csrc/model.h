@@ -712,11 +712,12 @@ struct Eval {
   // The same with the observations from a kernel argument declared
   // __restrict__: a kernel that also stores to global memory then still
   // reads them as uniform scalar loads.
+  template <int U = kUnroll>
   __device__ __forceinline__ static double advance_y(const DevModel &dm, const Y *__restrict__ y,
                                                      const typename M::Par &p, R (&st)[SR],
                                                      int64_t t0, int64_t t1) {
     (void)dm;
-    return M::advance(p, st, t0, t1, y);
+    return M::template advance<U>(p, st, t0, t1, y);
   }
   template <class F>
   __device__ __forceinline__ static void scan_y(const DevModel &dm, const Y *__restrict__ y,
@@ -747,6 +748,7 @@ struct Eval<Linreg<NREG>> {
     (void)st;
     return Linreg<NREG>::advance_x(p, t0, t1, dm.y, dm.X);
   }
+  template <int U = kUnroll>
   __device__ __forceinline__ static double advance_y(const DevModel &dm, const Y *__restrict__ y,
                                                      const typename Linreg<NREG>::Par &p,
                                                      double (&st)[1], int64_t t0, int64_t t1) {

@@ -150,9 +150,17 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 // step-size rule, V and its Cholesky factor in LDS, exactly as the separate
 // moments kernels do (k_mom_final).  Returns whether V was positive definite;
 // h receives the step size.
-template <int D, int W>
+// kOneWave: the block is this one wave (its barriers are block barriers);
+// otherwise only the block's first wave runs this, ordering its LDS
+// accesses by wavefront fences (LDS operations of one wave complete in
+// order), and the caller synchronises the block afterwards.
+template <int D, int W, bool kOneWave = true>
 __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double *Ms, double *Ls,
                                             double *sh_h, double &h) {
+  const auto sync = [] {
+    if constexpr (kOneWave) __syncthreads();
+    else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+  };
   constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
   const int lane = threadIdx.x;
   int32_t m = 0;
@@ -201,7 +209,7 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
     if (blockIdx.x == 0) *fm.mh_out = m;
     *sh_h = (double)m / 10.0;
   }
-  __syncthreads();
+  sync();
   // V in place: entry (r, c) with r, c < D reads only itself and column D,
   // which is not written here
   const double invP = 1.0 / (double)P;
@@ -213,20 +221,22 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
       Ms[r * W + c] = (Ms[r * W + c] - Ms[r * W + D] * Ms[c * W + D] * invP) / (double)(P - 1);
     }
   }
-  __syncthreads();
+  sync();
   h = *sh_h;
   return wave_cholesky_fixed<W, D>(Ms, Ls, h, blockIdx.x == 0 ? fm.hchol_out : nullptr,
                                    blockIdx.x == 0 ? fm.flags : nullptr);
 }
 
-template <class M>
-__global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
-                                                  double *logprior, double *loglik, void *state,
-                                                  const double *__restrict__ hchol, uint64_t seed,
-                                                  uint64_t run, uint64_t cycle, uint64_t iter,
-                                                  unsigned long long *n_accept, uint8_t *accepted,
-                                                  MomFuse fm,
-                                                  const typename M::Y *__restrict__ ydata) {
+// B threads (B/64 waves) per block, observations loaded U at a time; the
+// launch shape does not change any result.
+template <class M, int B = 64, int U = kUnroll>
+__global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
+                                                 double *logprior, double *loglik, void *state,
+                                                 const double *__restrict__ hchol, uint64_t seed,
+                                                 uint64_t run, uint64_t cycle, uint64_t iter,
+                                                 unsigned long long *n_accept, uint8_t *accepted,
+                                                 MomFuse fm,
+                                                 const typename M::Y *__restrict__ ydata) {
   constexpr int D = M::D;
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
@@ -234,13 +244,25 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
   constexpr int W = D < 16 ? 16 : 32;  // padded width of the moment matrices
   constexpr bool kCanFuse = D < 32;
   __shared__ double Ms[kCanFuse ? W * W : 1], Ls[kCanFuse ? W * chol_ld<W>() : 1], sh_h;
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
+  __shared__ int sh_ok;
+  const int64_t p = blockIdx.x * (int64_t)B + threadIdx.x;
   bool fused = false, chol_ok = true;
   double h = 0.0;
   if constexpr (kCanFuse) {
     if (fm.part) {
       fused = true;
-      chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h);
+      if constexpr (B == 64) {
+        chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h);
+      } else {
+        // the first wave factors V for the whole block
+        if (threadIdx.x < 64) {
+          const bool ok = fused_scale<D, W, false>(fm, P, Ms, Ls, &sh_h, h);
+          if (threadIdx.x == 0) sh_ok = ok;
+        }
+        __syncthreads();
+        chol_ok = sh_ok != 0;
+        h = sh_h;
+      }
     }
   }
   int acc = 0;
@@ -275,7 +297,7 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
     double ll1 = -INFINITY;
     if (lp1 > -INFINITY) {
       const auto par = M::params(pr);
-      ll1 = Eval<M>::advance_y(dm, ydata, par, st, 0, t);
+      ll1 = Eval<M>::template advance_y<U>(dm, ydata, par, st, 0, t);
       const double delta = (lp1 + ll1) - (logprior[p] + loglik[p]);
       const U64x4 w = draw4(seed, run, (uint64_t)p, cycle, iter, kAccept);
       acc = (log(u01_oo(w.x0)) < delta) ? 1 : 0;
@@ -291,7 +313,51 @@ __global__ void __launch_bounds__(64) k_mutate_rw(DevModel dm, int64_t P, int64_
     if (accepted) accepted[p] = (uint8_t)acc;
   }
   const unsigned long long mask = __ballot(acc);
-  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+  if ((threadIdx.x & 63) == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+}
+
+// Launch of the random-walk step in shape (B, U).
+template <class M, int B, int U>
+smc_status launch_rw_shape(const DevModel &m, int64_t P, int64_t t, double *theta,
+                           double *logprior, double *loglik, void *state, const double *hchol,
+                           uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
+                           int64_t *n_accept, uint8_t *accepted, const KernelTimer *timer,
+                           const MomFuse *fuse, hipStream_t s) {
+  auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
+  MomFuse fm{};
+  if (fuse) {
+    if (M::D >= 32) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 32");
+    fm = *fuse;
+  }
+  const typename M::Y *yd = Eval<M>::host_y(m);
+  if (timer)
+    hipExtLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), dim3(B), 0, s, timer->start,
+                          timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
+                          run, cycle, iter, acc, accepted, fm, yd);
+  else
+    hipLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), dim3(B), 0, s, m, P, t, theta,
+                       logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted, fm,
+                       yd);
+  return launch_status("mutate");
+}
+
+// Every tuned launch shape (threads per block 64, 128 or 256; observations
+// per load batch 4, 8 or 16) of a model's random-walk step.
+template <class M>
+smc_status launch_rw_any_shape(int32_t B, int32_t U, const DevModel &m, int64_t P, int64_t t,
+                               double *theta, double *logprior, double *loglik, void *state,
+                               const double *hchol, uint64_t seed, uint64_t run, uint64_t cycle,
+                               uint64_t iter, int64_t *n_accept, uint8_t *accepted,
+                               const KernelTimer *timer, const MomFuse *fuse, hipStream_t s) {
+#define SMC_RW_SHAPE(b, u)                                                                   \
+  if (B == b && U == u)                                                                     \
+    return launch_rw_shape<M, b, u>(m, P, t, theta, logprior, loglik, state, hchol, seed, run, \
+                                    cycle, iter, n_accept, accepted, timer, fuse, s);
+  SMC_RW_SHAPE(64, 4) SMC_RW_SHAPE(64, 8) SMC_RW_SHAPE(64, 16)
+  SMC_RW_SHAPE(128, 4) SMC_RW_SHAPE(128, 8) SMC_RW_SHAPE(128, 16)
+  SMC_RW_SHAPE(256, 4) SMC_RW_SHAPE(256, 8) SMC_RW_SHAPE(256, 16)
+#undef SMC_RW_SHAPE
+  return set_error(SMC_E_UNSUPPORTED, "launch shape %d x %d", B, U);
 }
 
 // The independent Gaussian Metropolis sampler (Section 3.3's alternative):
@@ -627,22 +693,8 @@ struct OpsOf {
                               uint64_t seed, uint64_t run, uint64_t cycle, uint64_t iter,
                               int64_t *n_accept, uint8_t *accepted, const KernelTimer *timer,
                               const MomFuse *fuse, hipStream_t s) {
-    auto *acc = reinterpret_cast<unsigned long long *>(n_accept);
-    MomFuse fm{};
-    if (fuse) {
-      if (M::D >= 32) return set_error(SMC_E_UNSUPPORTED, "folded proposal scale needs d < 32");
-      fm = *fuse;
-    }
-    const typename M::Y *yd = Eval<M>::host_y(m);
-    if (timer)
-      hipExtLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, timer->start,
-                            timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
-                            run, cycle, iter, acc, accepted, fm, yd);
-    else
-      hipLaunchKernelGGL(k_mutate_rw<M>, grid_for(P, 64), dim3(64), 0, s, m, P, t, theta,
-                         logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted,
-                         fm, yd);
-    return launch_status("mutate");
+    return launch_rw_shape<M, 64, kUnroll>(m, P, t, theta, logprior, loglik, state, hchol, seed,
+                                           run, cycle, iter, n_accept, accepted, timer, fuse, s);
   }
 
   static smc_status mutate_indep(const DevModel &m, int64_t P, int64_t t, double *theta,
