@@ -5,7 +5,8 @@ Each file holds the design and outputs of one adaptive run of the oracle
 M-phase lengths R_l, the accepted-move counts of every Metropolis step, and
 the log marginal likelihood with its NSE (Section 4.2).  Only `oracle/` and
 the input generator `synthdata/` are called.  Run from the repository root:
-`python tests/golden/write_oracle_runs.py`.
+`python tests/golden/write_oracle_runs.py [workload ...]` (default: all).
+The EGARCH(2) Student-t run takes about an hour on eight host threads.
 """
 import json
 import os
@@ -18,11 +19,13 @@ sys.path.insert(0, ROOT)
 import oracle as O  # noqa: E402
 import synthdata as SD  # noqa: E402
 
-RUNS = [("egarch11", 1)]
+RUNS = [("egarch11", 1), ("egarch2t", 1)]
 
 
-def main():
+def main(names):
     for name, seed in RUNS:
+        if names and name not in names:
+            continue
         w = SD.workload(name)
         om = O.Model.from_workload(w)
         rc, rec, _ = O.run(om, w.J, w.N, seed, check_every=1, Lmax=2048, RmaxRec=64)
@@ -40,8 +43,8 @@ def main():
         path = os.path.join(HERE, f"oracle_run_{name}_seed{seed}.json")
         with open(path, "w") as f:
             json.dump(out, f, indent=1)
-        print(path, L, out["log_ml"], out["nse"])
+        print(path, L, out["log_ml"], out["nse"], flush=True)
 
 
 if __name__ == "__main__":
-    main()
+    main(sys.argv[1:])
