@@ -324,7 +324,7 @@ typedef struct {
   int32_t RmaxRec;      /* record capacity in iterations per cycle */
   int64_t max_chunk;    /* C-phase chunk bound, as given to smc_workspace_bytes */
   int32_t test_fn;      /* SMC_TEST_*: the RNE rule's functions and the moment reports */
-  int32_t reserved;     /* must be 0 */
+  int32_t graph;        /* 0: host-driven cycles; 1: device-driven (see smc_run) */
   double E2;            /* 0.90: RNE threshold after a C phase that ends at a date of
                            interest (a multiple of force_every, burn_in or T) */
   int64_t burn_in;      /* log-score burn-in date b, a date of interest (0 = none) */
@@ -362,7 +362,20 @@ typedef struct {
  * wait), once per M iteration under the RNE rule, and once after the last
  * cycle (for its numerical flags); the log-ML is queued after that.  In an adaptive random-walk run each Metropolis step also
  * computes its proposal scale (the step-size rule, V and h L, recorded in
- * rec->hchol) from the moment partials itself. */
+ * rec->hchol) from the moment partials itself.
+ *
+ * With cfg->graph = 1 the adaptive random-walk run with deterministic R_l
+ * (stop_rule 0, no moment reports or timings, kappa * Rbar <= RmaxRec,
+ * Lmax <= 4096) is driven on the device: every stopping decision, the choice
+ * of R_l, the cycle's record and the next chunk are taken by kernels, and the
+ * host launches one captured step (a C-phase chunk, the S phase, Rbar M
+ * iterations, the step's end) until the run has ended, keeping up to three
+ * steps queued and never waiting for a decision.  The results are the
+ * host-driven run's, bit for bit.  The step graph is captured on the first
+ * such call for a given model, population, record and rule set, and launched
+ * again by later calls with the same ones (whatever their Philox key); the
+ * graph reads the key, dates, counters and record slots from the workspace,
+ * so calls that overlap on one population race.  SMC_E_UNSUPPORTED for the other configurations. */
 smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                    smc_run_record *rec, void *stream);
 

@@ -52,7 +52,7 @@ class RunConfig(C.Structure):
                 ("kappa", C.c_int32), ("stop_rule", C.c_int32), ("E1", C.c_double),
                 ("Rmax", C.c_int32), ("scheme", C.c_int32), ("kernel", C.c_int32),
                 ("replay", C.c_int32), ("Lmax", C.c_int32), ("RmaxRec", C.c_int32),
-                ("max_chunk", C.c_int64), ("test_fn", C.c_int32), ("reserved", C.c_int32),
+                ("max_chunk", C.c_int64), ("test_fn", C.c_int32), ("graph", C.c_int32),
                 ("E2", C.c_double), ("burn_in", C.c_int64)]
 
 
@@ -435,17 +435,19 @@ def smc_log_score(group_logwbar, t_end, burn_in, out=None, stream=None):
 def smc_run(model, pop, seed, run=0, check_every=1, force_every=0, D1=0.5, D2=0.2, Rbar=7,
             kappa=3, stop_rule=0, E1=0.35, Rmax=100, scheme=SMC_RESAMPLE_RESIDUAL,
             kernel=SMC_KERNEL_RW, record=None, replay=False, Lmax=512, RmaxRec=128,
-            test_fn=SMC_TEST_PARAMS, E2=0.90, burn_in=0, stream=None):
+            test_fn=SMC_TEST_PARAMS, E2=0.90, burn_in=0, graph=False, stream=None):
     """Whole simulator (adaptive, or replay of ``record``'s design).  The RNE
     rule (stop_rule=1) uses ``test_fn``'s functions, with E2 after a C phase
     that ends at a date of interest; a record made with ``test_fn`` also
-    receives the moment reports and the log score over ``burn_in``."""
+    receives the moment reports and the log score over ``burn_in``.  With
+    ``graph`` the adaptive random-walk run is driven on the device (one
+    captured step graph launched until the run ends; same results)."""
     rec = record if record is not None else Record(model, pop.J, Lmax, RmaxRec)
     if rec.G and rec.test_fn != test_fn:
         raise ValueError("the record's test functions differ from test_fn")
     cfg = RunConfig(pop.J, pop.N, Rng(seed, run), check_every, force_every, D1, D2, Rbar, kappa,
                     stop_rule, E1, Rmax, scheme, kernel, 1 if replay else 0, rec.Lmax,
-                    rec.RmaxRec, pop.max_chunk, test_fn, 0, E2, burn_in)
+                    rec.RmaxRec, pop.max_chunk, test_fn, 1 if graph else 0, E2, burn_in)
     _check(lib().smc_run(model.h, C.byref(pop.c), C.byref(cfg), C.byref(rec.c), _stream(stream)),
            "smc_run")
     return rec

@@ -55,6 +55,9 @@ WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
   off += align256((size_t)(kMomBlocks + 1) * mw * mw * sizeof(double));  // + the sums
   L.rpart = off;
   off += align256((size_t)J * 2 * kDMax * sizeof(double));
+  L.cyc = off;
+  off += align256(sizeof(CycleDyn)) +
+         align256((size_t)kGraphMaxCycles * (sizeof(int64_t) + sizeof(int32_t) + sizeof(double)));
   L.wcols = off;
   L.fixed = off;
   return L;
@@ -203,6 +206,40 @@ smc_status timing_event(size_t i, hipEvent_t *out) {
 }
 
 
+// Page-locked, coherent host word through which a device-driven run reports
+// its progress (k_cycle_end); one per host thread, kept for the life of the
+// process; NULL if it cannot be had.
+uint32_t *progress_word() {
+  thread_local uint32_t *w = nullptr;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void *p = nullptr;
+    const unsigned flags = hipHostMallocCoherent | hipHostMallocMapped | hipHostMallocPortable;
+    if (hipHostMalloc(&p, 256, flags) == hipSuccess) w = static_cast<uint32_t *>(p);
+  }
+  return w;
+}
+
+// The executable step graphs of device-driven runs, keyed by every value
+// their kernels take by value (model, arrays, sizes, rules; the key and the
+// dates come from the device state), so a run with the same set-up launches
+// the graph it captured before.  A few per host thread, the oldest replaced
+// first; kept for the life of the process.
+struct StepKey {
+  int32_t device;
+  int32_t J, N, check_every, Rbar, scheme;
+  int64_t cap;
+  double D1;
+  DevModel dm;
+  const void *arrays[14];
+};
+struct StepGraph {
+  StepKey key;
+  hipGraphExec_t exec;
+};
+constexpr size_t kStepGraphs = 4;
+
 }  // namespace
 
 // The S phase that an adaptive C phase may enqueue ahead of its last host
@@ -221,6 +258,9 @@ smc_status correct_impl(const smc_model *m, smc_particles *pop, int64_t t_from, 
 }  // namespace smc
 
 using namespace smc;
+
+smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                             smc_run_record *rec, hipStream_t s);
 
 extern "C" {
 
@@ -681,12 +721,14 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     return set_error(SMC_E_INVALID_ARG, "the independent sampler records its means");
   if (cfg->kernel == SMC_KERNEL_MALA && !pop->grad)
     return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
-  if (cfg->reserved != 0) return set_error(SMC_E_INVALID_ARG, "reserved field must be 0");
+  if (cfg->graph != 0 && cfg->graph != 1)
+    return set_error(SMC_E_INVALID_ARG, "graph must be 0 or 1");
   const int32_t G = smc_num_test_functions(m, cfg->test_fn);
   if (G < 1) return set_error(SMC_E_INVALID_ARG, "test functions %d", cfg->test_fn);
   if (cfg->burn_in < 0 || cfg->burn_in >= m->dev.T)
     return set_error(SMC_E_INVALID_ARG, "burn-in date %lld", (long long)cfg->burn_in);
   hipStream_t s = as_stream(stream);
+  if (cfg->graph) return run_device_driven(m, pop, cfg, rec, s);
   const int64_t P = (int64_t)pop->J * pop->N;
   const int32_t d = m->dev.d;
   const int64_t T = m->dev.T;
@@ -895,6 +937,239 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   return SMC_OK;
 }
 
+}  // extern "C"
+
+// Device-driven adaptive run (cfg->graph): after the eager set-up (flags,
+// counters, the prior draw, k_cycle_init), one captured step -- the C-phase
+// chunk (scan, RSS columns, decision, commit), the S phase, Rbar M slots and
+// k_cycle_end -- is launched again and again on the stream.  Every decision
+// is taken and applied on the device, so the host never waits for one: it
+// keeps up to three steps queued, reads the progress word to see how far the
+// run is, and stops launching once the run has ended.  The kernels, their
+// chunks and counters are those of the host-driven run, so both give the
+// same bits.
+smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
+                             smc_run_record *rec, hipStream_t s) {
+  smc_status st;
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const int32_t d = m->dev.d;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  const int32_t kR = cfg->kappa * cfg->Rbar;
+  if (cfg->kernel != SMC_KERNEL_RW || cfg->replay || cfg->stop_rule != 0 || rec->moments ||
+      rec->mutate_ms)
+    return set_error(SMC_E_UNSUPPORTED,
+                     "device-driven runs take the adaptive random-walk simulator with "
+                     "deterministic R_l, without moment reports or timings");
+  if (!(cfg->D1 > 0.0) || cfg->Rbar < 1 || cfg->kappa < 1 || kR > cfg->RmaxRec)
+    return set_error(SMC_E_INVALID_ARG, "device-driven runs need D1 > 0, Rbar >= 1, kappa >= 1 "
+                                        "and kappa Rbar <= RmaxRec");
+  if (cfg->Lmax > kGraphMaxCycles)
+    return set_error(SMC_E_INVALID_ARG, "device-driven runs record at most %d cycles",
+                     kGraphMaxCycles);
+  if (d + 1 > kDMax)
+    return set_error(SMC_E_UNSUPPORTED, "device-driven runs need d < %d", kDMax);
+  const int64_t cap = chunk_capacity(m, pop);
+  if (cap < 1) return set_error(SMC_E_WORKSPACE, "workspace has no room for C-phase chunks");
+  uint32_t *prog = progress_word();
+  if (!prog) return set_error(SMC_E_DEVICE, "no page-locked progress word");
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess) return set_error(SMC_E_DEVICE, "hipGetDevice failed");
+
+  CycleDyn *cyc = ws_at<CycleDyn>(pop, L.cyc);
+  int64_t *t_end_d = ws_at<int64_t>(pop, L.cyc + align256(sizeof(CycleDyn)));
+  int32_t *r_d = reinterpret_cast<int32_t *>(t_end_d + kGraphMaxCycles);
+  double *rss_d = reinterpret_cast<double *>(r_d + kGraphMaxCycles);
+  int32_t *mh = ws_at<int32_t>(pop, L.small + kSmallMh);
+  int32_t *dflags = ws_at<int32_t>(pop, L.small + kSmallFlags);
+  StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
+  DevModel dm = m->dev;
+  dm.cyc = cyc;
+
+  StepKey key;
+  memset(&key, 0, sizeof key);
+  key.device = dev;
+  key.J = pop->J;
+  key.N = pop->N;
+  key.check_every = cfg->check_every;
+  key.Rbar = cfg->Rbar;
+  key.scheme = cfg->scheme;
+  key.cap = cap;
+  key.D1 = cfg->D1;
+  key.dm = dm;
+  const void *arrays[14] = {pop->theta, pop->logprior, pop->loglik, pop->state,
+                            pop->logw,  pop->grad,     pop->ancestor, pop->ws,
+                            rec->n_accept, rec->hchol, rec->group_logwbar, prog,
+                            nullptr,    nullptr};
+  memcpy(key.arrays, arrays, sizeof arrays);
+  thread_local std::vector<StepGraph> graphs;
+  hipGraphExec_t exec = nullptr;
+  for (const StepGraph &g : graphs)
+    if (memcmp(&g.key, &key, sizeof key) == 0) exec = g.exec;
+  if (!exec) {
+    hipStream_t cs = nullptr;
+    if (hipStreamCreateWithFlags(&cs, hipStreamNonBlocking) != hipSuccess)
+      return set_error(SMC_E_DEVICE, "creating the capture stream failed");
+    hipGraph_t graph = nullptr;
+    auto capture = [&]() -> smc_status {
+      smc_status e;
+      double *W = ws_at<double>(pop, L.wcols);
+      double *rsscols = ws_at<double>(pop, L.rsscols);
+      if ((e = launch_cscan(dm, P, pop->theta, pop->state, pop->logw, 0, 0, cfg->check_every, 0,
+                            false, W, cs)) ||
+          (e = launch_rss_cols(W, P, cap, rsscols, cs, &cyc->nc)) ||
+          (e = launch_find_stop(rsscols, 0, 0, 0, cfg->check_every, 0, cfg->D1, stop_dev, cs,
+                                nullptr, 0, nullptr, cyc)) ||
+          (e = launch_ccommit(dm, P, pop->theta, pop->state, pop->logw, pop->loglik, 0, 0, false,
+                              cs, &stop_dev->t_commit)) ||
+          (e = launch_resample(pop->logw, pop->J, pop->N, cfg->scheme, 0, 0, 0, pop->ancestor,
+                               ws_at<double>(pop, L.cum), dflags, d, m->dev.S, state_bytes(m),
+                               pop->theta, pop->logprior, pop->loglik, pop->state, pop->grad,
+                               ws_at<double>(pop, L.gather), cs, nullptr, rec->group_logwbar,
+                               cyc)))
+        return e;
+      for (int32_t k = 1; k <= cfg->Rbar; ++k) {
+        MomArgs ma{};
+        ma.theta = pop->theta;
+        ma.P = P;
+        ma.d = d;
+        ma.target_permille = 250;
+        ma.part = ws_at<double>(pop, L.mpart);
+        ma.mh = mh;
+        ma.flags = dflags;
+        ma.cyc = cyc;
+        ma.slot = k;
+        MomFuse fm{};
+        int64_t nb = 0;
+        if ((e = launch_moment_partials(ma, &fm.part, nb, cs))) return e;
+        fm.nb = (int32_t)nb;
+        fm.target_permille = 250;
+        fm.mh_out = mh;  // the kernel picks the slot pair and rule for its iteration
+        fm.hchol_out = rec->hchol;
+        fm.flags = dflags;
+        if ((e = launch_mutate_rw(dm, P, m->dev.T, pop->theta, pop->logprior, pop->loglik,
+                                  pop->state, nullptr, 0, 0, 0, (uint64_t)k, rec->n_accept,
+                                  nullptr, cs, nullptr, &fm)))
+          return e;
+      }
+      return launch_cycle_end(cyc, t_end_d, r_d, rss_d, dflags, prog, cs);
+    };
+    if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
+      (void)hipStreamDestroy(cs);
+      return set_error(SMC_E_DEVICE, "beginning the step capture failed");
+    }
+    st = capture();
+    const hipError_t ec = hipStreamEndCapture(cs, &graph);
+    (void)hipStreamDestroy(cs);
+    if (st || ec != hipSuccess || !graph) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return st ? st : set_error(SMC_E_DEVICE, "capturing the step failed");
+    }
+    const hipError_t ei = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (ei != hipSuccess) return set_error(SMC_E_DEVICE, "instantiating the step failed");
+    if (graphs.size() >= kStepGraphs) {
+      (void)hipGraphExecDestroy(graphs.front().exec);
+      graphs.erase(graphs.begin());
+    }
+    graphs.push_back(StepGraph{key, exec});
+  }
+
+  // eager set-up, as the host-driven run does it
+  if ((st = fill_i32(dflags, 1, 0, s)) ||
+      (st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s)) ||
+      (st = smc_init_from_prior(m, pop, cfg->rng, s)))
+    return st;
+  CycleDyn init{};
+  init.seed = cfg->rng.seed;
+  init.run = cfg->rng.run;
+  init.T = m->dev.T;
+  init.P = P;
+  init.check_every = cfg->check_every;
+  init.force_every = cfg->force_every;
+  init.burn_in = cfg->burn_in;
+  init.cap = cap;
+  init.D2 = cfg->D2;
+  init.Rbar = cfg->Rbar;
+  init.kR = kR;
+  init.Lmax = cfg->Lmax;
+  init.rec_stride = cfg->RmaxRec;
+  init.m_slots = cfg->Rbar;
+  init.J = pop->J;
+  __atomic_store_n(prog, 0u, __ATOMIC_RELEASE);
+  if ((st = launch_cycle_init(cyc, init, s))) return st;
+
+  // Steps in flight: at most kAhead beyond the last one seen to finish.  The
+  // stream is polled every millisecond while the word stands still; once all
+  // its work has completed, the word gets 10 more ms before the run fails.
+  // Every step but the last few advances the committed date or runs M
+  // iterations, so a run takes at most T chunks and kappa steps of M slots
+  // per cycle: more launches than that mean the run is not progressing.
+  constexpr uint32_t kAhead = 3;
+  const int64_t max_steps = m->dev.T + (int64_t)cfg->Lmax * cfg->kappa + kAhead + 1;
+  uint32_t launched = 0, word = 0;
+  using clock = std::chrono::steady_clock;
+  for (;;) {
+    word = __atomic_load_n(prog, __ATOMIC_ACQUIRE);
+    if (word & 3u) break;
+    if (launched - (word >> 2) < kAhead) {
+      if ((int64_t)launched >= max_steps) {
+        (void)hipStreamSynchronize(s);
+        return set_error(SMC_E_DEVICE, "the device-driven run did not end in %lld steps",
+                         (long long)max_steps);
+      }
+      if (hipGraphLaunch(exec, s) != hipSuccess)
+        return set_error(SMC_E_DEVICE, "launching a step failed");
+      ++launched;
+      continue;
+    }
+    auto next_poll = clock::now() + std::chrono::milliseconds(1);
+    clock::time_point idle_since{};
+    bool idle = false;
+    const uint32_t seen = word;
+    while ((word = __atomic_load_n(prog, __ATOMIC_ACQUIRE)) == seen) {
+      const auto now = clock::now();
+      if (now < next_poll) continue;
+      next_poll = now + std::chrono::milliseconds(1);
+      if (!idle) {
+        const hipError_t q = hipStreamQuery(s);
+        if (q == hipErrorNotReady) continue;
+        if (q != hipSuccess) return set_error(SMC_E_DEVICE, "a step failed: %s",
+                                              hipGetErrorString(q));
+        idle = true;
+        idle_since = now;
+      } else if (now - idle_since > std::chrono::milliseconds(10)) {
+        return set_error(SMC_E_DEVICE, "the device-driven run stopped reporting progress");
+      }
+    }
+  }
+  CycleDyn fin{};
+  if (hipMemcpyAsync(&fin, cyc, sizeof fin, hipMemcpyDeviceToHost, s) != hipSuccess ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "reading the run's state failed");
+  const int32_t Ln = fin.l;
+  if (Ln > 0 &&
+      (hipMemcpyAsync(rec->t_end, t_end_d, Ln * sizeof(int64_t), hipMemcpyDeviceToHost, s) !=
+           hipSuccess ||
+       hipMemcpyAsync(rec->R, r_d, Ln * sizeof(int32_t), hipMemcpyDeviceToHost, s) != hipSuccess ||
+       hipMemcpyAsync(rec->rss, rss_d, Ln * sizeof(double), hipMemcpyDeviceToHost, s) !=
+           hipSuccess ||
+       hipStreamSynchronize(s) != hipSuccess))
+    return set_error(SMC_E_DEVICE, "reading the record failed");
+  rec->L = Ln;
+  rec->evals = fin.evals;
+  rec->mh_steps = fin.steps;
+  if (fin.err == 2) return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", fin.flags, Ln);
+  if (fin.err) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
+  if ((st = smc_log_ml(Ln, pop->J, rec->group_logwbar, rec->log_ml, s))) return st;
+  if (rec->log_score && cfg->burn_in > 0 &&
+      (st = smc_log_score(Ln, pop->J, rec->group_logwbar, rec->t_end, cfg->burn_in,
+                          rec->log_score, s)))
+    return st;
+  return SMC_OK;
+}
+
+extern "C" {
+
 smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                           uint64_t seed2, smc_run_record *rec1, smc_run_record *rec2,
                           double *seconds, void *stream) {
@@ -1000,7 +1275,7 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         return set_error(SMC_E_WORKSPACE, "run %d: the Langevin kernel needs %zu workspace bytes",
                          i, need);
     }
-    if (c.burn_in != 0 || r.moments || r.log_score || c.reserved != 0)
+    if (c.burn_in != 0 || r.moments || r.log_score || c.graph != 0)
       return set_error(SMC_E_UNSUPPORTED, "batched runs: no burn-in, moment reports or log score");
     if ((c.replay != 0) != replay)
       return set_error(SMC_E_INVALID_ARG, "all runs of a batch adapt, or all replay");

@@ -16,6 +16,8 @@ constexpr int kBlock = 256;    // threads per block of the bandwidth-shaped kern
 // Philox purposes (counter word 3, low byte).
 enum Purpose : uint64_t { kPrior = 1, kResample = 2, kProposal = 3, kAccept = 4 };
 
+struct CycleDyn;
+
 // Everything a kernel needs to know about a model, passed by value.
 struct DevModel {
   int32_t kind;
@@ -32,7 +34,51 @@ struct DevModel {
   const double *y;
   const float *y32;
   const double *X;
+  const CycleDyn *cyc;  // device-driven cycle (graph steps), else NULL
 };
+
+// State of an adaptive run whose C/S/M cycles are driven on the device
+// (smc_run with cfg->graph): one captured step (a C-phase chunk, the S phase,
+// up to m_slots M iterations, then k_cycle_end) is replayed until the run
+// ends.  The step's kernels read their dates, counters and record slots here
+// instead of taking them by value, and return at once when their gate is 0.
+struct CycleDyn {
+  // fixed for the run
+  uint64_t seed, run;  // the Philox key
+  int64_t T, P, check_every, force_every, burn_in, cap;
+  double D2;
+  int32_t Rbar, kR, Lmax, rec_stride, m_slots, J;
+  // the chunk of this step
+  int64_t t;        // committed date (the chunk starts here)
+  int64_t t1;       // end of the chunk
+  int64_t t_stop;   // last date of this cycle's C phase
+  int64_t t_phase;  // date this cycle's C phase began
+  int64_t chunk;    // length bound of this chunk
+  int64_t t_new;    // the decided date (the chunk's commit date; the M phase's date)
+  int64_t last_len; // length of the previous C phase
+  int64_t evals;    // particle x observation evaluations so far
+  int64_t steps;    // Metropolis iterations so far
+  double rss;       // RSS at the decided date
+  int32_t nc;       // checked dates in (t, t1]
+  int32_t l;        // cycle index (its Philox counter is l + 1)
+  int32_t zero_first;
+  // gates: the C-phase kernels (go_c), the scan (go_scan = go_c and nc > 0),
+  // the S phase (go_s) and the M slots (go_m); slot k runs iteration r0 + k
+  // while r0 + k <= R
+  int32_t go_c, go_scan, go_s, go_m;
+  int32_t r0, R;
+  int32_t done;     // 1: the run reached T
+  int32_t err;      // 1: the record is full, 2: a numerical flag was raised
+  int32_t flags;    // the flags word when err = 2
+  uint32_t progress;  // steps that did work
+};
+
+__device__ __forceinline__ bool m_slot_off(const CycleDyn *c, int32_t k) {
+  return c && (!c->go_m || c->r0 + k > c->R);
+}
+
+// Cycles a graph-replayed run records on the device.
+constexpr int32_t kGraphMaxCycles = 4096;
 
 // Workspace carve-up (offsets in bytes, each 256-aligned).  The speculative
 // C-phase columns come last, so their capacity follows from the workspace size.
@@ -43,6 +89,7 @@ struct WsLayout {
   size_t cum;      // [P] doubles (resample running sums)
   size_t mpart;    // [kMomBlocks + 1][W^2] doubles (moment partials and their sum)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
+  size_t cyc;      // CycleDyn, then t_end [kGraphMaxCycles] int64, R [..] int32, rss [..]
   size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
   size_t fixed;    // bytes before wcols
 };

@@ -10,6 +10,8 @@
 
 #include <type_traits>
 
+#include <algorithm>
+
 #include "common.h"
 #include "launch.h"
 #include "model.h"
@@ -121,9 +123,14 @@ __device__ __forceinline__ void rss_block_sum2(double &a, double &b, double *lds
 // (sum e)^2 / (P sum e^2) with e = exp(logw - max).  Columns of up to
 // kRssRegs * kRssBlock values: the maximum first, then the sums, the values
 // held in registers between the two passes.
-__global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss) {
+// Block b takes columns b, b + gridDim.x, ... below ncols (or *ncols_dev, the
+// count of a device-driven chunk).
+__global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, double *rss,
+                                                   int32_t ncols, const int32_t *ncols_dev) {
   __shared__ double sh[2 * (kRssBlock / 64)];
-  const double *w = W + blockIdx.x * P;
+  const int32_t nc = ncols_dev ? *ncols_dev : ncols;
+  for (int32_t col = blockIdx.x; col < nc; col += gridDim.x) {
+  const double *w = W + (int64_t)col * P;
   double v[kRssRegs];
   double mx = -INFINITY;
 #pragma unroll
@@ -144,7 +151,8 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
     }
   }
   rss_block_sum2(s1, s2, sh);
-  if (threadIdx.x == 0) rss[blockIdx.x] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
+  if (threadIdx.x == 0) rss[col] = (mx > -INFINITY) ? s1 * s1 / ((double)P * s2) : 0.0;
+  }  // every LDS write above follows a barrier, so the columns need none between them
 }
 
 // Longer columns in one pass: each thread keeps a running maximum m with
@@ -163,9 +171,13 @@ __device__ __forceinline__ Lse3 lse3_shfl_xor(const Lse3 &a, int off) {
   return Lse3{__shfl_xor(a.m, off, 64), __shfl_xor(a.s1, off, 64), __shfl_xor(a.s2, off, 64)};
 }
 
-__global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t P, double *rss) {
+__global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t P, double *rss,
+                                                        int32_t ncols,
+                                                        const int32_t *ncols_dev) {
   __shared__ Lse3 sh[kRssBlock / 64];
-  const double *w = W + blockIdx.x * P;
+  const int32_t nc = ncols_dev ? *ncols_dev : ncols;
+  for (int32_t col = blockIdx.x; col < nc; col += gridDim.x) {
+  const double *w = W + (int64_t)col * P;
   constexpr int kChunk = 16;
   Lse3 acc{-INFINITY, 0.0, 0.0};
   for (int64_t p0 = threadIdx.x; p0 < P; p0 += (int64_t)kChunk * kRssBlock) {
@@ -198,7 +210,9 @@ __global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t
 #pragma unroll
     for (int off = 8; off > 0; off >>= 1) t = lse3_merge(t, lse3_shfl_xor(t, off));
     if (threadIdx.x == 0)
-      rss[blockIdx.x] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
+      rss[col] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
+  }
+  __syncthreads();  // the first wave's reads of sh before the next column's writes
   }
 }
 
@@ -207,12 +221,23 @@ __global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t
 // holds date first + c * check_every, the multiples of check_every after t
 // up to t1, and t_max last when it is not a multiple.  With host_slot, the
 // decision and the flags word also go to host memory, every 32-bit word of
-// them paired with seq in an 8-byte word (DecisionSlot).
+// them paired with seq in an 8-byte word (DecisionSlot).  With cyc (a
+// device-driven chunk) the chunk comes from there, a chunk without checked
+// dates commits to t1 and does not end the phase, and the decision opens the
+// S and M phases of a phase that ended: R = kappa Rbar iterations when the
+// RSS is below D2, else Rbar (Section 3.3).
 __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc, int64_t t,
                                                   int64_t t1, int64_t check_every, int64_t t_max,
                                                   double rss_min, StopInfo *out,
                                                   DecisionSlot *host_slot, uint32_t seq,
-                                                  const int32_t *flags) {
+                                                  const int32_t *flags, CycleDyn *cyc) {
+  if (cyc) {
+    if (!cyc->go_c) return;
+    nc = cyc->nc;
+    t = cyc->t;
+    t1 = cyc->t1;
+    t_max = cyc->t_stop;
+  }
   int first = -1;
   for (int base = 0; base < nc; base += 64) {
     const int c = base + (int)threadIdx.x;
@@ -228,10 +253,19 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
     const int col = first >= 0 ? first : nc - 1;
     StopInfo o;
     o.t_commit = first < 0 ? t1 : (first < n_regular ? first_date + first * check_every : t_max);
-    o.rss = rss[col];
+    o.rss = nc > 0 ? rss[col] : (cyc ? cyc->rss : 1.0);
     o.below = first >= 0;
-    o.ends = first >= 0 || t1 >= t_max;
+    o.ends = nc > 0 && (first >= 0 || t1 >= t_max);
     *out = o;
+    if (cyc) {
+      const int32_t R = o.ends ? (o.rss < cyc->D2 ? cyc->kR : cyc->Rbar) : 0;
+      cyc->t_new = o.t_commit;
+      cyc->rss = o.rss;
+      cyc->R = R;
+      cyc->r0 = 0;
+      cyc->go_s = o.ends;
+      cyc->go_m = o.ends;
+    }
     if (host_slot) {
       const int32_t fl = *flags;
       const uint64_t tc = (uint64_t)o.t_commit;
@@ -242,6 +276,106 @@ __global__ void __launch_bounds__(64) k_find_stop(const double *rss, int32_t nc,
       dst[2] = make_uint4(seq, (uint32_t)fl, seq, (uint32_t)(o.ends | (o.below << 1)));
     }
   }
+}
+
+// ------------------------------------------------ device-driven cycles --
+// Last date of the C phase that starts at t: T, the next multiple of
+// force_every, or the burn-in date, whichever comes first.
+__device__ __forceinline__ int64_t cycle_stop(const CycleDyn &c, int64_t t) {
+  int64_t ts = c.T;
+  if (c.force_every > 0) ts = min(ts, (t / c.force_every + 1) * c.force_every);
+  if (c.burn_in > t) ts = min(ts, c.burn_in);
+  return ts;
+}
+
+// The chunk (t, t1] of length at most c.chunk, and its checked dates: the
+// multiples of check_every, and the phase's last date.
+__device__ __forceinline__ void cycle_open_chunk(CycleDyn &c) {
+  c.t1 = min(c.t + c.chunk, c.t_stop);
+  const int64_t ce = c.check_every;
+  c.nc = (int32_t)(c.t1 / ce - c.t / ce + ((c.t1 == c.t_stop && c.t_stop % ce != 0) ? 1 : 0));
+  c.go_c = 1;
+  c.go_scan = c.nc > 0;
+}
+
+// Start of a device-driven run: the fixed fields come from the host, the
+// first chunk opens at t = 0.
+__global__ void k_cycle_init(CycleDyn *c, CycleDyn init) {
+  if (threadIdx.x != 0) return;
+  init.t = 0;
+  init.t_phase = 0;
+  init.l = 0;
+  init.zero_first = 1;
+  init.last_len = 0;
+  init.evals = 0;
+  init.steps = 0;
+  init.rss = 1.0;
+  init.go_s = init.go_m = 0;
+  init.r0 = init.R = 0;
+  init.done = init.err = init.flags = 0;
+  init.progress = 0;
+  init.t_stop = cycle_stop(init, 0);
+  init.chunk = min<int64_t>(16, init.cap);
+  cycle_open_chunk(init);
+  *c = init;
+}
+
+// End of a device-driven step.  After the last M slot of a cycle: record the
+// cycle (date, iterations, RSS), count its evaluations, stop on a raised
+// flag, at T or with the record full, else open the next cycle's C phase
+// with a chunk twice the last phase's length plus 16 (the eager driver's
+// speculation, so the chunks and their rounding are the same).  After M
+// slots that leave iterations over: the next step runs only M slots.  After
+// a chunk that did not end the phase: the next chunk, twice as long.  The
+// host follows the run through *host: progress << 2 | err << 1 | done.
+__global__ void k_cycle_end(CycleDyn *cp, int64_t *t_end, int32_t *r_rec, double *rss_rec,
+                            const int32_t *flags, uint32_t *host) {
+  if (threadIdx.x != 0) return;
+  CycleDyn c = *cp;
+  if (c.done || c.err) return;
+  if (c.go_m) {
+    const int32_t r_done = c.r0 + c.m_slots;
+    if (r_done < c.R) {
+      c.r0 = r_done;
+      c.go_c = c.go_scan = c.go_s = 0;
+    } else {
+      const int32_t l = c.l;
+      t_end[l] = c.t_new;
+      r_rec[l] = c.R;
+      rss_rec[l] = c.rss;
+      c.evals += c.P * (c.t_new - c.t_phase) + (int64_t)c.R * c.P * c.t_new;
+      c.steps += c.R;
+      c.last_len = c.t_new - c.t_phase;
+      c.t = c.t_phase = c.t_new;
+      c.l = l + 1;
+      c.zero_first = 1;
+      c.go_c = c.go_scan = c.go_s = c.go_m = 0;
+      c.r0 = c.R = 0;
+      const int32_t fl = *flags;
+      if (fl) {
+        c.err = 2;
+        c.flags = fl;
+      } else if (c.t >= c.T) {
+        c.done = 1;
+      } else if (c.l >= c.Lmax) {
+        c.err = 1;
+      } else {
+        c.t_stop = cycle_stop(c, c.t);
+        c.chunk = min(max<int64_t>(16, 2 * c.last_len + 16), c.cap);
+        cycle_open_chunk(c);
+      }
+    }
+  } else if (c.go_c) {
+    c.t = c.t_new;
+    c.zero_first = 0;
+    c.chunk = min(2 * c.chunk, c.cap);
+    cycle_open_chunk(c);
+  }
+  c.progress += 1;
+  *cp = c;
+  __threadfence_system();
+  __hip_atomic_store(host, (c.progress << 2) | (c.err ? 2u : 0u) | (c.done ? 1u : 0u),
+                     __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
 // ------------------------------------------------------------ S phase (a3) --
@@ -533,8 +667,16 @@ __global__ void __launch_bounds__(kSBlock) k_resample(const double *logw, int32_
                                                       uint64_t cycle, int32_t *anc,
                                                       double *cum_ws, int32_t *flags,
                                                       GatherArgs g, const int32_t *go,
-                                                      double *group_logwbar) {
+                                                      double *group_logwbar,
+                                                      const CycleDyn *cyc) {
   if (go && *go == 0) return;  // enqueued ahead of a C phase that did not end
+  if (cyc) {  // a device-driven cycle: its S phase, key, counter and record row
+    if (!cyc->go_s) return;
+    seed = cyc->seed;
+    run = cyc->run;
+    cycle = (uint64_t)(cyc->l + 1);
+    group_logwbar += (int64_t)cyc->l * gridDim.x;
+  }
   extern __shared__ double lds_dyn[];
   __shared__ double shd[kSWaves];
   __shared__ int32_t shi[kSWaves];
@@ -674,7 +816,9 @@ __global__ void __launch_bounds__(kSBlock) k_resample(const double *logw, int32_
 // one W x W partial matrix.
 template <int W>
 __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_t P, int32_t d,
-                                                     int64_t chunk, double *part) {
+                                                     int64_t chunk, double *part,
+                                                     const CycleDyn *cyc, int32_t slot) {
+  if (m_slot_off(cyc, slot)) return;  // an unused M slot of a device-driven cycle
   constexpr int NT = W / 16;
   constexpr int NA = NT == 1 ? 1 : 3;  // tiles accumulated
   __shared__ double red[4][W * W];
@@ -756,7 +900,8 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
 // order (its loads in flight together), and the four subtotals are added in
 // wave order.
 __global__ void __launch_bounds__(256) k_mom_sum(const double *part, int32_t nb, int32_t n,
-                                                 double *out) {
+                                                 double *out, const CycleDyn *cyc, int32_t slot) {
+  if (m_slot_off(cyc, slot)) return;
   __shared__ double sub[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + lane;
@@ -1086,24 +1231,42 @@ smc_status launch_test_fns(const DevModel &m, int64_t P, const double *theta, co
 
 // ------------------------------------------------- model-independent ones --
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
-                           hipStream_t s) {
+                           hipStream_t s, const int32_t *ncols_dev) {
   if (ncols <= 0) return SMC_OK;
+  if (ncols > kMaxChunk)
+    return set_error(SMC_E_INVALID_ARG, "RSS of %lld columns", (long long)ncols);
+  // a device-driven chunk: up to ncols columns, a block per column up to a
+  // few per CU
+  const unsigned grid = (unsigned)(ncols_dev ? std::min<int64_t>(ncols, 512) : ncols);
   if (P <= (int64_t)kRssRegs * kRssBlock)
-    hipLaunchKernelGGL(k_rss_cols, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
+    hipLaunchKernelGGL(k_rss_cols, dim3(grid), dim3(kRssBlock), 0, s, W, P, rss, (int32_t)ncols,
+                       ncols_dev);
   else
-    hipLaunchKernelGGL(k_rss_cols_long, dim3((unsigned)ncols), dim3(kRssBlock), 0, s, W, P, rss);
+    hipLaunchKernelGGL(k_rss_cols_long, dim3(grid), dim3(kRssBlock), 0, s, W, P, rss,
+                       (int32_t)ncols, ncols_dev);
   return launch_status("correct/rss");
 }
 
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
                             int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
                             hipStream_t s, DecisionSlot *host_slot, uint32_t seq,
-                            const int32_t *flags) {
-  if (nc < 1 || nc > kMaxChunk)
+                            const int32_t *flags, CycleDyn *cyc) {
+  if (!cyc && (nc < 1 || nc > kMaxChunk))
     return set_error(SMC_E_INVALID_ARG, "stop search over %lld columns", (long long)nc);
   hipLaunchKernelGGL(k_find_stop, dim3(1), dim3(64), 0, s, rss, (int32_t)nc, t, t1, check_every,
-                     t_max, rss_min, out, host_slot, seq, flags);
+                     t_max, rss_min, out, host_slot, seq, flags, cyc);
   return launch_status("correct/find_stop");
+}
+
+smc_status launch_cycle_init(CycleDyn *c, const CycleDyn &init, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_init, dim3(1), dim3(64), 0, s, c, init);
+  return launch_status("cycle/init");
+}
+
+smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double *rss_rec,
+                            const int32_t *flags, uint32_t *host, hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, s, c, t_end, r_rec, rss_rec, flags, host);
+  return launch_status("cycle/end");
 }
 
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
@@ -1117,7 +1280,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
                            double *grad, double *tmp, hipStream_t s, const int32_t *go,
-                           double *group_logwbar) {
+                           double *group_logwbar, const CycleDyn *cyc) {
   const int64_t P = (int64_t)J * N;
   GatherArgs g{anc, P, d, S, st_bytes, grad != nullptr ? 1 : 0, theta, logprior, loglik, grad,
                state, tmp};
@@ -1127,7 +1290,7 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
                                            kGatherLdsBytes
                                      : (size_t)N * sizeof(int32_t);
   hipLaunchKernelGGL(k_resample, dim3(J), dim3(kSBlock), lds, s, logw, N, scheme, seed, run, cycle,
-                     anc, cum_ws, flags, g, go, group_logwbar);
+                     anc, cum_ws, flags, g, go, group_logwbar, cyc);
   return launch_status("resample");
 }
 
@@ -1153,10 +1316,10 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
     return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
   if (a.d + 1 <= 16) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part);
+                       a.d, chunk, a.part, a.cyc, a.slot);
   } else {
     hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part);
+                       a.d, chunk, a.part, a.cyc, a.slot);
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
@@ -1165,7 +1328,8 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   } else {
     // sums into the slot after the partials, then the final block reads them
     double *sums = a.part + nb * 1024;
-    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums);
+    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums,
+                     a.cyc, a.slot);
     if ((st = launch_status("particle_moments/sum"))) return st;
     MomArgs f = a;
     f.part = sums;
@@ -1184,16 +1348,17 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   *part = a.part;
   if (a.d + 1 <= 16) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part);
+                       a.d, chunk, a.part, a.cyc, a.slot);
     return launch_status("particle_moments/partial");
   }
   hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
-                     chunk, a.part);
+                     chunk, a.part, a.cyc, a.slot);
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
   // summed into the slot after the partials, as launch_moments does
   double *sums = a.part + nb * 1024;
-  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums);
+  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums,
+                     a.cyc, a.slot);
   *part = sums;
   nb = 1;
   return launch_status("particle_moments/sum");

@@ -100,27 +100,38 @@ smc_status launch_cscan(const DevModel &m, int64_t P, const double *theta, const
 smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, void *state,
                           double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
                           hipStream_t s, const int64_t *t1_dev = nullptr);
+// RSS of ncols columns; with ncols_dev (a device-driven chunk) of the first
+// *ncols_dev <= ncols columns.
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
-                           hipStream_t s);
+                           hipStream_t s, const int32_t *ncols_dev = nullptr);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
 // The stopping decision over nc RSS columns of the chunk (t, t1] into *out,
 // and with *flags into page-locked host memory host_slot (tagged with seq)
-// when that is not NULL.
+// when that is not NULL; with cyc, the chunk and decision of a device-driven
+// cycle (the by-value chunk arguments are then unused).
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,
                             int64_t check_every, int64_t t_max, double rss_min, StopInfo *out,
                             hipStream_t s, DecisionSlot *host_slot = nullptr, uint32_t seq = 0,
-                            const int32_t *flags = nullptr);
+                            const int32_t *flags = nullptr, CycleDyn *cyc = nullptr);
 // Resampling and the replacement of every particle by its ancestor, one block
 // per group; with `go` (device flag, may be NULL) the kernel does nothing
 // while *go is 0; with group_logwbar (may be NULL) it also writes each
-// group's log mean weight, as launch_group_logwbar does.
+// group's log mean weight, as launch_group_logwbar does.  With cyc, the S
+// phase of a device-driven cycle: it runs when the step's C phase ended, with
+// counter l + 1 and group weights in record row l.
 smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t scheme,
                            uint64_t seed, uint64_t run, uint64_t cycle, int32_t *anc,
                            double *cum_ws, int32_t *flags, int32_t d, int32_t S, int32_t st_bytes,
                            double *theta, double *logprior, double *loglik, void *state,
                            double *grad, double *tmp, hipStream_t s,
-                           const int32_t *go = nullptr, double *group_logwbar = nullptr);
+                           const int32_t *go = nullptr, double *group_logwbar = nullptr,
+                           const CycleDyn *cyc = nullptr);
+// Device-driven cycles (CycleDyn): the state's start, and the end of a step
+// (record, counters, the next chunk; progress word in mapped host memory).
+smc_status launch_cycle_init(CycleDyn *c, const CycleDyn &init, hipStream_t s);
+smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double *rss_rec,
+                            const int32_t *flags, uint32_t *host, hipStream_t s);
 struct MomArgs {
   const double *theta;
   int64_t P;
@@ -130,9 +141,10 @@ struct MomArgs {
   int32_t *mh;              // step size in tenths (device)
   const int64_t *prev_nacc; // accepts of the previous iteration, or NULL
   int32_t mh_reset;         // > 0: set mh to this value first
-  int32_t pad;
+  int32_t slot;             // with cyc: the M slot of a device-driven step (partials only)
   double *mean_out, *cov_out, *hchol;
   int32_t *flags;
+  const CycleDyn *cyc;      // device-driven cycle, else NULL
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
 // Only the partial sums of launch_moments, for a step that folds the rest in

@@ -74,6 +74,13 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
                                               const typename M::Y *__restrict__ ydata) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
+  if (const CycleDyn *c = dm.cyc) {  // a device-driven chunk
+    if (!c->go_scan) return;
+    t0 = c->t;
+    t1 = c->t1;
+    t_max = c->t_stop;
+    zero_first = c->zero_first;
+  }
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
   double th[M::D];
@@ -116,7 +123,8 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
 }
 
 // Commit: advance from t0 to t1 (or to *t1_dev when given), adding the log
-// densities to logw and loglik.
+// densities to logw and loglik.  A device-driven chunk takes t0, t1 and
+// zero_first from dm.cyc.
 template <class M>
 __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const double *theta,
                                                 void *state, double *logw, double *loglik,
@@ -125,6 +133,12 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
                                                 const typename M::Y *__restrict__ ydata) {
   const int64_t p = blockIdx.x * 64ll + threadIdx.x;
   if (p >= P) return;
+  if (const CycleDyn *c = dm.cyc) {
+    if (!c->go_c) return;
+    t0 = c->t;
+    t1 = c->t1;
+    zero_first = c->zero_first;
+  }
   if (t1_dev) t1 = min(t1, *t1_dev);
   using R = typename M::R;
   constexpr int SR = Eval<M>::SR;
@@ -228,7 +242,10 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
 }
 
 // B threads (B/64 waves) per block, observations loaded U at a time; the
-// launch shape does not change any result.
+// launch shape does not change any result.  In a device-driven cycle
+// (dm.cyc) the launch is M slot `iter` of its step: it runs iteration
+// r = r0 + iter of the cycle while r <= R, at the cycle's date and key, with
+// the record slots, step-size slots and rule of that iteration.
 template <class M, int B = 64, int U = kUnroll>
 __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
                                                  double *logprior, double *loglik, void *state,
@@ -245,6 +262,23 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
   constexpr bool kCanFuse = D < 32;
   __shared__ double Ms[kCanFuse ? W * W : 1], Ls[kCanFuse ? W * chol_ld<W>() : 1], sh_h;
   __shared__ int sh_ok;
+  if (const CycleDyn *c = dm.cyc) {
+    if (m_slot_off(c, (int32_t)iter)) return;
+    const int32_t r = c->r0 + (int32_t)iter;
+    iter = (uint64_t)r;
+    t = c->t_new;
+    seed = c->seed;
+    run = c->run;
+    cycle = (uint64_t)(c->l + 1);
+    const int64_t slot = (int64_t)c->l * c->rec_stride + (r - 1);
+    n_accept += slot;
+    fm.hchol_out += slot * D * D;
+    fm.prev_nacc = r == 1 ? nullptr : reinterpret_cast<const int64_t *>(n_accept) - 1;
+    fm.mh_reset = r == 1 ? 5 : 0;
+    int32_t *mh = fm.mh_out;  // the two step-size slots, alternating with r
+    fm.mh_in = (r & 1) ? mh + 1 : mh;
+    fm.mh_out = (r & 1) ? mh : mh + 1;
+  }
   const int64_t p = blockIdx.x * (int64_t)B + threadIdx.x;
   bool fused = false, chol_ok = true;
   double h = 0.0;
