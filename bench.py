@@ -385,6 +385,46 @@ def run_batched(steps):
                               ops_source="scope table"))
 
 
+def run_device_driven(name, precision, steps, warmup):
+    """Whole adaptive runs driven on the device (smc_run with graph=True: one
+    captured step graph launched until the run ends) beside the same runs
+    driven from the host, with the same seeds: mean ms per run each, and
+    whether the two agree to the bit (log ML, cycles)."""
+    import torch
+
+    import paper_1304_4334_amd as S
+    import synthdata as SD
+    from paper_1304_4334_amd import tune
+
+    w = SD.workload(name)
+    prec = S.SMC_FP64 if precision == "fp64" else S.SMC_FP32
+    m = S.Model.from_workload(w, precision=prec)
+    tune.apply(m, name, precision)
+    pop = S.Population(m, w.J, w.N, max_chunk=1024)
+    out = {}
+    mls = {}
+    for mode, graph in (("host_driven", False), ("device_driven", True)):
+        rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64)
+        for i in range(warmup):
+            S.smc_run(m, pop, seed=10_000 + i, record=rec, graph=graph)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        got = []
+        for k in range(steps):
+            S.smc_run(m, pop, seed=1 + k, record=rec, graph=graph)
+            s = rec.summary()
+            got.append((s["log_ml"], s["L"], s["mh_steps"]))
+        torch.cuda.synchronize()
+        secs = time.perf_counter() - t0
+        mls[mode] = got
+        out[mode] = dict(ms_per_run=1e3 * secs / steps)
+        log(f"[bench] {name}/{precision} {mode}: {1e3 * secs / steps:.2f} ms per run")
+    out["same_results"] = mls["host_driven"] == mls["device_driven"]
+    out["device_over_host_time"] = (out["device_driven"]["ms_per_run"]
+                                    / out["host_driven"]["ms_per_run"])
+    return out
+
+
 def run_variants(name, precision, steps):
     """Whole adaptive runs of one workload under each option of the method
     beside the default (residual resampling, deterministic R, RW steps):
@@ -610,8 +650,10 @@ def main():
 
     main_run = run_gpu(args.workload, precision, args.steps, args.warmup)
     comp = {}
-    tnse = batched = variants = None
+    tnse = batched = variants = driven = None
     if not args.no_companions and args.workload == "egarch2t":
+        driven = {f"{n}_{p}": run_device_driven(n, p, args.steps, args.warmup)
+                  for n, p in (("egarch2t", "fp32"), ("egarch11", "fp64"))}
         for prec in ("fp64", "fp32"):
             comp[f"egarch11_{prec}"] = run_gpu("egarch11", prec, args.steps, args.warmup)
         for prec in ("fp32", "fp64"):
@@ -671,6 +713,10 @@ def main():
                         "3 seeds (batched: 3 sets of 3 runs in one batch, groups pooled), after "
                         "one untimed run",
             "runs": tnse}
+    if driven is not None:
+        out["device_driven_runs"] = dict(
+            driven, workload="whole adaptive runs driven on the device from one captured step "
+                             "graph, beside the host-driven runs with the same seeds")
     if variants is not None:
         out["variants"] = dict(variants, workload=f"egarch11: {DESCR['egarch11']}, FP64 "
                                "recursion; defaults otherwise")

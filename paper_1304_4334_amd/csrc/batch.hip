@@ -92,9 +92,18 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   const int tid = threadIdx.x;
   const int d = st.d;
   const int64_t P = st.P;
-  double sum = 0.0;
-  for (int b = 0; b < dy.mom_nb; ++b) sum += st.part[b * 256 + tid];
-  Ms[tid] = sum;
+  // the partials added as k_mom_sum adds them: four quarters in block order,
+  // then the quarters in order
+  const int nb = dy.mom_nb, per = (nb + 3) / 4;
+  double q[4];
+#pragma unroll
+  for (int w = 0; w < 4; ++w) {
+    const int lo = min(nb, w * per), hi = min(nb, lo + per);
+    double s = 0.0;
+    for (int b = lo; b < hi; ++b) s += st.part[b * 256 + tid];
+    q[w] = s;
+  }
+  Ms[tid] = ((q[0] + q[1]) + q[2]) + q[3];
   if (tid == 0) {
     int32_t m = *st.mh;
     if (dy.mh_reset > 0) {

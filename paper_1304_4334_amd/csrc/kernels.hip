@@ -894,8 +894,8 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
     part[(int64_t)blockIdx.x * W * W + e] = (red[0][e] + red[1][e]) + (red[2][e] + red[3][e]);
 }
 
-// For 32-wide matrices the partial matrices are first added entry by entry
-// across many blocks, so the final block reads one matrix.  A block takes 64
+// The partial matrices are first added entry by entry across a few blocks,
+// so the final step reads one matrix.  A block takes 64
 // entries; each of its four waves adds a quarter of the partials in block
 // order (its loads in flight together), and the four subtotals are added in
 // wave order.
@@ -1294,15 +1294,16 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
   return launch_status("resample");
 }
 
-// Blocks of four waves (their loads pipelined), few enough that the final
-// block adds few partial matrices; each wave takes `chunk` particles (a
-// multiple of 32).  The batched moments use the same partition, so a run
-// gives the same sums alone or in a batch.
+// Blocks of four waves (their loads pipelined), about 128 of them, so each
+// wave's chain of loads is short (four batches of 32 particles at 65,536
+// particles); k_mom_sum then adds the partial matrices entry by entry (a
+// quarter of them per wave, the quarters in wave order) and the final step
+// reads one matrix.  Each wave takes `chunk` particles (a multiple of 32).
+// The batched moments use the same partition and order, so a run gives the
+// same sums alone or in a batch.
 void moment_partition(int64_t P, int32_t d, int64_t &chunk, int64_t &nb) {
-  // 16-wide matrices: about 32 blocks; 32-wide ones (four times the data per
-  // partial, three products per step): about 128 blocks, read by a final
-  // block of 1,024 threads.
-  const int64_t target = d + 1 <= 16 ? 32 : 128;
+  (void)d;
+  const int64_t target = 128;
   chunk = (P + 4 * target - 1) / (4 * target);
   chunk = ((chunk + 31) / 32) * 32;
   nb = (P + 4 * chunk - 1) / (4 * chunk);
@@ -1314,7 +1315,8 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   moment_partition(a.P, a.d, chunk, nb);
   if (nb > kMomBlocks)
     return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
-  if (a.d + 1 <= 16) {
+  const int n = a.d + 1 <= 16 ? 256 : 1024;  // entries of a partial matrix
+  if (n == 256) {
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
                        a.d, chunk, a.part, a.cyc, a.slot);
   } else {
@@ -1323,18 +1325,17 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
-  if (a.d + 1 <= 16) {
-    hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(256), 0, s, a, (int32_t)nb);
-  } else {
-    // sums into the slot after the partials, then the final block reads them
-    double *sums = a.part + nb * 1024;
-    hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums,
+  // sums into the slot after the partials, then the final block reads them
+  double *sums = a.part + nb * n;
+  hipLaunchKernelGGL(k_mom_sum, dim3(n / 64), dim3(256), 0, s, a.part, (int32_t)nb, n, sums,
                      a.cyc, a.slot);
-    if ((st = launch_status("particle_moments/sum"))) return st;
-    MomArgs f = a;
-    f.part = sums;
+  if ((st = launch_status("particle_moments/sum"))) return st;
+  MomArgs f = a;
+  f.part = sums;
+  if (n == 256)
+    hipLaunchKernelGGL(k_mom_final<16>, dim3(1), dim3(256), 0, s, f, 1);
+  else
     hipLaunchKernelGGL(k_mom_final<32>, dim3(1), dim3(1024), 0, s, f, 1);
-  }
   return launch_status("particle_moments/final");
 }
 
@@ -1345,19 +1346,18 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   moment_partition(a.P, a.d, chunk, nb);
   if (nb > kMomBlocks)
     return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
-  *part = a.part;
-  if (a.d + 1 <= 16) {
+  const int n = a.d + 1 <= 16 ? 256 : 1024;
+  if (n == 256)
     hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
                        a.d, chunk, a.part, a.cyc, a.slot);
-    return launch_status("particle_moments/partial");
-  }
-  hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P, a.d,
-                     chunk, a.part, a.cyc, a.slot);
+  else
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
+                       a.d, chunk, a.part, a.cyc, a.slot);
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
   // summed into the slot after the partials, as launch_moments does
-  double *sums = a.part + nb * 1024;
-  hipLaunchKernelGGL(k_mom_sum, dim3(1024 / 64), dim3(256), 0, s, a.part, (int32_t)nb, 1024, sums,
+  double *sums = a.part + nb * n;
+  hipLaunchKernelGGL(k_mom_sum, dim3(n / 64), dim3(256), 0, s, a.part, (int32_t)nb, n, sums,
                      a.cyc, a.slot);
   *part = sums;
   nb = 1;

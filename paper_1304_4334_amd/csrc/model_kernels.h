@@ -185,8 +185,7 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
   }
   // Lane entries idx = lane + 64 q; each batch issues the loads of every
   // entry before adding any, so the partials' latency is paid once per batch
-  // (a single round for up to 32 partials of a 16-wide matrix with d < 7,
-  // and for the pre-summed 32-wide partials).
+  // (a single round: the partials come pre-summed into one matrix).
   constexpr int Q = (E + 63) / 64;
   constexpr int kB = Q >= 32 ? 1 : 32 / Q;  // partials per entry in flight
   double sum[Q];

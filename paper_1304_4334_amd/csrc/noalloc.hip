@@ -78,7 +78,7 @@ extern "C" smc_status smc_particle_moments_noalloc(const smc_model *m, const smc
   int64_t chunk = 0, nb = 0;
   moment_partition(P, d, chunk, nb);
   const size_t W = d + 1 <= 16 ? 16 : 32;
-  const size_t need = (size_t)(nb + (W == 32 ? 1 : 0)) * W * W * sizeof(double);
+  const size_t need = (size_t)(nb + 1) * W * W * sizeof(double);
   if (nb > kMomBlocks || need > kPartBytes)
     return set_error(SMC_E_WORKSPACE, "moments of %lld particles need %zu scratch bytes > %zu",
                      (long long)P, need, kPartBytes);
