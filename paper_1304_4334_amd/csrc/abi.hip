@@ -45,7 +45,7 @@ WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
   L.small = off;
   off += align256(kSmallBytes);
   L.rsscols = off;
-  off += align256(kMaxChunk * sizeof(double));
+  off += align256((kMaxChunk + rss_slice_doubles((int64_t)P)) * sizeof(double));
   L.gather = off;
   off += align256((size_t)(2 * m.d + m.S + 2) * P * sizeof(double));
   L.cum = off;

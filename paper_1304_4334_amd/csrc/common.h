@@ -84,7 +84,7 @@ constexpr int32_t kGraphMaxCycles = 4096;
 // C-phase columns come last, so their capacity follows from the workspace size.
 struct WsLayout {
   size_t small;    // flags, mh, counters, small vectors (kSmallBytes)
-  size_t rsscols;  // [kMaxChunk] doubles
+  size_t rsscols;  // [kMaxChunk] doubles, then the RSS slices' partial sums
   size_t gather;   // [2d + S + 2][P] doubles
   size_t cum;      // [P] doubles (resample running sums)
   size_t mpart;    // [kMomBlocks + 1][W^2] doubles (moment partials and their sum)

@@ -155,9 +155,13 @@ __global__ void __launch_bounds__(1024) k_rss_cols(const double *W, int64_t P, d
   }  // every LDS write above follows a barrier, so the columns need none between them
 }
 
-// Longer columns in one pass: each thread keeps a running maximum m with
-// s1 = sum exp(w - m), s2 = sum exp(2 (w - m)), rescaled when m grows, over
-// chunks of 16 values; the block merges the triples in a fixed tree order.
+// Longer columns in slices of kRssSlice values (8 per thread, so more blocks
+// overlap their loads with other blocks' exponentials): block (column, slice) takes
+// its slice's maximum m and s1 = sum exp(w - m), s2 = sum exp(2 (w - m)) as
+// k_rss_cols does a whole column (values in registers, two passes), and
+// k_rss_merge combines a column's slices in slice order, rescaling by
+// exp(m_slice - m).  Blocks loop over (column, slice) pairs below
+// ncols * S (or *ncols_dev * S in a device-driven chunk).
 struct Lse3 {
   double m, s1, s2;
 };
@@ -167,53 +171,58 @@ __device__ __forceinline__ Lse3 lse3_merge(Lse3 a, Lse3 b) {
   const double ea = exp_nonpos(a.m - m), eb = exp_nonpos(b.m - m);
   return Lse3{m, a.s1 * ea + b.s1 * eb, a.s2 * ea * ea + b.s2 * eb * eb};
 }
-__device__ __forceinline__ Lse3 lse3_shfl_xor(const Lse3 &a, int off) {
-  return Lse3{__shfl_xor(a.m, off, 64), __shfl_xor(a.s1, off, 64), __shfl_xor(a.s2, off, 64)};
-}
 
-__global__ void __launch_bounds__(1024) k_rss_cols_long(const double *W, int64_t P, double *rss,
-                                                        int32_t ncols,
-                                                        const int32_t *ncols_dev) {
-  __shared__ Lse3 sh[kRssBlock / 64];
-  const int32_t nc = ncols_dev ? *ncols_dev : ncols;
-  for (int32_t col = blockIdx.x; col < nc; col += gridDim.x) {
-  const double *w = W + (int64_t)col * P;
-  constexpr int kChunk = 16;
-  Lse3 acc{-INFINITY, 0.0, 0.0};
-  for (int64_t p0 = threadIdx.x; p0 < P; p0 += (int64_t)kChunk * kRssBlock) {
-    double v[kChunk];
+constexpr int kSliceRegs = 8;  // values per thread in a slice: more blocks in flight per CU
+constexpr int64_t kRssSlice = (int64_t)kSliceRegs * kRssBlock;
+
+__global__ void __launch_bounds__(1024) k_rss_slices(const double *W, int64_t P, int32_t S,
+                                                     double *part, int32_t ncols,
+                                                     const int32_t *ncols_dev) {
+  __shared__ double sh[2 * (kRssBlock / 64)];
+  const int32_t total = (ncols_dev ? *ncols_dev : ncols) * S;
+  for (int32_t b = blockIdx.x; b < total; b += gridDim.x) {
+    const int32_t col = b / S, sl = b - col * S;
+    const int64_t p0 = (int64_t)sl * kRssSlice;
+    const int64_t n = min(kRssSlice, P - p0);
+    const double *w = W + (int64_t)col * P + p0;
+    double v[kSliceRegs];
 #pragma unroll
-    for (int u = 0; u < kChunk; ++u) {
-      const int64_t p = p0 + (int64_t)u * kRssBlock;
-      v[u] = p < P ? w[p] : -INFINITY;
+    for (int u = 0; u < kSliceRegs; ++u) {
+      const int64_t p = threadIdx.x + (int64_t)u * kRssBlock;
+      v[u] = p < n ? w[p] : -INFINITY;
     }
-    double m = v[0];
+    double mx = v[0];
 #pragma unroll
-    for (int u = 1; u < kChunk; ++u) m = fmax(m, v[u]);
-    Lse3 c{m, 0.0, 0.0};
-    if (m > -INFINITY) {
+    for (int u = 1; u < kSliceRegs; ++u) mx = fmax(mx, v[u]);
+    mx = rss_block_reduce<OpMax<double>>(mx, sh);
+    double s1 = 0.0, s2 = 0.0;
+    if (mx > -INFINITY) {
 #pragma unroll
-      for (int u = 0; u < kChunk; ++u) {
-        const double e = exp_nonpos(v[u] - m);
-        c.s1 += e;
-        c.s2 = fma(e, e, c.s2);
+      for (int u = 0; u < kSliceRegs; ++u) {
+        const double e = exp_nonpos(v[u] - mx);
+        s1 += e;
+        s2 = fma(e, e, s2);
       }
     }
-    acc = lse3_merge(acc, c);
-  }
-#pragma unroll
-  for (int off = 32; off > 0; off >>= 1) acc = lse3_merge(acc, lse3_shfl_xor(acc, off));
-  if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
-  __syncthreads();
-  if (threadIdx.x < 64) {
-    Lse3 t = (threadIdx.x < kRssBlock / 64) ? sh[threadIdx.x] : Lse3{-INFINITY, 0.0, 0.0};
-#pragma unroll
-    for (int off = 8; off > 0; off >>= 1) t = lse3_merge(t, lse3_shfl_xor(t, off));
-    if (threadIdx.x == 0)
-      rss[col] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
-  }
-  __syncthreads();  // the first wave's reads of sh before the next column's writes
-  }
+    rss_block_sum2(s1, s2, sh);
+    if (threadIdx.x == 0) {
+      part[3 * (int64_t)b] = mx;
+      part[3 * (int64_t)b + 1] = s1;
+      part[3 * (int64_t)b + 2] = s2;
+    }
+  }  // every LDS write above follows a barrier
+}
+
+__global__ void __launch_bounds__(256) k_rss_merge(const double *part, int64_t P, int32_t S,
+                                                   double *rss, int32_t ncols,
+                                                   const int32_t *ncols_dev) {
+  const int32_t nc = ncols_dev ? *ncols_dev : ncols;
+  const int32_t c = blockIdx.x * 256 + threadIdx.x;
+  if (c >= nc) return;
+  const double *q = part + 3 * (int64_t)c * S;
+  Lse3 acc{q[0], q[1], q[2]};
+  for (int32_t sl = 1; sl < S; ++sl) acc = lse3_merge(acc, Lse3{q[3 * sl], q[3 * sl + 1], q[3 * sl + 2]});
+  rss[c] = (acc.m > -INFINITY) ? acc.s1 * acc.s1 / ((double)P * acc.s2) : 0.0;
 }
 
 // The chunk's stopping decision (Section 3.3: the first checked date whose
@@ -1230,21 +1239,37 @@ smc_status launch_test_fns(const DevModel &m, int64_t P, const double *theta, co
 }
 
 // ------------------------------------------------- model-independent ones --
+int64_t rss_slice_doubles(int64_t P) {
+  return P <= (int64_t)kRssRegs * kRssBlock ? 0
+                                            : kMaxChunk * 3 * ((P + kRssSlice - 1) / kRssSlice);
+}
+
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s, const int32_t *ncols_dev) {
   if (ncols <= 0) return SMC_OK;
   if (ncols > kMaxChunk)
     return set_error(SMC_E_INVALID_ARG, "RSS of %lld columns", (long long)ncols);
-  // a device-driven chunk: up to ncols columns, a block per column up to a
-  // few per CU
-  const unsigned grid = (unsigned)(ncols_dev ? std::min<int64_t>(ncols, 512) : ncols);
-  if (P <= (int64_t)kRssRegs * kRssBlock)
+  if (P <= (int64_t)kRssRegs * kRssBlock) {
+    // a device-driven chunk: up to ncols columns, a block per column up to a
+    // few per CU
+    const unsigned grid = (unsigned)(ncols_dev ? std::min<int64_t>(ncols, 512) : ncols);
     hipLaunchKernelGGL(k_rss_cols, dim3(grid), dim3(kRssBlock), 0, s, W, P, rss, (int32_t)ncols,
                        ncols_dev);
-  else
-    hipLaunchKernelGGL(k_rss_cols_long, dim3(grid), dim3(kRssBlock), 0, s, W, P, rss,
-                       (int32_t)ncols, ncols_dev);
-  return launch_status("correct/rss");
+    return launch_status("correct/rss");
+  }
+  const int64_t S = (P + kRssSlice - 1) / kRssSlice;
+  if (S * ncols > INT32_MAX)
+    return set_error(SMC_E_UNSUPPORTED, "RSS of %lld slices", (long long)(S * ncols));
+  double *part = rss + kMaxChunk;  // the slices' sums follow the RSS values
+  const unsigned grid =
+      (unsigned)(ncols_dev ? std::min<int64_t>(ncols * S, 2048) : ncols * S);
+  hipLaunchKernelGGL(k_rss_slices, dim3(grid), dim3(kRssBlock), 0, s, W, P, (int32_t)S, part,
+                     (int32_t)ncols, ncols_dev);
+  smc_status st = launch_status("correct/rss slices");
+  if (st) return st;
+  hipLaunchKernelGGL(k_rss_merge, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, part, P,
+                     (int32_t)S, rss, (int32_t)ncols, ncols_dev);
+  return launch_status("correct/rss merge");
 }
 
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,

@@ -101,9 +101,12 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
                           double *logw, double *loglik, int64_t t0, int64_t t1, bool zero_first,
                           hipStream_t s, const int64_t *t1_dev = nullptr);
 // RSS of ncols columns; with ncols_dev (a device-driven chunk) of the first
-// *ncols_dev <= ncols columns.
+// *ncols_dev <= ncols columns.  rss is the workspace's RSS region:
+// [kMaxChunk] values, then rss_slice_doubles(P) doubles of partial sums of
+// columns longer than one slice.
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s, const int32_t *ncols_dev = nullptr);
+int64_t rss_slice_doubles(int64_t P);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
 // The stopping decision over nc RSS columns of the chunk (t, t1] into *out,
