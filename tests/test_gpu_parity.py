@@ -30,21 +30,29 @@ def _tol(prec):
 
 
 def _close(got, want, prec, n_obs):
-    """FP64: 1e-10 relative.  FP32: 1e-4 relative to the larger of the value
+    """FP64: 1e-10 relative.  FP32: 1e-5 relative to the larger of the value
     and one unit per observation (a sum of per-observation log densities of
-    either sign can be near zero while its terms are not)."""
+    either sign can be near zero while its terms are not).  Measured: the
+    log likelihood of posterior-like particles within 5e-8 of that scale
+    (7e-4 at T = 10,000), of prior draws within 8e-7; the log-weight
+    increment of a one-observation C phase from an FP32 state carried over
+    earlier dates within 4.1e-6."""
     got, want = np.asarray(got), np.asarray(want)
     same_inf = np.isinf(want) & (got == want)
     if prec != S.SMC_FP64:
-        # beyond the float range a log density is -inf in FP32; its weight is
-        # zero in either precision
-        same_inf |= (want < -1e30) & (got < -1e30)
+        # far beyond the float range a log density is -inf in FP32, and below
+        # -1e15 the FP32 recursion's relative error grows (2e-5 measured at
+        # -3.5e23); the weight is zero in either precision
+        same_inf |= (want < -1e15) & (got < -1e15)
     got = np.where(same_inf, 0.0, got)
     want = np.where(same_inf, 0.0, want)
     if prec == S.SMC_FP64:
         ok = np.abs(got - want) <= 1e-10 * np.abs(want) + 1e-12
     else:
-        ok = np.abs(got - want) <= 1e-4 * np.maximum(np.abs(want), max(n_obs, 1))
+        scale = np.maximum(np.abs(want), max(n_obs, 1))
+        ok = np.abs(got - want) <= 1e-5 * scale
+        if got.size:
+            print(f"[fp32] worst error {np.max(np.abs(got - want) / scale):.3e} of the scale")
     if not np.all(ok):
         i = int(np.argmin(ok))
         print(f"worst mismatch at {i}: got {got.flat[i]!r} want {want.flat[i]!r}")
@@ -119,7 +127,7 @@ def test_loglik_empty_and_bad_args():
 
 @pytest.mark.parametrize("name,prec,ce,J,N", [("linreg", 0, 1, 4, 64), ("egarch11", 0, 1, 4, 64),
                                               ("egarch11", 1, 1, 4, 64), ("egarch2t", 0, 3, 4, 64),
-                                              # RSS columns longer than 16,384 (one-pass kernel)
+                                              # RSS columns longer than 16,384 (sliced kernel)
                                               ("egarch11", 0, 1, 8, 4096)])
 def test_correct_matches_oracle(name, prec, ce, J, N):
     w = SD.workload(name, T=400)
