@@ -30,13 +30,13 @@ def _tol(prec):
 
 
 def _close(got, want, prec, n_obs):
-    """FP64: 1e-10 relative.  FP32: 1e-5 relative to the larger of the value
+    """FP64: 1e-10 relative.  FP32: 2e-5 relative to the larger of the value
     and one unit per observation (a sum of per-observation log densities of
     either sign can be near zero while its terms are not).  Measured: the
     log likelihood of posterior-like particles within 5e-8 of that scale
     (7e-4 at T = 10,000), of prior draws within 8e-7; the log-weight
-    increment of a one-observation C phase from an FP32 state carried over
-    earlier dates within 4.1e-6."""
+    increments of short C phases from an FP32 state carried over earlier
+    dates within 7.5e-6."""
     got, want = np.asarray(got), np.asarray(want)
     same_inf = np.isinf(want) & (got == want)
     if prec != S.SMC_FP64:
@@ -50,7 +50,7 @@ def _close(got, want, prec, n_obs):
         ok = np.abs(got - want) <= 1e-10 * np.abs(want) + 1e-12
     else:
         scale = np.maximum(np.abs(want), max(n_obs, 1))
-        ok = np.abs(got - want) <= 1e-5 * scale
+        ok = np.abs(got - want) <= 2e-5 * scale
         if got.size:
             print(f"[fp32] worst error {np.max(np.abs(got - want) / scale):.3e} of the scale")
     if not np.all(ok):
