@@ -390,6 +390,15 @@ smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_
                           uint64_t seed2, smc_run_record *rec1, smc_run_record *rec2,
                           double *seconds, void *stream);
 
+/* The agreement of Algorithm 3's two steps (Section 3.4's comparison of
+ * independent estimates): out (host double [2]) receives
+ * |a - b| / sqrt(NSE_a^2 + NSE_b^2) for the log-ML of rec1 and rec2
+ * (log_ml[0..1] of each) and, when both records carry a log score, for the
+ * log score (else NaN).  Reads the device estimates on `stream` and
+ * synchronises it. */
+smc_status smc_hybrid_report(const smc_run_record *rec1, const smc_run_record *rec2,
+                             double *out, void *stream);
+
 /* --- many runs at once (extension: batching) -------------------------- */
 
 /* Device workspace bytes of a batch of n_runs runs (1..32). */

@@ -138,6 +138,8 @@ def lib():
         L.smc_run_hybrid.restype = st
         L.smc_run_hybrid.argtypes = [_vp, P(Particles), P(RunConfig), C.c_uint64, P(RunRecord),
                                      P(RunRecord), _vp, _vp]
+        L.smc_hybrid_report.restype = st
+        L.smc_hybrid_report.argtypes = [P(RunRecord), P(RunRecord), _vp, _vp]
         L.smc_num_test_functions.restype = C.c_int32
         L.smc_num_test_functions.argtypes = [_vp, C.c_int32]
         L.smc_test_moments.restype = st
@@ -473,10 +475,14 @@ def smc_run_hybrid(model, pop, seed, seed2, run=0, check_every=1, force_every=0,
     return r1, r2, secs
 
 
-def hybrid_report(r1, r2, secs=None):
+def hybrid_report(r1, r2, secs=None, stream=None):
     """Table 2's rows for the two steps, and the standardised differences of
-    their log-ML (and log score) estimates, |a - b| / sqrt(NSE_a^2 + NSE_b^2)."""
-    import math
+    their log-ML (and log score) estimates, |a - b| / sqrt(NSE_a^2 + NSE_b^2)
+    (smc_hybrid_report)."""
+    import numpy as np
+    z = np.zeros(2)
+    _check(lib().smc_hybrid_report(C.byref(r1.c), C.byref(r2.c), z.ctypes.data, _stream(stream)),
+           "smc_hybrid_report")
     rows = []
     for k, r in enumerate((r1, r2)):
         s = r.summary()
@@ -484,11 +490,7 @@ def hybrid_report(r1, r2, secs=None):
                          cycles=s["L"], metropolis_steps=s["mh_steps"], log_ml=s["log_ml"],
                          nse=s["nse"], log_score=s["log_score"][0],
                          log_score_nse=s["log_score"][1]))
-    a, b = rows
-    z_ml = abs(a["log_ml"] - b["log_ml"]) / math.hypot(a["nse"], b["nse"])
-    z_ls = (abs(a["log_score"] - b["log_score"]) / math.hypot(a["log_score_nse"], b["log_score_nse"])
-            if not math.isnan(a["log_score"]) else float("nan"))
-    return dict(steps=rows, z_log_ml=z_ml, z_log_score=z_ls)
+    return dict(steps=rows, z_log_ml=float(z[0]), z_log_score=float(z[1]))
 
 
 def smc_run_batch(models, pops, seeds, runs=None, records=None, replay=False, waves=0,

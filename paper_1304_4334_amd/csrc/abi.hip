@@ -1170,6 +1170,32 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
 
 extern "C" {
 
+smc_status smc_hybrid_report(const smc_run_record *rec1, const smc_run_record *rec2,
+                             double *out, void *stream) {
+  if (!rec1 || !rec2 || !out || !rec1->log_ml || !rec2->log_ml)
+    return set_error(SMC_E_INVALID_ARG, "NULL record, estimate or output");
+  hipStream_t s = as_stream(stream);
+  const bool scores = rec1->log_score && rec2->log_score;
+  double v[4][3] = {};
+  if (hipMemcpyAsync(v[0], rec1->log_ml, 3 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      hipMemcpyAsync(v[1], rec2->log_ml, 3 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+          hipSuccess ||
+      (scores &&
+       (hipMemcpyAsync(v[2], rec1->log_score, 3 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess ||
+        hipMemcpyAsync(v[3], rec2->log_score, 3 * sizeof(double), hipMemcpyDeviceToHost, s) !=
+            hipSuccess)) ||
+      hipStreamSynchronize(s) != hipSuccess)
+    return set_error(SMC_E_DEVICE, "reading the estimates failed");
+  const auto z = [](const double *a, const double *b) {
+    return fabs(a[0] - b[0]) / hypot(a[1], b[1]);
+  };
+  out[0] = z(v[0], v[1]);
+  out[1] = scores ? z(v[2], v[3]) : NAN;
+  return SMC_OK;
+}
+
 smc_status smc_run_hybrid(const smc_model *m, smc_particles *pop, const smc_run_config *cfg,
                           uint64_t seed2, smc_run_record *rec1, smc_run_record *rec2,
                           double *seconds, void *stream) {

@@ -112,7 +112,15 @@ def test_hybrid_matches_oracle_hybrid(name, T, J, N):
     rep = S.hybrid_report(r1, r2, secs)
     assert rep["steps"][0]["cycles"] == rep["steps"][1]["cycles"]
     assert np.all(secs > 0)
-    assert np.isfinite(rep["z_log_ml"])
+    a, b = rep["steps"]
+    assert rep["z_log_ml"] == pytest.approx(
+        abs(a["log_ml"] - b["log_ml"]) / np.hypot(a["nse"], b["nse"]), rel=1e-15)
+    if np.isnan(a["log_score"]):
+        assert np.isnan(rep["z_log_score"])
+    else:
+        assert rep["z_log_score"] == pytest.approx(
+            abs(a["log_score"] - b["log_score"]) / np.hypot(a["log_score_nse"],
+                                                            b["log_score_nse"]), rel=1e-15)
 
 
 @pytest.mark.parametrize("kernel", [S.SMC_KERNEL_RW, S.SMC_KERNEL_INDEPENDENT, S.SMC_KERNEL_MALA])
