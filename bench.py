@@ -46,27 +46,32 @@ N_SIMD = 256 * 4
 # (FMA = 1; FP32 exp2/log2 = 4, quarter rate; FP64 exp/log1p = 17, the
 # range reduction, degree-11 polynomial and scaling of a full-precision
 # software exponential).
-def mixture_ops(K, I, exp_cost):
+def mixture_ops(K, I, exp_cost, fp32):
     """Lane-operations per particle-observation of egarch_KI with an
-    I-component normal mixture: the K factor updates (4 each, plus 3 per
-    extra factor for the cross-factor sums), z, eps = z E and the exponent
-    sum (3); per component eps - mu_i and the quadratic (3), the shift by the
-    maximum and the sum (about 2 each), the running maximum term and product
-    (2); one exp2 for E and one per component."""
-    rec = 4 * K + (3 * (K - 1) if K > 1 else 0) + 3
+    I-component normal mixture.  The recursion: FP64 (the form whose chain is
+    one exp2 and one fma) 4 per factor plus 3 per extra factor for the
+    cross-factor sums; FP32 (the eps form) 3 per factor plus one addition per
+    extra factor; then z, eps = z E and the exponent sum's accumulation (3).
+    Per component eps - mu_i and the quadratic (3), the shift by the maximum
+    and the sum (about 2 each), the running maximum term and product (2); one
+    exp2 for E and one per component."""
+    rec = (3 * K + (K - 1) if fp32 else 4 * K + (3 * (K - 1) if K > 1 else 0)) + 3
     mix = 3 * I + 2 * (I - 1) + I + 2
     return rec + mix + (1 + I) * exp_cost
 
 
 # The builder's counts of the kernels' algorithmic work (see above).
+# FP32 (the eps form): z, eps, 3 per factor, K - 1 additions, the exponent
+# sum's accumulation; the Gaussian term 1, or the Student-t factor 1, a pair
+# product and the log2's accumulation 1/2 each and half a log2.
 OPS_PER_EVAL = {
     ("linreg", "fp64"): 4,
-    ("egarch23", "fp64"): mixture_ops(2, 3, 17),
-    ("egarch23", "fp32"): mixture_ops(2, 3, 4),
+    ("egarch23", "fp64"): mixture_ops(2, 3, 17, False),
+    ("egarch23", "fp32"): mixture_ops(2, 3, 4, True),
     ("egarch11", "fp64"): 7 + 17,
-    ("egarch11", "fp32"): 7 + 1 + 4,
+    ("egarch11", "fp32"): 1 + 1 + 3 + 1 + 1 + 4,
     ("egarch2t", "fp64"): 10 + 17 + 3 + 17,
-    ("egarch2t", "fp32"): 10 + 1 + 4 + 3 + 4,
+    ("egarch2t", "fp32"): 1 + 1 + 6 + 1 + 1 + 1 + 1 + 4 + 2,
 }
 
 # Algorithmic VALU lane-slots per particle-observation from the hot-path
@@ -108,6 +113,8 @@ TRAFFIC_SOURCES = ["paper_1304_4334_amd/csrc/model_kernels.h", "paper_1304_4334_
                    "paper_1304_4334_amd/csrc/rng.h", "paper_1304_4334_amd/csrc/common.h",
                    "paper_1304_4334_amd/csrc/ops_egarch.hip",
                    "paper_1304_4334_amd/csrc/ops_mixture32.hip",
+                   "paper_1304_4334_amd/csrc/ops_shapes32.hip",
+                   "paper_1304_4334_amd/csrc/ops_shapes64.hip",
                    "paper_1304_4334_amd/csrc/chol.h", "paper_1304_4334_amd/csrc/launch.h"]
 
 
@@ -584,13 +591,14 @@ def kernel_probe():
     """A short fixed sequence for hardware-counter passes: a 256 MiB device
     copy (calibration of the byte counters), then one whole adaptive run of
     each roofline workload (EGARCH(1,1) FP64 16,384 particles; EGARCH(2)-t
-    FP32 and egarch_23 FP32, 65,536 particles).  The last cycle of each run
+    FP32 and egarch_23 FP32, 65,536 particles), in the bench's launch shapes.  The last cycle of each run
     ends at t = T; its M steps are the last `R_last` mutation dispatches of
     the run, whose counters give the traffic per launch at t = T."""
     import torch
 
     import paper_1304_4334_amd as S
     import synthdata as SD
+    from paper_1304_4334_amd import tune
 
     a = torch.ones(64 << 20, dtype=torch.float32, device="cuda")
     b = torch.empty_like(a)
@@ -603,6 +611,7 @@ def kernel_probe():
                        ("egarch23", S.SMC_FP32)):
         w = SD.workload(name)
         m = S.Model.from_workload(w, precision=prec)
+        tune.apply(m, name, "fp64" if prec == S.SMC_FP64 else "fp32")  # the bench's shape
         pop = S.Population(m, w.J, w.N, max_chunk=1024)
         rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64)
         S.smc_run(m, pop, seed=1, record=rec)

@@ -185,7 +185,7 @@ struct Adjoint<Egarch<K, SH, R, I>> {
     const R kap = (R)Md::kKappa;
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
-    st[K] = lastz * lastE;
+    st[K] = Md::shock(p, lastz, lastE);
     const double n = (double)t;
     double ll;
     if constexpr (kT) ll = n * (p.cst - p.lsig) + kLn2 * sv - p.hnu1 * t_scale<R>() * se;

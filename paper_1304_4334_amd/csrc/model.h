@@ -138,6 +138,7 @@ struct Egarch {
   // the FP32 rate).  A pair whose product exceeds the float range (shocks
   // beyond about 1e9 standard deviations) counts as a zero density.
   static constexpr bool kTPair = kT && sizeof(R_) == 4;
+  static constexpr bool kEps = sizeof(R_) == 4;  // the FP32 form of the step (see Par)
   using R = R_;
   using Y = R_;
 
@@ -156,10 +157,19 @@ struct Egarch {
   // m + log2 sum_i 2^(x_i - m), m = max_i x_i.  The sums are multiplied
   // over each block of observations (each lies in [1, I]) and one log2 is
   // taken per block.
+  //
+  // FP32 (kEps): the loop is bound by instruction issue rather than by its
+  // chain, so each factor adds the shock terms directly,
+  //   w_k,s+1 = (alpha_k w_ks - kappa beta_k c) + kappa gamma_k eps_s
+  //             + kappa beta_k |eps_s|,
+  // three fmas instead of four, with eps_s = z_s E_s formed once; and for
+  // Student-t shocks z_s, hence eps_s, is scaled by q = (nu - 2)^(-1/2) (the
+  // factor coefficients by 1/q), so 1 + eps^2/(nu - 2) is one fma.
   struct Par {
     R a[K], c0[K], kb[K], kg[K];  // alpha, -kappa beta c, kappa beta, kappa gamma
     R isig, mus;                  // 1/sigma_Y, mu_Y/sigma_Y
     R inu2;                       // 1/(nu - 2)
+    R kbe[K], kge[K], isige, muse, uzs;  // kEps: kb/q, kg/q, q/sigma_Y, q mu_Y/sigma_Y, 1/q
     R lw[kNM], nb[kNM], mu[kNM];  // mixture components (see above)
     double lsig;                  // log sigma_Y
     double cst;                   // per-observation log-density constant
@@ -253,6 +263,17 @@ struct Egarch {
     p.isig = (R)isig;
     p.mus = (R)(th[0] * 1e-3 * isig);
     p.lsig = th[1];
+    {
+      const double q = kT ? exp(-0.5 * th[2 + 3 * K]) : 1.0;  // (nu - 2)^(-1/2)
+#pragma unroll
+      for (int k = 0; k < K; ++k) {
+        p.kbe[k] = (R)(kKappa * exp(th[2 + K + k]) / q);
+        p.kge[k] = (R)(kKappa * th[2 + 2 * K + k] / q);
+      }
+      p.isige = (R)(isig * q);
+      p.muse = (R)(th[0] * 1e-3 * isig * q);
+      p.uzs = (R)(1.0 / q);
+    }
     if constexpr (kT) {
       const double nu = 2.0 + exp(th[2 + 3 * K]);
       p.inu2 = (R)exp(-th[2 + 3 * K]);
@@ -343,12 +364,62 @@ struct Egarch {
     R sw;
   };
 
+  // The shock eps = z E of an observation from step()'s E and z (z scaled
+  // by q in the kEps form).
+  __device__ __forceinline__ static R shock(const Par &p, R z, R E) {
+    if constexpr (kEps) return z * E * p.uzs;
+    else return z * E;
+  }
+
   // One observation: returns the exponent sum used (for log h), adds eps^2
   // (Gaussian), the Student-t term or the mixture's largest log2 term m to
   // ae (and multiplies the mixture's sum of 2^(x_i - m) into pm), reports E
-  // and z, and advances r to the next observation's exponents.
+  // and z (see shock()), and advances r to the next observation's exponents.
   __device__ __forceinline__ static R step(const Par &p, R y, Run &r, R &ae, R &pm, R &E_out,
                                            R &z_out) {
+    const R sw = r.sw;
+    if constexpr (kEps) {
+      const R Ef = exp2_fast(sw);
+      const R zq = fma(y, p.isige, -p.muse);
+      const R e = zq * Ef;  // eps q
+#pragma unroll
+      for (int k = 0; k < K; ++k)
+        r.w[k] = fma(p.kbe[k], fabs(e), fma(p.kge[k], e, fma(p.a[k], r.w[k], p.c0[k])));
+      R sw1 = r.w[0];
+#pragma unroll
+      for (int k = 1; k < K; ++k) sw1 += r.w[k];
+      r.sw = sw1;
+      if constexpr (kTPair) {
+        pm *= fma(e, e, (R)1);  // 1 + eps^2/(nu - 2); the caller takes the log2
+      } else if constexpr (kMix) {
+        R x[I];
+#pragma unroll
+        for (int i = 0; i < I; ++i) {
+          const R dd = e - p.mu[i];
+          x[i] = fma(p.nb[i] * dd, dd, p.lw[i]);
+        }
+        R mx = x[0];
+#pragma unroll
+        for (int i = 1; i < I; ++i) mx = fmax(mx, x[i]);
+        R sm = exp2_lean(x[0] - mx);
+#pragma unroll
+        for (int i = 1; i < I; ++i) sm += exp2_lean(x[i] - mx);
+        ae += mx;
+        pm *= sm;
+      } else {
+        ae = fma(e, e, ae);
+      }
+      E_out = Ef;
+      z_out = zq;
+      return sw;
+    } else {
+      return step_chain(p, y, r, ae, pm, E_out, z_out);
+    }
+  }
+
+  // FP64: the form whose loop-carried chain is one exp2 and one fma.
+  __device__ __forceinline__ static R step_chain(const Par &p, R y, Run &r, R &ae, R &pm,
+                                                 R &E_out, R &z_out) {
     const R sw = r.sw;
     // E = 2^sw.  For FP64 mixtures it is kept as Ef * 2^n: the exact scaling
     // by 2^n goes into the other factor of each product (off the
@@ -503,7 +574,7 @@ struct Egarch {
     const R kap = (R)kKappa;
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
-    st[K] = z * E;
+    st[K] = shock(p, z, E);
   }
 
   // Sum of log p(y_s | y_{1:s-1}, theta) over s = t0+1..t1.  st holds the
@@ -614,7 +685,7 @@ struct Egarch {
     if constexpr (kMix) se += (double)log2_fast(pm1);
 #pragma unroll
     for (int k = 0; k < K; ++k) st[k] = wl[k] / kap;
-    st[K] = z * E;
+    st[K] = shock(p, z, E);
     const double nd = (double)n;
     // log h_s = log sigma_Y - ln2 * sum_k w_ks
     if constexpr (kT) return nd * (p.cst - p.lsig) + kLn2 * sv - p.hnu1 * t_scale<R>() * se;
