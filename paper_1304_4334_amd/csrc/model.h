@@ -553,21 +553,34 @@ struct Egarch {
     int64_t s = t0 + 1;
     const int64_t nbat = (t1 - t0) / kUnroll;
     if (nbat > 0) {
-      R yb[kUnroll];
+      // two buffers filled alternately, each batch's loads issued before the
+      // previous batch is processed (see advance)
+      R ya[kUnroll], yc[kUnroll];
 #pragma unroll
-      for (int i = 0; i < kUnroll; ++i) yb[i] = y[s - 1 + i];
-      __asm__ volatile("" ::"s"(yb[0]), "s"(yb[kUnroll - 1]));  // see advance
-      for (int64_t b = 0; b < nbat; ++b, s += kUnroll) {
-        const Y *pn = y + (s - 1) + (b + 1 < nbat ? kUnroll : 0);
-        R yn[kUnroll];
+      for (int i = 0; i < kUnroll; ++i) ya[i] = y[s - 1 + i];
+      __asm__ volatile("" ::"s"(ya[0]), "s"(ya[kUnroll - 1]));
+      int64_t b = 0;
+      for (; b + 1 < nbat; b += 2, s += 2 * kUnroll) {
+        __asm__ volatile("" ::"s"(ya[0]), "s"(ya[kUnroll - 1]));
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) yn[i] = pn[i];
-        __asm__ volatile("" ::: "memory");  // the next batch's loads issue here (see advance)
+        for (int i = 0; i < kUnroll; ++i) yc[i] = y[s - 1 + kUnroll + i];
+        __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) one(s + i, yb[i]);
+        for (int i = 0; i < kUnroll; ++i) one(s + i, ya[i]);
+        __asm__ volatile("" ::"s"(yc[0]), "s"(yc[kUnroll - 1]));
+        const Y *pn = y + (s - 1) + (b + 2 < nbat ? 2 * kUnroll : kUnroll);
 #pragma unroll
-        for (int i = 0; i < kUnroll; ++i) yb[i] = yn[i];
+        for (int i = 0; i < kUnroll; ++i) ya[i] = pn[i];
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) one(s + kUnroll + i, yc[i]);
+      }
+      if (b < nbat) {
+#pragma unroll
+        for (int i = 0; i < kUnroll; ++i) one(s + i, ya[i]);
+        s += kUnroll;
       }
     }
     for (; s <= t1; ++s) one(s, y[s - 1]);
@@ -608,41 +621,61 @@ struct Egarch {
     constexpr int G = U < kAcc ? kAcc / U : 1;  // batches per group
     constexpr int Q = U > kAcc ? U / kAcc : 1;  // groups per batch
     const int nbat = nb * G / Q;  // whole batches (U = 16 may leave one group)
+    // Batch b of observations; bp = b % 2 (with U = 4 a group spans batches
+    // b and b + 1, b even).
+    auto batch = [&](const R(&yv)[U], int bp) {
+#pragma unroll
+      for (int i = 0; i < U; ++i) {
+        R Ed, zd;
+        const R sw = step(p, yv[i], r, ae, pm, Ed, zd);
+        // position in the group; its first term starts the group's sum
+        const int pos = (G > 1 ? bp * U : 0) + (i % kAcc);
+        if (pos == 0) av = sw;
+        else av += sw;
+        if constexpr (kTPair) {
+          if (pos & 1) {
+            ae += log2_fast(pm);
+            pm = (R)1;
+          }
+        }
+        if (pos == kAcc - 1) flush();
+      }
+    };
+    static_assert(G <= 2, "a group spans at most two batches");
     if (nbat > 0) {
-      R yb[U];
+      // Two buffers of observations, filled alternately, so no copies
+      // between batches.  Each batch's loads are issued before the previous
+      // batch is processed (the observations are read-only, so the compiler
+      // would otherwise place them just before their use).
+      R ya[U], yc[U];
 #pragma unroll
-      for (int i = 0; i < U; ++i) yb[i] = yp[i];
-      // the first batch is waited for here, so that the wait inside the loop
-      // covers only what the loop itself loads
-      __asm__ volatile("" ::"s"(yb[0]), "s"(yb[U - 1]));
-      for (int b = 0; b < nbat; ++b, yp += U) {
-        const Y *pn = yp + (b + 1 < nbat ? U : 0);
-        R yn[U];
+      for (int i = 0; i < U; ++i) ya[i] = yp[i];
+      // the first batch is waited for here, so that the waits inside the
+      // loop cover only what the loop itself loads
+      __asm__ volatile("" ::"s"(ya[0]), "s"(ya[U - 1]));
+      // A batch is waited for before the next one's loads are issued (a
+      // wait covers every scalar load in flight), i.e. after a whole batch
+      // of work since its own loads.
+      int b = 0;
+      for (; b + 1 < nbat; b += 2, yp += 2 * U) {
+        __asm__ volatile("" ::"s"(ya[0]), "s"(ya[U - 1]));
 #pragma unroll
-        for (int i = 0; i < U; ++i) yn[i] = pn[i];
-        // issues the next batch's loads here, a whole batch ahead of their
-        // use (the observations are read-only, so the compiler would
-        // otherwise place them just before it)
+        for (int i = 0; i < U; ++i) yc[i] = yp[U + i];
         __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
+        batch(ya, 0);
+        __asm__ volatile("" ::"s"(yc[0]), "s"(yc[U - 1]));
+        // batch b + 2, or batch b + 1 again when there is none (not used)
+        const Y *pn = yp + (b + 2 < nbat ? 2 * U : U);
 #pragma unroll
-        for (int i = 0; i < U; ++i) {
-          R Ed, zd;
-          const R sw = step(p, yb[i], r, ae, pm, Ed, zd);
-          // position in the group; its first term starts the group's sum
-          const int pos = (G > 1 ? (b % G) * U : 0) + (i % kAcc);
-          if (pos == 0) av = sw;
-          else av += sw;
-          if constexpr (kTPair) {
-            if (pos & 1) {
-              ae += log2_fast(pm);
-              pm = (R)1;
-            }
-          }
-          if (pos == kAcc - 1) flush();
-        }
-#pragma unroll
-        for (int i = 0; i < U; ++i) yb[i] = yn[i];
+        for (int i = 0; i < U; ++i) ya[i] = pn[i];
+        __asm__ volatile("" ::: "memory");
+        __builtin_amdgcn_sched_barrier(0);
+        batch(yc, 1);
+      }
+      if (b < nbat) {
+        batch(ya, 0);
+        yp += U;
       }
     }
     // a group left over by batches of 16
