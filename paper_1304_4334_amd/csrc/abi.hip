@@ -382,7 +382,8 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
 
 // The C phase with a first speculative chunk of `first_chunk` observations
 // (the driver passes a length predicted from the previous cycle).  Adaptive
-// chunks: scan every checked date, compute the RSS columns, decide the stop
+// chunks: scan every checked date (the scan reduces each wave's weights to
+// RSS sums on the fly), merge them into each date's RSS, decide the stop
 // on the device, and queue the commit to the decided date before the host
 // reads the decision back; with `ahead`, the S phase (which does nothing
 // unless the phase ended, and then also writes the group weights) is queued
@@ -459,7 +460,7 @@ smc_status smc::correct_impl(const smc_model *m, smc_particles *pop, int64_t t_f
       }
       if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, t, t1, check_every,
                              t_max, zero_first, W, s)) ||
-          (st = launch_rss_cols(W, P, nc, rsscols, s)) ||
+          (st = launch_rss_scan(W, P, nc, rsscols, s)) ||
           (st = launch_find_stop(rsscols, nc, t, t1, check_every, t_max, rss_min, stop_dev, s,
                                  slot, ++slot_seq, ws_at<int32_t>(pop, L.small + kSmallFlags))))
         return st;
@@ -1016,7 +1017,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
       double *rsscols = ws_at<double>(pop, L.rsscols);
       if ((e = launch_cscan(dm, P, pop->theta, pop->state, pop->logw, 0, 0, cfg->check_every, 0,
                             false, W, cs)) ||
-          (e = launch_rss_cols(W, P, cap, rsscols, cs, &cyc->nc)) ||
+          (e = launch_rss_scan(W, P, cap, rsscols, cs, &cyc->nc)) ||
           (e = launch_find_stop(rsscols, 0, 0, 0, cfg->check_every, 0, cfg->D1, stop_dev, cs,
                                 nullptr, 0, nullptr, cyc)) ||
           (e = launch_ccommit(dm, P, pop->theta, pop->state, pop->logw, pop->loglik, 0, 0, false,
@@ -1468,7 +1469,7 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         if ((st = launch_cscan(m->dev, P, pop->theta, pop->state, pop->logw, u.tc, t1,
                                c.check_every, u.t_stop, u.zero_first, ws_at<double>(pop, L.wcols),
                                s)) ||
-            (st = launch_rss_cols(ws_at<double>(pop, L.wcols), P, (int64_t)u.dates.size(),
+            (st = launch_rss_scan(ws_at<double>(pop, L.wcols), P, (int64_t)u.dates.size(),
                                   ws_at<double>(pop, L.rsscols), s)))
           return st;
         if (hipMemcpyAsync(host_rss + (size_t)i * kRow, ws_at<double>(pop, L.rsscols),

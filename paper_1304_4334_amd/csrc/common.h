@@ -90,7 +90,8 @@ struct WsLayout {
   size_t mpart;    // [kMomBlocks + 1][W^2] doubles (moment partials and their sum)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
   size_t cyc;      // CycleDyn, then t_end [kGraphMaxCycles] int64, R [..] int32, rss [..]
-  size_t wcols;    // [chunk][P] doubles: speculative C-phase log weights
+  size_t wcols;    // tail of [chunk][P] doubles: the C-phase scan's per-wave RSS sums
+                   // ([chunk][ceil(P/64)][3]) or the adjoint's checkpoints
   size_t fixed;    // bytes before wcols
 };
 

@@ -66,23 +66,6 @@ smc_status fill_i32(int32_t *a, int64_t n, int32_t v, hipStream_t s) {
   return launch_status("fill_i32");
 }
 
-// e^x for x <= 0 or -inf (weights relative to their maximum; -inf gives 0): x =
-// n ln 2 + r with n = rint(x log2 e) and r reduced against ln 2 split in two
-// doubles (|r| <= ln2/2, the first fma exact to one rounding of r), then
-// 2^(r log2 e) by the minimax polynomial of kExp2Coef and the scaling by 2^n.
-// About 20 operations against the library's 45; error within 2 ulp.
-constexpr double kLn2Hi = 0x1.62e42fefa39efp-1, kLn2Lo = 0x1.abc9e3b39803fp-56;
-__device__ __forceinline__ double exp_nonpos(double x) {
-  const double xc = fmax(x, -1100.0);  // keeps -inf out of the reduction
-  const double n = __builtin_rint(xc * kLog2e);
-  const double r = fma(-n, kLn2Lo, fma(-n, kLn2Hi, xc));
-  const double f = r * kLog2e;
-  double p = fma(kExp2Coef[11], f, kExp2Coef[10]);
-#pragma unroll
-  for (int k = 9; k >= 0; --k) p = fma(p, f, kExp2Coef[k]);
-  return x < -1100.0 ? 0.0 : __builtin_ldexp(p, (int)n);
-}
-
 constexpr int kRssBlock = 1024;
 constexpr int kRssRegs = 16;  // values per thread held in registers: P <= 16,384 per column
 
@@ -223,6 +206,37 @@ __global__ void __launch_bounds__(256) k_rss_merge(const double *part, int64_t P
   Lse3 acc{q[0], q[1], q[2]};
   for (int32_t sl = 1; sl < S; ++sl) acc = lse3_merge(acc, Lse3{q[3 * sl], q[3 * sl + 1], q[3 * sl + 2]});
   rss[c] = (acc.m > -INFINITY) ? acc.s1 * acc.s1 / ((double)P * acc.s2) : 0.0;
+}
+
+// RSS of the C-phase scan's dates from its per-wave triples (k_cscan):
+// block b takes dates b, b + gridDim.x, ... below ncols (or *ncols_dev); each
+// thread merges the triples of waves tid, tid + 256, ... in order, then the
+// block merges the threads' results in a fixed tree (lanes ^1 .. ^32 within
+// each wave, then the four waves in order).
+__device__ __forceinline__ Lse3 lse3_shfl_xor(const Lse3 &a, int off) {
+  return Lse3{__shfl_xor(a.m, off, 64), __shfl_xor(a.s1, off, 64), __shfl_xor(a.s2, off, 64)};
+}
+
+__global__ void __launch_bounds__(256) k_rss_scan(const double *trip, int64_t P, int32_t nw,
+                                                  double *rss, int32_t ncols,
+                                                  const int32_t *ncols_dev) {
+  __shared__ Lse3 sh[4];
+  const int32_t nc = ncols_dev ? *ncols_dev : ncols;
+  for (int32_t col = blockIdx.x; col < nc; col += gridDim.x) {
+    const double *q = trip + (int64_t)col * nw * 3;
+    Lse3 acc{-INFINITY, 0.0, 0.0};
+    for (int32_t w = threadIdx.x; w < nw; w += 256)
+      acc = lse3_merge(acc, Lse3{q[3 * w], q[3 * w + 1], q[3 * w + 2]});
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) acc = lse3_merge(acc, lse3_shfl_xor(acc, off));
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+      const Lse3 t = lse3_merge(lse3_merge(sh[0], sh[1]), lse3_merge(sh[2], sh[3]));
+      rss[col] = (t.m > -INFINITY) ? t.s1 * t.s1 / ((double)P * t.s2) : 0.0;
+    }
+    __syncthreads();  // sh is rewritten by the next date
+  }
 }
 
 // The chunk's stopping decision (Section 3.3: the first checked date whose
@@ -1270,6 +1284,19 @@ smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rs
   hipLaunchKernelGGL(k_rss_merge, dim3((unsigned)((ncols + 255) / 256)), dim3(256), 0, s, part, P,
                      (int32_t)S, rss, (int32_t)ncols, ncols_dev);
   return launch_status("correct/rss merge");
+}
+
+smc_status launch_rss_scan(const double *trip, int64_t P, int64_t ncols, double *rss,
+                           hipStream_t s, const int32_t *ncols_dev) {
+  if (ncols <= 0) return SMC_OK;
+  if (ncols > kMaxChunk)
+    return set_error(SMC_E_INVALID_ARG, "RSS of %lld dates", (long long)ncols);
+  const int64_t nw = (P + 63) / 64;
+  if (nw > INT32_MAX) return set_error(SMC_E_UNSUPPORTED, "%lld waves", (long long)nw);
+  const unsigned grid = (unsigned)(ncols_dev ? std::min<int64_t>(ncols, 1024) : ncols);
+  hipLaunchKernelGGL(k_rss_scan, dim3(grid), dim3(256), 0, s, trip, P, (int32_t)nw, rss,
+                     (int32_t)ncols, ncols_dev);
+  return launch_status("correct/rss");
 }
 
 smc_status launch_find_stop(const double *rss, int64_t nc, int64_t t, int64_t t1,

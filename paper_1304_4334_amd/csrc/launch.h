@@ -107,6 +107,11 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
 smc_status launch_rss_cols(const double *W, int64_t P, int64_t ncols, double *rss,
                            hipStream_t s, const int32_t *ncols_dev = nullptr);
 int64_t rss_slice_doubles(int64_t P);
+// RSS of the C-phase scan's recorded dates from its per-wave sums (trip, as
+// k_cscan writes them: [ncols][ceil(P/64)][3] doubles); with ncols_dev (a
+// device-driven chunk) of the first *ncols_dev <= ncols dates.
+smc_status launch_rss_scan(const double *trip, int64_t P, int64_t ncols, double *rss,
+                           hipStream_t s, const int32_t *ncols_dev = nullptr);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
 // The stopping decision over nc RSS columns of the chunk (t, t1] into *out,

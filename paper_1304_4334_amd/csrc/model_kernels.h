@@ -19,6 +19,7 @@
 #include "common.h"
 #include "launch.h"
 #include "model.h"
+#include "reduce.h"
 #include "rng.h"
 
 namespace smc {
@@ -61,19 +62,30 @@ __global__ void __launch_bounds__(64) k_init(DevModel dm, int64_t P, uint64_t se
 
 // ------------------------------------------------------------ C phase (a2) --
 // Speculative pass: from the committed state at t0, evaluate observations
-// t0+1..t1 and record the running log weight at every check date, without
-// committing anything.  Column c of W holds the c-th check date's weights;
-// the wave-uniform column pointer moves by P per recorded date, and the
-// dates are counted relative to t0 in 32 bits (a chunk holds at most
+// t0+1..t1 and, at every check date, the RSS sums of the running log weights
+// over the block's wave of 64 particles, without committing anything.  The
+// weights of up to 32 recorded dates wait in a ring in LDS; after every 16
+// observations (and at the end) each group of 16 dates is reduced: four
+// lanes per date take the maximum m of 16 weights each, then
+// s1 = sum exp(w - m) and s2 = sum exp(2 (w - m)), combined over the four
+// lanes (quad exchanges), and the wave's triple (m, s1, s2) for date c goes
+// to trip[(c * nwaves + wave) * 3] (k_rss_scan merges the waves).  Lanes
+// beyond P follow the recursion of particle P - 1 and record weight -inf.
+// Dates are counted relative to t0 in 32 bits (a chunk holds at most
 // kMaxChunk dates).  kEvery1: every date is checked (check_every = 1).
+constexpr int kScanRing = 32;  // recorded dates held in LDS (a power of two)
+
 template <class M, bool kEvery1>
 __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const double *theta,
                                               const void *state, const double *logw, int64_t t0,
                                               int64_t t1, int64_t check_every, int64_t t_max,
-                                              int32_t zero_first, double *W,
+                                              int32_t zero_first, double *trip,
                                               const typename M::Y *__restrict__ ydata) {
-  const int64_t p = blockIdx.x * 64ll + threadIdx.x;
-  if (p >= P) return;
+  __shared__ double ring[kScanRing * 64];
+  const int lane = threadIdx.x;
+  const int64_t p0 = blockIdx.x * 64ll + lane;
+  const bool live = p0 < P;
+  const int64_t p = live ? p0 : P - 1;
   if (const CycleDyn *c = dm.cyc) {  // a device-driven chunk
     if (!c->go_scan) return;
     t0 = c->t;
@@ -90,15 +102,62 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
   R st[SR];
 #pragma unroll
   for (int k = 0; k < SR; ++k) st[k] = (k < StoredS<M>::value) ? typed<R>(state)[k * P + p] : (R)0;
-  double lw = zero_first ? 0.0 : logw[p];
-  double *colp = W;  // the next column to record
+  double lw = !live ? -INFINITY : (zero_first ? 0.0 : logw[p]);
+  const int64_t nw = gridDim.x;
+  int32_t nrec = 0, ndone = 0;  // dates recorded, dates reduced
+  auto record = [&]() {
+    ring[(nrec & (kScanRing - 1)) * 64 + lane] = lw;
+    ++nrec;
+  };
+  // dates ndone .. ndone + n - 1 (n <= 16, all lanes)
+  auto reduce = [&](int32_t n) {
+    __syncthreads();  // the block is this wave: orders the ring's writes and reads
+    const int c = lane >> 2, q = lane & 3;
+    const bool mine = c < n;
+    double v[16];
+    double m = -INFINITY;
+    if (mine) {
+      const double *src = ring + ((ndone + c) & (kScanRing - 1)) * 64 + q * 16;
+#pragma unroll
+      for (int j = 0; j < 16; ++j) v[j] = src[j];
+#pragma unroll
+      for (int j = 0; j < 16; ++j) m = fmax(m, v[j]);
+    }
+    m = fmax(m, dpp_f64<0xB1>(m));
+    m = fmax(m, dpp_f64<0x4E>(m));
+    double s1 = 0.0, s2 = 0.0;
+    if (mine && m > -INFINITY) {
+#pragma unroll
+      for (int j = 0; j < 16; ++j) {
+        const double e = exp_nonpos(v[j] - m);
+        s1 += e;
+        s2 = fma(e, e, s2);
+      }
+    }
+    s1 += dpp_f64<0xB1>(s1);
+    s2 += dpp_f64<0xB1>(s2);
+    s1 += dpp_f64<0x4E>(s1);
+    s2 += dpp_f64<0x4E>(s2);
+    if (mine && q == 0) {
+      double *o = trip + ((int64_t)(ndone + c) * nw + blockIdx.x) * 3;
+      o[0] = m;
+      o[1] = s1;
+      o[2] = s2;
+    }
+    ndone += n;
+  };
+  auto group = [&]() {
+    if (nrec - ndone >= 16) reduce(16);
+  };
   if constexpr (kEvery1) {
-    Eval<M>::scan_y(dm, ydata, par, st, t0, t1, [&](int64_t, double lp) {
-      if (isnan(lp)) lp = -INFINITY;
-      lw += lp;
-      colp[p] = lw;
-      colp += P;
-    });
+    Eval<M>::scan_y(
+        dm, ydata, par, st, t0, t1,
+        [&](int64_t, double lp) {
+          if (isnan(lp)) lp = -INFINITY;
+          lw += lp;
+          record();
+        },
+        group);
   } else {
     // dates relative to t0: the next multiple of check_every, and t_max
     // (both capped beyond the chunk, where they are never reached)
@@ -108,18 +167,21 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
     const int32_t max_rel = (int32_t)(t_max - t0 < span ? t_max - t0 : span);
     const int32_t every = (int32_t)(check_every < span ? check_every : span);
     int32_t rel = 0;
-    Eval<M>::scan_y(dm, ydata, par, st, t0, t1, [&](int64_t, double lp) {
-      if (isnan(lp)) lp = -INFINITY;
-      lw += lp;
-      ++rel;
-      const bool at_check = rel == next_rel;
-      if (at_check || rel == max_rel) {
-        colp[p] = lw;
-        colp += P;
-      }
-      if (at_check) next_rel += every;
-    });
+    Eval<M>::scan_y(
+        dm, ydata, par, st, t0, t1,
+        [&](int64_t, double lp) {
+          if (isnan(lp)) lp = -INFINITY;
+          lw += lp;
+          ++rel;
+          const bool at_check = rel == next_rel;
+          if (at_check || rel == max_rel) record();
+          if (at_check) next_rel += every;
+        },
+        group);
   }
+  // at most 16 dates between two calls of group(), so the ring never holds
+  // more than 31 unreduced ones
+  while (nrec > ndone) reduce(min(16, nrec - ndone));
 }
 
 // Commit: advance from t0 to t1 (or to *t1_dev when given), adding the log

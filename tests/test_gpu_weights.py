@@ -1,7 +1,8 @@
-"""The weight sums of the C phase as compiled: the pooled RSS (k_rss_cols for
-columns up to 16,384 particles, k_rss_cols_long beyond) and the group log
-mean weights (k_group_logwbar) on crafted log-weight columns, against long
-double sums of the same values.
+"""The weight sums of the C phase as compiled: the pooled RSS of a weight
+column (k_rss_cols for columns up to 16,384 particles, k_rss_slices and
+k_rss_merge beyond), the adaptive path's RSS from the scan's per-wave sums
+(k_cscan, k_rss_scan) and the group log mean weights (k_group_logwbar) on
+crafted log-weight columns, against long double sums of the same values.
 
 The columns come from one observation of a one-regressor Gaussian
 regression: a particle with slope b and log variance 0 has log weight
@@ -88,7 +89,7 @@ def test_weight_sums_match_long_double(J, N):
             assert got[j] == ref
         else:
             assert abs(got[j] - ref) <= 1e-13 + 4e-16 * abs(ref), (j, got[j], ref)
-    # the adaptive path's columns (scan, then the same RSS kernels) agree
+    # the adaptive path's RSS (per-wave sums in the scan, merged) agrees
     g2 = _population(m, J, N, depth)
     t, rss2, _ = S.smc_correct(m, g2, 0, 1, check_every=1, rss_min=0.5)
     assert t == 1 and rss2 == pytest.approx(want, rel=tol)

@@ -5,7 +5,7 @@ kExp2Coef (model.h): the FP64 base-2 exponential's polynomial on
 [-1/2, 1/2]; its relative error against 2^f (50-digit arithmetic) must stay
 below 4e-17, a third of an ulp, and it must be exact at f = 0.
 
-kLn2Hi / kLn2Lo (kernels.hip): ln 2 split over two doubles for the weights'
+kLn2Hi / kLn2Lo (model.h): ln 2 split over two doubles for the weights'
 exponential, whose arithmetic is replayed here against long double.
 """
 import os
@@ -50,7 +50,7 @@ def test_exp2_coefficients_near_taylor():
         assert abs(ck / taylor - 1) < bound[k], (k, ck, taylor)
 
 
-KERNELS_HIP = os.path.join(ROOT, "paper_1304_4334_amd", "csrc", "kernels.hip")
+KERNELS_HIP = MODEL_H  # the weights' exponential sits beside the recursion's
 
 
 def _ln2_split():
@@ -69,7 +69,7 @@ def test_ln2_split_sums_to_ln2():
 
 
 def test_exp_nonpos_error_within_two_ulp(tmp_path):
-    """The weights' exponential (kernels.hip, exp_nonpos), replayed on the CPU
+    """The weights' exponential (model.h, exp_nonpos), replayed on the CPU
     with the same constants and fused multiply-adds, against long double
     expl on [-708, 0]; -inf gives 0 and 0 gives 1."""
     import shutil
