@@ -267,6 +267,7 @@ struct Egarch {
   }
 
   __device__ static Par params(const double *th) {
+    if constexpr (kEps) return params_f32(th);
     Par p;
 #pragma unroll
     for (int k = 0; k < K; ++k) {
@@ -315,6 +316,58 @@ struct Egarch {
     }
     return p;
   }
+  // FP32 models: the coefficients that enter the float recursion are
+  // computed in float (their float roundings were all that reached the
+  // recursion anyway); the per-observation log-density constant, log sigma_Y
+  // and (nu + 1)/2 stay FP64.
+  __device__ static Par params_f32(const double *th) {
+    Par p;
+    const float kap = (float)kKappa;
+    const float q = kT ? __expf(-0.5f * (float)th[2 + 3 * K]) : 1.0f;  // (nu - 2)^(-1/2)
+    const float iq = 1.0f / q;
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+      const float b = __expf((float)th[2 + K + k]);
+      const float x = (float)th[2 + k];  // tanh x = 1 - 2 / (e^(2x) + 1)
+      p.a[k] = (R)(1.0f - 2.0f / (__expf(2.0f * x) + 1.0f));
+      p.c0[k] = (R)(-kap * b * (float)kSqrt2OverPi);
+      p.kb[k] = (R)(kap * b);
+      p.kg[k] = (R)(kap * (float)th[2 + 2 * K + k]);
+      p.kbe[k] = p.kb[k] * iq;
+      p.kge[k] = p.kg[k] * iq;
+    }
+    const float isig = __expf(-(float)th[1]);
+    p.isig = (R)isig;
+    p.mus = (R)((float)(th[0] * 1e-3) * isig);
+    p.isige = (R)(isig * q);
+    p.muse = p.mus * q;
+    p.uzs = iq;
+    p.lsig = th[1];
+    if constexpr (kT) {
+      const double nu = 2.0 + exp(th[2 + 3 * K]);
+      p.inu2 = (R)(q * q);
+      p.hnu1 = 0.5 * (nu + 1.0);
+      p.cst = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * (nu - 2.0));
+    } else if constexpr (kMix) {
+      double pw[I], mu[I], sg[I];
+      mixture(th, pw, mu, sg);
+#pragma unroll
+      for (int i = 0; i < I; ++i) {
+        p.mu[i] = (R)mu[i];
+        p.lw[i] = (R)(log2(pw[i]) - log2(sg[i]));
+        p.nb[i] = (R)(-kLog2e / (2.0 * sg[i] * sg[i]));
+      }
+      p.inu2 = (R)0;
+      p.hnu1 = 0.5;
+      p.cst = -0.5 * kLog2Pi;
+    } else {
+      p.inu2 = (R)0;
+      p.hnu1 = 0.5;
+      p.cst = -0.5 * kLog2Pi;
+    }
+    return p;
+  }
+
 
   // Table 1 (and the nu extension): prior mean, standard deviation and its
   // logarithm of parameter i.  Hexadecimal literals are the correctly rounded

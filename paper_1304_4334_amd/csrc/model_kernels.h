@@ -341,6 +341,13 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
     fm.mh_out = (r & 1) ? mh : mh + 1;
   }
   const int64_t p = blockIdx.x * (int64_t)B + threadIdx.x;
+  // The particle's loads and its proposal draws first: their latency and
+  // arithmetic overlap the proposal scale's loads and factorisation.
+  const int64_t pc = p < P ? p : P - 1;
+  double th[D], z[D];
+#pragma unroll
+  for (int i = 0; i < D; ++i) th[i] = theta[i * P + pc];
+  normals<D>(seed, run, (uint64_t)pc, cycle, iter, kProposal, z, D);
   bool fused = false, chol_ok = true;
   double h = 0.0;
   if constexpr (kCanFuse) {
@@ -362,10 +369,7 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
   }
   int acc = 0;
   if (p < P) {
-    double th[D], z[D], pr[D];
-#pragma unroll
-    for (int i = 0; i < D; ++i) th[i] = theta[i * P + p];
-    normals<D>(seed, run, (uint64_t)p, cycle, iter, kProposal, z, D);
+    double pr[D];
     if (fused) {
       // h L rounded as the moments kernels round it: h * L_ik (0 without a factor)
 #pragma unroll
