@@ -93,14 +93,22 @@ __global__ void __launch_bounds__(256) k_batch_mom_final(BatchArgs a) {
   const int d = st.d;
   const int64_t P = st.P;
   // the partials added as k_mom_sum adds them: four quarters in block order,
-  // then the quarters in order
+  // then the quarters in order; each quarter's loads issued 32 at a time
   const int nb = dy.mom_nb, per = (nb + 3) / 4;
+  constexpr int kBatch = 32;
   double q[4];
 #pragma unroll
   for (int w = 0; w < 4; ++w) {
     const int lo = min(nb, w * per), hi = min(nb, lo + per);
     double s = 0.0;
-    for (int b = lo; b < hi; ++b) s += st.part[b * 256 + tid];
+    for (int b0 = lo; b0 < hi; b0 += kBatch) {
+      double x[kBatch];
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u) x[u] = (b0 + u < hi) ? st.part[(b0 + u) * 256 + tid] : 0.0;
+#pragma unroll
+      for (int u = 0; u < kBatch; ++u)
+        if (b0 + u < hi) s += x[u];
+    }
     q[w] = s;
   }
   Ms[tid] = ((q[0] + q[1]) + q[2]) + q[3];
