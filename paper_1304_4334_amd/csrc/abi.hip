@@ -942,7 +942,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
 
 // Device-driven adaptive run (cfg->graph): after the eager set-up (flags,
 // counters, the prior draw, k_cycle_init), one captured step -- the C-phase
-// chunk (scan, RSS columns, decision, commit), the S phase, Rbar M slots and
+// chunk (scan, RSS merge, decision, commit), the S phase, Rbar M slots and
 // k_cycle_end -- is launched again and again on the stream.  Every decision
 // is taken and applied on the device, so the host never waits for one: it
 // keeps up to three steps queued, reads the progress word to see how far the
@@ -1374,8 +1374,8 @@ smc_status smc_run_batch(int32_t n, const smc_model *const *models, smc_particle
         (st = smc_init_from_prior(models[i], pops[i], cfgs[i].rng, stream)))
       return st;
   }
-  // Pinned readback area of the adaptive C phases: per run, the chunk's RSS
-  // columns followed by the run's flags word (a replay reads nothing back, so
+  // Pinned readback area of the adaptive C phases: per run, the RSS of the
+  // chunk's checked dates followed by the run's flags word (a replay reads nothing back, so
   // it can be captured).  One area per host thread, grown on demand and kept.
   constexpr size_t kRow = kMaxChunk + 1;  // doubles per run
   double *host_rss = nullptr;

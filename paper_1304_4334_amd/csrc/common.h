@@ -80,8 +80,8 @@ __device__ __forceinline__ bool m_slot_off(const CycleDyn *c, int32_t k) {
 // Cycles a graph-replayed run records on the device.
 constexpr int32_t kGraphMaxCycles = 4096;
 
-// Workspace carve-up (offsets in bytes, each 256-aligned).  The speculative
-// C-phase columns come last, so their capacity follows from the workspace size.
+// Workspace carve-up (offsets in bytes, each 256-aligned).  The C-phase scan's
+// per-date sums come last, so the chunk capacity follows from the workspace size.
 struct WsLayout {
   size_t small;    // flags, mh, counters, small vectors (kSmallBytes)
   size_t rsscols;  // [kMaxChunk] doubles, then the RSS slices' partial sums

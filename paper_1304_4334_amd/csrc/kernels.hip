@@ -240,9 +240,9 @@ __global__ void __launch_bounds__(256) k_rss_scan(const double *trip, int64_t P,
 }
 
 // The chunk's stopping decision (Section 3.3: the first checked date whose
-// RSS is below rss_min): one wave scans the columns 64 at a time.  Column c
-// holds date first + c * check_every, the multiples of check_every after t
-// up to t1, and t_max last when it is not a multiple.  With host_slot, the
+// RSS is below rss_min): one wave scans the RSS values 64 at a time.  Value c
+// is that of date first + c * check_every, the multiples of check_every after
+// t up to t1, and t_max last when it is not a multiple.  With host_slot, the
 // decision and the flags word also go to host memory, every 32-bit word of
 // them paired with seq in an 8-byte word (DecisionSlot).  With cyc (a
 // device-driven chunk) the chunk comes from there, a chunk without checked

@@ -114,7 +114,7 @@ smc_status launch_rss_scan(const double *trip, int64_t P, int64_t ncols, double 
                            hipStream_t s, const int32_t *ncols_dev = nullptr);
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,
                                 hipStream_t s);
-// The stopping decision over nc RSS columns of the chunk (t, t1] into *out,
+// The stopping decision over the nc RSS values of the chunk (t, t1] into *out,
 // and with *flags into page-locked host memory host_slot (tagged with seq)
 // when that is not NULL; with cyc, the chunk and decision of a device-driven
 // cycle (the by-value chunk arguments are then unused).
