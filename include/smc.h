@@ -167,6 +167,21 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
                        int64_t check_every, double rss_min, double *group_logwbar,
                        int64_t *t_to, double *rss, void *stream);
 
+/* The same C phase (Algorithm 1 step 2a, with Section 3.3's stopping rule)
+ * with its outputs in device memory and no host synchronisation: *t_to
+ * (device int64 [1]) = the end date and, when rss is not NULL, *rss (device
+ * double [1]) = the RSS there; group_logwbar as for smc_correct.  The results
+ * are those of smc_correct, to the bit.  Argument errors are those of
+ * smc_correct; a numerical problem shows in smc_flags afterwards.  Every stopping decision is taken and applied
+ * on the device (the state lives in the workspace): smc_correct's sequence of
+ * chunks (16 observations, doubling up to the workspace's capacity) is
+ * enqueued up front, enough to reach t_max, and the chunks after the phase's
+ * end return at once, so the call can be captured in a graph.  Calls that
+ * overlap on one population race. */
+smc_status smc_correct_async(const smc_model *m, smc_particles *pop, int64_t t_from,
+                             int64_t t_max, int64_t check_every, double rss_min,
+                             double *group_logwbar, int64_t *t_to, double *rss, void *stream);
+
 /* S phase (Algorithm 1 step 2b) in every group independently: residual
  * (Section 3.3 default) or multinomial resampling on logw.  Residual: copy n
  * floor(N W_n) times, then draw the remaining R = N - sum floor(N W_n) from

@@ -106,6 +106,9 @@ def lib():
         L.smc_correct.restype = st
         L.smc_correct.argtypes = [_vp, P(Particles), C.c_int64, C.c_int64, C.c_int64,
                                   C.c_double, _vp, P(C.c_int64), P(C.c_double), _vp]
+        L.smc_correct_async.restype = st
+        L.smc_correct_async.argtypes = [_vp, P(Particles), C.c_int64, C.c_int64, C.c_int64,
+                                        C.c_double, _vp, _vp, _vp, _vp]
         L.smc_resample.restype = st
         L.smc_resample.argtypes = [_vp, P(Particles), C.c_int32, Rng, C.c_int32, _vp]
         L.smc_particle_moments.restype = st
@@ -271,6 +274,23 @@ def smc_correct(model, pop, t_from, t_max, check_every=1, rss_min=0.5, group_log
                              _ptr(glwb), C.byref(t_to), C.byref(rss) if want_rss else None,
                              _stream(stream)), "smc_correct")
     return t_to.value, (rss.value if want_rss else None), glwb
+
+
+def smc_correct_async(model, pop, t_from, t_max, check_every=1, rss_min=0.5,
+                      group_logwbar=None, t_to=None, rss=None, want_rss=True, stream=None):
+    """smc_correct with device outputs and no host synchronisation (capturable).
+    Returns (t_to int64 tensor [1], rss float64 tensor [1] or None,
+    group_logwbar tensor [J])."""
+    dev = model.device
+    glwb = group_logwbar if group_logwbar is not None else torch.empty(
+        pop.J, dtype=torch.float64, device=dev)
+    t_to = t_to if t_to is not None else torch.empty(1, dtype=torch.int64, device=dev)
+    if want_rss and rss is None:
+        rss = torch.empty(1, dtype=torch.float64, device=dev)
+    _check(lib().smc_correct_async(model.h, C.byref(pop.c), t_from, t_max, check_every, rss_min,
+                                   _ptr(glwb), _ptr(t_to), _ptr(rss) if want_rss else None,
+                                   _stream(stream)), "smc_correct_async")
+    return t_to, (rss if want_rss else None), glwb
 
 
 def smc_resample(model, pop, scheme=SMC_RESAMPLE_RESIDUAL, seed=1, run=0, cycle=1,

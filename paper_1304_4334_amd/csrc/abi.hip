@@ -378,6 +378,70 @@ smc_status smc_correct(const smc_model *m, smc_particles *pop, int64_t t_from, i
                       stream, 16);
 }
 
+smc_status smc_correct_async(const smc_model *m, smc_particles *pop, int64_t t_from,
+                             int64_t t_max, int64_t check_every, double rss_min,
+                             double *group_logwbar, int64_t *t_to, double *rss, void *stream) {
+  smc_status st;
+  if ((st = check_model(m)) || (st = check_pop(m, pop))) return st;
+  if (!group_logwbar || !t_to) return set_error(SMC_E_INVALID_ARG, "NULL output");
+  if (t_from < 0 || t_max > m->dev.T || t_from > t_max)
+    return set_error(SMC_E_INVALID_ARG, "dates 0 <= t_from <= t_max <= T violated");
+  if (check_every < 1) return set_error(SMC_E_INVALID_ARG, "check_every < 1");
+  hipStream_t s = as_stream(stream);
+  const int64_t P = (int64_t)pop->J * pop->N;
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  double *rsscols = ws_at<double>(pop, L.rsscols);
+  if (!(rss_min > 0.0 && t_from < t_max)) {
+    // the whole range, then the RSS of the final weights
+    if (t_max == t_from) {
+      if ((st = fill_f64(pop->logw, P, 0.0, s))) return st;
+    } else if ((st = launch_ccommit(m->dev, P, pop->theta, pop->state, pop->logw, pop->loglik,
+                                    t_from, t_max, true, s))) {
+      return st;
+    }
+    if ((rss && (st = launch_rss_cols(pop->logw, P, 1, rsscols, s))) ||
+        (st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s)))
+      return st;
+    return launch_phase_out(nullptr, rsscols, t_max, t_to, rss, s);
+  }
+  const int64_t cap = chunk_capacity(m, pop);
+  if (cap < 1) return set_error(SMC_E_WORKSPACE, "workspace has no room for C-phase chunks");
+  CycleDyn *cyc = ws_at<CycleDyn>(pop, L.cyc);
+  StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
+  DevModel dm = m->dev;
+  dm.cyc = cyc;
+  // The chunks of smc_correct (16 observations, doubling up to the
+  // workspace's capacity), enough of them to reach t_max; those after the
+  // phase's end return at once.
+  CycleDyn init{};
+  init.T = m->dev.T;
+  init.P = P;
+  init.check_every = check_every;
+  init.cap = cap;
+  init.t = init.t_phase = t_from;
+  init.t_stop = t_max;
+  init.chunk = std::min<int64_t>(16, cap);
+  init.zero_first = 1;
+  init.rss = 1.0;
+  init.J = pop->J;
+  if ((st = launch_phase_init(cyc, init, s))) return st;
+  double *W = ws_at<double>(pop, L.wcols);
+  for (int64_t covered = 0, chunk = init.chunk; covered < t_max - t_from;
+       covered += chunk, chunk = std::min(2 * chunk, cap)) {
+    if ((st = launch_cscan(dm, P, pop->theta, pop->state, pop->logw, 0, 0, check_every, 0, false,
+                           W, s)) ||
+        (st = launch_rss_scan(W, P, std::min<int64_t>(chunk, kMaxChunk), rsscols, s, &cyc->nc)) ||
+        (st = launch_find_stop(rsscols, 0, 0, 0, check_every, 0, rss_min, stop_dev, s, nullptr, 0,
+                               nullptr, cyc)) ||
+        (st = launch_ccommit(dm, P, pop->theta, pop->state, pop->logw, pop->loglik, 0, 0, false,
+                             s, &stop_dev->t_commit)) ||
+        (st = launch_phase_step(cyc, s)))
+      return st;
+  }
+  if ((st = launch_group_logwbar(pop->logw, pop->J, pop->N, group_logwbar, s))) return st;
+  return launch_phase_out(cyc, nullptr, 0, t_to, rss, s);
+}
+
 }  // extern "C"
 
 // The C phase with a first speculative chunk of `first_chunk` observations

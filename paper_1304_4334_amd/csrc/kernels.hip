@@ -401,6 +401,44 @@ __global__ void k_cycle_end(CycleDyn *cp, int64_t *t_end, int32_t *r_rec, double
                      __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
 }
 
+// A C phase driven on the device (smc_correct_async): the state opens its
+// first chunk; after each chunk the phase either has ended (its date and RSS
+// stay in the state) or opens the next chunk, twice as long; at the end the
+// date and RSS are copied to the caller's outputs.
+__global__ void k_phase_init(CycleDyn *c, CycleDyn init) {
+  if (threadIdx.x != 0) return;
+  cycle_open_chunk(init);
+  *c = init;
+}
+
+__global__ void k_phase_step(CycleDyn *cp) {
+  if (threadIdx.x != 0) return;
+  CycleDyn c = *cp;
+  if (!c.go_c) return;
+  if (c.go_s) {  // the decision ended the phase
+    c.go_c = c.go_scan = 0;
+    c.done = 1;
+  } else {
+    c.t = c.t_new;
+    c.zero_first = 0;
+    c.chunk = min(2 * c.chunk, c.cap);
+    cycle_open_chunk(c);
+  }
+  *cp = c;
+}
+
+__global__ void k_phase_out(const CycleDyn *c, const double *rss_src, int64_t t_fixed,
+                            int64_t *t_to, double *rss) {
+  if (threadIdx.x != 0) return;
+  if (c) {
+    t_to[0] = c->t_new;
+    if (rss) rss[0] = c->rss;
+  } else {
+    t_to[0] = t_fixed;
+    if (rss) rss[0] = rss_src[0];
+  }
+}
+
 // ------------------------------------------------------------ S phase (a3) --
 // One block of kSBlock threads (16 waves) per group.  The group's weights,
 // then their running residual sums, live in LDS when they fit (kCumLdsMax),
@@ -1319,6 +1357,22 @@ smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double 
                             const int32_t *flags, uint32_t *host, hipStream_t s) {
   hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, s, c, t_end, r_rec, rss_rec, flags, host);
   return launch_status("cycle/end");
+}
+
+smc_status launch_phase_init(CycleDyn *c, const CycleDyn &init, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_init, dim3(1), dim3(64), 0, s, c, init);
+  return launch_status("correct/phase init");
+}
+
+smc_status launch_phase_step(CycleDyn *c, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_step, dim3(1), dim3(64), 0, s, c);
+  return launch_status("correct/phase step");
+}
+
+smc_status launch_phase_out(const CycleDyn *c, const double *rss_src, int64_t t_fixed,
+                            int64_t *t_to, double *rss, hipStream_t s) {
+  hipLaunchKernelGGL(k_phase_out, dim3(1), dim3(64), 0, s, c, rss_src, t_fixed, t_to, rss);
+  return launch_status("correct/phase out");
 }
 
 smc_status launch_group_logwbar(const double *logw, int32_t J, int32_t N, double *out,

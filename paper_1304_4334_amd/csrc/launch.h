@@ -140,6 +140,13 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
 smc_status launch_cycle_init(CycleDyn *c, const CycleDyn &init, hipStream_t s);
 smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double *rss_rec,
                             const int32_t *flags, uint32_t *host, hipStream_t s);
+// A C phase driven on the device (smc_correct_async): open the first chunk,
+// advance after each chunk, copy the end date and RSS to the caller (with
+// c NULL: t_fixed and *rss_src).
+smc_status launch_phase_init(CycleDyn *c, const CycleDyn &init, hipStream_t s);
+smc_status launch_phase_step(CycleDyn *c, hipStream_t s);
+smc_status launch_phase_out(const CycleDyn *c, const double *rss_src, int64_t t_fixed,
+                            int64_t *t_to, double *rss, hipStream_t s);
 struct MomArgs {
   const double *theta;
   int64_t P;

@@ -2,7 +2,8 @@
 graph -- a C-phase chunk, the S phase, Rbar M slots, the step's end -- is
 launched until the run ends, every decision taken on the device.  The run
 equals the host-driven one to the bit, also when the cached graph is launched
-again after unrelated eager work."""
+again after unrelated eager work.  The device-driven C phase alone
+(smc_correct_async) equals smc_correct to the bit and can be captured."""
 import numpy as np
 import pytest
 import torch
@@ -77,3 +78,95 @@ def test_device_driven_run_rejects_what_it_does_not_drive():
     for kw in (dict(stop_rule=1), dict(kernel=S.SMC_KERNEL_INDEPENDENT), dict(RmaxRec=16)):
         with pytest.raises(S.SmcError):
             S.smc_run(m, p, seed=3, graph=True, Lmax=64, **kw)
+
+
+C_CASES = [
+    # name, T, J, N, check_every, max_chunk, rss_min
+    ("egarch11", 400, 4, 128, 1, 16, 0.5),
+    ("egarch2t", 300, 4, 96, 7, 32, 0.5),
+    ("egarch11", 250, 2, 64, 20, 16, 0.5),  # chunks with no checked date
+    ("linreg", 200, 4, 64, 1, 16, 0.0),     # the whole range, then its RSS
+]
+
+
+def _bits(x):
+    """The tensor's bit patterns (prior draws far in the tails leave NaN in
+    some particles' recursion state, and NaN equals nothing)."""
+    return x.view(torch.int64 if x.element_size() == 8 else torch.int32)
+
+
+def _pair(m, J, N, mc):
+    p1 = S.Population(m, J, N, max_chunk=mc)
+    p2 = S.Population(m, J, N, max_chunk=mc)
+    for p in (p1, p2):
+        S.smc_init_from_prior(m, p, seed=9)
+    return p1, p2
+
+
+@pytest.mark.parametrize("prec", [S.SMC_FP64, S.SMC_FP32])
+@pytest.mark.parametrize("case", C_CASES, ids=lambda c: "-".join(map(str, c)))
+def test_device_driven_c_phase_equals_smc_correct(prec, case):
+    """smc_correct_async (every stopping decision on the device, outputs in
+    device memory) gives smc_correct's end date, RSS, group weights and
+    particles to the bit, over three cycles with S phases between them."""
+    name, T, J, N, ce, mc, rss_min = case
+    if name == "linreg" and prec == S.SMC_FP32:
+        pytest.skip("the regression has no FP32 recursion")
+    w = SD.workload(name, T=T)
+    m = S.Model(w.kind, w.y[:T], X=None if w.X is None else w.X[:T], K=w.K, shock=w.shock,
+                precision=prec)
+    p1, p2 = _pair(m, J, N, mc)
+    t = 0
+    for cyc in range(3):
+        t_h, rss_h, g_h = S.smc_correct(m, p1, t, T, check_every=ce, rss_min=rss_min)
+        t_d, rss_d, g_d = S.smc_correct_async(m, p2, t, T, check_every=ce, rss_min=rss_min)
+        torch.cuda.synchronize()
+        assert int(t_d.item()) == t_h and t_h > t, cyc
+        assert float(rss_d.item()) == rss_h, cyc
+        assert torch.equal(_bits(g_d), _bits(g_h)), cyc
+        for a, b in ((p1.logw, p2.logw), (p1.loglik, p2.loglik)):
+            assert torch.equal(_bits(a), _bits(b)), cyc
+        if m.S:
+            assert torch.equal(_bits(p1.state), _bits(p2.state)), cyc
+        if t_h >= T:
+            break
+        for p in (p1, p2):
+            S.smc_resample(m, p, seed=4, cycle=cyc + 1)
+        t = t_h
+
+
+def test_device_driven_c_phase_in_a_graph():
+    """The device-driven C phase captured in a graph: every replay (after the
+    population's arrays are restored, with unrelated eager work between
+    replays) gives the host-driven call's results."""
+    w = SD.workload("egarch2t", T=400)
+    m = S.Model(w.kind, w.y[:400], K=w.K, shock=w.shock, precision=S.SMC_FP32)
+    p1, p2 = _pair(m, 4, 128, 32)
+    t_h, rss_h, g_h = S.smc_correct(m, p1, 0, 400, check_every=1, rss_min=0.5)
+    torch.cuda.synchronize()
+    saved = [x.clone() for x in (p2.state, p2.logw, p2.loglik)]
+    t_to = torch.zeros(1, dtype=torch.int64, device="cuda")
+    rss = torch.zeros(1, dtype=torch.float64, device="cuda")
+    glw = torch.zeros(4, dtype=torch.float64, device="cuda")
+    side = torch.cuda.Stream()
+    side.wait_stream(torch.cuda.current_stream())
+    with torch.cuda.stream(side):  # warm-up on the capture stream's side, as torch requires
+        S.smc_correct_async(m, p2, 0, 400, rss_min=0.5, group_logwbar=glw, t_to=t_to, rss=rss)
+    torch.cuda.current_stream().wait_stream(side)
+    torch.cuda.synchronize()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        S.smc_correct_async(m, p2, 0, 400, rss_min=0.5, group_logwbar=glw, t_to=t_to, rss=rss)
+    for rep in range(3):
+        for x, v in zip((p2.state, p2.logw, p2.loglik), saved):
+            x.copy_(v)
+        t_to.zero_()
+        rss.zero_()
+        p2.theta.add_(0.0)
+        torch.cuda.synchronize()
+        g.replay()
+        torch.cuda.synchronize()
+        assert int(t_to.item()) == t_h and float(rss.item()) == rss_h, rep
+        assert torch.equal(_bits(glw), _bits(g_h)), rep
+        for a, b in ((p1.logw, p2.logw), (p1.loglik, p2.loglik), (p1.state, p2.state)):
+            assert torch.equal(_bits(a), _bits(b)), rep
