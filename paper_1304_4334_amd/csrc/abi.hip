@@ -58,6 +58,8 @@ WsLayout ws_layout(const DevModel &m, int32_t J, int32_t N) {
   L.cyc = off;
   off += align256(sizeof(CycleDyn)) +
          align256((size_t)kGraphMaxCycles * (sizeof(int64_t) + sizeof(int32_t) + sizeof(double)));
+  L.acc = off;
+  off += 256 + align256((P + 63) / 64 * sizeof(int32_t));
   L.wcols = off;
   L.fixed = off;
   return L;
@@ -88,6 +90,17 @@ smc_status check_pop(const smc_model *m, const smc_particles *pop, bool need_ws 
       return set_error(SMC_E_WORKSPACE, "workspace of %zu bytes < %zu", pop->ws_bytes, L.fixed);
   }
   return SMC_OK;
+}
+
+// The workspace's accept-count sink (AccSink), or none when the workspace
+// does not hold the layout.
+AccSink acc_sink(const smc_model *m, const smc_particles *pop) {
+  if (!pop->ws || (reinterpret_cast<uintptr_t>(pop->ws) & 255)) return AccSink{};
+  const WsLayout L = ws_layout(m->dev, pop->J, pop->N);
+  if (pop->ws_bytes < L.fixed) return AccSink{};
+  char *base = static_cast<char *>(pop->ws) + L.acc;
+  return AccSink{reinterpret_cast<int32_t *>(base + 256),
+                 reinterpret_cast<unsigned long long *>(base)};
 }
 
 int64_t chunk_capacity(const smc_model *m, const smc_particles *pop) {
@@ -619,10 +632,17 @@ smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t
   if (!hchol || !n_accept) return set_error(SMC_E_INVALID_ARG, "hchol and n_accept are required");
   if (t < 0 || t > m->dev.T) return set_error(SMC_E_INVALID_ARG, "date t out of range");
   const int64_t P = (int64_t)pop->J * pop->N;
+  hipStream_t s = as_stream(stream);
+  // with a workspace, the counts go through its sink and are added at once
+  DevModel dm = m->dev;
+  dm.acc = acc_sink(m, pop);
+  auto flushed = [&](smc_status e) {
+    return (e || !dm.acc.part) ? e : launch_acc_flush(dm.acc, P, s);
+  };
   if (kernel == SMC_KERNEL_RW)
-    return launch_mutate_rw(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
-                            hchol, rng.seed, rng.run, (uint64_t)cycle, (uint64_t)iter, n_accept,
-                            accepted, as_stream(stream));
+    return flushed(launch_mutate_rw(dm, P, t, pop->theta, pop->logprior, pop->loglik,
+                                    pop->state, hchol, rng.seed, rng.run, (uint64_t)cycle,
+                                    (uint64_t)iter, n_accept, accepted, s));
   if (kernel == SMC_KERNEL_MALA) {
     if (!pop->grad) return set_error(SMC_E_INVALID_ARG, "the Langevin kernel needs pop->grad");
     if ((st = check_pop(m, pop))) return st;
@@ -631,16 +651,17 @@ smc_status smc_mutate(const smc_model *m, smc_particles *pop, int64_t t, int32_t
     if (pop->ws_bytes < L.wcols + need)
       return set_error(SMC_E_WORKSPACE, "Langevin step needs %zu workspace bytes",
                        L.wcols + need);
-    return launch_mutate_mala(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
-                              pop->grad, hchol, rng.seed, rng.run, (uint64_t)cycle,
-                              (uint64_t)iter, n_accept, accepted, ws_at<char>(pop, L.wcols),
-                              as_stream(stream));
+    return flushed(launch_mutate_mala(dm, P, t, pop->theta, pop->logprior, pop->loglik,
+                                      pop->state, pop->grad, hchol, rng.seed, rng.run,
+                                      (uint64_t)cycle, (uint64_t)iter, n_accept, accepted,
+                                      ws_at<char>(pop, L.wcols), s));
   }
   if (kernel == SMC_KERNEL_INDEPENDENT) {
     const int32_t d = m->dev.d;
-    return launch_mutate_indep(m->dev, P, t, pop->theta, pop->logprior, pop->loglik, pop->state,
-                               hchol, hchol + (int64_t)d * d, rng.seed, rng.run, (uint64_t)cycle,
-                               (uint64_t)iter, n_accept, accepted, as_stream(stream));
+    return flushed(launch_mutate_indep(dm, P, t, pop->theta, pop->logprior, pop->loglik,
+                                       pop->state, hchol, hchol + (int64_t)d * d, rng.seed,
+                                       rng.run, (uint64_t)cycle, (uint64_t)iter, n_accept,
+                                       accepted, s));
   }
   return set_error(SMC_E_INVALID_ARG, "kernel %d", kernel);
 }
@@ -802,11 +823,18 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   int32_t *dflags = ws_at<int32_t>(pop, L.small + kSmallFlags);
   if ((st = fill_i32(dflags, 1, 0, s))) return st;
   if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
+  // Each Metropolis step leaves its accept counts in the workspace's sink;
+  // the next iteration's moment partials add them to the record (after the
+  // phase's last step a launch of its own does).
+  DevModel dm = m->dev;
+  dm.acc = acc_sink(m, pop);
+  if ((st = fill_i64(reinterpret_cast<int64_t *>(dm.acc.pending), 1, 0, s))) return st;
   // Moments with the step-size rule folded in: no separate launch for it.
   MomArgs ma{};
   ma.theta = pop->theta;
   ma.P = P;
   ma.d = d;
+  ma.acc = dm.acc;
   ma.target_permille = cfg->kernel == SMC_KERNEL_MALA ? 574 : 250;
   ma.part = ws_at<double>(pop, L.mpart);
   ma.mh = mh;
@@ -919,12 +947,12 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       const KernelTimer timer{ev ? ev->a : nullptr, ev ? ev->b : nullptr};
       const KernelTimer *tp = ev && !bracket ? &timer : nullptr;
       if (indep) {
-        if ((st = launch_mutate_indep(m->dev, P, t_new, pop->theta, pop->logprior, pop->loglik,
+        if ((st = launch_mutate_indep(dm, P, t_new, pop->theta, pop->logprior, pop->loglik,
                                       pop->state, hl, mslot, cfg->rng.seed, cfg->rng.run,
                                       (uint64_t)(l + 1), (uint64_t)r, nacc, nullptr, s, tp)))
           return st;
       } else if (cfg->kernel == SMC_KERNEL_RW) {
-        if ((st = launch_mutate_rw(m->dev, P, t_new, pop->theta, pop->logprior, pop->loglik,
+        if ((st = launch_mutate_rw(dm, P, t_new, pop->theta, pop->logprior, pop->loglik,
                                    pop->state, fold ? nullptr : hl, cfg->rng.seed, cfg->rng.run,
                                    (uint64_t)(l + 1), (uint64_t)r, nacc, nullptr, s, tp,
                                    fold ? &fm : nullptr)))
@@ -935,6 +963,8 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       }
       if (ev && bracket && hipEventRecord(ev->b, s) != hipSuccess)
         return set_error(SMC_E_DEVICE, "event record failed");
+      // a replayed design computes no moments to carry the counts
+      if (cfg->replay && (st = launch_acc_flush(dm.acc, P, s))) return st;
       evals += P * t_new;
       ++steps;
       if (cfg->replay || cfg->stop_rule == 0) {
@@ -958,6 +988,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         if (rne > (at_date ? cfg->E2 : cfg->E1) || r >= cfg->Rmax) break;
       }
     }
+    if (!cfg->replay && (st = launch_acc_flush(dm.acc, P, s))) return st;  // the phase's last step
     if (rec->moments &&
         (st = smc_test_moments(m, pop, t_new, cfg->test_fn, rec->moments + (int64_t)l * G * 4,
                                stream)))
@@ -1049,6 +1080,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
   StopInfo *stop_dev = ws_at<StopInfo>(pop, L.small + kSmallStop);
   DevModel dm = m->dev;
   dm.cyc = cyc;
+  dm.acc = acc_sink(m, pop);
 
   StepKey key;
   memset(&key, 0, sizeof key);
@@ -1103,6 +1135,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
         ma.flags = dflags;
         ma.cyc = cyc;
         ma.slot = k;
+        ma.acc = dm.acc;  // adds the previous slot's accept counts
         MomFuse fm{};
         int64_t nb = 0;
         if ((e = launch_moment_partials(ma, &fm.part, nb, cs))) return e;
@@ -1116,7 +1149,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
                                   nullptr, cs, nullptr, &fm)))
           return e;
       }
-      return launch_cycle_end(cyc, t_end_d, r_d, rss_d, dflags, prog, cs);
+      return launch_cycle_end(cyc, t_end_d, r_d, rss_d, dflags, prog, dm.acc, cs);
     };
     if (hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal) != hipSuccess) {
       (void)hipStreamDestroy(cs);
@@ -1142,6 +1175,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
   // eager set-up, as the host-driven run does it
   if ((st = fill_i32(dflags, 1, 0, s)) ||
       (st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s)) ||
+      (st = fill_i64(reinterpret_cast<int64_t *>(dm.acc.pending), 1, 0, s)) ||
       (st = smc_init_from_prior(m, pop, cfg->rng, s)))
     return st;
   CycleDyn init{};

@@ -18,6 +18,19 @@ enum Purpose : uint64_t { kPrior = 1, kResample = 2, kProposal = 3, kAccept = 4 
 
 struct CycleDyn;
 
+// Accepted-proposal counts without same-address atomics (a launch's
+// per-wave atomic adds on one counter serialise in memory at its end, about
+// 10 us for 1,024 waves): each wave of a Metropolis step that holds particles
+// stores its count at its own index, and block 0 stores the address of the
+// counter the counts belong to in *pending.  A later kernel on the stream
+// (acc_flush: the next iteration's moment partials, a device-driven step's
+// end, or a launch of its own) adds them to that counter and clears
+// *pending.  part == NULL: the step adds to its counter atomically.
+struct AccSink {
+  int32_t *part;                // [ceil(P / 64)] per-wave counts
+  unsigned long long *pending;  // address of the counter they belong to, or 0
+};
+
 // Everything a kernel needs to know about a model, passed by value.
 struct DevModel {
   int32_t kind;
@@ -35,6 +48,7 @@ struct DevModel {
   const float *y32;
   const double *X;
   const CycleDyn *cyc;  // device-driven cycle (graph steps), else NULL
+  AccSink acc;          // where the Metropolis steps leave their accept counts
 };
 
 // State of an adaptive run whose C/S/M cycles are driven on the device
@@ -77,6 +91,35 @@ __device__ __forceinline__ bool m_slot_off(const CycleDyn *c, int32_t k) {
   return c && (!c->go_m || c->r0 + k > c->R);
 }
 
+// The end of a Metropolis step's wave (wave: its index in the launch): its
+// accept count goes to acc, or without a sink atomically to *n_accept.
+__device__ __forceinline__ void acc_store(const AccSink &acc, unsigned long long mask,
+                                          int64_t wave, int64_t P,
+                                          unsigned long long *n_accept) {
+  if (acc.part) {
+    if ((threadIdx.x & 63) == 0 && wave * 64 < P) acc.part[wave] = (int32_t)__popcll(mask);
+    if (blockIdx.x == 0 && threadIdx.x == 0)
+      *acc.pending = reinterpret_cast<unsigned long long>(n_accept);
+  } else if ((threadIdx.x & 63) == 0 && mask) {
+    atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+  }
+}
+
+// Adds the pending per-wave counts of a P-particle step to their counter and
+// clears the mark (nothing pending: nothing to do).  Called by a whole wave.
+__device__ __forceinline__ void acc_flush(const AccSink &acc, int64_t P) {
+  const unsigned long long dst = *acc.pending;
+  if (!dst) return;
+  const int lane = threadIdx.x & 63;
+  long long s = 0;
+  for (int64_t i = lane; i < (P + 63) / 64; i += 64) s += acc.part[i];
+  for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
+  if (lane == 0) {
+    *reinterpret_cast<long long *>(dst) += s;
+    *acc.pending = 0;
+  }
+}
+
 // Cycles a graph-replayed run records on the device.
 constexpr int32_t kGraphMaxCycles = 4096;
 
@@ -90,6 +133,8 @@ struct WsLayout {
   size_t mpart;    // [kMomBlocks + 1][W^2] doubles (moment partials and their sum)
   size_t rpart;    // [J][2 * kDMax] doubles (RNE)
   size_t cyc;      // CycleDyn, then t_end [kGraphMaxCycles] int64, R [..] int32, rss [..]
+  size_t acc;      // AccSink: the pending counter's address, then at +256 the
+                   // per-wave accept counts [ceil(P/64)] int32
   size_t wcols;    // tail of [chunk][P] doubles: the C-phase scan's per-wave RSS sums
                    // ([chunk][ceil(P/64)][3]) or the adjoint's checkpoints
   size_t fixed;    // bytes before wcols

@@ -352,7 +352,10 @@ __global__ void k_cycle_init(CycleDyn *c, CycleDyn init) {
 // a chunk that did not end the phase: the next chunk, twice as long.  The
 // host follows the run through *host: progress << 2 | err << 1 | done.
 __global__ void k_cycle_end(CycleDyn *cp, int64_t *t_end, int32_t *r_rec, double *rss_rec,
-                            const int32_t *flags, uint32_t *host) {
+                            const int32_t *flags, uint32_t *host, AccSink acc) {
+  // the last M slot's accept counts (the slots' own moment launches add
+  // those of the slots before them)
+  if (acc.pending) acc_flush(acc, cp->P);
   if (threadIdx.x != 0) return;
   CycleDyn c = *cp;
   if (c.done || c.err) return;
@@ -874,12 +877,19 @@ __global__ void __launch_bounds__(kSBlock) k_resample(const double *logw, int32_
 // lane l holds element (4r + l/16, l%16) of the 16x16 result.  With W = 32
 // each lane holds rows i and 16 + i, and three products per step give the
 // (0,0), (1,0) and (1,1) tiles of the symmetric result.  Each block writes
-// one W x W partial matrix.
+// one W x W partial matrix.  With sink.pending, one block more, the last,
+// adds the previous Metropolis step's accept counts to their counter
+// (acc_flush) while the others form the partials.
 template <int W>
 __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_t P, int32_t d,
                                                      int64_t chunk, double *part,
-                                                     const CycleDyn *cyc, int32_t slot) {
+                                                     const CycleDyn *cyc, int32_t slot,
+                                                     AccSink sink) {
   if (m_slot_off(cyc, slot)) return;  // an unused M slot of a device-driven cycle
+  if (sink.pending && blockIdx.x == gridDim.x - 1) {
+    if (threadIdx.x < 64) acc_flush(sink, P);
+    return;
+  }
   constexpr int NT = W / 16;
   constexpr int NA = NT == 1 ? 1 : 3;  // tiles accumulated
   __shared__ double red[4][W * W];
@@ -1354,9 +1364,18 @@ smc_status launch_cycle_init(CycleDyn *c, const CycleDyn &init, hipStream_t s) {
 }
 
 smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double *rss_rec,
-                            const int32_t *flags, uint32_t *host, hipStream_t s) {
-  hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, s, c, t_end, r_rec, rss_rec, flags, host);
+                            const int32_t *flags, uint32_t *host, const AccSink &acc,
+                            hipStream_t s) {
+  hipLaunchKernelGGL(k_cycle_end, dim3(1), dim3(64), 0, s, c, t_end, r_rec, rss_rec, flags, host,
+                     acc);
   return launch_status("cycle/end");
+}
+
+__global__ void k_acc_flush(AccSink acc, int64_t P) { acc_flush(acc, P); }
+
+smc_status launch_acc_flush(const AccSink &acc, int64_t P, hipStream_t s) {
+  hipLaunchKernelGGL(k_acc_flush, dim3(1), dim3(64), 0, s, acc, P);
+  return launch_status("accept counts");
 }
 
 smc_status launch_phase_init(CycleDyn *c, const CycleDyn &init, hipStream_t s) {
@@ -1421,13 +1440,14 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   moment_partition(a.P, a.d, chunk, nb);
   if (nb > kMomBlocks)
     return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
+  const int64_t xb = a.acc.pending ? 1 : 0;  // the accept-count flush
   const int n = a.d + 1 <= 16 ? 256 : 1024;  // entries of a partial matrix
   if (n == 256) {
-    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   } else {
-    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
@@ -1452,13 +1472,14 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   moment_partition(a.P, a.d, chunk, nb);
   if (nb > kMomBlocks)
     return set_error(SMC_E_WORKSPACE, "moments need %lld partials", (long long)nb);
+  const int64_t xb = a.acc.pending ? 1 : 0;  // the accept-count flush
   const int n = a.d + 1 <= 16 ? 256 : 1024;
   if (n == 256)
-    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   else
-    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
   // summed into the slot after the partials, as launch_moments does

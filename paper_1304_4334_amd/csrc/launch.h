@@ -139,7 +139,11 @@ smc_status launch_resample(const double *logw, int32_t J, int32_t N, int32_t sch
 // (record, counters, the next chunk; progress word in mapped host memory).
 smc_status launch_cycle_init(CycleDyn *c, const CycleDyn &init, hipStream_t s);
 smc_status launch_cycle_end(CycleDyn *c, int64_t *t_end, int32_t *r_rec, double *rss_rec,
-                            const int32_t *flags, uint32_t *host, hipStream_t s);
+                            const int32_t *flags, uint32_t *host, const AccSink &acc,
+                            hipStream_t s);
+// Adds the pending accept counts of a P-particle Metropolis step to their
+// counter (AccSink); nothing pending: nothing to do.
+smc_status launch_acc_flush(const AccSink &acc, int64_t P, hipStream_t s);
 // A C phase driven on the device (smc_correct_async): open the first chunk,
 // advance after each chunk, copy the end date and RSS to the caller (with
 // c NULL: t_fixed and *rss_src).
@@ -160,6 +164,8 @@ struct MomArgs {
   double *mean_out, *cov_out, *hchol;
   int32_t *flags;
   const CycleDyn *cyc;      // device-driven cycle, else NULL
+  AccSink acc;              // with acc.pending: the partials' launch also adds the
+                            // previous step's pending accept counts (acc_flush)
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
 // Only the partial sums of launch_moments, for a step that folds the rest in

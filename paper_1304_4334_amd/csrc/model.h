@@ -129,6 +129,46 @@ __device__ __forceinline__ double t_scale<float>() { return kLn2; }
 
 __device__ __forceinline__ double normal_logpdf_std(double z) { return -0.5 * kLog2Pi - 0.5 * z * z; }
 
+// The Student-t density's per-observation constant
+//   log Gamma((nu + 1)/2) - log Gamma(nu/2) - log(pi (nu - 2)) / 2,   nu > 2,
+// without the library's branchy lgamma.  With x = nu/2 >= 1, the recurrence
+// log Gamma(z + 1) = log Gamma(z) + log z moves both arguments up by 8:
+//   D(x) = D(x + 8) - log prod_{k<8} (x + k + 1/2) / (x + k),
+// D(z) = log Gamma(z + 1/2) - log Gamma(z).  At y = x + 8 >= 9 Stirling's
+// series, with the Bernoulli polynomials at 1/2 and at 0, gives
+//   D(y) = log(y)/2 + sum over odd k of (2^-k - 2) B_{k+1} / (k (k+1) y^k);
+// kLgHalf holds those coefficients for k = 1, 3, ..., 15 (the first omitted
+// term is below 3e-17 at y = 9).  All logarithms are taken at once, of
+// y r^2 / (pi (nu - 2)) with r the products' ratio.  Beyond x = 2^100 the
+// ratio is 1 to rounding (and its products would overflow), so the
+// products use min(x, 2^100).
+__device__ constexpr double kLgHalf[8] = {
+  -0x1.0000000000000p-3,
+  0x1.5555555555555p-8,
+  -0x1.999999999999ap-10,
+  0x1.36db6db6db6dbp-10,
+  -0x1.b8e38e38e38e4p-10,
+  0x1.f68ba2e8ba2e9p-9,
+  -0x1.a413b13b13b14p-7,
+  0x1.e426888888889p-5,
+};
+__device__ __forceinline__ double t_log_const(double nu) {
+  const double x = 0.5 * nu;
+  const double xs = fmin(x, 0x1p100);
+  double num = xs + 0.5, den = xs;
+#pragma unroll
+  for (int k = 1; k < 8; ++k) {
+    num *= xs + (k + 0.5);
+    den *= xs + k;
+  }
+  const double y = x + 8.0, iy = 1.0 / y, w = iy * iy;
+  double s = kLgHalf[7];
+#pragma unroll
+  for (int j = 6; j >= 0; --j) s = fma(s, w, kLgHalf[j]);
+  const double r = den / num;
+  return fma(s, iy, 0.5 * log(y * r * r / (M_PI * (nu - 2.0))));
+}
+
 // ---------------------------------------------------------------- EGARCH --
 // theta = (th1, th2, th3_1..K, th4_1..K, th5_1..K, then th9 = log(nu - 2) for
 // Student-t shocks or th6_1..I, th7_1..I, th8_1..I for normal-mixture shocks),
@@ -296,7 +336,7 @@ struct Egarch {
       const double nu = 2.0 + exp(th[2 + 3 * K]);
       p.inu2 = (R)exp(-th[2 + 3 * K]);
       p.hnu1 = 0.5 * (nu + 1.0);
-      p.cst = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * (nu - 2.0));
+      p.cst = t_log_const(nu);
     } else if constexpr (kMix) {
       double pw[I], mu[I], sg[I];
       mixture(th, pw, mu, sg);
@@ -347,7 +387,7 @@ struct Egarch {
       const double nu = 2.0 + exp(th[2 + 3 * K]);
       p.inu2 = (R)(q * q);
       p.hnu1 = 0.5 * (nu + 1.0);
-      p.cst = lgamma(0.5 * (nu + 1.0)) - lgamma(0.5 * nu) - 0.5 * log(M_PI * (nu - 2.0));
+      p.cst = t_log_const(nu);
     } else if constexpr (kMix) {
       double pw[I], mu[I], sg[I];
       mixture(th, pw, mu, sg);

@@ -411,8 +411,7 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
     }
     if (accepted) accepted[p] = (uint8_t)acc;
   }
-  const unsigned long long mask = __ballot(acc);
-  if ((threadIdx.x & 63) == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+  acc_store(dm.acc, __ballot(acc), (blockIdx.x * (int64_t)B + threadIdx.x) >> 6, P, n_accept);
 }
 
 // Launch of the random-walk step in shape (B, U).
@@ -522,8 +521,7 @@ __global__ void __launch_bounds__(64) k_mutate_indep(DevModel dm, int64_t P, int
     }
     if (accepted) accepted[p] = (uint8_t)acc;
   }
-  const unsigned long long mask = __ballot(acc);
-  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+  acc_store(dm.acc, __ballot(acc), blockIdx.x, P, n_accept);
 }
 
 // ------------------------------------------------- standalone likelihood --
@@ -719,8 +717,7 @@ __global__ void __launch_bounds__(64) k_mutate_mala(DevModel dm, int64_t P, int6
                       iter, ckpt, lds_dyn);
     if (accepted) accepted[p] = (uint8_t)acc;
   }
-  const unsigned long long mask = __ballot(acc);
-  if (threadIdx.x == 0 && mask) atomicAdd(n_accept, (unsigned long long)__popcll(mask));
+  acc_store(dm.acc, __ballot(acc), blockIdx.x, P, n_accept);
 }
 
 // ---------------------------------------------- functions of interest (f) --

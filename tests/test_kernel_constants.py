@@ -7,6 +7,13 @@ below 4e-17, a third of an ulp, and it must be exact at f = 0.
 
 kLn2Hi / kLn2Lo (model.h): ln 2 split over two doubles for the weights'
 exponential, whose arithmetic is replayed here against long double.
+
+kLgHalf and t_log_const (model.h): the Student-t density's constant
+log Gamma((nu+1)/2) - log Gamma(nu/2) - log(pi (nu - 2))/2 by an upward shift
+and Stirling's series.  The coefficients must be the series' own (Bernoulli
+numbers, rounded to double), and the device's double arithmetic, replayed
+here in the same order, must stay within 4e-15 of the exact constant
+(100-digit arithmetic) from nu just above 2 to nu = 1e40.
 """
 import os
 import re
@@ -119,3 +126,56 @@ int main(void) {{
         [str(exe)], check=True, capture_output=True, text=True).stdout.split())
     assert worst < 2.0, worst
     assert at_neg_inf == 0.0 and at_zero == 1.0
+
+
+def _lghalf_coefficients():
+    src = open(MODEL_H).read()
+    m = re.search(r"kLgHalf\[(\d+)\]\s*=\s*\{([^}]*)\}", src)
+    assert m, "kLgHalf not found"
+    vals = [float.fromhex(v.strip()) for v in m.group(2).split(",") if v.strip()]
+    assert len(vals) == int(m.group(1))
+    return vals
+
+
+def test_t_constant_series_coefficients_are_the_bernoulli_terms():
+    from fractions import Fraction as F
+    bern = {2: F(1, 6), 4: F(-1, 30), 6: F(1, 42), 8: F(-1, 30), 10: F(5, 66),
+            12: F(-691, 2730), 14: F(7, 6), 16: F(-3617, 510)}
+    got = _lghalf_coefficients()
+    for j, k in enumerate(range(1, 17, 2)):
+        want = (F(1, 2 ** k) - 2) * bern[k + 1] / (k * (k + 1))
+        assert got[j] == float(want), (k, got[j], float(want))
+
+
+def _t_log_const_replayed(nu):
+    """t_log_const's double arithmetic in the device's order (libm's log)."""
+    import math
+    c = _lghalf_coefficients()
+    x = 0.5 * nu
+    xs = min(x, 2.0 ** 100)
+    num, den = xs + 0.5, xs
+    for k in range(1, 8):
+        num *= xs + (k + 0.5)
+        den *= xs + k
+    y = x + 8.0
+    iy = 1.0 / y
+    w = iy * iy
+    s = c[7]
+    for j in range(6, -1, -1):
+        s = math.fma(s, w, c[j]) if hasattr(math, "fma") else s * w + c[j]
+    r = den / num
+    v = 0.5 * math.log(y * r * r / (math.pi * (nu - 2.0)))
+    return s * iy + v
+
+
+def test_t_constant_within_4e15_of_the_exact_value():
+    mp = pytest.importorskip("mpmath")
+    mp.mp.dps = 100  # the two log-gammas reach 1e42 at nu = 1e40
+    worst = 0.0
+    nus = [2.0 + 10.0 ** e for e in range(-12, 41)]
+    nus += [2.0 + 0.37 * k for k in range(1, 400)]
+    for nu in nus:
+        n = mp.mpf(nu)
+        exact = mp.loggamma((n + 1) / 2) - mp.loggamma(n / 2) - mp.log(mp.pi * (n - 2)) / 2
+        worst = max(worst, abs(float(exact - mp.mpf(_t_log_const_replayed(nu)))))
+    assert worst < 4e-15, worst
