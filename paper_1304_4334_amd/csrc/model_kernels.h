@@ -230,30 +230,55 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 // otherwise only the block's first wave runs this, ordering its LDS
 // accesses by wavefront fences (LDS operations of one wave complete in
 // order), and the caller synchronises the block afterwards.
+// The first partial matrix's entries (lane entries idx = lane + 64 q), the
+// step size and the previous accept count, loaded by the scaling wave ahead
+// of the step's proposal draws so that their latency overlaps those.
+template <int D>
+struct ScalePre {
+  static constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
+  static constexpr int Q = (E + 63) / 64;
+  double x0[Q];
+  int32_t m;
+  int64_t nacc;
+};
+
+template <int D, int W>
+__device__ __forceinline__ void fused_scale_issue(const MomFuse &fm, ScalePre<D> &pre) {
+  const int lane = threadIdx.x & 63;
+  pre.m = 0;
+  pre.nacc = 0;
+  if (lane == 0) {
+    pre.m = *fm.mh_in;
+    if (fm.mh_reset <= 0 && fm.prev_nacc) pre.nacc = *fm.prev_nacc;
+  }
+#pragma unroll
+  for (int q = 0; q < ScalePre<D>::Q; ++q) {
+    const int idx = lane + 64 * q;
+    const int e = (idx / (D + 1)) * W + idx % (D + 1);
+    pre.x0[q] = (idx < ScalePre<D>::E && fm.nb > 0) ? fm.part[e] : 0.0;
+  }
+}
+
 template <int D, int W, bool kOneWave = true>
 __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double *Ms, double *Ls,
-                                            double *sh_h, double &h) {
+                                            double *sh_h, double &h, const ScalePre<D> &pre) {
   const auto sync = [] {
     if constexpr (kOneWave) __syncthreads();
     else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
   };
-  constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
+  constexpr int E = ScalePre<D>::E;
   const int lane = threadIdx.x;
-  int32_t m = 0;
-  int64_t nacc = 0;
-  if (lane == 0) {
-    m = *fm.mh_in;
-    if (fm.mh_reset <= 0 && fm.prev_nacc) nacc = *fm.prev_nacc;
-  }
-  // Lane entries idx = lane + 64 q; each batch issues the loads of every
-  // entry before adding any, so the partials' latency is paid once per batch
-  // (a single round: the partials come pre-summed into one matrix).
-  constexpr int Q = (E + 63) / 64;
+  int32_t m = pre.m;
+  const int64_t nacc = pre.nacc;
+  // Lane entries idx = lane + 64 q, added in block order; the first partial
+  // came with pre, the rest (none when the partials come pre-summed into one
+  // matrix) in batches whose loads are all issued before any is added.
+  constexpr int Q = ScalePre<D>::Q;
   constexpr int kB = Q >= 32 ? 1 : 32 / Q;  // partials per entry in flight
   double sum[Q];
 #pragma unroll
-  for (int q = 0; q < Q; ++q) sum[q] = 0.0;
-  for (int b0 = 0; b0 < fm.nb; b0 += kB) {
+  for (int q = 0; q < Q; ++q) sum[q] = 0.0 + pre.x0[q];
+  for (int b0 = 1; b0 < fm.nb; b0 += kB) {
     double x[Q][kB];
 #pragma unroll
     for (int q = 0; q < Q; ++q) {
@@ -344,6 +369,9 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
   // The particle's loads and its proposal draws first: their latency and
   // arithmetic overlap the proposal scale's loads and factorisation.
   const int64_t pc = p < P ? p : P - 1;
+  ScalePre<D> pre;
+  if constexpr (kCanFuse)
+    if (fm.part && (B == 64 || threadIdx.x < 64)) fused_scale_issue<D, W>(fm, pre);
   double th[D], z[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) th[i] = theta[i * P + pc];
@@ -354,11 +382,11 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
     if (fm.part) {
       fused = true;
       if constexpr (B == 64) {
-        chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h);
+        chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h, pre);
       } else {
         // the first wave factors V for the whole block
         if (threadIdx.x < 64) {
-          const bool ok = fused_scale<D, W, false>(fm, P, Ms, Ls, &sh_h, h);
+          const bool ok = fused_scale<D, W, false>(fm, P, Ms, Ls, &sh_h, h, pre);
           if (threadIdx.x == 0) sh_ok = ok;
         }
         __syncthreads();
