@@ -824,8 +824,9 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   if ((st = fill_i32(dflags, 1, 0, s))) return st;
   if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
   // Each Metropolis step leaves its accept counts in the workspace's sink;
-  // the next iteration's moment partials add them to the record (after the
-  // phase's last step a launch of its own does).
+  // the next iteration's moment sums add them to the record (those of a
+  // phase's last step the next phase's first moments, and after the run's
+  // last step a launch of its own).
   DevModel dm = m->dev;
   dm.acc = acc_sink(m, pop);
   if ((st = fill_i64(reinterpret_cast<int64_t *>(dm.acc.pending), 1, 0, s))) return st;
@@ -884,6 +885,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     // correct_impl has waited for its last decision, which carried the flags
     if (fl_seen > 0 && l > 0) {
       rec->L = l;
+      (void)launch_acc_flush(dm.acc, P, s);  // the previous phase's last step
       return set_error(SMC_E_NUMERIC, "numerical flags 0x%x in cycle %d", fl_seen, l);
     }
     last_len = t_new - t;
@@ -988,7 +990,6 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
         if (rne > (at_date ? cfg->E2 : cfg->E1) || r >= cfg->Rmax) break;
       }
     }
-    if (!cfg->replay && (st = launch_acc_flush(dm.acc, P, s))) return st;  // the phase's last step
     if (rec->moments &&
         (st = smc_test_moments(m, pop, t_new, cfg->test_fn, rec->moments + (int64_t)l * G * 4,
                                stream)))
@@ -1000,6 +1001,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     rec->rss[l] = rss;
     t = t_new;
     ++l;
+    if (t >= T && (st = launch_acc_flush(dm.acc, P, s))) return st;  // the run's last step
     // without the pinned slot (or after the last cycle) the flags are read here
     if (!cfg->replay && (!decision_slot() || t >= T)) {
       int32_t fl = 0;
@@ -1135,7 +1137,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
         ma.flags = dflags;
         ma.cyc = cyc;
         ma.slot = k;
-        ma.acc = dm.acc;  // adds the previous slot's accept counts
+        ma.acc = dm.acc;  // the moment sums add the previous slot's accept counts
         MomFuse fm{};
         int64_t nb = 0;
         if ((e = launch_moment_partials(ma, &fm.part, nb, cs))) return e;

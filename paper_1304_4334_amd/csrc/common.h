@@ -23,8 +23,8 @@ struct CycleDyn;
 // 10 us for 1,024 waves): each wave of a Metropolis step that holds particles
 // stores its count at its own index, and block 0 stores the address of the
 // counter the counts belong to in *pending.  A later kernel on the stream
-// (acc_flush: the next iteration's moment partials, a device-driven step's
-// end, or a launch of its own) adds them to that counter and clears
+// (acc_flush: the next iteration's moment sums, a device-driven step's end,
+// or a launch of its own) adds them to that counter and clears
 // *pending.  part == NULL: the step adds to its counter atomically.
 struct AccSink {
   int32_t *part;                // [ceil(P / 64)] per-wave counts
@@ -106,16 +106,30 @@ __device__ __forceinline__ void acc_store(const AccSink &acc, unsigned long long
 }
 
 // Adds the pending per-wave counts of a P-particle step to their counter and
-// clears the mark (nothing pending: nothing to do).  Called by a whole wave.
+// clears the mark (nothing pending: nothing to do).  Called by a whole wave;
+// the counts are loaded together with the mark, and the total goes to the
+// counter by one atomic add, so the chain is a single round trip.
 __device__ __forceinline__ void acc_flush(const AccSink &acc, int64_t P) {
-  const unsigned long long dst = *acc.pending;
-  if (!dst) return;
   const int lane = threadIdx.x & 63;
+  const int64_t nw = (P + 63) / 64;
+  constexpr int kB = 16;  // loads per lane in flight together (1,024 waves in one round)
   long long s = 0;
-  for (int64_t i = lane; i < (P + 63) / 64; i += 64) s += acc.part[i];
+  unsigned long long dst = 0;
+  for (int64_t base = 0; base < nw; base += 64 * kB) {
+    int32_t x[kB];
+#pragma unroll
+    for (int u = 0; u < kB; ++u) {
+      const int64_t i = base + u * 64 + lane;
+      x[u] = i < nw ? acc.part[i] : 0;
+    }
+    if (base == 0) dst = *acc.pending;
+#pragma unroll
+    for (int u = 0; u < kB; ++u) s += x[u];
+  }
+  if (!dst) return;
   for (int off = 32; off > 0; off >>= 1) s += __shfl_xor(s, off);
   if (lane == 0) {
-    *reinterpret_cast<long long *>(dst) += s;
+    atomicAdd(reinterpret_cast<unsigned long long *>(dst), (unsigned long long)s);
     *acc.pending = 0;
   }
 }

@@ -129,7 +129,14 @@ __global__ void __launch_bounds__(64) k_cscan(DevModel dm, int64_t P, const doub
     if (mine && m > -INFINITY) {
 #pragma unroll
       for (int j = 0; j < 16; ++j) {
-        const double e = exp_nonpos(v[j] - m);
+        // FP32 recursions: the hardware base-2 exponential (its 1e-7 relative
+        // error is far below that of weights summed from FP32 log densities;
+        // terms below 2^-126 of the maximum are dropped); FP64: exp_nonpos
+        double e;
+        if constexpr (std::is_same_v<R, float>)
+          e = (double)__builtin_amdgcn_exp2f((float)((v[j] - m) * kLog2e));
+        else
+          e = exp_nonpos(v[j] - m);
         s1 += e;
         s2 = fma(e, e, s2);
       }
