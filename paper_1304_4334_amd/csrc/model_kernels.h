@@ -228,18 +228,15 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 }
 
 // ------------------------------------------------------------ M phase (a5) --
-// The proposal scale of a random-walk step computed by the step's own wave
-// (MomFuse): the moment partials summed entry by entry in block order, the
-// step-size rule, V and its Cholesky factor in LDS, exactly as the separate
-// moments kernels do (k_mom_final).  Returns whether V was positive definite;
-// h receives the step size.
-// kOneWave: the block is this one wave (its barriers are block barriers);
-// otherwise only the block's first wave runs this, ordering its LDS
-// accesses by wavefront fences (LDS operations of one wave complete in
-// order), and the caller synchronises the block afterwards.
+// The proposal scale of a random-walk step computed by one wave of the
+// step's own block, its scaling wave (MomFuse): the moment partials summed
+// entry by entry in block order, the step-size rule, V and its Cholesky
+// factor in LDS, exactly as the separate moments kernels do (k_mom_final).
+// Returns whether V was positive definite; h receives the step size.  The
+// wave orders its LDS accesses by wavefront fences (LDS operations of one
+// wave complete in order); the block synchronises afterwards.
 // The first partial matrix's entries (lane entries idx = lane + 64 q), the
-// step size and the previous accept count, loaded by the scaling wave ahead
-// of the step's proposal draws so that their latency overlaps those.
+// step size and the previous accept count, all loaded together.
 template <int D>
 struct ScalePre {
   static constexpr int E = (D + 1) * (D + 1);  // entries used: rows and columns 0..D
@@ -266,15 +263,12 @@ __device__ __forceinline__ void fused_scale_issue(const MomFuse &fm, ScalePre<D>
   }
 }
 
-template <int D, int W, bool kOneWave = true>
+template <int D, int W>
 __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double *Ms, double *Ls,
                                             double *sh_h, double &h, const ScalePre<D> &pre) {
-  const auto sync = [] {
-    if constexpr (kOneWave) __syncthreads();
-    else __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-  };
+  const auto sync = [] { __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront"); };
   constexpr int E = ScalePre<D>::E;
-  const int lane = threadIdx.x;
+  const int lane = threadIdx.x & 63;
   int32_t m = pre.m;
   const int64_t nacc = pre.nacc;
   // Lane entries idx = lane + 64 q, added in block order; the first partial
@@ -334,13 +328,17 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
                                    blockIdx.x == 0 ? fm.flags : nullptr);
 }
 
-// B threads (B/64 waves) per block, observations loaded U at a time; the
-// launch shape does not change any result.  In a device-driven cycle
-// (dm.cyc) the launch is M slot `iter` of its step: it runs iteration
-// r = r0 + iter of the cycle while r <= R, at the cycle's date and key, with
-// the record slots, step-size slots and rule of that iteration.
+// B particles (B/64 waves) per block, observations loaded U at a time; the
+// launch shape does not change any result.  With the proposal scale folded
+// in (fm.part), the launch has one wave more per block, threads B..B+63: it
+// loads the summed moments and factors V while the particle waves load
+// their particles and draw their proposals, and hands h L over in LDS.  In
+// a device-driven cycle (dm.cyc) the launch is M slot `iter` of its step: it
+// runs iteration r = r0 + iter of the cycle while r <= R, at the cycle's date
+// and key, with the record slots, step-size slots and rule of that iteration.
 template <class M, int B = 64, int U = kUnroll>
-__global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t t, double *theta,
+__global__ void __launch_bounds__(B + 64) k_mutate_rw(DevModel dm, int64_t P, int64_t t,
+                                                      double *theta,
                                                  double *logprior, double *loglik, void *state,
                                                  const double *__restrict__ hchol, uint64_t seed,
                                                  uint64_t run, uint64_t cycle, uint64_t iter,
@@ -372,13 +370,19 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
     fm.mh_in = (r & 1) ? mh + 1 : mh;
     fm.mh_out = (r & 1) ? mh : mh + 1;
   }
+  if constexpr (kCanFuse) {
+    if (threadIdx.x >= B) {  // the scaling wave (launched with fm.part only)
+      ScalePre<D> pre;
+      fused_scale_issue<D, W>(fm, pre);
+      double hs = 0.0;
+      const bool ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, hs, pre);
+      if (threadIdx.x == B) sh_ok = ok;
+      __syncthreads();
+      return;
+    }
+  }
   const int64_t p = blockIdx.x * (int64_t)B + threadIdx.x;
-  // The particle's loads and its proposal draws first: their latency and
-  // arithmetic overlap the proposal scale's loads and factorisation.
   const int64_t pc = p < P ? p : P - 1;
-  ScalePre<D> pre;
-  if constexpr (kCanFuse)
-    if (fm.part && (B == 64 || threadIdx.x < 64)) fused_scale_issue<D, W>(fm, pre);
   double th[D], z[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) th[i] = theta[i * P + pc];
@@ -388,18 +392,9 @@ __global__ void __launch_bounds__(B) k_mutate_rw(DevModel dm, int64_t P, int64_t
   if constexpr (kCanFuse) {
     if (fm.part) {
       fused = true;
-      if constexpr (B == 64) {
-        chol_ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, h, pre);
-      } else {
-        // the first wave factors V for the whole block
-        if (threadIdx.x < 64) {
-          const bool ok = fused_scale<D, W, false>(fm, P, Ms, Ls, &sh_h, h, pre);
-          if (threadIdx.x == 0) sh_ok = ok;
-        }
-        __syncthreads();
-        chol_ok = sh_ok != 0;
-        h = sh_h;
-      }
+      __syncthreads();  // the scaling wave's h L
+      chol_ok = sh_ok != 0;
+      h = sh_h;
     }
   }
   int acc = 0;
@@ -463,12 +458,13 @@ smc_status launch_rw_shape(const DevModel &m, int64_t P, int64_t t, double *thet
     fm = *fuse;
   }
   const typename M::Y *yd = Eval<M>::host_y(m);
+  const dim3 threads(fm.part ? B + 64 : B);  // the scaling wave of a folded scale
   if (timer)
-    hipExtLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), dim3(B), 0, s, timer->start,
+    hipExtLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), threads, 0, s, timer->start,
                           timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
                           run, cycle, iter, acc, accepted, fm, yd);
   else
-    hipLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), dim3(B), 0, s, m, P, t, theta,
+    hipLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), threads, 0, s, m, P, t, theta,
                        logprior, loglik, state, hchol, seed, run, cycle, iter, acc, accepted, fm,
                        yd);
   return launch_status("mutate");
