@@ -229,12 +229,13 @@ __global__ void __launch_bounds__(64) k_ccommit(DevModel dm, int64_t P, const do
 
 // ------------------------------------------------------------ M phase (a5) --
 // The proposal scale of a random-walk step computed by one wave of the
-// step's own block, its scaling wave (MomFuse): the moment partials summed
-// entry by entry in block order, the step-size rule, V and its Cholesky
-// factor in LDS, exactly as the separate moments kernels do (k_mom_final).
-// Returns whether V was positive definite; h receives the step size.  The
-// wave orders its LDS accesses by wavefront fences (LDS operations of one
-// wave complete in order); the block synchronises afterwards.
+// step's own block, its scaling wave or its first particle wave (MomFuse):
+// the moment partials summed entry by entry in block order, the step-size
+// rule, V and its Cholesky factor in LDS, exactly as the separate moments
+// kernels do (k_mom_final).  Returns whether V was positive definite; h
+// receives the step size.  The wave orders its LDS accesses by wavefront
+// fences (LDS operations of one wave complete in order); the block
+// synchronises afterwards.
 // The first partial matrix's entries (lane entries idx = lane + 64 q), the
 // step size and the previous accept count, all loaded together.
 template <int D>
@@ -330,14 +331,21 @@ __device__ __forceinline__ bool fused_scale(const MomFuse &fm, int64_t P, double
 
 // B particles (B/64 waves) per block, observations loaded U at a time; the
 // launch shape does not change any result.  With the proposal scale folded
-// in (fm.part), the launch has one wave more per block, threads B..B+63: it
-// loads the summed moments and factors V while the particle waves load
-// their particles and draw their proposals, and hands h L over in LDS.  In
+// in (fm.part) and B = 256, the launch has one wave more per block, threads
+// B..B+63: it loads the summed moments and factors V while the particle
+// waves load their particles and draw their proposals, and hands h L over in
+// LDS.  Smaller blocks, several to a compute unit, would then stack two
+// particle waves on some SIMDs while others hold only scaling waves, so
+// there the first particle wave does that work after its own draws.  In
 // a device-driven cycle (dm.cyc) the launch is M slot `iter` of its step: it
 // runs iteration r = r0 + iter of the cycle while r <= R, at the cycle's date
 // and key, with the record slots, step-size slots and rule of that iteration.
+template <int B>
+constexpr bool scale_wave() { return B >= 256; }
+
 template <class M, int B = 64, int U = kUnroll>
-__global__ void __launch_bounds__(B + 64) k_mutate_rw(DevModel dm, int64_t P, int64_t t,
+__global__ void __launch_bounds__(scale_wave<B>() ? B + 64 : B) k_mutate_rw(DevModel dm, int64_t P,
+                                                                            int64_t t,
                                                       double *theta,
                                                  double *logprior, double *loglik, void *state,
                                                  const double *__restrict__ hchol, uint64_t seed,
@@ -370,7 +378,8 @@ __global__ void __launch_bounds__(B + 64) k_mutate_rw(DevModel dm, int64_t P, in
     fm.mh_in = (r & 1) ? mh + 1 : mh;
     fm.mh_out = (r & 1) ? mh : mh + 1;
   }
-  if constexpr (kCanFuse) {
+  constexpr bool kScaleWave = scale_wave<B>();
+  if constexpr (kCanFuse && kScaleWave) {
     if (threadIdx.x >= B) {  // the scaling wave (launched with fm.part only)
       ScalePre<D> pre;
       fused_scale_issue<D, W>(fm, pre);
@@ -383,6 +392,11 @@ __global__ void __launch_bounds__(B + 64) k_mutate_rw(DevModel dm, int64_t P, in
   }
   const int64_t p = blockIdx.x * (int64_t)B + threadIdx.x;
   const int64_t pc = p < P ? p : P - 1;
+  // without a scaling wave, the first particle wave's scale loads go first,
+  // so that their latency overlaps its draws
+  ScalePre<D> pre;
+  if constexpr (kCanFuse && !kScaleWave)
+    if (fm.part && threadIdx.x < 64) fused_scale_issue<D, W>(fm, pre);
   double th[D], z[D];
 #pragma unroll
   for (int i = 0; i < D; ++i) th[i] = theta[i * P + pc];
@@ -392,7 +406,14 @@ __global__ void __launch_bounds__(B + 64) k_mutate_rw(DevModel dm, int64_t P, in
   if constexpr (kCanFuse) {
     if (fm.part) {
       fused = true;
-      __syncthreads();  // the scaling wave's h L
+      if constexpr (!kScaleWave) {
+        if (threadIdx.x < 64) {
+          double hs = 0.0;
+          const bool ok = fused_scale<D, W>(fm, P, Ms, Ls, &sh_h, hs, pre);
+          if (threadIdx.x == 0) sh_ok = ok;
+        }
+      }
+      __syncthreads();  // h L from the scaling wave (or the first particle wave)
       chol_ok = sh_ok != 0;
       h = sh_h;
     }
@@ -458,7 +479,7 @@ smc_status launch_rw_shape(const DevModel &m, int64_t P, int64_t t, double *thet
     fm = *fuse;
   }
   const typename M::Y *yd = Eval<M>::host_y(m);
-  const dim3 threads(fm.part ? B + 64 : B);  // the scaling wave of a folded scale
+  const dim3 threads(fm.part && scale_wave<B>() ? B + 64 : B);  // a folded scale's scaling wave
   if (timer)
     hipExtLaunchKernelGGL((k_mutate_rw<M, B, U>), grid_for(P, B), threads, 0, s, timer->start,
                           timer->stop, 0, m, P, t, theta, logprior, loglik, state, hchol, seed,
