@@ -41,6 +41,7 @@ METRIC = ("particle·obs log-lik evals/s; wall time to log-ML at NSE≤0.05 "
 # operations at 2.4 GHz.
 VALU_PEAK_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 N_SIMD = 256 * 4
+TIME_EVERY = 4  # timed runs put HIP events on every 4th Metropolis iteration
 
 # Algorithmic VALU lane-operations per particle-observation of the recursion
 # (FMA = 1; FP32 exp2/log2 = 4, quarter rate; FP64 exp/log1p = 17, the
@@ -286,7 +287,9 @@ def run_gpu(name, precision, steps, warmup):
     m = S.Model.from_workload(w, precision=prec)
     tune.apply(m, name, precision)
     pop = S.Population(m, w.J, w.N, max_chunk=1024)
-    rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64, time_mutate=True)
+    # HIP events on every 4th Metropolis iteration (all cycles are sampled
+    # alike); the untimed launches' entries are -1
+    rec = S.Record(m, w.J, Lmax=2048, RmaxRec=64, time_mutate=True, time_every=TIME_EVERY)
     force = 20 if name == "linreg" else 0
 
     def one(seed):
@@ -309,9 +312,11 @@ def run_gpu(name, precision, steps, warmup):
         L = s["L"]
         for l in range(L):
             Rl = int(s["R"][l])
-            mut_ms += float(rec.mutate_ms[l, :Rl].astype(np.float64).sum())
-            mut_evals += Rl * w.P * int(s["t_end"][l])
-            n_launch += Rl
+            ms_l = rec.mutate_ms[l, :Rl].astype(np.float64)
+            timed = ms_l >= 0
+            mut_ms += float(ms_l[timed].sum())
+            mut_evals += int(timed.sum()) * w.P * int(s["t_end"][l])
+            n_launch += int(timed.sum())
         log_mls.append(s["log_ml"])
         nses.append(s["nse"])
         cycles.append(L)

@@ -347,7 +347,8 @@ typedef struct {
 
 typedef struct {
   int32_t L;             /* out: cycles run */
-  int32_t reserved;
+  int32_t time_every;    /* with mutate_ms: time every k-th Metropolis iteration of
+                            the run, counted from the first (0 or 1: every one) */
   int64_t *t_end;        /* host [Lmax]: out (adaptive) / in (replay) */
   int32_t *R;            /* host [Lmax]: out / in */
   double *rss;           /* host [Lmax]: out, RSS at the end of each C phase */
@@ -357,11 +358,12 @@ typedef struct {
   double *log_ml;        /* device [3]: out, as smc_log_ml */
   int64_t evals;         /* out: particle x observation density evaluations */
   int64_t mh_steps;      /* out: Metropolis iterations */
-  float *mutate_ms;      /* host [Lmax][RmaxRec] or NULL: when given, each
-                            mutation launch carries HIP start and stop events
-                            on its own dispatch (a Langevin step, several
-                            kernels, is bracketed by two event records) and
-                            its duration in ms is stored here */
+  float *mutate_ms;      /* host [Lmax][RmaxRec] or NULL: when given, each timed
+                            mutation launch (time_every) carries HIP start and
+                            stop events on its own dispatch (a Langevin step,
+                            several kernels, is bracketed by two event records)
+                            and its duration in ms is stored here; the entries
+                            of untimed launches are -1 */
   double *moments;       /* device [Lmax][G][4] or NULL: smc_test_moments of
                             cfg->test_fn at the end of every cycle */
   double *log_score;     /* device [3] or NULL: smc_log_score over cfg->burn_in */

@@ -57,7 +57,7 @@ class RunConfig(C.Structure):
 
 
 class RunRecord(C.Structure):
-    _fields_ = [("L", C.c_int32), ("reserved", C.c_int32), ("t_end", _vp), ("R", _vp),
+    _fields_ = [("L", C.c_int32), ("time_every", C.c_int32), ("t_end", _vp), ("R", _vp),
                 ("rss", _vp), ("n_accept", _vp), ("hchol", _vp), ("group_logwbar", _vp),
                 ("log_ml", _vp), ("evals", C.c_int64), ("mh_steps", C.c_int64),
                 ("mutate_ms", _vp), ("moments", _vp), ("log_score", _vp), ("mean", _vp)]
@@ -381,9 +381,11 @@ def smc_flags(pop, stream=None):
 class Record:
     """Host and device arrays of a run's design and outputs."""
 
-    def __init__(self, model, J, Lmax=512, RmaxRec=128, time_mutate=False, test_fn=None):
+    def __init__(self, model, J, Lmax=512, RmaxRec=128, time_mutate=False, test_fn=None,
+                 time_every=1):
         """``test_fn`` (SMC_TEST_*) also keeps the moment report of every cycle
-        and the log score."""
+        and the log score; with ``time_mutate`` every ``time_every``-th
+        Metropolis iteration is timed (the others' entries are -1)."""
         import numpy as np
         d, dev = model.d, model.device
         self.Lmax, self.RmaxRec, self.J, self.d = Lmax, RmaxRec, J, d
@@ -402,7 +404,8 @@ class Record:
         self.log_score = (torch.full((3,), float("nan"), dtype=torch.float64, device=dev)
                           if self.G else None)
         self.mean = torch.zeros((Lmax, RmaxRec, d), dtype=torch.float64, device=dev)
-        self.c = RunRecord(0, 0, self.t_end.ctypes.data, self.R.ctypes.data, self.rss.ctypes.data,
+        self.c = RunRecord(0, time_every, self.t_end.ctypes.data, self.R.ctypes.data,
+                           self.rss.ctypes.data,
                            _ptr(self.n_accept), _ptr(self.hchol), _ptr(self.group_logwbar),
                            _ptr(self.log_ml), 0, 0,
                            self.mutate_ms.ctypes.data if time_mutate else None,

@@ -843,8 +843,8 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   if ((st = smc_init_from_prior(m, pop, cfg->rng, stream))) return st;
   int64_t t = 0, evals = 0, steps = 0, last_len = 0;
   int32_t l = 0;
-  // Optional per-launch timing of the mutation kernel: pairs of pooled
-  // events, resolved after the run.  The random-walk and independent kernels
+  // Optional per-launch timing of the mutation kernel (every time_every-th
+  // iteration): pairs of pooled events, resolved after the run.  The random-walk and independent kernels
   // carry the events on their own dispatch; the Langevin step (several
   // kernels) is bracketed by two event records.
   struct Timed {
@@ -852,6 +852,8 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
     int64_t slot = 0;
   };
   std::vector<Timed> timed;
+  if (rec->mutate_ms)
+    std::fill(rec->mutate_ms, rec->mutate_ms + (int64_t)cfg->Lmax * cfg->RmaxRec, -1.f);
   while (t < T) {
     if (l >= cfg->Lmax) return set_error(SMC_E_INVALID_ARG, "record holds only %d cycles", cfg->Lmax);
     int64_t t_stop = T;
@@ -936,7 +938,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
       }
       Timed *ev = nullptr;
       const bool bracket = cfg->kernel == SMC_KERNEL_MALA;
-      if (rec->mutate_ms) {
+      if (rec->mutate_ms && steps % std::max(1, rec->time_every) == 0) {
         timed.emplace_back();
         ev = &timed.back();
         ev->slot = (int64_t)l * cfg->RmaxRec + (r - 1);

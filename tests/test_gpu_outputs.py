@@ -123,28 +123,37 @@ def test_hybrid_matches_oracle_hybrid(name, T, J, N):
                                                             b["log_score_nse"]), rel=1e-15)
 
 
+@pytest.mark.parametrize("every", [1, 3])
 @pytest.mark.parametrize("kernel", [S.SMC_KERNEL_RW, S.SMC_KERNEL_INDEPENDENT, S.SMC_KERNEL_MALA])
-def test_mutation_timing_leaves_the_run_unchanged(kernel):
-    """Timing every mutation launch (events carried on the kernel's own
-    dispatch, or around the Langevin step's kernels) changes nothing the run
-    computes, and yields one positive duration per M step."""
+def test_mutation_timing_leaves_the_run_unchanged(kernel, every):
+    """Timing mutation launches (events carried on the kernel's own dispatch,
+    or around the Langevin step's kernels; every one, or every 3rd M step of
+    the run) changes nothing the run computes, and yields one positive
+    duration per timed M step and -1 for every other entry."""
     w = SD.workload("egarch11", T=300)
     gm = gpu_model(w)
     J, N = 4, 256
     out = []
     for timed in (False, True):
         g = S.Population(gm, J, N, max_chunk=64, with_grad=kernel == S.SMC_KERNEL_MALA)
-        rec = S.Record(gm, J, Lmax=200, RmaxRec=32, time_mutate=timed)
+        rec = S.Record(gm, J, Lmax=200, RmaxRec=32, time_mutate=timed, time_every=every)
         S.smc_run(gm, g, seed=11, kernel=kernel, record=rec)
         out.append((rec, rec.summary(), g.theta.cpu().numpy()))
     (_, a, th_a), (rec, b, th_b) = out
     assert np.array_equal(a["t_end"], b["t_end"]) and np.array_equal(a["R"], b["R"])
     assert a["log_ml"] == b["log_ml"] and a["nse"] == b["nse"]
     assert np.array_equal(th_a, th_b)
+    step = 0  # the run's M steps in order
     for l in range(b["L"]):
-        ms = rec.mutate_ms[l, :b["R"][l]]
-        assert np.all(ms > 0) and np.all(ms < 1e3), ms
-        assert np.all(rec.mutate_ms[l, b["R"][l]:] == 0)
+        for r in range(b["R"][l]):
+            ms = rec.mutate_ms[l, r]
+            if step % every == 0:
+                assert 0 < ms < 1e3, (l, r, ms)
+            else:
+                assert ms == -1, (l, r, ms)
+            step += 1
+        assert np.all(rec.mutate_ms[l, b["R"][l]:] == -1)
+    assert np.all(rec.mutate_ms[b["L"]:] == -1)
 
 
 def test_run_stops_on_numerical_flags():
