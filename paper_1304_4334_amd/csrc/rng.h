@@ -15,6 +15,20 @@ struct U64x4 {
   uint64_t x0, x1, x2, x3;
 };
 
+// The 128-bit product a b as (hi, lo) from four 32 x 32 -> 64-bit
+// multiply-adds: with a = a1 2^32 + a0 and b likewise, t = a0 b1 + hi(a0 b0)
+// and u = a1 b0 + lo(t) cannot overflow, lo = lo(u) 2^32 + lo(a0 b0) and
+// hi = a1 b1 + hi(t) + hi(u).
+__device__ __forceinline__ void mul_wide(uint64_t a, uint64_t b, uint64_t &hi, uint64_t &lo) {
+  const uint32_t a0 = (uint32_t)a, a1 = (uint32_t)(a >> 32);
+  const uint32_t b0 = (uint32_t)b, b1 = (uint32_t)(b >> 32);
+  const uint64_t p00 = (uint64_t)a0 * b0;
+  const uint64_t t = (uint64_t)a0 * b1 + (p00 >> 32);
+  const uint64_t u = (uint64_t)a1 * b0 + (uint32_t)t;
+  hi = (uint64_t)a1 * b1 + (t >> 32) + (u >> 32);
+  lo = (u << 32) | (uint32_t)p00;
+}
+
 __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1) {
   constexpr uint64_t kM0 = 0xD2E7470EE14C6C93ull, kM1 = 0xCA5A826395121157ull;
   constexpr uint64_t kW0 = 0x9E3779B97F4A7C15ull, kW1 = 0xBB67AE8584CAA73Bull;
@@ -24,8 +38,9 @@ __device__ __forceinline__ U64x4 philox4x64_10(U64x4 c, uint64_t k0, uint64_t k1
       k0 += kW0;
       k1 += kW1;
     }
-    const uint64_t lo0 = kM0 * c.x0, hi0 = __umul64hi(kM0, c.x0);
-    const uint64_t lo1 = kM1 * c.x2, hi1 = __umul64hi(kM1, c.x2);
+    uint64_t hi0, lo0, hi1, lo1;
+    mul_wide(kM0, c.x0, hi0, lo0);
+    mul_wide(kM1, c.x2, hi1, lo1);
     c = U64x4{hi1 ^ c.x1 ^ k0, lo1, hi0 ^ c.x3 ^ k1, lo0};
   }
   return c;
