@@ -126,9 +126,10 @@ typedef struct {
 smc_status smc_model_create(const smc_model_desc *desc, smc_model **out);
 smc_status smc_model_destroy(smc_model *m);
 /* Launch shape of the model's random-walk step (smc_mutate, smc_run) and of
- * its runs' share of a batch: threads (particles) per block, 64, 128 or 256,
- * and observations per load batch of the likelihood loop, 4, 8 or 16 (0 =
- * the defaults 64 and 8).  A shape changes only the speed: every shape gives
+ * its runs' share of a batch: particles per block, 64, 128 or 256 (one
+ * thread each; smc_run's 256-particle step blocks have one more wave, which
+ * forms the proposal scale), and observations per load batch of the
+ * likelihood loop, 4, 8 or 16 (0 = the defaults 64 and 8).  A shape changes only the speed: every shape gives
  * the same results to the bit.  Shapes other than the default exist for
  * EGARCH(1) with Gaussian shocks and EGARCH(2) with Student-t shocks
  * (SMC_E_UNSUPPORTED otherwise).  The handle is changed: call it before the

@@ -41,7 +41,7 @@ struct DevModel {
   int32_t d;
   int32_t S;
   int32_t ncomp;  // normal-mixture components I (mixture shocks), else 0
-  int32_t block;  // launch shape of the random-walk step: threads per block (0: 64)
+  int32_t block;  // launch shape of the random-walk step: particles per block (0: 64)
   int32_t unroll; // and observations per load batch (0: 8); smc_model_set_launch
   int64_t T;
   const double *y;
