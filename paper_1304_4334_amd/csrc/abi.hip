@@ -824,7 +824,7 @@ smc_status smc_run(const smc_model *m, smc_particles *pop, const smc_run_config 
   if ((st = fill_i32(dflags, 1, 0, s))) return st;
   if ((st = fill_i64(rec->n_accept, (int64_t)cfg->Lmax * cfg->RmaxRec, 0, s))) return st;
   // Each Metropolis step leaves its accept counts in the workspace's sink;
-  // the next iteration's moment sums add them to the record (those of a
+  // the next iteration's moment partials add them to the record (those of a
   // phase's last step the next phase's first moments, and after the run's
   // last step a launch of its own).
   DevModel dm = m->dev;
@@ -1139,7 +1139,7 @@ smc_status run_device_driven(const smc_model *m, smc_particles *pop, const smc_r
         ma.flags = dflags;
         ma.cyc = cyc;
         ma.slot = k;
-        ma.acc = dm.acc;  // the moment sums add the previous slot's accept counts
+        ma.acc = dm.acc;  // the moment partials add the previous slot's accept counts
         MomFuse fm{};
         int64_t nb = 0;
         if ((e = launch_moment_partials(ma, &fm.part, nb, cs))) return e;

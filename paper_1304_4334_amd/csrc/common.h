@@ -23,8 +23,8 @@ struct CycleDyn;
 // 10 us for 1,024 waves): each wave of a Metropolis step that holds particles
 // stores its count at its own index, and block 0 stores the address of the
 // counter the counts belong to in *pending.  A later kernel on the stream
-// (acc_flush: the next iteration's moment sums, a device-driven step's end,
-// or a launch of its own) adds them to that counter and clears
+// (acc_flush: the next iteration's moment partials, a device-driven step's
+// end, or a launch of its own) adds them to that counter and clears
 // *pending.  part == NULL: the step adds to its counter atomically.
 struct AccSink {
   int32_t *part;                // [ceil(P / 64)] per-wave counts

@@ -877,12 +877,19 @@ __global__ void __launch_bounds__(kSBlock) k_resample(const double *logw, int32_
 // lane l holds element (4r + l/16, l%16) of the 16x16 result.  With W = 32
 // each lane holds rows i and 16 + i, and three products per step give the
 // (0,0), (1,0) and (1,1) tiles of the symmetric result.  Each block writes
-// one W x W partial matrix.
+// one W x W partial matrix.  With sink.pending, one block more, the last,
+// adds the previous Metropolis step's accept counts to their counter
+// (acc_flush) while the others form the partials.
 template <int W>
 __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_t P, int32_t d,
                                                      int64_t chunk, double *part,
-                                                     const CycleDyn *cyc, int32_t slot) {
+                                                     const CycleDyn *cyc, int32_t slot,
+                                                     AccSink sink) {
   if (m_slot_off(cyc, slot)) return;  // an unused M slot of a device-driven cycle
+  if (sink.pending && blockIdx.x == gridDim.x - 1) {
+    if (threadIdx.x < 64) acc_flush(sink, P);
+    return;
+  }
   constexpr int NT = W / 16;
   constexpr int NA = NT == 1 ? 1 : 3;  // tiles accumulated
   __shared__ double red[4][W * W];
@@ -962,17 +969,10 @@ __global__ void __launch_bounds__(256) k_mom_partial(const double *theta, int64_
 // so the final step reads one matrix.  A block takes 64
 // entries; each of its four waves adds a quarter of the partials in block
 // order (its loads in flight together), and the four subtotals are added in
-// wave order.  With sink.pending, one block more, the last, adds the
-// previous Metropolis step's accept counts of the P particles to their
-// counter (acc_flush) while the others add the partials.
+// wave order.
 __global__ void __launch_bounds__(256) k_mom_sum(const double *part, int32_t nb, int32_t n,
-                                                 double *out, const CycleDyn *cyc, int32_t slot,
-                                                 AccSink sink, int64_t P) {
+                                                 double *out, const CycleDyn *cyc, int32_t slot) {
   if (m_slot_off(cyc, slot)) return;
-  if (sink.pending && blockIdx.x == gridDim.x - 1) {
-    if (threadIdx.x < 64) acc_flush(sink, P);
-    return;
-  }
   __shared__ double sub[4][64];
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int e = blockIdx.x * 64 + lane;
@@ -1443,18 +1443,18 @@ smc_status launch_moments(const MomArgs &a, hipStream_t s) {
   const int64_t xb = a.acc.pending ? 1 : 0;  // the accept-count flush
   const int n = a.d + 1 <= 16 ? 256 : 1024;  // entries of a partial matrix
   if (n == 256) {
-    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   } else {
-    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   }
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
   // sums into the slot after the partials, then the final block reads them
   double *sums = a.part + nb * n;
-  hipLaunchKernelGGL(k_mom_sum, dim3((unsigned)(n / 64 + xb)), dim3(256), 0, s, a.part,
-                     (int32_t)nb, n, sums, a.cyc, a.slot, a.acc, a.P);
+  hipLaunchKernelGGL(k_mom_sum, dim3(n / 64), dim3(256), 0, s, a.part, (int32_t)nb, n, sums,
+                     a.cyc, a.slot);
   if ((st = launch_status("particle_moments/sum"))) return st;
   MomArgs f = a;
   f.part = sums;
@@ -1475,17 +1475,17 @@ smc_status launch_moment_partials(const MomArgs &a, const double **part, int64_t
   const int64_t xb = a.acc.pending ? 1 : 0;  // the accept-count flush
   const int n = a.d + 1 <= 16 ? 256 : 1024;
   if (n == 256)
-    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<16>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   else
-    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)nb), dim3(kBlock), 0, s, a.theta, a.P,
-                       a.d, chunk, a.part, a.cyc, a.slot);
+    hipLaunchKernelGGL(k_mom_partial<32>, dim3((unsigned)(nb + xb)), dim3(kBlock), 0, s, a.theta,
+                       a.P, a.d, chunk, a.part, a.cyc, a.slot, a.acc);
   smc_status st = launch_status("particle_moments/partial");
   if (st) return st;
   // summed into the slot after the partials, as launch_moments does
   double *sums = a.part + nb * n;
-  hipLaunchKernelGGL(k_mom_sum, dim3((unsigned)(n / 64 + xb)), dim3(256), 0, s, a.part,
-                     (int32_t)nb, n, sums, a.cyc, a.slot, a.acc, a.P);
+  hipLaunchKernelGGL(k_mom_sum, dim3(n / 64), dim3(256), 0, s, a.part, (int32_t)nb, n, sums,
+                     a.cyc, a.slot);
   *part = sums;
   nb = 1;
   return launch_status("particle_moments/sum");

@@ -164,8 +164,8 @@ struct MomArgs {
   double *mean_out, *cov_out, *hchol;
   int32_t *flags;
   const CycleDyn *cyc;      // device-driven cycle, else NULL
-  AccSink acc;              // with acc.pending: the partials' sum launch also adds
-                            // the previous step's pending accept counts (acc_flush)
+  AccSink acc;              // with acc.pending: the partials' launch also adds the
+                            // previous step's pending accept counts (acc_flush)
 };
 smc_status launch_moments(const MomArgs &a, hipStream_t s);
 // Only the partial sums of launch_moments, for a step that folds the rest in
