@@ -923,23 +923,61 @@ enum { ORC_TEST_PARAMS = 0, ORC_TEST_MODEL = 1 };
 /* Number of test functions: the parameters (d), or the model's functions of
  * interest.  For EGARCH those are Section 5.2's g1 (log volatility), g2 (the
  * shock's third moment, mixtures only: it is zero for the symmetric shocks)
- * and g3 (the 3% loss probability; not for Student-t shocks, whose
- * distribution function is not provided).  The regression uses its
- * parameters. */
+ * and g3 (the 3% loss probability).  The regression uses its parameters. */
 int orc_num_test_fns(const orc_model *m, int which) {
   if (which == ORC_TEST_PARAMS || m->kind == ORC_LINREG) return orc_dim(m);
-  if (m->shock == ORC_MIXTURE) return 3;
-  if (m->shock == ORC_GAUSS) return 2;
-  return 1;
+  return m->shock == ORC_MIXTURE ? 3 : 2;
 }
 
 static double std_normal_cdf(double x) { return 0.5 * erfc(-x / sqrt(2.0)); }
+
+/* Regularised incomplete beta function I_x(a, b), 0 <= x <= 1: the
+ * continued fraction of DLMF 8.17.22,
+ *   I_x(a, b) = x^a (1 - x)^b / (a B(a, b)) / (1 + d1 / (1 + d2 / (1 + ...))),
+ *   d_{2m+1} = -(a + m)(a + b + m) x / ((a + 2m)(a + 2m + 1)),
+ *   d_{2m}   = m (b - m) x / ((a + 2m - 1)(a + 2m)),
+ * summed by the modified Lentz method where it converges quickly
+ * (x < (a + 1) / (a + b + 2)), else through I_x(a, b) = 1 - I_{1-x}(b, a).
+ * lx and l1x are log x and log(1 - x), passed separately so that neither
+ * loses digits to cancellation. */
+static double inc_beta(double a, double b, double x, double lx, double l1x) {
+  if (x > (a + 1.0) / (a + b + 2.0)) return 1.0 - inc_beta(b, a, 1.0 - x, l1x, lx);
+  const double tiny = 1e-300;
+  double f = 1.0, C = 1.0, D = 0.0;
+  for (int j = 1; j <= 100000; ++j) {
+    int m = j / 2;
+    double dj = (j & 1) ? -(a + m) * (a + b + m) * x / ((a + 2 * m) * (a + 2 * m + 1))
+                        : m * (b - m) * x / ((a + 2 * m - 1) * (a + 2 * m));
+    D = 1.0 + dj * D;
+    if (fabs(D) < tiny) D = tiny;
+    C = 1.0 + dj / C;
+    if (fabs(C) < tiny) C = tiny;
+    D = 1.0 / D;
+    f *= C * D;
+    if (fabs(C * D - 1.0) < 1e-16) break;
+  }
+  double lpre = a * lx + b * l1x + lgamma(a + b) - lgamma(a) - lgamma(b);
+  return exp(lpre) / (a * f);
+}
+
+/* Distribution function of the unit-variance Student-t shock (the density
+ * of step 4 of the likelihood) at x, nu2 = nu - 2: eps = z sqrt(nu2 / nu)
+ * with z ~ t_nu, and P(t_nu < z) = I_w(nu/2, 1/2) / 2 for z < 0 with
+ * w = nu / (nu + z^2) (DLMF 8.17.22's relation for the t distribution), which
+ * in terms of x is w = nu2 / (nu2 + x^2); symmetry gives z >= 0. */
+static double student_t_unit_cdf(double x, double nu2) {
+  double r = nu2 + x * x;
+  double tail = 0.5 * inc_beta(0.5 * (nu2 + 2.0), 0.5, nu2 / r, log(nu2) - log(r),
+                               2.0 * log(fabs(x)) - log(r));
+  return x < 0.0 ? tail : 1.0 - tail;
+}
 
 /* The test functions at parameter theta and state (v_1..v_K, eps_t) at date t:
  *   g1 = log sigma_Y + sum_k v_kt / 2 = log h_t;
  *   g2 = E(eps^3) = sum_i p_i (mu_i^3 + 3 mu_i sigma_i^2);
  *   g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) = F((-0.03 - mu_Y) / h_{t+1}),
- * F the shock distribution (Phi, or sum_i p_i Phi((x - mu_i) / sigma_i)),
+ * F the shock distribution (Phi, the unit-variance t, or
+ * sum_i p_i Phi((x - mu_i) / sigma_i)),
  * h_{t+1} from eq EGARCH_mod1 one step ahead (no innovation when t = 0). */
 void orc_test_fns(const orc_model *m, int which, const double *th, const double *state, int64_t t,
                   double *g) {
@@ -964,11 +1002,12 @@ void orc_test_fns(const orc_model *m, int which, const double *th, const double 
     for (int i = 0; i < m->I; ++i) m3 += pw[i] * (mc[i] * mc[i] * mc[i] + 3.0 * mc[i] * sg[i] * sg[i]);
     g[q++] = m3;
   }
-  if (m->shock == ORC_STUDENT_T) return;
   double h1 = exp(th[1]) * exp(vn / 2.0);
   double x = (-0.03 - th[0] / 1000.0) / h1;
   if (m->shock == ORC_GAUSS) {
     g[q++] = std_normal_cdf(x);
+  } else if (m->shock == ORC_STUDENT_T) {
+    g[q++] = student_t_unit_cdf(x, exp(th[2 + 3 * K]));
   } else {
     double F = 0.0;
     for (int i = 0; i < m->I; ++i) F += pw[i] * std_normal_cdf((x - mc[i]) / sg[i]);

@@ -11,6 +11,7 @@ import math
 import numpy as np
 import pytest
 from scipy import stats
+from scipy.integrate import simpson
 
 import oracle as O
 import synthdata as SD
@@ -365,11 +366,12 @@ def test_log_volatility_is_the_simulated_path(name):
         assert g[0] == pytest.approx(math.log(h[t - 1]), rel=1e-10)
 
 
-@pytest.mark.parametrize("name", ["egarch11", "egarch23"])
+@pytest.mark.parametrize("name", ["egarch11", "egarch23", "egarch2t"])
 def test_loss_probability_and_skewness_by_quadrature(name):
     """g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) from the conditional density
     of the next observation (the oracle's likelihood as a function of
-    y_{t+1}, integrated); g2 = its standardised third moment."""
+    y_{t+1}, integrated), for Gaussian, mixture and Student-t shocks; g2 = its
+    standardised third moment."""
     T = 41
     w = SD.workload(name, T=T)
     m = O.Model.from_workload(w)
@@ -387,7 +389,9 @@ def test_loss_probability_and_skewness_by_quadrature(name):
         y2[T - 1] = yv
         mm = O.Model(O.EGARCH, T, y2, K=w.K, shock=w.shock, I=w.I)
         dens.append(math.exp(O.loglik(mm, x)[0] - ll_prev))
-    assert g[-1] == pytest.approx(np.trapezoid(dens, grid), rel=5e-6, abs=1e-9)
+    # Simpson's rule on the grid; the mass below mu_Y - 1 (50 scales) is
+    # under 1e-10 of g3 even for the t shocks' heavier tail
+    assert g[-1] == pytest.approx(simpson(dens, x=grid), rel=1e-8, abs=1e-12)
     assert 0.001 < g[-1] < 0.999
     if name == "egarch23":
         p, mu, sg = O.mixture_params(m, x)
@@ -395,6 +399,34 @@ def test_loss_probability_and_skewness_by_quadrature(name):
         z = np.linspace(-15, 15, 60001)
         f = sum(p[i] * stats.norm.pdf(z, mu[i], sg[i]) for i in range(len(p)))
         assert g[1] == pytest.approx(np.trapezoid(z ** 3 * f, z), rel=1e-6, abs=1e-9)
+
+
+def test_student_t_loss_probability_matches_scipy():
+    """g3 for Student-t shocks is the t_nu distribution function at the
+    standardised point x sqrt(nu / (nu - 2)) (the shock has unit variance):
+    checked against scipy over the tails, the centre and nu from near 2 to
+    far beyond the prior's range.  With t = 0 and sigma_Y = 1, g3's argument
+    x is set through mu_Y alone.  Dropping the standardisation, or taking the
+    wrong side of the incomplete-beta symmetry, fails it.  Above nu = 1000 the
+    log-gamma difference in 1/B(nu/2, 1/2) cancels to about a(log a)
+    ulp-relative, a = nu/2, which sets the looser bar there."""
+    w = SD.workload("egarch2t", T=50)
+    m = O.Model.from_workload(w)
+    assert O.num_test_fns(m) == 2
+    th = w.theta_true.copy()
+    th[1] = 0.0
+    st = np.zeros(m.S)
+    for nu in (2.05, 2.5, 3.0, 4.0, 7.3, 12.0, 30.0, 200.0, 1000.0, 1e4, 1e7):
+        th[2 + 3 * w.K] = math.log(nu - 2.0)
+        for x in (-80.0, -6.0, -1.5, -0.2, 0.0, 1e-3, 0.7, 3.0, 50.0):
+            th[0] = -1000.0 * (x + 0.03)
+            g = O.test_fns(m, th, st, 0)
+            want = stats.t.cdf(x * math.sqrt(nu / (nu - 2.0)), nu)
+            rel = 1e-11 if nu <= 1000.0 else 1e-7
+            # relative in the lower tail, absolute near 1
+            assert g[1] == pytest.approx(want, rel=rel, abs=1e-15 if x < 0 else rel), (nu, x)
+    th[0] = -1000.0 * 0.03
+    assert O.test_fns(m, th, st, 0)[1] == 0.5
 
 
 def test_log_score_matches_closed_form():
