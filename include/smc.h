@@ -266,9 +266,10 @@ smc_status smc_log_score(int32_t L, int32_t J, const double *group_logwbar, cons
 /* Number of test functions: d for SMC_TEST_PARAMS; for SMC_TEST_MODEL, EGARCH
  * has Section 5.2's g1 = log sigma_Y + sum_k v_kt / 2 (log volatility at the
  * current date), g2 = E(eps^3) (mixture shocks only; zero for symmetric
- * shocks) and g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) (not for Student-t
- * shocks), in that order; the regression uses its parameters.  -1 for a NULL
- * model or a bad `which`. */
+ * shocks) and g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) (with the shock's
+ * distribution function: normal, unit-variance Student-t or the mixture), in
+ * that order; the regression uses its parameters.  -1 for a NULL model or a
+ * bad `which`. */
 int32_t smc_num_test_functions(const smc_model *m, int32_t which);
 
 /* Posterior moments of the test functions over the (equally weighted)

@@ -169,6 +169,44 @@ __device__ __forceinline__ double t_log_const(double nu) {
   return fma(s, iy, 0.5 * log(y * r * r / (M_PI * (nu - 2.0))));
 }
 
+// Distribution function of the unit-variance Student-t shock at x, with
+// nu2 = nu - 2.  The shock is z sqrt(nu2 / nu) with z ~ t_nu, and
+// P(t_nu < z) = I_w(nu/2, 1/2) / 2 for z < 0 with w = nu / (nu + z^2)
+// (DLMF 8.17.22's relation); in terms of x, w = nu2 / (nu2 + x^2), and
+// symmetry gives x >= 0.  The regularised incomplete beta function is the
+// continued fraction of DLMF 8.17.22 summed by the modified Lentz method, at
+// (nu/2, 1/2, w) or, where that converges slowly (w > (a + 1) / (a + b + 2)),
+// at (1/2, nu/2, 1 - w) through I_w(a, b) = 1 - I_{1-w}(b, a).  Both share
+// the prefactor w^(nu/2) (1 - w)^(1/2) / B(nu/2, 1/2), whose log-beta is the
+// t density's constant plus log(nu2)/2.  log w and log(1 - w) are formed
+// from nu2, x^2 and their sum, so neither cancels.  At most 4,096 terms: a
+// few hundred suffice for any nu the prior reaches.
+__device__ inline double t_unit_cdf(double x, double nu2) {
+  const double r = nu2 + x * x, lr = log(r);
+  const double lw = log(nu2) - lr, l1w = 2.0 * log(fabs(x)) - lr;
+  const double ha = 0.5 * (nu2 + 2.0);
+  const bool swap = nu2 * (ha + 2.5) > (ha + 1.0) * r;
+  const double a = swap ? 0.5 : ha, b = swap ? ha : 0.5;
+  const double xw = swap ? x * x / r : nu2 / r;
+  double f = 1.0, c = 1.0, dd = 0.0;
+  for (int j = 1; j <= 4096; ++j) {
+    const double m = (double)(j >> 1), a2m = a + 2.0 * m;
+    const double dj = (j & 1) ? -(a + m) * (a + b + m) * xw / (a2m * (a2m + 1.0))
+                              : m * (b - m) * xw / ((a2m - 1.0) * a2m);
+    dd = fma(dj, dd, 1.0);
+    if (fabs(dd) < 1e-300) dd = 1e-300;
+    c = 1.0 + dj / c;
+    if (fabs(c) < 1e-300) c = 1e-300;
+    dd = 1.0 / dd;
+    f *= c * dd;
+    if (fabs(c * dd - 1.0) < 1e-16) break;
+  }
+  const double lib = t_log_const(nu2 + 2.0) + 0.5 * log(nu2);
+  const double I = exp(fma(ha, lw, 0.5 * l1w) + lib) / (a * f);
+  const double tail = 0.5 * (swap ? 1.0 - I : I);
+  return x < 0.0 ? tail : 1.0 - tail;
+}
+
 // ---------------------------------------------------------------- EGARCH --
 // theta = (th1, th2, th3_1..K, th4_1..K, th5_1..K, then th9 = log(nu - 2) for
 // Student-t shocks or th6_1..I, th7_1..I, th8_1..I for normal-mixture shocks),
@@ -271,10 +309,10 @@ struct Egarch {
   // Functions of interest of Section 5.2 at date t, from theta and the state
   // (v_1..v_K, eps_t): g1 = log sigma_Y + sum_k v_kt / 2 (log volatility);
   // for mixtures g2 = E(eps^3) = sum_i p_i (mu_i^3 + 3 mu_i sigma_i^2); and
-  // (not for Student-t shocks) g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) =
-  // F((-0.03 - mu_Y) / h_{t+1}) with h_{t+1} one step of eq EGARCH_mod1 ahead
-  // (no innovation when t = 0) and F the shock's distribution function.
-  static constexpr int kTests = kMix ? 3 : (kT ? 1 : 2);
+  // g3 = P(Y_{t+1} < -0.03 | theta, y_{1:t}) = F((-0.03 - mu_Y) / h_{t+1})
+  // with h_{t+1} one step of eq EGARCH_mod1 ahead (no innovation when t = 0)
+  // and F the shock's distribution function.
+  static constexpr int kTests = kMix ? 3 : 2;
   __device__ static void test_fns(const double *th, const R (&st)[S], int64_t t, double *g) {
     double vs = 0.0, vn = 0.0;
     const double e = (double)st[K];
@@ -288,7 +326,6 @@ struct Egarch {
     }
     int q = 0;
     g[q++] = th[1] + 0.5 * vs;
-    if constexpr (kT) return;
     const double x = (-0.03 - th[0] * 1e-3) / (exp(th[1]) * exp(0.5 * vn));
     if constexpr (kMix) {
       double pw[I], mu[I], sg[I];
@@ -301,6 +338,8 @@ struct Egarch {
       }
       g[q++] = m3;
       g[q++] = F;
+    } else if constexpr (kT) {
+      g[q++] = t_unit_cdf(x, exp(th[2 + 3 * K]));
     } else {
       g[q++] = 0.5 * erfc(-x / M_SQRT2);
     }

@@ -80,7 +80,7 @@ def test_model_dims_and_workspace():
 
 def test_number_of_test_functions():
     L = S._lib.lib()
-    for kw, want in [(dict(), 2), (dict(K=2, shock=1), 1), (dict(K=2, shock=2, ncomp=3), 3),
+    for kw, want in [(dict(), 2), (dict(K=2, shock=1), 2), (dict(K=2, shock=2, ncomp=3), 3),
                      (dict(kind=1, nreg=3, X=C.c_void_p(0x1000)), 4)]:
         h = C.c_void_p()
         assert L.smc_model_create(C.byref(_desc(**kw)), C.byref(h)) == 0

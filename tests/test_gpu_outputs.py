@@ -1,10 +1,11 @@
 """GPU parity of the simulator's reported outputs against the oracle: the
 functions of interest and their posterior moments with NSE and RNE
-(Sections 2.3, 5.2), the RNE stopping rule with E2 at dates of interest
-(Section 3.3) and the log score over a burn-in (Section 4.2).
+(Sections 2.3, 5.2; the loss probability for every shock), the RNE stopping
+rule with E2 at dates of interest (Section 3.3) and the log score over a
+burn-in (Section 4.2).
 
 Tolerances: moments 1e-9 relative (FP64 everywhere; the loss probability
-goes through erfc on both sides); adaptive decisions (cycle ends and M-phase
+goes through erfc, or the t's continued fraction, on both sides); adaptive decisions (cycle ends and M-phase
 lengths) exact; log scores 1e-10 relative on a replayed design and within
 3.5 NSE of the regression's closed form.
 """
@@ -38,6 +39,33 @@ def test_test_moments_match_oracle(name, which):
     got = S.smc_test_moments(gm, g, t, which).cpu().numpy()
     assert got.shape == want.shape == (S.smc_num_test_functions(gm, which), 4)
     assert np.allclose(got, want, rtol=1e-9, atol=1e-14), (got, want)
+
+
+@pytest.mark.parametrize("nu", [2.05, 3.0, 12.0, 200.0, 1e4])
+def test_student_t_loss_probability_matches_oracle(nu):
+    """g3 with Student-t shocks against the oracle's, case by case: each
+    (nu, x) is a population of identical particles at t = 0 with sigma_Y = 1,
+    so g3's argument is x and the population mean is the particle's value.
+    Both tails, the centre and x = 0, nu from near 2 to far beyond the
+    prior's reach.  Both sides sum the same continued fraction to full
+    precision, each with its own log-gamma: 1e-12 relative, and 1e-10 at
+    nu = 1e4, where the oracle's difference of log-gamma values near 4e4
+    cancels to about 1e-11."""
+    w = SD.workload("egarch2t", T=50)
+    gm, om = gpu_model(w), ora_model(w)
+    th = w.theta_true.copy()
+    th[1] = 0.0
+    th[2 + 3 * w.K] = np.log(nu - 2.0)
+    rel = 1e-12 if nu < 1000 else 1e-10
+    for x in (-80.0, -6.0, -1.5, -0.2, 0.0, 1e-3, 0.7, 3.0, 50.0):
+        th[0] = -1000.0 * (x + 0.03)
+        opop = O.Pop(om, 2, 64)
+        opop.theta[:] = th
+        want = O.test_fns(om, th, np.zeros(om.S), 0)
+        got = S.smc_test_moments(gm, pop_to_gpu(gm, opop), 0, S.SMC_TEST_MODEL).cpu().numpy()
+        assert got[0, 0] == want[0], x
+        assert got[1, 0] == pytest.approx(want[1], rel=rel, abs=1e-300), (x, got[1, 0], want[1])
+        assert got[1, 1] <= 1e-12 * max(want[1], 1e-300), x  # identical particles
 
 
 def test_rne_rule_with_e2_matches_oracle_run():
