@@ -122,6 +122,7 @@ TRAFFIC_SOURCES = ["paper_1304_4334_amd/csrc/model_kernels.h", "paper_1304_4334_
                    "paper_1304_4334_amd/csrc/ops_mixture32.hip",
                    "paper_1304_4334_amd/csrc/ops_shapes32.hip",
                    "paper_1304_4334_amd/csrc/ops_shapes64.hip",
+                   "paper_1304_4334_amd/csrc/ops_shapes_mix32.hip",
                    "paper_1304_4334_amd/csrc/chol.h", "paper_1304_4334_amd/csrc/launch.h"]
 
 

@@ -10,8 +10,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libsmc.so")
 SOURCES = ["kernels.hip", "ops_linreg.hip", "ops_egarch.hip", "ops_mixture64.hip",
-           "ops_mixture32.hip", "ops_shapes32.hip", "ops_shapes64.hip", "batch.hip", "abi.hip",
-           "noalloc.hip"]
+           "ops_mixture32.hip", "ops_shapes32.hip", "ops_shapes64.hip", "ops_shapes_mix32.hip",
+           "ops_shapes_mix64.hip", "batch.hip", "abi.hip", "noalloc.hip"]
 
 HIPCC = "/opt/rocm/bin/hipcc"
 HIPCC_FLAGS = [

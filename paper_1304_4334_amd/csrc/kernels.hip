@@ -1220,8 +1220,9 @@ smc_status launch_ccommit(const DevModel &m, int64_t P, const double *theta, voi
 }
 
 bool has_launch_shapes(const DevModel &m) {
-  return m.kind == SMC_MODEL_EGARCH && ((m.K == 1 && m.shock == SMC_SHOCK_GAUSS) ||
-                                        (m.K == 2 && m.shock == SMC_SHOCK_STUDENT_T));
+  return m.kind == SMC_MODEL_EGARCH &&
+         ((m.K == 1 && m.shock == SMC_SHOCK_GAUSS) || (m.K == 2 && m.shock == SMC_SHOCK_STUDENT_T) ||
+          (m.K == 2 && m.shock == SMC_SHOCK_MIXTURE && m.ncomp == 3));
 }
 
 smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *theta,
@@ -1230,6 +1231,15 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
                             int64_t *n_accept, uint8_t *accepted, hipStream_t s,
                             const KernelTimer *timer, const MomFuse *fuse) {
   const bool shaped = (m.block != 0 && m.block != 64) || (m.unroll != 0 && m.unroll != kUnroll);
+  if (shaped && m.shock == SMC_SHOCK_MIXTURE) {
+    return m.prec == SMC_FP32
+               ? launch_mutate_rw_shaped_mix32(m, P, t, theta, logprior, loglik, state, hchol,
+                                               seed, run, cycle, iter, n_accept, accepted, timer,
+                                               fuse, s)
+               : launch_mutate_rw_shaped_mix64(m, P, t, theta, logprior, loglik, state, hchol,
+                                               seed, run, cycle, iter, n_accept, accepted, timer,
+                                               fuse, s);
+  }
   if (shaped) {
     return m.prec == SMC_FP32
                ? launch_mutate_rw_shaped32(m, P, t, theta, logprior, loglik, state, hchol, seed,

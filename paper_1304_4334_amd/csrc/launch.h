@@ -183,8 +183,8 @@ smc_status launch_mutate_rw(const DevModel &m, int64_t P, int64_t t, double *the
                             const KernelTimer *timer = nullptr, const MomFuse *fuse = nullptr);
 // The random-walk step in the model's tuned launch shape (m.block threads
 // per block, m.unroll observations per load batch), for the models that have
-// tuned shapes (ops_shapes32.hip, ops_shapes64.hip); SMC_E_UNSUPPORTED
-// otherwise.
+// tuned shapes (ops_shapes32.hip, ops_shapes64.hip, and for egarch_23
+// ops_shapes_mix32.hip, ops_shapes_mix64.hip); SMC_E_UNSUPPORTED otherwise.
 smc_status launch_mutate_rw_shaped32(const DevModel &m, int64_t P, int64_t t, double *theta,
                                      double *logprior, double *loglik, void *state,
                                      const double *hchol, uint64_t seed, uint64_t run,
@@ -197,6 +197,18 @@ smc_status launch_mutate_rw_shaped64(const DevModel &m, int64_t P, int64_t t, do
                                      uint64_t cycle, uint64_t iter, int64_t *n_accept,
                                      uint8_t *accepted, const KernelTimer *timer,
                                      const MomFuse *fuse, hipStream_t s);
+smc_status launch_mutate_rw_shaped_mix32(const DevModel &m, int64_t P, int64_t t, double *theta,
+                                        double *logprior, double *loglik, void *state,
+                                        const double *hchol, uint64_t seed, uint64_t run,
+                                        uint64_t cycle, uint64_t iter, int64_t *n_accept,
+                                        uint8_t *accepted, const KernelTimer *timer,
+                                        const MomFuse *fuse, hipStream_t s);
+smc_status launch_mutate_rw_shaped_mix64(const DevModel &m, int64_t P, int64_t t, double *theta,
+                                        double *logprior, double *loglik, void *state,
+                                        const double *hchol, uint64_t seed, uint64_t run,
+                                        uint64_t cycle, uint64_t iter, int64_t *n_accept,
+                                        uint8_t *accepted, const KernelTimer *timer,
+                                        const MomFuse *fuse, hipStream_t s);
 // Whether a model has tuned launch shapes.
 bool has_launch_shapes(const DevModel &m);
 smc_status launch_loglik(const DevModel &m, int64_t P, const double *theta, int64_t t,

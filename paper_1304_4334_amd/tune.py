@@ -1,12 +1,15 @@
 """Autotuner of the launch shapes: times the random-walk step of each tuned
-model (EGARCH(1,1) Gaussian and EGARCH(2) Student-t, FP64 and FP32) at its
-workload's full size for every launch shape (particles per block 64, 128 or
-256; observations per load batch 4, 8 or 16), and whole adaptive batches of
-the batched workload for every shape and several persistent wave counts, and
-records the fastest in tuned.json beside this file.  Every shape gives the
-same results to the bit, so the choice changes only the speed.
+model (EGARCH(1,1) Gaussian, EGARCH(2) Student-t and egarch_23's
+normal-mixture shocks, FP64 and FP32) at its workload's full size for every
+launch shape (particles per block 64, 128 or 256; observations per load batch
+4, 8 or 16), and whole adaptive batches of the batched workload for every
+shape and several persistent wave counts, and records the fastest in
+tuned.json beside this file.  Every shape gives the same results to the bit,
+so the choice changes only the speed.
 
 Run on the GPU:  python -m paper_1304_4334_amd.tune  [out.json]
+                 python -m paper_1304_4334_amd.tune --only egarch23/fp32,egarch23/fp64
+(the second form re-tunes the named steps and keeps every other entry)
 """
 from __future__ import annotations
 
@@ -21,7 +24,8 @@ from . import _lib
 HERE = os.path.dirname(os.path.abspath(__file__))
 TUNED = os.path.join(HERE, "tuned.json")
 SHAPES = [(b, u) for b in (64, 128, 256) for u in (4, 8, 16)]
-MODELS = [("egarch11", "fp64"), ("egarch11", "fp32"), ("egarch2t", "fp32"), ("egarch2t", "fp64")]
+MODELS = [("egarch11", "fp64"), ("egarch11", "fp32"), ("egarch2t", "fp32"), ("egarch2t", "fp64"),
+          ("egarch23", "fp32"), ("egarch23", "fp64")]
 
 
 def _load():
@@ -113,15 +117,22 @@ def tune_batch(wave_counts=(1024, 2048, 4096)):
     return out
 
 
-def main(out_path=TUNED):
-    res = {"mutate": {}, "batch": {}}
-    for name, prec in MODELS:
+def main(out_path=TUNED, only=None):
+    """Tunes every model and the batch, or with `only` (a list of
+    (name, precision)) just those steps, keeping the file's other entries."""
+    res = {"mutate": {}, "batch": {}} if only is None else _load()
+    res.setdefault("mutate", {})
+    for name, prec in (MODELS if only is None else only):
         t = tune_mutate(name, prec)
         (b, u) = min(t, key=t.get)
         res["mutate"][f"{name}/{prec}"] = {"block": b, "unroll": u,
                                            "seconds": {f"{k[0]}x{k[1]}": v for k, v in t.items()}}
         print(f"[tune] {name}/{prec}: best {b} x {u} ({t[(b, u)] * 1e6:.1f} us; "
               f"default {t[(64, 8)] * 1e6:.1f} us)", flush=True)
+    if only is not None:
+        with open(out_path, "w") as f:
+            json.dump(res, f, indent=1)
+        return res
     t = tune_batch()
     (b, u, wv) = min(t, key=t.get)
     res["batch"] = {"block": b, "unroll": u, "waves": wv,
@@ -139,4 +150,10 @@ if __name__ == "__main__":
     root = os.path.dirname(HERE)
     if root not in sys.path:
         sys.path.insert(0, root)
-    main(sys.argv[1] if len(sys.argv) > 1 else TUNED)
+    args = sys.argv[1:]
+    only = None
+    if "--only" in args:
+        i = args.index("--only")
+        only = [tuple(x.split("/")) for x in args[i + 1].split(",")]
+        del args[i:i + 2]
+    main(args[0] if args else TUNED, only)

@@ -2,7 +2,7 @@
 observations per load batch 4, 8 or 16): every shape gives the default
 shape's results to the bit - single steps, whole adaptive runs (the proposal
 scale folded into the step, one wave factoring it for a multi-wave block)
-and batches - for the four model / precision pairs that have tuned shapes."""
+and batches - for the six model / precision pairs that have tuned shapes."""
 import numpy as np
 import pytest
 import torch
@@ -16,13 +16,13 @@ pytestmark = pytest.mark.gpu
 
 SHAPES = [(b, u) for b in (64, 128, 256) for u in (4, 8, 16)]
 PAIRS = [("egarch11", S.SMC_FP64), ("egarch11", S.SMC_FP32), ("egarch2t", S.SMC_FP32),
-         ("egarch2t", S.SMC_FP64)]
+         ("egarch2t", S.SMC_FP64), ("egarch23", S.SMC_FP32), ("egarch23", S.SMC_FP64)]
 
 
 @pytest.mark.parametrize("name,prec", PAIRS)
 def test_every_shape_steps_to_the_same_bits(name, prec):
     w = SD.workload(name, T=517)
-    m = S.Model(w.kind, w.y[:w.T], K=w.K, shock=w.shock, precision=prec)
+    m = S.Model(w.kind, w.y[:w.T], K=w.K, shock=w.shock, precision=prec, I=w.I)
     J, N = 3, 333  # ragged blocks for every shape
     th = SD.random_thetas(w, J * N, 5, spread=0.02)
     om = O.Model.from_workload(w)
@@ -51,7 +51,7 @@ def test_every_shape_steps_to_the_same_bits(name, prec):
 @pytest.mark.parametrize("name,prec", PAIRS)
 def test_adaptive_run_in_any_shape_is_the_same_run(name, prec):
     w = SD.workload(name, T=300)
-    m = S.Model(w.kind, w.y[:w.T], K=w.K, shock=w.shock, precision=prec)
+    m = S.Model(w.kind, w.y[:w.T], K=w.K, shock=w.shock, precision=prec, I=w.I)
     J, N = 4, 160
     res = {}
     for b, u in ((64, 8), (256, 16), (128, 4)):
@@ -89,10 +89,10 @@ def test_batch_in_any_shape_is_the_same_batch(shape):
 
 
 def test_shape_arguments_are_checked():
-    w = SD.workload("egarch23", T=50)
+    w = SD.workload("egarch34", T=50)
     m = S.Model.from_workload(w)
     with pytest.raises(S.SmcError):
-        m.set_launch(256, 8)  # no tuned shapes for mixtures
+        m.set_launch(256, 8)  # tuned shapes for egarch_23 alone among the mixtures
     m.set_launch(64, 8)  # the default is always allowed
     w = SD.workload("egarch11", T=50)
     m = S.Model.from_workload(w)
