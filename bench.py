@@ -63,8 +63,9 @@ def mixture_ops(K, I, exp_cost, fp32):
 
 # The builder's counts of the kernels' algorithmic work (see above).
 # FP32 (the eps form): z, eps, 3 per factor, K - 1 additions, the exponent
-# sum's accumulation; the Gaussian term 1, or the Student-t factor 1, a pair
-# product and the log2's accumulation 1/2 each and half a log2.
+# sum's accumulation; the Gaussian term 1, or the Student-t factor 1, the
+# product of four factors (3/4), the log2's accumulation (1/4) and a quarter
+# of a log2 (one log2 per four observations).
 OPS_PER_EVAL = {
     ("linreg", "fp64"): 4,
     ("egarch23", "fp64"): mixture_ops(2, 3, 17, False),
@@ -72,7 +73,7 @@ OPS_PER_EVAL = {
     ("egarch11", "fp64"): 7 + 17,
     ("egarch11", "fp32"): 1 + 1 + 3 + 1 + 1 + 4,
     ("egarch2t", "fp64"): 10 + 17 + 3 + 17,
-    ("egarch2t", "fp32"): 1 + 1 + 6 + 1 + 1 + 1 + 1 + 4 + 2,
+    ("egarch2t", "fp32"): 1 + 1 + 6 + 1 + 1 + 1 + 0.75 + 0.25 + 4 + 1,
 }
 
 # Algorithmic VALU lane-slots per particle-observation from the hot-path
@@ -86,7 +87,7 @@ OPS_SCOPE = {
 
 
 SCOPE_NOTE = ("achieved counts the scope table's lane-slots per evaluation; the FP32 kernels "
-              "need fewer (paired log2 and the eps form of the factor update: "
+              "need fewer (one log2 per four observations and the eps form of the factor update: "
               "ops_per_eval_builder), so frac may exceed 1; frac_builder_ops is the fraction "
               "of the VALU issue peak the kernel's own operations reach")
 

@@ -169,15 +169,15 @@ struct Adjoint<Egarch<K, SH, R, I>> {
             se += (double)log2_fast(pm);
             pm = (R)1;
           }
-        } else if constexpr (Md::kTPair) {
-          // FP32 Student-t factors, multiplied in pairs (Egarch::kTPair)
-          if (j & 1) {
+        } else if constexpr (Md::kTProd) {
+          // FP32 Student-t factors, multiplied in groups (Egarch::kTProd)
+          if (j % Md::kTGroup == Md::kTGroup - 1) {
             ae += log2_fast(pm);
             pm = (R)1;
           }
         }
       }
-      if constexpr (Md::kTPair) ae += log2_fast(pm);
+      if constexpr (Md::kTProd) ae += log2_fast(pm);
       sv += (double)av;
       se += (double)ae;
       if constexpr (kMix) se += (double)log2_fast(pm);
