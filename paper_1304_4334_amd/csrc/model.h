@@ -765,7 +765,11 @@ struct Egarch {
     const int n = (int)(t1 - t0);
     const int nm = n - 1;  // all but the last observation
     const int nb = nm / kAcc;  // whole groups
-    // group sums (carried across the two batches of a group when U = 4)
+    // group sums (carried across the two batches of a group when U = 4).
+    // FP32 recursions carry them over two groups (kF) before adding them
+    // to the FP64 totals: groups 2j and 2j + 1 form one span, the same for
+    // every U, which halves the conversions and FP64 additions.
+    constexpr int kF = sizeof(R) == 4 ? 2 : 1;  // groups per FP64 flush
     R av = (R)0, ae = (R)0, pm = (R)1;
     auto flush = [&]() {
       sv += (double)av;
@@ -778,15 +782,19 @@ struct Egarch {
     constexpr int Q = U > kAcc ? U / kAcc : 1;  // groups per batch
     const int nbat = nb * G / Q;  // whole batches (U = 16 may leave one group)
     // Batch b of observations; bp = b % 2 (with U = 4 a group spans batches
-    // b and b + 1, b even).
-    auto batch = [&](const R(&yv)[U], int bp) {
+    // b and b + 1, b even, and godd is the parity of its group b / 2).
+    auto batch = [&](const R(&yv)[U], int bp, int godd) {
 #pragma unroll
       for (int i = 0; i < U; ++i) {
         R Ed, zd;
         const R sw = step(p, yv[i], r, ae, pm, Ed, zd);
-        // position in the group; its first term starts the group's sum
+        // position in the group, and the group's parity: batches of 16
+        // hold groups 2j and 2j + 1, batches of 8 are groups (b even in
+        // the first call of a pair), batches of 4 are told
         const int pos = (G > 1 ? bp * U : 0) + (i % kAcc);
-        if (pos == 0) av = sw;
+        const int odd = Q > 1 ? (i / kAcc) & 1 : (G > 1 ? godd : bp);
+        // the first term of a flush span starts its sum
+        if (pos == 0 && (kF == 1 || !odd)) av = sw;
         else av += sw;
         if constexpr (kTProd) {
           if (pos % kTGroup == kTGroup - 1) {
@@ -794,7 +802,7 @@ struct Egarch {
             pm = (R)1;
           }
         }
-        if (pos == kAcc - 1) flush();
+        if (pos == kAcc - 1 && (kF == 1 || odd)) flush();
       }
     };
     static_assert(G <= 2, "a group spans at most two batches");
@@ -819,7 +827,7 @@ struct Egarch {
         for (int i = 0; i < U; ++i) yc[i] = yp[U + i];
         __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
-        batch(ya, 0);
+        batch(ya, 0, (b >> 1) & 1);
         __asm__ volatile("" ::"s"(yc[0]), "s"(yc[U - 1]));
         // batch b + 2, or batch b + 1 again when there is none (not used)
         const Y *pn = yp + (b + 2 < nbat ? 2 * U : U);
@@ -827,14 +835,15 @@ struct Egarch {
         for (int i = 0; i < U; ++i) ya[i] = pn[i];
         __asm__ volatile("" ::: "memory");
         __builtin_amdgcn_sched_barrier(0);
-        batch(yc, 1);
+        batch(yc, 1, (b >> 1) & 1);
       }
       if (b < nbat) {
-        batch(ya, 0);
+        batch(ya, 0, (b >> 1) & 1);
         yp += U;
       }
     }
-    // a group left over by batches of 16
+    // a group left over by batches of 16 (group 2j, as nbat batches of 16
+    // hold an even number of groups)
     for (int g = nbat * Q / G; g < nb; ++g, yp += kAcc) {
       R yb[kAcc];
 #pragma unroll
@@ -843,7 +852,7 @@ struct Egarch {
       for (int i = 0; i < kAcc; ++i) {
         R Ed, zd;
         const R sw = step(p, yb[i], r, ae, pm, Ed, zd);
-        if (i == 0) av = sw;
+        if (i == 0 && (kF == 1 || !(g & 1))) av = sw;
         else av += sw;
         if constexpr (kTProd) {
           if (i % kTGroup == kTGroup - 1) {
@@ -852,8 +861,10 @@ struct Egarch {
           }
         }
       }
-      flush();
+      if (kF == 1 || (g & 1)) flush();
     }
+    // an odd number of groups leaves the last one's span open
+    if (kF == 2 && (nb & 1)) flush();
     for (int i = nb * kAcc; i < nm; ++i, ++yp) {
       R ae1 = (R)0, pm1 = (R)1, Ed, zd;
       const R av1 = step(p, *yp, r, ae1, pm1, Ed, zd);
