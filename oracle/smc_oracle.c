@@ -966,6 +966,7 @@ static double inc_beta(double a, double b, double x, double lx, double l1x) {
  * w = nu / (nu + z^2) (DLMF 8.17.22's relation for the t distribution), which
  * in terms of x is w = nu2 / (nu2 + x^2); symmetry gives z >= 0. */
 static double student_t_unit_cdf(double x, double nu2) {
+  if (isinf(x)) return x < 0.0 ? 0.0 : 1.0; /* the limits at -inf and +inf */
   double r = nu2 + x * x;
   double tail = 0.5 * inc_beta(0.5 * (nu2 + 2.0), 0.5, nu2 / r, log(nu2) - log(r),
                                2.0 * log(fabs(x)) - log(r));

@@ -427,6 +427,11 @@ def test_student_t_loss_probability_matches_scipy():
             assert g[1] == pytest.approx(want, rel=rel, abs=1e-15 if x < 0 else rel), (nu, x)
     th[0] = -1000.0 * 0.03
     assert O.test_fns(m, th, st, 0)[1] == 0.5
+    # the limits: mu_Y = +inf puts x at -inf, mu_Y = -inf at +inf
+    th[0] = math.inf
+    assert O.test_fns(m, th, st, 0)[1] == 0.0
+    th[0] = -math.inf
+    assert O.test_fns(m, th, st, 0)[1] == 1.0
 
 
 def test_log_score_matches_closed_form():
