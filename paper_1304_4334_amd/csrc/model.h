@@ -182,6 +182,7 @@ __device__ __forceinline__ double t_log_const(double nu) {
 // from nu2, x^2 and their sum, so neither cancels.  At most 4,096 terms: a
 // few hundred suffice for any nu the prior reaches.
 __device__ inline double t_unit_cdf(double x, double nu2) {
+  if (isinf(x)) return x < 0.0 ? 0.0 : 1.0;
   const double r = nu2 + x * x, lr = log(r);
   const double lw = log(nu2) - lr, l1w = 2.0 * log(fabs(x)) - lr;
   const double ha = 0.5 * (nu2 + 2.0);

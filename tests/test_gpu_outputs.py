@@ -57,7 +57,7 @@ def test_student_t_loss_probability_matches_oracle(nu):
     th[1] = 0.0
     th[2 + 3 * w.K] = np.log(nu - 2.0)
     rel = 1e-12 if nu < 1000 else 1e-10
-    for x in (-80.0, -6.0, -1.5, -0.2, 0.0, 1e-3, 0.7, 3.0, 50.0):
+    for x in (-np.inf, -80.0, -6.0, -1.5, -0.2, 0.0, 1e-3, 0.7, 3.0, 50.0, np.inf):
         th[0] = -1000.0 * (x + 0.03)
         opop = O.Pop(om, 2, 64)
         opop.theta[:] = th
@@ -66,6 +66,7 @@ def test_student_t_loss_probability_matches_oracle(nu):
         assert got[0, 0] == want[0], x
         assert got[1, 0] == pytest.approx(want[1], rel=rel, abs=1e-300), (x, got[1, 0], want[1])
         assert got[1, 1] <= 1e-12 * max(want[1], 1e-300), x  # identical particles
+    assert want[1] == 1.0  # the last case, x = +inf
 
 
 def test_rne_rule_with_e2_matches_oracle_run():
