@@ -1,7 +1,7 @@
 """The FP32 likelihood recursion against the FP64 oracle, result by result.
 
-The recursion's per-observation terms are FP32 (accumulated in FP64 every
-eight observations); weights, log-sum-exp, moments, the marginal likelihood
+The recursion's per-observation terms are FP32 (added to FP64 totals every
+sixteen observations); weights, log-sum-exp, moments, the marginal likelihood
 and its NSE stay FP64.  Each test measures the error of one result and
 prints it ("[fp32] ..." lines):
   - the log-likelihood at t = T of sampled particles at the workloads' full

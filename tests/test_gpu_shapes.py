@@ -28,24 +28,27 @@ def test_every_shape_steps_to_the_same_bits(name, prec):
     om = O.Model.from_workload(w)
     lp = torch.tensor([O.logprior(om, th[p]) for p in range(J * N)], dtype=torch.float64)
     hl = torch.from_numpy(np.linalg.cholesky(np.cov(th.T)) * 0.1).cuda()
-    out = {}
-    for b, u in SHAPES:
-        m.set_launch(b, u)
-        g = S.Population(m, J, N)
-        g.theta.copy_(torch.from_numpy(th.T.copy()))
-        g.loglik.copy_(S.smc_loglik(m, g.theta, w.T))
-        g.logprior.copy_(lp)
-        acc = torch.zeros(J * N, dtype=torch.uint8, device="cuda")
-        n = S.smc_mutate(m, g, w.T, hl, seed=3, cycle=2, it=1, accepted=acc)
-        out[(b, u)] = (theta_np(g), g.loglik.cpu().numpy(), g.state.cpu().numpy(),
-                       acc.cpu().numpy(), int(n.item()))
-    m.set_launch(0, 0)
-    ref = out[(64, 8)]
-    assert 0 < ref[4] < J * N
-    for k, v in out.items():
-        for a, b_ in zip(v[:4], ref[:4]):
-            assert np.array_equal(a, b_), k
-        assert v[4] == ref[4], k
+    # t = 517 and 509: 64 and 63 whole groups of 8 observations (the FP32
+    # sums are added to FP64 every two groups, so 63 leaves one group open)
+    for t in (w.T, w.T - 8):
+        out = {}
+        for b, u in SHAPES:
+            m.set_launch(b, u)
+            g = S.Population(m, J, N)
+            g.theta.copy_(torch.from_numpy(th.T.copy()))
+            g.loglik.copy_(S.smc_loglik(m, g.theta, t))
+            g.logprior.copy_(lp)
+            acc = torch.zeros(J * N, dtype=torch.uint8, device="cuda")
+            n = S.smc_mutate(m, g, t, hl, seed=3, cycle=2, it=1, accepted=acc)
+            out[(b, u)] = (theta_np(g), g.loglik.cpu().numpy(), g.state.cpu().numpy(),
+                           acc.cpu().numpy(), int(n.item()))
+        m.set_launch(0, 0)
+        ref = out[(64, 8)]
+        assert 0 < ref[4] < J * N
+        for k, v in out.items():
+            for a, b_ in zip(v[:4], ref[:4]):
+                assert np.array_equal(a, b_), (t, k)
+            assert v[4] == ref[4], (t, k)
 
 
 @pytest.mark.parametrize("name,prec", PAIRS)
