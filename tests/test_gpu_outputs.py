@@ -69,11 +69,13 @@ def test_student_t_loss_probability_matches_oracle(nu):
     assert want[1] == 1.0  # the last case, x = +inf
 
 
-def test_rne_rule_with_e2_matches_oracle_run():
-    """Adaptive run with the RNE rule over the model's functions of interest,
-    dates of interest every 40 observations: the same cycle ends, M-phase
-    lengths, reports and log-ML as the oracle's run."""
-    w = SD.workload("egarch23", T=120)
+@pytest.mark.parametrize("name", ["egarch23", "egarch2t"])
+def test_rne_rule_with_e2_matches_oracle_run(name):
+    """Adaptive run with the RNE rule over the model's functions of interest
+    (for Student-t shocks g1 and the t loss probability), dates of interest
+    every 40 observations: the same cycle ends, M-phase lengths, reports and
+    log-ML as the oracle's run."""
+    w = SD.workload(name, T=120)
     gm, om = gpu_model(w), ora_model(w)
     J, N = 8, 64
     rc, orec, _ = O.run(om, J, N, 3, check_every=1, force_every=40, stop_rule=1, E1=0.2, E2=0.6,

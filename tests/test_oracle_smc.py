@@ -427,6 +427,17 @@ def test_student_t_loss_probability_matches_scipy():
             assert g[1] == pytest.approx(want, rel=rel, abs=1e-15 if x < 0 else rel), (nu, x)
     th[0] = -1000.0 * 0.03
     assert O.test_fns(m, th, st, 0)[1] == 0.5
+    # textbook closed forms of the t distribution function, z = x sqrt(nu / (nu - 2)):
+    # nu = 3: 1/2 + (z / (sqrt 3 (1 + z^2/3)) + atan(z / sqrt 3)) / pi;
+    # nu = 4: 1/2 + z (z^2 + 6) / (2 (z^2 + 4)^(3/2))
+    for nu, cdf in ((3.0, lambda z: 0.5 + (z / (math.sqrt(3.0) * (1.0 + z * z / 3.0))
+                                           + math.atan(z / math.sqrt(3.0))) / math.pi),
+                    (4.0, lambda z: 0.5 + z * (z * z + 6.0) / (2.0 * (z * z + 4.0) ** 1.5))):
+        th[2 + 3 * w.K] = math.log(nu - 2.0)
+        for x in (-7.0, -2.0, -0.4, 0.3, 1.1, 5.0):
+            th[0] = -1000.0 * (x + 0.03)
+            want = cdf(x * math.sqrt(nu / (nu - 2.0)))
+            assert O.test_fns(m, th, st, 0)[1] == pytest.approx(want, rel=1e-12, abs=1e-15), (nu, x)
     # the limits: mu_Y = +inf puts x at -inf, mu_Y = -inf at +inf
     th[0] = math.inf
     assert O.test_fns(m, th, st, 0)[1] == 0.0
